@@ -1,0 +1,196 @@
+"""ctypes binding of the plain FP64 CPU oracle (``mmfv_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it to check the HIP library.  The product never imports
+it.  ``build()`` compiles the C source with gcc (no fast-math, no FP
+contraction, so every operation is rounded once as written).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mmfv_oracle.c")
+_LIB = os.path.join(_HERE, "libmmfv_oracle.so")
+MAXM = 8
+N_DIAG_HEAD = 8
+
+
+def build(force=True):
+    """Compile the oracle into ``oracle/libmmfv_oracle.so``."""
+    if not force and os.path.exists(_LIB) and \
+            os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("n_mat", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
+                ("y1", C.c_double),
+                ("gamma", C.c_double * MAXM), ("pinf", C.c_double * MAXM),
+                ("bc", C.c_int32 * 4), ("inflow_W", C.c_double * 4),
+                ("inflow_mat", C.c_int32), ("rk_order", C.c_int32),
+                ("cfl", C.c_double), ("alpha_mix", C.c_double),
+                ("k_ext", C.c_int32), ("band_ls", C.c_int32)]
+
+
+def make_config(cfg):
+    c = Config()
+    for k in ("dim", "nx", "ny", "n_mat", "inflow_mat", "rk_order", "k_ext",
+              "band_ls"):
+        setattr(c, k, int(cfg[k]))
+    for k in ("x0", "x1", "y0", "y1", "cfl", "alpha_mix"):
+        setattr(c, k, float(cfg[k]))
+    for m in range(cfg["n_mat"]):
+        c.gamma[m] = float(cfg["gamma"][m])
+        c.pinf[m] = float(cfg["pinf"][m])
+    for q in range(4):
+        c.bc[q] = int(cfg["bc"][q])
+        c.inflow_W[q] = float(cfg["inflow_W"][q])
+    return c
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or \
+                os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        L.or_create.restype = vp
+        L.or_create.argtypes = [C.POINTER(Config)]
+        L.or_destroy.argtypes = [vp]
+        L.or_init.argtypes = [vp, dp, ip, dp]
+        L.or_step.argtypes = [vp, C.c_int]
+        L.or_get.argtypes = [vp, vp, vp, vp, vp]
+        L.or_get_apertures.argtypes = [vp, vp, vp]
+        L.or_get_closure.argtypes = [vp, vp, vp]
+        L.or_diag.argtypes = [vp, dp]
+        L.or_set_dt.argtypes = [vp, C.c_double]
+        L.or_err_cell.restype = C.c_long
+        L.or_err_cell.argtypes = [vp]
+        d = C.c_double
+        L.or_t_weno5.restype = d
+        L.or_t_weno5.argtypes = [d, d, d, d, d]
+        L.or_t_hllc.argtypes = [vp, C.c_int, dp, dp, dp]
+        L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """One solver instance.  ``cfg`` is a plain dict (see ``workloads``)."""
+
+    def __init__(self, cfg):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self._h = lib().or_create(C.byref(self._c))
+        if not self._h:
+            raise ValueError("oracle: invalid configuration")
+        self.ny, self.nx = int(cfg["ny"]), int(cfg["nx"])
+        self.M, self.nv = int(cfg["n_mat"]), int(cfg["dim"]) + 2
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_destroy(h)
+            self._h = None
+
+    def init(self, phi, chi, W):
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.ny, self.nx)
+        chi = np.ascontiguousarray(chi, dtype=np.int32).reshape(self.ny, self.nx)
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(
+            self.M, self.nv, self.ny, self.nx)
+        return lib().or_init(self._h, phi, chi, W)
+
+    def step(self, n=1):
+        return lib().or_step(self._h, int(n))
+
+    def set_dt(self, dt):
+        lib().or_set_dt(self._h, float(dt))
+
+    def hllc(self, m, WL, WR):
+        F = np.zeros(4)
+        lib().or_t_hllc(self._h, int(m), np.ascontiguousarray(WL, float),
+                        np.ascontiguousarray(WR, float), F)
+        return F
+
+    def iface(self, mL, WL, mR, WR):
+        out = np.zeros(4)
+        lib().or_t_iface(self._h, int(mL), np.ascontiguousarray(WL, float),
+                         int(mR), np.ascontiguousarray(WR, float), out)
+        return dict(SL=out[0], SR=out[1], SM=out[2], pstar=out[3])
+
+    def err_cell(self):
+        return lib().or_err_cell(self._h)
+
+    def get(self):
+        Q = np.zeros((self.M, self.nv, self.ny, self.nx))
+        al = np.zeros((self.M, self.ny, self.nx))
+        phi = np.zeros((self.ny, self.nx))
+        chi = np.zeros((self.ny, self.nx), dtype=np.int32)
+        lib().or_get(self._h, _ptr(Q), _ptr(al), _ptr(phi), _ptr(chi))
+        return dict(Q=Q, alpha=al, phi=phi, chi=chi)
+
+    def apertures(self):
+        Ax = np.zeros((self.M, self.ny, self.nx + 1))
+        Ay = np.zeros((self.M, self.ny + 1, self.nx)) if self.cfg["dim"] == 2 \
+            else None
+        lib().or_get_apertures(self._h, _ptr(Ax), _ptr(Ay))
+        return Ax, Ay
+
+    def closure(self):
+        cx = np.zeros((self.M, self.ny, self.nx))
+        cy = np.zeros((self.M, self.ny, self.nx))
+        lib().or_get_closure(self._h, _ptr(cx), _ptr(cy))
+        return cx, cy
+
+    def diag(self):
+        out = np.zeros(N_DIAG_HEAD + 2 * self.M * 4)
+        lib().or_diag(self._h, out)
+        M = self.M
+        head = out[:N_DIAG_HEAD]
+        return dict(t=head[0], dt=head[1], steps=int(head[2]),
+                    n_posfix=int(head[3]), n_fluxskip=int(head[4]),
+                    n_ifskip=int(head[5]), n_stranded=int(head[6]),
+                    n_mixsrc=int(head[7]),
+                    bnd=out[8:8 + 4 * M].reshape(M, 4),
+                    xsum=out[8 + 4 * M:8 + 8 * M].reshape(M, 4))
+
+
+def weno5(v1, v2, v3, v4, v5):
+    return lib().or_t_weno5(float(v1), float(v2), float(v3), float(v4), float(v5))
+
+
+def run(workload, steps=None):
+    """Initialise an oracle from a workload dict and advance it."""
+    o = Oracle(workload["cfg"])
+    rc = o.init(workload["phi"], workload["chi"], workload["W"])
+    if rc:
+        raise RuntimeError(f"oracle init failed: {rc}")
+    n = workload["steps"] if steps is None else steps
+    if n:
+        rc = o.step(n)
+        if rc:
+            raise RuntimeError(f"oracle step failed: {rc} at cell {o.err_cell()}")
+    return o

@@ -1,0 +1,1481 @@
+/*
+ * mmfv_oracle.c -- plain, slow, single-threaded FP64 CPU reference of one time
+ * step of the conservative sharp-interface method for compressible
+ * multi-material flows (Pan, Han, Hu & Adams, arXiv:1704.00519).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * checked against.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it; the product library never links or calls it,
+ * and the two share no code, headers or generated tables.
+ *
+ * Every routine below follows a passage of the paper (section / equation
+ * named in its comment).  Where the paper is silent or garbled, the reading
+ * taken is stated in the comment ("Reading: ...").  The loops are plain nested
+ * loops over cells in row-major order; nothing is blocked, fused or reordered
+ * beyond what the method states.
+ *
+ * Conventions
+ *   * Uniform Cartesian grid, nx x ny interior cells (ny = 1 in 1D), a frame of
+ *     H = 4 halo cells on every side (none in y for 1D).
+ *   * Per-material conserved state Q^r = alpha^r U^r with 4 components
+ *     (rho, rho u, rho v, rho E); in 1D the rho v component stays exactly 0.
+ *   * Stiffened-gas EOS p = (gamma-1) rho e - gamma p_inf (ideal gas: p_inf = 0;
+ *     Sec. 2.1 names the stiffened gas but prints no formula).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_H 4
+#define OR_NV 4
+#define OR_MAXM 8
+
+enum { OR_OK = 0, OR_EINVAL = 1, OR_ENOMEM = 2, OR_ENONPHYS = 4,
+       OR_ESTATE = 5 };
+enum { BC_TRANSMISSIVE = 0, BC_REFLECTIVE = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
+
+/* Plain-old-data configuration, laid out for ctypes. */
+typedef struct {
+  int32_t dim, nx, ny, n_mat;
+  double x0, x1, y0, y1;
+  double gamma[OR_MAXM], pinf[OR_MAXM];
+  int32_t bc[4]; /* x-lo, x-hi, y-lo, y-hi */
+  double inflow_W[4];
+  int32_t inflow_mat, rk_order;
+  double cfl, alpha_mix;
+  int32_t k_ext, band_ls;
+} or_config;
+
+typedef struct {
+  or_config c;
+  int M, NX, NY, HY, NC;
+  double dx, dy, h, bls, idx, idy;
+  double igm1[OR_MAXM];
+  /* regional level set: current stage, time n, next stage */
+  double *phi, *phin, *phit;
+  int *chi, *chin, *chit;
+  /* conserved state [M][4][NC]: current stage, time n, after the RK update */
+  double *Q, *Qn, *Qt;
+  /* cut-cell geometry [M][NC]; ax[k] is the x-face i+1/2 of cell k,
+     ay[k] the y-face j+1/2 */
+  double *al, *ax, *ay, *cx, *cy;
+  /* primitive state and validity [M][4][NC], [M][NC] */
+  double *W, *lw;
+  unsigned char *Wv, *lok, *band, *band2;
+  int *list;
+  double *X;       /* interface exchange [M][4][NC] */
+  double *vx, *vy; /* level-set advection velocity v^n */
+  unsigned char *vok, *reg; /* velocity set / level-set update region */
+  double *lv;       /* velocity extension scratch */
+  double *Fx, *Fy; /* face fluxes [M][4][NC] */
+  double *mass;    /* [M][NC] scratch for the volume-fraction correction */
+  double *cv;      /* corner scratch [NC] */
+  int *co;         /* corner owner scratch [NC] */
+  unsigned char *xs; /* X_s bitmask [NC] */
+  double *mixM;    /* [M][3][4][NC] mixing exchanges */
+  int *mixT;       /* [M][3][NC] mixing target cell (-1 = none) */
+  double t, dt, dt_fixed;
+  long nstep;
+  long n_posfix, n_fluxskip, n_ifskip, n_stranded, n_mixsrc;
+  double bnd[OR_MAXM][OR_NV], bnd_c[OR_MAXM][OR_NV];
+  double xsum[OR_MAXM][OR_NV], xsum_c[OR_MAXM][OR_NV];
+  int err_code;
+  long err_cell;
+} St;
+
+#define ID(s, i, j) (((j) + (s)->HY) * (s)->NX + (i) + OR_H)
+#define M1(s, a, m, k) ((a)[(size_t)(m) * (s)->NC + (k)])
+#define M4(s, a, m, v, k) ((a)[((size_t)(m) * OR_NV + (v)) * (s)->NC + (k)])
+
+static void neumaier(double *sum, double *comp, double x) {
+  double t = *sum + x;
+  if (fabs(*sum) >= fabs(x))
+    *comp += (*sum - t) + x;
+  else
+    *comp += (x - t) + *sum;
+  *sum = t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermodynamics (Sec. 2.1; general-EOS sound speed, Sec. 2.3.2)            */
+/* ------------------------------------------------------------------------ */
+
+/* primitive (rho, u, v, p) from conserved cell averages U (not alpha U) */
+static void prim(const St *s, int m, const double *U, double *W) {
+  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  double rho = U[0];
+  double u = U[1] / rho;
+  double v = U[2] / rho;
+  double ke = 0.5 * rho * (u * u + v * v);
+  W[0] = rho;
+  W[1] = u;
+  W[2] = v;
+  W[3] = (g - 1.0) * (U[3] - ke) - g * pinf;
+}
+
+/* total energy density rho E of a primitive state */
+static double energy(const St *s, int m, double rho, double u, double v,
+                     double p) {
+  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  return (p + g * pinf) * s->igm1[m] + 0.5 * rho * (u * u + v * v);
+}
+
+/* Wave-speed estimates of the HLLC solver for two states that may obey
+ * different EOS (Sec. 2.3.2, the S_L/S_R estimate and the Roe averages of
+ * Psi, Upsilon and p/rho).  Stiffened gas: Psi = (p + gamma p_inf)/rho,
+ * Upsilon = gamma - 1, so c^2 = Psi + Upsilon p/rho = gamma (p + p_inf)/rho.
+ * States are (rho, u_normal, u_tangential, p). */
+static void wave_speeds(const double *WL, double gL, double piL,
+                        const double *WR, double gR, double piR, double *SL,
+                        double *SR) {
+  double rL = WL[0], uL = WL[1], pL = WL[3];
+  double rR = WR[0], uR = WR[1], pR = WR[3];
+  double irL = 1.0 / rL, irR = 1.0 / rR;
+  double porL = pL * irL, porR = pR * irR;
+  double psiL = (pL + gL * piL) * irL, psiR = (pR + gR * piR) * irR;
+  double upsL = gL - 1.0, upsR = gR - 1.0;
+  double cL = sqrt(psiL + upsL * porL);
+  double cR = sqrt(psiR + upsR * porR);
+  double sL = sqrt(rL), sR = sqrt(rR);
+  double iw = 1.0 / (sL + sR);
+  double psi_t = (sL * psiL + sR * psiR) * iw;
+  double ups_t = (sL * upsL + sR * upsR) * iw;
+  double u_t = (sL * uL + sR * uR) * iw;
+  double du = (uR - uL) * iw;
+  double por_t = (sL * porL + sR * porR) * iw + 0.5 * (sL * sR) * (du * du);
+  double c_t = sqrt(psi_t + ups_t * por_t);
+  *SL = fmin(uL - cL, u_t - c_t);
+  *SR = fmax(u_t + c_t, uR + cR);
+}
+
+/* Contact speed S_M of Toro's HLLC solver (Sec. 2.3.2).  The two momentum
+ * terms and the pressure difference are summed separately, so swapping the
+ * two states and the sign of the velocities gives exactly -S_M. */
+static double contact_speed(const double *WL, const double *WR, double SL,
+                            double SR) {
+  double rL = WL[0], uL = WL[1], pL = WL[3];
+  double rR = WR[0], uR = WR[1], pR = WR[3];
+  double num = ((SR - uR) * rR * uR + (uL - SL) * rL * uL) + (pL - pR);
+  double den = (SR - uR) * rR + (uL - SL) * rL;
+  return num / den;
+}
+
+/* HLLC flux (Toro) across a cell face inside one material.  W are
+ * (rho, u_n, u_t, p); F = (mass, normal momentum, tangential momentum,
+ * energy). */
+static void hllc_flux(const St *s, int m, const double *WL, const double *WR,
+                      double *F) {
+  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  double SL, SR;
+  wave_speeds(WL, g, pinf, WR, g, pinf, &SL, &SR);
+  double SM = contact_speed(WL, WR, SL, SR);
+  const double *Wk;
+  double Sk;
+  int star;
+  if (SL >= 0.0) {
+    Wk = WL; Sk = SL; star = 0;
+  } else if (SM >= 0.0) {
+    Wk = WL; Sk = SL; star = 1;
+  } else if (SR > 0.0) {
+    Wk = WR; Sk = SR; star = 1;
+  } else {
+    Wk = WR; Sk = SR; star = 0;
+  }
+  double r = Wk[0], u = Wk[1], v = Wk[2], p = Wk[3];
+  double E = energy(s, m, r, u, v, p);
+  double ru = r * u;
+  F[0] = ru;
+  F[1] = ru * u + p;
+  F[2] = ru * v;
+  F[3] = u * (E + p);
+  if (star) {
+    double d = Sk - u;
+    double mk = r * d;
+    double coef = mk / (Sk - SM);
+    double Us0 = coef;
+    double Us1 = coef * SM;
+    double Us2 = coef * v;
+    double Us3 = coef * (E / r + (SM - u) * (SM + p / mk));
+    F[0] = F[0] + Sk * (Us0 - r);
+    F[1] = F[1] + Sk * (Us1 - ru);
+    F[2] = F[2] + Sk * (Us2 - r * v);
+    F[3] = F[3] + Sk * (Us3 - E);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 5th-order WENO-JS (Sec. 3 intro: fluid and level set use 5th-order WENO) */
+/* ------------------------------------------------------------------------ */
+/* Left-biased value at i+1/2 from (v1..v5) = (f_{i-2}, ..., f_{i+2}).
+ * Jiang-Shu smoothness indicators, linear weights (1/10, 6/10, 3/10),
+ * eps = 1e-6, power 2.  The nonlinear weights d_k/(eps+beta_k)^2 are
+ * multiplied through by the product of the three squared denominators, so
+ * the normalised combination needs a single division; the 1/6 of the three
+ * candidate stencils is folded into the same division.  Algebraically this is
+ * the textbook formula. */
+static double weno5(double v1, double v2, double v3, double v4, double v5) {
+  double t, u;
+  t = v1 - 2.0 * v2 + v3;
+  u = v1 - 4.0 * v2 + 3.0 * v3;
+  double b0 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  t = v2 - 2.0 * v3 + v4;
+  u = v2 - v4;
+  double b1 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  t = v3 - 2.0 * v4 + v5;
+  u = 3.0 * v3 - 4.0 * v4 + v5;
+  double b2 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  double e0 = 1e-6 + b0, e1 = 1e-6 + b1, e2 = 1e-6 + b2;
+  e0 = e0 * e0;
+  e1 = e1 * e1;
+  e2 = e2 * e2;
+  double a0 = 0.1 * (e1 * e2);
+  double a1 = 0.6 * (e0 * e2);
+  double a2 = 0.3 * (e0 * e1);
+  double q0 = 2.0 * v1 - 7.0 * v2 + 11.0 * v3;
+  double q1 = -v2 + 5.0 * v3 + 2.0 * v4;
+  double q2 = 2.0 * v3 + 5.0 * v4 - v5;
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * (a0 + a1 + a2));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary frames                                                          */
+/* ------------------------------------------------------------------------ */
+/* Reading: transmissive/outflow = zero-gradient copy, reflective = mirror
+ * with the normal velocity negated, inflow = a fixed state of one material
+ * (Case V: inflow/outflow left/right, symmetric top/bottom). */
+static int src_lo(int i, int type) { return type == BC_REFLECTIVE ? -1 - i : 0; }
+static int src_hi(int i, int n, int type) {
+  return type == BC_REFLECTIVE ? 2 * n - 1 - i : n - 1;
+}
+
+static void fill_d(St *s, double *f, double sx, double sy) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = -OR_H; i < 0; i++) {
+      int tl = s->c.bc[0], th = s->c.bc[1];
+      f[ID(s, i, j)] = f[ID(s, src_lo(i, tl), j)] * (tl == BC_REFLECTIVE ? sx : 1.0);
+      int ih = nx + (-1 - i); /* nx .. nx+3 */
+      f[ID(s, ih, j)] = f[ID(s, src_hi(ih, nx, th), j)] * (th == BC_REFLECTIVE ? sx : 1.0);
+    }
+  if (s->c.dim < 2) return;
+  for (int i = -OR_H; i < nx + OR_H; i++)
+    for (int j = -OR_H; j < 0; j++) {
+      int tl = s->c.bc[2], th = s->c.bc[3];
+      f[ID(s, i, j)] = f[ID(s, i, src_lo(j, tl))] * (tl == BC_REFLECTIVE ? sy : 1.0);
+      int jh = ny + (-1 - j);
+      f[ID(s, i, jh)] = f[ID(s, i, src_hi(jh, ny, th))] * (th == BC_REFLECTIVE ? sy : 1.0);
+    }
+}
+
+static void fill_i(St *s, int *f) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = -OR_H; i < 0; i++) {
+      f[ID(s, i, j)] = f[ID(s, src_lo(i, s->c.bc[0]), j)];
+      int ih = nx + (-1 - i);
+      f[ID(s, ih, j)] = f[ID(s, src_hi(ih, nx, s->c.bc[1]), j)];
+    }
+  if (s->c.dim < 2) return;
+  for (int i = -OR_H; i < nx + OR_H; i++)
+    for (int j = -OR_H; j < 0; j++) {
+      f[ID(s, i, j)] = f[ID(s, i, src_lo(j, s->c.bc[2]))];
+      int jh = ny + (-1 - j);
+      f[ID(s, i, jh)] = f[ID(s, i, src_hi(jh, ny, s->c.bc[3]))];
+    }
+}
+
+/* Primitive-state frame of every material.  On an inflow side the inflow
+ * material receives the fixed state; the other materials are copied. */
+static void fill_W(St *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int m = 0; m < s->M; m++) {
+    double *f[4];
+    for (int v = 0; v < 4; v++) f[v] = &M4(s, s->W, m, v, 0);
+    unsigned char *fv = &M1(s, s->Wv, m, 0);
+    /* x sides */
+    for (int v = 0; v < 4; v++) {
+      double sx = (v == 1) ? -1.0 : 1.0;
+      for (int j = 0; j < ny; j++)
+        for (int i = -OR_H; i < 0; i++) {
+          int tl = s->c.bc[0], th = s->c.bc[1];
+          f[v][ID(s, i, j)] = f[v][ID(s, src_lo(i, tl), j)] * (tl == BC_REFLECTIVE ? sx : 1.0);
+          int ih = nx + (-1 - i);
+          f[v][ID(s, ih, j)] = f[v][ID(s, src_hi(ih, nx, th), j)] * (th == BC_REFLECTIVE ? sx : 1.0);
+        }
+    }
+    for (int j = 0; j < ny; j++)
+      for (int i = -OR_H; i < 0; i++) {
+        fv[ID(s, i, j)] = fv[ID(s, src_lo(i, s->c.bc[0]), j)];
+        int ih = nx + (-1 - i);
+        fv[ID(s, ih, j)] = fv[ID(s, src_hi(ih, nx, s->c.bc[1]), j)];
+      }
+    for (int side = 0; side < 2; side++)
+      if (s->c.bc[side] == BC_INFLOW && m == s->c.inflow_mat)
+        for (int j = 0; j < ny; j++)
+          for (int i = -OR_H; i < 0; i++) {
+            int ii = side == 0 ? i : nx + (-1 - i);
+            for (int v = 0; v < 4; v++) f[v][ID(s, ii, j)] = s->c.inflow_W[v];
+            fv[ID(s, ii, j)] = 1;
+          }
+    if (s->c.dim < 2) continue;
+    /* y sides */
+    for (int v = 0; v < 4; v++) {
+      double sy = (v == 2) ? -1.0 : 1.0;
+      for (int i = -OR_H; i < nx + OR_H; i++)
+        for (int j = -OR_H; j < 0; j++) {
+          int tl = s->c.bc[2], th = s->c.bc[3];
+          f[v][ID(s, i, j)] = f[v][ID(s, i, src_lo(j, tl))] * (tl == BC_REFLECTIVE ? sy : 1.0);
+          int jh = ny + (-1 - j);
+          f[v][ID(s, i, jh)] = f[v][ID(s, i, src_hi(jh, ny, th))] * (th == BC_REFLECTIVE ? sy : 1.0);
+        }
+    }
+    for (int i = -OR_H; i < nx + OR_H; i++)
+      for (int j = -OR_H; j < 0; j++) {
+        fv[ID(s, i, j)] = fv[ID(s, i, src_lo(j, s->c.bc[2]))];
+        int jh = ny + (-1 - j);
+        fv[ID(s, i, jh)] = fv[ID(s, i, src_hi(jh, ny, s->c.bc[3]))];
+      }
+    for (int side = 2; side < 4; side++)
+      if (s->c.bc[side] == BC_INFLOW && m == s->c.inflow_mat)
+        for (int i = -OR_H; i < nx + OR_H; i++)
+          for (int j = -OR_H; j < 0; j++) {
+            int jj = side == 2 ? j : ny + (-1 - j);
+            for (int v = 0; v < 4; v++) f[v][ID(s, i, jj)] = s->c.inflow_W[v];
+            fv[ID(s, i, jj)] = 1;
+          }
+  }
+}
+
+static void fill_ls(St *s, double *phi, int *chi) {
+  fill_d(s, phi, 1.0, 1.0);
+  fill_i(s, chi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-region level set (Sec. 2.2)                                        */
+/* ------------------------------------------------------------------------ */
+/* Construction operator C_r (Eq. construction): +phi inside material r,
+ * -phi elsewhere. */
+static double lsv(const double *phi, const int *chi, int r, int k) {
+  return chi[k] == r ? phi[k] : -phi[k];
+}
+
+/* Local material set X_s: the distinct indicators of the 3x3 block around a
+ * cell.  Reading: the strict inequalities printed for V_s would select the
+ * cell alone; the block of the cell and its 8 neighbours is meant. */
+static void local_sets(St *s, const int *chi, unsigned char *xs) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      unsigned char b = 0;
+      for (int dj = -two; dj <= two; dj++)
+        for (int di = -1; di <= 1; di++) b |= (unsigned char)(1u << chi[ID(s, i + di, j + dj)]);
+      xs[ID(s, i, j)] = b;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cut-cell geometry (Sec. 2.3: volume fraction alpha, apertures A,          */
+/* interface segment Delta Omega)                                           */
+/* ------------------------------------------------------------------------ */
+/* Reading (tie rule): a point is inside material r if its local level-set
+ * value is positive, or zero while r is the smallest indicator among the
+ * cells that define the point; this gives every zero a single owner. */
+static int inside(double v, int owner, int r) {
+  return v > 0.0 || (v == 0.0 && owner == r);
+}
+
+/* Fraction of a segment on which the linear interpolant of its end values is
+ * inside. */
+static double seg_frac(double v0, int in0, double v1, int in1) {
+  if (in0 && in1) return 1.0;
+  if (!in0 && !in1) return 0.0;
+  double vp = in0 ? v0 : v1, vm = in0 ? v1 : v0;
+  if (vp <= 0.0) return 0.0;
+  return vp / (vp - vm);
+}
+
+/* Fraction of a triangle on which the linear interpolant of its vertex values
+ * is inside. */
+static double tri_frac(double a, int ia, double b, int ib, double c, int ic) {
+  int n = ia + ib + ic;
+  if (n == 3) return 1.0;
+  if (n == 0) return 0.0;
+  if (n == 1) {
+    double p, q, r;
+    if (ia) { p = a; q = b; r = c; }
+    else if (ib) { p = b; q = a; r = c; }
+    else { p = c; q = a; r = b; }
+    if (p <= 0.0) return 0.0;
+    return (p * p) / ((p - q) * (p - r));
+  }
+  double o, p, q;
+  if (!ia) { o = a; p = b; q = c; }
+  else if (!ib) { o = b; p = a; q = c; }
+  else { o = c; p = a; q = b; }
+  if (o >= 0.0) return 1.0;
+  return 1.0 - (o * o) / ((o - p) * (o - q));
+}
+
+/* Volume fractions, face apertures and interface closure vectors of every
+ * material, from the regional level set (phi, chi) with filled frame.
+ * Reading (geometry; the two-phase formulas of hu2006conservative are not
+ * reproduced in the paper): in 2D the local level set is interpolated
+ * piecewise linearly on the four triangles spanned by the cell centre and
+ * each face; corner values are the mean of the four surrounding cells.  The
+ * aperture of a face is the inside fraction of the linear interpolant between
+ * its two corners, the volume fraction the inside area fraction of the four
+ * triangles.  In 1D the face value is the mean of the two cells.  The
+ * interface segment Delta Omega^r times its normal (pointing into r) closes
+ * the polygon: c^r = ((A_{i+1/2} - A_{i-1/2}) dy, (A_{j+1/2} - A_{j-1/2}) dx). */
+static void geometry(St *s, const double *phi, const int *chi) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int r = 0; r < s->M; r++) {
+    double *al = &M1(s, s->al, r, 0), *ax = &M1(s, s->ax, r, 0),
+           *ay = &M1(s, s->ay, r, 0), *cx = &M1(s, s->cx, r, 0),
+           *cy = &M1(s, s->cy, r, 0);
+    if (s->c.dim == 1) {
+      for (int i = -1; i < nx; i++) {
+        int a = ID(s, i, 0), b = ID(s, i + 1, 0);
+        double f = (lsv(phi, chi, r, a) + lsv(phi, chi, r, b)) * 0.5;
+        int own = chi[a] < chi[b] ? chi[a] : chi[b];
+        s->cv[a] = f;
+        s->co[a] = own;
+        ax[a] = inside(f, own, r) ? 1.0 : 0.0;
+      }
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, 0), kl = ID(s, i - 1, 0);
+        double c = lsv(phi, chi, r, k);
+        int ic = inside(c, chi[k], r);
+        int il = inside(s->cv[kl], s->co[kl], r), ir = inside(s->cv[k], s->co[k], r);
+        al[k] = (seg_frac(s->cv[kl], il, c, ic) + seg_frac(c, ic, s->cv[k], ir)) * 0.5;
+        cx[k] = ax[k] - ax[kl];
+        cy[k] = 0.0;
+      }
+      continue;
+    }
+    /* corners (i+1/2, j+1/2) for i, j in [-1, n) */
+    for (int j = -1; j < ny; j++)
+      for (int i = -1; i < nx; i++) {
+        int k00 = ID(s, i, j), k10 = ID(s, i + 1, j), k01 = ID(s, i, j + 1),
+            k11 = ID(s, i + 1, j + 1);
+        double v = ((lsv(phi, chi, r, k00) + lsv(phi, chi, r, k11)) +
+                    (lsv(phi, chi, r, k10) + lsv(phi, chi, r, k01))) * 0.25;
+        int own = chi[k00];
+        if (chi[k10] < own) own = chi[k10];
+        if (chi[k01] < own) own = chi[k01];
+        if (chi[k11] < own) own = chi[k11];
+        s->cv[k00] = v;
+        s->co[k00] = own;
+      }
+    /* x-faces i+1/2 (i in [-1,nx)), endpoints corners (i, j-1) and (i, j) */
+    for (int j = 0; j < ny; j++)
+      for (int i = -1; i < nx; i++) {
+        int ka = ID(s, i, j - 1), kb = ID(s, i, j);
+        ax[kb] = seg_frac(s->cv[ka], inside(s->cv[ka], s->co[ka], r), s->cv[kb],
+                          inside(s->cv[kb], s->co[kb], r));
+      }
+    /* y-faces j+1/2 (j in [-1,ny)), endpoints corners (i-1, j) and (i, j) */
+    for (int j = -1; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int ka = ID(s, i - 1, j), kb = ID(s, i, j);
+        ay[kb] = seg_frac(s->cv[ka], inside(s->cv[ka], s->co[ka], r), s->cv[kb],
+                          inside(s->cv[kb], s->co[kb], r));
+      }
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, j);
+        int ksw = ID(s, i - 1, j - 1), kse = ID(s, i, j - 1), knw = ID(s, i - 1, j),
+            kne = k;
+        double c = lsv(phi, chi, r, k);
+        int ic = inside(c, chi[k], r);
+        double vsw = s->cv[ksw], vse = s->cv[kse], vnw = s->cv[knw], vne = s->cv[kne];
+        int isw = inside(vsw, s->co[ksw], r), ise = inside(vse, s->co[kse], r),
+            inw = inside(vnw, s->co[knw], r), ine = inside(vne, s->co[kne], r);
+        double tl = tri_frac(vsw, isw, vnw, inw, c, ic);
+        double tr = tri_frac(vse, ise, vne, ine, c, ic);
+        double tb = tri_frac(vsw, isw, vse, ise, c, ic);
+        double tt = tri_frac(vnw, inw, vne, ine, c, ic);
+        al[k] = ((tl + tr) + (tb + tt)) * 0.25;
+        cx[k] = (ax[k] - ax[ID(s, i - 1, j)]) * s->dy;
+        cy[k] = (ay[k] - ay[ID(s, i, j - 1)]) * s->dx;
+      }
+  }
+}
+
+/* Volume-fraction correction for a multi-material-cell (Sec. 2.3.1,
+ * Eq. vol_corr2): in cells where three or more materials have alpha > 0, the
+ * material of least mass alpha*rho (the cell's own indicator excluded, it is
+ * not changed) absorbs 1 - sum(alpha).  Reading: ties go to the smaller
+ * index; if the lightest would become negative it is set to 0 and the rest
+ * passes to the next lightest.  mass[m][k] is the partial density. */
+static void vf_correction(St *s, const int *chi, const double *mass) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j), n = 0;
+      for (int r = 0; r < s->M; r++)
+        if (M1(s, s->al, r, k) > 0.0) n++;
+      if (n < 3) continue;
+      double sum = 0.0;
+      for (int r = 0; r < s->M; r++) sum += M1(s, s->al, r, k);
+      double d = 1.0 - sum;
+      int used = 0;
+      while (d != 0.0) {
+        int best = -1;
+        for (int r = 0; r < s->M; r++) {
+          if (r == chi[k] || (used >> r & 1) || !(M1(s, s->al, r, k) > 0.0)) continue;
+          if (best < 0 || M1(s, mass, r, k) < M1(s, mass, best, k)) best = r;
+        }
+        if (best < 0) break;
+        used |= 1 << best;
+        double nv = M1(s, s->al, best, k) + d;
+        if (nv < 0.0) {
+          M1(s, s->al, best, k) = 0.0;
+          d = nv;
+        } else {
+          M1(s, s->al, best, k) = nv;
+          d = 0.0;
+        }
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real and ghost primitive states (Sec. 2.3.2: the real state of the       */
+/* primary material, the ghost state otherwise)                             */
+/* ------------------------------------------------------------------------ */
+static void record_err(St *s, int code, int i, int j) {
+  long lin = (long)j * s->c.nx + i;
+  if (s->err_code == OR_OK || lin < s->err_cell) {
+    s->err_code = code;
+    s->err_cell = lin;
+  }
+}
+
+/* Real cells of material r: chi == r and alpha^r > 0; W = prim(Q / alpha).
+ * Reading (guards): rho <= 0, p + p_inf <= 0 or a non-finite value there is
+ * a non-physical state and stops the run. */
+static void real_states(St *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+  memset(s->Wv, 0, (size_t)s->M * s->NC);
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j), r = s->chi[k];
+      double a = M1(s, s->al, r, k);
+      if (!(a > 0.0)) continue;
+      double U[4], W[4];
+      for (int v = 0; v < 4; v++) U[v] = M4(s, s->Q, r, v, k) / a;
+      prim(s, r, U, W);
+      if (!(W[0] > 0.0) || !(W[3] + s->c.pinf[r] > 0.0) || !isfinite(W[1]) ||
+          !isfinite(W[2]) || !isfinite(W[0]) || !isfinite(W[3]))
+        record_err(s, OR_ENONPHYS, i, j);
+      for (int v = 0; v < 4; v++) M4(s, s->W, r, v, k) = W[v];
+      M1(s, s->Wv, r, k) = 1;
+    }
+}
+
+/* Ghost states by extrapolation (the paper defers to hu2006conservative).
+ * Reading: cells within Chebyshev distance 4 of a real cell of r form its
+ * ghost band.  Jacobi sweeps take each ghost cell from its upwind neighbours
+ * along the direction of increasing phi^r (central differences), weighted
+ * by the gradient components; only neighbours valid after the previous sweep
+ * count.  k_ext such sweeps are followed by 4 sweeps that take the mean of
+ * the valid 8-neighbours (2-neighbours in 1D) for any cell still empty, which
+ * reaches every cell of the band. */
+static void extension(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2, R = 4;
+  size_t nc = s->NC;
+  for (int r = 0; r < s->M; r++) {
+    unsigned char *v = &M1(s, s->Wv, r, 0);
+    unsigned char *rb = s->band2, *b = s->band;
+    /* ghost band: dilation of the real mask by R cells (rows, then columns) */
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        unsigned char h = 0;
+        for (int di = -R; di <= R; di++)
+          if (i + di >= 0 && i + di < nx) h |= v[ID(s, i + di, j)];
+        rb[ID(s, i, j)] = h;
+      }
+    int n = 0;
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        unsigned char h = 0;
+        for (int dj = -R * two; dj <= R * two; dj++)
+          if (j + dj >= 0 && j + dj < ny) h |= rb[ID(s, i, j + dj)];
+        b[ID(s, i, j)] = h;
+        if (h && !v[ID(s, i, j)]) s->list[n++] = ID(s, i, j);
+      }
+    int sweeps = s->c.k_ext + 4;
+    for (int it = 0; it < sweeps; it++) {
+      int upwind = it < s->c.k_ext;
+      for (int q = 0; q < n; q++) {
+        int k = s->list[q];
+        int i = k % s->NX - OR_H, j = k / s->NX - s->HY;
+        double *out = &s->lw[(size_t)q * 4];
+        s->lok[q] = 0;
+        if (v[k]) continue;
+        if (upwind) {
+          double gx = lsv(s->phi, s->chi, r, ID(s, i + 1, j)) - lsv(s->phi, s->chi, r, ID(s, i - 1, j));
+          double gy = two ? lsv(s->phi, s->chi, r, ID(s, i, j + 1)) - lsv(s->phi, s->chi, r, ID(s, i, j - 1)) : 0.0;
+          int kx = -1, ky = -1;
+          if (gx != 0.0) {
+            int ii = i + (gx > 0.0 ? 1 : -1);
+            if (ii >= 0 && ii < nx && v[ID(s, ii, j)]) kx = ID(s, ii, j);
+          }
+          if (gy != 0.0) {
+            int jj = j + (gy > 0.0 ? 1 : -1);
+            if (jj >= 0 && jj < ny && v[ID(s, i, jj)]) ky = ID(s, i, jj);
+          }
+          if (kx >= 0 && ky >= 0) {
+            double wx = fabs(gx), wy = fabs(gy);
+            for (int c = 0; c < 4; c++)
+              out[c] = (wx * M4(s, s->W, r, c, kx) + wy * M4(s, s->W, r, c, ky)) / (wx + wy);
+            s->lok[q] = 1;
+          } else if (kx >= 0) {
+            for (int c = 0; c < 4; c++) out[c] = M4(s, s->W, r, c, kx);
+            s->lok[q] = 1;
+          } else if (ky >= 0) {
+            for (int c = 0; c < 4; c++) out[c] = M4(s, s->W, r, c, ky);
+            s->lok[q] = 1;
+          }
+        } else {
+          /* mean of the valid neighbours, summed in mirror-symmetric pairs:
+             rows (-1 + +1) + 0, within a row (-1 + +1) + 0 */
+          double row[3][4];
+          int cnt = 0;
+          for (int dj = -1; dj <= 1; dj++) {
+            double a[3][4];
+            for (int di = -1; di <= 1; di++) {
+              int ii = i + di, jj = j + dj, ok2 = 0;
+              if ((di != 0 || dj != 0) && (two || dj == 0) && ii >= 0 && ii < nx &&
+                  jj >= 0 && jj < ny && v[ID(s, ii, jj)]) ok2 = 1;
+              for (int c = 0; c < 4; c++)
+                a[di + 1][c] = ok2 ? M4(s, s->W, r, c, ID(s, ii, jj)) : 0.0;
+              cnt += ok2;
+            }
+            for (int c = 0; c < 4; c++) row[dj + 1][c] = (a[0][c] + a[2][c]) + a[1][c];
+          }
+          if (cnt > 0) {
+            for (int c = 0; c < 4; c++)
+              out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
+            s->lok[q] = 1;
+          }
+        }
+      }
+      /* Jacobi: commit after the whole sweep */
+      for (int q = 0; q < n; q++) {
+        if (!s->lok[q]) continue;
+        int k = s->list[q];
+        for (int c = 0; c < 4; c++) M4(s, s->W, r, c, k) = s->lw[(size_t)q * 4 + c];
+        v[k] = 1;
+      }
+    }
+  }
+  (void)nc;
+}
+
+/* CFL time step (Sec. 2.3, Sec. 3: CFL number 0.6).  Reading: one step size
+ * per time step from the time-n state, dt = CFL h / max over real cells of
+ * max(|u| + c, |v| + c). */
+static double cfl_dt(St *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+  double smax = 0.0;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j), r = s->chi[k];
+      if (!M1(s, s->Wv, r, k)) continue;
+      double rho = M4(s, s->W, r, 0, k), u = M4(s, s->W, r, 1, k),
+             v = M4(s, s->W, r, 2, k), p = M4(s, s->W, r, 3, k);
+      double c = sqrt(s->c.gamma[r] * (p + s->c.pinf[r]) / rho);
+      double a = fabs(u) + c, b = fabs(v) + c;
+      double w = a > b ? a : b;
+      if (w > smax) smax = w;
+    }
+  return s->c.cfl * s->h / smax;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reduced interface-interaction model (Sec. 2.3.2)                          */
+/* ------------------------------------------------------------------------ */
+/* In every cell whose local set holds two or more materials only the two
+ * heaviest (by partial mass alpha rho = Q_rho) interact: a the heavier, b the
+ * other; ties go to the smaller index.  The interface is present when the
+ * closure vector c^a of a is non-zero.  Its normal n = c^a/|c^a| points into
+ * a (Reading: the closure vector replaces grad phi^a / |grad phi^a|; the two
+ * agree to first order, and this choice keeps a uniform pressure exactly in
+ * equilibrium).  The Riemann problem takes the lighter material as the left
+ * state and the heavier as the right one, each the real state where it is
+ * the cell's indicator and its ghost state otherwise.  With the HLLC contact
+ * speed S_M and star pressure p* the exchange is
+ * X^a = (0, p* c^a_x, p* c^a_y, p* S_M |c^a|), X^b = -X^a, zero for every
+ * other material.  Reading: p* is the mean of its two equal forms.  At
+ * stage 0 the interface velocity S_M n is kept for the level set. */
+static void interface_exchange(St *s, int stage) {
+  int nx = s->c.nx, ny = s->c.ny;
+  memset(s->X, 0, (size_t)s->M * 4 * s->NC * sizeof(double));
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      if (stage == 0) {
+        s->vx[k] = 0.0;
+        s->vy[k] = 0.0;
+        s->vok[k] = 0;
+      }
+      unsigned b = s->xs[k];
+      if ((b & (b - 1)) == 0) continue;
+      int a = -1, bb = -1;
+      for (int r = 0; r < s->M; r++) {
+        if (!(b >> r & 1)) continue;
+        if (a < 0 || M4(s, s->Q, r, 0, k) > M4(s, s->Q, a, 0, k)) a = r;
+      }
+      for (int r = 0; r < s->M; r++) {
+        if (!(b >> r & 1) || r == a) continue;
+        if (bb < 0 || M4(s, s->Q, r, 0, k) > M4(s, s->Q, bb, 0, k)) bb = r;
+      }
+      double cxa = M1(s, s->cx, a, k), cya = M1(s, s->cy, a, k);
+      if (cxa == 0.0 && cya == 0.0) continue;
+      if (!M1(s, s->Wv, a, k) || !M1(s, s->Wv, bb, k)) {
+        s->n_ifskip++;
+        continue;
+      }
+      double nrm = sqrt(cxa * cxa + cya * cya);
+      double nxv = cxa / nrm, nyv = cya / nrm;
+      double WL[4], WR[4];
+      WL[0] = M4(s, s->W, bb, 0, k);
+      WL[1] = M4(s, s->W, bb, 1, k) * nxv + M4(s, s->W, bb, 2, k) * nyv;
+      WL[2] = 0.0;
+      WL[3] = M4(s, s->W, bb, 3, k);
+      WR[0] = M4(s, s->W, a, 0, k);
+      WR[1] = M4(s, s->W, a, 1, k) * nxv + M4(s, s->W, a, 2, k) * nyv;
+      WR[2] = 0.0;
+      WR[3] = M4(s, s->W, a, 3, k);
+      double SL, SR;
+      wave_speeds(WL, s->c.gamma[bb], s->c.pinf[bb], WR, s->c.gamma[a], s->c.pinf[a], &SL, &SR);
+      double SM = contact_speed(WL, WR, SL, SR);
+      double pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
+      double ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
+                         (pR + WR[0] * (SR - uR) * (SM - uR)));
+      M4(s, s->X, a, 0, k) = 0.0;
+      M4(s, s->X, a, 1, k) = ps * cxa;
+      M4(s, s->X, a, 2, k) = ps * cya;
+      M4(s, s->X, a, 3, k) = ps * SM * nrm;
+      for (int v = 0; v < 4; v++) M4(s, s->X, bb, v, k) = -M4(s, s->X, a, v, k);
+      if (stage == 0) {
+        s->vx[k] = SM * nxv;
+        s->vy[k] = SM * nyv;
+        s->vok[k] = 1;
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Aperture-weighted face fluxes (Eq. discretized_equ)                       */
+/* ------------------------------------------------------------------------ */
+/* Flux of material r across a face with A^r > 0: component-wise WENO5 of the
+ * primitive variables from the six cells around the face (the right state is
+ * the same routine on the mirrored stencil), then HLLC.  Reading (guards): if
+ * a reconstructed density or p + p_inf is not positive, or a stencil cell has
+ * no state, the first-order states of the two face cells are used. */
+static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
+                     double *F) {
+  double WL[4], WR[4], Wc[6][4];
+  int ok = 1;
+  for (int q = 0; q < 6; q++) {
+    if (!M1(s, s->Wv, r, kk[q])) ok = 0;
+    for (int v = 0; v < 4; v++) Wc[q][v] = M4(s, s->W, r, v, kk[q]);
+  }
+  if (!M1(s, s->Wv, r, kk[2]) || !M1(s, s->Wv, r, kk[3])) {
+    s->n_fluxskip++;
+    for (int v = 0; v < 4; v++) F[v] = 0.0;
+    return 0;
+  }
+  /* component order: rho, normal velocity, tangential velocity, p */
+  int perm[4] = {0, normal == 0 ? 1 : 2, normal == 0 ? 2 : 1, 3};
+  if (ok) {
+    for (int v = 0; v < 4; v++) {
+      int c = perm[v];
+      WL[v] = weno5(Wc[0][c], Wc[1][c], Wc[2][c], Wc[3][c], Wc[4][c]);
+      WR[v] = weno5(Wc[5][c], Wc[4][c], Wc[3][c], Wc[2][c], Wc[1][c]);
+    }
+    double pinf = s->c.pinf[r];
+    if (!(WL[0] > 0.0) || !(WR[0] > 0.0) || !(WL[3] + pinf > 0.0) ||
+        !(WR[3] + pinf > 0.0))
+      ok = 0;
+  }
+  if (!ok) {
+    s->n_posfix++;
+    for (int v = 0; v < 4; v++) {
+      WL[v] = Wc[2][perm[v]];
+      WR[v] = Wc[3][perm[v]];
+    }
+  }
+  double G[4];
+  hllc_flux(s, r, WL, WR, G);
+  F[0] = G[0];
+  F[1 + (normal == 0 ? 0 : 1)] = G[1];
+  F[1 + (normal == 0 ? 1 : 0)] = G[2];
+  F[3] = G[3];
+  return 1;
+}
+
+static void fluxes(St *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int r = 0; r < s->M; r++) {
+    for (int j = 0; j < ny; j++)
+      for (int i = -1; i < nx; i++) {
+        int k = ID(s, i, j);
+        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        if (M1(s, s->ax, r, k) > 0.0) {
+          int kk[6];
+          for (int q = 0; q < 6; q++) kk[q] = ID(s, i - 2 + q, j);
+          face_flux(s, r, kk, 0, F);
+        }
+        for (int v = 0; v < 4; v++) M4(s, s->Fx, r, v, k) = F[v];
+      }
+    if (s->c.dim < 2) continue;
+    for (int j = -1; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, j);
+        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        if (M1(s, s->ay, r, k) > 0.0) {
+          int kk[6];
+          for (int q = 0; q < 6; q++) kk[q] = ID(s, i, j - 2 + q);
+          face_flux(s, r, kk, 1, F);
+        }
+        for (int v = 0; v < 4; v++) M4(s, s->Fy, r, v, k) = F[v];
+      }
+  }
+}
+
+/* RK-stage coefficients of the beta-form used for the level set (Eq.
+ * local-advection) and the fluid alike.  Reading: third-order SSP
+ * Runge-Kutta (Shu-Osher), beta = (0, 3/4, 1/3); rk_order 2 gives the
+ * paper's second-order TVD scheme, beta = (0, 1/2). */
+static int rk_stages(const St *s, double *b, double *c, double *w) {
+  if (s->c.rk_order == 2) {
+    b[0] = 0.0; b[1] = 0.5;
+    c[0] = 1.0; c[1] = 0.5;
+    w[0] = 0.5; w[1] = 0.5;
+    return 2;
+  }
+  b[0] = 0.0; b[1] = 0.75; b[2] = 1.0 / 3.0;
+  c[0] = 1.0; c[1] = 0.25; c[2] = 2.0 / 3.0;
+  w[0] = 1.0 / 6.0; w[1] = 1.0 / 6.0; w[2] = 2.0 / 3.0;
+  return 3;
+}
+
+/* Stage update of Eq. discretized_equ in the beta-form:
+ * Q* = b Q^n + c [Q^(s) + dt/dx (A F)_{i-1/2} - (A F)_{i+1/2}) + dt/dy (...)
+ *                 + dt/(dx dy) X].
+ * Reading: the y bracket is scaled by dt/dy (the printed dt/dx is a slip;
+ * dx = dy in every workload here).  In 1D the exchange is scaled by dt/dx. */
+static void rk_update(St *s, double b, double c, double w) {
+  int nx = s->c.nx, ny = s->c.ny;
+  double lx = s->dt / s->dx, ly = s->dt / s->dy;
+  double lv = s->c.dim == 2 ? s->dt / (s->dx * s->dy) : s->dt / s->dx;
+  for (int r = 0; r < s->M; r++)
+    for (int v = 0; v < 4; v++) {
+      for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+          int k = ID(s, i, j), kl = ID(s, i - 1, j);
+          double Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, k);
+          double fl = Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0;
+          double fr = Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, k) : 0.0;
+          double rhs = lx * (fl - fr);
+          if (s->c.dim == 2) {
+            int kb = ID(s, i, j - 1);
+            double Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, k);
+            double fb = Ab > 0.0 ? Ab * M4(s, s->Fy, r, v, kb) : 0.0;
+            double ft = At > 0.0 ? At * M4(s, s->Fy, r, v, k) : 0.0;
+            rhs = rhs + ly * (fb - ft);
+          }
+          rhs = rhs + lv * M4(s, s->X, r, v, k);
+          M4(s, s->Qt, r, v, k) = b * M4(s, s->Qn, r, v, k) + c * (M4(s, s->Q, r, v, k) + rhs);
+        }
+      /* conservation book-keeping: net inflow through the domain boundary and
+         exchange totals, weighted by the stage's share of the full step */
+      double in = 0.0;
+      for (int j = 0; j < ny; j++) {
+        int kl = ID(s, -1, j), kr = ID(s, nx - 1, j);
+        double Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, kr);
+        in += lx * ((Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0) -
+                    (Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, kr) : 0.0));
+      }
+      if (s->c.dim == 2)
+        for (int i = 0; i < nx; i++) {
+          int kb = ID(s, i, -1), kt = ID(s, i, ny - 1);
+          double Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, kt);
+          in += ly * ((Ab > 0.0 ? Ab * M4(s, s->Fy, r, v, kb) : 0.0) -
+                      (At > 0.0 ? At * M4(s, s->Fy, r, v, kt) : 0.0));
+        }
+      double xsum = 0.0;
+      for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) xsum += lv * M4(s, s->X, r, v, ID(s, i, j));
+      neumaier(&s->bnd[r][v], &s->bnd_c[r][v], w * in);
+      neumaier(&s->xsum[r][v], &s->xsum_c[r][v], w * xsum);
+    }
+}
+
+/* Advection velocity v^n of the level set (Eq. local-advection uses the
+ * time-n velocity in every sub-step).  Reading: interface cells carry the
+ * interface velocity S_M n of their Riemann problem; it is carried off the
+ * interface by 4 Jacobi sweeps over band cells (phi^n below the band width),
+ * each taking the upwind neighbours towards smaller phi weighted by the
+ * gradient components of phi; every other cell takes the velocity of its own
+ * material's state (0 if it has none). */
+static void ls_velocity(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
+  int n = 0;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      if (!s->vok[k] && s->phi[k] < s->bls) s->list[n++] = k;
+    }
+  for (int it = 0; it < 4; it++) {
+    for (int q = 0; q < n; q++) {
+      int k = s->list[q];
+      int i = k % s->NX - OR_H, j = k / s->NX - s->HY;
+      s->lok[q] = 0;
+      if (s->vok[k]) continue;
+      double gx = s->phi[ID(s, i + 1, j)] - s->phi[ID(s, i - 1, j)];
+      double gy = two ? s->phi[ID(s, i, j + 1)] - s->phi[ID(s, i, j - 1)] : 0.0;
+      int kx = -1, ky = -1;
+      if (gx != 0.0) {
+        int ii = i - (gx > 0.0 ? 1 : -1);
+        if (ii >= 0 && ii < nx && s->vok[ID(s, ii, j)]) kx = ID(s, ii, j);
+      }
+      if (gy != 0.0) {
+        int jj = j - (gy > 0.0 ? 1 : -1);
+        if (jj >= 0 && jj < ny && s->vok[ID(s, i, jj)]) ky = ID(s, i, jj);
+      }
+      double *o = &s->lv[(size_t)q * 2];
+      if (kx >= 0 && ky >= 0) {
+        double wx = fabs(gx), wy = fabs(gy);
+        o[0] = (wx * s->vx[kx] + wy * s->vx[ky]) / (wx + wy);
+        o[1] = (wx * s->vy[kx] + wy * s->vy[ky]) / (wx + wy);
+        s->lok[q] = 1;
+      } else if (kx >= 0) {
+        o[0] = s->vx[kx];
+        o[1] = s->vy[kx];
+        s->lok[q] = 1;
+      } else if (ky >= 0) {
+        o[0] = s->vx[ky];
+        o[1] = s->vy[ky];
+        s->lok[q] = 1;
+      }
+    }
+    for (int q = 0; q < n; q++)
+      if (s->lok[q]) {
+        int k = s->list[q];
+        s->vx[k] = s->lv[(size_t)q * 2];
+        s->vy[k] = s->lv[(size_t)q * 2 + 1];
+        s->vok[k] = 1;
+      }
+  }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j), r = s->chi[k];
+      if (s->vok[k]) continue;
+      if (M1(s, s->Wv, r, k)) {
+        s->vx[k] = M4(s, s->W, r, 1, k);
+        s->vy[k] = M4(s, s->W, r, 2, k);
+      }
+    }
+}
+
+/* Level-set update region.  Reading: the narrow band is the set of cells
+ * with phi below the band width or a mixed local set; a cell is updated when
+ * such a cell lies within Chebyshev distance 3 (the reach of the HJ-WENO5
+ * stencil), so the band follows a moving interface; all other cells keep
+ * phi at the band width. */
+static void ls_region(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
+  unsigned char *f = s->band, *rb = s->band2;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      unsigned b = s->xs[k];
+      f[k] = (unsigned char)(s->phi[k] < s->bls || (b & (b - 1)) != 0);
+    }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      unsigned char h = 0;
+      for (int di = -3; di <= 3; di++)
+        if (i + di >= 0 && i + di < nx) h |= f[ID(s, i + di, j)];
+      rb[ID(s, i, j)] = h;
+    }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      unsigned char h = 0;
+      for (int dj = -3 * two; dj <= 3 * two; dj++)
+        if (j + dj >= 0 && j + dj < ny) h |= rb[ID(s, i, j + dj)];
+      s->reg[ID(s, i, j)] = h;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-set stage (Sec. 2.2, Eq. local-advection and Eq. reconstruction)   */
+/* ------------------------------------------------------------------------ */
+/* For every cell of the update region and every r in its local set X_s: construct phi^r on the stencil, take the HJ-WENO5 upwind
+ * derivative (the WENO5 routine applied to the five one-sided divided
+ * differences on the upwind side of v^n), advance with the beta-form, then
+ * reconstruct phi = |max_r phi^r|, chi = argmax_r phi^r (ties: smaller
+ * index).  Reading: phi is clamped to the band width; cells outside the
+ * region keep their values; no reinitialisation is applied. */
+static double hj_deriv(St *s, int r, int i, int j, int dir, double vel) {
+  double d[7]; /* divided differences d(q) = (phi_q - phi_{q-1})/h, q = i-2 .. i+3 */
+  double ih = dir == 0 ? s->idx : s->idy;
+  for (int q = 0; q < 6; q++) {
+    int o = q - 2;
+    int k1 = dir == 0 ? ID(s, i + o, j) : ID(s, i, j + o);
+    int k0 = dir == 0 ? ID(s, i + o - 1, j) : ID(s, i, j + o - 1);
+    d[q] = (lsv(s->phi, s->chi, r, k1) - lsv(s->phi, s->chi, r, k0)) * ih;
+  }
+  if (vel > 0.0) return weno5(d[0], d[1], d[2], d[3], d[4]);
+  if (vel < 0.0) return weno5(d[5], d[4], d[3], d[2], d[1]);
+  return 0.0;
+}
+
+static void levelset_stage(St *s, double b, double c) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      if (!s->reg[k]) {
+        s->phit[k] = s->phi[k];
+        s->chit[k] = s->chi[k];
+        continue;
+      }
+      double best = 0.0;
+      int br = -1;
+      for (int r = 0; r < s->M; r++) {
+        if (!(s->xs[k] >> r & 1)) continue;
+        double gx = hj_deriv(s, r, i, j, 0, s->vx[k]);
+        double adv = s->vx[k] * gx;
+        if (s->c.dim == 2) {
+          double gy = hj_deriv(s, r, i, j, 1, s->vy[k]);
+          adv = adv + s->vy[k] * gy;
+        }
+        double val = lsv(s->phi, s->chi, r, k) - s->dt * adv;
+        double nv = b * lsv(s->phin, s->chin, r, k) + c * val;
+        if (br < 0 || nv > best) {
+          best = nv;
+          br = r;
+        }
+      }
+      double a = fabs(best);
+      s->phit[k] = a < s->bls ? a : s->bls;
+      s->chit[k] = br;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mixing of small, new and vanishing cut cells (Sec. 2.3.2, after each RK  */
+/* sub-step)                                                                */
+/* ------------------------------------------------------------------------ */
+/* Reading (the weights of hu2006conservative are not reproduced in the
+ * paper): for each material r, a source cell has 0 < alpha < alpha_mix, or
+ * alpha > 0 with its centre outside r (chi != r: it has no real state of
+ * its own), or alpha = 0 with a non-zero state.  Its targets are the
+ * neighbours in x, in y and diagonally along the side of increasing phi^r
+ * (central differences g); a target needs alpha_t >= alpha_mix and chi = r.  Weights g_x^2 alpha_x,
+ * g_y^2 alpha_y and |g_x g_y| alpha_xy, normalised.  Exchange from target t:
+ * M_t = beta_t (alpha_s Q_t - alpha_t Q_s)/(alpha_s + alpha_t), added to the
+ * source and taken from the target, all from pre-mixing values (a target
+ * sums what it receives in mirror-symmetric pairs of neighbours).  For a
+ * vanishing source (alpha_s = 0) this is M_t = -beta_t Q_s; the last target
+ * in the order x, y, diagonal takes the exact remainder, so the source is
+ * left at exactly zero.  Without an
+ * eligible target the 8-neighbour (2-neighbour in 1D) of largest alpha >=
+ * alpha_mix and chi = r takes the whole exchange (ties: lower linear index); without one
+ * the cell is left as it is and counted. */
+static void mixing(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
+  double amix = s->c.alpha_mix;
+  size_t nc = s->NC;
+  for (int r = 0; r < s->M; r++) {
+    int *T = s->mixT;
+    double *Mx = s->mixM;
+    for (size_t q = 0; q < 3 * nc; q++) T[q] = -1;
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, j);
+        double as = M1(s, s->al, r, k);
+        if (!(as < amix) && s->chit[k] == r) continue;
+        if (!(as > 0.0)) {
+          int nz = 0;
+          for (int v = 0; v < 4; v++)
+            if (M4(s, s->Qt, r, v, k) != 0.0) nz = 1;
+          if (!nz) continue;
+        }
+        s->n_mixsrc++;
+        double gx = lsv(s->phit, s->chit, r, ID(s, i + 1, j)) - lsv(s->phit, s->chit, r, ID(s, i - 1, j));
+        double gy = two ? lsv(s->phit, s->chit, r, ID(s, i, j + 1)) - lsv(s->phit, s->chit, r, ID(s, i, j - 1)) : 0.0;
+        int sx = gx > 0.0 ? 1 : (gx < 0.0 ? -1 : 0);
+        int sy = gy > 0.0 ? 1 : (gy < 0.0 ? -1 : 0);
+        int tk[3] = {-1, -1, -1};
+        double w[3] = {0.0, 0.0, 0.0};
+        if (sx != 0 && i + sx >= 0 && i + sx < nx) {
+          int t = ID(s, i + sx, j);
+          double at = M1(s, s->al, r, t);
+          if (at >= amix && s->chit[t] == r) { tk[0] = t; w[0] = gx * gx * at; }
+        }
+        if (sy != 0 && j + sy >= 0 && j + sy < ny) {
+          int t = ID(s, i, j + sy);
+          double at = M1(s, s->al, r, t);
+          if (at >= amix && s->chit[t] == r) { tk[1] = t; w[1] = gy * gy * at; }
+        }
+        if (sx != 0 && sy != 0 && i + sx >= 0 && i + sx < nx && j + sy >= 0 && j + sy < ny) {
+          int t = ID(s, i + sx, j + sy);
+          double at = M1(s, s->al, r, t);
+          if (at >= amix && s->chit[t] == r) { tk[2] = t; w[2] = fabs(gx * gy) * at; }
+        }
+        double wsum = (w[0] + w[1]) + w[2];
+        double beta[3] = {0.0, 0.0, 0.0};
+        if (wsum > 0.0) {
+          for (int q = 0; q < 3; q++)
+            if (w[q] > 0.0) beta[q] = w[q] / wsum;
+            else tk[q] = -1;
+        } else {
+          tk[0] = tk[1] = tk[2] = -1;
+          double bestA = -1.0;
+          int bt = -1;
+          for (int dj = -two; dj <= two; dj++)
+            for (int di = -1; di <= 1; di++) {
+              if (di == 0 && dj == 0) continue;
+              int ii = i + di, jj = j + dj;
+              if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+              int t = ID(s, ii, jj);
+              double at = M1(s, s->al, r, t);
+              if (at >= amix && s->chit[t] == r && at > bestA) { bestA = at; bt = t; }
+            }
+          if (bt < 0) {
+            s->n_stranded++;
+            continue;
+          }
+          tk[0] = bt;
+          beta[0] = 1.0;
+        }
+        int last = -1;
+        for (int q = 0; q < 3; q++) {
+          T[(size_t)q * nc + k] = tk[q];
+          if (tk[q] >= 0) last = q;
+        }
+        if (as > 0.0) {
+          for (int q = 0; q < 3; q++) {
+            if (tk[q] < 0) continue;
+            double at = M1(s, s->al, r, tk[q]);
+            for (int v = 0; v < 4; v++) {
+              double Qs = M4(s, s->Qt, r, v, k), Qtg = M4(s, s->Qt, r, v, tk[q]);
+              Mx[((size_t)q * 4 + v) * nc + k] = beta[q] * ((as * Qtg - at * Qs) / (as + at));
+            }
+          }
+        } else {
+          /* vanishing cell: with alpha_s = 0 the exchange is M_t = -beta_t Q_s;
+             the last target takes the exact remainder so the source ends at 0 */
+          for (int v = 0; v < 4; v++) {
+            double Qs = M4(s, s->Qt, r, v, k), acc = Qs;
+            for (int q = 0; q < 3; q++) {
+              if (tk[q] < 0) continue;
+              double m = q == last ? -acc : -(beta[q] * Qs);
+              Mx[((size_t)q * 4 + v) * nc + k] = m;
+              acc = acc + m;
+            }
+          }
+        }
+      }
+    /* apply as a gather: sources add their exchanges in target order, targets
+       subtract what their 8 neighbours sent them, in row-major order */
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, j);
+        for (int v = 0; v < 4; v++) {
+          double q0 = M4(s, s->Qt, r, v, k);
+          int src = 0;
+          for (int q = 0; q < 3; q++)
+            if (T[(size_t)q * nc + k] >= 0) {
+              q0 = q0 + Mx[((size_t)q * 4 + v) * nc + k];
+              src = 1;
+            }
+          if (!src) {
+            /* received exchanges, summed in mirror-symmetric pairs */
+            double row[3];
+            for (int dj = -1; dj <= 1; dj++) {
+              double a[3] = {0.0, 0.0, 0.0};
+              for (int di = -1; di <= 1; di++) {
+                int ii = i + di, jj = j + dj;
+                if ((di == 0 && dj == 0) || (!two && dj != 0) || ii < 0 || ii >= nx ||
+                    jj < 0 || jj >= ny) continue;
+                int n = ID(s, ii, jj);
+                for (int q = 0; q < 3; q++)
+                  if (T[(size_t)q * nc + n] == k) a[di + 1] = Mx[((size_t)q * 4 + v) * nc + n];
+              }
+              row[dj + 1] = (a[0] + a[2]) + a[1];
+            }
+            q0 = q0 - ((row[0] + row[2]) + row[1]);
+          }
+          M4(s, s->Q, r, v, k) = q0;
+        }
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public C API used by the tests through ctypes                            */
+/* ------------------------------------------------------------------------ */
+static void *zalloc(size_t n) { return calloc(n ? n : 1, 1); }
+
+void or_destroy(St *s) {
+  if (!s) return;
+  void *p[] = {s->phi, s->phin, s->phit, s->chi, s->chin, s->chit, s->Q,
+               s->Qn, s->Qt, s->al, s->ax, s->ay, s->cx, s->cy, s->W, s->lw,
+               s->Wv, s->lok, s->band, s->band2, s->list, s->vok, s->reg, s->lv, s->X, s->vx, s->vy, s->Fx, s->Fy,
+               s->mass, s->cv, s->co, s->xs, s->mixM, s->mixT};
+  for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); i++) free(p[i]);
+  free(s);
+}
+
+St *or_create(const or_config *c) {
+  if (!c || (c->dim != 1 && c->dim != 2) || c->nx < 1 || c->ny < 1 ||
+      (c->dim == 1 && c->ny != 1) || c->n_mat < 1 || c->n_mat > OR_MAXM)
+    return NULL;
+  St *s = (St *)zalloc(sizeof(St));
+  s->c = *c;
+  s->M = c->n_mat;
+  s->NX = c->nx + 2 * OR_H;
+  s->HY = c->dim == 2 ? OR_H : 0;
+  s->NY = c->ny + 2 * s->HY;
+  s->NC = s->NX * s->NY;
+  s->dx = (c->x1 - c->x0) / c->nx;
+  s->dy = c->dim == 2 ? (c->y1 - c->y0) / c->ny : 1.0;
+  s->h = c->dim == 2 ? (s->dx < s->dy ? s->dx : s->dy) : s->dx;
+  s->bls = c->band_ls * s->h;
+  s->idx = 1.0 / s->dx;
+  s->idy = 1.0 / s->dy;
+  for (int m = 0; m < s->M; m++) s->igm1[m] = 1.0 / (c->gamma[m] - 1.0);
+  size_t nc = s->NC, M = s->M;
+  s->phi = zalloc(nc * 8); s->phin = zalloc(nc * 8); s->phit = zalloc(nc * 8);
+  s->chi = zalloc(nc * 4); s->chin = zalloc(nc * 4); s->chit = zalloc(nc * 4);
+  s->Q = zalloc(M * 4 * nc * 8); s->Qn = zalloc(M * 4 * nc * 8); s->Qt = zalloc(M * 4 * nc * 8);
+  s->al = zalloc(M * nc * 8); s->ax = zalloc(M * nc * 8); s->ay = zalloc(M * nc * 8);
+  s->cx = zalloc(M * nc * 8); s->cy = zalloc(M * nc * 8);
+  s->W = zalloc(M * 4 * nc * 8); s->lw = zalloc(4 * nc * 8);
+  s->Wv = zalloc(M * nc); s->lok = zalloc(nc); s->band = zalloc(nc);
+  s->band2 = zalloc(nc); s->list = zalloc(nc * 4);
+  s->X = zalloc(M * 4 * nc * 8);
+  s->vx = zalloc(nc * 8); s->vy = zalloc(nc * 8);
+  s->vok = zalloc(nc); s->reg = zalloc(nc); s->lv = zalloc(2 * nc * 8);
+  s->Fx = zalloc(M * 4 * nc * 8); s->Fy = zalloc(M * 4 * nc * 8);
+  s->mass = zalloc(M * nc * 8);
+  s->cv = zalloc(nc * 8); s->co = zalloc(nc * 4); s->xs = zalloc(nc);
+  s->mixM = zalloc(3 * 4 * nc * 8); s->mixT = zalloc(3 * nc * 4);
+  if (!s->mixT || !s->mixM || !s->Q) {
+    or_destroy(s);
+    return NULL;
+  }
+  return s;
+}
+
+/* Initial state: phi, chi [ny][nx]; W [n_mat][dim+2][ny][nx] primitive
+ * (rho, u, [v], p) of each material, used wherever that material has a
+ * volume fraction.  Q^0 = alpha^0 U(W), with alpha^0 corrected by the
+ * masses alpha * rho. */
+int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      if (chi[q] < 0 || chi[q] >= s->M || !(phi[q] >= 0.0)) return OR_EINVAL;
+      s->phi[ID(s, i, j)] = phi[q];
+      s->chi[ID(s, i, j)] = chi[q];
+    }
+  fill_ls(s, s->phi, s->chi);
+  geometry(s, s->phi, s->chi);
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        size_t q = (size_t)j * nx + i;
+        M1(s, s->mass, r, ID(s, i, j)) =
+            M1(s, s->al, r, ID(s, i, j)) * W[((size_t)r * nv + 0) * plane + q];
+      }
+  vf_correction(s, s->chi, s->mass);
+  s->err_code = OR_OK;
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        size_t q = (size_t)j * nx + i;
+        int k = ID(s, i, j);
+        double a = M1(s, s->al, r, k);
+        double w[4];
+        w[0] = W[((size_t)r * nv + 0) * plane + q];
+        w[1] = W[((size_t)r * nv + 1) * plane + q];
+        w[2] = nv == 4 ? W[((size_t)r * nv + 2) * plane + q] : 0.0;
+        w[3] = W[((size_t)r * nv + nv - 1) * plane + q];
+        if (a > 0.0 && (!(w[0] > 0.0) || !(w[3] + s->c.pinf[r] > 0.0) ||
+                        !isfinite(w[1]) || !isfinite(w[2])))
+          record_err(s, OR_ENONPHYS, i, j);
+        double U[4];
+        U[0] = w[0];
+        U[1] = w[0] * w[1];
+        U[2] = w[0] * w[2];
+        U[3] = energy(s, r, w[0], w[1], w[2], w[3]);
+        for (int v = 0; v < 4; v++) M4(s, s->Q, r, v, k) = a > 0.0 ? a * U[v] : 0.0;
+      }
+  s->t = 0.0;
+  s->nstep = 0;
+  memset(s->bnd, 0, sizeof(s->bnd));
+  memset(s->bnd_c, 0, sizeof(s->bnd_c));
+  memset(s->xsum, 0, sizeof(s->xsum));
+  memset(s->xsum_c, 0, sizeof(s->xsum_c));
+  return s->err_code;
+}
+
+/* Replay a fixed step size instead of the CFL one (0 = CFL). */
+void or_set_dt(St *s, double dt) { s->dt_fixed = dt; }
+
+/* One full time step in the fixed stage order: primitive and ghost states,
+ * (dt at stage 0), interface exchange, fluxes and RK update, level-set
+ * stage, frame of the level set, geometry + correction of the new stage,
+ * mixing. */
+int or_step(St *s, int nsteps) {
+  double b[3], c[3], w[3];
+  int ns = rk_stages(s, b, c, w);
+  size_t qb = (size_t)s->M * 4 * s->NC * sizeof(double);
+  for (int n = 0; n < nsteps; n++) {
+    memcpy(s->Qn, s->Q, qb);
+    memcpy(s->phin, s->phi, s->NC * sizeof(double));
+    memcpy(s->chin, s->chi, s->NC * sizeof(int));
+    for (int st = 0; st < ns; st++) {
+      s->err_code = OR_OK;
+      local_sets(s, s->chi, s->xs);
+      real_states(s);
+      if (s->err_code) return s->err_code;
+      if (st == 0) s->dt = s->dt_fixed > 0.0 ? s->dt_fixed : cfl_dt(s);
+      extension(s);
+      fill_W(s);
+      interface_exchange(s, st);
+      if (st == 0) ls_velocity(s);
+      fluxes(s);
+      rk_update(s, b[st], c[st], w[st]);
+      ls_region(s);
+      levelset_stage(s, b[st], c[st]);
+      fill_ls(s, s->phit, s->chit);
+      geometry(s, s->phit, s->chit);
+      for (int r = 0; r < s->M; r++)
+        for (size_t k = 0; k < (size_t)s->NC; k++)
+          M1(s, s->mass, r, k) = M4(s, s->Qt, r, 0, k);
+      vf_correction(s, s->chit, s->mass);
+      mixing(s);
+      double *tp = s->phi; s->phi = s->phit; s->phit = tp;
+      int *tc = s->chi; s->chi = s->chit; s->chit = tc;
+    }
+    s->t += s->dt;
+    s->nstep++;
+  }
+  return OR_OK;
+}
+
+/* Copy out Q [n_mat][dim+2][ny][nx], alpha [n_mat][ny][nx] (nullable),
+ * phi, chi [ny][nx] (nullable). */
+int or_get(const St *s, double *Q, double *alpha, double *phi, int32_t *chi) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      int k = ID(s, i, j);
+      for (int r = 0; r < s->M; r++) {
+        if (Q) {
+          Q[((size_t)r * nv + 0) * plane + q] = M4(s, s->Q, r, 0, k);
+          Q[((size_t)r * nv + 1) * plane + q] = M4(s, s->Q, r, 1, k);
+          if (nv == 4) Q[((size_t)r * nv + 2) * plane + q] = M4(s, s->Q, r, 2, k);
+          Q[((size_t)r * nv + nv - 1) * plane + q] = M4(s, s->Q, r, 3, k);
+        }
+        if (alpha) alpha[(size_t)r * plane + q] = M1(s, s->al, r, k);
+      }
+      if (phi) phi[q] = s->phi[k];
+      if (chi) chi[q] = s->chi[k];
+    }
+  return OR_OK;
+}
+
+/* Face apertures of the current geometry: Ax [n_mat][ny][nx+1] (x-face i-1/2
+ * at column i), Ay [n_mat][ny+1][nx] (y-face j-1/2 at row j). */
+int or_get_apertures(const St *s, double *Ax, double *Ay) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int r = 0; r < s->M; r++) {
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i <= nx; i++)
+        Ax[((size_t)r * ny + j) * (nx + 1) + i] = M1(s, s->ax, r, ID(s, i - 1, j));
+    if (Ay && s->c.dim == 2)
+      for (int j = 0; j <= ny; j++)
+        for (int i = 0; i < nx; i++)
+          Ay[((size_t)r * (ny + 1) + j) * nx + i] = M1(s, s->ay, r, ID(s, i, j - 1));
+  }
+  return OR_OK;
+}
+
+/* Diagnostics: out[0..7] = t, dt, steps, positivity fallbacks, skipped
+ * fluxes, skipped interfaces, stranded mixing sources, mixing sources;
+ * then bnd[n_mat][4] (net boundary inflow) and xsum[n_mat][4] (exchange
+ * totals), both as increments of sum(Q). */
+int or_diag(const St *s, double *out) {
+  out[0] = s->t;
+  out[1] = s->dt;
+  out[2] = (double)s->nstep;
+  out[3] = (double)s->n_posfix;
+  out[4] = (double)s->n_fluxskip;
+  out[5] = (double)s->n_ifskip;
+  out[6] = (double)s->n_stranded;
+  out[7] = (double)s->n_mixsrc;
+  for (int r = 0; r < s->M; r++)
+    for (int v = 0; v < 4; v++) {
+      out[8 + r * 4 + v] = s->bnd[r][v] + s->bnd_c[r][v];
+      out[8 + s->M * 4 + r * 4 + v] = s->xsum[r][v] + s->xsum_c[r][v];
+    }
+  return OR_OK;
+}
+
+long or_err_cell(const St *s) { return s->err_cell; }
+
+/* ------------------------------------------------------------------------ */
+/* Unit entry points for the oracle's own pins                              */
+/* ------------------------------------------------------------------------ */
+double or_t_weno5(double v1, double v2, double v3, double v4, double v5) {
+  return weno5(v1, v2, v3, v4, v5);
+}
+
+/* HLLC face flux of material m between primitive states (rho, un, ut, p). */
+void or_t_hllc(const St *s, int m, const double *WL, const double *WR, double *F) {
+  hllc_flux(s, m, WL, WR, F);
+}
+
+/* Interface Riemann problem between material mL (left state) and mR (right
+ * state), states (rho, un, ut, p); out = (S_L, S_R, S_M, p*). */
+void or_t_iface(const St *s, int mL, const double *WL, int mR, const double *WR,
+                double *out) {
+  double SL, SR;
+  wave_speeds(WL, s->c.gamma[mL], s->c.pinf[mL], WR, s->c.gamma[mR], s->c.pinf[mR], &SL, &SR);
+  double SM = contact_speed(WL, WR, SL, SR);
+  double pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
+  out[0] = SL;
+  out[1] = SR;
+  out[2] = SM;
+  out[3] = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) + (pR + WR[0] * (SR - uR) * (SM - uR)));
+}
+
+/* Interface closure vectors of the current geometry, [n_mat][ny][nx] each. */
+int or_get_closure(const St *s, double *cx, double *cy) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        size_t q = ((size_t)r * ny + j) * nx + i;
+        cx[q] = M1(s, s->cx, r, ID(s, i, j));
+        cy[q] = M1(s, s->cy, r, ID(s, i, j));
+      }
+  return OR_OK;
+}
