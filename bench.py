@@ -1,0 +1,110 @@
+#!/usr/bin/env python3
+"""Throughput of the cut-cell multi-material step on one MI355X.
+
+One "step" is one full time step of the method (all Runge-Kutta stages of
+geometry, ghost states, interface exchange, fluxes, level set and mixing)
+on the 2D triple-point problem (Case III of the paper, 7 x 3 box, 896 x 384
+uniform cells, three ideal gases, reflective walls), FP64, synthetic analytic
+initial data already resident on the GPU.  The unit of work is one active
+material-cell RK-substep update (a cell/material pair with alpha > 0,
+updated in one stage), counted on the device.
+
+Prints one JSON line.  Also reports the dominant kernel against the HBM
+roofline (HIP events around its launches on the stream it runs on) and the
+CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(workload, steps):
+    import oracle
+    o = oracle.Oracle(workload["cfg"])
+    assert o.init(workload["phi"], workload["chi"], workload["W"]) == 0
+    t0 = time.perf_counter()
+    rc = o.step(steps)
+    el = time.perf_counter() - t0
+    if rc:
+        return None
+    d = o.diag()
+    return dict(value=d["n_updates"] / el, unit="updates/s", cores=1, kind="oracle",
+                sample=f"{workload['name']} {workload['cfg']['nx']}x{workload['cfg']['ny']}, "
+                       f"first {steps} steps from t=0, single-threaded C oracle "
+                       f"({d['n_updates']} updates in {el:.2f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1704_00519_amd as pk
+    import workloads as wl
+
+    w = wl.triple_point()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    s = pk.Solver(w["cfg"], stream=stream.cuda_stream)
+    s.init(w["phi"], w["chi"], w["W"])
+    if args.warmup:
+        s.step(args.warmup)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    d0 = s.diag()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    d1 = s.diag()
+    prof = s.profile()
+    updates = d1["n_updates"] - d0["n_updates"]
+    value = updates / (ms * 1e-3)
+
+    bulk_s = prof["bulk_ms"] * 1e-3
+    achieved = prof["bulk_bytes"] / bulk_s / 1e9 if bulk_s > 0 else 0.0
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="k_flux_bulk2",
+                    launches=prof["bulk_launches"],
+                    avg_launch_us=round(prof["bulk_ms"] * 1e3 / max(1, prof["bulk_launches"]), 2),
+                    bytes_per_launch=prof["bulk_bytes"] / max(1, prof["bulk_launches"]),
+                    share_of_step=round(prof["bulk_ms"] / ms, 4))
+    out = dict(metric="material-cell RK-substep updates/sec (plain)",
+               value=value, unit="updates/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="triple_point_896x384", grid=[896, 384],
+                           materials=3, rk_stages=3, cfl=0.6,
+                           t_start=d0["t"], t_end=d1["t"],
+                           wall_s=round(wall, 3)),
+               roofline=roofline)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

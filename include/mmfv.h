@@ -1,0 +1,155 @@
+/*
+ * mmfv.h -- C ABI of the MI355X (gfx950) library for the conservative
+ * sharp-interface method for compressible multi-material flows of Pan, Han,
+ * Hu & Adams (arXiv:1704.00519).
+ *
+ * One context advances one uniform-grid problem (1D or 2D) of up to
+ * MM_MAX_MAT materials, each with its own stiffened-gas EOS, in FP64 on one
+ * GPU.  The state is the regional level set (unsigned distance phi >= 0 and
+ * integer indicator chi, Sec. 2.2) plus, per material r, the conserved cell
+ * averages Q^r = alpha^r U^r (Eq. discretized_equ).  One call of mm_step
+ * advances whole time steps of the method: cut-cell geometry from the level
+ * set (Sec. 2.3), volume-fraction correction in cells of three or more
+ * materials (Sec. 2.3.1, Eq. vol_corr2), per-material WENO5 / HLLC fluxes
+ * scaled by apertures, the reduced interface-exchange model (Sec. 2.3.2),
+ * the multi-region level-set advance (Sec. 2.2, Eq. local-advection and
+ * Eq. reconstruction), mixing of small/new/vanishing cells after every
+ * Runge-Kutta sub-step, with the third-order SSP Runge-Kutta scheme in the
+ * beta-form of Eq. local-advection.
+ *
+ * Conventions
+ *   Arrays crossing the ABI are C-ordered, interior cells only:
+ *     phi, chi   [ny][nx]
+ *     W, Q       [n_mat][dim+2][ny][nx], components (rho, u, [v], p) for W and
+ *                (rho, rho u, [rho v], rho E) for Q = alpha U
+ *     alpha      [n_mat][ny][nx]
+ *   ny = 1 in 1D.  ptr_kind says whether pointers are host (MM_HOST) or
+ *   device (MM_DEVICE) memory of the context's GPU; device pointers may be
+ *   torch tensors' data_ptr().  Pointers are borrowed for the call only.
+ *   All work is enqueued on the stream given to mm_create; calls that return
+ *   data to host memory, or report errors, synchronise that stream.
+ *
+ * Errors: every function returns an mm_status; no exceptions cross the ABI.
+ * mm_last_error() gives a message for the last failure on a context.
+ */
+#ifndef MMFV_H
+#define MMFV_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_EINVAL = 1,    /* bad argument or configuration; nothing was changed  */
+  MM_ENOMEM = 2,    /* device allocation failed                            */
+  MM_EDEVICE = 3,   /* HIP runtime error                                   */
+  MM_ENONPHYS = 4,  /* rho <= 0, p + p_inf <= 0 or non-finite in a real cell */
+  MM_ESTATE = 5,    /* call order (e.g. mm_step before mm_init_state)      */
+  MM_ENOTIMPL = 6   /* entry point declared but not available              */
+} mm_status;
+
+enum { MM_BC_TRANSMISSIVE = 0, MM_BC_REFLECTIVE = 1, MM_BC_INFLOW = 2,
+       MM_BC_OUTFLOW = 3 };
+enum { MM_HOST = 0, MM_DEVICE = 1 };
+#define MM_MAX_MAT 8
+
+/* Problem description (plain old data, caller-owned, copied by mm_create). */
+typedef struct {
+  int32_t dim, nx, ny, n_mat;    /* dim 1 or 2; ny = 1 when dim = 1         */
+  double x0, x1, y0, y1;         /* domain; cells are (x1-x0)/nx wide       */
+  double gamma[MM_MAX_MAT];      /* stiffened gas: p = (gamma-1) rho e      */
+  double pinf[MM_MAX_MAT];       /*                    - gamma p_inf        */
+  int32_t bc[4];                 /* MM_BC_* of x-lo, x-hi, y-lo, y-hi       */
+  double inflow_W[4];            /* (rho, u, v, p) on MM_BC_INFLOW sides    */
+  int32_t inflow_mat, rk_order;  /* material of the inflow; 3 (or 2)        */
+  double cfl, alpha_mix;         /* CFL number (0.6); mixing threshold 0.5  */
+  int32_t k_ext, band_ls;        /* upwind ghost sweeps (8); band width in  */
+                                 /* cells of the level set (8)              */
+} mm_config;
+
+/* Diagnostics of a context (mm_get_diagnostics). */
+typedef struct {
+  double t, dt;            /* time reached, last step size                  */
+  int64_t steps;           /* time steps taken                              */
+  int64_t n_posfix;        /* faces that fell back to first-order states    */
+  int64_t n_fluxskip;      /* faces with A > 0 whose cells had no state     */
+  int64_t n_ifskip;        /* interfaces skipped for lack of a ghost state  */
+  int64_t n_stranded;      /* mixing sources without an eligible target     */
+  int64_t n_mixsrc;        /* mixing sources processed                      */
+  int64_t n_updates;       /* active material-cell RK-substep updates       */
+  int64_t err_cell;        /* j*nx+i of the lowest non-physical real cell   */
+                           /* found, -1 if none                             */
+} mm_diag;
+
+typedef struct mm_ctx mm_ctx;
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null
+ * stream.  MM_EINVAL for an invalid configuration (dim, sizes, n_mat,
+ * gamma <= 1, bc codes, rk_order, cfl <= 0). */
+mm_status mm_create(const mm_config *cfg, void *hip_stream, mm_ctx **out);
+
+/* Initial state (Sec. 2.2 / Eq. discretized_equ): phi >= 0 and chi in
+ * [0, n_mat) per cell, and for every material a primitive field W that is
+ * used wherever that material has a volume fraction.  Builds the cut-cell
+ * geometry, applies the volume-fraction correction with masses alpha*rho,
+ * and sets Q^0 = alpha U(W).  MM_EINVAL for NULL arrays; MM_ENONPHYS if a
+ * state with alpha > 0 is non-physical. */
+mm_status mm_init_state(mm_ctx *ctx, const double *phi, const int32_t *chi,
+                        const double *W, int32_t ptr_kind);
+
+/* Advance n_steps time steps (one step = all Runge-Kutta stages, with the
+ * step size from the CFL condition of the time-n state, or the value set by
+ * mm_set_dt).  record_tape must be 0 (no adjoint tape is kept).  If t_out is
+ * not NULL it receives the time reached.  Synchronises the stream and
+ * returns MM_ENONPHYS if a non-physical real state appeared (the state is
+ * then undefined; err_cell in the diagnostics names the cell). */
+mm_status mm_step(mm_ctx *ctx, int32_t n_steps, int32_t record_tape,
+                  double *t_out);
+
+/* Copy out Q (required) and, if not NULL, alpha, phi and chi of the current
+ * state, interior cells only, in the layouts above. */
+mm_status mm_get_conserved(mm_ctx *ctx, double *Q, double *alpha,
+                           double *phi, int32_t *chi, int32_t ptr_kind);
+
+/* Diagnostics; synchronises the stream. */
+mm_status mm_get_diagnostics(mm_ctx *ctx, mm_diag *out);
+
+/* Replay a fixed step size instead of the CFL one; dt <= 0 restores CFL. */
+mm_status mm_set_dt(mm_ctx *ctx, double dt);
+
+/* Adjoint of one time step (reverse of the step above).  Declared for the
+ * differentiation form of the method; returns MM_ENOTIMPL in this build. */
+mm_status mm_adjoint_step(mm_ctx *ctx, const double *lamQ_in,
+                          const double *lamPhi_in, double *lamQ_out,
+                          double *lamPhi_out, int32_t ptr_kind);
+
+/* Measurement of the dominant kernel.  With profiling enabled, every launch
+ * of the bulk flux/update kernel (cells away from interfaces) is bracketed
+ * by HIP events on the context's stream; mm_get_profile synchronises and
+ * returns the summed kernel time, the number of launches, and the
+ * algorithmic HBM bytes those launches had to move (per bulk update: read
+ * Q^(s), write Q^(s+1), and read Q^n in every stage but the first; 8-byte
+ * words of dim+2 components). */
+typedef struct {
+  double bulk_ms;          /* summed duration of the bulk launches          */
+  int64_t bulk_launches;
+  int64_t bulk_updates;    /* material-cell updates done by those launches  */
+  double bulk_bytes;       /* algorithmic bytes of those updates            */
+} mm_profile;
+mm_status mm_set_profiling(mm_ctx *ctx, int32_t enable);
+mm_status mm_get_profile(mm_ctx *ctx, mm_profile *out);
+
+/* Release every device buffer of the context. */
+mm_status mm_destroy(mm_ctx *ctx);
+
+/* Message of the last failure on ctx (thread-unsafe; valid until the next
+ * call on ctx).  NULL ctx gives the last mm_create failure. */
+const char *mm_last_error(const mm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMFV_H */

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmfv_oracle.c")
 _LIB = os.path.join(_HERE, "libmmfv_oracle.so")
 MAXM = 8
-N_DIAG_HEAD = 8
+N_DIAG_HEAD = 9
 
 
 def build(force=True):
@@ -173,9 +173,9 @@ class Oracle:
         return dict(t=head[0], dt=head[1], steps=int(head[2]),
                     n_posfix=int(head[3]), n_fluxskip=int(head[4]),
                     n_ifskip=int(head[5]), n_stranded=int(head[6]),
-                    n_mixsrc=int(head[7]),
-                    bnd=out[8:8 + 4 * M].reshape(M, 4),
-                    xsum=out[8 + 4 * M:8 + 8 * M].reshape(M, 4))
+                    n_mixsrc=int(head[7]), n_updates=int(head[8]),
+                    bnd=out[9:9 + 4 * M].reshape(M, 4),
+                    xsum=out[9 + 4 * M:9 + 8 * M].reshape(M, 4))
 
 
 def weno5(v1, v2, v3, v4, v5):

@@ -77,7 +77,7 @@ typedef struct {
   int *mixT;       /* [M][3][NC] mixing target cell (-1 = none) */
   double t, dt, dt_fixed;
   long nstep;
-  long n_posfix, n_fluxskip, n_ifskip, n_stranded, n_mixsrc;
+  long n_posfix, n_fluxskip, n_ifskip, n_stranded, n_mixsrc, n_upd;
   double bnd[OR_MAXM][OR_NV], bnd_c[OR_MAXM][OR_NV];
   double xsum[OR_MAXM][OR_NV], xsum_c[OR_MAXM][OR_NV];
   int err_code;
@@ -873,6 +873,11 @@ static int rk_stages(const St *s, double *b, double *c, double *w) {
  * dx = dy in every workload here).  In 1D the exchange is scaled by dt/dx. */
 static void rk_update(St *s, double b, double c, double w) {
   int nx = s->c.nx, ny = s->c.ny;
+  /* unit of work: one material-cell with alpha > 0 updated in one stage */
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++)
+        if (M1(s, s->al, r, ID(s, i, j)) > 0.0) s->n_upd++;
   double lx = s->dt / s->dx, ly = s->dt / s->dy;
   double lv = s->c.dim == 2 ? s->dt / (s->dx * s->dy) : s->dt / s->dx;
   for (int r = 0; r < s->M; r++)
@@ -1418,10 +1423,10 @@ int or_get_apertures(const St *s, double *Ax, double *Ay) {
   return OR_OK;
 }
 
-/* Diagnostics: out[0..7] = t, dt, steps, positivity fallbacks, skipped
- * fluxes, skipped interfaces, stranded mixing sources, mixing sources;
- * then bnd[n_mat][4] (net boundary inflow) and xsum[n_mat][4] (exchange
- * totals), both as increments of sum(Q). */
+/* Diagnostics: out[0..8] = t, dt, steps, positivity fallbacks, skipped
+ * fluxes, skipped interfaces, stranded mixing sources, mixing sources,
+ * material-cell updates; then bnd[n_mat][4] (net boundary inflow) and
+ * xsum[n_mat][4] (exchange totals), both as increments of sum(Q). */
 int or_diag(const St *s, double *out) {
   out[0] = s->t;
   out[1] = s->dt;
@@ -1431,10 +1436,11 @@ int or_diag(const St *s, double *out) {
   out[5] = (double)s->n_ifskip;
   out[6] = (double)s->n_stranded;
   out[7] = (double)s->n_mixsrc;
+  out[8] = (double)s->n_upd;
   for (int r = 0; r < s->M; r++)
     for (int v = 0; v < 4; v++) {
-      out[8 + r * 4 + v] = s->bnd[r][v] + s->bnd_c[r][v];
-      out[8 + s->M * 4 + r * 4 + v] = s->xsum[r][v] + s->xsum_c[r][v];
+      out[9 + r * 4 + v] = s->bnd[r][v] + s->bnd_c[r][v];
+      out[9 + s->M * 4 + r * 4 + v] = s->xsum[r][v] + s->xsum_c[r][v];
     }
   return OR_OK;
 }

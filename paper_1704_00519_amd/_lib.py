@@ -1,0 +1,190 @@
+"""ctypes binding of the C ABI in ``include/mmfv.h`` (argument marshalling
+only: every step of the method runs in the HIP kernels of ``libmmfv.so``).
+
+Arrays may be numpy arrays (host memory) or torch tensors on the GPU
+(device memory, passed by ``data_ptr()``).  Torch is used for device memory
+and the HIP stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmmfv.so")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENONPHYS, MM_ESTATE, MM_ENOTIMPL = range(7)
+MM_HOST, MM_DEVICE = 0, 1
+MAX_MAT = 8
+STATUS = {0: "MM_OK", 1: "MM_EINVAL", 2: "MM_ENOMEM", 3: "MM_EDEVICE",
+          4: "MM_ENONPHYS", 5: "MM_ESTATE", 6: "MM_ENOTIMPL"}
+
+EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
+           "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step", "mm_destroy",
+           "mm_last_error", "mm_set_profiling", "mm_get_profile")
+
+
+class MMConfig(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("n_mat", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
+                ("y1", C.c_double),
+                ("gamma", C.c_double * MAX_MAT), ("pinf", C.c_double * MAX_MAT),
+                ("bc", C.c_int32 * 4), ("inflow_W", C.c_double * 4),
+                ("inflow_mat", C.c_int32), ("rk_order", C.c_int32),
+                ("cfl", C.c_double), ("alpha_mix", C.c_double),
+                ("k_ext", C.c_int32), ("band_ls", C.c_int32)]
+
+
+class MMDiag(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("steps", C.c_int64),
+                ("n_posfix", C.c_int64), ("n_fluxskip", C.c_int64),
+                ("n_ifskip", C.c_int64), ("n_stranded", C.c_int64),
+                ("n_mixsrc", C.c_int64), ("n_updates", C.c_int64),
+                ("err_cell", C.c_int64)]
+
+
+class MMProfile(C.Structure):
+    _fields_ = [("bulk_ms", C.c_double), ("bulk_launches", C.c_int64),
+                ("bulk_updates", C.c_int64), ("bulk_bytes", C.c_double)]
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load ``libmmfv.so``; raise if it has not been built (there is no
+    fallback implementation)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_1704_00519_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        L.mm_create.argtypes = [C.POINTER(MMConfig), vp, C.POINTER(vp)]
+        L.mm_init_state.argtypes = [vp, vp, vp, vp, i32]
+        L.mm_step.argtypes = [vp, i32, i32, C.POINTER(dbl)]
+        L.mm_get_conserved.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.mm_get_diagnostics.argtypes = [vp, C.POINTER(MMDiag)]
+        L.mm_set_dt.argtypes = [vp, dbl]
+        L.mm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.mm_destroy.argtypes = [vp]
+        L.mm_set_profiling.argtypes = [vp, i32]
+        L.mm_get_profile.argtypes = [vp, C.POINTER(MMProfile)]
+        L.mm_last_error.argtypes = [vp]
+        L.mm_last_error.restype = C.c_char_p
+        for name in ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
+                     "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step",
+                     "mm_destroy", "mm_set_profiling", "mm_get_profile"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def make_config(cfg):
+    c = MMConfig()
+    for k in ("dim", "nx", "ny", "n_mat", "inflow_mat", "rk_order", "k_ext",
+              "band_ls"):
+        setattr(c, k, int(cfg[k]))
+    for k in ("x0", "x1", "y0", "y1", "cfl", "alpha_mix"):
+        setattr(c, k, float(cfg[k]))
+    for m in range(int(cfg["n_mat"])):
+        c.gamma[m] = float(cfg["gamma"][m])
+        c.pinf[m] = float(cfg["pinf"][m])
+    for q in range(4):
+        c.bc[q] = int(cfg["bc"][q])
+        c.inflow_W[q] = float(cfg["inflow_W"][q])
+    return c
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class Solver:
+    """One context of the HIP library.  ``cfg``: dict with the fields of
+    ``mm_config``; ``stream``: a hipStream_t handle (int) or None."""
+
+    def __init__(self, cfg, stream=None):
+        L = load()
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        h = C.c_void_p()
+        st = L.mm_create(C.byref(self._c), C.c_void_p(stream or 0), C.byref(h))
+        if st != MM_OK:
+            raise MMError(st, L.mm_last_error(None).decode())
+        self._h = h
+        self.ny, self.nx = int(cfg["ny"]), int(cfg["nx"])
+        self.M, self.nv = int(cfg["n_mat"]), int(cfg["dim"]) + 2
+
+    def _check(self, st):
+        if st != MM_OK:
+            raise MMError(st, load().mm_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def init(self, phi, chi, W):
+        if _is_torch(phi):
+            st = load().mm_init_state(self._h, C.c_void_p(phi.data_ptr()),
+                                      C.c_void_p(chi.data_ptr()),
+                                      C.c_void_p(W.data_ptr()), MM_DEVICE)
+        else:
+            phi = np.ascontiguousarray(phi, np.float64)
+            chi = np.ascontiguousarray(chi, np.int32)
+            W = np.ascontiguousarray(W, np.float64)
+            assert phi.size == self.nx * self.ny and chi.size == phi.size
+            assert W.size == self.M * self.nv * phi.size
+            st = load().mm_init_state(self._h, phi.ctypes.data, chi.ctypes.data,
+                                      W.ctypes.data, MM_HOST)
+        self._check(st)
+
+    def step(self, n=1):
+        t = C.c_double()
+        self._check(load().mm_step(self._h, int(n), 0, C.byref(t)))
+        return t.value
+
+    def set_dt(self, dt):
+        self._check(load().mm_set_dt(self._h, float(dt)))
+
+    def get(self):
+        Q = np.zeros((self.M, self.nv, self.ny, self.nx))
+        al = np.zeros((self.M, self.ny, self.nx))
+        phi = np.zeros((self.ny, self.nx))
+        chi = np.zeros((self.ny, self.nx), np.int32)
+        self._check(load().mm_get_conserved(self._h, Q.ctypes.data, al.ctypes.data,
+                                            phi.ctypes.data, chi.ctypes.data,
+                                            MM_HOST))
+        return dict(Q=Q, alpha=al, phi=phi, chi=chi)
+
+    def get_device(self, Q, alpha=None, phi=None, chi=None):
+        """Write the state into torch tensors on the device (no host copy)."""
+        p = lambda a: C.c_void_p(a.data_ptr()) if a is not None else None
+        self._check(load().mm_get_conserved(self._h, p(Q), p(alpha), p(phi),
+                                            p(chi), MM_DEVICE))
+
+    def set_profiling(self, on=True):
+        self._check(load().mm_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        p = MMProfile()
+        self._check(load().mm_get_profile(self._h, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in MMProfile._fields_}
+
+    def diag(self):
+        d = MMDiag()
+        self._check(load().mm_get_diagnostics(self._h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in MMDiag._fields_}

@@ -1,0 +1,32 @@
+"""Build the HIP library ``libmmfv.so`` for gfx950 (in-tree)."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "mmfv_lib.hip")
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("mmfv_math.h", "mmfv_kernels.h")] + \
+    [os.path.join(ROOT, "include", "mmfv.h")]
+LIB = os.path.join(HERE, "libmmfv.so")
+
+# FP64 throughout, every operation rounded once as written (no contraction,
+# no fast-math); packed FP32 instructions disabled.
+FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17",
+         "-ffp-contract=off", "-fno-fast-math",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(verbose=False):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp", SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL if not verbose else None)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

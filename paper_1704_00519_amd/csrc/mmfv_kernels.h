@@ -1,0 +1,1387 @@
+// HIP kernels of the cut-cell multi-material step for gfx950.
+//
+// Layout (HBM): every field is a padded Cartesian array of NC = NX*NY cells
+// with a frame of H = 4 halo cells (none in y for 1D).  Conserved state is
+// SoA [material][component][cell] with NV = dim+2 components; geometry is
+// [material][cell]; primitive ghost/real states are [material][4][cell].
+// A per-cell occupancy byte (bit r set = material r's slot may be non-zero)
+// travels with each state buffer, so a cell away from interfaces only ever
+// touches its own material's slot.
+#pragma once
+#include "mmfv_math.h"
+
+namespace mmfv {
+
+struct Bufs {
+  double* Q[3];
+  uint8_t* occ[3];
+  double *phi, *ptmp, *phin;
+  uint8_t *chi, *ctmp, *chin;
+  double *al, *ax, *ay, *cx, *cy;
+  double* W;
+  uint8_t* Wit;
+  uint8_t *cut, *xs, *dcut, *dls, *rowc, *rowl, *nrow, *near4, *bulk;
+  double* X;
+  double *vx, *vy;
+  uint8_t* vit;
+  double* mixM;
+  int32_t* mixT;
+  uint32_t *srcStamp, *tgtStamp;
+  double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t
+  unsigned long long* ctr; // smax bits, error cell, counters
+};
+
+enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
+enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
+       C_UPD, C_UPDB0, C_UPDB1, C_N };
+constexpr unsigned long long NO_ERR = ~0ull;
+
+MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
+MMD bool interior(const Params& P, int i, int j) {
+  return i >= 0 && i < P.nx && j >= 0 && j < P.ny;
+}
+MMD double lsv(const double* phi, const uint8_t* chi, int r, int k) {
+  return chi[k] == r ? phi[k] : -phi[k];
+}
+MMD bool errored(const Bufs& B) { return B.ctr[C_ERR] != NO_ERR; }
+MMD void flag_error(const Params& P, const Bufs& B, int i, int j) {
+  atomicMin(&B.ctr[C_ERR], (unsigned long long)j * P.nx + i);
+}
+MMD bool nonphys(const Prim& w, double pinf) {
+  return !(w.r > 0.0) || !(w.p + pinf > 0.0) || !isfinite(w.u) ||
+         !isfinite(w.v) || !isfinite(w.r) || !isfinite(w.p);
+}
+
+// conserved component v (0..3 = rho, rho u, rho v, rho E) of material r;
+// zero unless the occupancy bit is set; in 1D rho v is identically zero
+template <int D>
+MMD double loadQ(const Params& P, const double* Q, const uint8_t* occ, int r,
+                 int v, int k) {
+  if (!((occ[k] >> r) & 1)) return 0.0;
+  if (D == 1) {
+    if (v == 2) return 0.0;
+    if (v == 3) v = 2;
+  }
+  return Q[((size_t)r * (D + 2) + v) * P.NC + k];
+}
+template <int D>
+MMD void storeQ(const Params& P, double* Q, int r, int v, int k, double x) {
+  if (D == 1) {
+    if (v == 2) return;
+    if (v == 3) v = 2;
+  }
+  Q[((size_t)r * (D + 2) + v) * P.NC + k] = x;
+}
+MMD double& M1(const Params& P, double* a, int r, int k) {
+  return a[(size_t)r * P.NC + k];
+}
+MMD double& M4(const Params& P, double* a, int r, int v, int k) {
+  return a[((size_t)r * 4 + v) * P.NC + k];
+}
+
+// geometry readers: cut cells carry stored values, all others are pure
+template <int D>
+MMD double alpha_at(const Params& P, const Bufs& B, int r, int k) {
+  return B.cut[k] ? B.al[(size_t)r * P.NC + k] : (B.chi[k] == r ? 1.0 : 0.0);
+}
+// aperture of the x-face i+1/2 of row j (i in [-1, nx-1])
+template <int D>
+MMD double apx(const Params& P, const Bufs& B, int r, int i, int j) {
+  int kl = cid(P, i, j), kr = cid(P, i + 1, j);
+  int knc;
+  if (i < 0) {
+    if (B.cut[kr]) return B.ax[(size_t)r * P.NC + kl];
+    knc = kr;
+  } else if (i >= P.nx - 1) {
+    if (B.cut[kl]) return B.ax[(size_t)r * P.NC + kl];
+    knc = kl;
+  } else {
+    if (B.cut[kl] && B.cut[kr]) return B.ax[(size_t)r * P.NC + kl];
+    knc = B.cut[kl] ? kr : kl;
+  }
+  return B.chi[knc] == r ? 1.0 : 0.0;
+}
+// aperture of the y-face j+1/2 of column i (j in [-1, ny-1])
+MMD double apy(const Params& P, const Bufs& B, int r, int i, int j) {
+  int kb = cid(P, i, j), kt = cid(P, i, j + 1);
+  int knc;
+  if (j < 0) {
+    if (B.cut[kt]) return B.ay[(size_t)r * P.NC + kb];
+    knc = kt;
+  } else if (j >= P.ny - 1) {
+    if (B.cut[kb]) return B.ay[(size_t)r * P.NC + kb];
+    knc = kb;
+  } else {
+    if (B.cut[kb] && B.cut[kt]) return B.ay[(size_t)r * P.NC + kb];
+    knc = B.cut[kb] ? kt : kb;
+  }
+  return B.chi[knc] == r ? 1.0 : 0.0;
+}
+
+// primitive state of material r at a cell: computed on the fly in pure
+// cells of r (alpha = 1), read from the real/ghost buffer elsewhere
+template <int D>
+MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
+              const uint8_t* occs, int r, int i, int j, bool& valid) {
+  int k = cid(P, i, j);
+  if (interior(P, i, j) && !B.cut[k] && B.chi[k] == r) {
+    valid = true;
+    double U0 = loadQ<D>(P, Qs, occs, r, 0, k) / 1.0;
+    double U1 = loadQ<D>(P, Qs, occs, r, 1, k) / 1.0;
+    double U2 = loadQ<D>(P, Qs, occs, r, 2, k) / 1.0;
+    double U3 = loadQ<D>(P, Qs, occs, r, 3, k) / 1.0;
+    return prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+  }
+  // buffer states are refreshed each stage only within four cells of a cut
+  // cell (and in the frame); anything older is stale
+  valid = B.Wit[(size_t)r * P.NC + k] != 0 &&
+          (!interior(P, i, j) || B.dcut[k] <= 4);
+  Prim w;
+  w.r = B.W[((size_t)r * 4 + 0) * P.NC + k];
+  w.u = B.W[((size_t)r * 4 + 1) * P.NC + k];
+  w.v = B.W[((size_t)r * 4 + 2) * P.NC + k];
+  w.p = B.W[((size_t)r * 4 + 3) * P.NC + k];
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Boundary frames
+// ---------------------------------------------------------------------------
+MMD int src_lo(int i, int type) { return type == 1 ? -1 - i : 0; }
+MMD int src_hi(int i, int n, int type) { return type == 1 ? 2 * n - 1 - i : n - 1; }
+
+// level set, x sides: rows j in [0, ny), 2*H halo cells per row
+__global__ void k_bc_ls_x(Params P, Bufs B, double* phi, uint8_t* chi) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.ny * 2 * H) return;
+  int j = t / (2 * H), q = t % (2 * H);
+  int i, si;
+  if (q < H) {
+    i = -1 - q;
+    si = src_lo(i, P.bc[0]);
+  } else {
+    i = P.nx + (q - H);
+    si = src_hi(i, P.nx, P.bc[1]);
+  }
+  int k = cid(P, i, j), ks = cid(P, si, j);
+  phi[k] = phi[ks];
+  chi[k] = chi[ks];
+}
+// level set, y sides: columns i in [-H, nx+H)
+__global__ void k_bc_ls_y(Params P, Bufs B, double* phi, uint8_t* chi) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int ncol = P.nx + 2 * H;
+  if (t >= ncol * 2 * H) return;
+  int i = t / (2 * H) - H, q = t % (2 * H);
+  int j, sj;
+  if (q < H) {
+    j = -1 - q;
+    sj = src_lo(j, P.bc[2]);
+  } else {
+    j = P.ny + (q - H);
+    sj = src_hi(j, P.ny, P.bc[3]);
+  }
+  int k = cid(P, i, j), ks = cid(P, i, sj);
+  phi[k] = phi[ks];
+  chi[k] = chi[ks];
+}
+
+// primitive states of every material, x sides (inflow: fixed state of the
+// inflow material)
+template <int D>
+__global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.ny * 2 * H * P.M) return;
+  int r = t / (P.ny * 2 * H);
+  int rem = t % (P.ny * 2 * H);
+  int j = rem / (2 * H), q = rem % (2 * H);
+  int i, si, type;
+  if (q < H) {
+    i = -1 - q;
+    type = P.bc[0];
+    si = src_lo(i, type);
+  } else {
+    i = P.nx + (q - H);
+    type = P.bc[1];
+    si = src_hi(i, P.nx, type);
+  }
+  int k = cid(P, i, j);
+  size_t o = (size_t)r * 4 * P.NC;
+  if (type == 2 && r == P.inflow_mat) {
+    for (int v = 0; v < 4; v++) B.W[o + (size_t)v * P.NC + k] = P.inflow_W[v];
+    B.Wit[(size_t)r * P.NC + k] = 1;
+    return;
+  }
+  bool valid;
+  Prim w = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, si, j, valid);
+  double sx = type == 1 ? -1.0 : 1.0;
+  B.W[o + k] = w.r;
+  B.W[o + (size_t)P.NC + k] = w.u * sx;
+  B.W[o + (size_t)2 * P.NC + k] = w.v;
+  B.W[o + (size_t)3 * P.NC + k] = w.p;
+  B.Wit[(size_t)r * P.NC + k] = valid ? 1 : 0;
+}
+__global__ void k_bc_W_y(Params P, Bufs B, int sidx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int ncol = P.nx + 2 * H;
+  if (t >= ncol * 2 * H * P.M) return;
+  int r = t / (ncol * 2 * H);
+  int rem = t % (ncol * 2 * H);
+  int i = rem / (2 * H) - H, q = rem % (2 * H);
+  int j, sj, type;
+  if (q < H) {
+    j = -1 - q;
+    type = P.bc[2];
+    sj = src_lo(j, type);
+  } else {
+    j = P.ny + (q - H);
+    type = P.bc[3];
+    sj = src_hi(j, P.ny, type);
+  }
+  int k = cid(P, i, j);
+  size_t o = (size_t)r * 4 * P.NC;
+  if (type == 2 && r == P.inflow_mat) {
+    for (int v = 0; v < 4; v++) B.W[o + (size_t)v * P.NC + k] = P.inflow_W[v];
+    B.Wit[(size_t)r * P.NC + k] = 1;
+    return;
+  }
+  bool valid;
+  Prim w = Wget<2>(P, B, B.Q[sidx], B.occ[sidx], r, i, sj, valid);
+  double sy = type == 1 ? -1.0 : 1.0;
+  B.W[o + k] = w.r;
+  B.W[o + (size_t)P.NC + k] = w.u;
+  B.W[o + (size_t)2 * P.NC + k] = w.v * sy;
+  B.W[o + (size_t)3 * P.NC + k] = w.p;
+  B.Wit[(size_t)r * P.NC + k] = valid ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Classification of the current level set: local material sets (3x3 block),
+// cut cells, and Chebyshev distances to the nearest cut cell and to the
+// nearest narrow-band cell (phi below the band width, or cut), capped at 15.
+// ---------------------------------------------------------------------------
+#define CELL_LOOP_2D                                         \
+  int i = blockIdx.x * blockDim.x + threadIdx.x;             \
+  int j = blockIdx.y * blockDim.y + threadIdx.y;             \
+  if (i >= P.nx || j >= P.ny) return;                        \
+  int k = cid(P, i, j);
+
+template <int D>
+__global__ void k_classify(Params P, Bufs B) {
+  CELL_LOOP_2D
+  unsigned b = 0;
+  for (int dj = -(D == 2); dj <= (D == 2); dj++)
+    for (int di = -1; di <= 1; di++) b |= 1u << B.chi[cid(P, i + di, j + dj)];
+  B.xs[k] = (uint8_t)b;
+  bool c = (b & (b - 1)) != 0;
+  B.cut[k] = c;
+  B.rowc[k] = (uint8_t)(c ? 1 : 0);
+  B.rowl[k] = (uint8_t)((c || B.phi[k] < P.bls) ? 1 : 0);
+}
+
+constexpr int RD = 15;  // distance cap
+template <int D>
+__global__ void k_dist_row(Params P, Bufs B) {
+  CELL_LOOP_2D
+  // rowc/rowl hold 0/1 flags on entry of the cells; distances go to dcut/dls
+  int dc = RD, dl = RD;
+  for (int di = -RD + 1; di <= RD - 1; di++) {
+    int ii = i + di;
+    if (ii < 0 || ii >= P.nx) continue;
+    int kk = cid(P, ii, j);
+    int a = di < 0 ? -di : di;
+    if (B.rowc[kk] && a < dc) dc = a;
+    if (B.rowl[kk] && a < dl) dl = a;
+  }
+  B.dcut[k] = (uint8_t)dc;
+  B.dls[k] = (uint8_t)dl;
+}
+// column pass: d = min over dj of max(|dj|, row distance); written back into
+// rowc/rowl (then swapped by the host)
+__global__ void k_dist_col(Params P, Bufs B) {
+  CELL_LOOP_2D
+  int dc = RD, dl = RD;
+  for (int dj = -RD + 1; dj <= RD - 1; dj++) {
+    int jj = j + dj;
+    if (jj < 0 || jj >= P.ny) continue;
+    int kk = cid(P, i, jj);
+    int a = dj < 0 ? -dj : dj;
+    int c = B.dcut[kk] > a ? B.dcut[kk] : a;
+    int l = B.dls[kk] > a ? B.dls[kk] : a;
+    if (c < dc) dc = c;
+    if (l < dl) dl = l;
+  }
+  B.rowc[k] = (uint8_t)dc;
+  B.rowl[k] = (uint8_t)dl;
+}
+
+// ghost-band membership: OR of the real-material bits within Chebyshev 4
+template <int D>
+__global__ void k_near_row(Params P, Bufs B) {
+  CELL_LOOP_2D
+  if (B.dcut[k] > 8) {
+    B.nrow[k] = 0;
+    return;
+  }
+  unsigned b = 0;
+  for (int di = -4; di <= 4; di++) {
+    int ii = i + di;
+    if (ii < 0 || ii >= P.nx) continue;
+    int kk = cid(P, ii, j);
+    int r = B.chi[kk];
+    if (alpha_at<D>(P, B, r, kk) > 0.0) b |= 1u << r;
+  }
+  B.nrow[k] = (uint8_t)b;
+}
+template <int D>
+__global__ void k_near_col(Params P, Bufs B) {
+  CELL_LOOP_2D
+  if (B.dcut[k] > 4) return;
+  unsigned b = 0;
+  if (D == 1) {
+    b = B.nrow[k];
+  } else {
+    for (int dj = -4; dj <= 4; dj++) {
+      int jj = j + dj;
+      if (jj < 0 || jj >= P.ny) continue;
+      b |= B.nrow[cid(P, i, jj)];
+    }
+  }
+  B.near4[k] = (uint8_t)b;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of cut cells (Sec. 2.3) + volume-fraction correction (Eq.
+// vol_corr2).  mass: partial densities from state buffer midx, or (init)
+// alpha * rho of the initial primitive field Win.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_geom(Params P, Bufs B, int midx, const double* Win) {
+  CELL_LOOP_2D
+  if (!B.cut[k]) return;
+  const double* phi = B.phi;
+  const uint8_t* chi = B.chi;
+  double al[MAXM];
+  for (int r = 0; r < P.M; r++) {
+    if (D == 1) {
+      int kl = cid(P, i - 1, j), kr = cid(P, i + 1, j);
+      double c = lsv(phi, chi, r, k);
+      double fl = (lsv(phi, chi, r, kl) + c) * 0.5;
+      double fr = (c + lsv(phi, chi, r, kr)) * 0.5;
+      int ol = chi[kl] < chi[k] ? chi[kl] : chi[k];
+      int orr = chi[k] < chi[kr] ? chi[k] : chi[kr];
+      bool il = inside(fl, ol, r), ir = inside(fr, orr, r), ic = inside(c, chi[k], r);
+      double Al = il ? 1.0 : 0.0, Ar = ir ? 1.0 : 0.0;
+      al[r] = (seg_frac(fl, il, c, ic) + seg_frac(c, ic, fr, ir)) * 0.5;
+      B.ax[(size_t)r * P.NC + k] = Ar;
+      if (i == 0) B.ax[(size_t)r * P.NC + kl] = Al;
+      B.cx[(size_t)r * P.NC + k] = Ar - Al;
+      B.cy[(size_t)r * P.NC + k] = 0.0;
+      continue;
+    }
+    // corner (i+a-1/2, j+b-1/2) for a, b in {0, 1}: cells (i+a-1 .. i+a,
+    // j+b-1 .. j+b)
+    double cv[2][2];
+    int co[2][2];
+    for (int b = 0; b < 2; b++)
+      for (int a = 0; a < 2; a++) {
+        int ci = i + a - 1, cj = j + b - 1;
+        int k00 = cid(P, ci, cj), k10 = cid(P, ci + 1, cj),
+            k01 = cid(P, ci, cj + 1), k11 = cid(P, ci + 1, cj + 1);
+        cv[b][a] = ((lsv(phi, chi, r, k00) + lsv(phi, chi, r, k11)) +
+                    (lsv(phi, chi, r, k10) + lsv(phi, chi, r, k01))) * 0.25;
+        int o = chi[k00];
+        if (chi[k10] < o) o = chi[k10];
+        if (chi[k01] < o) o = chi[k01];
+        if (chi[k11] < o) o = chi[k11];
+        co[b][a] = o;
+      }
+    double vsw = cv[0][0], vse = cv[0][1], vnw = cv[1][0], vne = cv[1][1];
+    bool isw = inside(vsw, co[0][0], r), ise = inside(vse, co[0][1], r),
+         inw = inside(vnw, co[1][0], r), ine = inside(vne, co[1][1], r);
+    double c = lsv(phi, chi, r, k);
+    bool ic = inside(c, chi[k], r);
+    double Ar = seg_frac(vse, ise, vne, ine);  // x-face i+1/2
+    double Al = seg_frac(vsw, isw, vnw, inw);  // x-face i-1/2
+    double At = seg_frac(vnw, inw, vne, ine);  // y-face j+1/2
+    double Ab = seg_frac(vsw, isw, vse, ise);  // y-face j-1/2
+    double tl = tri_frac(vsw, isw, vnw, inw, c, ic);
+    double tr = tri_frac(vse, ise, vne, ine, c, ic);
+    double tb = tri_frac(vsw, isw, vse, ise, c, ic);
+    double tt = tri_frac(vnw, inw, vne, ine, c, ic);
+    al[r] = ((tl + tr) + (tb + tt)) * 0.25;
+    size_t o = (size_t)r * P.NC;
+    B.ax[o + k] = Ar;
+    B.ay[o + k] = At;
+    if (i == 0) B.ax[o + cid(P, -1, j)] = Al;
+    if (j == 0) B.ay[o + cid(P, i, -1)] = Ab;
+    B.cx[o + k] = (Ar - Al) * P.dy;
+    B.cy[o + k] = (At - Ab) * P.dx;
+  }
+  // volume-fraction correction in cells with three or more materials
+  int n = 0;
+  for (int r = 0; r < P.M; r++)
+    if (al[r] > 0.0) n++;
+  if (n >= 3) {
+    double mass[MAXM];
+    for (int r = 0; r < P.M; r++) {
+      if (Win) {
+        size_t plane = (size_t)P.nx * P.ny;
+        mass[r] = al[r] * Win[((size_t)r * (D + 2)) * plane + (size_t)j * P.nx + i];
+      } else {
+        mass[r] = loadQ<D>(P, B.Q[midx], B.occ[midx], r, 0, k);
+      }
+    }
+    double sum = 0.0;
+    for (int r = 0; r < P.M; r++) sum += al[r];
+    double d = 1.0 - sum;
+    unsigned used = 0;
+    int prim = chi[k];
+    while (d != 0.0) {
+      int best = -1;
+      for (int r = 0; r < P.M; r++) {
+        if (r == prim || ((used >> r) & 1) || !(al[r] > 0.0)) continue;
+        if (best < 0 || mass[r] < mass[best]) best = r;
+      }
+      if (best < 0) break;
+      used |= 1u << best;
+      double nv = al[best] + d;
+      if (nv < 0.0) {
+        al[best] = 0.0;
+        d = nv;
+      } else {
+        al[best] = nv;
+        d = 0.0;
+      }
+    }
+  }
+  for (int r = 0; r < P.M; r++) B.al[(size_t)r * P.NC + k] = al[r];
+}
+
+// initial conserved state Q0 = alpha U(W) in buffer 0
+template <int D>
+__global__ void k_init_Q(Params P, Bufs B, const double* Win) {
+  CELL_LOOP_2D
+  size_t plane = (size_t)P.nx * P.ny, q = (size_t)j * P.nx + i;
+  unsigned occ = 0;
+  for (int r = 0; r < P.M; r++) {
+    double a = alpha_at<D>(P, B, r, k);
+    double w0 = Win[((size_t)r * (D + 2) + 0) * plane + q];
+    double w1 = Win[((size_t)r * (D + 2) + 1) * plane + q];
+    double w2 = D == 2 ? Win[((size_t)r * (D + 2) + 2) * plane + q] : 0.0;
+    double w3 = Win[((size_t)r * (D + 2) + D + 1) * plane + q];
+    if (a > 0.0 && (!(w0 > 0.0) || !(w3 + P.pinf[r] > 0.0) || !isfinite(w1) ||
+                    !isfinite(w2)))
+      flag_error(P, B, i, j);
+    double U[4];
+    U[0] = w0;
+    U[1] = w0 * w1;
+    U[2] = w0 * w2;
+    U[3] = total_energy(w0, w1, w2, w3, P.gamma[r], P.pinf[r], P.igm1[r]);
+    bool nz = false;
+    for (int v = 0; v < 4; v++) {
+      double x = a > 0.0 ? a * U[v] : 0.0;
+      storeQ<D>(P, B.Q[0], r, v, k, x);
+      if (x != 0.0) nz = true;
+    }
+    if (nz) occ |= 1u << r;
+  }
+  B.occ[0][k] = (uint8_t)occ;
+}
+
+// ---------------------------------------------------------------------------
+// Real states of cut cells, reset of ghost validity in the extension region
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_real(Params P, Bufs B, int sidx) {
+  CELL_LOOP_2D
+  if (errored(B) || B.dcut[k] > 4) return;
+  for (int r = 0; r < P.M; r++) B.Wit[(size_t)r * P.NC + k] = 0;
+  if (!B.cut[k]) return;
+  int r = B.chi[k];
+  double a = B.al[(size_t)r * P.NC + k];
+  if (!(a > 0.0)) return;
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  double U0 = loadQ<D>(P, Q, occ, r, 0, k) / a;
+  double U1 = loadQ<D>(P, Q, occ, r, 1, k) / a;
+  double U2 = loadQ<D>(P, Q, occ, r, 2, k) / a;
+  double U3 = loadQ<D>(P, Q, occ, r, 3, k) / a;
+  Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+  if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
+  size_t o = (size_t)r * 4 * P.NC;
+  B.W[o + k] = w.r;
+  B.W[o + (size_t)P.NC + k] = w.u;
+  B.W[o + (size_t)2 * P.NC + k] = w.v;
+  B.W[o + (size_t)3 * P.NC + k] = w.p;
+  B.Wit[(size_t)r * P.NC + k] = 1;
+}
+
+// CFL step size from the time-n state: max over real cells of
+// max(|u| + c, |v| + c); positive doubles order like their bit patterns
+template <int D>
+__global__ void k_dt(Params P, Bufs B, int sidx) {
+  __shared__ double red[256];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  double w = 0.0;
+  if (i < P.nx && j < P.ny) {
+    int k = cid(P, i, j), r = B.chi[k];
+    if (alpha_at<D>(P, B, r, k) > 0.0) {
+      bool valid;
+      Prim s = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
+      double c = sqrt(P.gamma[r] * (s.p + P.pinf[r]) / s.r);
+      double a = fabs(s.u) + c, b = fabs(s.v) + c;
+      w = a > b ? a : b;
+      if (!(w > 0.0)) w = 0.0;
+    }
+  }
+  red[tid] = w;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) atomicMax(&B.ctr[C_SMAX], (unsigned long long)__double_as_longlong(red[0]));
+}
+template <int D>
+__global__ void k_dt_fin(Params P, Bufs B) {
+  double smax = __longlong_as_double((long long)B.ctr[C_SMAX]);
+  B.ctr[C_SMAX] = 0;
+  double dt = B.scal[S_DTFIX] > 0.0 ? B.scal[S_DTFIX] : P.cfl * P.h / smax;
+  B.scal[S_DT] = dt;
+  B.scal[S_LX] = dt / P.dx;
+  B.scal[S_LY] = dt / P.dy;
+  B.scal[S_LV] = D == 2 ? dt / (P.dx * P.dy) : dt / P.dx;
+}
+__global__ void k_time_advance(Params P, Bufs B) { B.scal[S_T] += B.scal[S_DT]; }
+
+// ---------------------------------------------------------------------------
+// Ghost states: Jacobi sweeps over the ghost band of every material
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_ext(Params P, Bufs B, int sidx, int sweep) {
+  CELL_LOOP_2D
+  if (errored(B) || B.dcut[k] > 4) return;
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  for (int r = 0; r < P.M; r++) {
+    if (!((B.near4[k] >> r) & 1)) continue;
+    if (!B.cut[k] && B.chi[k] == r) continue;  // pure real cell
+    if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
+    auto valid_prev = [&](int ii, int jj) -> bool {
+      if (!interior(P, ii, jj)) return false;
+      int kk = cid(P, ii, jj);
+      if (!B.cut[kk] && B.chi[kk] == r) return true;
+      if (B.dcut[kk] > 4) return false;
+      uint8_t it = B.Wit[(size_t)r * P.NC + kk];
+      return it != 0 && it <= sweep + 1;
+    };
+    double out[4];
+    bool ok = false;
+    if (sweep < P.kext) {
+      double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
+      double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
+      int xi = -1, yj = -1;
+      bool hx = false, hy = false;
+      if (gx != 0.0) {
+        xi = i + (gx > 0.0 ? 1 : -1);
+        hx = valid_prev(xi, j);
+      }
+      if (gy != 0.0) {
+        yj = j + (gy > 0.0 ? 1 : -1);
+        hy = valid_prev(i, yj);
+      }
+      bool vd;
+      if (hx && hy) {
+        Prim a = Wget<D>(P, B, Q, occ, r, xi, j, vd);
+        Prim b = Wget<D>(P, B, Q, occ, r, i, yj, vd);
+        double wx = fabs(gx), wy = fabs(gy);
+        out[0] = (wx * a.r + wy * b.r) / (wx + wy);
+        out[1] = (wx * a.u + wy * b.u) / (wx + wy);
+        out[2] = (wx * a.v + wy * b.v) / (wx + wy);
+        out[3] = (wx * a.p + wy * b.p) / (wx + wy);
+        ok = true;
+      } else if (hx || hy) {
+        Prim a = hx ? Wget<D>(P, B, Q, occ, r, xi, j, vd) : Wget<D>(P, B, Q, occ, r, i, yj, vd);
+        out[0] = a.r;
+        out[1] = a.u;
+        out[2] = a.v;
+        out[3] = a.p;
+        ok = true;
+      }
+    } else {
+      double row[3][4];
+      int cnt = 0;
+      for (int dj = -1; dj <= 1; dj++) {
+        double a[3][4];
+        for (int di = -1; di <= 1; di++) {
+          bool use = (di != 0 || dj != 0) && (D == 2 || dj == 0) &&
+                     valid_prev(i + di, j + dj);
+          Prim w;
+          w.r = w.u = w.v = w.p = 0.0;
+          bool vd;
+          if (use) w = Wget<D>(P, B, Q, occ, r, i + di, j + dj, vd);
+          a[di + 1][0] = use ? w.r : 0.0;
+          a[di + 1][1] = use ? w.u : 0.0;
+          a[di + 1][2] = use ? w.v : 0.0;
+          a[di + 1][3] = use ? w.p : 0.0;
+          cnt += use ? 1 : 0;
+        }
+        for (int c = 0; c < 4; c++) row[dj + 1][c] = (a[0][c] + a[2][c]) + a[1][c];
+      }
+      if (cnt > 0) {
+        for (int c = 0; c < 4; c++)
+          out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
+        ok = true;
+      }
+    }
+    if (ok) {
+      size_t o = (size_t)r * 4 * P.NC;
+      for (int c = 0; c < 4; c++) B.W[o + (size_t)c * P.NC + k] = out[c];
+      B.Wit[(size_t)r * P.NC + k] = (uint8_t)(sweep + 2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced interface interaction (Sec. 2.3.2) in cut cells
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_iface(Params P, Bufs B, int sidx, int stage0) {
+  CELL_LOOP_2D
+  if (errored(B) || !B.cut[k]) return;
+  for (int r = 0; r < P.M; r++)
+    for (int v = 0; v < 4; v++) B.X[((size_t)r * 4 + v) * P.NC + k] = 0.0;
+  unsigned b = B.xs[k];
+  if ((b & (b - 1)) == 0) return;
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  int a = -1, bb = -1;
+  for (int r = 0; r < P.M; r++) {
+    if (!((b >> r) & 1)) continue;
+    if (a < 0 || loadQ<D>(P, Q, occ, r, 0, k) > loadQ<D>(P, Q, occ, a, 0, k)) a = r;
+  }
+  for (int r = 0; r < P.M; r++) {
+    if (!((b >> r) & 1) || r == a) continue;
+    if (bb < 0 || loadQ<D>(P, Q, occ, r, 0, k) > loadQ<D>(P, Q, occ, bb, 0, k)) bb = r;
+  }
+  double cxa = B.cx[(size_t)a * P.NC + k], cya = B.cy[(size_t)a * P.NC + k];
+  if (cxa == 0.0 && cya == 0.0) return;
+  bool va, vb;
+  Prim Wa = Wget<D>(P, B, Q, occ, a, i, j, va);
+  Prim Wb = Wget<D>(P, B, Q, occ, bb, i, j, vb);
+  if (!va || !vb) {
+    atomicAdd(&B.ctr[C_IFSKIP], 1ull);
+    return;
+  }
+  double nrm = sqrt(cxa * cxa + cya * cya);
+  double nxv = cxa / nrm, nyv = cya / nrm;
+  Prim L, R;
+  L.r = Wb.r;
+  L.u = Wb.u * nxv + Wb.v * nyv;
+  L.v = 0.0;
+  L.p = Wb.p;
+  R.r = Wa.r;
+  R.u = Wa.u * nxv + Wa.v * nyv;
+  R.v = 0.0;
+  R.p = Wa.p;
+  double SL, SR;
+  wave_speeds(L, P.gamma[bb], P.pinf[bb], R, P.gamma[a], P.pinf[a], SL, SR);
+  double SM = contact_speed(L, R, SL, SR);
+  double ps = 0.5 * ((L.p + L.r * (SL - L.u) * (SM - L.u)) +
+                     (R.p + R.r * (SR - R.u) * (SM - R.u)));
+  double X1 = ps * cxa, X2 = ps * cya, X3 = ps * SM * nrm;
+  size_t oa = (size_t)a * 4 * P.NC, ob = (size_t)bb * 4 * P.NC;
+  B.X[oa + (size_t)1 * P.NC + k] = X1;
+  B.X[oa + (size_t)2 * P.NC + k] = X2;
+  B.X[oa + (size_t)3 * P.NC + k] = X3;
+  B.X[ob + k] = -0.0;
+  B.X[ob + (size_t)1 * P.NC + k] = -X1;
+  B.X[ob + (size_t)2 * P.NC + k] = -X2;
+  B.X[ob + (size_t)3 * P.NC + k] = -X3;
+  if (stage0) {
+    B.vx[k] = SM * nxv;
+    B.vy[k] = SM * nyv;
+    B.vit[k] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level-set advection velocity v^n (stage 0)
+// ---------------------------------------------------------------------------
+constexpr int RV = 12;  // reach of the level-set band over one step
+template <int D>
+__global__ void k_vreset(Params P, Bufs B) {
+  CELL_LOOP_2D
+  if (B.dls[k] > RV) return;
+  B.vit[k] = 0;
+}
+template <int D>
+__global__ void k_vext(Params P, Bufs B, int sweep) {
+  CELL_LOOP_2D
+  if (errored(B) || B.dls[k] != 0 || !(B.phi[k] < P.bls) || B.vit[k] != 0) return;
+  auto valid_prev = [&](int ii, int jj) -> bool {
+    if (!interior(P, ii, jj)) return false;
+    uint8_t it = B.vit[cid(P, ii, jj)];
+    return it != 0 && it <= sweep + 1;
+  };
+  double gx = B.phi[cid(P, i + 1, j)] - B.phi[cid(P, i - 1, j)];
+  double gy = D == 2 ? B.phi[cid(P, i, j + 1)] - B.phi[cid(P, i, j - 1)] : 0.0;
+  int kx = -1, ky = -1;
+  if (gx != 0.0) {
+    int ii = i - (gx > 0.0 ? 1 : -1);
+    if (valid_prev(ii, j)) kx = cid(P, ii, j);
+  }
+  if (gy != 0.0) {
+    int jj = j - (gy > 0.0 ? 1 : -1);
+    if (valid_prev(i, jj)) ky = cid(P, i, jj);
+  }
+  double ox, oy;
+  if (kx >= 0 && ky >= 0) {
+    double wx = fabs(gx), wy = fabs(gy);
+    ox = (wx * B.vx[kx] + wy * B.vx[ky]) / (wx + wy);
+    oy = (wx * B.vy[kx] + wy * B.vy[ky]) / (wx + wy);
+  } else if (kx >= 0) {
+    ox = B.vx[kx];
+    oy = B.vy[kx];
+  } else if (ky >= 0) {
+    ox = B.vx[ky];
+    oy = B.vy[ky];
+  } else {
+    return;
+  }
+  B.vx[k] = ox;
+  B.vy[k] = oy;
+  B.vit[k] = (uint8_t)(sweep + 2);
+}
+// remaining cells: velocity of the cell's own material; also keep the
+// time-n level set for the whole reach of this step's band
+template <int D>
+__global__ void k_vfill(Params P, Bufs B, int sidx) {
+  CELL_LOOP_2D
+  if (B.dls[k] > RV) return;
+  B.phin[k] = B.phi[k];
+  B.chin[k] = B.chi[k];
+  if (B.vit[k] != 0) return;
+  bool valid;
+  Prim w = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], B.chi[k], i, j, valid);
+  B.vx[k] = valid ? w.u : 0.0;
+  B.vy[k] = valid ? w.v : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Fluxes and RK stage update
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_bulkflag(Params P, Bufs B, int sidx, int nidx) {
+  CELL_LOOP_2D
+  uint8_t own = (uint8_t)(1u << B.chi[k]);
+  B.bulk[k] = (B.dcut[k] > 3 && B.occ[sidx][k] == own && B.occ[nidx][k] == own) ? 1 : 0;
+}
+
+// flux of material r across the face between cell (i, j) and its +1
+// neighbour in direction dir (0: x, 1: y); stencil of six cells
+template <int D>
+MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
+                   const uint8_t* occ, int r, int i, int j, int dir,
+                   bool count, double F[4]) {
+  Prim Wc[6];
+  bool vc[6];
+  bool ok = true;
+  for (int q = 0; q < 6; q++) {
+    int ii = dir == 0 ? i - 2 + q : i, jj = dir == 0 ? j : j - 2 + q;
+    Wc[q] = Wget<D>(P, B, Q, occ, r, ii, jj, vc[q]);
+    if (!vc[q]) ok = false;
+  }
+  if (!vc[2] || !vc[3]) {
+    if (count) atomicAdd(&B.ctr[C_FLUXSKIP], 1ull);
+    F[0] = F[1] = F[2] = F[3] = 0.0;
+    return;
+  }
+  double pinf = P.pinf[r];
+  Prim L, R;
+  auto nrm = [&](const Prim& w) { return dir == 0 ? w.u : w.v; };
+  auto tng = [&](const Prim& w) { return dir == 0 ? w.v : w.u; };
+  if (ok) {
+    L.r = weno5(Wc[0].r, Wc[1].r, Wc[2].r, Wc[3].r, Wc[4].r);
+    L.u = weno5(nrm(Wc[0]), nrm(Wc[1]), nrm(Wc[2]), nrm(Wc[3]), nrm(Wc[4]));
+    L.v = D == 2 ? weno5(tng(Wc[0]), tng(Wc[1]), tng(Wc[2]), tng(Wc[3]), tng(Wc[4])) : 0.0;
+    L.p = weno5(Wc[0].p, Wc[1].p, Wc[2].p, Wc[3].p, Wc[4].p);
+    R.r = weno5(Wc[5].r, Wc[4].r, Wc[3].r, Wc[2].r, Wc[1].r);
+    R.u = weno5(nrm(Wc[5]), nrm(Wc[4]), nrm(Wc[3]), nrm(Wc[2]), nrm(Wc[1]));
+    R.v = D == 2 ? weno5(tng(Wc[5]), tng(Wc[4]), tng(Wc[3]), tng(Wc[2]), tng(Wc[1])) : 0.0;
+    R.p = weno5(Wc[5].p, Wc[4].p, Wc[3].p, Wc[2].p, Wc[1].p);
+    if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + pinf > 0.0) || !(R.p + pinf > 0.0))
+      ok = false;
+  }
+  if (!ok) {
+    if (count) atomicAdd(&B.ctr[C_POSFIX], 1ull);
+    L.r = Wc[2].r; L.u = nrm(Wc[2]); L.v = tng(Wc[2]); L.p = Wc[2].p;
+    R.r = Wc[3].r; R.u = nrm(Wc[3]); R.v = tng(Wc[3]); R.p = Wc[3].p;
+  }
+  double G[4];
+  hllc_flux(L, R, P.gamma[r], pinf, P.igm1[r], G);
+  F[0] = G[0];
+  F[1] = dir == 0 ? G[1] : G[2];
+  F[2] = dir == 0 ? G[2] : G[1];
+  F[3] = G[3];
+}
+
+// general update of every material in cells next to interfaces
+template <int D>
+__global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
+                            double bcoef, double ccoef) {
+  CELL_LOOP_2D
+  if (errored(B) || B.bulk[k]) return;
+  const double* Qs = B.Q[sidx];
+  const double* Qn = B.Q[nidx];
+  const uint8_t* os = B.occ[sidx];
+  const uint8_t* on = B.occ[nidx];
+  double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+  // non-cut cells are real cells of their material: check them here
+  if (!B.cut[k]) {
+    bool vd;
+    int r = B.chi[k];
+    Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
+    if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
+  }
+  double out[MAXM][4];
+  unsigned occ = 0;
+  unsigned long long nact = 0;
+  for (int r = 0; r < P.M; r++)
+    if (alpha_at<D>(P, B, r, k) > 0.0) nact++;
+  if (nact) atomicAdd(&B.ctr[C_UPD], nact);
+  for (int r = 0; r < P.M; r++) {
+    double Fl[4] = {0, 0, 0, 0}, Fr[4] = {0, 0, 0, 0}, Fb[4] = {0, 0, 0, 0},
+           Ft[4] = {0, 0, 0, 0};
+    double Al = apx<D>(P, B, r, i - 1, j), Ar = apx<D>(P, B, r, i, j);
+    double Ab = 0.0, At = 0.0;
+    if (Al > 0.0) face_flux<D>(P, B, Qs, os, r, i - 1, j, 0, i == 0, Fl);
+    if (Ar > 0.0) face_flux<D>(P, B, Qs, os, r, i, j, 0, true, Fr);
+    if (D == 2) {
+      Ab = apy(P, B, r, i, j - 1);
+      At = apy(P, B, r, i, j);
+      if (Ab > 0.0) face_flux<D>(P, B, Qs, os, r, i, j - 1, 1, j == 0, Fb);
+      if (At > 0.0) face_flux<D>(P, B, Qs, os, r, i, j, 1, true, Ft);
+    }
+    bool nz = false;
+    for (int v = 0; v < 4; v++) {
+      if (D == 1 && v == 2) {
+        out[r][v] = 0.0;
+        continue;
+      }
+      double fl = Al > 0.0 ? Al * Fl[v] : 0.0;
+      double fr = Ar > 0.0 ? Ar * Fr[v] : 0.0;
+      double rhs = lx * (fl - fr);
+      if (D == 2) {
+        double fb = Ab > 0.0 ? Ab * Fb[v] : 0.0;
+        double ft = At > 0.0 ? At * Ft[v] : 0.0;
+        rhs = rhs + ly * (fb - ft);
+      }
+      double X = B.cut[k] ? B.X[((size_t)r * 4 + v) * P.NC + k] : 0.0;
+      rhs = rhs + lv * X;
+      double qn = loadQ<D>(P, Qn, on, r, v, k);
+      double qs = loadQ<D>(P, Qs, os, r, v, k);
+      double x = bcoef * qn + ccoef * (qs + rhs);
+      out[r][v] = x;
+      if (x != 0.0) nz = true;
+    }
+    if (nz) occ |= 1u << r;
+  }
+  for (int r = 0; r < P.M; r++)
+    if ((occ >> r) & 1)
+      for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[r][v]);
+  B.occ[didx][k] = (uint8_t)occ;
+}
+
+// Bulk update: cells with no cut cell within three cells and only their own
+// material present.  There alpha = A = 1 and the exchange term vanishes
+// (Sec. 2.4: the single-material block degenerates to standard finite
+// volumes).  The primitive states of a (TX+6) x (TY+6) tile are staged in LDS
+// once; each face flux is computed once and shared by its two cells.
+constexpr int TX = 32, TY = 8;
+__global__ void __launch_bounds__(256)
+k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
+             double ccoef, int stage0) {
+  __shared__ double sW[4][TY + 6][TX + 6];
+  __shared__ double sF[4][(TX + 1) * TY + TX * (TY + 1)];
+  __shared__ uint8_t sChi[TY + 6][TX + 6];
+  __shared__ uint8_t sBulk[TY + 2][TX + 2];
+  int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  int i = i0 + tx, j = j0 + ty;
+  bool inb = i < P.nx && j < P.ny;
+  int k = inb ? cid(P, i, j) : 0;
+  bool isb = inb && B.bulk[k];
+  int nb = __syncthreads_count(isb);
+  if (nb == 0 || errored(B)) return;
+  if (tid == 0) {
+    atomicAdd(&B.ctr[C_UPD], (unsigned long long)nb);
+    atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nb);
+  }
+  const double* Qs = B.Q[sidx];
+  // stage the tile + 3-cell frame: pure cells from Q, frame cells outside the
+  // domain from the boundary states
+  for (int q = tid; q < (TX + 6) * (TY + 6); q += 256) {
+    int ci = i0 - 3 + q % (TX + 6), cj = j0 - 3 + q / (TX + 6);
+    double r_ = 1.0, u_ = 0.0, v_ = 0.0, p_ = 1.0;
+    uint8_t ch = 0;
+    if (ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H) {
+      int kk = cid(P, ci, cj);
+      ch = B.chi[kk];
+      if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny) {
+        size_t o = (size_t)ch * 4 * P.NC + kk;
+        bool has = (B.occ[sidx][kk] >> ch) & 1;
+        double U0 = has ? Qs[o] / 1.0 : 0.0, U1 = has ? Qs[o + P.NC] / 1.0 : 0.0,
+               U2 = has ? Qs[o + 2 * (size_t)P.NC] / 1.0 : 0.0,
+               U3 = has ? Qs[o + 3 * (size_t)P.NC] / 1.0 : 0.0;
+        Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[ch], P.pinf[ch]);
+        r_ = w.r; u_ = w.u; v_ = w.v; p_ = w.p;
+      } else {
+        size_t o = (size_t)ch * 4 * P.NC + kk;
+        r_ = B.W[o];
+        u_ = B.W[o + P.NC];
+        v_ = B.W[o + 2 * (size_t)P.NC];
+        p_ = B.W[o + 3 * (size_t)P.NC];
+      }
+    }
+    int lx = q % (TX + 6), ly = q / (TX + 6);
+    sW[0][ly][lx] = r_;
+    sW[1][ly][lx] = u_;
+    sW[2][ly][lx] = v_;
+    sW[3][ly][lx] = p_;
+    sChi[ly][lx] = ch;
+  }
+  for (int q = tid; q < (TX + 2) * (TY + 2); q += 256) {
+    int ci = i0 - 1 + q % (TX + 2), cj = j0 - 1 + q / (TX + 2);
+    uint8_t bf = 0;
+    if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny) bf = B.bulk[cid(P, ci, cj)];
+    sBulk[q / (TX + 2)][q % (TX + 2)] = bf;
+  }
+  __syncthreads();
+  // faces: x-faces f < (TX+1)*TY (left face of tile cell (fi, fj)), then
+  // y-faces (bottom face of tile cell (fi, fj))
+  const int NFX = (TX + 1) * TY, NF = NFX + TX * (TY + 1);
+  for (int f = tid; f < NF; f += 256) {
+    int dir, fi, fj;
+    if (f < NFX) {
+      dir = 0;
+      fi = f % (TX + 1);
+      fj = f / (TX + 1);
+    } else {
+      dir = 1;
+      fi = (f - NFX) % TX;
+      fj = (f - NFX) / TX;
+    }
+    // the two cells of the face in tile coordinates: (fi-1, fj) | (fi, fj)
+    // or (fi, fj-1) | (fi, fj); sBulk is offset by one
+    bool need = dir == 0 ? (sBulk[fj + 1][fi] || sBulk[fj + 1][fi + 1])
+                         : (sBulk[fj][fi + 1] || sBulk[fj + 1][fi + 1]);
+    if (!need) continue;
+    int m = dir == 0 ? (sBulk[fj + 1][fi + 1] ? sChi[fj + 3][fi + 3] : sChi[fj + 3][fi + 2])
+                     : (sBulk[fj + 1][fi + 1] ? sChi[fj + 3][fi + 3] : sChi[fj + 2][fi + 3]);
+    double c[6][4];
+    for (int q = 0; q < 6; q++) {
+      int lx = dir == 0 ? fi + q : fi + 3;      // cells fi-3 .. fi+2 (+3 offset)
+      int ly = dir == 0 ? fj + 3 : fj + q;
+      c[q][0] = sW[0][ly][lx];
+      c[q][1] = dir == 0 ? sW[1][ly][lx] : sW[2][ly][lx];
+      c[q][2] = dir == 0 ? sW[2][ly][lx] : sW[1][ly][lx];
+      c[q][3] = sW[3][ly][lx];
+    }
+    double pinf = P.pinf[m];
+    Prim L, R;
+    L.r = weno5(c[0][0], c[1][0], c[2][0], c[3][0], c[4][0]);
+    L.u = weno5(c[0][1], c[1][1], c[2][1], c[3][1], c[4][1]);
+    L.v = weno5(c[0][2], c[1][2], c[2][2], c[3][2], c[4][2]);
+    L.p = weno5(c[0][3], c[1][3], c[2][3], c[3][3], c[4][3]);
+    R.r = weno5(c[5][0], c[4][0], c[3][0], c[2][0], c[1][0]);
+    R.u = weno5(c[5][1], c[4][1], c[3][1], c[2][1], c[1][1]);
+    R.v = weno5(c[5][2], c[4][2], c[3][2], c[2][2], c[1][2]);
+    R.p = weno5(c[5][3], c[4][3], c[3][3], c[2][3], c[1][3]);
+    if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + pinf > 0.0) || !(R.p + pinf > 0.0)) {
+      atomicAdd(&B.ctr[C_POSFIX], 1ull);
+      L.r = c[2][0]; L.u = c[2][1]; L.v = c[2][2]; L.p = c[2][3];
+      R.r = c[3][0]; R.u = c[3][1]; R.v = c[3][2]; R.p = c[3][3];
+    }
+    double G[4];
+    hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], G);
+    sF[0][f] = G[0];
+    sF[1][f] = dir == 0 ? G[1] : G[2];
+    sF[2][f] = dir == 0 ? G[2] : G[1];
+    sF[3][f] = G[3];
+  }
+  __syncthreads();
+  if (!isb) return;
+  int m = sChi[ty + 3][tx + 3];
+  {
+    Prim w;
+    w.r = sW[0][ty + 3][tx + 3];
+    w.u = sW[1][ty + 3][tx + 3];
+    w.v = sW[2][ty + 3][tx + 3];
+    w.p = sW[3][ty + 3][tx + 3];
+    if (nonphys(w, P.pinf[m])) flag_error(P, B, i, j);
+  }
+  double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+  int fl = ty * (TX + 1) + tx, fr = fl + 1;
+  int fb = NFX + ty * TX + tx, ft = fb + TX;
+  size_t o = (size_t)m * 4 * P.NC + k;
+  const double* Qn = B.Q[nidx];
+  double* Qd = B.Q[didx];
+  for (int v = 0; v < 4; v++) {
+    double rhs = lx * (sF[v][fl] - sF[v][fr]);
+    rhs = rhs + ly * (sF[v][fb] - sF[v][ft]);
+    rhs = rhs + lv * 0.0;
+    double qs = Qs[o + (size_t)v * P.NC];
+    double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
+    Qd[o + (size_t)v * P.NC] = x;
+  }
+  B.occ[didx][k] = (uint8_t)(1u << m);
+}
+
+// 1D bulk update: 256-cell tiles with a 3-cell frame
+constexpr int T1 = 256;
+__global__ void __launch_bounds__(256)
+k_flux_bulk1(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
+             double ccoef, int stage0) {
+  __shared__ double sW[3][T1 + 6];
+  __shared__ double sF[3][T1 + 1];
+  __shared__ uint8_t sChi[T1 + 6];
+  __shared__ uint8_t sBulk[T1 + 2];
+  int tid = threadIdx.x;
+  int i0 = blockIdx.x * T1, i = i0 + tid;
+  bool inb = i < P.nx;
+  int k = inb ? cid(P, i, 0) : 0;
+  bool isb = inb && B.bulk[k];
+  int nb = __syncthreads_count(isb);
+  if (nb == 0 || errored(B)) return;
+  if (tid == 0) {
+    atomicAdd(&B.ctr[C_UPD], (unsigned long long)nb);
+    atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nb);
+  }
+  const double* Qs = B.Q[sidx];
+  for (int q = tid; q < T1 + 6; q += 256) {
+    int ci = i0 - 3 + q;
+    double r_ = 1.0, u_ = 0.0, p_ = 1.0;
+    uint8_t ch = 0;
+    if (ci >= -H && ci < P.nx + H) {
+      int kk = cid(P, ci, 0);
+      ch = B.chi[kk];
+      if (ci >= 0 && ci < P.nx) {
+        size_t o = (size_t)ch * 3 * P.NC + kk;
+        bool has = (B.occ[sidx][kk] >> ch) & 1;
+        double U0 = has ? Qs[o] / 1.0 : 0.0, U1 = has ? Qs[o + P.NC] / 1.0 : 0.0,
+               U3 = has ? Qs[o + 2 * (size_t)P.NC] / 1.0 : 0.0;
+        Prim w = prim_from_U(U0, U1, 0.0, U3, P.gamma[ch], P.pinf[ch]);
+        r_ = w.r; u_ = w.u; p_ = w.p;
+      } else {
+        size_t o = (size_t)ch * 4 * P.NC + kk;
+        r_ = B.W[o];
+        u_ = B.W[o + P.NC];
+        p_ = B.W[o + 3 * (size_t)P.NC];
+      }
+    }
+    sW[0][q] = r_;
+    sW[1][q] = u_;
+    sW[2][q] = p_;
+    sChi[q] = ch;
+  }
+  for (int q = tid; q < T1 + 2; q += 256) {
+    int ci = i0 - 1 + q;
+    sBulk[q] = (ci >= 0 && ci < P.nx) ? B.bulk[cid(P, ci, 0)] : 0;
+  }
+  __syncthreads();
+  for (int f = tid; f < T1 + 1; f += 256) {
+    // face f: between tile cells f-1 and f
+    if (!(sBulk[f] || sBulk[f + 1])) continue;
+    int m = sBulk[f + 1] ? sChi[f + 3] : sChi[f + 2];
+    double pinf = P.pinf[m];
+    const double* R0 = sW[0];
+    const double* U0 = sW[1];
+    const double* P0 = sW[2];
+    Prim L, R;
+    L.r = weno5(R0[f], R0[f + 1], R0[f + 2], R0[f + 3], R0[f + 4]);
+    L.u = weno5(U0[f], U0[f + 1], U0[f + 2], U0[f + 3], U0[f + 4]);
+    L.v = 0.0;
+    L.p = weno5(P0[f], P0[f + 1], P0[f + 2], P0[f + 3], P0[f + 4]);
+    R.r = weno5(R0[f + 5], R0[f + 4], R0[f + 3], R0[f + 2], R0[f + 1]);
+    R.u = weno5(U0[f + 5], U0[f + 4], U0[f + 3], U0[f + 2], U0[f + 1]);
+    R.v = 0.0;
+    R.p = weno5(P0[f + 5], P0[f + 4], P0[f + 3], P0[f + 2], P0[f + 1]);
+    if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + pinf > 0.0) || !(R.p + pinf > 0.0)) {
+      atomicAdd(&B.ctr[C_POSFIX], 1ull);
+      L.r = R0[f + 2]; L.u = U0[f + 2]; L.p = P0[f + 2];
+      R.r = R0[f + 3]; R.u = U0[f + 3]; R.p = P0[f + 3];
+    }
+    double G[4];
+    hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], G);
+    sF[0][f] = G[0];
+    sF[1][f] = G[1];
+    sF[2][f] = G[3];
+  }
+  __syncthreads();
+  if (!isb) return;
+  int m = sChi[tid + 3];
+  {
+    Prim w;
+    w.r = sW[0][tid + 3];
+    w.u = sW[1][tid + 3];
+    w.v = 0.0;
+    w.p = sW[2][tid + 3];
+    if (nonphys(w, P.pinf[m])) flag_error(P, B, i, 0);
+  }
+  double lx = B.scal[S_LX], lv = B.scal[S_LV];
+  size_t o = (size_t)m * 3 * P.NC + k;
+  const double* Qn = B.Q[nidx];
+  double* Qd = B.Q[didx];
+  for (int v = 0; v < 3; v++) {
+    double rhs = lx * (sF[v][tid] - sF[v][tid + 1]);
+    rhs = rhs + lv * 0.0;
+    double qs = Qs[o + (size_t)v * P.NC];
+    double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
+    Qd[o + (size_t)v * P.NC] = x;
+  }
+  B.occ[didx][k] = (uint8_t)(1u << m);
+}
+
+// ---------------------------------------------------------------------------
+// Level-set stage (Sec. 2.2): construct, HJ-WENO5 upwind, RK, reconstruct
+// ---------------------------------------------------------------------------
+template <int D>
+MMD double hj_deriv(const Params& P, const Bufs& B, int r, int i, int j,
+                    int dir, double vel) {
+  double d[6];
+  double ih = dir == 0 ? P.idx : P.idy;
+  for (int q = 0; q < 6; q++) {
+    int o = q - 2;
+    int k1 = dir == 0 ? cid(P, i + o, j) : cid(P, i, j + o);
+    int k0 = dir == 0 ? cid(P, i + o - 1, j) : cid(P, i, j + o - 1);
+    d[q] = (lsv(B.phi, B.chi, r, k1) - lsv(B.phi, B.chi, r, k0)) * ih;
+  }
+  if (vel > 0.0) return weno5(d[0], d[1], d[2], d[3], d[4]);
+  if (vel < 0.0) return weno5(d[5], d[4], d[3], d[2], d[1]);
+  return 0.0;
+}
+
+template <int D>
+__global__ void k_ls(Params P, Bufs B, double bcoef, double ccoef) {
+  CELL_LOOP_2D
+  if (errored(B) || B.dls[k] > 3) return;
+  double dt = B.scal[S_DT];
+  double best = 0.0;
+  int br = -1;
+  unsigned xs = B.xs[k];
+  for (int r = 0; r < P.M; r++) {
+    if (!((xs >> r) & 1)) continue;
+    double gx = hj_deriv<D>(P, B, r, i, j, 0, B.vx[k]);
+    double adv = B.vx[k] * gx;
+    if (D == 2) {
+      double gy = hj_deriv<D>(P, B, r, i, j, 1, B.vy[k]);
+      adv = adv + B.vy[k] * gy;
+    }
+    double val = lsv(B.phi, B.chi, r, k) - dt * adv;
+    double nv = bcoef * lsv(B.phin, B.chin, r, k) + ccoef * val;
+    if (br < 0 || nv > best) {
+      best = nv;
+      br = r;
+    }
+  }
+  double a = fabs(best);
+  B.ptmp[k] = a < P.bls ? a : P.bls;
+  B.ctmp[k] = (uint8_t)br;
+}
+template <int D>
+__global__ void k_ls_commit(Params P, Bufs B) {
+  CELL_LOOP_2D
+  if (errored(B) || B.dls[k] > 3) return;
+  B.phi[k] = B.ptmp[k];
+  B.chi[k] = B.ctmp[k];
+}
+
+// ---------------------------------------------------------------------------
+// Mixing (Sec. 2.3.2, after each sub-step): exchanges from sources, then a
+// gather that applies them in place
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_mix1(Params P, Bufs B, int didx, uint32_t stamp) {
+  CELL_LOOP_2D
+  if (errored(B)) return;
+  const double* Q = B.Q[didx];
+  const uint8_t* occ = B.occ[didx];
+  uint8_t own = (uint8_t)(1u << B.chi[k]);
+  if (!B.cut[k] && occ[k] == own) return;
+  double amix = P.amix;
+  for (int r = 0; r < P.M; r++) {
+    double as = alpha_at<D>(P, B, r, k);
+    if (!(as < amix) && B.chi[k] == r) continue;
+    if (!(as > 0.0)) {
+      bool nz = false;
+      for (int v = 0; v < 4; v++)
+        if (loadQ<D>(P, Q, occ, r, v, k) != 0.0) nz = true;
+      if (!nz) continue;
+    }
+    atomicAdd(&B.ctr[C_MIXSRC], 1ull);
+    double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
+    double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
+    int sx = gx > 0.0 ? 1 : (gx < 0.0 ? -1 : 0);
+    int sy = gy > 0.0 ? 1 : (gy < 0.0 ? -1 : 0);
+    int tk[3] = {-1, -1, -1};
+    double w[3] = {0.0, 0.0, 0.0};
+    auto eligible = [&](int ii, int jj, double& at) -> bool {
+      if (!interior(P, ii, jj)) return false;
+      int t = cid(P, ii, jj);
+      at = alpha_at<D>(P, B, r, t);
+      return at >= amix && B.chi[t] == r;
+    };
+    double at;
+    if (sx != 0 && eligible(i + sx, j, at)) {
+      tk[0] = cid(P, i + sx, j);
+      w[0] = gx * gx * at;
+    }
+    if (sy != 0 && eligible(i, j + sy, at)) {
+      tk[1] = cid(P, i, j + sy);
+      w[1] = gy * gy * at;
+    }
+    if (sx != 0 && sy != 0 && eligible(i + sx, j + sy, at)) {
+      tk[2] = cid(P, i + sx, j + sy);
+      w[2] = fabs(gx * gy) * at;
+    }
+    double wsum = (w[0] + w[1]) + w[2];
+    double beta[3] = {0.0, 0.0, 0.0};
+    if (wsum > 0.0) {
+      for (int q = 0; q < 3; q++)
+        if (w[q] > 0.0)
+          beta[q] = w[q] / wsum;
+        else
+          tk[q] = -1;
+    } else {
+      tk[0] = tk[1] = tk[2] = -1;
+      double bestA = -1.0;
+      int bt = -1;
+      for (int dj = -(D == 2); dj <= (D == 2); dj++)
+        for (int di = -1; di <= 1; di++) {
+          if (di == 0 && dj == 0) continue;
+          if (eligible(i + di, j + dj, at) && at > bestA) {
+            bestA = at;
+            bt = cid(P, i + di, j + dj);
+          }
+        }
+      if (bt < 0) {
+        atomicAdd(&B.ctr[C_STRANDED], 1ull);
+        continue;
+      }
+      tk[0] = bt;
+      beta[0] = 1.0;
+    }
+    int last = -1;
+    for (int q = 0; q < 3; q++) {
+      B.mixT[((size_t)r * 3 + q) * P.NC + k] = tk[q];
+      if (tk[q] >= 0) {
+        last = q;
+        B.tgtStamp[(size_t)r * P.NC + tk[q]] = stamp;
+      }
+    }
+    B.srcStamp[(size_t)r * P.NC + k] = stamp;
+    for (int v = 0; v < 4; v++) {
+      double Qs = loadQ<D>(P, Q, occ, r, v, k), acc = Qs;
+      for (int q = 0; q < 3; q++) {
+        if (tk[q] < 0) continue;
+        double m;
+        if (as > 0.0) {
+          double at2 = alpha_at<D>(P, B, r, tk[q]);
+          double Qt = loadQ<D>(P, Q, occ, r, v, tk[q]);
+          m = beta[q] * ((as * Qt - at2 * Qs) / (as + at2));
+        } else {
+          m = q == last ? -acc : -(beta[q] * Qs);
+          acc = acc + m;
+        }
+        B.mixM[(((size_t)r * 3 + q) * 4 + v) * P.NC + k] = m;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ void k_mix2(Params P, Bufs B, int didx, uint32_t stamp) {
+  CELL_LOOP_2D
+  if (errored(B)) return;
+  double* Q = B.Q[didx];
+  uint8_t* occp = B.occ[didx];
+  unsigned occ = occp[k];
+  bool touched = false;
+  for (int r = 0; r < P.M; r++) {
+    bool src = B.srcStamp[(size_t)r * P.NC + k] == stamp;
+    bool tgt = B.tgtStamp[(size_t)r * P.NC + k] == stamp;
+    if (!src && !tgt) continue;
+    touched = true;
+    double nq[4];
+    bool nz = false;
+    for (int v = 0; v < 4; v++) {
+      double q0 = loadQ<D>(P, Q, (const uint8_t*)occp, r, v, k);
+      if (src) {
+        for (int q = 0; q < 3; q++)
+          if (B.mixT[((size_t)r * 3 + q) * P.NC + k] >= 0)
+            q0 = q0 + B.mixM[(((size_t)r * 3 + q) * 4 + v) * P.NC + k];
+      } else {
+        double row[3];
+        for (int dj = -1; dj <= 1; dj++) {
+          double a[3] = {0.0, 0.0, 0.0};
+          for (int di = -1; di <= 1; di++) {
+            int ii = i + di, jj = j + dj;
+            if ((di == 0 && dj == 0) || (D == 1 && dj != 0) || !interior(P, ii, jj)) continue;
+            int n = cid(P, ii, jj);
+            if (B.srcStamp[(size_t)r * P.NC + n] != stamp) continue;
+            for (int q = 0; q < 3; q++)
+              if (B.mixT[((size_t)r * 3 + q) * P.NC + n] == k)
+                a[di + 1] = B.mixM[(((size_t)r * 3 + q) * 4 + v) * P.NC + n];
+          }
+          row[dj + 1] = (a[0] + a[2]) + a[1];
+        }
+        q0 = q0 - ((row[0] + row[2]) + row[1]);
+      }
+      nq[v] = q0;
+      if (q0 != 0.0 && !(D == 1 && v == 2)) nz = true;
+    }
+    if (nz) {
+      for (int v = 0; v < 4; v++) storeQ<D>(P, Q, r, v, k, nq[v]);
+      occ |= 1u << r;
+    } else {
+      occ &= ~(1u << r);
+    }
+  }
+  if (touched) occp[k] = (uint8_t)occ;
+}
+
+// ---------------------------------------------------------------------------
+// Output packing: interior Q [M][NV][ny][nx], alpha, phi, chi
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_pack(Params P, Bufs B, int sidx, double* Qo, double* ao,
+                       double* po, int32_t* co) {
+  CELL_LOOP_2D
+  size_t plane = (size_t)P.nx * P.ny, q = (size_t)j * P.nx + i;
+  for (int r = 0; r < P.M; r++) {
+    if (Qo) {
+      Qo[((size_t)r * (D + 2) + 0) * plane + q] = loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, 0, k);
+      Qo[((size_t)r * (D + 2) + 1) * plane + q] = loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, 1, k);
+      if (D == 2)
+        Qo[((size_t)r * (D + 2) + 2) * plane + q] = loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, 2, k);
+      Qo[((size_t)r * (D + 2) + D + 1) * plane + q] = loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, 3, k);
+    }
+    if (ao) ao[(size_t)r * plane + q] = alpha_at<D>(P, B, r, k);
+  }
+  if (po) po[q] = B.phi[k];
+  if (co) co[q] = B.chi[k];
+}
+
+// initial level set from an interior [ny][nx] array
+__global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* chi) {
+  CELL_LOOP_2D
+  size_t q = (size_t)j * P.nx + i;
+  B.phi[k] = phi[q];
+  B.chi[k] = (uint8_t)chi[q];
+}
+
+}  // namespace mmfv

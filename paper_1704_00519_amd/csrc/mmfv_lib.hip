@@ -1,0 +1,510 @@
+// Host side of the C ABI declared in include/mmfv.h: context, device
+// buffers, and the fixed order of kernels in one time step.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mmfv.h"
+#include "mmfv_kernels.h"
+
+using namespace mmfv;
+
+struct mm_ctx {
+  mm_config cfg;
+  Params P;
+  Bufs B;
+  hipStream_t stream = nullptr;
+  int D = 2;
+  uint32_t stamp = 1;
+  bool ready = false;
+  int64_t steps = 0;
+  std::string err;
+  std::vector<void*> allocs;
+  double* d_in = nullptr;   // staging of host inputs/outputs
+  size_t d_in_bytes = 0;
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // pairs around bulk launches
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  unsigned long long prof_u0 = 0, prof_u1 = 0;  // counters at enable time
+};
+
+static void prof_mark(mm_ctx* c) {
+  if (!c->profiling) return;
+  if (c->ev_used == c->ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    c->ev.push_back(e);
+  }
+  (void)hipEventRecord(c->ev[c->ev_used++], c->stream);
+}
+
+// sum the recorded pairs and recycle the events
+static void prof_collect(mm_ctx* c) {
+  if (c->ev_used < 2) return;
+  (void)hipEventSynchronize(c->ev[c->ev_used - 1]);
+  for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]) == hipSuccess) c->prof_ms += ms;
+    c->prof_launches++;
+  }
+  c->ev_used = 0;
+}
+
+static std::string g_create_err;
+
+static mm_status fail(mm_ctx* c, mm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return s;
+}
+
+#define HIP_OK(ctx, call)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(ctx, MM_EDEVICE, std::string(#call) + ": " +              \
+                                       hipGetErrorString(e_));              \
+  } while (0)
+
+template <typename T>
+static hipError_t dalloc(mm_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T) ? n * sizeof(T) : 1);
+  if (e != hipSuccess) return e;
+  e = hipMemset(q, 0, n * sizeof(T) ? n * sizeof(T) : 1);
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  return e;
+}
+
+static void free_all(mm_ctx* c) {
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->d_in) (void)hipFree(c->d_in);
+  c->d_in = nullptr;
+}
+
+extern "C" const char* mm_last_error(const mm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+static bool valid_config(const mm_config* c, std::string& why) {
+  if (c->dim != 1 && c->dim != 2) return why = "dim must be 1 or 2", false;
+  if (c->nx < 1 || c->ny < 1) return why = "nx, ny must be >= 1", false;
+  if (c->dim == 1 && c->ny != 1) return why = "ny must be 1 in 1D", false;
+  if (c->n_mat < 1 || c->n_mat > MM_MAX_MAT) return why = "n_mat out of range", false;
+  if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0)))
+    return why = "empty domain", false;
+  for (int m = 0; m < c->n_mat; m++)
+    if (!(c->gamma[m] > 1.0) || !(c->pinf[m] >= 0.0))
+      return why = "gamma must exceed 1 and p_inf be >= 0", false;
+  for (int q = 0; q < 4; q++)
+    if (c->bc[q] < 0 || c->bc[q] > 3) return why = "bad boundary code", false;
+  if (c->inflow_mat < 0 || c->inflow_mat >= c->n_mat) return why = "bad inflow_mat", false;
+  if (c->rk_order != 2 && c->rk_order != 3) return why = "rk_order must be 2 or 3", false;
+  if (!(c->cfl > 0.0)) return why = "cfl must be positive", false;
+  if (!(c->alpha_mix >= 0.0 && c->alpha_mix <= 1.0)) return why = "alpha_mix out of range", false;
+  if (c->k_ext < 0 || c->k_ext > 8) return why = "k_ext must be in [0, 8]", false;
+  if (c->band_ls < 1 || c->band_ls > 64) return why = "band_ls out of range", false;
+  if ((int64_t)(c->nx + 2 * H) * (c->dim == 2 ? c->ny + 2 * H : 1) > (int64_t)1 << 31)
+    return why = "grid too large", false;
+  return true;
+}
+
+extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, MM_EINVAL, "NULL argument");
+  std::string why;
+  if (!valid_config(cfg, why)) return fail(nullptr, MM_EINVAL, why);
+  mm_ctx* c = new mm_ctx();
+  c->cfg = *cfg;
+  c->D = cfg->dim;
+  c->stream = (hipStream_t)hip_stream;
+  Params& P = c->P;
+  memset(&P, 0, sizeof(P));
+  P.dim = cfg->dim;
+  P.nx = cfg->nx;
+  P.ny = cfg->ny;
+  P.NX = cfg->nx + 2 * H;
+  P.HY = cfg->dim == 2 ? H : 0;
+  P.NY = cfg->ny + 2 * P.HY;
+  P.NC = P.NX * P.NY;
+  P.M = cfg->n_mat;
+  P.dx = (cfg->x1 - cfg->x0) / cfg->nx;
+  P.dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  P.h = cfg->dim == 2 ? (P.dx < P.dy ? P.dx : P.dy) : P.dx;
+  P.bls = cfg->band_ls * P.h;
+  P.idx = 1.0 / P.dx;
+  P.idy = 1.0 / P.dy;
+  P.amix = cfg->alpha_mix;
+  P.kext = cfg->k_ext;
+  P.cfl = cfg->cfl;
+  for (int m = 0; m < P.M; m++) {
+    P.gamma[m] = cfg->gamma[m];
+    P.pinf[m] = cfg->pinf[m];
+    P.igm1[m] = 1.0 / (cfg->gamma[m] - 1.0);
+  }
+  for (int q = 0; q < 4; q++) {
+    P.bc[q] = cfg->bc[q];
+    P.inflow_W[q] = cfg->inflow_W[q];
+  }
+  P.inflow_mat = cfg->inflow_mat;
+
+  size_t nc = P.NC, M = P.M, nv = P.dim + 2;
+  Bufs& B = c->B;
+  memset(&B, 0, sizeof(B));
+  hipError_t e = hipSuccess;
+#define A(p, n)                               \
+  if (e == hipSuccess) e = dalloc(c, &(p), (n));
+  for (int b = 0; b < 3; b++) {
+    A(B.Q[b], M * nv * nc);
+    A(B.occ[b], nc);
+  }
+  A(B.phi, nc); A(B.ptmp, nc); A(B.phin, nc);
+  A(B.chi, nc); A(B.ctmp, nc); A(B.chin, nc);
+  A(B.al, M * nc); A(B.ax, M * nc); A(B.ay, M * nc); A(B.cx, M * nc); A(B.cy, M * nc);
+  A(B.W, M * 4 * nc); A(B.Wit, M * nc);
+  A(B.cut, nc); A(B.xs, nc); A(B.dcut, nc); A(B.dls, nc); A(B.rowc, nc); A(B.rowl, nc);
+  A(B.nrow, nc); A(B.near4, nc); A(B.bulk, nc);
+  A(B.X, M * 4 * nc);
+  A(B.vx, nc); A(B.vy, nc); A(B.vit, nc);
+  A(B.mixM, M * 3 * 4 * nc); A(B.mixT, M * 3 * nc);
+  A(B.srcStamp, M * nc); A(B.tgtStamp, M * nc);
+  A(B.scal, 8); A(B.ctr, C_N);
+#undef A
+  if (e != hipSuccess) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, e == hipErrorOutOfMemory ? MM_ENOMEM : MM_EDEVICE,
+                std::string("allocation: ") + hipGetErrorString(e));
+  }
+  unsigned long long init_ctr[C_N] = {0};
+  init_ctr[C_ERR] = NO_ERR;
+  if (hipMemcpy(B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, MM_EDEVICE, "counter init");
+  }
+  *out = c;
+  return MM_OK;
+}
+
+extern "C" mm_status mm_destroy(mm_ctx* c) {
+  if (!c) return MM_EINVAL;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+static dim3 cell_block(const mm_ctx* c) { return c->D == 2 ? dim3(64, 4) : dim3(256, 1); }
+static dim3 cell_grid(const mm_ctx* c) {
+  dim3 b = cell_block(c);
+  return dim3((c->P.nx + b.x - 1) / b.x, (c->P.ny + b.y - 1) / b.y);
+}
+static dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+#define LAUNCH(kern, grid, block, ...) \
+  hipLaunchKernelGGL(kern, grid, block, 0, c->stream, __VA_ARGS__)
+
+template <int D>
+static void bc_ls(mm_ctx* c) {
+  const Params& P = c->P;
+  LAUNCH(k_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, c->B, c->B.phi, c->B.chi);
+  if (D == 2)
+    LAUNCH(k_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, c->B, c->B.phi,
+           c->B.chi);
+}
+
+template <int D>
+static void classify(mm_ctx* c) {
+  const Params& P = c->P;
+  LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B);
+  LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B);
+  if (D == 2) {
+    LAUNCH(k_dist_col, cell_grid(c), cell_block(c), P, c->B);
+    std::swap(c->B.dcut, c->B.rowc);
+    std::swap(c->B.dls, c->B.rowl);
+  }
+}
+
+template <int D>
+static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double b,
+                  double cc) {
+  const Params& P = c->P;
+  dim3 g = cell_grid(c), bl = cell_block(c);
+  LAUNCH(k_real<D>, g, bl, P, c->B, sidx);
+  if (s == 0) {
+    LAUNCH(k_dt<D>, g, bl, P, c->B, sidx);
+    LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
+  }
+  LAUNCH(k_near_row<D>, g, bl, P, c->B);
+  LAUNCH(k_near_col<D>, g, bl, P, c->B);
+  for (int sw = 0; sw < P.kext + 4; sw++) LAUNCH(k_ext<D>, g, bl, P, c->B, sidx, sw);
+  LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
+  if (D == 2)
+    LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
+  if (s == 0) LAUNCH(k_vreset<D>, g, bl, P, c->B);
+  LAUNCH(k_iface<D>, g, bl, P, c->B, sidx, s == 0 ? 1 : 0);
+  if (s == 0) {
+    for (int sw = 0; sw < 4; sw++) LAUNCH(k_vext<D>, g, bl, P, c->B, sw);
+    LAUNCH(k_vfill<D>, g, bl, P, c->B, sidx);
+  }
+  LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx);
+  prof_mark(c);
+  if (D == 2)
+    LAUNCH(k_flux_bulk2, dim3((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY), dim3(TX, TY), P,
+           c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
+  else
+    LAUNCH(k_flux_bulk1, dim3((P.nx + T1 - 1) / T1), dim3(T1), P, c->B, sidx, nidx, didx, b,
+           cc, s == 0 ? 1 : 0);
+  prof_mark(c);
+  if (c->ev_used >= 4096) prof_collect(c);
+  LAUNCH(k_flux_band<D>, g, bl, P, c->B, sidx, nidx, didx, b, cc);
+  LAUNCH(k_ls<D>, g, bl, P, c->B, b, cc);
+  LAUNCH(k_ls_commit<D>, g, bl, P, c->B);
+  bc_ls<D>(c);
+  classify<D>(c);
+  LAUNCH(k_geom<D>, g, bl, P, c->B, didx, (const double*)nullptr);
+  uint32_t st = c->stamp++;
+  LAUNCH(k_mix1<D>, g, bl, P, c->B, didx, st);
+  LAUNCH(k_mix2<D>, g, bl, P, c->B, didx, st);
+  (void)ns;
+}
+
+template <int D>
+static void one_step(mm_ctx* c) {
+  double b[3], cc[3];
+  int ns;
+  if (c->cfg.rk_order == 2) {
+    ns = 2;
+    b[0] = 0.0; b[1] = 0.5;
+    cc[0] = 1.0; cc[1] = 0.5;
+  } else {
+    ns = 3;
+    b[0] = 0.0; b[1] = 0.75; b[2] = 1.0 / 3.0;
+    cc[0] = 1.0; cc[1] = 0.25; cc[2] = 2.0 / 3.0;
+  }
+  // buffers: 0 holds time n; stages write 1, 2 and finally 0 in place
+  int sidx = 0;
+  for (int s = 0; s < ns; s++) {
+    int didx = s == ns - 1 ? 0 : s + 1;
+    stage<D>(c, s, ns, sidx, 0, didx, b[s], cc[s]);
+    sidx = didx;
+  }
+  hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(1), 0, c->stream, c->P, c->B);
+}
+
+static mm_status stage_inputs(mm_ctx* c, size_t bytes, const void* src, int ptr_kind,
+                              const void** dev) {
+  if (ptr_kind == MM_DEVICE) {
+    *dev = src;
+    return MM_OK;
+  }
+  return MM_OK;
+}
+
+extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* chi,
+                                   const double* W, int32_t ptr_kind) {
+  if (!c) return MM_EINVAL;
+  if (!phi || !chi || !W) return fail(c, MM_EINVAL, "NULL input array");
+  if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
+  const Params& P = c->P;
+  size_t plane = (size_t)P.nx * P.ny, nv = P.dim + 2;
+  size_t nW = (size_t)P.M * nv * plane;
+  const double *dphi = phi, *dW = W;
+  const int32_t* dchi = chi;
+  if (ptr_kind == MM_HOST) {
+    for (size_t q = 0; q < plane; q++)
+      if (chi[q] < 0 || chi[q] >= P.M || !(phi[q] >= 0.0))
+        return fail(c, MM_EINVAL, "chi out of range or phi negative");
+    size_t need = (plane + nW) * sizeof(double) + plane * sizeof(int32_t);
+    if (c->d_in_bytes < need) {
+      if (c->d_in) (void)hipFree(c->d_in);
+      c->d_in = nullptr;
+      c->d_in_bytes = 0;
+      if (hipMalloc(&c->d_in, need) != hipSuccess) return fail(c, MM_ENOMEM, "staging buffer");
+      c->d_in_bytes = need;
+    }
+    double* p0 = c->d_in;
+    double* w0 = p0 + plane;
+    int32_t* c0 = (int32_t*)(w0 + nW);
+    HIP_OK(c, hipMemcpyAsync(p0, phi, plane * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(w0, W, nW * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c0, chi, plane * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    dphi = p0;
+    dW = w0;
+    dchi = c0;
+  }
+  unsigned long long init_ctr[C_N] = {0};
+  init_ctr[C_ERR] = NO_ERR;
+  HIP_OK(c, hipMemcpyAsync(c->B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemsetAsync(c->B.scal, 0, 8 * sizeof(double), c->stream));
+  for (int b = 0; b < 3; b++) HIP_OK(c, hipMemsetAsync(c->B.occ[b], 0, P.NC, c->stream));
+  dim3 g = cell_grid(c), bl = cell_block(c);
+  LAUNCH(k_load_ls, g, bl, P, c->B, dphi, dchi);
+  if (c->D == 2) {
+    bc_ls<2>(c);
+    classify<2>(c);
+    LAUNCH(k_geom<2>, g, bl, P, c->B, 0, dW);
+    LAUNCH(k_init_Q<2>, g, bl, P, c->B, dW);
+  } else {
+    bc_ls<1>(c);
+    classify<1>(c);
+    LAUNCH(k_geom<1>, g, bl, P, c->B, 0, dW);
+    LAUNCH(k_init_Q<1>, g, bl, P, c->B, dW);
+  }
+  HIP_OK(c, hipGetLastError());
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  unsigned long long ctr[C_N];
+  HIP_OK(c, hipMemcpy(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  c->steps = 0;
+  c->ready = true;
+  if (ctr[C_ERR] != NO_ERR) {
+    c->ready = false;
+    return fail(c, MM_ENONPHYS, "non-physical initial state at cell " + std::to_string(ctr[C_ERR]));
+  }
+  (void)stage_inputs;
+  return MM_OK;
+}
+
+extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, double* t_out) {
+  if (!c) return MM_EINVAL;
+  if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
+  if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
+  if (record_tape) return fail(c, MM_ENOTIMPL, "adjoint tape not available");
+  for (int n = 0; n < n_steps; n++) {
+    if (c->D == 2) one_step<2>(c);
+    else one_step<1>(c);
+  }
+  HIP_OK(c, hipGetLastError());
+  c->steps += n_steps;
+  if (t_out) {
+    HIP_OK(c, hipMemcpyAsync(t_out, c->B.scal + S_T, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  unsigned long long err = 0;
+  HIP_OK(c, hipMemcpyAsync(&err, c->B.ctr + C_ERR, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (err != NO_ERR) {
+    c->ready = false;
+    return fail(c, MM_ENONPHYS, "non-physical state at cell " + std::to_string(err));
+  }
+  return MM_OK;
+}
+
+extern "C" mm_status mm_get_conserved(mm_ctx* c, double* Q, double* alpha, double* phi,
+                                      int32_t* chi, int32_t ptr_kind) {
+  if (!c) return MM_EINVAL;
+  if (!Q) return fail(c, MM_EINVAL, "Q must not be NULL");
+  if (!c->ready && c->steps == 0) return fail(c, MM_ESTATE, "no state");
+  if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
+  const Params& P = c->P;
+  size_t plane = (size_t)P.nx * P.ny, nv = P.dim + 2;
+  size_t nQ = (size_t)P.M * nv * plane, nA = (size_t)P.M * plane;
+  dim3 g = cell_grid(c), bl = cell_block(c);
+  if (ptr_kind == MM_DEVICE) {
+    if (c->D == 2) LAUNCH(k_pack<2>, g, bl, P, c->B, 0, Q, alpha, phi, chi);
+    else LAUNCH(k_pack<1>, g, bl, P, c->B, 0, Q, alpha, phi, chi);
+    HIP_OK(c, hipGetLastError());
+    return MM_OK;
+  }
+  size_t need = (nQ + nA + plane) * sizeof(double) + plane * sizeof(int32_t);
+  if (c->d_in_bytes < need) {
+    if (c->d_in) (void)hipFree(c->d_in);
+    c->d_in = nullptr;
+    c->d_in_bytes = 0;
+    if (hipMalloc(&c->d_in, need) != hipSuccess) return fail(c, MM_ENOMEM, "staging buffer");
+    c->d_in_bytes = need;
+  }
+  double* q0 = c->d_in;
+  double* a0 = q0 + nQ;
+  double* p0 = a0 + nA;
+  int32_t* c0 = (int32_t*)(p0 + plane);
+  if (c->D == 2) LAUNCH(k_pack<2>, g, bl, P, c->B, 0, q0, a0, p0, c0);
+  else LAUNCH(k_pack<1>, g, bl, P, c->B, 0, q0, a0, p0, c0);
+  HIP_OK(c, hipGetLastError());
+  HIP_OK(c, hipMemcpyAsync(Q, q0, nQ * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (alpha)
+    HIP_OK(c, hipMemcpyAsync(alpha, a0, nA * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (phi)
+    HIP_OK(c, hipMemcpyAsync(phi, p0, plane * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (chi)
+    HIP_OK(c, hipMemcpyAsync(chi, c0, plane * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
+  if (!c || !out) return MM_EINVAL;
+  unsigned long long ctr[C_N];
+  double scal[8];
+  HIP_OK(c, hipMemcpyAsync(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipMemcpyAsync(scal, c->B.scal, sizeof(scal), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  out->t = scal[S_T];
+  out->dt = scal[S_DT];
+  out->steps = c->steps;
+  out->n_posfix = (int64_t)ctr[C_POSFIX];
+  out->n_fluxskip = (int64_t)ctr[C_FLUXSKIP];
+  out->n_ifskip = (int64_t)ctr[C_IFSKIP];
+  out->n_stranded = (int64_t)ctr[C_STRANDED];
+  out->n_mixsrc = (int64_t)ctr[C_MIXSRC];
+  out->n_updates = (int64_t)ctr[C_UPD];
+  out->err_cell = ctr[C_ERR] == NO_ERR ? -1 : (int64_t)ctr[C_ERR];
+  return MM_OK;
+}
+
+extern "C" mm_status mm_set_dt(mm_ctx* c, double dt) {
+  if (!c) return MM_EINVAL;
+  double v = dt > 0.0 ? dt : 0.0;
+  HIP_OK(c, hipMemcpyAsync(c->B.scal + S_DTFIX, &v, sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double*, const double*, double*, double*,
+                                     int32_t) {
+  if (!c) return MM_EINVAL;
+  return fail(c, MM_ENOTIMPL, "adjoint step not available in this build");
+}
+
+extern "C" mm_status mm_set_profiling(mm_ctx* c, int32_t enable) {
+  if (!c) return MM_EINVAL;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  unsigned long long ctr[C_N];
+  HIP_OK(c, hipMemcpy(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  c->profiling = enable != 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  c->prof_u0 = ctr[C_UPDB0];
+  c->prof_u1 = ctr[C_UPDB1];
+  return MM_OK;
+}
+
+extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
+  if (!c || !out) return MM_EINVAL;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  unsigned long long ctr[C_N];
+  HIP_OK(c, hipMemcpy(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  double w = 8.0 * (c->P.dim + 2);
+  double u0 = (double)(ctr[C_UPDB0] - c->prof_u0), u1 = (double)(ctr[C_UPDB1] - c->prof_u1);
+  out->bulk_ms = c->prof_ms;
+  out->bulk_launches = c->prof_launches;
+  out->bulk_updates = (int64_t)(u0 + u1);
+  out->bulk_bytes = u0 * 2.0 * w + u1 * 3.0 * w;
+  return MM_OK;
+}

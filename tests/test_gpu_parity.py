@@ -1,0 +1,195 @@
+"""GPU parity: the HIP library (called through its C ABI) against the FP64
+CPU oracle on the same seeded inputs.
+
+Both sides evaluate every expression in the same order with one rounding per
+operation, so the expected outcome is bit-for-bit equality; the bar written
+in each test is the 1e-9 relative L1 error per conserved field (material x
+component) and exact equality for the integer indicator chi.  Sizes span
+several LDS tiles with ragged tails; full-size grids run a few steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+REL_L1 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1704_00519_amd as pk
+    pk.load()
+    return pk
+
+
+def run_both(pk, w, steps, dt=None):
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    if dt:
+        o.set_dt(dt)
+        s.set_dt(dt)
+    if steps:
+        assert o.step(steps) == 0
+        s.step(steps)
+    return o, s
+
+
+def assert_parity(o, s, rel=REL_L1, label=""):
+    g, h = o.get(), s.get()
+    assert np.array_equal(g["chi"], h["chi"]), f"{label}: chi differs"
+    Q0, Q1 = g["Q"], h["Q"]
+    M, nv = Q0.shape[:2]
+    for m in range(M):
+        for v in range(nv):
+            ref = math.fsum(np.abs(Q0[m, v]).ravel())
+            err = math.fsum(np.abs(Q1[m, v] - Q0[m, v]).ravel())
+            if ref == 0.0:
+                assert err == 0.0, f"{label}: material {m} comp {v} should be empty"
+            else:
+                assert err / ref <= rel, f"{label}: material {m} comp {v} rel L1 {err / ref:.3e}"
+    assert np.abs(g["alpha"] - h["alpha"]).max() <= 1e-12, label
+    assert np.abs(g["phi"] - h["phi"]).max() <= 1e-12, label
+    do, dg = o.diag(), s.diag()
+    assert dg["t"] == pytest.approx(do["t"], rel=1e-12), label
+    return dict(bitwise=bool(np.array_equal(Q0, Q1)),
+                max_abs=float(np.abs(Q0 - Q1).max()))
+
+
+CASES = {
+    "tube": lambda: wl.shock_tube_1d(),
+    "tube_face_aligned_sym": lambda: wl.shock_tube_1d(
+        n=200, x_if=(0.4, 0.6), gammas=(1.667, 1.4, 1.667), pinfs=(0, 0, 0),
+        rhos=(0.125, 1.0, 0.125), ps=(0.1, 1.0, 0.1)),
+    "triple_small": lambda: wl.triple_point(nx=112, ny=48),
+    "bubble_small": lambda: wl.shock_bubble(nx=200, ny=52),
+    "uniform_circle": lambda: wl.uniform_pressure_2d(shape="circle"),
+    "uniform_lines": lambda: wl.uniform_pressure_2d(shape="lines", nx=45, ny=37),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_initial_state_identical(pk, name):
+    w = CASES[name]()
+    o, s = run_both(pk, w, 0)
+    g, h = o.get(), s.get()
+    for k in ("Q", "alpha", "phi", "chi"):
+        assert np.array_equal(g[k], h[k]), k
+
+
+@pytest.mark.parametrize("name,steps", [("tube", 200), ("tube_face_aligned_sym", 150),
+                                        ("triple_small", 60), ("bubble_small", 80),
+                                        ("uniform_circle", 40), ("uniform_lines", 40)])
+def test_steps_match_oracle(pk, name, steps):
+    w = CASES[name]()
+    o, s = run_both(pk, w, steps)
+    info = assert_parity(o, s, label=name)
+    print(name, info)
+
+
+def test_rk2_variant(pk):
+    w = wl.shock_tube_1d()
+    w["cfg"]["rk_order"] = 2
+    o, s = run_both(pk, w, 100)
+    assert_parity(o, s, label="rk2")
+
+
+def test_single_material_2d_random(pk):
+    ny, nx = 37, 70
+    rng = np.random.default_rng(3)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / nx
+    X, Y = np.meshgrid(x, y)
+    r = 1.0 + 0.3 * np.exp(-((X - 0.4) ** 2 + (Y - 0.25) ** 2) / 0.02)
+    p = 1.0 + 0.5 * np.exp(-((X - 0.6) ** 2 + (Y - 0.3) ** 2) / 0.01) + 0.01 * rng.random((ny, nx))
+    cfg = wl.base_config(dim=2, nx=nx, ny=ny, x1=1.0, y1=ny / nx, n_mat=1,
+                         gamma=[1.4], pinf=[0.0],
+                         bc=[wl.BC_REFLECTIVE, wl.BC_TRANSMISSIVE, wl.BC_REFLECTIVE,
+                             wl.BC_OUTFLOW])
+    w = dict(cfg=cfg, phi=np.full((ny, nx), 1.0), chi=np.zeros((ny, nx), np.int32),
+             W=np.array([r, 0.1 * np.sin(6 * Y), 0.05 * np.cos(3 * X), p])[None])
+    o, s = run_both(pk, w, 20)
+    assert_parity(o, s, label="single2d")
+
+
+def test_fixed_dt_replay(pk):
+    w = wl.shock_tube_1d()
+    o, s = run_both(pk, w, 50, dt=2.5e-4)
+    assert_parity(o, s, label="fixed dt")
+    assert s.diag()["t"] == pytest.approx(50 * 2.5e-4, rel=1e-14)
+
+
+def test_tiny_grids(pk):
+    # grids narrower than one tile and than the stencil
+    for nx, ny in ((9, 1), (12, 5)):
+        if ny == 1:
+            w = wl.shock_tube_1d(n=nx, x_if=(0.35, 0.62))
+        else:
+            w = wl.uniform_pressure_2d(nx=nx, ny=ny)
+        o, s = run_both(pk, w, 5)
+        assert_parity(o, s, label=f"{nx}x{ny}")
+
+
+def test_full_size_triple_point_first_steps(pk):
+    w = wl.triple_point()
+    o, s = run_both(pk, w, 3)
+    assert_parity(o, s, label="triple full")
+
+
+def test_full_size_shock_bubble_first_steps(pk):
+    w = wl.shock_bubble()
+    o, s = run_both(pk, w, 2)
+    assert_parity(o, s, label="bubble full")
+
+
+def test_adjoint_workload_size(pk):
+    # the 512 x 128 shock-bubble of the gradient study, past the first
+    # interface contact of the shock
+    w = wl.shock_bubble(nx=512, ny=128)
+    o, s = run_both(pk, w, 40)
+    assert_parity(o, s, label="bubble 512")
+
+
+def test_run_is_deterministic(pk):
+    w = wl.triple_point(nx=112, ny=48)
+    a = pk.Solver(w["cfg"])
+    a.init(w["phi"], w["chi"], w["W"])
+    a.step(30)
+    b = pk.Solver(w["cfg"])
+    b.init(w["phi"], w["chi"], w["W"])
+    b.step(30)
+    ga, gb = a.get(), b.get()
+    for k in ("Q", "alpha", "phi", "chi"):
+        assert np.array_equal(ga[k], gb[k])
+
+
+def test_nonphysical_initial_state_reported(pk):
+    w = wl.shock_tube_1d()
+    w["W"][1, 2, 0, 130] = -5.0  # negative pressure inside material B
+    s = pk.Solver(w["cfg"])
+    with pytest.raises(pk.MMError) as e:
+        s.init(w["phi"], w["chi"], w["W"])
+    assert e.value.status == 4
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 4
+
+
+def test_step_before_init_is_state_error(pk):
+    s = pk.Solver(wl.shock_tube_1d()["cfg"])
+    with pytest.raises(pk.MMError) as e:
+        s.step(1)
+    assert e.value.status == 5
+
+
+def test_adjoint_entry_point_reports_not_implemented(pk):
+    import ctypes as C
+    s = pk.Solver(wl.shock_tube_1d()["cfg"])
+    st = pk.load().mm_adjoint_step(s._h, None, None, None, None, 0)
+    assert st == 6
+    del C
