@@ -267,8 +267,9 @@ __global__ void k_bc_W_y(Params P, Bufs B, int sidx) {
   int k = cid(P, i, j);
 
 template <int D>
-__global__ void k_classify(Params P, Bufs B) {
-  CELL_LOOP_2D
+MMD void b_classify(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   unsigned b = 0;
   for (int dj = -(D == 2); dj <= (D == 2); dj++)
     for (int di = -1; di <= 1; di++) b |= 1u << B.chi[cid(P, i + di, j + dj)];
@@ -278,11 +279,19 @@ __global__ void k_classify(Params P, Bufs B) {
   B.rowc[k] = (uint8_t)(c ? 1 : 0);
   B.rowl[k] = (uint8_t)((c || B.phi[k] < P.bls) ? 1 : 0);
 }
+template <int D>
+__global__ void k_classify(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_classify<D>(P, B, i, j);
+}
 
 constexpr int RD = 15;  // distance cap
 template <int D>
-__global__ void k_dist_row(Params P, Bufs B) {
-  CELL_LOOP_2D
+MMD void b_dist_row(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   // rowc/rowl hold 0/1 flags on entry of the cells; distances go to dcut/dls
   int dc = RD, dl = RD;
   for (int di = -RD + 1; di <= RD - 1; di++) {
@@ -295,6 +304,13 @@ __global__ void k_dist_row(Params P, Bufs B) {
   }
   B.dcut[k] = (uint8_t)dc;
   B.dls[k] = (uint8_t)dl;
+}
+template <int D>
+__global__ void k_dist_row(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_dist_row<D>(P, B, i, j);
 }
 // column pass: d = min over dj of max(|dj|, row distance); written back into
 // rowc/rowl (then swapped by the host)
@@ -317,8 +333,9 @@ __global__ void k_dist_col(Params P, Bufs B) {
 
 // ghost-band membership: OR of the real-material bits within Chebyshev 4
 template <int D>
-__global__ void k_near_row(Params P, Bufs B) {
-  CELL_LOOP_2D
+MMD void b_near_row(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   if (B.dcut[k] > 8) {
     B.nrow[k] = 0;
     return;
@@ -334,8 +351,16 @@ __global__ void k_near_row(Params P, Bufs B) {
   B.nrow[k] = (uint8_t)b;
 }
 template <int D>
-__global__ void k_near_col(Params P, Bufs B) {
-  CELL_LOOP_2D
+__global__ void k_near_row(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_near_row<D>(P, B, i, j);
+}
+template <int D>
+MMD void b_near_col(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   if (B.dcut[k] > 4) return;
   unsigned b = 0;
   if (D == 1) {
@@ -349,6 +374,13 @@ __global__ void k_near_col(Params P, Bufs B) {
   }
   B.near4[k] = (uint8_t)b;
 }
+template <int D>
+__global__ void k_near_col(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_near_col<D>(P, B, i, j);
+}
 
 // ---------------------------------------------------------------------------
 // Geometry of cut cells (Sec. 2.3) + volume-fraction correction (Eq.
@@ -356,8 +388,9 @@ __global__ void k_near_col(Params P, Bufs B) {
 // alpha * rho of the initial primitive field Win.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_geom(Params P, Bufs B, int midx, const double* Win) {
-  CELL_LOOP_2D
+MMD void b_geom(const Params& P, const Bufs& B, int i, int j, int midx, const double* Win) {
+  int k = cid(P, i, j);
+  (void)k;
   if (!B.cut[k]) return;
   const double* phi = B.phi;
   const uint8_t* chi = B.chi;
@@ -457,11 +490,19 @@ __global__ void k_geom(Params P, Bufs B, int midx, const double* Win) {
   }
   for (int r = 0; r < P.M; r++) B.al[(size_t)r * P.NC + k] = al[r];
 }
+template <int D>
+__global__ void k_geom(Params P, Bufs B, int midx, const double* Win) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_geom<D>(P, B, i, j, midx, Win);
+}
 
 // initial conserved state Q0 = alpha U(W) in buffer 0
 template <int D>
-__global__ void k_init_Q(Params P, Bufs B, const double* Win) {
-  CELL_LOOP_2D
+MMD void b_init_Q(const Params& P, const Bufs& B, int i, int j, const double* Win) {
+  int k = cid(P, i, j);
+  (void)k;
   size_t plane = (size_t)P.nx * P.ny, q = (size_t)j * P.nx + i;
   unsigned occ = 0;
   for (int r = 0; r < P.M; r++) {
@@ -488,13 +529,21 @@ __global__ void k_init_Q(Params P, Bufs B, const double* Win) {
   }
   B.occ[0][k] = (uint8_t)occ;
 }
+template <int D>
+__global__ void k_init_Q(Params P, Bufs B, const double* Win) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_init_Q<D>(P, B, i, j, Win);
+}
 
 // ---------------------------------------------------------------------------
 // Real states of cut cells, reset of ghost validity in the extension region
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_real(Params P, Bufs B, int sidx) {
-  CELL_LOOP_2D
+MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.dcut[k] > 4) return;
   for (int r = 0; r < P.M; r++) B.Wit[(size_t)r * P.NC + k] = 0;
   if (!B.cut[k]) return;
@@ -515,6 +564,13 @@ __global__ void k_real(Params P, Bufs B, int sidx) {
   B.W[o + (size_t)2 * P.NC + k] = w.v;
   B.W[o + (size_t)3 * P.NC + k] = w.p;
   B.Wit[(size_t)r * P.NC + k] = 1;
+}
+template <int D>
+__global__ void k_real(Params P, Bufs B, int sidx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_real<D>(P, B, i, j, sidx);
 }
 
 // CFL step size from the time-n state: max over real cells of
@@ -561,8 +617,9 @@ __global__ void k_time_advance(Params P, Bufs B) { B.scal[S_T] += B.scal[S_DT]; 
 // Ghost states: Jacobi sweeps over the ghost band of every material
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_ext(Params P, Bufs B, int sidx, int sweep) {
-  CELL_LOOP_2D
+MMD void b_ext(const Params& P, const Bufs& B, int i, int j, int sidx, int sweep) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.dcut[k] > 4) return;
   const double* Q = B.Q[sidx];
   const uint8_t* occ = B.occ[sidx];
@@ -644,13 +701,21 @@ __global__ void k_ext(Params P, Bufs B, int sidx, int sweep) {
     }
   }
 }
+template <int D>
+__global__ void k_ext(Params P, Bufs B, int sidx, int sweep) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_ext<D>(P, B, i, j, sidx, sweep);
+}
 
 // ---------------------------------------------------------------------------
 // Reduced interface interaction (Sec. 2.3.2) in cut cells
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_iface(Params P, Bufs B, int sidx, int stage0) {
-  CELL_LOOP_2D
+MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int stage0) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || !B.cut[k]) return;
   for (int r = 0; r < P.M; r++)
     for (int v = 0; v < 4; v++) B.X[((size_t)r * 4 + v) * P.NC + k] = 0.0;
@@ -707,20 +772,36 @@ __global__ void k_iface(Params P, Bufs B, int sidx, int stage0) {
     B.vit[k] = 1;
   }
 }
+template <int D>
+__global__ void k_iface(Params P, Bufs B, int sidx, int stage0) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_iface<D>(P, B, i, j, sidx, stage0);
+}
 
 // ---------------------------------------------------------------------------
 // Level-set advection velocity v^n (stage 0)
 // ---------------------------------------------------------------------------
 constexpr int RV = 12;  // reach of the level-set band over one step
 template <int D>
-__global__ void k_vreset(Params P, Bufs B) {
-  CELL_LOOP_2D
+MMD void b_vreset(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   if (B.dls[k] > RV) return;
   B.vit[k] = 0;
 }
 template <int D>
-__global__ void k_vext(Params P, Bufs B, int sweep) {
-  CELL_LOOP_2D
+__global__ void k_vreset(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_vreset<D>(P, B, i, j);
+}
+template <int D>
+MMD void b_vext(const Params& P, const Bufs& B, int i, int j, int sweep) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.dls[k] != 0 || !(B.phi[k] < P.bls) || B.vit[k] != 0) return;
   auto valid_prev = [&](int ii, int jj) -> bool {
     if (!interior(P, ii, jj)) return false;
@@ -756,11 +837,19 @@ __global__ void k_vext(Params P, Bufs B, int sweep) {
   B.vy[k] = oy;
   B.vit[k] = (uint8_t)(sweep + 2);
 }
+template <int D>
+__global__ void k_vext(Params P, Bufs B, int sweep) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_vext<D>(P, B, i, j, sweep);
+}
 // remaining cells: velocity of the cell's own material; also keep the
 // time-n level set for the whole reach of this step's band
 template <int D>
-__global__ void k_vfill(Params P, Bufs B, int sidx) {
-  CELL_LOOP_2D
+MMD void b_vfill(const Params& P, const Bufs& B, int i, int j, int sidx) {
+  int k = cid(P, i, j);
+  (void)k;
   if (B.dls[k] > RV) return;
   B.phin[k] = B.phi[k];
   B.chin[k] = B.chi[k];
@@ -770,15 +859,30 @@ __global__ void k_vfill(Params P, Bufs B, int sidx) {
   B.vx[k] = valid ? w.u : 0.0;
   B.vy[k] = valid ? w.v : 0.0;
 }
+template <int D>
+__global__ void k_vfill(Params P, Bufs B, int sidx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_vfill<D>(P, B, i, j, sidx);
+}
 
 // ---------------------------------------------------------------------------
 // Fluxes and RK stage update
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_bulkflag(Params P, Bufs B, int sidx, int nidx) {
-  CELL_LOOP_2D
+MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int nidx) {
+  int k = cid(P, i, j);
+  (void)k;
   uint8_t own = (uint8_t)(1u << B.chi[k]);
   B.bulk[k] = (B.dcut[k] > 3 && B.occ[sidx][k] == own && B.occ[nidx][k] == own) ? 1 : 0;
+}
+template <int D>
+__global__ void k_bulkflag(Params P, Bufs B, int sidx, int nidx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_bulkflag<D>(P, B, i, j, sidx, nidx);
 }
 
 // flux of material r across the face between cell (i, j) and its +1
@@ -831,9 +935,10 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
 
 // general update of every material in cells next to interfaces
 template <int D>
-__global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
+MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int nidx, int didx,
                             double bcoef, double ccoef) {
-  CELL_LOOP_2D
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.bulk[k]) return;
   const double* Qs = B.Q[sidx];
   const double* Qn = B.Q[nidx];
@@ -894,6 +999,14 @@ __global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
     if ((occ >> r) & 1)
       for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[r][v]);
   B.occ[didx][k] = (uint8_t)occ;
+}
+template <int D>
+__global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
+                            double bcoef, double ccoef) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_flux_band<D>(P, B, i, j, sidx, nidx, didx, bcoef, ccoef);
 }
 
 // Bulk update: cells with no cut cell within three cells and only their own
@@ -1166,8 +1279,9 @@ MMD double hj_deriv(const Params& P, const Bufs& B, int r, int i, int j,
 }
 
 template <int D>
-__global__ void k_ls(Params P, Bufs B, double bcoef, double ccoef) {
-  CELL_LOOP_2D
+MMD void b_ls(const Params& P, const Bufs& B, int i, int j, double bcoef, double ccoef) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.dls[k] > 3) return;
   double dt = B.scal[S_DT];
   double best = 0.0;
@@ -1193,11 +1307,26 @@ __global__ void k_ls(Params P, Bufs B, double bcoef, double ccoef) {
   B.ctmp[k] = (uint8_t)br;
 }
 template <int D>
-__global__ void k_ls_commit(Params P, Bufs B) {
-  CELL_LOOP_2D
+__global__ void k_ls(Params P, Bufs B, double bcoef, double ccoef) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_ls<D>(P, B, i, j, bcoef, ccoef);
+}
+template <int D>
+MMD void b_ls_commit(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B) || B.dls[k] > 3) return;
   B.phi[k] = B.ptmp[k];
   B.chi[k] = B.ctmp[k];
+}
+template <int D>
+__global__ void k_ls_commit(Params P, Bufs B) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_ls_commit<D>(P, B, i, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -1205,8 +1334,9 @@ __global__ void k_ls_commit(Params P, Bufs B) {
 // gather that applies them in place
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_mix1(Params P, Bufs B, int didx, uint32_t stamp) {
-  CELL_LOOP_2D
+MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B)) return;
   const double* Q = B.Q[didx];
   const uint8_t* occ = B.occ[didx];
@@ -1302,10 +1432,18 @@ __global__ void k_mix1(Params P, Bufs B, int didx, uint32_t stamp) {
     }
   }
 }
+template <int D>
+__global__ void k_mix1(Params P, Bufs B, int didx, uint32_t stamp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_mix1<D>(P, B, i, j, didx, stamp);
+}
 
 template <int D>
-__global__ void k_mix2(Params P, Bufs B, int didx, uint32_t stamp) {
-  CELL_LOOP_2D
+MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp) {
+  int k = cid(P, i, j);
+  (void)k;
   if (errored(B)) return;
   double* Q = B.Q[didx];
   uint8_t* occp = B.occ[didx];
@@ -1353,14 +1491,22 @@ __global__ void k_mix2(Params P, Bufs B, int didx, uint32_t stamp) {
   }
   if (touched) occp[k] = (uint8_t)occ;
 }
+template <int D>
+__global__ void k_mix2(Params P, Bufs B, int didx, uint32_t stamp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_mix2<D>(P, B, i, j, didx, stamp);
+}
 
 // ---------------------------------------------------------------------------
 // Output packing: interior Q [M][NV][ny][nx], alpha, phi, chi
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_pack(Params P, Bufs B, int sidx, double* Qo, double* ao,
+MMD void b_pack(const Params& P, const Bufs& B, int i, int j, int sidx, double* Qo, double* ao,
                        double* po, int32_t* co) {
-  CELL_LOOP_2D
+  int k = cid(P, i, j);
+  (void)k;
   size_t plane = (size_t)P.nx * P.ny, q = (size_t)j * P.nx + i;
   for (int r = 0; r < P.M; r++) {
     if (Qo) {
@@ -1374,6 +1520,14 @@ __global__ void k_pack(Params P, Bufs B, int sidx, double* Qo, double* ao,
   }
   if (po) po[q] = B.phi[k];
   if (co) co[q] = B.chi[k];
+}
+template <int D>
+__global__ void k_pack(Params P, Bufs B, int sidx, double* Qo, double* ao,
+                       double* po, int32_t* co) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_pack<D>(P, B, i, j, sidx, Qo, ao, po, co);
 }
 
 // initial level set from an interior [ny][nx] array
