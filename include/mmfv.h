@@ -142,6 +142,38 @@ typedef struct {
 mm_status mm_set_profiling(mm_ctx *ctx, int32_t enable);
 mm_status mm_get_profile(mm_ctx *ctx, mm_profile *out);
 
+/* ---- Batched form ------------------------------------------------------
+ * Many independent 1D problems of uneven size (same n_mat and rk_order)
+ * advanced together: one persistent launch, one workgroup per instance,
+ * each instance with its own step size, EOS and boundaries; the launch is
+ * replayed from a HIP graph.  Arrays are the concatenation of the
+ * instances' interior cells in instance order: phi, chi [sum nx]; instance
+ * q's W and Q blocks are [n_mat][3][nx_q] starting at n_mat*3*off_q
+ * doubles, alpha [n_mat][nx_q] at n_mat*off_q, with off_q the sum of the
+ * nx of the instances before q.  Results are identical, bit for bit, to
+ * advancing each instance alone with mm_step. */
+typedef struct mm_batch mm_batch;
+mm_status mm_batch_create(const mm_config *cfgs, int32_t n_inst, void *hip_stream,
+                          mm_batch **out);
+mm_status mm_batch_init_state(mm_batch *b, const double *phi, const int32_t *chi,
+                              const double *W, int32_t ptr_kind);
+/* Advance every instance n_steps steps; synchronises and returns
+ * MM_ENONPHYS if any instance met a non-physical state.  The first call
+ * chooses the workgroup size by timing candidates on a snapshot of the state
+ * (restored afterwards) unless mm_batch_set_threads fixed it. */
+mm_status mm_batch_step(mm_batch *b, int32_t n_steps);
+mm_status mm_batch_get_conserved(mm_batch *b, double *Q, double *alpha, double *phi,
+                                 int32_t *chi, int32_t ptr_kind);
+/* out has n_inst entries. */
+mm_status mm_batch_get_diagnostics(mm_batch *b, mm_diag *out);
+/* threads: 64, 128, 256, 512 or 1024, or 0 to choose by measurement. */
+mm_status mm_batch_set_threads(mm_batch *b, int32_t threads);
+/* Chosen workgroup size and, if tune_ms is not NULL, the 5 trial timings
+ * (64 .. 1024 threads) of the last tuning. */
+mm_status mm_batch_get_threads(mm_batch *b, int32_t *threads, float *tune_ms);
+mm_status mm_batch_destroy(mm_batch *b);
+const char *mm_batch_last_error(const mm_batch *b);
+
 /* Release every device buffer of the context. */
 mm_status mm_destroy(mm_ctx *ctx);
 

@@ -2,8 +2,8 @@
 for compressible multi-material flows (Pan, Han, Hu & Adams,
 arXiv:1704.00519): a C-ABI HIP library (``libmmfv.so``, ``include/mmfv.h``)
 and this thin Python binding."""
-from ._lib import (MM_DEVICE, MM_HOST, MMError, Solver, load, make_config,
-                   LIB_PATH, EXPORTS)
+from ._lib import (MM_DEVICE, MM_HOST, MMError, Solver, Batch, load,
+                   make_config, LIB_PATH, EXPORTS)
 
-__all__ = ["Solver", "MMError", "load", "make_config", "MM_HOST", "MM_DEVICE",
+__all__ = ["Solver", "Batch", "MMError", "load", "make_config", "MM_HOST", "MM_DEVICE",
            "LIB_PATH", "EXPORTS"]

@@ -23,7 +23,11 @@ STATUS = {0: "MM_OK", 1: "MM_EINVAL", 2: "MM_ENOMEM", 3: "MM_EDEVICE",
 
 EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
            "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step", "mm_destroy",
-           "mm_last_error", "mm_set_profiling", "mm_get_profile")
+           "mm_last_error", "mm_set_profiling", "mm_get_profile",
+           "mm_batch_create", "mm_batch_init_state", "mm_batch_step",
+           "mm_batch_get_conserved", "mm_batch_get_diagnostics",
+           "mm_batch_set_threads", "mm_batch_get_threads", "mm_batch_destroy",
+           "mm_batch_last_error")
 
 
 class MMConfig(C.Structure):
@@ -80,6 +84,21 @@ def load():
         L.mm_destroy.argtypes = [vp]
         L.mm_set_profiling.argtypes = [vp, i32]
         L.mm_get_profile.argtypes = [vp, C.POINTER(MMProfile)]
+        L.mm_batch_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
+        L.mm_batch_init_state.argtypes = [vp, vp, vp, vp, i32]
+        L.mm_batch_step.argtypes = [vp, i32]
+        L.mm_batch_get_conserved.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.mm_batch_get_diagnostics.argtypes = [vp, vp]
+        L.mm_batch_set_threads.argtypes = [vp, i32]
+        L.mm_batch_get_threads.argtypes = [vp, C.POINTER(i32), vp]
+        L.mm_batch_destroy.argtypes = [vp]
+        L.mm_batch_last_error.argtypes = [vp]
+        L.mm_batch_last_error.restype = C.c_char_p
+        for name in ("mm_batch_create", "mm_batch_init_state", "mm_batch_step",
+                     "mm_batch_get_conserved", "mm_batch_get_diagnostics",
+                     "mm_batch_set_threads", "mm_batch_get_threads",
+                     "mm_batch_destroy"):
+            getattr(L, name).restype = i32
         L.mm_last_error.argtypes = [vp]
         L.mm_last_error.restype = C.c_char_p
         for name in ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
@@ -188,3 +207,76 @@ class Solver:
         d = MMDiag()
         self._check(load().mm_get_diagnostics(self._h, C.byref(d)))
         return {k: getattr(d, k) for k, _ in MMDiag._fields_}
+
+
+class Batch:
+    """Many ragged 1D instances advanced by one persistent launch.
+    ``instances``: list of workload dicts (cfg, phi, chi, W) with the same
+    n_mat and rk_order."""
+
+    def __init__(self, instances, stream=None):
+        L = load()
+        self.n = len(instances)
+        cfgs = (MMConfig * self.n)(*[make_config(w["cfg"]) for w in instances])
+        self._cfgs = cfgs
+        h = C.c_void_p()
+        st = L.mm_batch_create(cfgs, self.n, C.c_void_p(stream or 0), C.byref(h))
+        if st != MM_OK:
+            raise MMError(st, L.mm_batch_last_error(None).decode())
+        self._h = h
+        self.nx = [int(w["cfg"]["nx"]) for w in instances]
+        self.M = int(instances[0]["cfg"]["n_mat"])
+        self.off = np.concatenate([[0], np.cumsum(self.nx)]).astype(np.int64)
+
+    def _check(self, st):
+        if st != MM_OK:
+            raise MMError(st, load().mm_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mm_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def init(self, instances):
+        phi = np.concatenate([np.asarray(w["phi"], np.float64).ravel() for w in instances])
+        chi = np.concatenate([np.asarray(w["chi"], np.int32).ravel() for w in instances])
+        W = np.concatenate([np.asarray(w["W"], np.float64).ravel() for w in instances])
+        self._check(load().mm_batch_init_state(self._h, phi.ctypes.data, chi.ctypes.data,
+                                               W.ctypes.data, MM_HOST))
+
+    def step(self, n=1):
+        self._check(load().mm_batch_step(self._h, int(n)))
+
+    def set_threads(self, t):
+        self._check(load().mm_batch_set_threads(self._h, int(t)))
+
+    def threads(self):
+        t = C.c_int32()
+        ms = (C.c_float * 5)()
+        self._check(load().mm_batch_get_threads(self._h, C.byref(t), ms))
+        return t.value, list(ms)
+
+    def get(self):
+        """List of per-instance dicts (Q [M][3][1][nx], alpha, phi, chi)."""
+        N = int(self.off[-1])
+        Q = np.zeros(self.M * 3 * N)
+        al = np.zeros(self.M * N)
+        phi = np.zeros(N)
+        chi = np.zeros(N, np.int32)
+        self._check(load().mm_batch_get_conserved(self._h, Q.ctypes.data, al.ctypes.data,
+                                                  phi.ctypes.data, chi.ctypes.data, MM_HOST))
+        out = []
+        for q, nx in enumerate(self.nx):
+            o = int(self.off[q])
+            out.append(dict(
+                Q=Q[self.M * 3 * o:self.M * 3 * (o + nx)].reshape(self.M, 3, 1, nx),
+                alpha=al[self.M * o:self.M * (o + nx)].reshape(self.M, 1, nx),
+                phi=phi[o:o + nx].reshape(1, nx), chi=chi[o:o + nx].reshape(1, nx)))
+        return out
+
+    def diag(self):
+        arr = (MMDiag * self.n)()
+        self._check(load().mm_batch_get_diagnostics(self._h, arr))
+        return [{k: getattr(d, k) for k, _ in MMDiag._fields_} for d in arr]

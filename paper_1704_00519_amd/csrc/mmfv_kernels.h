@@ -33,7 +33,7 @@ struct Bufs {
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
-       C_UPD, C_UPDB0, C_UPDB1, C_N };
+       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 
 MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
@@ -151,9 +151,7 @@ MMD int src_lo(int i, int type) { return type == 1 ? -1 - i : 0; }
 MMD int src_hi(int i, int n, int type) { return type == 1 ? 2 * n - 1 - i : n - 1; }
 
 // level set, x sides: rows j in [0, ny), 2*H halo cells per row
-__global__ void k_bc_ls_x(Params P, Bufs B, double* phi, uint8_t* chi) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P.ny * 2 * H) return;
+MMD void b_bc_ls_x(const Params& P, int t, double* phi, uint8_t* chi) {
   int j = t / (2 * H), q = t % (2 * H);
   int i, si;
   if (q < H) {
@@ -166,6 +164,11 @@ __global__ void k_bc_ls_x(Params P, Bufs B, double* phi, uint8_t* chi) {
   int k = cid(P, i, j), ks = cid(P, si, j);
   phi[k] = phi[ks];
   chi[k] = chi[ks];
+}
+__global__ void k_bc_ls_x(Params P, Bufs B, double* phi, uint8_t* chi) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.ny * 2 * H) return;
+  b_bc_ls_x(P, t, phi, chi);
 }
 // level set, y sides: columns i in [-H, nx+H)
 __global__ void k_bc_ls_y(Params P, Bufs B, double* phi, uint8_t* chi) {
@@ -189,9 +192,7 @@ __global__ void k_bc_ls_y(Params P, Bufs B, double* phi, uint8_t* chi) {
 // primitive states of every material, x sides (inflow: fixed state of the
 // inflow material)
 template <int D>
-__global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P.ny * 2 * H * P.M) return;
+MMD void b_bc_W_x(const Params& P, const Bufs& B, int t, int sidx) {
   int r = t / (P.ny * 2 * H);
   int rem = t % (P.ny * 2 * H);
   int j = rem / (2 * H), q = rem % (2 * H);
@@ -220,6 +221,12 @@ __global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
   B.W[o + (size_t)2 * P.NC + k] = w.v;
   B.W[o + (size_t)3 * P.NC + k] = w.p;
   B.Wit[(size_t)r * P.NC + k] = valid ? 1 : 0;
+}
+template <int D>
+__global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.ny * 2 * H * P.M) return;
+  b_bc_W_x<D>(P, B, t, sidx);
 }
 __global__ void k_bc_W_y(Params P, Bufs B, int sidx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -576,23 +583,35 @@ __global__ void k_real(Params P, Bufs B, int sidx) {
 // CFL step size from the time-n state: max over real cells of
 // max(|u| + c, |v| + c); positive doubles order like their bit patterns
 template <int D>
+MMD double b_dt_cell(const Params& P, const Bufs& B, int i, int j, int sidx) {
+  int k = cid(P, i, j), r = B.chi[k];
+  double w = 0.0;
+  if (alpha_at<D>(P, B, r, k) > 0.0) {
+    bool valid;
+    Prim s = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
+    double c = sqrt(P.gamma[r] * (s.p + P.pinf[r]) / s.r);
+    double a = fabs(s.u) + c, b = fabs(s.v) + c;
+    w = a > b ? a : b;
+    if (!(w > 0.0)) w = 0.0;
+  }
+  return w;
+}
+template <int D>
+MMD void dt_finish(const Params& P, const Bufs& B, double smax) {
+  double dt = B.scal[S_DTFIX] > 0.0 ? B.scal[S_DTFIX] : P.cfl * P.h / smax;
+  B.scal[S_DT] = dt;
+  B.scal[S_LX] = dt / P.dx;
+  B.scal[S_LY] = dt / P.dy;
+  B.scal[S_LV] = D == 2 ? dt / (P.dx * P.dy) : dt / P.dx;
+}
+template <int D>
 __global__ void k_dt(Params P, Bufs B, int sidx) {
   __shared__ double red[256];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int tid = threadIdx.y * blockDim.x + threadIdx.x;
   double w = 0.0;
-  if (i < P.nx && j < P.ny) {
-    int k = cid(P, i, j), r = B.chi[k];
-    if (alpha_at<D>(P, B, r, k) > 0.0) {
-      bool valid;
-      Prim s = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
-      double c = sqrt(P.gamma[r] * (s.p + P.pinf[r]) / s.r);
-      double a = fabs(s.u) + c, b = fabs(s.v) + c;
-      w = a > b ? a : b;
-      if (!(w > 0.0)) w = 0.0;
-    }
-  }
+  if (i < P.nx && j < P.ny) w = b_dt_cell<D>(P, B, i, j, sidx);
   red[tid] = w;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -605,11 +624,7 @@ template <int D>
 __global__ void k_dt_fin(Params P, Bufs B) {
   double smax = __longlong_as_double((long long)B.ctr[C_SMAX]);
   B.ctr[C_SMAX] = 0;
-  double dt = B.scal[S_DTFIX] > 0.0 ? B.scal[S_DTFIX] : P.cfl * P.h / smax;
-  B.scal[S_DT] = dt;
-  B.scal[S_LX] = dt / P.dx;
-  B.scal[S_LY] = dt / P.dy;
-  B.scal[S_LV] = D == 2 ? dt / (P.dx * P.dy) : dt / P.dx;
+  dt_finish<D>(P, B, smax);
 }
 __global__ void k_time_advance(Params P, Bufs B) { B.scal[S_T] += B.scal[S_DT]; }
 
@@ -1154,28 +1169,31 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
   B.occ[didx][k] = (uint8_t)(1u << m);
 }
 
-// 1D bulk update: 256-cell tiles with a 3-cell frame
-constexpr int T1 = 256;
-__global__ void __launch_bounds__(256)
-k_flux_bulk1(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
-             double ccoef, int stage0) {
-  __shared__ double sW[3][T1 + 6];
-  __shared__ double sF[3][T1 + 1];
-  __shared__ uint8_t sChi[T1 + 6];
-  __shared__ uint8_t sBulk[T1 + 2];
-  int tid = threadIdx.x;
-  int i0 = blockIdx.x * T1, i = i0 + tid;
+// 1D bulk update of one tile of T = blockDim.x cells starting at i0, with a
+// 3-cell frame staged in LDS; every thread of the workgroup must call it.
+// LDS arrays are sized for T <= T1MAX.
+constexpr int T1MAX = 1024;
+struct Bulk1Smem {
+  double W[3][T1MAX + 6];
+  double F[3][T1MAX + 1];
+  uint8_t chi[T1MAX + 6];
+  uint8_t bulk[T1MAX + 2];
+};
+MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int sidx,
+                    int nidx, int didx, double bcoef, double ccoef, int stage0) {
+  int T = blockDim.x, tid = threadIdx.x;
+  int i = i0 + tid;
   bool inb = i < P.nx;
   int k = inb ? cid(P, i, 0) : 0;
   bool isb = inb && B.bulk[k];
   int nb = __syncthreads_count(isb);
-  if (nb == 0 || errored(B)) return;
+  if (nb == 0 || errored(B)) return;  // uniform across the workgroup
   if (tid == 0) {
     atomicAdd(&B.ctr[C_UPD], (unsigned long long)nb);
     atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nb);
   }
   const double* Qs = B.Q[sidx];
-  for (int q = tid; q < T1 + 6; q += 256) {
+  for (int q = tid; q < T + 6; q += T) {
     int ci = i0 - 3 + q;
     double r_ = 1.0, u_ = 0.0, p_ = 1.0;
     uint8_t ch = 0;
@@ -1196,24 +1214,24 @@ k_flux_bulk1(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
         p_ = B.W[o + 3 * (size_t)P.NC];
       }
     }
-    sW[0][q] = r_;
-    sW[1][q] = u_;
-    sW[2][q] = p_;
-    sChi[q] = ch;
+    S.W[0][q] = r_;
+    S.W[1][q] = u_;
+    S.W[2][q] = p_;
+    S.chi[q] = ch;
   }
-  for (int q = tid; q < T1 + 2; q += 256) {
+  for (int q = tid; q < T + 2; q += T) {
     int ci = i0 - 1 + q;
-    sBulk[q] = (ci >= 0 && ci < P.nx) ? B.bulk[cid(P, ci, 0)] : 0;
+    S.bulk[q] = (ci >= 0 && ci < P.nx) ? B.bulk[cid(P, ci, 0)] : 0;
   }
   __syncthreads();
-  for (int f = tid; f < T1 + 1; f += 256) {
+  for (int f = tid; f < T + 1; f += T) {
     // face f: between tile cells f-1 and f
-    if (!(sBulk[f] || sBulk[f + 1])) continue;
-    int m = sBulk[f + 1] ? sChi[f + 3] : sChi[f + 2];
+    if (!(S.bulk[f] || S.bulk[f + 1])) continue;
+    int m = S.bulk[f + 1] ? S.chi[f + 3] : S.chi[f + 2];
     double pinf = P.pinf[m];
-    const double* R0 = sW[0];
-    const double* U0 = sW[1];
-    const double* P0 = sW[2];
+    const double* R0 = S.W[0];
+    const double* U0 = S.W[1];
+    const double* P0 = S.W[2];
     Prim L, R;
     L.r = weno5(R0[f], R0[f + 1], R0[f + 2], R0[f + 3], R0[f + 4]);
     L.u = weno5(U0[f], U0[f + 1], U0[f + 2], U0[f + 3], U0[f + 4]);
@@ -1230,33 +1248,41 @@ k_flux_bulk1(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
     }
     double G[4];
     hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], G);
-    sF[0][f] = G[0];
-    sF[1][f] = G[1];
-    sF[2][f] = G[3];
+    S.F[0][f] = G[0];
+    S.F[1][f] = G[1];
+    S.F[2][f] = G[3];
   }
   __syncthreads();
-  if (!isb) return;
-  int m = sChi[tid + 3];
-  {
+  if (isb) {
+    int m = S.chi[tid + 3];
     Prim w;
-    w.r = sW[0][tid + 3];
-    w.u = sW[1][tid + 3];
+    w.r = S.W[0][tid + 3];
+    w.u = S.W[1][tid + 3];
     w.v = 0.0;
-    w.p = sW[2][tid + 3];
+    w.p = S.W[2][tid + 3];
     if (nonphys(w, P.pinf[m])) flag_error(P, B, i, 0);
+    double lx = B.scal[S_LX], lv = B.scal[S_LV];
+    size_t o = (size_t)m * 3 * P.NC + k;
+    const double* Qn = B.Q[nidx];
+    double* Qd = B.Q[didx];
+    for (int v = 0; v < 3; v++) {
+      double rhs = lx * (S.F[v][tid] - S.F[v][tid + 1]);
+      rhs = rhs + lv * 0.0;
+      double qs = Qs[o + (size_t)v * P.NC];
+      double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
+      Qd[o + (size_t)v * P.NC] = x;
+    }
+    B.occ[didx][k] = (uint8_t)(1u << m);
   }
-  double lx = B.scal[S_LX], lv = B.scal[S_LV];
-  size_t o = (size_t)m * 3 * P.NC + k;
-  const double* Qn = B.Q[nidx];
-  double* Qd = B.Q[didx];
-  for (int v = 0; v < 3; v++) {
-    double rhs = lx * (sF[v][tid] - sF[v][tid + 1]);
-    rhs = rhs + lv * 0.0;
-    double qs = Qs[o + (size_t)v * P.NC];
-    double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
-    Qd[o + (size_t)v * P.NC] = x;
-  }
-  B.occ[didx][k] = (uint8_t)(1u << m);
+  __syncthreads();  // the LDS tile is reused by the next call
+}
+
+constexpr int T1 = 256;
+__global__ void __launch_bounds__(256)
+k_flux_bulk1(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
+             double ccoef, int stage0) {
+  __shared__ Bulk1Smem S;
+  bulk1_tile(P, B, S, blockIdx.x * blockDim.x, sidx, nidx, didx, bcoef, ccoef, stage0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1531,11 +1557,154 @@ __global__ void k_pack(Params P, Bufs B, int sidx, double* Qo, double* ao,
 }
 
 // initial level set from an interior [ny][nx] array
-__global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* chi) {
-  CELL_LOOP_2D
+template <int D>
+MMD void b_load_ls(const Params& P, const Bufs& B, int i, int j, const double* phi,
+                   const int32_t* chi) {
+  int k = cid(P, i, j);
   size_t q = (size_t)j * P.nx + i;
   B.phi[k] = phi[q];
   B.chi[k] = (uint8_t)chi[q];
 }
+__global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* chi) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= P.nx || j >= P.ny) return;
+  b_load_ls<2>(P, B, i, j, phi, chi);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched 1D instances: one workgroup advances one instance through all
+// steps; every phase of the step is a loop of the workgroup's threads over
+// the instance's cells followed by a workgroup barrier.  Instances are
+// independent, so no grid-wide synchronisation is needed.
+// ---------------------------------------------------------------------------
+#define PHASE(call)                                       \
+  do {                                                    \
+    for (int i_ = tid; i_ < P.nx; i_ += T) { call; }      \
+    __syncthreads();                                      \
+  } while (0)
+
+struct BatchSmem {
+  Params P;
+  Bufs B;
+  Bulk1Smem S;
+  double red[T1MAX];
+};
+
+MMD void batch_load(const Params* Pa, const Bufs* Ba, BatchSmem& sm) {
+  if (threadIdx.x == 0) {
+    sm.P = Pa[blockIdx.x];
+    sm.B = Ba[blockIdx.x];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024)
+k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
+  __shared__ BatchSmem sm;
+  batch_load(Pa, Ba, sm);
+  const Params& P = sm.P;
+  const Bufs& B = sm.B;
+  int tid = threadIdx.x, T = blockDim.x;
+  double bc[3], cc[3];
+  int ns;
+  if (rk_order == 2) {
+    ns = 2;
+    bc[0] = 0.0; bc[1] = 0.5;
+    cc[0] = 1.0; cc[1] = 0.5;
+  } else {
+    ns = 3;
+    bc[0] = 0.0; bc[1] = 0.75; bc[2] = 1.0 / 3.0;
+    cc[0] = 1.0; cc[1] = 0.25; cc[2] = 2.0 / 3.0;
+  }
+  uint32_t stamp = (uint32_t)B.ctr[C_STAMP];
+  for (int n = 0; n < nsteps; n++) {
+    __syncthreads();
+    if (errored(B)) break;
+    int sidx = 0;
+    for (int s = 0; s < ns; s++) {
+      int didx = s == ns - 1 ? 0 : s + 1;
+      PHASE(b_real<1>(P, B, i_, 0, sidx));
+      if (s == 0) {
+        double w = 0.0;
+        for (int i = tid; i < P.nx; i += T) w = fmax(w, b_dt_cell<1>(P, B, i, 0, sidx));
+        sm.red[tid] = w;
+        __syncthreads();
+        for (int h = T / 2; h > 0; h >>= 1) {
+          if (tid < h) sm.red[tid] = fmax(sm.red[tid], sm.red[tid + h]);
+          __syncthreads();
+        }
+        if (tid == 0) dt_finish<1>(P, B, sm.red[0]);
+        __syncthreads();
+      }
+      PHASE(b_near_row<1>(P, B, i_, 0));
+      PHASE(b_near_col<1>(P, B, i_, 0));
+      for (int sw = 0; sw < P.kext + 4; sw++) PHASE(b_ext<1>(P, B, i_, 0, sidx, sw));
+      for (int t = tid; t < 2 * H * P.M; t += T) b_bc_W_x<1>(P, B, t, sidx);
+      __syncthreads();
+      if (s == 0) PHASE(b_vreset<1>(P, B, i_, 0));
+      PHASE(b_iface<1>(P, B, i_, 0, sidx, s == 0 ? 1 : 0));
+      if (s == 0) {
+        for (int sw = 0; sw < 4; sw++) PHASE(b_vext<1>(P, B, i_, 0, sw));
+        PHASE(b_vfill<1>(P, B, i_, 0, sidx));
+      }
+      PHASE(b_bulkflag<1>(P, B, i_, 0, sidx, 0));
+      for (int i0 = 0; i0 < P.nx; i0 += T)
+        bulk1_tile(P, B, sm.S, i0, sidx, 0, didx, bc[s], cc[s], s == 0 ? 1 : 0);
+      PHASE(b_flux_band<1>(P, B, i_, 0, sidx, 0, didx, bc[s], cc[s]));
+      PHASE(b_ls<1>(P, B, i_, 0, bc[s], cc[s]));
+      PHASE(b_ls_commit<1>(P, B, i_, 0));
+      for (int t = tid; t < 2 * H; t += T) b_bc_ls_x(P, t, B.phi, B.chi);
+      __syncthreads();
+      PHASE(b_classify<1>(P, B, i_, 0));
+      PHASE(b_dist_row<1>(P, B, i_, 0));
+      PHASE(b_geom<1>(P, B, i_, 0, didx, (const double*)nullptr));
+      PHASE(b_mix1<1>(P, B, i_, 0, didx, stamp));
+      PHASE(b_mix2<1>(P, B, i_, 0, didx, stamp));
+      stamp++;
+      sidx = didx;
+    }
+    if (tid == 0) B.scal[S_T] += B.scal[S_DT];
+  }
+  __syncthreads();
+  if (tid == 0) B.ctr[C_STAMP] = stamp;
+}
+
+// initial state of every instance; arrays are the concatenation of the
+// instances' interior cells (offset off[q] cells for instance q)
+__global__ void __launch_bounds__(1024)
+k_batch1d_init(const Params* Pa, const Bufs* Ba, const double* phi, const int32_t* chi,
+               const double* W, const int64_t* off) {
+  __shared__ BatchSmem sm;
+  batch_load(Pa, Ba, sm);
+  const Params& P = sm.P;
+  const Bufs& B = sm.B;
+  int tid = threadIdx.x, T = blockDim.x;
+  int64_t o = off[blockIdx.x];
+  const double* Wq = W + (size_t)P.M * 3 * o;
+  PHASE(b_load_ls<1>(P, B, i_, 0, phi + o, chi + o));
+  for (int t = tid; t < 2 * H; t += T) b_bc_ls_x(P, t, B.phi, B.chi);
+  __syncthreads();
+  PHASE(b_classify<1>(P, B, i_, 0));
+  PHASE(b_dist_row<1>(P, B, i_, 0));
+  PHASE(b_geom<1>(P, B, i_, 0, 0, Wq));
+  PHASE(b_init_Q<1>(P, B, i_, 0, Wq));
+}
+
+__global__ void __launch_bounds__(1024)
+k_batch1d_pack(const Params* Pa, const Bufs* Ba, double* Q, double* alpha, double* phi,
+               int32_t* chi, const int64_t* off) {
+  __shared__ BatchSmem sm;
+  batch_load(Pa, Ba, sm);
+  const Params& P = sm.P;
+  const Bufs& B = sm.B;
+  int tid = threadIdx.x, T = blockDim.x;
+  int64_t o = off[blockIdx.x];
+  PHASE(b_pack<1>(P, B, i_, 0, 0, Q ? Q + (size_t)P.M * 3 * o : nullptr,
+                  alpha ? alpha + (size_t)P.M * o : nullptr, phi ? phi + o : nullptr,
+                  chi ? chi + o : nullptr));
+}
+#undef PHASE
 
 }  // namespace mmfv

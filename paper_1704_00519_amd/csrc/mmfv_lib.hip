@@ -118,15 +118,8 @@ static bool valid_config(const mm_config* c, std::string& why) {
   return true;
 }
 
-extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** out) {
-  if (!cfg || !out) return fail(nullptr, MM_EINVAL, "NULL argument");
-  std::string why;
-  if (!valid_config(cfg, why)) return fail(nullptr, MM_EINVAL, why);
-  mm_ctx* c = new mm_ctx();
-  c->cfg = *cfg;
-  c->D = cfg->dim;
-  c->stream = (hipStream_t)hip_stream;
-  Params& P = c->P;
+static Params make_params(const mm_config* cfg) {
+  Params P;
   memset(&P, 0, sizeof(P));
   P.dim = cfg->dim;
   P.nx = cfg->nx;
@@ -155,6 +148,19 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
     P.inflow_W[q] = cfg->inflow_W[q];
   }
   P.inflow_mat = cfg->inflow_mat;
+  return P;
+}
+
+extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, MM_EINVAL, "NULL argument");
+  std::string why;
+  if (!valid_config(cfg, why)) return fail(nullptr, MM_EINVAL, why);
+  mm_ctx* c = new mm_ctx();
+  c->cfg = *cfg;
+  c->D = cfg->dim;
+  c->stream = (hipStream_t)hip_stream;
+  c->P = make_params(cfg);
+  const Params& P = c->P;
 
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
   Bufs& B = c->B;
@@ -508,3 +514,5 @@ extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
   out->bulk_bytes = u0 * 2.0 * w + u1 * 3.0 * w;
   return MM_OK;
 }
+
+#include "mmfv_batch.h"
