@@ -63,7 +63,8 @@ static size_t layout_bufs(const Params& P, Bufs& B, char* base) {
   take(B.cx, M * nc); take(B.cy, M * nc);
   take(B.W, M * 4 * nc); take(B.Wit, M * nc);
   take(B.cut, nc); take(B.xs, nc); take(B.dcut, nc); take(B.dls, nc);
-  take(B.rowc, nc); take(B.rowl, nc); take(B.nrow, nc); take(B.near4, nc);
+  take(B.rowc, nc); take(B.rowl, nc); take(B.tdc, nc); take(B.tdl, nc);
+  take(B.nrow, nc); take(B.near4, nc);
   take(B.bulk, nc);
   take(B.X, M * 4 * nc);
   take(B.vx, nc); take(B.vy, nc); take(B.vit, nc);

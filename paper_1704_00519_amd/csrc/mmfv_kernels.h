@@ -20,7 +20,7 @@ struct Bufs {
   double *al, *ax, *ay, *cx, *cy;
   double* W;
   uint8_t* Wit;
-  uint8_t *cut, *xs, *dcut, *dls, *rowc, *rowl, *nrow, *near4, *bulk;
+  uint8_t *cut, *xs, *dcut, *dls, *rowc, *rowl, *tdc, *tdl, *nrow, *near4, *bulk;
   double* X;
   double *vx, *vy;
   uint8_t* vit;
@@ -309,8 +309,9 @@ MMD void b_dist_row(const Params& P, const Bufs& B, int i, int j) {
     if (B.rowc[kk] && a < dc) dc = a;
     if (B.rowl[kk] && a < dl) dl = a;
   }
-  B.dcut[k] = (uint8_t)dc;
-  B.dls[k] = (uint8_t)dl;
+  // 1D: final distances; 2D: row distances for the column pass
+  (D == 1 ? B.dcut : B.tdc)[k] = (uint8_t)dc;
+  (D == 1 ? B.dls : B.tdl)[k] = (uint8_t)dl;
 }
 template <int D>
 __global__ void k_dist_row(Params P, Bufs B) {
@@ -319,8 +320,7 @@ __global__ void k_dist_row(Params P, Bufs B) {
   if (i >= P.nx || j >= P.ny) return;
   b_dist_row<D>(P, B, i, j);
 }
-// column pass: d = min over dj of max(|dj|, row distance); written back into
-// rowc/rowl (then swapped by the host)
+// column pass: d = min over dj of max(|dj|, row distance)
 __global__ void k_dist_col(Params P, Bufs B) {
   CELL_LOOP_2D
   int dc = RD, dl = RD;
@@ -329,14 +329,16 @@ __global__ void k_dist_col(Params P, Bufs B) {
     if (jj < 0 || jj >= P.ny) continue;
     int kk = cid(P, i, jj);
     int a = dj < 0 ? -dj : dj;
-    int c = B.dcut[kk] > a ? B.dcut[kk] : a;
-    int l = B.dls[kk] > a ? B.dls[kk] : a;
+    int c = B.tdc[kk] > a ? B.tdc[kk] : a;
+    int l = B.tdl[kk] > a ? B.tdl[kk] : a;
     if (c < dc) dc = c;
     if (l < dl) dl = l;
   }
-  B.rowc[k] = (uint8_t)dc;
-  B.rowl[k] = (uint8_t)dl;
+  B.dcut[k] = (uint8_t)dc;
+  B.dls[k] = (uint8_t)dl;
 }
+// next mixing stamp (device-resident so a captured step can be replayed)
+__global__ void k_stamp_next(Params P, Bufs B) { B.ctr[C_STAMP] += 1; }
 
 // ghost-band membership: OR of the real-material bits within Chebyshev 4
 template <int D>
@@ -1459,11 +1461,11 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   }
 }
 template <int D>
-__global__ void k_mix1(Params P, Bufs B, int didx, uint32_t stamp) {
+__global__ void k_mix1(Params P, Bufs B, int didx) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
-  b_mix1<D>(P, B, i, j, didx, stamp);
+  b_mix1<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP]);
 }
 
 template <int D>
@@ -1518,11 +1520,11 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   if (touched) occp[k] = (uint8_t)occ;
 }
 template <int D>
-__global__ void k_mix2(Params P, Bufs B, int didx, uint32_t stamp) {
+__global__ void k_mix2(Params P, Bufs B, int didx) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
-  b_mix2<D>(P, B, i, j, didx, stamp);
+  b_mix2<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP]);
 }
 
 // ---------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -26,6 +27,9 @@ struct mm_ctx {
   double* d_in = nullptr;   // staging of host inputs/outputs
   size_t d_in_bytes = 0;
   bool profiling = false;
+  hipGraph_t step_g = nullptr;      // one captured time step
+  hipGraphExec_t step_x = nullptr;
+  bool graph_off = false;
   std::vector<hipEvent_t> ev;  // pairs around bulk launches
   size_t ev_used = 0;
   double prof_ms = 0.0;
@@ -83,6 +87,10 @@ static hipError_t dalloc(mm_ctx* c, T** p, size_t n) {
 }
 
 static void free_all(mm_ctx* c) {
+  if (c->step_x) (void)hipGraphExecDestroy(c->step_x);
+  if (c->step_g) (void)hipGraphDestroy(c->step_g);
+  c->step_x = nullptr;
+  c->step_g = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   for (void* p : c->allocs) (void)hipFree(p);
@@ -177,6 +185,7 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.al, M * nc); A(B.ax, M * nc); A(B.ay, M * nc); A(B.cx, M * nc); A(B.cy, M * nc);
   A(B.W, M * 4 * nc); A(B.Wit, M * nc);
   A(B.cut, nc); A(B.xs, nc); A(B.dcut, nc); A(B.dls, nc); A(B.rowc, nc); A(B.rowl, nc);
+  A(B.tdc, nc); A(B.tdl, nc);
   A(B.nrow, nc); A(B.near4, nc); A(B.bulk, nc);
   A(B.X, M * 4 * nc);
   A(B.vx, nc); A(B.vy, nc); A(B.vit, nc);
@@ -192,6 +201,7 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   }
   unsigned long long init_ctr[C_N] = {0};
   init_ctr[C_ERR] = NO_ERR;
+  init_ctr[C_STAMP] = 1;
   if (hipMemcpy(B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice) != hipSuccess) {
     free_all(c);
     delete c;
@@ -237,11 +247,7 @@ static void classify(mm_ctx* c) {
   const Params& P = c->P;
   LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B);
   LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B);
-  if (D == 2) {
-    LAUNCH(k_dist_col, cell_grid(c), cell_block(c), P, c->B);
-    std::swap(c->B.dcut, c->B.rowc);
-    std::swap(c->B.dls, c->B.rowl);
-  }
+  if (D == 2) LAUNCH(k_dist_col, cell_grid(c), cell_block(c), P, c->B);
 }
 
 template <int D>
@@ -282,9 +288,9 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
   bc_ls<D>(c);
   classify<D>(c);
   LAUNCH(k_geom<D>, g, bl, P, c->B, didx, (const double*)nullptr);
-  uint32_t st = c->stamp++;
-  LAUNCH(k_mix1<D>, g, bl, P, c->B, didx, st);
-  LAUNCH(k_mix2<D>, g, bl, P, c->B, didx, st);
+  LAUNCH(k_mix1<D>, g, bl, P, c->B, didx);
+  LAUNCH(k_mix2<D>, g, bl, P, c->B, didx);
+  LAUNCH(k_stamp_next, dim3(1), dim3(1), P, c->B);
   (void)ns;
 }
 
@@ -354,6 +360,7 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   }
   unsigned long long init_ctr[C_N] = {0};
   init_ctr[C_ERR] = NO_ERR;
+  init_ctr[C_STAMP] = 1;
   HIP_OK(c, hipMemcpyAsync(c->B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemsetAsync(c->B.scal, 0, 8 * sizeof(double), c->stream));
   for (int b = 0; b < 3; b++) HIP_OK(c, hipMemsetAsync(c->B.occ[b], 0, P.NC, c->stream));
@@ -389,9 +396,32 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
   if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
   if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
   if (record_tape) return fail(c, MM_ENOTIMPL, "adjoint tape not available");
+  // Replay one captured step per time step when the work goes to a real
+  // stream; the null stream cannot be captured, and per-kernel profiling
+  // needs its events between launches.
+  bool graph = c->stream && !c->profiling && !c->graph_off && getenv("MMFV_NO_GRAPH") == nullptr;
+  if (graph && !c->step_x) {
+    bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      if (c->D == 2) one_step<2>(c);
+      else one_step<1>(c);
+      ok = hipStreamEndCapture(c->stream, &c->step_g) == hipSuccess && c->step_g;
+    }
+    if (ok) ok = hipGraphInstantiate(&c->step_x, c->step_g, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      c->graph_off = true;
+      graph = false;
+    }
+  }
   for (int n = 0; n < n_steps; n++) {
-    if (c->D == 2) one_step<2>(c);
-    else one_step<1>(c);
+    if (graph) {
+      HIP_OK(c, hipGraphLaunch(c->step_x, c->stream));
+    } else if (c->D == 2) {
+      one_step<2>(c);
+    } else {
+      one_step<1>(c);
+    }
   }
   HIP_OK(c, hipGetLastError());
   c->steps += n_steps;

@@ -193,3 +193,61 @@ def test_adjoint_entry_point_reports_not_implemented(pk):
     st = pk.load().mm_adjoint_step(s._h, None, None, None, None, 0)
     assert st == 6
     del C
+
+
+def hip_stream():
+    import ctypes as C
+    h = C.c_void_p()
+    assert C.CDLL("libamdhip64.so").hipStreamCreate(C.byref(h)) == 0
+    return h.value
+
+
+def test_graph_replay_matches_oracle(pk):
+    # on a non-null stream each time step is replayed from a captured graph
+    w = wl.triple_point(nx=112, ny=48)
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    s = pk.Solver(w["cfg"], stream=hip_stream())
+    s.init(w["phi"], w["chi"], w["W"])
+    for chunk in (1, 4, 15):
+        assert o.step(chunk) == 0
+        s.step(chunk)
+        assert_parity(o, s, label=f"graph after {chunk}")
+
+
+def batch_instances(n, nmin, nmax, steps):
+    return wl.batched_tubes(n_inst=n, nmin=nmin, nmax=nmax, steps=steps)
+
+
+@pytest.mark.parametrize("threads", [0, 64, 1024])
+def test_batched_instances_match_oracle(pk, threads):
+    steps = 25
+    insts = batch_instances(12, 40, 700, steps)
+    b = pk.Batch(insts)
+    b.init(insts)
+    if threads:
+        b.set_threads(threads)
+    b.step(steps)
+    got = b.get()
+    diags = b.diag()
+    for q, w in enumerate(insts):
+        o = oracle.run(w, steps=steps)
+        g = o.get()
+        for k in ("Q", "alpha", "phi", "chi"):
+            assert np.array_equal(g[k], got[q][k]), (q, k)
+        assert diags[q]["t"] == o.diag()["t"]
+
+
+def test_batched_first_instances_of_the_workload(pk):
+    # the seeded 256-instance workload; the first 8 instances are checked
+    # against the oracle after 40 steps
+    insts = wl.batched_tubes(steps=40)
+    b = pk.Batch(insts)
+    b.init(insts)
+    b.step(40)
+    got = b.get()
+    for q in range(8):
+        o = oracle.run(insts[q], steps=40)
+        g = o.get()
+        for k in ("Q", "alpha", "phi", "chi"):
+            assert np.array_equal(g[k], got[q][k]), (q, k)
