@@ -27,13 +27,14 @@ struct Bufs {
   double* mixM;
   int32_t* mixT;
   uint32_t *srcStamp, *tgtStamp;
+  int32_t* tiles;          // active tiles of the current stage
   double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t
   unsigned long long* ctr; // smax bits, error cell, counters
 };
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
-       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_N };
+       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 
 MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
@@ -1574,6 +1575,86 @@ __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* ch
   b_load_ls<2>(P, B, i, j, phi, chi);
 }
 
+
+// ---------------------------------------------------------------------------
+// Active tiles.  Work near interfaces touches a few percent of the cells;
+// after each level-set update the tiles (16 x 16 cells in 2D, 256 in 1D)
+// that hold, within one cell of the tile, a cell within 8 of a cut cell,
+// within 12 of the level-set band, or a material state other than its own,
+// are listed, and the near-interface kernels walk that list.  Every cell
+// those kernels act on lies in a listed tile, so results do not change.
+// ---------------------------------------------------------------------------
+MMD int tile_w(const Params& P) { return P.dim == 2 ? 16 : 256; }
+MMD int tile_h(const Params& P) { return P.dim == 2 ? 16 : 1; }
+MMD int tiles_x(const Params& P) { return (P.nx + tile_w(P) - 1) / tile_w(P); }
+
+__global__ void k_tiles_reset(Params P, Bufs B) { B.ctr[C_NTILES] = 0; }
+
+__global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
+  int tw = tile_w(P), th = tile_h(P);
+  int tile = blockIdx.x;
+  int i0 = (tile % tiles_x(P)) * tw, j0 = (tile / tiles_x(P)) * th;
+  int ew = tw + 2, eh = P.dim == 2 ? th + 2 : 1;
+  bool f = false;
+  for (int q = threadIdx.x; q < ew * eh; q += blockDim.x) {
+    int i = i0 - 1 + q % ew, j = P.dim == 2 ? j0 - 1 + q / ew : 0;
+    if (!interior(P, i, j)) continue;
+    int k = cid(P, i, j);
+    uint8_t own = (uint8_t)(1u << B.chi[k]);
+    if (B.dcut[k] <= 8 || B.dls[k] <= RV || B.occ[didx][k] != own || B.occ[nidx][k] != own)
+      f = true;
+  }
+  if (__syncthreads_or(f) && threadIdx.x == 0) {
+    unsigned long long at = atomicAdd(&B.ctr[C_NTILES], 1ull);
+    B.tiles[at] = tile;
+  }
+}
+
+// run body(i, j) over the cells of the listed tiles; 256 threads per block
+template <typename F>
+MMD void for_tiles(const Params& P, const Bufs& B, F body) {
+  int ntile = (int)B.ctr[C_NTILES];
+  int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    int tile = B.tiles[t];
+    int i = (tile % ntx) * tw + (int)threadIdx.x % tw;
+    int j = (tile / ntx) * th + (int)threadIdx.x / tw;
+    if (i < P.nx && j < P.ny) body(i, j);
+  }
+}
+
+#define TILE_KERNEL(name, body, decl, ...)                                   \
+  template <int D>                                                          \
+  __global__ void __launch_bounds__(256) name(Params P, Bufs B decl) {     \
+    for_tiles(P, B, [&](int i, int j) { body<D>(P, B, i, j __VA_ARGS__); }); \
+  }
+#define COMMA ,
+TILE_KERNEL(t_real, b_real, COMMA int sidx, COMMA sidx)
+TILE_KERNEL(t_near_row, b_near_row, )
+TILE_KERNEL(t_near_col, b_near_col, )
+TILE_KERNEL(t_ext, b_ext, COMMA int sidx COMMA int sweep, COMMA sidx COMMA sweep)
+TILE_KERNEL(t_vreset, b_vreset, )
+TILE_KERNEL(t_iface, b_iface, COMMA int sidx COMMA int stage0, COMMA sidx COMMA stage0)
+TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
+TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
+TILE_KERNEL(t_flux_band, b_flux_band,
+            COMMA int sidx COMMA int nidx COMMA int didx COMMA double bc COMMA double cc,
+            COMMA sidx COMMA nidx COMMA didx COMMA bc COMMA cc)
+TILE_KERNEL(t_ls, b_ls, COMMA double bc COMMA double cc, COMMA bc COMMA cc)
+TILE_KERNEL(t_ls_commit, b_ls_commit, )
+TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
+template <int D>
+__global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
+  uint32_t st = (uint32_t)B.ctr[C_STAMP];
+  for_tiles(P, B, [&](int i, int j) { b_mix1<D>(P, B, i, j, didx, st); });
+}
+template <int D>
+__global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx) {
+  uint32_t st = (uint32_t)B.ctr[C_STAMP];
+  for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st); });
+}
+#undef TILE_KERNEL
+#undef COMMA
 
 // ---------------------------------------------------------------------------
 // Batched 1D instances: one workgroup advances one instance through all

@@ -191,6 +191,7 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.vx, nc); A(B.vy, nc); A(B.vit, nc);
   A(B.mixM, M * 3 * 4 * nc); A(B.mixT, M * 3 * nc);
   A(B.srcStamp, M * nc); A(B.tgtStamp, M * nc);
+  A(B.tiles, (size_t)((P.nx + 15) / 16 + 16) * ((P.ny + 15) / 16 + 1));
   A(B.scal, 8); A(B.ctr, C_N);
 #undef A
   if (e != hipSuccess) {
@@ -250,27 +251,44 @@ static void classify(mm_ctx* c) {
   if (D == 2) LAUNCH(k_dist_col, cell_grid(c), cell_block(c), P, c->B);
 }
 
+static int n_tiles(const Params& P) {
+  int tw = P.dim == 2 ? 16 : 256, th = P.dim == 2 ? 16 : 1;
+  return ((P.nx + tw - 1) / tw) * ((P.ny + th - 1) / th);
+}
+static dim3 tile_grid(const mm_ctx* c) {
+  int n = n_tiles(c->P);
+  return dim3(n < 1024 ? n : 1024);
+}
+
+// list the active tiles after the level set of the next stage is known
+template <int D>
+static void build_tiles(mm_ctx* c, int didx, int nidx) {
+  LAUNCH(k_tiles_reset, dim3(1), dim3(1), c->P, c->B);
+  LAUNCH(k_tiles, dim3(n_tiles(c->P)), dim3(256), c->P, c->B, didx, nidx);
+}
+
 template <int D>
 static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double b,
                   double cc) {
   const Params& P = c->P;
   dim3 g = cell_grid(c), bl = cell_block(c);
-  LAUNCH(k_real<D>, g, bl, P, c->B, sidx);
+  dim3 tg = tile_grid(c), tb(256);
+  LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
   if (s == 0) {
     LAUNCH(k_dt<D>, g, bl, P, c->B, sidx);
     LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
   }
-  LAUNCH(k_near_row<D>, g, bl, P, c->B);
-  LAUNCH(k_near_col<D>, g, bl, P, c->B);
-  for (int sw = 0; sw < P.kext + 4; sw++) LAUNCH(k_ext<D>, g, bl, P, c->B, sidx, sw);
+  LAUNCH(t_near_row<D>, tg, tb, P, c->B);
+  LAUNCH(t_near_col<D>, tg, tb, P, c->B);
+  for (int sw = 0; sw < P.kext + 4; sw++) LAUNCH(t_ext<D>, tg, tb, P, c->B, sidx, sw);
   LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
   if (D == 2)
     LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
-  if (s == 0) LAUNCH(k_vreset<D>, g, bl, P, c->B);
-  LAUNCH(k_iface<D>, g, bl, P, c->B, sidx, s == 0 ? 1 : 0);
+  if (s == 0) LAUNCH(t_vreset<D>, tg, tb, P, c->B);
+  LAUNCH(t_iface<D>, tg, tb, P, c->B, sidx, s == 0 ? 1 : 0);
   if (s == 0) {
-    for (int sw = 0; sw < 4; sw++) LAUNCH(k_vext<D>, g, bl, P, c->B, sw);
-    LAUNCH(k_vfill<D>, g, bl, P, c->B, sidx);
+    for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
+    LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
   LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx);
   prof_mark(c);
@@ -282,14 +300,15 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
            cc, s == 0 ? 1 : 0);
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
-  LAUNCH(k_flux_band<D>, g, bl, P, c->B, sidx, nidx, didx, b, cc);
-  LAUNCH(k_ls<D>, g, bl, P, c->B, b, cc);
-  LAUNCH(k_ls_commit<D>, g, bl, P, c->B);
+  LAUNCH(t_flux_band<D>, tg, tb, P, c->B, sidx, nidx, didx, b, cc);
+  LAUNCH(t_ls<D>, tg, tb, P, c->B, b, cc);
+  LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
   bc_ls<D>(c);
   classify<D>(c);
-  LAUNCH(k_geom<D>, g, bl, P, c->B, didx, (const double*)nullptr);
-  LAUNCH(k_mix1<D>, g, bl, P, c->B, didx);
-  LAUNCH(k_mix2<D>, g, bl, P, c->B, didx);
+  build_tiles<D>(c, didx, nidx);
+  LAUNCH(t_geom<D>, tg, tb, P, c->B, didx, (const double*)nullptr);
+  LAUNCH(t_mix1<D>, tg, tb, P, c->B, didx);
+  LAUNCH(t_mix2<D>, tg, tb, P, c->B, didx);
   LAUNCH(k_stamp_next, dim3(1), dim3(1), P, c->B);
   (void)ns;
 }
@@ -371,11 +390,13 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
     classify<2>(c);
     LAUNCH(k_geom<2>, g, bl, P, c->B, 0, dW);
     LAUNCH(k_init_Q<2>, g, bl, P, c->B, dW);
+    build_tiles<2>(c, 0, 0);
   } else {
     bc_ls<1>(c);
     classify<1>(c);
     LAUNCH(k_geom<1>, g, bl, P, c->B, 0, dW);
     LAUNCH(k_init_Q<1>, g, bl, P, c->B, dW);
+    build_tiles<1>(c, 0, 0);
   }
   HIP_OK(c, hipGetLastError());
   HIP_OK(c, hipStreamSynchronize(c->stream));
