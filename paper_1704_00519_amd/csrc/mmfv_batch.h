@@ -71,6 +71,8 @@ static size_t layout_bufs(const Params& P, Bufs& B, char* base) {
   take(B.mixM, M * 3 * 4 * nc); take(B.mixT, M * 3 * nc);
   take(B.srcStamp, M * nc); take(B.tgtStamp, M * nc);
   take(B.tiles, 1);
+  take(B.blist, 1);
+  B.glist = nullptr;  // the batched kernel sweeps cells, not a queue
   take(B.scal, 8); take(B.ctr, C_N);
   return (at + 255) & ~(size_t)255;
 }

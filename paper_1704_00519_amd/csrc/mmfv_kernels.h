@@ -28,13 +28,15 @@ struct Bufs {
   int32_t* mixT;
   uint32_t *srcStamp, *tgtStamp;
   int32_t* tiles;          // active tiles of the current stage
+  int32_t* blist;          // cells updated by the general (band) path
+  int32_t* glist;          // (cell, material) pairs waiting for a ghost state
   double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t
   unsigned long long* ctr; // smax bits, error cell, counters
 };
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
-       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_N };
+       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 
 MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
@@ -226,6 +228,7 @@ MMD void b_bc_W_x(const Params& P, const Bufs& B, int t, int sidx) {
 template <int D>
 __global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) B.ctr[C_NBAND] = 0;  // the band list is rebuilt by k_bulkflag
   if (t >= P.ny * 2 * H * P.M) return;
   b_bc_W_x<D>(P, B, t, sidx);
 }
@@ -291,6 +294,7 @@ template <int D>
 __global__ void k_classify(Params P, Bufs B) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i == 0 && j == 0) B.ctr[C_NTILES] = 0;  // the tile list is rebuilt next
   if (i >= P.nx || j >= P.ny) return;
   b_classify<D>(P, B, i, j);
 }
@@ -383,6 +387,16 @@ MMD void b_near_col(const Params& P, const Bufs& B, int i, int j) {
     }
   }
   B.near4[k] = (uint8_t)b;
+  if (B.glist) {
+    // queue the (cell, material) pairs of the ghost band that have no state
+    for (int r = 0; r < P.M; r++) {
+      if (!((b >> r) & 1)) continue;
+      if (!B.cut[k] && B.chi[k] == r) continue;
+      if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
+      unsigned long long at = atomicAdd(&B.ctr[C_NGHOST], 1ull);
+      B.glist[at] = k * 8 + r;
+    }
+  }
 }
 template <int D>
 __global__ void k_near_col(Params P, Bufs B) {
@@ -634,89 +648,94 @@ __global__ void k_time_advance(Params P, Bufs B) { B.scal[S_T] += B.scal[S_DT]; 
 // ---------------------------------------------------------------------------
 // Ghost states: Jacobi sweeps over the ghost band of every material
 // ---------------------------------------------------------------------------
+// one ghost-extension sweep for material r at cell (i, j)
+template <int D>
+MMD void ext_one(const Params& P, const Bufs& B, int i, int j, int r, int sidx, int sweep) {
+  int k = cid(P, i, j);
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  auto valid_prev = [&](int ii, int jj) -> bool {
+    if (!interior(P, ii, jj)) return false;
+    int kk = cid(P, ii, jj);
+    if (!B.cut[kk] && B.chi[kk] == r) return true;
+    if (B.dcut[kk] > 4) return false;
+    uint8_t it = B.Wit[(size_t)r * P.NC + kk];
+    return it != 0 && it <= sweep + 1;
+  };
+  double out[4];
+  bool ok = false;
+  if (sweep < P.kext) {
+    double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
+    double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
+    int xi = -1, yj = -1;
+    bool hx = false, hy = false;
+    if (gx != 0.0) {
+      xi = i + (gx > 0.0 ? 1 : -1);
+      hx = valid_prev(xi, j);
+    }
+    if (gy != 0.0) {
+      yj = j + (gy > 0.0 ? 1 : -1);
+      hy = valid_prev(i, yj);
+    }
+    bool vd;
+    if (hx && hy) {
+      Prim a = Wget<D>(P, B, Q, occ, r, xi, j, vd);
+      Prim b = Wget<D>(P, B, Q, occ, r, i, yj, vd);
+      double wx = fabs(gx), wy = fabs(gy);
+      out[0] = (wx * a.r + wy * b.r) / (wx + wy);
+      out[1] = (wx * a.u + wy * b.u) / (wx + wy);
+      out[2] = (wx * a.v + wy * b.v) / (wx + wy);
+      out[3] = (wx * a.p + wy * b.p) / (wx + wy);
+      ok = true;
+    } else if (hx || hy) {
+      Prim a = hx ? Wget<D>(P, B, Q, occ, r, xi, j, vd) : Wget<D>(P, B, Q, occ, r, i, yj, vd);
+      out[0] = a.r;
+      out[1] = a.u;
+      out[2] = a.v;
+      out[3] = a.p;
+      ok = true;
+    }
+  } else {
+    double row[3][4];
+    int cnt = 0;
+    for (int dj = -1; dj <= 1; dj++) {
+      double a[3][4];
+      for (int di = -1; di <= 1; di++) {
+        bool use = (di != 0 || dj != 0) && (D == 2 || dj == 0) &&
+                   valid_prev(i + di, j + dj);
+        Prim w;
+        w.r = w.u = w.v = w.p = 0.0;
+        bool vd;
+        if (use) w = Wget<D>(P, B, Q, occ, r, i + di, j + dj, vd);
+        a[di + 1][0] = use ? w.r : 0.0;
+        a[di + 1][1] = use ? w.u : 0.0;
+        a[di + 1][2] = use ? w.v : 0.0;
+        a[di + 1][3] = use ? w.p : 0.0;
+        cnt += use ? 1 : 0;
+      }
+      for (int c = 0; c < 4; c++) row[dj + 1][c] = (a[0][c] + a[2][c]) + a[1][c];
+    }
+    if (cnt > 0) {
+      for (int c = 0; c < 4; c++)
+        out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
+      ok = true;
+    }
+  }
+  if (ok) {
+    size_t o = (size_t)r * 4 * P.NC;
+    for (int c = 0; c < 4; c++) B.W[o + (size_t)c * P.NC + k] = out[c];
+    B.Wit[(size_t)r * P.NC + k] = (uint8_t)(sweep + 2);
+  }
+}
 template <int D>
 MMD void b_ext(const Params& P, const Bufs& B, int i, int j, int sidx, int sweep) {
   int k = cid(P, i, j);
-  (void)k;
   if (errored(B) || B.dcut[k] > 4) return;
-  const double* Q = B.Q[sidx];
-  const uint8_t* occ = B.occ[sidx];
   for (int r = 0; r < P.M; r++) {
     if (!((B.near4[k] >> r) & 1)) continue;
     if (!B.cut[k] && B.chi[k] == r) continue;  // pure real cell
     if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
-    auto valid_prev = [&](int ii, int jj) -> bool {
-      if (!interior(P, ii, jj)) return false;
-      int kk = cid(P, ii, jj);
-      if (!B.cut[kk] && B.chi[kk] == r) return true;
-      if (B.dcut[kk] > 4) return false;
-      uint8_t it = B.Wit[(size_t)r * P.NC + kk];
-      return it != 0 && it <= sweep + 1;
-    };
-    double out[4];
-    bool ok = false;
-    if (sweep < P.kext) {
-      double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
-      double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
-      int xi = -1, yj = -1;
-      bool hx = false, hy = false;
-      if (gx != 0.0) {
-        xi = i + (gx > 0.0 ? 1 : -1);
-        hx = valid_prev(xi, j);
-      }
-      if (gy != 0.0) {
-        yj = j + (gy > 0.0 ? 1 : -1);
-        hy = valid_prev(i, yj);
-      }
-      bool vd;
-      if (hx && hy) {
-        Prim a = Wget<D>(P, B, Q, occ, r, xi, j, vd);
-        Prim b = Wget<D>(P, B, Q, occ, r, i, yj, vd);
-        double wx = fabs(gx), wy = fabs(gy);
-        out[0] = (wx * a.r + wy * b.r) / (wx + wy);
-        out[1] = (wx * a.u + wy * b.u) / (wx + wy);
-        out[2] = (wx * a.v + wy * b.v) / (wx + wy);
-        out[3] = (wx * a.p + wy * b.p) / (wx + wy);
-        ok = true;
-      } else if (hx || hy) {
-        Prim a = hx ? Wget<D>(P, B, Q, occ, r, xi, j, vd) : Wget<D>(P, B, Q, occ, r, i, yj, vd);
-        out[0] = a.r;
-        out[1] = a.u;
-        out[2] = a.v;
-        out[3] = a.p;
-        ok = true;
-      }
-    } else {
-      double row[3][4];
-      int cnt = 0;
-      for (int dj = -1; dj <= 1; dj++) {
-        double a[3][4];
-        for (int di = -1; di <= 1; di++) {
-          bool use = (di != 0 || dj != 0) && (D == 2 || dj == 0) &&
-                     valid_prev(i + di, j + dj);
-          Prim w;
-          w.r = w.u = w.v = w.p = 0.0;
-          bool vd;
-          if (use) w = Wget<D>(P, B, Q, occ, r, i + di, j + dj, vd);
-          a[di + 1][0] = use ? w.r : 0.0;
-          a[di + 1][1] = use ? w.u : 0.0;
-          a[di + 1][2] = use ? w.v : 0.0;
-          a[di + 1][3] = use ? w.p : 0.0;
-          cnt += use ? 1 : 0;
-        }
-        for (int c = 0; c < 4; c++) row[dj + 1][c] = (a[0][c] + a[2][c]) + a[1][c];
-      }
-      if (cnt > 0) {
-        for (int c = 0; c < 4; c++)
-          out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
-        ok = true;
-      }
-    }
-    if (ok) {
-      size_t o = (size_t)r * 4 * P.NC;
-      for (int c = 0; c < 4; c++) B.W[o + (size_t)c * P.NC + k] = out[c];
-      B.Wit[(size_t)r * P.NC + k] = (uint8_t)(sweep + 2);
-    }
+    ext_one<D>(P, B, i, j, r, sidx, sweep);
   }
 }
 template <int D>
@@ -889,18 +908,50 @@ __global__ void k_vfill(Params P, Bufs B, int sidx) {
 // Fluxes and RK stage update
 // ---------------------------------------------------------------------------
 template <int D>
-MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int nidx) {
-  int k = cid(P, i, j);
-  (void)k;
+MMD bool is_bulk(const Params& P, const Bufs& B, int k, int sidx, int nidx) {
   uint8_t own = (uint8_t)(1u << B.chi[k]);
-  B.bulk[k] = (B.dcut[k] > 3 && B.occ[sidx][k] == own && B.occ[nidx][k] == own) ? 1 : 0;
+  return B.dcut[k] > 3 && B.occ[sidx][k] == own && B.occ[nidx][k] == own;
 }
 template <int D>
-__global__ void k_bulkflag(Params P, Bufs B, int sidx, int nidx) {
+MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int nidx) {
+  int k = cid(P, i, j);
+  B.bulk[k] = is_bulk<D>(P, B, k, sidx, nidx) ? 1 : 0;
+}
+// Bulk flags for the stage, the compact list of all other cells, and (at
+// stage 0) the CFL maximum.  Every thread reaches the barriers.
+template <int D>
+__global__ void __launch_bounds__(256) k_bulkflag(Params P, Bufs B, int sidx, int nidx,
+                                                  int with_dt) {
+  __shared__ int s_cnt, s_base;
+  __shared__ double red[256];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_bulkflag<D>(P, B, i, j, sidx, nidx);
+  int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  bool inb = i < P.nx && j < P.ny;
+  int k = inb ? cid(P, i, j) : 0;
+  bool band = false;
+  if (inb) {
+    bool bk = is_bulk<D>(P, B, k, sidx, nidx);
+    B.bulk[k] = bk ? 1 : 0;
+    band = !bk;
+  }
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  int my = band ? atomicAdd(&s_cnt, 1) : 0;
+  __syncthreads();
+  if (tid == 0 && s_cnt) s_base = (int)atomicAdd(&B.ctr[C_NBAND], (unsigned long long)s_cnt);
+  __syncthreads();
+  if (band) B.blist[s_base + my] = k;
+  if (with_dt) {
+    red[tid] = inb ? b_dt_cell<D>(P, B, i, j, sidx) : 0.0;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+      __syncthreads();
+    }
+    if (tid == 0)
+      atomicMax(&B.ctr[C_SMAX], (unsigned long long)__double_as_longlong(red[0]));
+  }
 }
 
 // flux of material r across the face between cell (i, j) and its +1
@@ -1472,8 +1523,6 @@ __global__ void k_mix1(Params P, Bufs B, int didx) {
 template <int D>
 MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp) {
   int k = cid(P, i, j);
-  (void)k;
-  if (errored(B)) return;
   double* Q = B.Q[didx];
   uint8_t* occp = B.occ[didx];
   unsigned occ = occp[k];
@@ -1483,28 +1532,42 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     bool tgt = B.tgtStamp[(size_t)r * P.NC + k] == stamp;
     if (!src && !tgt) continue;
     touched = true;
+    // exchanges that apply to this cell: its own (as a source) or those its
+    // neighbours sent it (as a target); at most one slot per neighbour
+    const double* mrow[3][3];
+    for (int dj = 0; dj < 3; dj++)
+      for (int di = 0; di < 3; di++) mrow[dj][di] = nullptr;
+    if (src) {
+      for (int q = 0; q < 3; q++)
+        if (B.mixT[((size_t)r * 3 + q) * P.NC + k] >= 0)
+          mrow[0][q] = B.mixM + ((size_t)r * 3 + q) * 4 * P.NC + k;
+    } else {
+      for (int dj = -1; dj <= 1; dj++)
+        for (int di = -1; di <= 1; di++) {
+          int ii = i + di, jj = j + dj;
+          if ((di == 0 && dj == 0) || (D == 1 && dj != 0) || !interior(P, ii, jj)) continue;
+          int n = cid(P, ii, jj);
+          if (B.srcStamp[(size_t)r * P.NC + n] != stamp) continue;
+          for (int q = 0; q < 3; q++)
+            if (B.mixT[((size_t)r * 3 + q) * P.NC + n] == k)
+              mrow[dj + 1][di + 1] = B.mixM + ((size_t)r * 3 + q) * 4 * P.NC + n;
+        }
+    }
     double nq[4];
     bool nz = false;
     for (int v = 0; v < 4; v++) {
       double q0 = loadQ<D>(P, Q, (const uint8_t*)occp, r, v, k);
+      size_t ov = (size_t)v * P.NC;
       if (src) {
         for (int q = 0; q < 3; q++)
-          if (B.mixT[((size_t)r * 3 + q) * P.NC + k] >= 0)
-            q0 = q0 + B.mixM[(((size_t)r * 3 + q) * 4 + v) * P.NC + k];
+          if (mrow[0][q]) q0 = q0 + mrow[0][q][ov];
       } else {
         double row[3];
-        for (int dj = -1; dj <= 1; dj++) {
-          double a[3] = {0.0, 0.0, 0.0};
-          for (int di = -1; di <= 1; di++) {
-            int ii = i + di, jj = j + dj;
-            if ((di == 0 && dj == 0) || (D == 1 && dj != 0) || !interior(P, ii, jj)) continue;
-            int n = cid(P, ii, jj);
-            if (B.srcStamp[(size_t)r * P.NC + n] != stamp) continue;
-            for (int q = 0; q < 3; q++)
-              if (B.mixT[((size_t)r * 3 + q) * P.NC + n] == k)
-                a[di + 1] = B.mixM[(((size_t)r * 3 + q) * 4 + v) * P.NC + n];
-          }
-          row[dj + 1] = (a[0] + a[2]) + a[1];
+        for (int dj = 0; dj < 3; dj++) {
+          double a0 = mrow[dj][0] ? mrow[dj][0][ov] : 0.0;
+          double a1 = mrow[dj][1] ? mrow[dj][1][ov] : 0.0;
+          double a2 = mrow[dj][2] ? mrow[dj][2][ov] : 0.0;
+          row[dj] = (a0 + a2) + a1;
         }
         q0 = q0 - ((row[0] + row[2]) + row[1]);
       }
@@ -1577,6 +1640,98 @@ __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* ch
 
 
 // ---------------------------------------------------------------------------
+// General update of the listed (non-bulk) cells: one lane per face of a cell
+// computes that face's aperture-weighted flux for every material; the lane
+// of the left face then combines them into the stage update.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_flux_list(Params P, Bufs B, int sidx, int nidx,
+                                                   int didx, double bcoef, double ccoef) {
+  constexpr int FPC = D == 2 ? 4 : 2;  // faces per cell
+  constexpr int CPB = 256 / FPC;       // cells per block
+  __shared__ double sF[CPB][FPC][MAXM][4];
+  int tid = threadIdx.x, c = tid / FPC, f = tid % FPC;
+  int nb = (int)B.ctr[C_NBAND];
+  if (errored(B)) return;
+  const double* Qs = B.Q[sidx];
+  const uint8_t* os = B.occ[sidx];
+  for (int base = blockIdx.x * CPB; base < nb; base += gridDim.x * CPB) {
+    int idx = base + c;
+    bool act = idx < nb;
+    int k = act ? B.blist[idx] : 0;
+    int i = k % P.NX - H, j = k / P.NX - P.HY;
+    if (act) {
+      for (int r = 0; r < P.M; r++) {
+        double A;
+        int fi, fj, dir;
+        bool count;
+        if (f == 0) { A = apx<D>(P, B, r, i - 1, j); fi = i - 1; fj = j; dir = 0; count = i == 0; }
+        else if (f == 1) { A = apx<D>(P, B, r, i, j); fi = i; fj = j; dir = 0; count = true; }
+        else if (f == 2) { A = apy(P, B, r, i, j - 1); fi = i; fj = j - 1; dir = 1; count = j == 0; }
+        else { A = apy(P, B, r, i, j); fi = i; fj = j; dir = 1; count = true; }
+        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        if (A > 0.0) face_flux<D>(P, B, Qs, os, r, fi, fj, dir, count, F);
+        for (int v = 0; v < 4; v++) sF[c][f][r][v] = A > 0.0 ? A * F[v] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (act && f == 0) {
+      const double* Qn = B.Q[nidx];
+      const uint8_t* on = B.occ[nidx];
+      double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+      if (!B.cut[k]) {
+        bool vd;
+        int r = B.chi[k];
+        Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
+        if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
+      }
+      unsigned long long nact = 0;
+      unsigned occ = 0;
+      for (int r = 0; r < P.M; r++) {
+        if (alpha_at<D>(P, B, r, k) > 0.0) nact++;
+        double out[4];
+        bool nz = false;
+        for (int v = 0; v < 4; v++) {
+          if (D == 1 && v == 2) {
+            out[v] = 0.0;
+            continue;
+          }
+          double rhs = lx * (sF[c][0][r][v] - sF[c][1][r][v]);
+          if (D == 2) rhs = rhs + ly * (sF[c][2][r][v] - sF[c][FPC - 1][r][v]);
+          double X = B.cut[k] ? B.X[((size_t)r * 4 + v) * P.NC + k] : 0.0;
+          rhs = rhs + lv * X;
+          double qn = loadQ<D>(P, Qn, on, r, v, k);
+          double qs = loadQ<D>(P, Qs, os, r, v, k);
+          double x = bcoef * qn + ccoef * (qs + rhs);
+          out[v] = x;
+          if (x != 0.0) nz = true;
+        }
+        if (nz) {
+          occ |= 1u << r;
+          for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[v]);
+        }
+      }
+      B.occ[didx][k] = (uint8_t)occ;
+      if (nact) atomicAdd(&B.ctr[C_UPD], nact);
+    }
+    __syncthreads();
+  }
+}
+
+// one ghost-extension sweep over the queued (cell, material) pairs
+template <int D>
+__global__ void __launch_bounds__(256) k_ext_list(Params P, Bufs B, int sidx, int sweep) {
+  int n = (int)B.ctr[C_NGHOST];
+  if (errored(B)) return;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    int e = B.glist[q];
+    int k = e >> 3, r = e & 7;
+    if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
+    ext_one<D>(P, B, k % P.NX - H, k / P.NX - P.HY, r, sidx, sweep);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Active tiles.  Work near interfaces touches a few percent of the cells;
 // after each level-set update the tiles (16 x 16 cells in 2D, 256 in 1D)
 // that hold, within one cell of the tile, a cell within 8 of a cut cell,
@@ -1629,7 +1784,15 @@ MMD void for_tiles(const Params& P, const Bufs& B, F body) {
     for_tiles(P, B, [&](int i, int j) { body<D>(P, B, i, j __VA_ARGS__); }); \
   }
 #define COMMA ,
-TILE_KERNEL(t_real, b_real, COMMA int sidx, COMMA sidx)
+template <int D>
+__global__ void __launch_bounds__(256) t_real(Params P, Bufs B, int sidx) {
+  // a new mixing stamp per stage (the previous stage's mixing is complete)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    B.ctr[C_STAMP] += 1;
+    B.ctr[C_NGHOST] = 0;  // refilled by t_near_col
+  }
+  for_tiles(P, B, [&](int i, int j) { b_real<D>(P, B, i, j, sidx); });
+}
 TILE_KERNEL(t_near_row, b_near_row, )
 TILE_KERNEL(t_near_col, b_near_col, )
 TILE_KERNEL(t_ext, b_ext, COMMA int sidx COMMA int sweep, COMMA sidx COMMA sweep)

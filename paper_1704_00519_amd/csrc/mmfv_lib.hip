@@ -192,6 +192,8 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.mixM, M * 3 * 4 * nc); A(B.mixT, M * 3 * nc);
   A(B.srcStamp, M * nc); A(B.tgtStamp, M * nc);
   A(B.tiles, (size_t)((P.nx + 15) / 16 + 16) * ((P.ny + 15) / 16 + 1));
+  A(B.blist, nc);
+  A(B.glist, M * nc);
   A(B.scal, 8); A(B.ctr, C_N);
 #undef A
   if (e != hipSuccess) {
@@ -263,7 +265,6 @@ static dim3 tile_grid(const mm_ctx* c) {
 // list the active tiles after the level set of the next stage is known
 template <int D>
 static void build_tiles(mm_ctx* c, int didx, int nidx) {
-  LAUNCH(k_tiles_reset, dim3(1), dim3(1), c->P, c->B);
   LAUNCH(k_tiles, dim3(n_tiles(c->P)), dim3(256), c->P, c->B, didx, nidx);
 }
 
@@ -274,13 +275,10 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
   LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
-  if (s == 0) {
-    LAUNCH(k_dt<D>, g, bl, P, c->B, sidx);
-    LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
-  }
   LAUNCH(t_near_row<D>, tg, tb, P, c->B);
   LAUNCH(t_near_col<D>, tg, tb, P, c->B);
-  for (int sw = 0; sw < P.kext + 4; sw++) LAUNCH(t_ext<D>, tg, tb, P, c->B, sidx, sw);
+  for (int sw = 0; sw < P.kext + 4; sw++)
+    LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
   LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
   if (D == 2)
     LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
@@ -290,7 +288,8 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
     for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
-  LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx);
+  LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx, s == 0 ? 1 : 0);
+  if (s == 0) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
   prof_mark(c);
   if (D == 2)
     LAUNCH(k_flux_bulk2, dim3((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY), dim3(TX, TY), P,
@@ -300,7 +299,7 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
            cc, s == 0 ? 1 : 0);
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
-  LAUNCH(t_flux_band<D>, tg, tb, P, c->B, sidx, nidx, didx, b, cc);
+  LAUNCH(k_flux_list<D>, dim3(512), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
   LAUNCH(t_ls<D>, tg, tb, P, c->B, b, cc);
   LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
   bc_ls<D>(c);
@@ -309,7 +308,6 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
   LAUNCH(t_geom<D>, tg, tb, P, c->B, didx, (const double*)nullptr);
   LAUNCH(t_mix1<D>, tg, tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, tg, tb, P, c->B, didx);
-  LAUNCH(k_stamp_next, dim3(1), dim3(1), P, c->B);
   (void)ns;
 }
 
