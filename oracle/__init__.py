@@ -15,20 +15,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmfv_oracle.c")
+_DUAL = os.path.join(_HERE, "or_dual.h")
 _LIB = os.path.join(_HERE, "libmmfv_oracle.so")
+_LIB_T = os.path.join(_HERE, "libmmfv_oracle_tangent.so")
 MAXM = 8
 N_DIAG_HEAD = 9
 
 
+def _stale(lib, srcs):
+    return not os.path.exists(lib) or \
+        any(os.path.getmtime(lib) < os.path.getmtime(x) for x in srcs)
+
+
 def build(force=True):
-    """Compile the oracle into ``oracle/libmmfv_oracle.so``."""
-    if not force and os.path.exists(_LIB) and \
-            os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
-    subprocess.check_call(cmd)
-    os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle into ``oracle/libmmfv_oracle.so`` (C, double) and
+    its tangent build ``oracle/libmmfv_oracle_tangent.so`` (the same source
+    compiled as C++ with a value+derivative scalar)."""
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+    if force or _stale(_LIB, [_SRC]):
+        subprocess.check_call(["gcc", *flags, "-o", _LIB + ".tmp", _SRC, "-lm"])
+        os.replace(_LIB + ".tmp", _LIB)
+    if force or _stale(_LIB_T, [_SRC, _DUAL]):
+        subprocess.check_call(["g++", "-std=c++17", "-DOR_TANGENT", *flags, "-o",
+                               _LIB_T + ".tmp", "-x", "c++", _SRC, "-lm"])
+        os.replace(_LIB_T + ".tmp", _LIB_T)
     return _LIB
 
 
@@ -60,16 +70,15 @@ def make_config(cfg):
     return c
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or \
-                os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+def lib(tangent=False):
+    path = _LIB_T if tangent else _LIB
+    if path not in _libs:
+        if _stale(_LIB, [_SRC]) or _stale(_LIB_T, [_SRC, _DUAL]):
+            build(force=False)
+        L = C.CDLL(path)
         vp = C.c_void_p
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
@@ -83,6 +92,7 @@ def lib():
         L.or_get_closure.argtypes = [vp, vp, vp]
         L.or_diag.argtypes = [vp, dp]
         L.or_set_dt.argtypes = [vp, C.c_double]
+        L.or_set_state.argtypes = [vp, dp, dp, ip]
         L.or_err_cell.restype = C.c_long
         L.or_err_cell.argtypes = [vp]
         d = C.c_double
@@ -90,8 +100,13 @@ def lib():
         L.or_t_weno5.argtypes = [d, d, d, d, d]
         L.or_t_hllc.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
-        _lib = L
-    return _lib
+        if tangent:
+            L.or_init_tangent.argtypes = [vp, dp, ip, dp, dp]
+            L.or_set_inflow_tangent.argtypes = [vp, dp]
+            L.or_seed_state.argtypes = [vp, dp, dp]
+            L.or_get_tangent.argtypes = [vp, vp, vp, vp]
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -99,12 +114,19 @@ def _ptr(a):
 
 
 class Oracle:
-    """One solver instance.  ``cfg`` is a plain dict (see ``workloads``)."""
+    """One solver instance.  ``cfg`` is a plain dict (see ``workloads``).
+    With ``tangent=True`` the instance is the tangent build: every value is
+    the same, and each quantity also carries one directional derivative
+    (seeded by ``init_tangent``, ``set_inflow_tangent`` or ``seed_state``,
+    read by ``get_tangent``); the step size is held fixed under
+    differentiation."""
 
-    def __init__(self, cfg):
+    def __init__(self, cfg, tangent=False):
         self.cfg = dict(cfg)
+        self.tangent = bool(tangent)
+        self._L = lib(self.tangent)
         self._c = make_config(cfg)
-        self._h = lib().or_create(C.byref(self._c))
+        self._h = self._L.or_create(C.byref(self._c))
         if not self._h:
             raise ValueError("oracle: invalid configuration")
         self.ny, self.nx = int(cfg["ny"]), int(cfg["nx"])
@@ -113,7 +135,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().or_destroy(h)
+            self._L.or_destroy(h)
             self._h = None
 
     def init(self, phi, chi, W):
@@ -121,53 +143,53 @@ class Oracle:
         chi = np.ascontiguousarray(chi, dtype=np.int32).reshape(self.ny, self.nx)
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(
             self.M, self.nv, self.ny, self.nx)
-        return lib().or_init(self._h, phi, chi, W)
+        return self._L.or_init(self._h, phi, chi, W)
 
     def step(self, n=1):
-        return lib().or_step(self._h, int(n))
+        return self._L.or_step(self._h, int(n))
 
     def set_dt(self, dt):
-        lib().or_set_dt(self._h, float(dt))
+        self._L.or_set_dt(self._h, float(dt))
 
     def hllc(self, m, WL, WR):
         F = np.zeros(4)
-        lib().or_t_hllc(self._h, int(m), np.ascontiguousarray(WL, float),
+        self._L.or_t_hllc(self._h, int(m), np.ascontiguousarray(WL, float),
                         np.ascontiguousarray(WR, float), F)
         return F
 
     def iface(self, mL, WL, mR, WR):
         out = np.zeros(4)
-        lib().or_t_iface(self._h, int(mL), np.ascontiguousarray(WL, float),
+        self._L.or_t_iface(self._h, int(mL), np.ascontiguousarray(WL, float),
                          int(mR), np.ascontiguousarray(WR, float), out)
         return dict(SL=out[0], SR=out[1], SM=out[2], pstar=out[3])
 
     def err_cell(self):
-        return lib().or_err_cell(self._h)
+        return self._L.or_err_cell(self._h)
 
     def get(self):
         Q = np.zeros((self.M, self.nv, self.ny, self.nx))
         al = np.zeros((self.M, self.ny, self.nx))
         phi = np.zeros((self.ny, self.nx))
         chi = np.zeros((self.ny, self.nx), dtype=np.int32)
-        lib().or_get(self._h, _ptr(Q), _ptr(al), _ptr(phi), _ptr(chi))
+        self._L.or_get(self._h, _ptr(Q), _ptr(al), _ptr(phi), _ptr(chi))
         return dict(Q=Q, alpha=al, phi=phi, chi=chi)
 
     def apertures(self):
         Ax = np.zeros((self.M, self.ny, self.nx + 1))
         Ay = np.zeros((self.M, self.ny + 1, self.nx)) if self.cfg["dim"] == 2 \
             else None
-        lib().or_get_apertures(self._h, _ptr(Ax), _ptr(Ay))
+        self._L.or_get_apertures(self._h, _ptr(Ax), _ptr(Ay))
         return Ax, Ay
 
     def closure(self):
         cx = np.zeros((self.M, self.ny, self.nx))
         cy = np.zeros((self.M, self.ny, self.nx))
-        lib().or_get_closure(self._h, _ptr(cx), _ptr(cy))
+        self._L.or_get_closure(self._h, _ptr(cx), _ptr(cy))
         return cx, cy
 
     def diag(self):
         out = np.zeros(N_DIAG_HEAD + 2 * self.M * 4)
-        lib().or_diag(self._h, out)
+        self._L.or_diag(self._h, out)
         M = self.M
         head = out[:N_DIAG_HEAD]
         return dict(t=head[0], dt=head[1], steps=int(head[2]),
@@ -176,6 +198,44 @@ class Oracle:
                     n_mixsrc=int(head[7]), n_updates=int(head[8]),
                     bnd=out[9:9 + 4 * M].reshape(M, 4),
                     xsum=out[9 + 4 * M:9 + 8 * M].reshape(M, 4))
+
+    def set_state(self, Q, phi, chi):
+        """Replace (Q, phi, chi); the geometry is rebuilt from the level set
+        with the current partial densities as correction masses."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(self.M, self.nv, self.ny, self.nx)
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.ny, self.nx)
+        chi = np.ascontiguousarray(chi, dtype=np.int32).reshape(self.ny, self.nx)
+        return self._L.or_set_state(self._h, Q, phi, chi)
+
+    # -- tangent build only ------------------------------------------------
+    def init_tangent(self, phi, chi, W, dW):
+        """Initial state with derivative dW of the primitive input field."""
+        assert self.tangent
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.ny, self.nx)
+        chi = np.ascontiguousarray(chi, dtype=np.int32).reshape(self.ny, self.nx)
+        shp = (self.M, self.nv, self.ny, self.nx)
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(shp)
+        dW = np.ascontiguousarray(dW, dtype=np.float64).reshape(shp)
+        return self._L.or_init_tangent(self._h, phi, chi, W, dW)
+
+    def set_inflow_tangent(self, d):
+        assert self.tangent
+        self._L.or_set_inflow_tangent(self._h, np.ascontiguousarray(d, dtype=np.float64))
+
+    def seed_state(self, dQ, dphi):
+        """Set the derivative of the current state (Q, phi)."""
+        assert self.tangent
+        dQ = np.ascontiguousarray(dQ, dtype=np.float64).reshape(self.M, self.nv, self.ny, self.nx)
+        dphi = np.ascontiguousarray(dphi, dtype=np.float64).reshape(self.ny, self.nx)
+        self._L.or_seed_state(self._h, dQ, dphi)
+
+    def get_tangent(self):
+        assert self.tangent
+        dQ = np.zeros((self.M, self.nv, self.ny, self.nx))
+        da = np.zeros((self.M, self.ny, self.nx))
+        dphi = np.zeros((self.ny, self.nx))
+        self._L.or_get_tangent(self._h, _ptr(dQ), _ptr(da), _ptr(dphi))
+        return dict(Q=dQ, alpha=da, phi=dphi)
 
 
 def weno5(v1, v2, v3, v4, v5):

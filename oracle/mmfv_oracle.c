@@ -27,6 +27,24 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The arithmetic type of the state and of every computed quantity.  The
+ * plain build (C) uses double.  The tangent build compiles this same file as
+ * C++ with OR_TANGENT defined, where real carries a value and one directional
+ * derivative (forward-mode differentiation); its values are computed by the
+ * same double operations in the same order, so both builds take the same
+ * branches and produce bitwise the same values.  RV() is the value of a
+ * real, CONST_R() a real with the derivative dropped. */
+#ifdef OR_TANGENT
+#include "or_dual.h"
+typedef or_dual real;
+#define RV(x) or_value(x)
+#define CONST_R(x) or_dual(or_value(x))
+#else
+typedef double real;
+#define RV(x) (x)
+#define CONST_R(x) (x)
+#endif
+
 #define OR_H 4
 #define OR_NV 4
 #define OR_MAXM 8
@@ -53,33 +71,35 @@ typedef struct {
   double dx, dy, h, bls, idx, idy;
   double igm1[OR_MAXM];
   /* regional level set: current stage, time n, next stage */
-  double *phi, *phin, *phit;
+  real *phi, *phin, *phit;
   int *chi, *chin, *chit;
   /* conserved state [M][4][NC]: current stage, time n, after the RK update */
-  double *Q, *Qn, *Qt;
+  real *Q, *Qn, *Qt;
   /* cut-cell geometry [M][NC]; ax[k] is the x-face i+1/2 of cell k,
      ay[k] the y-face j+1/2 */
-  double *al, *ax, *ay, *cx, *cy;
+  real *al, *ax, *ay, *cx, *cy;
   /* primitive state and validity [M][4][NC], [M][NC] */
-  double *W, *lw;
+  real *W, *lw;
   unsigned char *Wv, *lok, *band, *band2;
   int *list;
-  double *X;       /* interface exchange [M][4][NC] */
-  double *vx, *vy; /* level-set advection velocity v^n */
+  real *X;       /* interface exchange [M][4][NC] */
+  real *vx, *vy; /* level-set advection velocity v^n */
   unsigned char *vok, *reg; /* velocity set / level-set update region */
-  double *lv;       /* velocity extension scratch */
-  double *Fx, *Fy; /* face fluxes [M][4][NC] */
-  double *mass;    /* [M][NC] scratch for the volume-fraction correction */
-  double *cv;      /* corner scratch [NC] */
+  real *lv;       /* velocity extension scratch */
+  real *Fx, *Fy; /* face fluxes [M][4][NC] */
+  real *mass;    /* [M][NC] scratch for the volume-fraction correction */
+  real *cv;      /* corner scratch [NC] */
   int *co;         /* corner owner scratch [NC] */
   unsigned char *xs; /* X_s bitmask [NC] */
-  double *mixM;    /* [M][3][4][NC] mixing exchanges */
+  real *mixM;    /* [M][3][4][NC] mixing exchanges */
   int *mixT;       /* [M][3][NC] mixing target cell (-1 = none) */
-  double t, dt, dt_fixed;
+  real inflow[4];  /* primitive state on inflow sides */
+  double t, dt_fixed;
+  real dt;         /* step size; its derivative is always zero (frozen) */
   long nstep;
   long n_posfix, n_fluxskip, n_ifskip, n_stranded, n_mixsrc, n_upd;
-  double bnd[OR_MAXM][OR_NV], bnd_c[OR_MAXM][OR_NV];
-  double xsum[OR_MAXM][OR_NV], xsum_c[OR_MAXM][OR_NV];
+  real bnd[OR_MAXM][OR_NV], bnd_c[OR_MAXM][OR_NV];
+  real xsum[OR_MAXM][OR_NV], xsum_c[OR_MAXM][OR_NV];
   int err_code;
   long err_cell;
 } St;
@@ -88,8 +108,8 @@ typedef struct {
 #define M1(s, a, m, k) ((a)[(size_t)(m) * (s)->NC + (k)])
 #define M4(s, a, m, v, k) ((a)[((size_t)(m) * OR_NV + (v)) * (s)->NC + (k)])
 
-static void neumaier(double *sum, double *comp, double x) {
-  double t = *sum + x;
+static void neumaier(real *sum, real *comp, real x) {
+  real t = *sum + x;
   if (fabs(*sum) >= fabs(x))
     *comp += (*sum - t) + x;
   else
@@ -102,12 +122,12 @@ static void neumaier(double *sum, double *comp, double x) {
 /* ------------------------------------------------------------------------ */
 
 /* primitive (rho, u, v, p) from conserved cell averages U (not alpha U) */
-static void prim(const St *s, int m, const double *U, double *W) {
+static void prim(const St *s, int m, const real *U, real *W) {
   double g = s->c.gamma[m], pinf = s->c.pinf[m];
-  double rho = U[0];
-  double u = U[1] / rho;
-  double v = U[2] / rho;
-  double ke = 0.5 * rho * (u * u + v * v);
+  real rho = U[0];
+  real u = U[1] / rho;
+  real v = U[2] / rho;
+  real ke = 0.5 * rho * (u * u + v * v);
   W[0] = rho;
   W[1] = u;
   W[2] = v;
@@ -115,8 +135,8 @@ static void prim(const St *s, int m, const double *U, double *W) {
 }
 
 /* total energy density rho E of a primitive state */
-static double energy(const St *s, int m, double rho, double u, double v,
-                     double p) {
+static real energy(const St *s, int m, real rho, real u, real v,
+                     real p) {
   double g = s->c.gamma[m], pinf = s->c.pinf[m];
   return (p + g * pinf) * s->igm1[m] + 0.5 * rho * (u * u + v * v);
 }
@@ -126,25 +146,25 @@ static double energy(const St *s, int m, double rho, double u, double v,
  * Psi, Upsilon and p/rho).  Stiffened gas: Psi = (p + gamma p_inf)/rho,
  * Upsilon = gamma - 1, so c^2 = Psi + Upsilon p/rho = gamma (p + p_inf)/rho.
  * States are (rho, u_normal, u_tangential, p). */
-static void wave_speeds(const double *WL, double gL, double piL,
-                        const double *WR, double gR, double piR, double *SL,
-                        double *SR) {
-  double rL = WL[0], uL = WL[1], pL = WL[3];
-  double rR = WR[0], uR = WR[1], pR = WR[3];
-  double irL = 1.0 / rL, irR = 1.0 / rR;
-  double porL = pL * irL, porR = pR * irR;
-  double psiL = (pL + gL * piL) * irL, psiR = (pR + gR * piR) * irR;
-  double upsL = gL - 1.0, upsR = gR - 1.0;
-  double cL = sqrt(psiL + upsL * porL);
-  double cR = sqrt(psiR + upsR * porR);
-  double sL = sqrt(rL), sR = sqrt(rR);
-  double iw = 1.0 / (sL + sR);
-  double psi_t = (sL * psiL + sR * psiR) * iw;
-  double ups_t = (sL * upsL + sR * upsR) * iw;
-  double u_t = (sL * uL + sR * uR) * iw;
-  double du = (uR - uL) * iw;
-  double por_t = (sL * porL + sR * porR) * iw + 0.5 * (sL * sR) * (du * du);
-  double c_t = sqrt(psi_t + ups_t * por_t);
+static void wave_speeds(const real *WL, double gL, double piL,
+                        const real *WR, double gR, double piR, real *SL,
+                        real *SR) {
+  real rL = WL[0], uL = WL[1], pL = WL[3];
+  real rR = WR[0], uR = WR[1], pR = WR[3];
+  real irL = 1.0 / rL, irR = 1.0 / rR;
+  real porL = pL * irL, porR = pR * irR;
+  real psiL = (pL + gL * piL) * irL, psiR = (pR + gR * piR) * irR;
+  real upsL = gL - 1.0, upsR = gR - 1.0;
+  real cL = sqrt(psiL + upsL * porL);
+  real cR = sqrt(psiR + upsR * porR);
+  real sL = sqrt(rL), sR = sqrt(rR);
+  real iw = 1.0 / (sL + sR);
+  real psi_t = (sL * psiL + sR * psiR) * iw;
+  real ups_t = (sL * upsL + sR * upsR) * iw;
+  real u_t = (sL * uL + sR * uR) * iw;
+  real du = (uR - uL) * iw;
+  real por_t = (sL * porL + sR * porR) * iw + 0.5 * (sL * sR) * (du * du);
+  real c_t = sqrt(psi_t + ups_t * por_t);
   *SL = fmin(uL - cL, u_t - c_t);
   *SR = fmax(u_t + c_t, uR + cR);
 }
@@ -152,26 +172,26 @@ static void wave_speeds(const double *WL, double gL, double piL,
 /* Contact speed S_M of Toro's HLLC solver (Sec. 2.3.2).  The two momentum
  * terms and the pressure difference are summed separately, so swapping the
  * two states and the sign of the velocities gives exactly -S_M. */
-static double contact_speed(const double *WL, const double *WR, double SL,
-                            double SR) {
-  double rL = WL[0], uL = WL[1], pL = WL[3];
-  double rR = WR[0], uR = WR[1], pR = WR[3];
-  double num = ((SR - uR) * rR * uR + (uL - SL) * rL * uL) + (pL - pR);
-  double den = (SR - uR) * rR + (uL - SL) * rL;
+static real contact_speed(const real *WL, const real *WR, real SL,
+                            real SR) {
+  real rL = WL[0], uL = WL[1], pL = WL[3];
+  real rR = WR[0], uR = WR[1], pR = WR[3];
+  real num = ((SR - uR) * rR * uR + (uL - SL) * rL * uL) + (pL - pR);
+  real den = (SR - uR) * rR + (uL - SL) * rL;
   return num / den;
 }
 
 /* HLLC flux (Toro) across a cell face inside one material.  W are
  * (rho, u_n, u_t, p); F = (mass, normal momentum, tangential momentum,
  * energy). */
-static void hllc_flux(const St *s, int m, const double *WL, const double *WR,
-                      double *F) {
+static void hllc_flux(const St *s, int m, const real *WL, const real *WR,
+                      real *F) {
   double g = s->c.gamma[m], pinf = s->c.pinf[m];
-  double SL, SR;
+  real SL, SR;
   wave_speeds(WL, g, pinf, WR, g, pinf, &SL, &SR);
-  double SM = contact_speed(WL, WR, SL, SR);
-  const double *Wk;
-  double Sk;
+  real SM = contact_speed(WL, WR, SL, SR);
+  const real *Wk;
+  real Sk;
   int star;
   if (SL >= 0.0) {
     Wk = WL; Sk = SL; star = 0;
@@ -182,21 +202,21 @@ static void hllc_flux(const St *s, int m, const double *WL, const double *WR,
   } else {
     Wk = WR; Sk = SR; star = 0;
   }
-  double r = Wk[0], u = Wk[1], v = Wk[2], p = Wk[3];
-  double E = energy(s, m, r, u, v, p);
-  double ru = r * u;
+  real r = Wk[0], u = Wk[1], v = Wk[2], p = Wk[3];
+  real E = energy(s, m, r, u, v, p);
+  real ru = r * u;
   F[0] = ru;
   F[1] = ru * u + p;
   F[2] = ru * v;
   F[3] = u * (E + p);
   if (star) {
-    double d = Sk - u;
-    double mk = r * d;
-    double coef = mk / (Sk - SM);
-    double Us0 = coef;
-    double Us1 = coef * SM;
-    double Us2 = coef * v;
-    double Us3 = coef * (E / r + (SM - u) * (SM + p / mk));
+    real d = Sk - u;
+    real mk = r * d;
+    real coef = mk / (Sk - SM);
+    real Us0 = coef;
+    real Us1 = coef * SM;
+    real Us2 = coef * v;
+    real Us3 = coef * (E / r + (SM - u) * (SM + p / mk));
     F[0] = F[0] + Sk * (Us0 - r);
     F[1] = F[1] + Sk * (Us1 - ru);
     F[2] = F[2] + Sk * (Us2 - r * v);
@@ -214,27 +234,27 @@ static void hllc_flux(const St *s, int m, const double *WL, const double *WR,
  * the normalised combination needs a single division; the 1/6 of the three
  * candidate stencils is folded into the same division.  Algebraically this is
  * the textbook formula. */
-static double weno5(double v1, double v2, double v3, double v4, double v5) {
-  double t, u;
+static real weno5(real v1, real v2, real v3, real v4, real v5) {
+  real t, u;
   t = v1 - 2.0 * v2 + v3;
   u = v1 - 4.0 * v2 + 3.0 * v3;
-  double b0 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  real b0 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
   t = v2 - 2.0 * v3 + v4;
   u = v2 - v4;
-  double b1 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  real b1 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
   t = v3 - 2.0 * v4 + v5;
   u = 3.0 * v3 - 4.0 * v4 + v5;
-  double b2 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
-  double e0 = 1e-6 + b0, e1 = 1e-6 + b1, e2 = 1e-6 + b2;
+  real b2 = (13.0 / 12.0) * (t * t) + 0.25 * (u * u);
+  real e0 = 1e-6 + b0, e1 = 1e-6 + b1, e2 = 1e-6 + b2;
   e0 = e0 * e0;
   e1 = e1 * e1;
   e2 = e2 * e2;
-  double a0 = 0.1 * (e1 * e2);
-  double a1 = 0.6 * (e0 * e2);
-  double a2 = 0.3 * (e0 * e1);
-  double q0 = 2.0 * v1 - 7.0 * v2 + 11.0 * v3;
-  double q1 = -v2 + 5.0 * v3 + 2.0 * v4;
-  double q2 = 2.0 * v3 + 5.0 * v4 - v5;
+  real a0 = 0.1 * (e1 * e2);
+  real a1 = 0.6 * (e0 * e2);
+  real a2 = 0.3 * (e0 * e1);
+  real q0 = 2.0 * v1 - 7.0 * v2 + 11.0 * v3;
+  real q1 = -v2 + 5.0 * v3 + 2.0 * v4;
+  real q2 = 2.0 * v3 + 5.0 * v4 - v5;
   return (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * (a0 + a1 + a2));
 }
 
@@ -249,7 +269,7 @@ static int src_hi(int i, int n, int type) {
   return type == BC_REFLECTIVE ? 2 * n - 1 - i : n - 1;
 }
 
-static void fill_d(St *s, double *f, double sx, double sy) {
+static void fill_d(St *s, real *f, double sx, double sy) {
   int nx = s->c.nx, ny = s->c.ny;
   for (int j = 0; j < ny; j++)
     for (int i = -OR_H; i < 0; i++) {
@@ -290,7 +310,7 @@ static void fill_i(St *s, int *f) {
 static void fill_W(St *s) {
   int nx = s->c.nx, ny = s->c.ny;
   for (int m = 0; m < s->M; m++) {
-    double *f[4];
+    real *f[4];
     for (int v = 0; v < 4; v++) f[v] = &M4(s, s->W, m, v, 0);
     unsigned char *fv = &M1(s, s->Wv, m, 0);
     /* x sides */
@@ -315,7 +335,7 @@ static void fill_W(St *s) {
         for (int j = 0; j < ny; j++)
           for (int i = -OR_H; i < 0; i++) {
             int ii = side == 0 ? i : nx + (-1 - i);
-            for (int v = 0; v < 4; v++) f[v][ID(s, ii, j)] = s->c.inflow_W[v];
+            for (int v = 0; v < 4; v++) f[v][ID(s, ii, j)] = s->inflow[v];
             fv[ID(s, ii, j)] = 1;
           }
     if (s->c.dim < 2) continue;
@@ -341,13 +361,13 @@ static void fill_W(St *s) {
         for (int i = -OR_H; i < nx + OR_H; i++)
           for (int j = -OR_H; j < 0; j++) {
             int jj = side == 2 ? j : ny + (-1 - j);
-            for (int v = 0; v < 4; v++) f[v][ID(s, i, jj)] = s->c.inflow_W[v];
+            for (int v = 0; v < 4; v++) f[v][ID(s, i, jj)] = s->inflow[v];
             fv[ID(s, i, jj)] = 1;
           }
   }
 }
 
-static void fill_ls(St *s, double *phi, int *chi) {
+static void fill_ls(St *s, real *phi, int *chi) {
   fill_d(s, phi, 1.0, 1.0);
   fill_i(s, chi);
 }
@@ -357,7 +377,7 @@ static void fill_ls(St *s, double *phi, int *chi) {
 /* ------------------------------------------------------------------------ */
 /* Construction operator C_r (Eq. construction): +phi inside material r,
  * -phi elsewhere. */
-static double lsv(const double *phi, const int *chi, int r, int k) {
+static real lsv(const real *phi, const int *chi, int r, int k) {
   return chi[k] == r ? phi[k] : -phi[k];
 }
 
@@ -382,35 +402,35 @@ static void local_sets(St *s, const int *chi, unsigned char *xs) {
 /* Reading (tie rule): a point is inside material r if its local level-set
  * value is positive, or zero while r is the smallest indicator among the
  * cells that define the point; this gives every zero a single owner. */
-static int inside(double v, int owner, int r) {
+static int inside(real v, int owner, int r) {
   return v > 0.0 || (v == 0.0 && owner == r);
 }
 
 /* Fraction of a segment on which the linear interpolant of its end values is
  * inside. */
-static double seg_frac(double v0, int in0, double v1, int in1) {
+static real seg_frac(real v0, int in0, real v1, int in1) {
   if (in0 && in1) return 1.0;
   if (!in0 && !in1) return 0.0;
-  double vp = in0 ? v0 : v1, vm = in0 ? v1 : v0;
+  real vp = in0 ? v0 : v1, vm = in0 ? v1 : v0;
   if (vp <= 0.0) return 0.0;
   return vp / (vp - vm);
 }
 
 /* Fraction of a triangle on which the linear interpolant of its vertex values
  * is inside. */
-static double tri_frac(double a, int ia, double b, int ib, double c, int ic) {
+static real tri_frac(real a, int ia, real b, int ib, real c, int ic) {
   int n = ia + ib + ic;
   if (n == 3) return 1.0;
   if (n == 0) return 0.0;
   if (n == 1) {
-    double p, q, r;
+    real p, q, r;
     if (ia) { p = a; q = b; r = c; }
     else if (ib) { p = b; q = a; r = c; }
     else { p = c; q = a; r = b; }
     if (p <= 0.0) return 0.0;
     return (p * p) / ((p - q) * (p - r));
   }
-  double o, p, q;
+  real o, p, q;
   if (!ia) { o = a; p = b; q = c; }
   else if (!ib) { o = b; p = a; q = c; }
   else { o = c; p = a; q = b; }
@@ -429,16 +449,16 @@ static double tri_frac(double a, int ia, double b, int ib, double c, int ic) {
  * triangles.  In 1D the face value is the mean of the two cells.  The
  * interface segment Delta Omega^r times its normal (pointing into r) closes
  * the polygon: c^r = ((A_{i+1/2} - A_{i-1/2}) dy, (A_{j+1/2} - A_{j-1/2}) dx). */
-static void geometry(St *s, const double *phi, const int *chi) {
+static void geometry(St *s, const real *phi, const int *chi) {
   int nx = s->c.nx, ny = s->c.ny;
   for (int r = 0; r < s->M; r++) {
-    double *al = &M1(s, s->al, r, 0), *ax = &M1(s, s->ax, r, 0),
+    real *al = &M1(s, s->al, r, 0), *ax = &M1(s, s->ax, r, 0),
            *ay = &M1(s, s->ay, r, 0), *cx = &M1(s, s->cx, r, 0),
            *cy = &M1(s, s->cy, r, 0);
     if (s->c.dim == 1) {
       for (int i = -1; i < nx; i++) {
         int a = ID(s, i, 0), b = ID(s, i + 1, 0);
-        double f = (lsv(phi, chi, r, a) + lsv(phi, chi, r, b)) * 0.5;
+        real f = (lsv(phi, chi, r, a) + lsv(phi, chi, r, b)) * 0.5;
         int own = chi[a] < chi[b] ? chi[a] : chi[b];
         s->cv[a] = f;
         s->co[a] = own;
@@ -446,7 +466,7 @@ static void geometry(St *s, const double *phi, const int *chi) {
       }
       for (int i = 0; i < nx; i++) {
         int k = ID(s, i, 0), kl = ID(s, i - 1, 0);
-        double c = lsv(phi, chi, r, k);
+        real c = lsv(phi, chi, r, k);
         int ic = inside(c, chi[k], r);
         int il = inside(s->cv[kl], s->co[kl], r), ir = inside(s->cv[k], s->co[k], r);
         al[k] = (seg_frac(s->cv[kl], il, c, ic) + seg_frac(c, ic, s->cv[k], ir)) * 0.5;
@@ -460,7 +480,7 @@ static void geometry(St *s, const double *phi, const int *chi) {
       for (int i = -1; i < nx; i++) {
         int k00 = ID(s, i, j), k10 = ID(s, i + 1, j), k01 = ID(s, i, j + 1),
             k11 = ID(s, i + 1, j + 1);
-        double v = ((lsv(phi, chi, r, k00) + lsv(phi, chi, r, k11)) +
+        real v = ((lsv(phi, chi, r, k00) + lsv(phi, chi, r, k11)) +
                     (lsv(phi, chi, r, k10) + lsv(phi, chi, r, k01))) * 0.25;
         int own = chi[k00];
         if (chi[k10] < own) own = chi[k10];
@@ -488,15 +508,15 @@ static void geometry(St *s, const double *phi, const int *chi) {
         int k = ID(s, i, j);
         int ksw = ID(s, i - 1, j - 1), kse = ID(s, i, j - 1), knw = ID(s, i - 1, j),
             kne = k;
-        double c = lsv(phi, chi, r, k);
+        real c = lsv(phi, chi, r, k);
         int ic = inside(c, chi[k], r);
-        double vsw = s->cv[ksw], vse = s->cv[kse], vnw = s->cv[knw], vne = s->cv[kne];
+        real vsw = s->cv[ksw], vse = s->cv[kse], vnw = s->cv[knw], vne = s->cv[kne];
         int isw = inside(vsw, s->co[ksw], r), ise = inside(vse, s->co[kse], r),
             inw = inside(vnw, s->co[knw], r), ine = inside(vne, s->co[kne], r);
-        double tl = tri_frac(vsw, isw, vnw, inw, c, ic);
-        double tr = tri_frac(vse, ise, vne, ine, c, ic);
-        double tb = tri_frac(vsw, isw, vse, ise, c, ic);
-        double tt = tri_frac(vnw, inw, vne, ine, c, ic);
+        real tl = tri_frac(vsw, isw, vnw, inw, c, ic);
+        real tr = tri_frac(vse, ise, vne, ine, c, ic);
+        real tb = tri_frac(vsw, isw, vse, ise, c, ic);
+        real tt = tri_frac(vnw, inw, vne, ine, c, ic);
         al[k] = ((tl + tr) + (tb + tt)) * 0.25;
         cx[k] = (ax[k] - ax[ID(s, i - 1, j)]) * s->dy;
         cy[k] = (ay[k] - ay[ID(s, i, j - 1)]) * s->dx;
@@ -510,7 +530,7 @@ static void geometry(St *s, const double *phi, const int *chi) {
  * not changed) absorbs 1 - sum(alpha).  Reading: ties go to the smaller
  * index; if the lightest would become negative it is set to 0 and the rest
  * passes to the next lightest.  mass[m][k] is the partial density. */
-static void vf_correction(St *s, const int *chi, const double *mass) {
+static void vf_correction(St *s, const int *chi, const real *mass) {
   int nx = s->c.nx, ny = s->c.ny;
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
@@ -518,9 +538,9 @@ static void vf_correction(St *s, const int *chi, const double *mass) {
       for (int r = 0; r < s->M; r++)
         if (M1(s, s->al, r, k) > 0.0) n++;
       if (n < 3) continue;
-      double sum = 0.0;
+      real sum = 0.0;
       for (int r = 0; r < s->M; r++) sum += M1(s, s->al, r, k);
-      double d = 1.0 - sum;
+      real d = 1.0 - sum;
       int used = 0;
       while (d != 0.0) {
         int best = -1;
@@ -530,7 +550,7 @@ static void vf_correction(St *s, const int *chi, const double *mass) {
         }
         if (best < 0) break;
         used |= 1 << best;
-        double nv = M1(s, s->al, best, k) + d;
+        real nv = M1(s, s->al, best, k) + d;
         if (nv < 0.0) {
           M1(s, s->al, best, k) = 0.0;
           d = nv;
@@ -563,9 +583,9 @@ static void real_states(St *s) {
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       int k = ID(s, i, j), r = s->chi[k];
-      double a = M1(s, s->al, r, k);
+      real a = M1(s, s->al, r, k);
       if (!(a > 0.0)) continue;
-      double U[4], W[4];
+      real U[4], W[4];
       for (int v = 0; v < 4; v++) U[v] = M4(s, s->Q, r, v, k) / a;
       prim(s, r, U, W);
       if (!(W[0] > 0.0) || !(W[3] + s->c.pinf[r] > 0.0) || !isfinite(W[1]) ||
@@ -613,12 +633,12 @@ static void extension(St *s) {
       for (int q = 0; q < n; q++) {
         int k = s->list[q];
         int i = k % s->NX - OR_H, j = k / s->NX - s->HY;
-        double *out = &s->lw[(size_t)q * 4];
+        real *out = &s->lw[(size_t)q * 4];
         s->lok[q] = 0;
         if (v[k]) continue;
         if (upwind) {
-          double gx = lsv(s->phi, s->chi, r, ID(s, i + 1, j)) - lsv(s->phi, s->chi, r, ID(s, i - 1, j));
-          double gy = two ? lsv(s->phi, s->chi, r, ID(s, i, j + 1)) - lsv(s->phi, s->chi, r, ID(s, i, j - 1)) : 0.0;
+          real gx = lsv(s->phi, s->chi, r, ID(s, i + 1, j)) - lsv(s->phi, s->chi, r, ID(s, i - 1, j));
+          real gy = two ? lsv(s->phi, s->chi, r, ID(s, i, j + 1)) - lsv(s->phi, s->chi, r, ID(s, i, j - 1)) : 0.0;
           int kx = -1, ky = -1;
           if (gx != 0.0) {
             int ii = i + (gx > 0.0 ? 1 : -1);
@@ -629,7 +649,7 @@ static void extension(St *s) {
             if (jj >= 0 && jj < ny && v[ID(s, i, jj)]) ky = ID(s, i, jj);
           }
           if (kx >= 0 && ky >= 0) {
-            double wx = fabs(gx), wy = fabs(gy);
+            real wx = fabs(gx), wy = fabs(gy);
             for (int c = 0; c < 4; c++)
               out[c] = (wx * M4(s, s->W, r, c, kx) + wy * M4(s, s->W, r, c, ky)) / (wx + wy);
             s->lok[q] = 1;
@@ -643,10 +663,10 @@ static void extension(St *s) {
         } else {
           /* mean of the valid neighbours, summed in mirror-symmetric pairs:
              rows (-1 + +1) + 0, within a row (-1 + +1) + 0 */
-          double row[3][4];
+          real row[3][4];
           int cnt = 0;
           for (int dj = -1; dj <= 1; dj++) {
-            double a[3][4];
+            real a[3][4];
             for (int di = -1; di <= 1; di++) {
               int ii = i + di, jj = j + dj, ok2 = 0;
               if ((di != 0 || dj != 0) && (two || dj == 0) && ii >= 0 && ii < nx &&
@@ -659,7 +679,7 @@ static void extension(St *s) {
           }
           if (cnt > 0) {
             for (int c = 0; c < 4; c++)
-              out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
+              out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (real)cnt;
             s->lok[q] = 1;
           }
         }
@@ -679,18 +699,18 @@ static void extension(St *s) {
 /* CFL time step (Sec. 2.3, Sec. 3: CFL number 0.6).  Reading: one step size
  * per time step from the time-n state, dt = CFL h / max over real cells of
  * max(|u| + c, |v| + c). */
-static double cfl_dt(St *s) {
+static real cfl_dt(St *s) {
   int nx = s->c.nx, ny = s->c.ny;
-  double smax = 0.0;
+  real smax = 0.0;
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       int k = ID(s, i, j), r = s->chi[k];
       if (!M1(s, s->Wv, r, k)) continue;
-      double rho = M4(s, s->W, r, 0, k), u = M4(s, s->W, r, 1, k),
+      real rho = M4(s, s->W, r, 0, k), u = M4(s, s->W, r, 1, k),
              v = M4(s, s->W, r, 2, k), p = M4(s, s->W, r, 3, k);
-      double c = sqrt(s->c.gamma[r] * (p + s->c.pinf[r]) / rho);
-      double a = fabs(u) + c, b = fabs(v) + c;
-      double w = a > b ? a : b;
+      real c = sqrt(s->c.gamma[r] * (p + s->c.pinf[r]) / rho);
+      real a = fabs(u) + c, b = fabs(v) + c;
+      real w = a > b ? a : b;
       if (w > smax) smax = w;
     }
   return s->c.cfl * s->h / smax;
@@ -714,7 +734,7 @@ static double cfl_dt(St *s) {
  * stage 0 the interface velocity S_M n is kept for the level set. */
 static void interface_exchange(St *s, int stage) {
   int nx = s->c.nx, ny = s->c.ny;
-  memset(s->X, 0, (size_t)s->M * 4 * s->NC * sizeof(double));
+  memset(s->X, 0, (size_t)s->M * 4 * s->NC * sizeof(real));
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       int k = ID(s, i, j);
@@ -734,15 +754,15 @@ static void interface_exchange(St *s, int stage) {
         if (!(b >> r & 1) || r == a) continue;
         if (bb < 0 || M4(s, s->Q, r, 0, k) > M4(s, s->Q, bb, 0, k)) bb = r;
       }
-      double cxa = M1(s, s->cx, a, k), cya = M1(s, s->cy, a, k);
+      real cxa = M1(s, s->cx, a, k), cya = M1(s, s->cy, a, k);
       if (cxa == 0.0 && cya == 0.0) continue;
       if (!M1(s, s->Wv, a, k) || !M1(s, s->Wv, bb, k)) {
         s->n_ifskip++;
         continue;
       }
-      double nrm = sqrt(cxa * cxa + cya * cya);
-      double nxv = cxa / nrm, nyv = cya / nrm;
-      double WL[4], WR[4];
+      real nrm = sqrt(cxa * cxa + cya * cya);
+      real nxv = cxa / nrm, nyv = cya / nrm;
+      real WL[4], WR[4];
       WL[0] = M4(s, s->W, bb, 0, k);
       WL[1] = M4(s, s->W, bb, 1, k) * nxv + M4(s, s->W, bb, 2, k) * nyv;
       WL[2] = 0.0;
@@ -751,11 +771,11 @@ static void interface_exchange(St *s, int stage) {
       WR[1] = M4(s, s->W, a, 1, k) * nxv + M4(s, s->W, a, 2, k) * nyv;
       WR[2] = 0.0;
       WR[3] = M4(s, s->W, a, 3, k);
-      double SL, SR;
+      real SL, SR;
       wave_speeds(WL, s->c.gamma[bb], s->c.pinf[bb], WR, s->c.gamma[a], s->c.pinf[a], &SL, &SR);
-      double SM = contact_speed(WL, WR, SL, SR);
-      double pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
-      double ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
+      real SM = contact_speed(WL, WR, SL, SR);
+      real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
+      real ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
                          (pR + WR[0] * (SR - uR) * (SM - uR)));
       M4(s, s->X, a, 0, k) = 0.0;
       M4(s, s->X, a, 1, k) = ps * cxa;
@@ -779,8 +799,8 @@ static void interface_exchange(St *s, int stage) {
  * a reconstructed density or p + p_inf is not positive, or a stencil cell has
  * no state, the first-order states of the two face cells are used. */
 static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
-                     double *F) {
-  double WL[4], WR[4], Wc[6][4];
+                     real *F) {
+  real WL[4], WR[4], Wc[6][4];
   int ok = 1;
   for (int q = 0; q < 6; q++) {
     if (!M1(s, s->Wv, r, kk[q])) ok = 0;
@@ -811,7 +831,7 @@ static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
       WR[v] = Wc[3][perm[v]];
     }
   }
-  double G[4];
+  real G[4];
   hllc_flux(s, r, WL, WR, G);
   F[0] = G[0];
   F[1 + (normal == 0 ? 0 : 1)] = G[1];
@@ -826,7 +846,7 @@ static void fluxes(St *s) {
     for (int j = 0; j < ny; j++)
       for (int i = -1; i < nx; i++) {
         int k = ID(s, i, j);
-        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        real F[4] = {0.0, 0.0, 0.0, 0.0};
         if (M1(s, s->ax, r, k) > 0.0) {
           int kk[6];
           for (int q = 0; q < 6; q++) kk[q] = ID(s, i - 2 + q, j);
@@ -838,7 +858,7 @@ static void fluxes(St *s) {
     for (int j = -1; j < ny; j++)
       for (int i = 0; i < nx; i++) {
         int k = ID(s, i, j);
-        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        real F[4] = {0.0, 0.0, 0.0, 0.0};
         if (M1(s, s->ay, r, k) > 0.0) {
           int kk[6];
           for (int q = 0; q < 6; q++) kk[q] = ID(s, i, j - 2 + q);
@@ -878,22 +898,22 @@ static void rk_update(St *s, double b, double c, double w) {
     for (int j = 0; j < ny; j++)
       for (int i = 0; i < nx; i++)
         if (M1(s, s->al, r, ID(s, i, j)) > 0.0) s->n_upd++;
-  double lx = s->dt / s->dx, ly = s->dt / s->dy;
-  double lv = s->c.dim == 2 ? s->dt / (s->dx * s->dy) : s->dt / s->dx;
+  real lx = s->dt / s->dx, ly = s->dt / s->dy;
+  real lv = s->c.dim == 2 ? s->dt / (s->dx * s->dy) : s->dt / s->dx;
   for (int r = 0; r < s->M; r++)
     for (int v = 0; v < 4; v++) {
       for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
           int k = ID(s, i, j), kl = ID(s, i - 1, j);
-          double Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, k);
-          double fl = Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0;
-          double fr = Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, k) : 0.0;
-          double rhs = lx * (fl - fr);
+          real Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, k);
+          real fl = Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0;
+          real fr = Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, k) : 0.0;
+          real rhs = lx * (fl - fr);
           if (s->c.dim == 2) {
             int kb = ID(s, i, j - 1);
-            double Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, k);
-            double fb = Ab > 0.0 ? Ab * M4(s, s->Fy, r, v, kb) : 0.0;
-            double ft = At > 0.0 ? At * M4(s, s->Fy, r, v, k) : 0.0;
+            real Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, k);
+            real fb = Ab > 0.0 ? Ab * M4(s, s->Fy, r, v, kb) : 0.0;
+            real ft = At > 0.0 ? At * M4(s, s->Fy, r, v, k) : 0.0;
             rhs = rhs + ly * (fb - ft);
           }
           rhs = rhs + lv * M4(s, s->X, r, v, k);
@@ -901,21 +921,21 @@ static void rk_update(St *s, double b, double c, double w) {
         }
       /* conservation book-keeping: net inflow through the domain boundary and
          exchange totals, weighted by the stage's share of the full step */
-      double in = 0.0;
+      real in = 0.0;
       for (int j = 0; j < ny; j++) {
         int kl = ID(s, -1, j), kr = ID(s, nx - 1, j);
-        double Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, kr);
+        real Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, kr);
         in += lx * ((Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0) -
                     (Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, kr) : 0.0));
       }
       if (s->c.dim == 2)
         for (int i = 0; i < nx; i++) {
           int kb = ID(s, i, -1), kt = ID(s, i, ny - 1);
-          double Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, kt);
+          real Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, kt);
           in += ly * ((Ab > 0.0 ? Ab * M4(s, s->Fy, r, v, kb) : 0.0) -
                       (At > 0.0 ? At * M4(s, s->Fy, r, v, kt) : 0.0));
         }
-      double xsum = 0.0;
+      real xsum = 0.0;
       for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) xsum += lv * M4(s, s->X, r, v, ID(s, i, j));
       neumaier(&s->bnd[r][v], &s->bnd_c[r][v], w * in);
@@ -944,8 +964,8 @@ static void ls_velocity(St *s) {
       int i = k % s->NX - OR_H, j = k / s->NX - s->HY;
       s->lok[q] = 0;
       if (s->vok[k]) continue;
-      double gx = s->phi[ID(s, i + 1, j)] - s->phi[ID(s, i - 1, j)];
-      double gy = two ? s->phi[ID(s, i, j + 1)] - s->phi[ID(s, i, j - 1)] : 0.0;
+      real gx = s->phi[ID(s, i + 1, j)] - s->phi[ID(s, i - 1, j)];
+      real gy = two ? s->phi[ID(s, i, j + 1)] - s->phi[ID(s, i, j - 1)] : 0.0;
       int kx = -1, ky = -1;
       if (gx != 0.0) {
         int ii = i - (gx > 0.0 ? 1 : -1);
@@ -955,9 +975,9 @@ static void ls_velocity(St *s) {
         int jj = j - (gy > 0.0 ? 1 : -1);
         if (jj >= 0 && jj < ny && s->vok[ID(s, i, jj)]) ky = ID(s, i, jj);
       }
-      double *o = &s->lv[(size_t)q * 2];
+      real *o = &s->lv[(size_t)q * 2];
       if (kx >= 0 && ky >= 0) {
-        double wx = fabs(gx), wy = fabs(gy);
+        real wx = fabs(gx), wy = fabs(gy);
         o[0] = (wx * s->vx[kx] + wy * s->vx[ky]) / (wx + wy);
         o[1] = (wx * s->vy[kx] + wy * s->vy[ky]) / (wx + wy);
         s->lok[q] = 1;
@@ -1029,8 +1049,8 @@ static void ls_region(St *s) {
  * reconstruct phi = |max_r phi^r|, chi = argmax_r phi^r (ties: smaller
  * index).  Reading: phi is clamped to the band width; cells outside the
  * region keep their values; no reinitialisation is applied. */
-static double hj_deriv(St *s, int r, int i, int j, int dir, double vel) {
-  double d[7]; /* divided differences d(q) = (phi_q - phi_{q-1})/h, q = i-2 .. i+3 */
+static real hj_deriv(St *s, int r, int i, int j, int dir, real vel) {
+  real d[7]; /* divided differences d(q) = (phi_q - phi_{q-1})/h, q = i-2 .. i+3 */
   double ih = dir == 0 ? s->idx : s->idy;
   for (int q = 0; q < 6; q++) {
     int o = q - 2;
@@ -1053,24 +1073,24 @@ static void levelset_stage(St *s, double b, double c) {
         s->chit[k] = s->chi[k];
         continue;
       }
-      double best = 0.0;
+      real best = 0.0;
       int br = -1;
       for (int r = 0; r < s->M; r++) {
         if (!(s->xs[k] >> r & 1)) continue;
-        double gx = hj_deriv(s, r, i, j, 0, s->vx[k]);
-        double adv = s->vx[k] * gx;
+        real gx = hj_deriv(s, r, i, j, 0, s->vx[k]);
+        real adv = s->vx[k] * gx;
         if (s->c.dim == 2) {
-          double gy = hj_deriv(s, r, i, j, 1, s->vy[k]);
+          real gy = hj_deriv(s, r, i, j, 1, s->vy[k]);
           adv = adv + s->vy[k] * gy;
         }
-        double val = lsv(s->phi, s->chi, r, k) - s->dt * adv;
-        double nv = b * lsv(s->phin, s->chin, r, k) + c * val;
+        real val = lsv(s->phi, s->chi, r, k) - s->dt * adv;
+        real nv = b * lsv(s->phin, s->chin, r, k) + c * val;
         if (br < 0 || nv > best) {
           best = nv;
           br = r;
         }
       }
-      double a = fabs(best);
+      real a = fabs(best);
       s->phit[k] = a < s->bls ? a : s->bls;
       s->chit[k] = br;
     }
@@ -1102,12 +1122,12 @@ static void mixing(St *s) {
   size_t nc = s->NC;
   for (int r = 0; r < s->M; r++) {
     int *T = s->mixT;
-    double *Mx = s->mixM;
+    real *Mx = s->mixM;
     for (size_t q = 0; q < 3 * nc; q++) T[q] = -1;
     for (int j = 0; j < ny; j++)
       for (int i = 0; i < nx; i++) {
         int k = ID(s, i, j);
-        double as = M1(s, s->al, r, k);
+        real as = M1(s, s->al, r, k);
         if (!(as < amix) && s->chit[k] == r) continue;
         if (!(as > 0.0)) {
           int nz = 0;
@@ -1116,36 +1136,36 @@ static void mixing(St *s) {
           if (!nz) continue;
         }
         s->n_mixsrc++;
-        double gx = lsv(s->phit, s->chit, r, ID(s, i + 1, j)) - lsv(s->phit, s->chit, r, ID(s, i - 1, j));
-        double gy = two ? lsv(s->phit, s->chit, r, ID(s, i, j + 1)) - lsv(s->phit, s->chit, r, ID(s, i, j - 1)) : 0.0;
+        real gx = lsv(s->phit, s->chit, r, ID(s, i + 1, j)) - lsv(s->phit, s->chit, r, ID(s, i - 1, j));
+        real gy = two ? lsv(s->phit, s->chit, r, ID(s, i, j + 1)) - lsv(s->phit, s->chit, r, ID(s, i, j - 1)) : 0.0;
         int sx = gx > 0.0 ? 1 : (gx < 0.0 ? -1 : 0);
         int sy = gy > 0.0 ? 1 : (gy < 0.0 ? -1 : 0);
         int tk[3] = {-1, -1, -1};
-        double w[3] = {0.0, 0.0, 0.0};
+        real w[3] = {0.0, 0.0, 0.0};
         if (sx != 0 && i + sx >= 0 && i + sx < nx) {
           int t = ID(s, i + sx, j);
-          double at = M1(s, s->al, r, t);
+          real at = M1(s, s->al, r, t);
           if (at >= amix && s->chit[t] == r) { tk[0] = t; w[0] = gx * gx * at; }
         }
         if (sy != 0 && j + sy >= 0 && j + sy < ny) {
           int t = ID(s, i, j + sy);
-          double at = M1(s, s->al, r, t);
+          real at = M1(s, s->al, r, t);
           if (at >= amix && s->chit[t] == r) { tk[1] = t; w[1] = gy * gy * at; }
         }
         if (sx != 0 && sy != 0 && i + sx >= 0 && i + sx < nx && j + sy >= 0 && j + sy < ny) {
           int t = ID(s, i + sx, j + sy);
-          double at = M1(s, s->al, r, t);
+          real at = M1(s, s->al, r, t);
           if (at >= amix && s->chit[t] == r) { tk[2] = t; w[2] = fabs(gx * gy) * at; }
         }
-        double wsum = (w[0] + w[1]) + w[2];
-        double beta[3] = {0.0, 0.0, 0.0};
+        real wsum = (w[0] + w[1]) + w[2];
+        real beta[3] = {0.0, 0.0, 0.0};
         if (wsum > 0.0) {
           for (int q = 0; q < 3; q++)
             if (w[q] > 0.0) beta[q] = w[q] / wsum;
             else tk[q] = -1;
         } else {
           tk[0] = tk[1] = tk[2] = -1;
-          double bestA = -1.0;
+          real bestA = -1.0;
           int bt = -1;
           for (int dj = -two; dj <= two; dj++)
             for (int di = -1; di <= 1; di++) {
@@ -1153,7 +1173,7 @@ static void mixing(St *s) {
               int ii = i + di, jj = j + dj;
               if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
               int t = ID(s, ii, jj);
-              double at = M1(s, s->al, r, t);
+              real at = M1(s, s->al, r, t);
               if (at >= amix && s->chit[t] == r && at > bestA) { bestA = at; bt = t; }
             }
           if (bt < 0) {
@@ -1171,9 +1191,9 @@ static void mixing(St *s) {
         if (as > 0.0) {
           for (int q = 0; q < 3; q++) {
             if (tk[q] < 0) continue;
-            double at = M1(s, s->al, r, tk[q]);
+            real at = M1(s, s->al, r, tk[q]);
             for (int v = 0; v < 4; v++) {
-              double Qs = M4(s, s->Qt, r, v, k), Qtg = M4(s, s->Qt, r, v, tk[q]);
+              real Qs = M4(s, s->Qt, r, v, k), Qtg = M4(s, s->Qt, r, v, tk[q]);
               Mx[((size_t)q * 4 + v) * nc + k] = beta[q] * ((as * Qtg - at * Qs) / (as + at));
             }
           }
@@ -1181,10 +1201,10 @@ static void mixing(St *s) {
           /* vanishing cell: with alpha_s = 0 the exchange is M_t = -beta_t Q_s;
              the last target takes the exact remainder so the source ends at 0 */
           for (int v = 0; v < 4; v++) {
-            double Qs = M4(s, s->Qt, r, v, k), acc = Qs;
+            real Qs = M4(s, s->Qt, r, v, k), acc = Qs;
             for (int q = 0; q < 3; q++) {
               if (tk[q] < 0) continue;
-              double m = q == last ? -acc : -(beta[q] * Qs);
+              real m = q == last ? -acc : -(beta[q] * Qs);
               Mx[((size_t)q * 4 + v) * nc + k] = m;
               acc = acc + m;
             }
@@ -1197,7 +1217,7 @@ static void mixing(St *s) {
       for (int i = 0; i < nx; i++) {
         int k = ID(s, i, j);
         for (int v = 0; v < 4; v++) {
-          double q0 = M4(s, s->Qt, r, v, k);
+          real q0 = M4(s, s->Qt, r, v, k);
           int src = 0;
           for (int q = 0; q < 3; q++)
             if (T[(size_t)q * nc + k] >= 0) {
@@ -1206,9 +1226,9 @@ static void mixing(St *s) {
             }
           if (!src) {
             /* received exchanges, summed in mirror-symmetric pairs */
-            double row[3];
+            real row[3];
             for (int dj = -1; dj <= 1; dj++) {
-              double a[3] = {0.0, 0.0, 0.0};
+              real a[3] = {0.0, 0.0, 0.0};
               for (int di = -1; di <= 1; di++) {
                 int ii = i + di, jj = j + dj;
                 if ((di == 0 && dj == 0) || (!two && dj != 0) || ii < 0 || ii >= nx ||
@@ -1230,6 +1250,9 @@ static void mixing(St *s) {
 /* ------------------------------------------------------------------------ */
 /* Public C API used by the tests through ctypes                            */
 /* ------------------------------------------------------------------------ */
+#ifdef __cplusplus
+extern "C" {
+#endif
 static void *zalloc(size_t n) { return calloc(n ? n : 1, 1); }
 
 void or_destroy(St *s) {
@@ -1260,22 +1283,29 @@ St *or_create(const or_config *c) {
   s->idx = 1.0 / s->dx;
   s->idy = 1.0 / s->dy;
   for (int m = 0; m < s->M; m++) s->igm1[m] = 1.0 / (c->gamma[m] - 1.0);
-  size_t nc = s->NC, M = s->M;
-  s->phi = zalloc(nc * 8); s->phin = zalloc(nc * 8); s->phit = zalloc(nc * 8);
-  s->chi = zalloc(nc * 4); s->chin = zalloc(nc * 4); s->chit = zalloc(nc * 4);
-  s->Q = zalloc(M * 4 * nc * 8); s->Qn = zalloc(M * 4 * nc * 8); s->Qt = zalloc(M * 4 * nc * 8);
-  s->al = zalloc(M * nc * 8); s->ax = zalloc(M * nc * 8); s->ay = zalloc(M * nc * 8);
-  s->cx = zalloc(M * nc * 8); s->cy = zalloc(M * nc * 8);
-  s->W = zalloc(M * 4 * nc * 8); s->lw = zalloc(4 * nc * 8);
-  s->Wv = zalloc(M * nc); s->lok = zalloc(nc); s->band = zalloc(nc);
-  s->band2 = zalloc(nc); s->list = zalloc(nc * 4);
-  s->X = zalloc(M * 4 * nc * 8);
-  s->vx = zalloc(nc * 8); s->vy = zalloc(nc * 8);
-  s->vok = zalloc(nc); s->reg = zalloc(nc); s->lv = zalloc(2 * nc * 8);
-  s->Fx = zalloc(M * 4 * nc * 8); s->Fy = zalloc(M * 4 * nc * 8);
-  s->mass = zalloc(M * nc * 8);
-  s->cv = zalloc(nc * 8); s->co = zalloc(nc * 4); s->xs = zalloc(nc);
-  s->mixM = zalloc(3 * 4 * nc * 8); s->mixT = zalloc(3 * nc * 4);
+  size_t nc = s->NC, M = s->M, R = sizeof(real);
+  s->phi = (real *)zalloc(nc * R); s->phin = (real *)zalloc(nc * R);
+  s->phit = (real *)zalloc(nc * R);
+  s->chi = (int *)zalloc(nc * 4); s->chin = (int *)zalloc(nc * 4); s->chit = (int *)zalloc(nc * 4);
+  s->Q = (real *)zalloc(M * 4 * nc * R); s->Qn = (real *)zalloc(M * 4 * nc * R);
+  s->Qt = (real *)zalloc(M * 4 * nc * R);
+  s->al = (real *)zalloc(M * nc * R); s->ax = (real *)zalloc(M * nc * R);
+  s->ay = (real *)zalloc(M * nc * R);
+  s->cx = (real *)zalloc(M * nc * R); s->cy = (real *)zalloc(M * nc * R);
+  s->W = (real *)zalloc(M * 4 * nc * R); s->lw = (real *)zalloc(4 * nc * R);
+  s->Wv = (unsigned char *)zalloc(M * nc); s->lok = (unsigned char *)zalloc(nc);
+  s->band = (unsigned char *)zalloc(nc);
+  s->band2 = (unsigned char *)zalloc(nc); s->list = (int *)zalloc(nc * 4);
+  s->X = (real *)zalloc(M * 4 * nc * R);
+  s->vx = (real *)zalloc(nc * R); s->vy = (real *)zalloc(nc * R);
+  s->vok = (unsigned char *)zalloc(nc); s->reg = (unsigned char *)zalloc(nc);
+  s->lv = (real *)zalloc(2 * nc * R);
+  s->Fx = (real *)zalloc(M * 4 * nc * R); s->Fy = (real *)zalloc(M * 4 * nc * R);
+  s->mass = (real *)zalloc(M * nc * R);
+  s->cv = (real *)zalloc(nc * R); s->co = (int *)zalloc(nc * 4);
+  s->xs = (unsigned char *)zalloc(nc);
+  s->mixM = (real *)zalloc(3 * 4 * nc * R); s->mixT = (int *)zalloc(3 * nc * 4);
+  for (int v = 0; v < 4; v++) s->inflow[v] = c->inflow_W[v];
   if (!s->mixT || !s->mixM || !s->Q) {
     or_destroy(s);
     return NULL;
@@ -1287,7 +1317,18 @@ St *or_create(const or_config *c) {
  * (rho, u, [v], p) of each material, used wherever that material has a
  * volume fraction.  Q^0 = alpha^0 U(W), with alpha^0 corrected by the
  * masses alpha * rho. */
-int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
+/* Input field W (and, in the tangent build, its derivative dW, nullable). */
+static real w_in(const double *W, const double *dW, size_t at) {
+#ifdef OR_TANGENT
+  return or_dual(W[at], dW ? dW[at] : 0.0);
+#else
+  (void)dW;
+  return W[at];
+#endif
+}
+
+static int init_impl(St *s, const double *phi, const int32_t *chi, const double *W,
+                     const double *dW) {
   int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
   size_t plane = (size_t)nx * ny;
   for (int j = 0; j < ny; j++)
@@ -1304,7 +1345,7 @@ int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
       for (int i = 0; i < nx; i++) {
         size_t q = (size_t)j * nx + i;
         M1(s, s->mass, r, ID(s, i, j)) =
-            M1(s, s->al, r, ID(s, i, j)) * W[((size_t)r * nv + 0) * plane + q];
+            M1(s, s->al, r, ID(s, i, j)) * w_in(W, dW, ((size_t)r * nv + 0) * plane + q);
       }
   vf_correction(s, s->chi, s->mass);
   s->err_code = OR_OK;
@@ -1313,16 +1354,16 @@ int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
       for (int i = 0; i < nx; i++) {
         size_t q = (size_t)j * nx + i;
         int k = ID(s, i, j);
-        double a = M1(s, s->al, r, k);
-        double w[4];
-        w[0] = W[((size_t)r * nv + 0) * plane + q];
-        w[1] = W[((size_t)r * nv + 1) * plane + q];
-        w[2] = nv == 4 ? W[((size_t)r * nv + 2) * plane + q] : 0.0;
-        w[3] = W[((size_t)r * nv + nv - 1) * plane + q];
+        real a = M1(s, s->al, r, k);
+        real w[4];
+        w[0] = w_in(W, dW, ((size_t)r * nv + 0) * plane + q);
+        w[1] = w_in(W, dW, ((size_t)r * nv + 1) * plane + q);
+        w[2] = nv == 4 ? w_in(W, dW, ((size_t)r * nv + 2) * plane + q) : (real)0.0;
+        w[3] = w_in(W, dW, ((size_t)r * nv + nv - 1) * plane + q);
         if (a > 0.0 && (!(w[0] > 0.0) || !(w[3] + s->c.pinf[r] > 0.0) ||
                         !isfinite(w[1]) || !isfinite(w[2])))
           record_err(s, OR_ENONPHYS, i, j);
-        double U[4];
+        real U[4];
         U[0] = w[0];
         U[1] = w[0] * w[1];
         U[2] = w[0] * w[2];
@@ -1338,6 +1379,45 @@ int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
   return s->err_code;
 }
 
+int or_init(St *s, const double *phi, const int32_t *chi, const double *W) {
+  return init_impl(s, phi, chi, W, NULL);
+}
+
+/* Geometry and correction of the current level set, as after a step
+ * (masses: the partial densities of the current state). */
+static void state_geometry(St *s) {
+  fill_ls(s, s->phi, s->chi);
+  geometry(s, s->phi, s->chi);
+  for (int r = 0; r < s->M; r++)
+    for (size_t k = 0; k < (size_t)s->NC; k++) M1(s, s->mass, r, k) = M4(s, s->Q, r, 0, k);
+  vf_correction(s, s->chi, s->mass);
+}
+
+/* Replace the state: Q [n_mat][dim+2][ny][nx] (alpha U), phi >= 0 and chi
+ * [ny][nx]; the geometry is rebuilt.  Derivative parts (tangent build) are
+ * cleared. */
+int or_set_state(St *s, const double *Q, const double *phi, const int32_t *chi) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  for (size_t q = 0; q < plane; q++)
+    if (chi[q] < 0 || chi[q] >= s->M || !(phi[q] >= 0.0)) return OR_EINVAL;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      int k = ID(s, i, j);
+      for (int r = 0; r < s->M; r++) {
+        M4(s, s->Q, r, 0, k) = Q[((size_t)r * nv + 0) * plane + q];
+        M4(s, s->Q, r, 1, k) = Q[((size_t)r * nv + 1) * plane + q];
+        M4(s, s->Q, r, 2, k) = nv == 4 ? Q[((size_t)r * nv + 2) * plane + q] : 0.0;
+        M4(s, s->Q, r, 3, k) = Q[((size_t)r * nv + nv - 1) * plane + q];
+      }
+      s->phi[k] = phi[q];
+      s->chi[k] = chi[q];
+    }
+  state_geometry(s);
+  return OR_OK;
+}
+
 /* Replay a fixed step size instead of the CFL one (0 = CFL). */
 void or_set_dt(St *s, double dt) { s->dt_fixed = dt; }
 
@@ -1348,17 +1428,19 @@ void or_set_dt(St *s, double dt) { s->dt_fixed = dt; }
 int or_step(St *s, int nsteps) {
   double b[3], c[3], w[3];
   int ns = rk_stages(s, b, c, w);
-  size_t qb = (size_t)s->M * 4 * s->NC * sizeof(double);
+  size_t qb = (size_t)s->M * 4 * s->NC * sizeof(real);
   for (int n = 0; n < nsteps; n++) {
     memcpy(s->Qn, s->Q, qb);
-    memcpy(s->phin, s->phi, s->NC * sizeof(double));
+    memcpy(s->phin, s->phi, s->NC * sizeof(real));
     memcpy(s->chin, s->chi, s->NC * sizeof(int));
     for (int st = 0; st < ns; st++) {
       s->err_code = OR_OK;
       local_sets(s, s->chi, s->xs);
       real_states(s);
       if (s->err_code) return s->err_code;
-      if (st == 0) s->dt = s->dt_fixed > 0.0 ? s->dt_fixed : cfl_dt(s);
+      /* the step size is a function of the state, but it is held fixed
+         under differentiation (the derivative is taken at frozen dt) */
+      if (st == 0) s->dt = s->dt_fixed > 0.0 ? (real)s->dt_fixed : CONST_R(cfl_dt(s));
       extension(s);
       fill_W(s);
       interface_exchange(s, st);
@@ -1374,10 +1456,10 @@ int or_step(St *s, int nsteps) {
           M1(s, s->mass, r, k) = M4(s, s->Qt, r, 0, k);
       vf_correction(s, s->chit, s->mass);
       mixing(s);
-      double *tp = s->phi; s->phi = s->phit; s->phit = tp;
+      real *tp = s->phi; s->phi = s->phit; s->phit = tp;
       int *tc = s->chi; s->chi = s->chit; s->chit = tc;
     }
-    s->t += s->dt;
+    s->t += RV(s->dt);
     s->nstep++;
   }
   return OR_OK;
@@ -1394,14 +1476,14 @@ int or_get(const St *s, double *Q, double *alpha, double *phi, int32_t *chi) {
       int k = ID(s, i, j);
       for (int r = 0; r < s->M; r++) {
         if (Q) {
-          Q[((size_t)r * nv + 0) * plane + q] = M4(s, s->Q, r, 0, k);
-          Q[((size_t)r * nv + 1) * plane + q] = M4(s, s->Q, r, 1, k);
-          if (nv == 4) Q[((size_t)r * nv + 2) * plane + q] = M4(s, s->Q, r, 2, k);
-          Q[((size_t)r * nv + nv - 1) * plane + q] = M4(s, s->Q, r, 3, k);
+          Q[((size_t)r * nv + 0) * plane + q] = RV(M4(s, s->Q, r, 0, k));
+          Q[((size_t)r * nv + 1) * plane + q] = RV(M4(s, s->Q, r, 1, k));
+          if (nv == 4) Q[((size_t)r * nv + 2) * plane + q] = RV(M4(s, s->Q, r, 2, k));
+          Q[((size_t)r * nv + nv - 1) * plane + q] = RV(M4(s, s->Q, r, 3, k));
         }
-        if (alpha) alpha[(size_t)r * plane + q] = M1(s, s->al, r, k);
+        if (alpha) alpha[(size_t)r * plane + q] = RV(M1(s, s->al, r, k));
       }
-      if (phi) phi[q] = s->phi[k];
+      if (phi) phi[q] = RV(s->phi[k]);
       if (chi) chi[q] = s->chi[k];
     }
   return OR_OK;
@@ -1414,11 +1496,11 @@ int or_get_apertures(const St *s, double *Ax, double *Ay) {
   for (int r = 0; r < s->M; r++) {
     for (int j = 0; j < ny; j++)
       for (int i = 0; i <= nx; i++)
-        Ax[((size_t)r * ny + j) * (nx + 1) + i] = M1(s, s->ax, r, ID(s, i - 1, j));
+        Ax[((size_t)r * ny + j) * (nx + 1) + i] = RV(M1(s, s->ax, r, ID(s, i - 1, j)));
     if (Ay && s->c.dim == 2)
       for (int j = 0; j <= ny; j++)
         for (int i = 0; i < nx; i++)
-          Ay[((size_t)r * (ny + 1) + j) * nx + i] = M1(s, s->ay, r, ID(s, i, j - 1));
+          Ay[((size_t)r * (ny + 1) + j) * nx + i] = RV(M1(s, s->ay, r, ID(s, i, j - 1)));
   }
   return OR_OK;
 }
@@ -1429,7 +1511,7 @@ int or_get_apertures(const St *s, double *Ax, double *Ay) {
  * xsum[n_mat][4] (exchange totals), both as increments of sum(Q). */
 int or_diag(const St *s, double *out) {
   out[0] = s->t;
-  out[1] = s->dt;
+  out[1] = RV(s->dt);
   out[2] = (double)s->nstep;
   out[3] = (double)s->n_posfix;
   out[4] = (double)s->n_fluxskip;
@@ -1439,8 +1521,8 @@ int or_diag(const St *s, double *out) {
   out[8] = (double)s->n_upd;
   for (int r = 0; r < s->M; r++)
     for (int v = 0; v < 4; v++) {
-      out[9 + r * 4 + v] = s->bnd[r][v] + s->bnd_c[r][v];
-      out[9 + s->M * 4 + r * 4 + v] = s->xsum[r][v] + s->xsum_c[r][v];
+      out[9 + r * 4 + v] = RV(s->bnd[r][v] + s->bnd_c[r][v]);
+      out[9 + s->M * 4 + r * 4 + v] = RV(s->xsum[r][v] + s->xsum_c[r][v]);
     }
   return OR_OK;
 }
@@ -1451,26 +1533,37 @@ long or_err_cell(const St *s) { return s->err_cell; }
 /* Unit entry points for the oracle's own pins                              */
 /* ------------------------------------------------------------------------ */
 double or_t_weno5(double v1, double v2, double v3, double v4, double v5) {
-  return weno5(v1, v2, v3, v4, v5);
+  return RV(weno5(v1, v2, v3, v4, v5));
 }
 
 /* HLLC face flux of material m between primitive states (rho, un, ut, p). */
 void or_t_hllc(const St *s, int m, const double *WL, const double *WR, double *F) {
-  hllc_flux(s, m, WL, WR, F);
+  real L[4], R[4], G[4];
+  for (int v = 0; v < 4; v++) {
+    L[v] = WL[v];
+    R[v] = WR[v];
+  }
+  hllc_flux(s, m, L, R, G);
+  for (int v = 0; v < 4; v++) F[v] = RV(G[v]);
 }
 
 /* Interface Riemann problem between material mL (left state) and mR (right
  * state), states (rho, un, ut, p); out = (S_L, S_R, S_M, p*). */
-void or_t_iface(const St *s, int mL, const double *WL, int mR, const double *WR,
+void or_t_iface(const St *s, int mL, const double *WLd, int mR, const double *WRd,
                 double *out) {
-  double SL, SR;
+  real WL[4], WR[4];
+  for (int v = 0; v < 4; v++) {
+    WL[v] = WLd[v];
+    WR[v] = WRd[v];
+  }
+  real SL, SR;
   wave_speeds(WL, s->c.gamma[mL], s->c.pinf[mL], WR, s->c.gamma[mR], s->c.pinf[mR], &SL, &SR);
-  double SM = contact_speed(WL, WR, SL, SR);
-  double pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
-  out[0] = SL;
-  out[1] = SR;
-  out[2] = SM;
-  out[3] = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) + (pR + WR[0] * (SR - uR) * (SM - uR)));
+  real SM = contact_speed(WL, WR, SL, SR);
+  real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
+  out[0] = RV(SL);
+  out[1] = RV(SR);
+  out[2] = RV(SM);
+  out[3] = RV(0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) + (pR + WR[0] * (SR - uR) * (SM - uR))));
 }
 
 /* Interface closure vectors of the current geometry, [n_mat][ny][nx] each. */
@@ -1480,8 +1573,73 @@ int or_get_closure(const St *s, double *cx, double *cy) {
     for (int j = 0; j < ny; j++)
       for (int i = 0; i < nx; i++) {
         size_t q = ((size_t)r * ny + j) * nx + i;
-        cx[q] = M1(s, s->cx, r, ID(s, i, j));
-        cy[q] = M1(s, s->cy, r, ID(s, i, j));
+        cx[q] = RV(M1(s, s->cx, r, ID(s, i, j)));
+        cy[q] = RV(M1(s, s->cy, r, ID(s, i, j)));
       }
   return OR_OK;
 }
+
+#ifdef OR_TANGENT
+/* ------------------------------------------------------------------------ */
+/* Tangent build only: directional derivatives of the discrete step         */
+/* ------------------------------------------------------------------------ */
+/* Initial state with the derivative dW of the input field W (same layout);
+ * the level set carries no derivative. */
+int or_init_tangent(St *s, const double *phi, const int32_t *chi, const double *W,
+                    const double *dW) {
+  return init_impl(s, phi, chi, W, dW);
+}
+
+/* Derivative of the primitive state on inflow sides (held for every step). */
+void or_set_inflow_tangent(St *s, const double *d) {
+  for (int v = 0; v < 4; v++) s->inflow[v] = or_dual(RV(s->inflow[v]), d[v]);
+}
+
+/* Replace the derivative part of the current state: dQ [n_mat][dim+2][ny][nx]
+ * and dphi [ny][nx]; the geometry is rebuilt as by or_set_state. */
+void or_seed_state(St *s, const double *dQ, const double *dphi) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      int k = ID(s, i, j);
+      for (int r = 0; r < s->M; r++) {
+        int src[4] = {0, 1, nv == 4 ? 2 : -1, nv - 1};
+        for (int v = 0; v < 4; v++) {
+          real *x = &M4(s, s->Q, r, v, k);
+          *x = or_dual(RV(*x), src[v] < 0 ? 0.0 : dQ[((size_t)r * nv + src[v]) * plane + q]);
+        }
+      }
+      s->phi[k] = or_dual(RV(s->phi[k]), dphi[q]);
+    }
+  /* the geometry of the current level set is an input of the next step */
+  state_geometry(s);
+}
+
+/* Derivative parts of the state: dQ, dalpha (nullable), dphi (nullable). */
+int or_get_tangent(const St *s, double *dQ, double *dalpha, double *dphi) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      int k = ID(s, i, j);
+      for (int r = 0; r < s->M; r++) {
+        if (dQ) {
+          dQ[((size_t)r * nv + 0) * plane + q] = M4(s, s->Q, r, 0, k).d;
+          dQ[((size_t)r * nv + 1) * plane + q] = M4(s, s->Q, r, 1, k).d;
+          if (nv == 4) dQ[((size_t)r * nv + 2) * plane + q] = M4(s, s->Q, r, 2, k).d;
+          dQ[((size_t)r * nv + nv - 1) * plane + q] = M4(s, s->Q, r, 3, k).d;
+        }
+        if (dalpha) dalpha[(size_t)r * plane + q] = M1(s, s->al, r, k).d;
+      }
+      if (dphi) dphi[q] = s->phi[k].d;
+    }
+  return OR_OK;
+}
+#endif
+
+#ifdef __cplusplus
+}
+#endif
