@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -87,6 +89,42 @@ def batched(pk, wl, stream, steps, ref_inst=8, ref_steps=30):
                 speedup=rate / per_rate)
 
 
+def adjoint_leg(pk, wl, stream, steps=300, K=30):
+    """Differentiation form on the 512 x 128 nested shock-bubble: gradient of
+    the bubble's centroid x-position after `steps` steps with respect to
+    (shell density, core density, shock Mach number) through the library's
+    reverse steps, checkpoint every K steps.  Cost = wall time of (forward
+    with tape + all reverse steps) over that of the plain forward run."""
+    import torch
+    from paper_1704_00519_amd import adjoint as ad
+    prob = ad.NestedBubble(wl.shock_bubble(nx=512, ny=128))
+    params = np.array([0.138, 3.15, 1.22])
+    s = prob.solver(params, stream=stream.cuda_stream)
+    s.step(2)  # graph capture and first-touch outside the timing
+    s = prob.solver(params, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s = prob.solver(params, stream=stream.cuda_stream)
+    alpha0 = s.get()["alpha"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, record=K)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    g = ad.reverse_gradient(prob, s, alpha0, steps, params)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    J, _ = ad.centroid(s.get()["alpha"], prob.x)
+    return dict(workload="nested_shock_bubble_512x128", steps=steps, checkpoint_every=K,
+                forward_s=round(t_fwd, 4), forward_with_tape_s=round(t_rec, 4),
+                forward_and_reverse_s=round(t_all, 4), ratio=t_all / t_fwd,
+                J=J, gradient=[float(x) for x in g],
+                parameters=["rho_shell", "rho_core", "mach"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +134,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -159,6 +198,8 @@ def main():
                roofline=roofline)
     if not args.no_batch:
         out["batched"] = batched(pk, wl, stream, args.batch_steps)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(pk, wl, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out))

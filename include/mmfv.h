@@ -81,6 +81,17 @@ typedef struct {
   int64_t n_updates;       /* active material-cell RK-substep updates       */
   int64_t err_cell;        /* j*nx+i of the lowest non-physical real cell   */
                            /* found, -1 if none                             */
+  /* Conservation book-keeping (Eq. discretized_equ, Sec. 2.3.2: a material's
+   * total changes only through the domain boundary and its exchange term),
+   * per material and component (rho, rho u, rho v, rho E; rho v = 0 in 1D):
+   * sum_Q is the sum of Q over the cells now; bnd_in the net inflow through
+   * the domain boundary and exch the exchange total, both accumulated since
+   * mm_init_state with each stage weighted by its share of the step, so that
+   * sum_Q(now) - sum_Q(init) = bnd_in + exch up to rounding.  Partial sums
+   * are combined in a fixed order: repeated runs give identical values. */
+  double sum_Q[MM_MAX_MAT][4];
+  double bnd_in[MM_MAX_MAT][4];
+  double exch[MM_MAX_MAT][4];
 } mm_diag;
 
 typedef struct mm_ctx mm_ctx;
@@ -102,10 +113,13 @@ mm_status mm_init_state(mm_ctx *ctx, const double *phi, const int32_t *chi,
 
 /* Advance n_steps time steps (one step = all Runge-Kutta stages, with the
  * step size from the CFL condition of the time-n state, or the value set by
- * mm_set_dt).  record_tape must be 0 (no adjoint tape is kept).  If t_out is
- * not NULL it receives the time reached.  Synchronises the stream and
- * returns MM_ENONPHYS if a non-physical real state appeared (the state is
- * then undefined; err_cell in the diagnostics names the cell). */
+ * mm_set_dt).  record_tape = K > 0 keeps a tape for mm_adjoint_step: a
+ * checkpoint of the state every K steps and the step size of every step
+ * (a new tape starts unless the previous call recorded with the same K and
+ * no step has been reversed since); record_tape = 0 ends any tape.  If t_out
+ * is not NULL it receives the time reached.  Synchronises the stream once
+ * and returns MM_ENONPHYS if a non-physical real state appeared (the state
+ * is then undefined; err_cell in the diagnostics names the cell). */
 mm_status mm_step(mm_ctx *ctx, int32_t n_steps, int32_t record_tape,
                   double *t_out);
 
@@ -120,11 +134,35 @@ mm_status mm_get_diagnostics(mm_ctx *ctx, mm_diag *out);
 /* Replay a fixed step size instead of the CFL one; dt <= 0 restores CFL. */
 mm_status mm_set_dt(mm_ctx *ctx, double dt);
 
-/* Adjoint of one time step (reverse of the step above).  Declared for the
- * differentiation form of the method; returns MM_ENOTIMPL in this build. */
+/* Differentiation (Sec. 2.3, Eq. discretized_equ, Eq. local-advection; the
+ * method's step, transposed).  Reverses the last recorded step that has not
+ * been reversed yet: given the adjoint of the state after it (dJ/dQ
+ * [n_mat][dim+2][ny][nx], dJ/dphi [ny][nx], and dJ/dalpha [n_mat][ny][nx]
+ * of its volume fractions), produce the adjoint of the state before it.
+ * The step is linearised about the recorded trajectory with its step size
+ * held fixed and every branch (upwind choices, HLLC wave pattern, ghost
+ * sources, interface pairs, mixing sources and targets, level-set argmax,
+ * volume-fraction correction) as the forward step took it.  A NULL lamQ_in
+ * or lamPhi_in continues from the adjoint left by the previous call (zero
+ * on the first); lamAlpha_in may be NULL.  lamQ_out / lamPhi_out may be
+ * NULL.  The segment of the tape that holds the step is recomputed from
+ * its checkpoint when first needed.  The forward state after the recorded
+ * run and the diagnostics are left as they were.  Pointers are host or
+ * device per ptr_kind.  MM_ESTATE without a recorded step to reverse.
+ * Synchronises the stream. */
 mm_status mm_adjoint_step(mm_ctx *ctx, const double *lamQ_in,
-                          const double *lamPhi_in, double *lamQ_out,
-                          double *lamPhi_out, int32_t ptr_kind);
+                          const double *lamPhi_in, const double *lamAlpha_in,
+                          double *lamQ_out, double *lamPhi_out,
+                          int32_t ptr_kind);
+
+/* Adjoint of the inflow state (rho, u, v, p) collected by the reverse steps
+ * taken since the tape's last step (host array of 4). */
+mm_status mm_adjoint_inflow(mm_ctx *ctx, double *out);
+
+/* Steps on the tape, steps still to reverse, and (dt not NULL, host array
+ * of `recorded` entries) the recorded step sizes. */
+mm_status mm_tape_info(mm_ctx *ctx, int64_t *recorded, int64_t *remaining,
+                       double *dt);
 
 /* Measurement of the dominant kernel.  With profiling enabled, every launch
  * of the bulk flux/update kernel (cells away from interfaces) is bracketed

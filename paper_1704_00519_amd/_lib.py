@@ -22,7 +22,8 @@ STATUS = {0: "MM_OK", 1: "MM_EINVAL", 2: "MM_ENOMEM", 3: "MM_EDEVICE",
           4: "MM_ENONPHYS", 5: "MM_ESTATE", 6: "MM_ENOTIMPL"}
 
 EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
-           "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step", "mm_destroy",
+           "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step", "mm_adjoint_inflow",
+           "mm_tape_info", "mm_destroy",
            "mm_last_error", "mm_set_profiling", "mm_get_profile",
            "mm_batch_create", "mm_batch_init_state", "mm_batch_step",
            "mm_batch_get_conserved", "mm_batch_get_diagnostics",
@@ -47,7 +48,21 @@ class MMDiag(C.Structure):
                 ("n_posfix", C.c_int64), ("n_fluxskip", C.c_int64),
                 ("n_ifskip", C.c_int64), ("n_stranded", C.c_int64),
                 ("n_mixsrc", C.c_int64), ("n_updates", C.c_int64),
-                ("err_cell", C.c_int64)]
+                ("err_cell", C.c_int64),
+                ("sum_Q", (C.c_double * 4) * 8), ("bnd_in", (C.c_double * 4) * 8),
+                ("exch", (C.c_double * 4) * 8)]
+
+
+_DIAG_ARRAYS = ("sum_Q", "bnd_in", "exch")
+
+
+def _diag_dict(d, n_mat):
+    out = {}
+    for k, _ in MMDiag._fields_:
+        v = getattr(d, k)
+        out[k] = np.array([[v[r][c] for c in range(4)] for r in range(n_mat)]) \
+            if k in _DIAG_ARRAYS else v
+    return out
 
 
 class MMProfile(C.Structure):
@@ -80,7 +95,9 @@ def load():
         L.mm_get_conserved.argtypes = [vp, vp, vp, vp, vp, i32]
         L.mm_get_diagnostics.argtypes = [vp, C.POINTER(MMDiag)]
         L.mm_set_dt.argtypes = [vp, dbl]
-        L.mm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.mm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+        L.mm_adjoint_inflow.argtypes = [vp, vp]
+        L.mm_tape_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.mm_destroy.argtypes = [vp]
         L.mm_set_profiling.argtypes = [vp, i32]
         L.mm_get_profile.argtypes = [vp, C.POINTER(MMProfile)]
@@ -103,6 +120,7 @@ def load():
         L.mm_last_error.restype = C.c_char_p
         for name in ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
                      "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step",
+                     "mm_adjoint_inflow", "mm_tape_info",
                      "mm_destroy", "mm_set_profiling", "mm_get_profile"):
             getattr(L, name).restype = i32
         _lib = L
@@ -171,10 +189,48 @@ class Solver:
                                       W.ctypes.data, MM_HOST)
         self._check(st)
 
-    def step(self, n=1):
+    def step(self, n=1, record=0):
+        """Advance n steps; record = K > 0 keeps the adjoint tape with a
+        checkpoint every K steps."""
         t = C.c_double()
-        self._check(load().mm_step(self._h, int(n), 0, C.byref(t)))
+        self._check(load().mm_step(self._h, int(n), int(record), C.byref(t)))
         return t.value
+
+    def adjoint_step(self, lamQ=None, lamPhi=None, lamAlpha=None, out=True):
+        """Reverse the last recorded step.  Inputs (numpy, interior layout)
+        replace the carried adjoint; None continues from it.  Returns
+        (lamQ, lamPhi) of the state before the step, or None with out=False."""
+        def inp(a, shape):
+            if a is None:
+                return None, None
+            a = np.ascontiguousarray(a, np.float64).reshape(shape)
+            return a, a.ctypes.data
+        qa, qp = inp(lamQ, (self.M, self.nv, self.ny, self.nx))
+        pa, pp = inp(lamPhi, (self.ny, self.nx))
+        aa, ap = inp(lamAlpha, (self.M, self.ny, self.nx))
+        oq = op = None
+        if out:
+            oq = np.zeros((self.M, self.nv, self.ny, self.nx))
+            op = np.zeros((self.ny, self.nx))
+        self._check(load().mm_adjoint_step(
+            self._h, qp, pp, ap, oq.ctypes.data if out else None,
+            op.ctypes.data if out else None, MM_HOST))
+        del qa, pa, aa
+        return (oq, op) if out else None
+
+    def adjoint_inflow(self):
+        out = np.zeros(4)
+        self._check(load().mm_adjoint_inflow(self._h, out.ctypes.data))
+        return out
+
+    def tape(self):
+        """(recorded steps, steps left to reverse, recorded step sizes)."""
+        n, rem = C.c_int64(), C.c_int64()
+        self._check(load().mm_tape_info(self._h, C.byref(n), C.byref(rem), None))
+        dt = np.zeros(max(n.value, 1))
+        if n.value:
+            self._check(load().mm_tape_info(self._h, None, None, dt.ctypes.data))
+        return n.value, rem.value, dt[:n.value]
 
     def set_dt(self, dt):
         self._check(load().mm_set_dt(self._h, float(dt)))
@@ -206,7 +262,7 @@ class Solver:
     def diag(self):
         d = MMDiag()
         self._check(load().mm_get_diagnostics(self._h, C.byref(d)))
-        return {k: getattr(d, k) for k, _ in MMDiag._fields_}
+        return _diag_dict(d, self.M)
 
 
 class Batch:
@@ -279,4 +335,4 @@ class Batch:
     def diag(self):
         arr = (MMDiag * self.n)()
         self._check(load().mm_batch_get_diagnostics(self._h, arr))
-        return [{k: getattr(d, k) for k, _ in MMDiag._fields_} for d in arr]
+        return [_diag_dict(d, self.M) for d in arr]

@@ -1,0 +1,383 @@
+// Host side of the adjoint entry points: the tape of recorded steps
+// (checkpoints every K steps and the step sizes), recomputation of one
+// segment with per-stage snapshots, and the reverse of one time step.
+// Included once, at the end of mmfv_lib.hip.
+#pragma once
+
+// ---------------------------------------------------------------------------
+// Snapshots of the state at the start of a stage: Q and occupancy of the
+// stage's input buffer, the level set with its frame, the geometry and the
+// record of the volume-fraction correction; after stage 0 of a step also
+// the level-set velocity and the time-n level set.
+// ---------------------------------------------------------------------------
+struct SnapLayout {
+  size_t q, phi, geo, occ, chi, vfc, bytes;  // stage snapshot offsets
+  size_t vx, vy, phin, chin, ext_bytes;      // step extras offsets
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static SnapLayout snap_layout(const Params& P) {
+  SnapLayout L;
+  size_t nc = P.NC, M = P.M, nv = P.dim + 2, at = 0;
+  L.q = at; at = align256(at + M * nv * nc * 8);
+  L.phi = at; at = align256(at + nc * 8);
+  L.geo = at; at = align256(at + 5 * M * nc * 8);
+  L.occ = at; at = align256(at + nc);
+  L.chi = at; at = align256(at + nc);
+  L.vfc = at; at = align256(at + nc * 2);
+  L.bytes = at;
+  at = 0;
+  L.vx = at; at = align256(at + nc * 8);
+  L.vy = at; at = align256(at + nc * 8);
+  L.phin = at; at = align256(at + nc * 8);
+  L.chin = at; at = align256(at + nc);
+  L.ext_bytes = at;
+  return L;
+}
+
+static void cpy(mm_ctx* c, void* dst, const void* src, size_t n) {
+  (void)hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, c->stream);
+}
+
+static void geo_ptrs(mm_ctx* c, double* g[5]) {
+  g[0] = c->B.al; g[1] = c->B.ax; g[2] = c->B.ay; g[3] = c->B.cx; g[4] = c->B.cy;
+}
+
+static void snap_save(mm_ctx* c, char* dst, int sidx) {
+  const Params& P = c->P;
+  SnapLayout L = snap_layout(P);
+  size_t nc = P.NC, M = P.M, nv = P.dim + 2;
+  cpy(c, dst + L.q, c->B.Q[sidx], M * nv * nc * 8);
+  cpy(c, dst + L.phi, c->B.phi, nc * 8);
+  double* g[5];
+  geo_ptrs(c, g);
+  for (int q = 0; q < 5; q++) cpy(c, dst + L.geo + q * M * nc * 8, g[q], M * nc * 8);
+  cpy(c, dst + L.occ, c->B.occ[sidx], nc);
+  cpy(c, dst + L.chi, c->B.chi, nc);
+  cpy(c, dst + L.vfc, c->B.vfc, nc * 2);
+}
+
+// restore a stage snapshot into buffer sidx and rebuild the classification
+// and the tile list of that stage
+template <int D>
+static void snap_load(mm_ctx* c, const char* src, int sidx) {
+  const Params& P = c->P;
+  SnapLayout L = snap_layout(P);
+  size_t nc = P.NC, M = P.M, nv = P.dim + 2;
+  cpy(c, c->B.Q[sidx], src + L.q, M * nv * nc * 8);
+  cpy(c, c->B.phi, src + L.phi, nc * 8);
+  double* g[5];
+  geo_ptrs(c, g);
+  for (int q = 0; q < 5; q++) cpy(c, g[q], src + L.geo + q * M * nc * 8, M * nc * 8);
+  cpy(c, c->B.occ[sidx], src + L.occ, nc);
+  cpy(c, c->B.chi, src + L.chi, nc);
+  cpy(c, c->B.vfc, src + L.vfc, nc * 2);
+  classify<D>(c);
+  build_tiles<D>(c, sidx, 0);
+}
+
+static void ext_save(mm_ctx* c, char* dst) {
+  SnapLayout L = snap_layout(c->P);
+  size_t nc = c->P.NC;
+  cpy(c, dst + L.vx, c->B.vx, nc * 8);
+  cpy(c, dst + L.vy, c->B.vy, nc * 8);
+  cpy(c, dst + L.phin, c->B.phin, nc * 8);
+  cpy(c, dst + L.chin, c->B.chin, nc);
+}
+static void ext_load(mm_ctx* c, const char* src) {
+  SnapLayout L = snap_layout(c->P);
+  size_t nc = c->P.NC;
+  cpy(c, c->B.vx, src + L.vx, nc * 8);
+  cpy(c, c->B.vy, src + L.vy, nc * 8);
+  cpy(c, c->B.phin, src + L.phin, nc * 8);
+  cpy(c, c->B.chin, src + L.chin, nc);
+}
+
+// fixed step size of recorded step n for the recomputation
+template <int D>
+static void use_tape_dt(mm_ctx* c, int64_t n) {
+  cpy(c, c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
+  LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
+}
+
+// segment buffer: per step, ns stage snapshots then the step extras
+static size_t seg_step_bytes(const mm_ctx* c, int ns) {
+  SnapLayout L = snap_layout(c->P);
+  return ns * L.bytes + L.ext_bytes;
+}
+static char* seg_stage(mm_ctx* c, int64_t rel, int s, int ns) {
+  return c->seg + rel * seg_step_bytes(c, ns) + s * snap_layout(c->P).bytes;
+}
+static char* seg_ext(mm_ctx* c, int64_t rel, int ns) {
+  return c->seg + rel * seg_step_bytes(c, ns) + ns * snap_layout(c->P).bytes;
+}
+
+static hipError_t grow(mm_ctx* c, char** p, size_t* cap, size_t need) {
+  if (*cap >= need) return hipSuccess;
+  if (*p) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(*p);
+  }
+  *p = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc((void**)p, need);
+  if (e == hipSuccess) *cap = need;
+  return e;
+}
+
+// recompute recorded steps [n0, n1) from the checkpoint at n0 and keep the
+// stage snapshots of every step
+template <int D>
+static void load_segment(mm_ctx* c, int64_t n0, int64_t n1) {
+  double b[3], cc[3], w[3];
+  int ns = rk_coefs(c->cfg, b, cc, w);
+  snap_load<D>(c, c->ckpt[n0 / c->tape_K], 0);
+  for (int64_t n = n0; n < n1; n++) {
+    use_tape_dt<D>(c, n);
+    for (int s = 0; s < ns; s++) {
+      int sidx = stage_src(s), didx = stage_dst(s, ns);
+      snap_save(c, seg_stage(c, n - n0, s, ns), sidx);
+      stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
+      if (s == 0) ext_save(c, seg_ext(c, n - n0, ns));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint buffers (allocated on first use)
+// ---------------------------------------------------------------------------
+static mm_status adj_alloc(mm_ctx* c) {
+  if (c->adj_ready) return MM_OK;
+  const Params& P = c->P;
+  size_t nc = P.NC, M = P.M, nv = P.dim + 2;
+  Adj& A = c->A;
+  memset(&A, 0, sizeof(A));
+  hipError_t e = hipSuccess;
+#define AA(p, n)                                     \
+  if (e == hipSuccess) {                             \
+    e = dalloc(c, &(p), (n));                        \
+  }
+  AA(A.lQ, M * 4 * nc); AA(A.lQs, M * 4 * nc); AA(A.lQn, M * 4 * nc);
+  AA(A.lphi, nc); AA(A.lphis, nc); AA(A.lphin, nc);
+  AA(A.lW, M * 4 * nc);
+  AA(A.lal, M * nc); AA(A.lax, M * nc); AA(A.lay, M * nc); AA(A.lcx, M * nc); AA(A.lcy, M * nc);
+  AA(A.lvx, nc); AA(A.lvy, nc);
+  AA(A.linflow, 4);
+  AA(A.Qstar, M * nv * nc); AA(A.occstar, nc);
+  AA(A.lalpha, M * nc);
+  AA(c->ctr_save, C_N); AA(c->scal_save, 8); AA(c->cons_save, CONS_N);
+#undef AA
+  if (e != hipSuccess) return fail(c, MM_ENOMEM, "adjoint buffers");
+  c->adj_ready = true;
+  return MM_OK;
+}
+
+static void zero(mm_ctx* c, void* p, size_t bytes) {
+  (void)hipMemsetAsync(p, 0, bytes, c->stream);
+}
+
+__global__ void k_restore_ctr(unsigned long long* ctr, const unsigned long long* save) {
+  int t = threadIdx.x;
+  if (t < C_N && t != C_STAMP) ctr[t] = save[t];
+}
+
+// reverse of recorded step n: on entry A.lQ / A.lphi hold the adjoint of the
+// state after step n (and A.lalpha that of its volume fractions), on exit
+// that of the state before it
+template <int D>
+static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
+  const Params& P = c->P;
+  size_t nc = P.NC, M = P.M;
+  double b[3], cc[3], w[3];
+  int ns = rk_coefs(c->cfg, b, cc, w);
+  dim3 g = cell_grid(c), bl = cell_block(c);
+  Adj& A = c->A;
+  int64_t rel = n - c->seg_n0;
+  zero(c, A.lQn, M * 4 * nc * 8);
+  zero(c, A.lphin, nc * 8);
+  zero(c, A.lvx, nc * 8);
+  zero(c, A.lvy, nc * 8);
+  int nfx0 = (P.nx + 1) * P.ny, nfx1 = P.nx * (P.ny + 1);
+  for (int s = ns - 1; s >= 0; s--) {
+    int sidx = stage_src(s), didx = stage_dst(s, ns);
+    auto load = [&]() {
+      snap_load<D>(c, seg_stage(c, rel, s, ns), sidx);
+      if (s > 0) {
+        // time-n state in buffer 0, velocity and time-n level set of stage 0
+        SnapLayout L = snap_layout(P);
+        const char* s0 = seg_stage(c, rel, 0, ns);
+        cpy(c, c->B.Q[0], s0 + L.q, M * (P.dim + 2) * nc * 8);
+        cpy(c, c->B.occ[0], s0 + L.occ, nc);
+        ext_load(c, seg_ext(c, rel, ns));
+      }
+      use_tape_dt<D>(c, n);
+    };
+    // phase 1: the whole stage, then mixing and the new geometry
+    load();
+    stage_fluid<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
+    stage_levelset<D>(c, didx, 0, b[s], cc[s], true, A.Qstar, A.occstar);
+    cpy(c, A.lQs, A.lQ, M * 4 * nc * 8);
+    cpy(c, A.lphis, A.lphi, nc * 8);
+    zero(c, A.lal, M * nc * 8);
+    LAUNCH(k_a_mix<D>, g, bl, P, c->B, A);
+    if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
+    zero(c, A.lax, M * nc * 8);
+    zero(c, A.lay, M * nc * 8);
+    zero(c, A.lcx, M * nc * 8);
+    zero(c, A.lcy, M * nc * 8);
+    LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphis);
+    if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
+    LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
+    // phase 2: the stage up to the new level set (not committed)
+    load();
+    stage_fluid<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
+    stage_levelset<D>(c, didx, 0, b[s], cc[s], false);
+    zero(c, A.lphi, nc * 8);
+    zero(c, A.lW, M * 4 * nc * 8);
+    zero(c, A.lal, M * nc * 8);
+    zero(c, A.lax, M * nc * 8);
+    zero(c, A.lay, M * nc * 8);
+    zero(c, A.lcx, M * nc * 8);
+    zero(c, A.lcy, M * nc * 8);
+    LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
+    LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);
+    LAUNCH(k_a_flux<D>, lin_grid(nfx0), dim3(256), P, c->B, A, sidx, cc[s], 0);
+    if (D == 2) LAUNCH(k_a_flux<D>, lin_grid(nfx1), dim3(256), P, c->B, A, sidx, cc[s], 1);
+    if (s == 0) {
+      LAUNCH(k_a_vfill<D>, g, bl, P, c->B, A, sidx);
+      for (int sw = 3; sw >= 0; sw--) LAUNCH(k_a_vext<D>, g, bl, P, c->B, A, sw);
+    }
+    LAUNCH(k_a_iface<D>, g, bl, P, c->B, A, sidx, cc[s], s == 0 ? 1 : 0);
+    if (D == 2)
+      LAUNCH(k_a_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, A);
+    LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
+    for (int sw = P.kext + 3; sw >= 0; sw--)
+      LAUNCH(k_a_ext<D>, dim3(256), dim3(256), P, c->B, A, sidx, sw);
+    LAUNCH(k_a_real<D>, g, bl, P, c->B, A, sidx);
+    LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphi);
+    if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
+    LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
+  }
+  LAUNCH(k_a_finish, g, bl, P, A);
+}
+
+extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const double* lamPhi_in,
+                                     const double* lamAlpha_in, double* lamQ_out,
+                                     double* lamPhi_out, int32_t ptr_kind) {
+  if (!c) return MM_EINVAL;
+  if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
+  if (c->tape_K <= 0 || c->tape_rev <= 0)
+    return fail(c, MM_ESTATE, "no recorded step left to reverse");
+  mm_status st = adj_alloc(c);
+  if (st != MM_OK) return st;
+  const Params& P = c->P;
+  size_t plane = (size_t)P.nx * P.ny, nv = P.dim + 2;
+  size_t nQ = (size_t)P.M * nv * plane, nA = (size_t)P.M * plane;
+  Adj& A = c->A;
+  SnapLayout L = snap_layout(P);
+  // first reverse call: keep the forward state after the last recorded step
+  if (c->tape_rev == c->tape_n) {
+    HIP_OK(c, grow(c, &c->final_snap, &c->final_cap, L.bytes));
+    snap_save(c, c->final_snap, 0);
+    zero(c, A.linflow, 4 * 8);
+    zero(c, A.lQ, (size_t)P.M * 4 * P.NC * 8);
+    zero(c, A.lphi, (size_t)P.NC * 8);
+  }
+  cpy(c, c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
+  cpy(c, c->scal_save, c->B.scal, 8 * sizeof(double));
+  cpy(c, c->cons_save, c->B.cons, CONS_N * sizeof(double));
+  // inputs (device copies of host arrays in the staging buffer)
+  const double *dQ = lamQ_in, *dphi = lamPhi_in, *dal = lamAlpha_in;
+  if (ptr_kind == MM_HOST && (lamQ_in || lamPhi_in || lamAlpha_in || lamQ_out || lamPhi_out)) {
+    size_t need = (nQ + plane + nA) * sizeof(double);
+    if (c->d_in_bytes < need) {
+      if (c->d_in) (void)hipFree(c->d_in);
+      c->d_in = nullptr;
+      c->d_in_bytes = 0;
+      if (hipMalloc(&c->d_in, need) != hipSuccess) return fail(c, MM_ENOMEM, "staging buffer");
+      c->d_in_bytes = need;
+    }
+    double* q0 = c->d_in;
+    double* p0 = q0 + nQ;
+    double* a0 = p0 + plane;
+    if (lamQ_in)
+      HIP_OK(c, hipMemcpyAsync(q0, lamQ_in, nQ * 8, hipMemcpyHostToDevice, c->stream));
+    if (lamPhi_in)
+      HIP_OK(c, hipMemcpyAsync(p0, lamPhi_in, plane * 8, hipMemcpyHostToDevice, c->stream));
+    if (lamAlpha_in)
+      HIP_OK(c, hipMemcpyAsync(a0, lamAlpha_in, nA * 8, hipMemcpyHostToDevice, c->stream));
+    dQ = lamQ_in ? q0 : nullptr;
+    dphi = lamPhi_in ? p0 : nullptr;
+    dal = lamAlpha_in ? a0 : nullptr;
+  }
+  dim3 g = cell_grid(c), bl = cell_block(c);
+  if (dQ || dphi || dal) {
+    if (c->D == 2) LAUNCH(k_a_unpack<2>, g, bl, P, A, dQ, dphi, dal);
+    else LAUNCH(k_a_unpack<1>, g, bl, P, A, dQ, dphi, dal);
+  }
+  int64_t n = c->tape_rev - 1;
+  int64_t K = c->tape_K, n0 = (n / K) * K, n1 = n0 + K < c->tape_n ? n0 + K : c->tape_n;
+  if (c->seg_n0 != n0) {
+    double b[3], cc[3], w[3];
+    int ns = rk_coefs(c->cfg, b, cc, w);
+    HIP_OK(c, grow(c, &c->seg, &c->seg_cap, (size_t)(n1 - n0) * seg_step_bytes(c, ns)));
+    if (c->D == 2) load_segment<2>(c, n0, n1);
+    else load_segment<1>(c, n0, n1);
+    c->seg_n0 = n0;
+  }
+  if (c->D == 2) reverse_step<2>(c, n, dal != nullptr);
+  else reverse_step<1>(c, n, dal != nullptr);
+  c->tape_rev--;
+  // outputs
+  if (lamQ_out || lamPhi_out) {
+    double* oq = lamQ_out;
+    double* op = lamPhi_out;
+    if (ptr_kind == MM_HOST) {
+      oq = c->d_in;
+      op = c->d_in + nQ;
+    }
+    if (c->D == 2) LAUNCH(k_a_pack<2>, g, bl, P, A, oq, lamPhi_out ? op : nullptr);
+    else LAUNCH(k_a_pack<1>, g, bl, P, A, oq, lamPhi_out ? op : nullptr);
+    if (ptr_kind == MM_HOST) {
+      if (lamQ_out) HIP_OK(c, hipMemcpyAsync(lamQ_out, oq, nQ * 8, hipMemcpyDeviceToHost, c->stream));
+      if (lamPhi_out)
+        HIP_OK(c, hipMemcpyAsync(lamPhi_out, op, plane * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+  // the forward state after the recorded run, and the diagnostics, as they were
+  if (c->D == 2) snap_load<2>(c, c->final_snap, 0);
+  else snap_load<1>(c, c->final_snap, 0);
+  hipLaunchKernelGGL(k_restore_ctr, dim3(1), dim3(64), 0, c->stream, c->B.ctr,
+                     (const unsigned long long*)c->ctr_save);
+  cpy(c, c->B.scal, c->scal_save, 8 * sizeof(double));
+  cpy(c, c->B.cons, c->cons_save, CONS_N * sizeof(double));
+  HIP_OK(c, hipGetLastError());
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_adjoint_inflow(mm_ctx* c, double* out) {
+  if (!c || !out) return MM_EINVAL;
+  if (!c->adj_ready) {
+    for (int v = 0; v < 4; v++) out[v] = 0.0;
+    return MM_OK;
+  }
+  HIP_OK(c, hipMemcpyAsync(out, c->A.linflow, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_tape_info(mm_ctx* c, int64_t* recorded, int64_t* remaining,
+                                  double* dt) {
+  if (!c) return MM_EINVAL;
+  if (recorded) *recorded = c->tape_K > 0 ? c->tape_n : 0;
+  if (remaining) *remaining = c->tape_K > 0 ? c->tape_rev : 0;
+  if (dt && c->tape_K > 0 && c->tape_n > 0) {
+    HIP_OK(c, hipMemcpyAsync(dt, c->tape_dt, c->tape_n * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
+  return MM_OK;
+}

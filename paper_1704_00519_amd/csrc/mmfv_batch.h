@@ -74,6 +74,9 @@ static size_t layout_bufs(const Params& P, Bufs& B, char* base) {
   take(B.blist, 1);
   B.glist = nullptr;  // the batched kernel sweeps cells, not a queue
   take(B.scal, 8); take(B.ctr, C_N);
+  take(B.vfc, nc);
+  take(B.cons, CONS_N);
+  B.cpart = nullptr;  // each instance reduces within its own workgroup
   return (at + 255) & ~(size_t)255;
 }
 
@@ -84,17 +87,20 @@ __global__ void k_batch_ctr_init(const Bufs* Ba, int n) {
   Ba[q].ctr[C_ERR] = NO_ERR;
   Ba[q].ctr[C_STAMP] = 1;  // stamp arrays start zeroed
   for (int c = 0; c < 8; c++) Ba[q].scal[c] = 0.0;
+  for (int c = 0; c < CONS_N; c++) Ba[q].cons[c] = 0.0;
 }
 __global__ void k_batch_err(const Bufs* Ba, int n, unsigned long long* out) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   out[q] = Ba[q].ctr[C_ERR];
 }
-__global__ void k_batch_diag(const Bufs* Ba, int n, unsigned long long* ctr, double* scal) {
+__global__ void k_batch_diag(const Bufs* Ba, int n, unsigned long long* ctr, double* scal,
+                             double* cons) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   for (int c = 0; c < C_N; c++) ctr[(size_t)q * C_N + c] = Ba[q].ctr[c];
   for (int c = 0; c < 8; c++) scal[(size_t)q * 8 + c] = Ba[q].scal[c];
+  for (int c = 0; c < CONS_N; c++) cons[(size_t)q * CONS_N + c] = Ba[q].cons[c];
 }
 
 static void batch_free(mm_batch* b) {
@@ -390,20 +396,31 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
   if (!b || !out) return MM_EINVAL;
   unsigned long long* dctr = nullptr;
   double* dscal = nullptr;
-  BHIP_OK(b, hipMalloc((void**)&dctr, sizeof(unsigned long long) * C_N * b->n));
-  BHIP_OK(b, hipMalloc((void**)&dscal, sizeof(double) * 8 * b->n));
-  hipLaunchKernelGGL(k_batch_diag, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->dB, b->n,
-                     dctr, dscal);
+  double* dcons = nullptr;
+  hipError_t e = hipMalloc((void**)&dctr, sizeof(unsigned long long) * C_N * b->n);
+  if (e == hipSuccess) e = hipMalloc((void**)&dscal, sizeof(double) * 8 * b->n);
+  if (e == hipSuccess) e = hipMalloc((void**)&dcons, sizeof(double) * CONS_N * b->n);
   std::vector<unsigned long long> ctr((size_t)C_N * b->n);
-  std::vector<double> scal((size_t)8 * b->n);
-  hipError_t e = hipMemcpyAsync(ctr.data(), dctr, ctr.size() * sizeof(ctr[0]),
-                                hipMemcpyDeviceToHost, b->stream);
+  std::vector<double> scal((size_t)8 * b->n), cons((size_t)CONS_N * b->n);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_batch1d_qsum, dim3(b->n), dim3(256), 0, b->stream, b->dP, b->dB);
+    hipLaunchKernelGGL(k_batch_diag, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->dB,
+                       b->n, dctr, dscal, dcons);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctr.data(), dctr, ctr.size() * sizeof(ctr[0]), hipMemcpyDeviceToHost,
+                       b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(scal.data(), dscal, scal.size() * sizeof(double), hipMemcpyDeviceToHost,
                        b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cons.data(), dcons, cons.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  (void)hipFree(dctr);
-  (void)hipFree(dscal);
+  if (dctr) (void)hipFree(dctr);
+  if (dscal) (void)hipFree(dscal);
+  if (dcons) (void)hipFree(dcons);
   if (e != hipSuccess) return bfail(b, MM_EDEVICE, hipGetErrorString(e));
   for (int q = 0; q < b->n; q++) {
     const unsigned long long* c = &ctr[(size_t)q * C_N];
@@ -419,6 +436,7 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
     d.n_mixsrc = (int64_t)c[C_MIXSRC];
     d.n_updates = (int64_t)c[C_UPD];
     d.err_cell = c[C_ERR] == NO_ERR ? -1 : (int64_t)c[C_ERR];
+    cons_to_diag(&cons[(size_t)q * CONS_N], b->M, &d);
   }
   return MM_OK;
 }

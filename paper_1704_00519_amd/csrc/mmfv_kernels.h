@@ -30,6 +30,11 @@ struct Bufs {
   int32_t* tiles;          // active tiles of the current stage
   int32_t* blist;          // cells updated by the general (band) path
   int32_t* glist;          // (cell, material) pairs waiting for a ghost state
+  uint16_t* vfc;           // per cut cell: volume-fraction correction taken
+                           // (low byte: absorbing material or 0xff, high
+                           // byte: materials set to zero)
+  double* cons;            // conservation book-keeping, CONS_N doubles
+  double* cpart;           // per-workgroup partial sums of the book-keeping
   double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t
   unsigned long long* ctr; // smax bits, error cell, counters
 };
@@ -38,6 +43,12 @@ enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
        C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
+// book-keeping regions of MAXM x 4 doubles each: accumulated net boundary
+// inflow and its compensation, accumulated exchange and its compensation,
+// and the last computed sums of Q
+enum { CONS_BND = 0, CONS_BNDC = 1, CONS_X = 2, CONS_XC = 3, CONS_Q = 4, CONS_N = 5 * MAXM * 4 };
+// cells (or boundary rows and columns) per workgroup of the partial sums
+constexpr int CONS_CH = 2048;
 
 MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
 MMD bool interior(const Params& P, int i, int j) {
@@ -121,13 +132,15 @@ MMD double apy(const Params& P, const Bufs& B, int r, int i, int j) {
   return B.chi[knc] == r ? 1.0 : 0.0;
 }
 
-// primitive state of material r at a cell: computed on the fly in pure
-// cells of r (alpha = 1), read from the real/ghost buffer elsewhere
+// primitive state of material r at a cell: read from the real/ghost buffer
+// within seven cells of a cut cell (where it is refreshed every stage),
+// computed on the fly in the pure cells farther away (alpha = 1)
 template <int D>
 MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
               const uint8_t* occs, int r, int i, int j, bool& valid) {
   int k = cid(P, i, j);
-  if (interior(P, i, j) && !B.cut[k] && B.chi[k] == r) {
+  bool in = interior(P, i, j);
+  if (in && B.dcut[k] > 7 && B.chi[k] == r) {
     valid = true;
     double U0 = loadQ<D>(P, Qs, occs, r, 0, k) / 1.0;
     double U1 = loadQ<D>(P, Qs, occs, r, 1, k) / 1.0;
@@ -135,10 +148,9 @@ MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
     double U3 = loadQ<D>(P, Qs, occs, r, 3, k) / 1.0;
     return prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
   }
-  // buffer states are refreshed each stage only within four cells of a cut
-  // cell (and in the frame); anything older is stale
-  valid = B.Wit[(size_t)r * P.NC + k] != 0 &&
-          (!interior(P, i, j) || B.dcut[k] <= 4);
+  // buffer states are refreshed each stage within seven cells of a cut cell
+  // (and in the frame); anything older is stale
+  valid = B.Wit[(size_t)r * P.NC + k] != 0 && (!in || B.dcut[k] <= 7);
   Prim w;
   w.r = B.W[((size_t)r * 4 + 0) * P.NC + k];
   w.u = B.W[((size_t)r * 4 + 1) * P.NC + k];
@@ -477,6 +489,7 @@ MMD void b_geom(const Params& P, const Bufs& B, int i, int j, int midx, const do
   }
   // volume-fraction correction in cells with three or more materials
   int n = 0;
+  unsigned vfc_f = 0xff, vfc_z = 0;
   for (int r = 0; r < P.M; r++)
     if (al[r] > 0.0) n++;
   if (n >= 3) {
@@ -506,13 +519,16 @@ MMD void b_geom(const Params& P, const Bufs& B, int i, int j, int midx, const do
       if (nv < 0.0) {
         al[best] = 0.0;
         d = nv;
+        vfc_z |= 1u << best;
       } else {
         al[best] = nv;
         d = 0.0;
+        vfc_f = (unsigned)best;
       }
     }
   }
   for (int r = 0; r < P.M; r++) B.al[(size_t)r * P.NC + k] = al[r];
+  if (B.vfc) B.vfc[k] = (uint16_t)(vfc_f | (vfc_z << 8));
 }
 template <int D>
 __global__ void k_geom(Params P, Bufs B, int midx, const double* Win) {
@@ -567,12 +583,10 @@ __global__ void k_init_Q(Params P, Bufs B, const double* Win) {
 template <int D>
 MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
   int k = cid(P, i, j);
-  (void)k;
-  if (errored(B) || B.dcut[k] > 4) return;
+  if (errored(B) || B.dcut[k] > 7) return;
   for (int r = 0; r < P.M; r++) B.Wit[(size_t)r * P.NC + k] = 0;
-  if (!B.cut[k]) return;
   int r = B.chi[k];
-  double a = B.al[(size_t)r * P.NC + k];
+  double a = B.cut[k] ? B.al[(size_t)r * P.NC + k] : 1.0;
   if (!(a > 0.0)) return;
   const double* Q = B.Q[sidx];
   const uint8_t* occ = B.occ[sidx];
@@ -581,7 +595,8 @@ MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
   double U2 = loadQ<D>(P, Q, occ, r, 2, k) / a;
   double U3 = loadQ<D>(P, Q, occ, r, 3, k) / a;
   Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
-  if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
+  // pure cells are checked where they are updated; cut cells here
+  if (B.cut[k] && nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
   size_t o = (size_t)r * 4 * P.NC;
   B.W[o + k] = w.r;
   B.W[o + (size_t)P.NC + k] = w.u;
@@ -657,8 +672,7 @@ MMD void ext_one(const Params& P, const Bufs& B, int i, int j, int r, int sidx, 
   auto valid_prev = [&](int ii, int jj) -> bool {
     if (!interior(P, ii, jj)) return false;
     int kk = cid(P, ii, jj);
-    if (!B.cut[kk] && B.chi[kk] == r) return true;
-    if (B.dcut[kk] > 4) return false;
+    if (B.dcut[kk] > 7) return B.chi[kk] == r;
     uint8_t it = B.Wit[(size_t)r * P.NC + kk];
     return it != 0 && it <= sweep + 1;
   };
@@ -1739,6 +1753,186 @@ __global__ void __launch_bounds__(256) k_ext_list(Params P, Bufs B, int sidx, in
 // are listed, and the near-interface kernels walk that list.  Every cell
 // those kernels act on lies in a listed tile, so results do not change.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Conservation book-keeping (Eq. discretized_equ: a material's total changes
+// only by the fluxes through the domain boundary and by its exchange term):
+// per stage, the net boundary inflow and the exchange total of every
+// material and component, weighted by the stage's share of the full step
+// and added to compensated (Neumaier) running sums; on demand, the sums of
+// Q.  Partial sums are formed per workgroup over fixed index ranges and
+// combined in a fixed order, so the results do not depend on scheduling.
+// ---------------------------------------------------------------------------
+MMD double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// sums of v[0..7] over the workgroup (blockDim.x a multiple of 64, at most
+// 1024) in a fixed order; the results are left in thread 0's v.  red holds
+// 8 doubles per wavefront.
+MMD void block_sum8(double v[8], double* red) {
+  int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int x = 0; x < 8; x++) v[x] = wave_sum(v[x]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int x = 0; x < 8; x++) red[w * 8 + x] = v[x];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int x = 0; x < 8; x++) {
+      double t = 0.0;
+      for (int q = 0; q < nw; q++) t += red[q * 8 + x];
+      v[x] = t;
+    }
+}
+
+MMD void neumaier_add(double* sum, double* comp, double x) {
+  double t = *sum + x;
+  if (fabs(*sum) >= fabs(x))
+    *comp += (*sum - t) + x;
+  else
+    *comp += (x - t) + *sum;
+  *sum = t;
+}
+
+// add one stage's totals of material r (t[0..3] boundary inflow, t[4..7]
+// exchange), weighted by the stage's share w of the step
+MMD void cons_accumulate(const Bufs& B, int r, const double t[8], double w) {
+  for (int v = 0; v < 4; v++) {
+    neumaier_add(&B.cons[(CONS_BND * MAXM + r) * 4 + v], &B.cons[(CONS_BNDC * MAXM + r) * 4 + v],
+                 w * t[v]);
+    neumaier_add(&B.cons[(CONS_X * MAXM + r) * 4 + v], &B.cons[(CONS_XC * MAXM + r) * 4 + v],
+                 w * t[4 + v]);
+  }
+}
+
+// flux term of one domain-boundary face of material r: side 0 is the low
+// face of row/column q (x-face i-1/2 of row q, or y-face j-1/2 of column q),
+// side 1 the high face; out = A F (0 where A = 0)
+template <int D>
+MMD void cons_face(const Params& P, const Bufs& B, const double* Qs, const uint8_t* os, int r,
+                   int dir, int q, int side, double out[4]) {
+  double F[4] = {0, 0, 0, 0};
+  double A;
+  if (dir == 0) {
+    int i = side == 0 ? -1 : P.nx - 1;
+    A = apx<D>(P, B, r, i, q);
+    if (A > 0.0) face_flux<D>(P, B, Qs, os, r, i, q, 0, false, F);
+  } else {
+    int j = side == 0 ? -1 : P.ny - 1;
+    A = apy(P, B, r, q, j);
+    if (A > 0.0) face_flux<D>(P, B, Qs, os, r, q, j, 1, false, F);
+  }
+  for (int v = 0; v < 4; v++) out[v] = A > 0.0 ? A * F[v] : 0.0;
+}
+
+// net inflow of material r through the two boundary faces of row q
+// (q < ny) or of column q - ny (2D, ny <= q < ny + nx)
+template <int D>
+MMD void cons_boundary(const Params& P, const Bufs& B, const double* Qs, const uint8_t* os,
+                       int r, long q, double out[4]) {
+  int dir = q < P.ny ? 0 : 1;
+  int qq = dir == 0 ? (int)q : (int)(q - P.ny);
+  double lo[4], hi[4];
+  cons_face<D>(P, B, Qs, os, r, dir, qq, 0, lo);
+  cons_face<D>(P, B, Qs, os, r, dir, qq, 1, hi);
+  double l = dir == 0 ? B.scal[S_LX] : B.scal[S_LY];
+  for (int v = 0; v < 4; v++) out[v] = l * (lo[v] - hi[v]);
+}
+
+MMD int cons_rows(const Params& P) { return P.dim == 2 ? P.ny + P.nx : 1; }
+
+// Grid (nbb + ncb, M): workgroups x < nbb take 256 boundary rows/columns
+// each, the others CONS_CH cells each (exchange); y is the material.
+// Partials cpart[x][r][8]: net boundary inflow, exchange.
+template <int D>
+__global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, int nbb) {
+  __shared__ double red[4 * 8];
+  const double* Qs = B.Q[sidx];
+  const uint8_t* os = B.occ[sidx];
+  int r = blockIdx.y;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double* part = B.cpart + ((size_t)blockIdx.x * P.M + r) * 8;
+  if ((int)blockIdx.x < nbb) {
+    long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q < cons_rows(P)) cons_boundary<D>(P, B, Qs, os, r, q, acc);
+  } else {
+    long q0 = (long)(blockIdx.x - nbb) * CONS_CH, n = (long)P.nx * P.ny;
+    bool any = false;
+    double lv = B.scal[S_LV];
+    for (int m = threadIdx.x; m < CONS_CH; m += 256) {
+      long q = q0 + m;
+      if (q >= n) break;
+      int k = cid(P, (int)(q % P.nx), (int)(q / P.nx));
+      if (!B.cut[k]) continue;
+      any = true;
+      for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + k];
+    }
+    if (!__syncthreads_or(any)) {
+      if (threadIdx.x < 8) part[threadIdx.x] = 0.0;
+      return;
+    }
+  }
+  block_sum8(acc, red);
+  if (threadIdx.x == 0)
+    for (int v = 0; v < 8; v++) part[v] = acc[v];
+}
+
+// combine the partials of nblk workgroups in a fixed order and add the
+// stage totals, weighted by w, to the running sums (one thread per material
+// and quantity)
+__global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w) {
+  int x = threadIdx.x;
+  if (x >= P.M * 8) return;
+  int r = x / 8, v = x % 8;
+  double a = 0.0;
+  for (int b = 0; b < nblk; b++) a += B.cpart[((size_t)b * P.M + r) * 8 + v];
+  if (v < 4)
+    neumaier_add(&B.cons[(CONS_BND * MAXM + r) * 4 + v], &B.cons[(CONS_BNDC * MAXM + r) * 4 + v],
+                 w * a);
+  else
+    neumaier_add(&B.cons[(CONS_X * MAXM + r) * 4 + v - 4],
+                 &B.cons[(CONS_XC * MAXM + r) * 4 + v - 4], w * a);
+}
+
+// this thread's part of the sums of Q (state buffer sidx) of material r over
+// cells q0 + tid, q0 + tid + T, ... below q1; out[4..7] = 0
+template <int D>
+MMD void qsum_range(const Params& P, const Bufs& B, int sidx, int r, long q0, long q1, int tid,
+                    int T, double acc[8]) {
+  for (int v = 0; v < 8; v++) acc[v] = 0.0;
+  for (long q = q0 + tid; q < q1; q += T) {
+    int k = cid(P, (int)(q % P.nx), (int)(q / P.nx));
+    for (int v = 0; v < 4; v++) acc[v] += loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, v, k);
+  }
+}
+
+// sums of Q per material and component: partials over CONS_CH cells per
+// workgroup, then k_qsum_fin
+template <int D>
+__global__ void __launch_bounds__(256) k_qsum_part(Params P, Bufs B, int sidx) {
+  __shared__ double red[4 * 8];
+  long q0 = (long)blockIdx.x * CONS_CH, n = (long)P.nx * P.ny;
+  long q1 = q0 + CONS_CH < n ? q0 + CONS_CH : n;
+  for (int r = 0; r < P.M; r++) {
+    double acc[8];
+    qsum_range<D>(P, B, sidx, r, q0, q1, threadIdx.x, 256, acc);
+    block_sum8(acc, red);
+    if (threadIdx.x == 0)
+      for (int v = 0; v < 4; v++) B.cpart[((size_t)blockIdx.x * P.M + r) * 4 + v] = acc[v];
+  }
+}
+__global__ void __launch_bounds__(256) k_qsum_fin(Params P, Bufs B, int nblk) {
+  __shared__ double red[4 * 8];
+  for (int r = 0; r < P.M; r++) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+      for (int v = 0; v < 4; v++) a[v] += B.cpart[((size_t)b * P.M + r) * 4 + v];
+    block_sum8(a, red);
+    if (threadIdx.x == 0)
+      for (int v = 0; v < 4; v++) B.cons[(CONS_Q * MAXM + r) * 4 + v] = a[v];
+  }
+}
+
 MMD int tile_w(const Params& P) { return P.dim == 2 ? 16 : 256; }
 MMD int tile_h(const Params& P) { return P.dim == 2 ? 16 : 1; }
 MMD int tiles_x(const Params& P) { return (P.nx + tile_w(P) - 1) / tile_w(P); }
@@ -1853,16 +2047,18 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
   const Params& P = sm.P;
   const Bufs& B = sm.B;
   int tid = threadIdx.x, T = blockDim.x;
-  double bc[3], cc[3];
+  double bc[3], cc[3], wc[3];
   int ns;
   if (rk_order == 2) {
     ns = 2;
     bc[0] = 0.0; bc[1] = 0.5;
     cc[0] = 1.0; cc[1] = 0.5;
+    wc[0] = 0.5; wc[1] = 0.5;
   } else {
     ns = 3;
     bc[0] = 0.0; bc[1] = 0.75; bc[2] = 1.0 / 3.0;
     cc[0] = 1.0; cc[1] = 0.25; cc[2] = 2.0 / 3.0;
+    wc[0] = 1.0 / 6.0; wc[1] = 1.0 / 6.0; wc[2] = 2.0 / 3.0;
   }
   uint32_t stamp = (uint32_t)B.ctr[C_STAMP];
   for (int n = 0; n < nsteps; n++) {
@@ -1899,6 +2095,27 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       for (int i0 = 0; i0 < P.nx; i0 += T)
         bulk1_tile(P, B, sm.S, i0, sidx, 0, didx, bc[s], cc[s], s == 0 ? 1 : 0);
       PHASE(b_flux_band<1>(P, B, i_, 0, sidx, 0, didx, bc[s], cc[s]));
+      {
+        // conservation book-keeping: the 2 M boundary faces in parallel,
+        // then the exchange of the cut cells, one material at a time
+        double* fb = sm.red;  // [2 M][4] boundary face terms A F
+        if (tid < 2 * P.M)
+          cons_face<1>(P, B, B.Q[sidx], B.occ[sidx], tid >> 1, 0, 0, tid & 1, fb + tid * 4);
+        __syncthreads();
+        double lv = B.scal[S_LV], lx = B.scal[S_LX];
+        for (int r = 0; r < P.M; r++) {
+          double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          for (int i = tid; i < P.nx; i += T) {
+            int k = cid(P, i, 0);
+            if (B.cut[k])
+              for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + k];
+          }
+          if (tid == 0)
+            for (int v = 0; v < 4; v++) acc[v] = lx * (fb[2 * r * 4 + v] - fb[(2 * r + 1) * 4 + v]);
+          block_sum8(acc, sm.red + 64);
+          if (tid == 0) cons_accumulate(B, r, acc, wc[s]);
+        }
+      }
       PHASE(b_ls<1>(P, B, i_, 0, bc[s], cc[s]));
       PHASE(b_ls_commit<1>(P, B, i_, 0));
       for (int t = tid; t < 2 * H; t += T) b_bc_ls_x(P, t, B.phi, B.chi);
@@ -1950,6 +2167,22 @@ k_batch1d_pack(const Params* Pa, const Bufs* Ba, double* Q, double* alpha, doubl
   PHASE(b_pack<1>(P, B, i_, 0, 0, Q ? Q + (size_t)P.M * 3 * o : nullptr,
                   alpha ? alpha + (size_t)P.M * o : nullptr, phi ? phi + o : nullptr,
                   chi ? chi + o : nullptr));
+}
+
+// sums of Q per material and component of every instance (one workgroup
+// per instance)
+__global__ void __launch_bounds__(1024) k_batch1d_qsum(const Params* Pa, const Bufs* Ba) {
+  __shared__ BatchSmem sm;
+  batch_load(Pa, Ba, sm);
+  const Params& P = sm.P;
+  const Bufs& B = sm.B;
+  for (int r = 0; r < P.M; r++) {
+    double acc[8];
+    qsum_range<1>(P, B, 0, r, 0, P.nx, threadIdx.x, blockDim.x, acc);
+    block_sum8(acc, sm.red);
+    if (threadIdx.x == 0)
+      for (int v = 0; v < 4; v++) B.cons[(CONS_Q * MAXM + r) * 4 + v] = acc[v];
+  }
 }
 #undef PHASE
 

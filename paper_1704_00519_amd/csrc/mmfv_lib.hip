@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "mmfv.h"
+#include "mmfv_adjoint.h"
 #include "mmfv_kernels.h"
 
 using namespace mmfv;
@@ -35,6 +36,23 @@ struct mm_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   unsigned long long prof_u0 = 0, prof_u1 = 0;  // counters at enable time
+  // tape of recorded steps for the adjoint: a checkpoint every tape_K steps
+  // and the step size of every step; tape_rev steps are still to reverse
+  int tape_K = 0;
+  int64_t tape_n = 0, tape_rev = 0;
+  std::vector<char*> ckpt;
+  double* tape_dt = nullptr;
+  size_t tape_dt_cap = 0;
+  char* seg = nullptr;  // stage snapshots of the recomputed segment
+  size_t seg_cap = 0;
+  int64_t seg_n0 = -1;
+  char* final_snap = nullptr;  // state after the last recorded step
+  size_t final_cap = 0;
+  bool adj_ready = false;
+  Adj A;
+  unsigned long long* ctr_save = nullptr;
+  double* scal_save = nullptr;
+  double* cons_save = nullptr;
 };
 
 static void prof_mark(mm_ctx* c) {
@@ -95,6 +113,15 @@ static void free_all(mm_ctx* c) {
   c->ev.clear();
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  for (char* p : c->ckpt) (void)hipFree(p);
+  c->ckpt.clear();
+  void* extra[] = {c->tape_dt, c->seg, c->final_snap};
+  for (void* p : extra)
+    if (p) (void)hipFree(p);
+  c->tape_dt = nullptr;
+  c->seg = nullptr;
+  c->final_snap = nullptr;
+  c->adj_ready = false;
   if (c->d_in) (void)hipFree(c->d_in);
   c->d_in = nullptr;
 }
@@ -125,6 +152,17 @@ static bool valid_config(const mm_config* c, std::string& why) {
     return why = "grid too large", false;
   return true;
 }
+
+// workgroups of the book-keeping partial sums: boundary rows and columns
+// (256 per workgroup), then cells (CONS_CH per workgroup)
+static int cons_bnd_blocks(const Params& P) {
+  int n = P.dim == 2 ? P.nx + P.ny : 1;
+  return (n + 255) / 256;
+}
+static int cons_cell_blocks(const Params& P) {
+  return (int)(((long)P.nx * P.ny + CONS_CH - 1) / CONS_CH);
+}
+static int cons_blocks(const Params& P) { return cons_bnd_blocks(P) + cons_cell_blocks(P); }
 
 static Params make_params(const mm_config* cfg) {
   Params P;
@@ -195,6 +233,9 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.blist, nc);
   A(B.glist, M * nc);
   A(B.scal, 8); A(B.ctr, C_N);
+  A(B.vfc, nc);
+  A(B.cons, CONS_N);
+  A(B.cpart, (size_t)cons_blocks(P) * M * 8);
 #undef A
   if (e != hipSuccess) {
     free_all(c);
@@ -268,9 +309,12 @@ static void build_tiles(mm_ctx* c, int didx, int nidx) {
   LAUNCH(k_tiles, dim3(n_tiles(c->P)), dim3(256), c->P, c->B, didx, nidx);
 }
 
+// first half of a stage: real and ghost states, interface exchange (and at
+// stage 0 the level-set velocity and dt), fluxes and the RK update into
+// buffer didx, conservation book-keeping
 template <int D>
-static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double b,
-                  double cc) {
+static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
+                        double w) {
   const Params& P = c->P;
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
@@ -300,37 +344,69 @@ static void stage(mm_ctx* c, int s, int ns, int sidx, int nidx, int didx, double
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
   LAUNCH(k_flux_list<D>, dim3(512), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
+  LAUNCH(k_cons_part<D>, dim3(cons_blocks(P), P.M), dim3(256), P, c->B, sidx,
+         cons_bnd_blocks(P));
+  LAUNCH(k_cons_fin, dim3(1), dim3(64), P, c->B, cons_blocks(P), w);
+}
+
+// second half: level-set stage and its frame, classification, geometry and
+// correction of the new level set, mixing (with save, Q* is copied before
+// the mixing for the adjoint)
+template <int D>
+static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
+                           bool commit = true, double* save_Q = nullptr,
+                           uint8_t* save_occ = nullptr) {
+  const Params& P = c->P;
+  dim3 tg = tile_grid(c), tb(256);
   LAUNCH(t_ls<D>, tg, tb, P, c->B, b, cc);
+  if (!commit) return;
   LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
   bc_ls<D>(c);
   classify<D>(c);
   build_tiles<D>(c, didx, nidx);
   LAUNCH(t_geom<D>, tg, tb, P, c->B, didx, (const double*)nullptr);
+  if (save_Q) {
+    (void)hipMemcpyAsync(save_Q, c->B.Q[didx], (size_t)P.M * (D + 2) * P.NC * sizeof(double),
+                         hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(save_occ, c->B.occ[didx], (size_t)P.NC, hipMemcpyDeviceToDevice,
+                         c->stream);
+  }
   LAUNCH(t_mix1<D>, tg, tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, tg, tb, P, c->B, didx);
-  (void)ns;
 }
 
 template <int D>
-static void one_step(mm_ctx* c) {
-  double b[3], cc[3];
-  int ns;
-  if (c->cfg.rk_order == 2) {
-    ns = 2;
+static void stage(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
+                  double w) {
+  stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w);
+  stage_levelset<D>(c, didx, nidx, b, cc);
+}
+
+// beta-form coefficients, and each stage's share w of the full step in the
+// final combination (used by the conservation book-keeping)
+static int rk_coefs(const mm_config& cfg, double* b, double* cc, double* w) {
+  if (cfg.rk_order == 2) {
     b[0] = 0.0; b[1] = 0.5;
     cc[0] = 1.0; cc[1] = 0.5;
-  } else {
-    ns = 3;
-    b[0] = 0.0; b[1] = 0.75; b[2] = 1.0 / 3.0;
-    cc[0] = 1.0; cc[1] = 0.25; cc[2] = 2.0 / 3.0;
+    w[0] = 0.5; w[1] = 0.5;
+    return 2;
   }
-  // buffers: 0 holds time n; stages write 1, 2 and finally 0 in place
-  int sidx = 0;
-  for (int s = 0; s < ns; s++) {
-    int didx = s == ns - 1 ? 0 : s + 1;
-    stage<D>(c, s, ns, sidx, 0, didx, b[s], cc[s]);
-    sidx = didx;
-  }
+  b[0] = 0.0; b[1] = 0.75; b[2] = 1.0 / 3.0;
+  cc[0] = 1.0; cc[1] = 0.25; cc[2] = 2.0 / 3.0;
+  w[0] = 1.0 / 6.0; w[1] = 1.0 / 6.0; w[2] = 2.0 / 3.0;
+  return 3;
+}
+// state buffers of stage s of ns: 0 holds time n; stages write 1, 2 and
+// finally 0 in place
+static int stage_src(int s) { return s; }
+static int stage_dst(int s, int ns) { return s == ns - 1 ? 0 : s + 1; }
+
+template <int D>
+static void one_step(mm_ctx* c) {
+  double b[3], cc[3], w[3];
+  int ns = rk_coefs(c->cfg, b, cc, w);
+  for (int s = 0; s < ns; s++)
+    stage<D>(c, s, stage_src(s), 0, stage_dst(s, ns), b[s], cc[s], w[s]);
   hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(1), 0, c->stream, c->P, c->B);
 }
 
@@ -380,6 +456,7 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   init_ctr[C_STAMP] = 1;
   HIP_OK(c, hipMemcpyAsync(c->B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemsetAsync(c->B.scal, 0, 8 * sizeof(double), c->stream));
+  HIP_OK(c, hipMemsetAsync(c->B.cons, 0, CONS_N * sizeof(double), c->stream));
   for (int b = 0; b < 3; b++) HIP_OK(c, hipMemsetAsync(c->B.occ[b], 0, P.NC, c->stream));
   dim3 g = cell_grid(c), bl = cell_block(c);
   LAUNCH(k_load_ls, g, bl, P, c->B, dphi, dchi);
@@ -410,14 +487,11 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   return MM_OK;
 }
 
-extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, double* t_out) {
-  if (!c) return MM_EINVAL;
-  if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
-  if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
-  if (record_tape) return fail(c, MM_ENOTIMPL, "adjoint tape not available");
-  // Replay one captured step per time step when the work goes to a real
-  // stream; the null stream cannot be captured, and per-kernel profiling
-  // needs its events between launches.
+// enqueue n time steps: one captured step replayed per time step when the
+// work goes to a real stream (the null stream cannot be captured, and
+// per-kernel profiling needs its events between launches), else direct
+// launches
+static mm_status launch_steps(mm_ctx* c, int32_t n_steps) {
   bool graph = c->stream && !c->profiling && !c->graph_off && getenv("MMFV_NO_GRAPH") == nullptr;
   if (graph && !c->step_x) {
     bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -444,6 +518,12 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
   }
   HIP_OK(c, hipGetLastError());
   c->steps += n_steps;
+  return MM_OK;
+}
+
+// after a batch of steps: optional time output, then the error check (the
+// one synchronisation)
+static mm_status finish_steps(mm_ctx* c, double* t_out) {
   if (t_out) {
     HIP_OK(c, hipMemcpyAsync(t_out, c->B.scal + S_T, sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
@@ -456,6 +536,22 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
     return fail(c, MM_ENONPHYS, "non-physical state at cell " + std::to_string(err));
   }
   return MM_OK;
+}
+
+static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_out);
+
+extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, double* t_out) {
+  if (!c) return MM_EINVAL;
+  if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
+  if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
+  if (record_tape < 0) return fail(c, MM_EINVAL, "record_tape < 0");
+  if (record_tape > 0) return step_record(c, n_steps, record_tape, t_out);
+  c->tape_K = 0;  // plain steps end any tape
+  c->tape_n = c->tape_rev = 0;
+  c->seg_n0 = -1;
+  mm_status st = launch_steps(c, n_steps);
+  if (st != MM_OK) return st;
+  return finish_steps(c, t_out);
 }
 
 extern "C" mm_status mm_get_conserved(mm_ctx* c, double* Q, double* alpha, double* phi,
@@ -500,10 +596,31 @@ extern "C" mm_status mm_get_conserved(mm_ctx* c, double* Q, double* alpha, doubl
   return MM_OK;
 }
 
+// copy the book-keeping of one context (or instance) into a diag record
+static void cons_to_diag(const double* cons, int M, mm_diag* out) {
+  memset(out->sum_Q, 0, sizeof(out->sum_Q));
+  memset(out->bnd_in, 0, sizeof(out->bnd_in));
+  memset(out->exch, 0, sizeof(out->exch));
+  for (int r = 0; r < M; r++)
+    for (int v = 0; v < 4; v++) {
+      out->sum_Q[r][v] = cons[(CONS_Q * MAXM + r) * 4 + v];
+      out->bnd_in[r][v] = cons[(CONS_BND * MAXM + r) * 4 + v] + cons[(CONS_BNDC * MAXM + r) * 4 + v];
+      out->exch[r][v] = cons[(CONS_X * MAXM + r) * 4 + v] + cons[(CONS_XC * MAXM + r) * 4 + v];
+    }
+}
+
 extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   if (!c || !out) return MM_EINVAL;
   unsigned long long ctr[C_N];
   double scal[8];
+  std::vector<double> cons(CONS_N);
+  int nqb = cons_cell_blocks(c->P);
+  if (c->D == 2) LAUNCH(k_qsum_part<2>, dim3(nqb), dim3(256), c->P, c->B, 0);
+  else LAUNCH(k_qsum_part<1>, dim3(nqb), dim3(256), c->P, c->B, 0);
+  LAUNCH(k_qsum_fin, dim3(1), dim3(256), c->P, c->B, nqb);
+  HIP_OK(c, hipGetLastError());
+  HIP_OK(c, hipMemcpyAsync(cons.data(), c->B.cons, CONS_N * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
   HIP_OK(c, hipMemcpyAsync(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipMemcpyAsync(scal, c->B.scal, sizeof(scal), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -517,6 +634,7 @@ extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   out->n_mixsrc = (int64_t)ctr[C_MIXSRC];
   out->n_updates = (int64_t)ctr[C_UPD];
   out->err_cell = ctr[C_ERR] == NO_ERR ? -1 : (int64_t)ctr[C_ERR];
+  cons_to_diag(cons.data(), c->P.M, out);
   return MM_OK;
 }
 
@@ -527,12 +645,6 @@ extern "C" mm_status mm_set_dt(mm_ctx* c, double dt) {
                            c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return MM_OK;
-}
-
-extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double*, const double*, double*, double*,
-                                     int32_t) {
-  if (!c) return MM_EINVAL;
-  return fail(c, MM_ENOTIMPL, "adjoint step not available in this build");
 }
 
 extern "C" mm_status mm_set_profiling(mm_ctx* c, int32_t enable) {
@@ -565,3 +677,48 @@ extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
 }
 
 #include "mmfv_batch.h"
+
+#include "mmfv_adjoint_host.h"
+
+// Steps with the tape kept: a checkpoint of the state every K steps and the
+// step size of every step.  A new tape starts when none is open, when K
+// changes, or once reverse steps have been taken.
+static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_out) {
+  if (c->tape_K != K || c->tape_rev != c->tape_n) {
+    c->tape_K = K;
+    c->tape_n = c->tape_rev = 0;
+    c->seg_n0 = -1;
+  }
+  size_t need = (size_t)(c->tape_n + n_steps) * sizeof(double);
+  if (need > c->tape_dt_cap) {
+    double* nd = nullptr;
+    size_t cap = need * 2;
+    HIP_OK(c, hipMalloc((void**)&nd, cap));
+    if (c->tape_dt && c->tape_n)
+      HIP_OK(c, hipMemcpyAsync(nd, c->tape_dt, c->tape_n * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (c->tape_dt) (void)hipFree(c->tape_dt);
+    c->tape_dt = nd;
+    c->tape_dt_cap = cap;
+  }
+  SnapLayout L = snap_layout(c->P);
+  for (int n = 0; n < n_steps; n++) {
+    if (c->tape_n % K == 0) {
+      size_t q = (size_t)(c->tape_n / K);
+      if (q >= c->ckpt.size()) {
+        char* p = nullptr;
+        HIP_OK(c, hipMalloc((void**)&p, L.bytes));
+        c->ckpt.push_back(p);
+      }
+      snap_save(c, c->ckpt[q], 0);
+    }
+    mm_status st = launch_steps(c, 1);
+    if (st != MM_OK) return st;
+    cpy(c, c->tape_dt + c->tape_n, c->B.scal + S_DT, sizeof(double));
+    c->tape_n++;
+    c->tape_rev = c->tape_n;
+  }
+  c->seg_n0 = -1;
+  return finish_steps(c, t_out);
+}

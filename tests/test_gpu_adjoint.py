@@ -1,0 +1,176 @@
+"""GPU adjoint (mm_adjoint_step) against the oracle's tangent build.
+
+Both sides differentiate the same discrete step about the same trajectory
+(the forward states are bit-identical), with the step size held fixed and
+the branch pattern of the forward run.  Checks:
+
+* dot products <lambda, J delta> (oracle tangent of delta) against
+  <J^T lambda, delta> (library adjoint of lambda) for random delta in (Q,
+  phi) and random lambda in (Q, phi, alpha) over one and several steps;
+* the gradient of the nested-bubble centroid with respect to (shell
+  density, core density, shock Mach number) against three tangent runs, and
+  against central differences of the library with the recorded step sizes.
+
+The configurations avoid exact ties of the branch tests at the base point
+(interfaces lying exactly on cell faces, as in the triple-point set-up, make
+the step non-differentiable there; see the adjoint notes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DOT_REL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1704_00519_amd as pk
+    pk.load()
+    return pk
+
+
+def single2d(nx=40, ny=24):
+    rng = np.random.default_rng(3)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / nx
+    X, Y = np.meshgrid(x, y)
+    r = 1.0 + 0.3 * np.exp(-((X - 0.4) ** 2 + (Y - 0.25) ** 2) / 0.02)
+    p = 1.0 + 0.5 * np.exp(-((X - 0.6) ** 2 + (Y - 0.3) ** 2) / 0.01) + 0.01 * rng.random((ny, nx))
+    cfg = wl.base_config(dim=2, nx=nx, ny=ny, x1=1.0, y1=ny / nx, n_mat=1, gamma=[1.4],
+                         pinf=[0.0], bc=[wl.BC_REFLECTIVE, wl.BC_TRANSMISSIVE,
+                                         wl.BC_REFLECTIVE, wl.BC_OUTFLOW])
+    return dict(cfg=cfg, phi=np.full((ny, nx), 1.0), chi=np.zeros((ny, nx), np.int32),
+                W=np.array([r, 0.1 * np.sin(6 * Y), 0.05 * np.cos(3 * X), p])[None])
+
+
+def drifting_bubble(nx=96, ny=32):
+    w = wl.shock_bubble(nx=nx, ny=ny)
+    w["W"] = w["W"].copy()
+    w["W"][:, 1] += 0.3
+    w["W"][:, 2] += 0.1
+    w["cfg"]["bc"] = [wl.BC_TRANSMISSIVE] * 4
+    return w
+
+
+CASES = {
+    "single2d": (single2d, 3, 1),
+    "tube_1step": (lambda: wl.shock_tube_1d(n=120), 20, 1),
+    "tube_4steps": (lambda: wl.shock_tube_1d(n=120), 20, 4),
+    "drifting_bubble": (drifting_bubble, 15, 1),
+    "bubble_at_rest_2steps": (lambda: wl.shock_bubble(nx=128, ny=32), 20, 2),
+    "bubble_hit_3steps": (lambda: wl.shock_bubble(nx=128, ny=32), 60, 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_dot_product_against_tangent(pk, name):
+    make, n0, nsteps = CASES[name]
+    w = make()
+    o = oracle.Oracle(w["cfg"], tangent=True)
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    assert o.step(n0) == 0
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    s.step(n0)
+    g0 = o.get()
+    h0 = s.get()
+    for k in ("Q", "alpha", "phi", "chi"):
+        assert np.array_equal(g0[k], h0[k]), k
+    rng = np.random.default_rng(11)
+    dQ = rng.standard_normal(g0["Q"].shape) * np.abs(g0["Q"])
+    hc = (w["cfg"]["x1"] - w["cfg"]["x0"]) / w["cfg"]["nx"]
+    dphi = rng.standard_normal(g0["phi"].shape) * hc * (g0["phi"] < 7 * hc)
+    o.seed_state(dQ, dphi)
+    assert o.step(nsteps) == 0
+    tan = o.get_tangent()
+    s.step(nsteps, record=2)
+    g1 = o.get()
+    lQ = rng.standard_normal(g1["Q"].shape)
+    lphi = rng.standard_normal(g1["phi"].shape)
+    la = rng.standard_normal(g1["alpha"].shape)
+    lhs = np.sum(lQ * tan["Q"]) + np.sum(lphi * tan["phi"]) + np.sum(la * tan["alpha"])
+    if nsteps == 1:
+        aQ, aphi = s.adjoint_step(lQ, lphi, la)
+    else:
+        s.adjoint_step(lQ, lphi, la, out=False)
+        for _ in range(nsteps - 2):
+            s.adjoint_step(out=False)
+        aQ, aphi = s.adjoint_step()
+    rhs = np.sum(aQ * dQ) + np.sum(aphi * dphi)
+    rel = abs(lhs - rhs) / max(abs(lhs), 1e-300)
+    print(name, lhs, rhs, rel)
+    assert rel <= DOT_REL
+    # the reverse steps leave the forward state of the recorded run in place
+    h1 = s.get()
+    for k in ("Q", "alpha", "phi", "chi"):
+        assert np.array_equal(g1[k], h1[k]), k
+
+
+def test_tape_state_errors(pk):
+    w = wl.shock_tube_1d(n=80)
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    with pytest.raises(pk.MMError) as e:
+        s.adjoint_step(np.zeros((3, 3, 1, 80)), np.zeros((1, 80)))
+    assert e.value.status == 5
+    s.step(2, record=1)
+    n, rem, dt = s.tape()
+    assert (n, rem) == (2, 2) and np.all(dt > 0)
+    s.adjoint_step(out=False)
+    s.adjoint_step(out=False)
+    with pytest.raises(pk.MMError) as e:
+        s.adjoint_step()
+    assert e.value.status == 5
+    # a plain step ends the tape
+    s.step(1, record=1)
+    s.step(1)
+    assert s.tape()[0] == 0
+
+
+def tangent_gradient(prob, params, steps):
+    from paper_1704_00519_amd import adjoint as ad
+    w = prob.w
+    W, inflow = prob.fields(torch.tensor(params))
+    cfg = dict(w["cfg"])
+    cfg["inflow_W"] = [float(v) for v in inflow]
+    g = np.zeros(3)
+    for q in range(3):
+        e = torch.zeros(3, dtype=torch.float64)
+        e[q] = 1.0
+        _, (dW, dinf) = torch.autograd.functional.jvp(prob.fields, (torch.tensor(params),), (e,))
+        o = oracle.Oracle(cfg, tangent=True)
+        assert o.init_tangent(w["phi"], w["chi"], W.numpy(), dW.numpy()) == 0
+        o.set_inflow_tangent(dinf.numpy())
+        assert o.step(steps) == 0
+        _, gJ = ad.centroid(o.get()["alpha"], prob.x)
+        g[q] = np.sum(gJ * o.get_tangent()["alpha"])
+    return g
+
+
+def test_centroid_gradient_against_tangent_and_differences(pk):
+    from paper_1704_00519_amd import adjoint as ad
+    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32))
+    params = np.array([0.138, 3.15, 1.22])
+    steps, K = 70, 16  # past the first contact of the shock with the shell
+    p = torch.tensor(params, requires_grad=True)
+    J = ad.CentroidGradient.apply(p, prob, steps, K)
+    J.backward()
+    g = p.grad.numpy()
+    gt = tangent_gradient(prob, params, steps)
+    print("adjoint", g, "tangent", gt)
+    assert np.all(np.abs(g - gt) <= 1e-8 * np.abs(gt).max())
+    # central differences of the library, step sizes of the nominal run
+    _, s, _ = prob.run(params, steps, record=1)
+    dts = s.tape()[2]
+    for q in range(3):
+        h = 1e-6 * abs(params[q])
+        Jp = prob.run(params + h * np.eye(3)[q], steps, dts=dts)[0]
+        Jm = prob.run(params - h * np.eye(3)[q], steps, dts=dts)[0]
+        fd = (Jp - Jm) / (2 * h)
+        print("param", q, "fd", fd, "adjoint", g[q])
+        assert abs(fd - g[q]) <= 1e-4 * max(abs(g[q]), 1e-3 * np.abs(g).max())

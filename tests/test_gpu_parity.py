@@ -187,14 +187,6 @@ def test_step_before_init_is_state_error(pk):
     assert e.value.status == 5
 
 
-def test_adjoint_entry_point_reports_not_implemented(pk):
-    import ctypes as C
-    s = pk.Solver(wl.shock_tube_1d()["cfg"])
-    st = pk.load().mm_adjoint_step(s._h, None, None, None, None, 0)
-    assert st == 6
-    del C
-
-
 def hip_stream():
     import ctypes as C
     h = C.c_void_p()
@@ -251,3 +243,77 @@ def test_batched_first_instances_of_the_workload(pk):
         g = o.get()
         for k in ("Q", "alpha", "phi", "chi"):
             assert np.array_equal(g[k], got[q][k]), (q, k)
+
+
+def field_sums(Q, dim):
+    """Per material and component (rho, rho u, rho v, rho E) sums of Q and
+    of |Q|, exactly rounded (math.fsum); rho v is zero in 1D."""
+    M = Q.shape[0]
+    comps = [0, 1, 2, 3] if dim == 2 else [0, 1, 3]
+    s, a = np.zeros((M, 4)), np.zeros((M, 4))
+    for r in range(M):
+        for c, v in enumerate(comps):
+            s[r, v] = math.fsum(Q[r, c].ravel())
+            a[r, v] = math.fsum(np.abs(Q[r, c]).ravel())
+    return s, a
+
+
+def check_bookkeeping(dg, dg0, do, Q, dim, label):
+    """dg, dg0: library diagnostics now and right after init; do: the
+    oracle's diagnostics; Q: the oracle's state now."""
+    ref, absref = field_sums(Q, dim)
+    # sums of Q: fixed-order partial sums against the exactly rounded sum
+    assert np.all(np.abs(dg["sum_Q"] - ref) <= 1e-13 * np.maximum(absref, 1e-300)), label
+    # boundary and exchange totals are sums of many terms that largely cancel
+    # (a closed interface under uniform pressure exchanges nothing net), so
+    # their rounding is judged against the material's largest total
+    scale = np.maximum(absref.max(axis=1, keepdims=True), 1e-300)
+    # boundary inflow and exchange: the oracle's terms in another order
+    assert np.all(np.abs(dg["bnd_in"] - do["bnd"]) <= 1e-13 * scale), label
+    assert np.all(np.abs(dg["exch"] - do["xsum"]) <= 1e-13 * scale), label
+    # the balance of every material and component closes to 1e-13
+    bal = dg["sum_Q"] - dg0["sum_Q"] - dg["bnd_in"] - dg["exch"]
+    assert np.all(np.abs(bal) <= 1e-13 * scale), (label, bal)
+    # mass is never exchanged; momentum and energy exchange cancel over
+    # the materials (X^b = -X^a)
+    assert np.all(dg["exch"][:, 0] == 0.0), label
+    assert np.all(np.abs(dg["exch"].sum(axis=0)) <= 1e-13 * scale.max()), label
+
+
+@pytest.mark.parametrize("name,steps", [("tube", 200), ("triple_small", 60),
+                                        ("bubble_small", 80)])
+def test_conservation_bookkeeping(pk, name, steps):
+    w = CASES[name]()
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    dg0 = s.diag()
+    assert o.step(steps) == 0
+    s.step(steps)
+    dg = s.diag()
+    check_bookkeeping(dg, dg0, o.diag(), o.get()["Q"], w["cfg"]["dim"], name)
+    # reflective walls all round: no mass crosses the boundary
+    if name == "triple_small":
+        _, absref = field_sums(o.get()["Q"], 2)
+        assert np.all(np.abs(dg["bnd_in"][:, 0]) <= 1e-14 * absref[:, 0])
+    # fixed-order reductions: a second run reports identical values
+    s2 = pk.Solver(w["cfg"])
+    s2.init(w["phi"], w["chi"], w["W"])
+    s2.step(steps)
+    d2 = s2.diag()
+    for k in ("sum_Q", "bnd_in", "exch"):
+        assert np.array_equal(dg[k], d2[k]), k
+
+
+def test_batched_bookkeeping(pk):
+    steps = 30
+    insts = batch_instances(6, 40, 500, steps)
+    b = pk.Batch(insts)
+    b.init(insts)
+    d0 = b.diag()
+    b.step(steps)
+    d1 = b.diag()
+    for q, w in enumerate(insts):
+        o = oracle.run(w, steps=steps)
+        check_bookkeeping(d1[q], d0[q], o.diag(), o.get()["Q"], 1, f"instance {q}")
