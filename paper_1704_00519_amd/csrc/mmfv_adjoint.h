@@ -57,19 +57,27 @@ MMD void aadd(double* p, double x) {
   int k = cid(P, i, j);
 
 // ---------------------------------------------------------------------------
-// Mixing (Sec. 2.3.2).  Q^(s+1) = Q* + sum of exchanges; the exchanges are
-// recomputed from Q* and the geometry of the new level set.  In: A.lQ (the
-// adjoint of Q^(s+1), already copied into A.lQs); out: A.lQs, A.lal (new
-// geometry), A.lphis (through the normal directions).
+// Mixing (Sec. 2.3.2).  Q^(s+1) = Q* + sum of exchanges; sources, targets
+// and exchanges are recomputed from Q* (A.Qstar) and the new level set and
+// geometry (in B).  In: A.lQ (the adjoint of Q^(s+1), already copied into
+// A.lQs); out: A.lQs, A.lal (new geometry), A.lphis (through the normal
+// directions).
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ void k_a_mix(Params P, Bufs B, Adj A) {
   ADJ_CELL_LOOP
-  uint32_t stamp = (uint32_t)B.ctr[C_STAMP];
   double amix = P.amix;
+  // the sources of the forward mixing, from Q* and the new geometry
+  if (!B.cut[k] && A.occstar[k] == (uint8_t)(1u << B.chi[k])) return;
   for (int r = 0; r < P.M; r++) {
-    if (B.srcStamp[(size_t)r * P.NC + k] != stamp) continue;
     double as = alpha_at<D>(P, B, r, k);
+    if (!(as < amix) && B.chi[k] == r) continue;
+    if (!(as > 0.0)) {
+      bool nz = false;
+      for (int v = 0; v < 4; v++)
+        if (loadQ<D>(P, A.Qstar, A.occstar, r, v, k) != 0.0) nz = true;
+      if (!nz) continue;
+    }
     int kxp = cid(P, i + 1, j), kxm = cid(P, i - 1, j);
     double gx = lsv(B.phi, B.chi, r, kxp) - lsv(B.phi, B.chi, r, kxm);
     double gy = 0.0;

@@ -101,16 +101,30 @@ static void use_tape_dt(mm_ctx* c, int64_t n) {
   LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
 }
 
-// segment buffer: per step, ns stage snapshots then the step extras
+// Q* of a stage (after the update, before mixing) and its occupancy
+static size_t qstar_bytes(const Params& P) {
+  return align256((size_t)P.M * (P.dim + 2) * P.NC * 8) + align256((size_t)P.NC);
+}
+// segment buffer: per step, ns stage snapshots, ns copies of Q*, then the
+// step extras
 static size_t seg_step_bytes(const mm_ctx* c, int ns) {
   SnapLayout L = snap_layout(c->P);
-  return ns * L.bytes + L.ext_bytes;
+  return ns * (L.bytes + qstar_bytes(c->P)) + L.ext_bytes;
 }
 static char* seg_stage(mm_ctx* c, int64_t rel, int s, int ns) {
   return c->seg + rel * seg_step_bytes(c, ns) + s * snap_layout(c->P).bytes;
 }
+static char* seg_qstar(mm_ctx* c, int64_t rel, int s, int ns) {
+  return c->seg + rel * seg_step_bytes(c, ns) + ns * snap_layout(c->P).bytes +
+         s * qstar_bytes(c->P);
+}
+static uint8_t* seg_qstar_occ(mm_ctx* c, int64_t rel, int s, int ns) {
+  return (uint8_t*)(seg_qstar(c, rel, s, ns) +
+                    align256((size_t)c->P.M * (c->P.dim + 2) * c->P.NC * 8));
+}
 static char* seg_ext(mm_ctx* c, int64_t rel, int ns) {
-  return c->seg + rel * seg_step_bytes(c, ns) + ns * snap_layout(c->P).bytes;
+  return c->seg + rel * seg_step_bytes(c, ns) +
+         ns * (snap_layout(c->P).bytes + qstar_bytes(c->P));
 }
 
 static hipError_t grow(mm_ctx* c, char** p, size_t* cap, size_t need) {
@@ -138,7 +152,8 @@ static void load_segment(mm_ctx* c, int64_t n0, int64_t n1) {
     for (int s = 0; s < ns; s++) {
       int sidx = stage_src(s), didx = stage_dst(s, ns);
       snap_save(c, seg_stage(c, n - n0, s, ns), sidx);
-      stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
+      stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s], (double*)seg_qstar(c, n - n0, s, ns),
+               seg_qstar_occ(c, n - n0, s, ns));
       if (s == 0) ext_save(c, seg_ext(c, n - n0, ns));
     }
   }
@@ -159,13 +174,23 @@ static mm_status adj_alloc(mm_ctx* c) {
     e = dalloc(c, &(p), (n));                        \
   }
   AA(A.lQ, M * 4 * nc); AA(A.lQs, M * 4 * nc); AA(A.lQn, M * 4 * nc);
-  AA(A.lphi, nc); AA(A.lphis, nc); AA(A.lphin, nc);
-  AA(A.lW, M * 4 * nc);
-  AA(A.lal, M * nc); AA(A.lax, M * nc); AA(A.lay, M * nc); AA(A.lcx, M * nc); AA(A.lcy, M * nc);
+  AA(A.lphis, nc); AA(A.lphin, nc);
+  // one block, cleared at once each stage: lW, lal, lax, lay, lcx, lcy, lphi
+  double* blk = nullptr;
+  AA(blk, (M * 4 + 5 * M + 1) * nc);
+  if (e == hipSuccess) {
+    A.lW = blk;
+    A.lal = blk + M * 4 * nc;
+    A.lax = A.lal + M * nc;
+    A.lay = A.lax + M * nc;
+    A.lcx = A.lay + M * nc;
+    A.lcy = A.lcx + M * nc;
+    A.lphi = A.lcy + M * nc;
+  }
   AA(A.lvx, nc); AA(A.lvy, nc);
   AA(A.linflow, 4);
-  AA(A.Qstar, M * nv * nc); AA(A.occstar, nc);
   AA(A.lalpha, M * nc);
+  (void)nv;
   AA(c->ctr_save, C_N); AA(c->scal_save, 8); AA(c->cons_save, CONS_N);
 #undef AA
   if (e != hipSuccess) return fail(c, MM_ENOMEM, "adjoint buffers");
@@ -201,45 +226,37 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
   int nfx0 = (P.nx + 1) * P.ny, nfx1 = P.nx * (P.ny + 1);
   for (int s = ns - 1; s >= 0; s--) {
     int sidx = stage_src(s), didx = stage_dst(s, ns);
-    auto load = [&]() {
-      snap_load<D>(c, seg_stage(c, rel, s, ns), sidx);
-      if (s > 0) {
-        // time-n state in buffer 0, velocity and time-n level set of stage 0
-        SnapLayout L = snap_layout(P);
-        const char* s0 = seg_stage(c, rel, 0, ns);
-        cpy(c, c->B.Q[0], s0 + L.q, M * (P.dim + 2) * nc * 8);
-        cpy(c, c->B.occ[0], s0 + L.occ, nc);
-        ext_load(c, seg_ext(c, rel, ns));
-      }
-      use_tape_dt<D>(c, n);
-    };
-    // phase 1: the whole stage, then mixing and the new geometry
-    load();
-    stage_fluid<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
-    stage_levelset<D>(c, didx, 0, b[s], cc[s], true, A.Qstar, A.occstar);
+    // phase 1: mixing and the geometry of the new level set, from the
+    // snapshot that follows this stage and the stage's Q*
+    const char* next;
+    if (s + 1 < ns) next = seg_stage(c, rel, s + 1, ns);
+    else if (n + 1 == c->tape_n) next = c->final_snap;
+    else if (n + 1 < c->seg_n1) next = seg_stage(c, rel + 1, 0, ns);
+    else next = c->ckpt[(n + 1) / c->tape_K];
+    snap_load<D>(c, next, didx);
+    A.Qstar = (double*)seg_qstar(c, rel, s, ns);
+    A.occstar = seg_qstar_occ(c, rel, s, ns);
     cpy(c, A.lQs, A.lQ, M * 4 * nc * 8);
     cpy(c, A.lphis, A.lphi, nc * 8);
-    zero(c, A.lal, M * nc * 8);
+    zero(c, A.lal, 5 * M * nc * 8);  // lal, lax, lay, lcx, lcy
     LAUNCH(k_a_mix<D>, g, bl, P, c->B, A);
     if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
-    zero(c, A.lax, M * nc * 8);
-    zero(c, A.lay, M * nc * 8);
-    zero(c, A.lcx, M * nc * 8);
-    zero(c, A.lcy, M * nc * 8);
     LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphis);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
     LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
-    // phase 2: the stage up to the new level set (not committed)
-    load();
-    stage_fluid<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s]);
-    stage_levelset<D>(c, didx, 0, b[s], cc[s], false);
-    zero(c, A.lphi, nc * 8);
-    zero(c, A.lW, M * 4 * nc * 8);
-    zero(c, A.lal, M * nc * 8);
-    zero(c, A.lax, M * nc * 8);
-    zero(c, A.lay, M * nc * 8);
-    zero(c, A.lcx, M * nc * 8);
-    zero(c, A.lcy, M * nc * 8);
+    // phase 2: the stage's own states (no fluxes or update)
+    snap_load<D>(c, seg_stage(c, rel, s, ns), sidx);
+    if (s > 0) {
+      // time-n state in buffer 0, velocity and time-n level set of stage 0
+      SnapLayout L = snap_layout(P);
+      const char* s0 = seg_stage(c, rel, 0, ns);
+      cpy(c, c->B.Q[0], s0 + L.q, M * (P.dim + 2) * nc * 8);
+      cpy(c, c->B.occ[0], s0 + L.occ, nc);
+      ext_load(c, seg_ext(c, rel, ns));
+    }
+    use_tape_dt<D>(c, n);
+    stage_states<D>(c, s, sidx);
+    zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi
     LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
     LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);
     LAUNCH(k_a_flux<D>, lin_grid(nfx0), dim3(256), P, c->B, A, sidx, cc[s], 0);
@@ -325,6 +342,7 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
     if (c->D == 2) load_segment<2>(c, n0, n1);
     else load_segment<1>(c, n0, n1);
     c->seg_n0 = n0;
+    c->seg_n1 = n1;
   }
   if (c->D == 2) reverse_step<2>(c, n, dal != nullptr);
   else reverse_step<1>(c, n, dal != nullptr);

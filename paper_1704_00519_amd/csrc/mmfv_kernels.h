@@ -1841,20 +1841,34 @@ MMD void cons_boundary(const Params& P, const Bufs& B, const double* Qs, const u
 
 MMD int cons_rows(const Params& P) { return P.dim == 2 ? P.ny + P.nx : 1; }
 
-// Grid (nbb + ncb, M): workgroups x < nbb take 256 boundary rows/columns
-// each, the others CONS_CH cells each (exchange); y is the material.
-// Partials cpart[x][r][8]: net boundary inflow, exchange.
+// Grid (nbb + ncb, M): workgroups x < nbb take 128 boundary rows/columns
+// each (one thread per boundary face), the others CONS_CH cells each
+// (exchange); y is the material.  Partials cpart[x][r][8]: net boundary
+// inflow, exchange.
+constexpr int CONS_ROWS = 128;
 template <int D>
 __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, int nbb) {
   __shared__ double red[4 * 8];
+  __shared__ double face[CONS_ROWS][2][4];
   const double* Qs = B.Q[sidx];
   const uint8_t* os = B.occ[sidx];
   int r = blockIdx.y;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* part = B.cpart + ((size_t)blockIdx.x * P.M + r) * 8;
   if ((int)blockIdx.x < nbb) {
-    long q = (long)blockIdx.x * 256 + threadIdx.x;
-    if (q < cons_rows(P)) cons_boundary<D>(P, B, Qs, os, r, q, acc);
+    // thread t: face (side t & 1) of row/column q
+    int t = threadIdx.x, row = t >> 1, side = t & 1;
+    long q = (long)blockIdx.x * CONS_ROWS + row;
+    bool ok = q < cons_rows(P);
+    double f[4] = {0, 0, 0, 0};
+    int dir = q < P.ny ? 0 : 1;
+    if (ok) cons_face<D>(P, B, Qs, os, r, dir, dir == 0 ? (int)q : (int)(q - P.ny), side, f);
+    for (int v = 0; v < 4; v++) face[row][side][v] = f[v];
+    __syncthreads();
+    if (ok && side == 0) {
+      double l = dir == 0 ? B.scal[S_LX] : B.scal[S_LY];
+      for (int v = 0; v < 4; v++) acc[v] = l * (face[row][0][v] - face[row][1][v]);
+    }
   } else {
     long q0 = (long)(blockIdx.x - nbb) * CONS_CH, n = (long)P.nx * P.ny;
     bool any = false;
@@ -1877,15 +1891,19 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
     for (int v = 0; v < 8; v++) part[v] = acc[v];
 }
 
-// combine the partials of nblk workgroups in a fixed order and add the
-// stage totals, weighted by w, to the running sums (one thread per material
-// and quantity)
+// combine the partials of nblk workgroups in a fixed order (eight
+// interleaved running sums, then their sum) and add the stage totals,
+// weighted by w, to the running sums (one thread per material and quantity)
 __global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w) {
   int x = threadIdx.x;
   if (x >= P.M * 8) return;
   int r = x / 8, v = x % 8;
-  double a = 0.0;
-  for (int b = 0; b < nblk; b++) a += B.cpart[((size_t)b * P.M + r) * 8 + v];
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8)
+    for (int u = 0; u < 8; u++) s8[u] += B.cpart[((size_t)(b + u) * P.M + r) * 8 + v];
+  for (int u = 0; b + u < nblk; u++) s8[u] += B.cpart[((size_t)(b + u) * P.M + r) * 8 + v];
+  double a = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   if (v < 4)
     neumaier_add(&B.cons[(CONS_BND * MAXM + r) * 4 + v], &B.cons[(CONS_BNDC * MAXM + r) * 4 + v],
                  w * a);
