@@ -64,7 +64,7 @@ MMD void aadd(double* p, double x) {
 // directions).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_mix(Params P, Bufs B, Adj A) {
+__global__ void __launch_bounds__(256) k_a_mix(Params P, Bufs B, Adj A) {
   ADJ_CELL_LOOP
   double amix = P.amix;
   // the sources of the forward mixing, from Q* and the new geometry
@@ -212,7 +212,7 @@ __global__ void k_a_mix(Params P, Bufs B, Adj A) {
 }
 
 // adjoint of the step's output volume fractions (interior layout in lalpha)
-__global__ void k_a_add_alpha(Params P, Bufs B, Adj A) {
+__global__ void __launch_bounds__(256) k_a_add_alpha(Params P, Bufs B, Adj A) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
@@ -227,7 +227,7 @@ __global__ void k_a_add_alpha(Params P, Bufs B, Adj A) {
 // level set through the corner and centre values.  Out: lphi_out (atomics).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_geom(Params P, Bufs B, Adj A, double* lphi_out) {
+__global__ void __launch_bounds__(256) k_a_geom(Params P, Bufs B, Adj A, double* lphi_out) {
   ADJ_CELL_LOOP
   if (!B.cut[k]) return;
   const double* phi = B.phi;
@@ -317,7 +317,7 @@ __global__ void k_a_geom(Params P, Bufs B, Adj A, double* lphi_out) {
 // Frames of the level set: every frame cell is a copy of an inside cell, so
 // its adjoint is added to that cell (y sides first, the reverse of the fill).
 // ---------------------------------------------------------------------------
-__global__ void k_a_bc_ls_y(Params P, double* l) {
+__global__ void __launch_bounds__(256) k_a_bc_ls_y(Params P, double* l) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int ncol = P.nx + 2 * H;
   if (t >= ncol * 2 * H) return;
@@ -335,7 +335,7 @@ __global__ void k_a_bc_ls_y(Params P, double* l) {
   l[k] = 0.0;
   aadd(&l[ks], x);
 }
-__global__ void k_a_bc_ls_x(Params P, double* l) {
+__global__ void __launch_bounds__(256) k_a_bc_ls_x(Params P, double* l) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.ny * 2 * H) return;
   int j = t / (2 * H), q = t % (2 * H);
@@ -391,7 +391,7 @@ MMD void a_hj(const Params& P, const Bufs& B, const Adj& A, int r, int i, int j,
 }
 
 template <int D>
-__global__ void k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef) {
+__global__ void __launch_bounds__(256) k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef) {
   ADJ_CELL_LOOP
   double lp = A.lphis[k];
   if (B.dls[k] > 3) {
@@ -440,7 +440,7 @@ __global__ void k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef) {
 // ---------------------------------------------------------------------------
 // RK stage update Q* = b Q^n + c (Q^(s) + rhs): lQn += b lQs, lQ = c lQs.
 // ---------------------------------------------------------------------------
-__global__ void k_a_update(Params P, Adj A, double bcoef, double ccoef) {
+__global__ void __launch_bounds__(256) k_a_update(Params P, Adj A, double bcoef, double ccoef) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
@@ -549,7 +549,7 @@ MMD void a_face(const Params& P, const Bufs& B, const Adj& A, const double* Q,
 }
 
 template <int D>
-__global__ void k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef, int dir) {
+__global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef, int dir) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int nfx = dir == 0 ? P.nx + 1 : P.nx, nfy = dir == 0 ? P.ny : P.ny + 1;
   if (t >= nfx * nfy) return;
@@ -599,7 +599,7 @@ __global__ void k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef, int di
 // band cells, then the extension sweeps in reverse.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_vfill(Params P, Bufs B, Adj A, int sidx) {
+__global__ void __launch_bounds__(256) k_a_vfill(Params P, Bufs B, Adj A, int sidx) {
   ADJ_CELL_LOOP
   if (B.dls[k] > RV || B.vit[k] != 0) return;
   double lx = A.lvx[k], ly = A.lvy[k];
@@ -615,7 +615,7 @@ __global__ void k_a_vfill(Params P, Bufs B, Adj A, int sidx) {
 }
 
 template <int D>
-__global__ void k_a_vext(Params P, Bufs B, Adj A, int sweep) {
+__global__ void __launch_bounds__(256) k_a_vext(Params P, Bufs B, Adj A, int sweep) {
   ADJ_CELL_LOOP
   if (B.vit[k] != sweep + 2) return;
   double lox = A.lvx[k], loy = A.lvy[k];
@@ -672,7 +672,7 @@ __global__ void k_a_vext(Params P, Bufs B, Adj A, int sweep) {
 // interface velocity S_M n.  Out: A.lW of the pair, A.lcx / A.lcy of a.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_iface(Params P, Bufs B, Adj A, int sidx, double ccoef, int stage0) {
+__global__ void __launch_bounds__(256) k_a_iface(Params P, Bufs B, Adj A, int sidx, double ccoef, int stage0) {
   ADJ_CELL_LOOP
   if (!B.cut[k]) return;
   unsigned b = B.xs[k];
@@ -751,7 +751,7 @@ __global__ void k_a_iface(Params P, Bufs B, Adj A, int sidx, double ccoef, int s
 // negated at a reflective side) of a state next to the boundary, or the
 // fixed inflow state.  y sides first, the reverse of the fill.
 // ---------------------------------------------------------------------------
-__global__ void k_a_bc_W_y(Params P, Bufs B, Adj A) {
+__global__ void __launch_bounds__(256) k_a_bc_W_y(Params P, Bufs B, Adj A) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int ncol = P.nx + 2 * H;
   if (t >= ncol * 2 * H * P.M) return;
@@ -784,7 +784,7 @@ __global__ void k_a_bc_W_y(Params P, Bufs B, Adj A) {
   aadd(&A4(P, A.lW, r, 2, ks), l[2] * sy);
   aadd(&A4(P, A.lW, r, 3, ks), l[3]);
 }
-__global__ void k_a_bc_W_x(Params P, Bufs B, Adj A) {
+__global__ void __launch_bounds__(256) k_a_bc_W_x(Params P, Bufs B, Adj A) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.ny * 2 * H * P.M) return;
   int r = t / (P.ny * 2 * H);
@@ -913,7 +913,7 @@ __global__ void __launch_bounds__(256) k_a_ext(Params P, Bufs B, Adj A, int sidx
 // Real states W = prim(Q / alpha): to Q^(s) and, in cut cells, to alpha.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_real(Params P, Bufs B, Adj A, int sidx) {
+__global__ void __launch_bounds__(256) k_a_real(Params P, Bufs B, Adj A, int sidx) {
   ADJ_CELL_LOOP
   const double* Q = B.Q[sidx];
   const uint8_t* occ = B.occ[sidx];
@@ -955,7 +955,7 @@ __global__ void k_a_real(Params P, Bufs B, Adj A, int sidx) {
 // [ny][nx]) and the padded adjoint buffers.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_a_unpack(Params P, Adj A, const double* lQ, const double* lphi,
+__global__ void __launch_bounds__(256) k_a_unpack(Params P, Adj A, const double* lQ, const double* lphi,
                            const double* lalpha) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -976,7 +976,7 @@ __global__ void k_a_unpack(Params P, Adj A, const double* lQ, const double* lphi
   if (lphi) A.lphi[k] = lphi[q];
 }
 template <int D>
-__global__ void k_a_pack(Params P, Adj A, double* lQ, double* lphi) {
+__global__ void __launch_bounds__(256) k_a_pack(Params P, Adj A, double* lQ, double* lphi) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
@@ -991,7 +991,7 @@ __global__ void k_a_pack(Params P, Adj A, double* lQ, double* lphi) {
 }
 // end of a step: the time-n adjoints collected from later stages join those
 // of the stage-0 input
-__global__ void k_a_finish(Params P, Adj A) {
+__global__ void __launch_bounds__(256) k_a_finish(Params P, Adj A) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;

@@ -40,6 +40,49 @@ static void cpy(mm_ctx* c, void* dst, const void* src, size_t n) {
   (void)hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, c->stream);
 }
 
+// Several device-to-device copies in one launch (grid y = copy index);
+// every buffer starts 8-byte aligned.
+constexpr int MAXCOPY = 16;
+struct CopyList {
+  const char* src[MAXCOPY];
+  char* dst[MAXCOPY];
+  size_t bytes[MAXCOPY];
+  int n;
+};
+__global__ void __launch_bounds__(256) k_copy_multi(CopyList L) {
+  int e = blockIdx.y;
+  if (e >= L.n) return;
+  size_t words = L.bytes[e] / 8, tail = L.bytes[e] % 8;
+  const double* s8 = (const double*)L.src[e];
+  double* d8 = (double*)L.dst[e];
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+       w += (size_t)gridDim.x * blockDim.x)
+    d8[w] = s8[w];
+  if (blockIdx.x == 0 && threadIdx.x < tail)
+    L.dst[e][words * 8 + threadIdx.x] = L.src[e][words * 8 + threadIdx.x];
+}
+struct Copies {
+  CopyList L;
+  size_t maxw = 0;
+  Copies() { L.n = 0; }
+  void add(void* dst, const void* src, size_t bytes) {
+    L.src[L.n] = (const char*)src;
+    L.dst[L.n] = (char*)dst;
+    L.bytes[L.n] = bytes;
+    L.n++;
+    if (bytes / 8 > maxw) maxw = bytes / 8;
+  }
+  void run(mm_ctx* c) {
+    if (!L.n) return;
+    unsigned gx = (unsigned)((maxw + 255) / 256);
+    if (gx > 512) gx = 512;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_copy_multi, dim3(gx, L.n), dim3(256), 0, c->stream, L);
+    L.n = 0;
+    maxw = 0;
+  }
+};
+
 static void geo_ptrs(mm_ctx* c, double* g[5]) {
   g[0] = c->B.al; g[1] = c->B.ax; g[2] = c->B.ay; g[3] = c->B.cx; g[4] = c->B.cy;
 }
@@ -48,31 +91,36 @@ static void snap_save(mm_ctx* c, char* dst, int sidx) {
   const Params& P = c->P;
   SnapLayout L = snap_layout(P);
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
-  cpy(c, dst + L.q, c->B.Q[sidx], M * nv * nc * 8);
-  cpy(c, dst + L.phi, c->B.phi, nc * 8);
+  Copies cp;
+  cp.add(dst + L.q, c->B.Q[sidx], M * nv * nc * 8);
+  cp.add(dst + L.phi, c->B.phi, nc * 8);
   double* g[5];
   geo_ptrs(c, g);
-  for (int q = 0; q < 5; q++) cpy(c, dst + L.geo + q * M * nc * 8, g[q], M * nc * 8);
-  cpy(c, dst + L.occ, c->B.occ[sidx], nc);
-  cpy(c, dst + L.chi, c->B.chi, nc);
-  cpy(c, dst + L.vfc, c->B.vfc, nc * 2);
+  for (int q = 0; q < 5; q++) cp.add(dst + L.geo + q * M * nc * 8, g[q], M * nc * 8);
+  cp.add(dst + L.occ, c->B.occ[sidx], nc);
+  cp.add(dst + L.chi, c->B.chi, nc);
+  cp.add(dst + L.vfc, c->B.vfc, nc * 2);
+  cp.run(c);
 }
 
-// restore a stage snapshot into buffer sidx and rebuild the classification
-// and the tile list of that stage
+// restore a stage snapshot into buffer sidx (with optional extra copies in
+// the same launch) and rebuild the classification and the tile list
 template <int D>
-static void snap_load(mm_ctx* c, const char* src, int sidx) {
+static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = nullptr) {
   const Params& P = c->P;
   SnapLayout L = snap_layout(P);
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
-  cpy(c, c->B.Q[sidx], src + L.q, M * nv * nc * 8);
-  cpy(c, c->B.phi, src + L.phi, nc * 8);
+  Copies own;
+  Copies& cp = extra ? *extra : own;
+  cp.add(c->B.Q[sidx], src + L.q, M * nv * nc * 8);
+  cp.add(c->B.phi, src + L.phi, nc * 8);
   double* g[5];
   geo_ptrs(c, g);
-  for (int q = 0; q < 5; q++) cpy(c, g[q], src + L.geo + q * M * nc * 8, M * nc * 8);
-  cpy(c, c->B.occ[sidx], src + L.occ, nc);
-  cpy(c, c->B.chi, src + L.chi, nc);
-  cpy(c, c->B.vfc, src + L.vfc, nc * 2);
+  for (int q = 0; q < 5; q++) cp.add(g[q], src + L.geo + q * M * nc * 8, M * nc * 8);
+  cp.add(c->B.occ[sidx], src + L.occ, nc);
+  cp.add(c->B.chi, src + L.chi, nc);
+  cp.add(c->B.vfc, src + L.vfc, nc * 2);
+  cp.run(c);
   classify<D>(c);
   build_tiles<D>(c, sidx, 0);
 }
@@ -80,18 +128,20 @@ static void snap_load(mm_ctx* c, const char* src, int sidx) {
 static void ext_save(mm_ctx* c, char* dst) {
   SnapLayout L = snap_layout(c->P);
   size_t nc = c->P.NC;
-  cpy(c, dst + L.vx, c->B.vx, nc * 8);
-  cpy(c, dst + L.vy, c->B.vy, nc * 8);
-  cpy(c, dst + L.phin, c->B.phin, nc * 8);
-  cpy(c, dst + L.chin, c->B.chin, nc);
+  Copies cp;
+  cp.add(dst + L.vx, c->B.vx, nc * 8);
+  cp.add(dst + L.vy, c->B.vy, nc * 8);
+  cp.add(dst + L.phin, c->B.phin, nc * 8);
+  cp.add(dst + L.chin, c->B.chin, nc);
+  cp.run(c);
 }
-static void ext_load(mm_ctx* c, const char* src) {
+static void ext_add(mm_ctx* c, Copies& cp, const char* src) {
   SnapLayout L = snap_layout(c->P);
   size_t nc = c->P.NC;
-  cpy(c, c->B.vx, src + L.vx, nc * 8);
-  cpy(c, c->B.vy, src + L.vy, nc * 8);
-  cpy(c, c->B.phin, src + L.phin, nc * 8);
-  cpy(c, c->B.chin, src + L.chin, nc);
+  cp.add(c->B.vx, src + L.vx, nc * 8);
+  cp.add(c->B.vy, src + L.vy, nc * 8);
+  cp.add(c->B.phin, src + L.phin, nc * 8);
+  cp.add(c->B.chin, src + L.chin, nc);
 }
 
 // fixed step size of recorded step n for the recomputation
@@ -244,16 +294,17 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphis);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
     LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
-    // phase 2: the stage's own states (no fluxes or update)
-    snap_load<D>(c, seg_stage(c, rel, s, ns), sidx);
+    // phase 2: the stage's own states (no fluxes or update); for s > 0 also
+    // the time-n state in buffer 0, the velocity and time-n level set
+    Copies cp;
     if (s > 0) {
-      // time-n state in buffer 0, velocity and time-n level set of stage 0
       SnapLayout L = snap_layout(P);
       const char* s0 = seg_stage(c, rel, 0, ns);
-      cpy(c, c->B.Q[0], s0 + L.q, M * (P.dim + 2) * nc * 8);
-      cpy(c, c->B.occ[0], s0 + L.occ, nc);
-      ext_load(c, seg_ext(c, rel, ns));
+      cp.add(c->B.Q[0], s0 + L.q, M * (P.dim + 2) * nc * 8);
+      cp.add(c->B.occ[0], s0 + L.occ, nc);
+      ext_add(c, cp, seg_ext(c, rel, ns));
     }
+    snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp);
     use_tape_dt<D>(c, n);
     stage_states<D>(c, s, sidx);
     zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi

@@ -242,7 +242,8 @@ extern "C" mm_status mm_batch_init_state(mm_batch* b, const double* phi, const i
 }
 
 static void batch_launch_direct(mm_batch* b, int n_steps, int threads) {
-  hipLaunchKernelGGL(k_batch1d, dim3(b->n), dim3(threads), 0, b->stream,
+  auto kern = threads <= 256 ? k_batch1d<256> : (threads <= 512 ? k_batch1d<512> : k_batch1d<1024>);
+  hipLaunchKernelGGL(kern, dim3(b->n), dim3(threads), 0, b->stream,
                      (const Params*)b->dP, (const Bufs*)b->dB, n_steps, b->rk);
 }
 

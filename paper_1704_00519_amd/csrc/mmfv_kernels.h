@@ -2058,7 +2058,10 @@ MMD void batch_load(const Params* Pa, const Bufs* Ba, BatchSmem& sm) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(1024)
+// MAXT: the largest workgroup the variant runs with (its register budget
+// follows from it: 128 registers at 1024 threads, 256 at 512, 512 at 256)
+template <int MAXT>
+__global__ void __launch_bounds__(MAXT)
 k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
   __shared__ BatchSmem sm;
   batch_load(Pa, Ba, sm);
