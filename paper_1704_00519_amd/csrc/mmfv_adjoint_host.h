@@ -42,7 +42,7 @@ static void cpy(mm_ctx* c, void* dst, const void* src, size_t n) {
 
 // Several device-to-device copies in one launch (grid y = copy index);
 // every buffer starts 8-byte aligned.
-constexpr int MAXCOPY = 16;
+constexpr int MAXCOPY = 24;
 struct CopyList {
   const char* src[MAXCOPY];
   char* dst[MAXCOPY];
@@ -151,11 +151,27 @@ static void use_tape_dt(mm_ctx* c, int64_t n) {
   LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
 }
 
-// Q* of a stage (after the update, before mixing) and its occupancy
-static size_t qstar_bytes(const Params& P) {
-  return align256((size_t)P.M * (P.dim + 2) * P.NC * 8) + align256((size_t)P.NC);
+// Per stage, besides the snapshot: Q* (after the update, before mixing)
+// with its occupancy, and the states the stage read: primitive states W and
+// their validity marks, the ghost queue with its length, the velocity marks
+struct StageExtra {
+  size_t q, occ, W, Wit, glist, nghost, vit, bytes;
+};
+static StageExtra stage_extra(const Params& P) {
+  StageExtra E;
+  size_t nc = P.NC, M = P.M, at = 0;
+  E.q = at; at = align256(at + M * (P.dim + 2) * nc * 8);
+  E.occ = at; at = align256(at + nc);
+  E.W = at; at = align256(at + M * 4 * nc * 8);
+  E.Wit = at; at = align256(at + M * nc);
+  E.glist = at; at = align256(at + M * nc * 4);
+  E.nghost = at; at = align256(at + 8);
+  E.vit = at; at = align256(at + nc);
+  E.bytes = at;
+  return E;
 }
-// segment buffer: per step, ns stage snapshots, ns copies of Q*, then the
+static size_t qstar_bytes(const Params& P) { return stage_extra(P).bytes; }
+// segment buffer: per step, ns stage snapshots, ns stage extras, then the
 // step extras
 static size_t seg_step_bytes(const mm_ctx* c, int ns) {
   SnapLayout L = snap_layout(c->P);
@@ -169,8 +185,19 @@ static char* seg_qstar(mm_ctx* c, int64_t rel, int s, int ns) {
          s * qstar_bytes(c->P);
 }
 static uint8_t* seg_qstar_occ(mm_ctx* c, int64_t rel, int s, int ns) {
-  return (uint8_t*)(seg_qstar(c, rel, s, ns) +
-                    align256((size_t)c->P.M * (c->P.dim + 2) * c->P.NC * 8));
+  return (uint8_t*)(seg_qstar(c, rel, s, ns) + stage_extra(c->P).occ);
+}
+// the states read by stage s, kept / restored in the same layout
+static void states_copies(mm_ctx* c, Copies& cp, char* blk, bool save) {
+  StageExtra E = stage_extra(c->P);
+  size_t nc = c->P.NC, M = c->P.M;
+  void* dev[5] = {c->B.W, c->B.Wit, c->B.glist, &c->B.ctr[C_NGHOST], c->B.vit};
+  size_t off[5] = {E.W, E.Wit, E.glist, E.nghost, E.vit};
+  size_t n[5] = {M * 4 * nc * 8, M * nc, M * nc * 4, 8, nc};
+  for (int q = 0; q < 5; q++) {
+    if (save) cp.add(blk + off[q], dev[q], n[q]);
+    else cp.add(dev[q], blk + off[q], n[q]);
+  }
 }
 static char* seg_ext(mm_ctx* c, int64_t rel, int ns) {
   return c->seg + rel * seg_step_bytes(c, ns) +
@@ -204,6 +231,9 @@ static void load_segment(mm_ctx* c, int64_t n0, int64_t n1) {
       snap_save(c, seg_stage(c, n - n0, s, ns), sidx);
       stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s], (double*)seg_qstar(c, n - n0, s, ns),
                seg_qstar_occ(c, n - n0, s, ns));
+      Copies cp;
+      states_copies(c, cp, seg_qstar(c, n - n0, s, ns), true);
+      cp.run(c);
       if (s == 0) ext_save(c, seg_ext(c, n - n0, ns));
     }
   }
@@ -294,8 +324,9 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphis);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
     LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
-    // phase 2: the stage's own states (no fluxes or update); for s > 0 also
-    // the time-n state in buffer 0, the velocity and time-n level set
+    // phase 2: the stage's input with the states it read (kept by the
+    // segment recompute); for s > 0 also the time-n state in buffer 0, the
+    // velocity and the time-n level set
     Copies cp;
     if (s > 0) {
       SnapLayout L = snap_layout(P);
@@ -304,9 +335,9 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
       cp.add(c->B.occ[0], s0 + L.occ, nc);
       ext_add(c, cp, seg_ext(c, rel, ns));
     }
+    states_copies(c, cp, seg_qstar(c, rel, s, ns), false);
     snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp);
     use_tape_dt<D>(c, n);
-    stage_states<D>(c, s, sidx);
     zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi
     LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
     LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);

@@ -1,8 +1,10 @@
 """Write the oracle's results at the full step counts of the workloads.
 
 Runs the CPU oracle only (no GPU code) and stores, per workload, an .npz
-with: the time reached and step count (or the step at which the run stopped
-with a non-physical state), the full indicator field chi, per
+with: the time reached and step count (a run that meets a non-physical state
+stops; the stored state is then the one after the last complete step, and
+the status and cell of the failing step are kept), the full indicator field
+chi, per
 (material, component) sums of Q and |Q|, and the complete state (Q, alpha,
 phi) at a fixed sample of cells: every cell within one cell of an interface
 at the end, plus a seeded random sample.  The GPU parity test recomputes the
@@ -55,6 +57,9 @@ def main():
     assert o.init(w["phi"], w["chi"], w["W"]) == 0
     t0 = time.time()
     done, status, chunk = 0, 0, 50
+    # a step that meets a non-physical state stops part-way; the stored state
+    # is the one after the last complete step
+    g, d = o.get(), o.diag()
     while done < steps:
         n = min(chunk, steps - done)
         for _ in range(n):
@@ -62,11 +67,10 @@ def main():
             if status:
                 break
             done += 1
+            g, d = o.get(), o.diag()
         print(f"{name}: {done}/{steps} steps, {time.time() - t0:.0f}s", flush=True)
         if status:
             break
-    g = o.get()
-    d = o.diag()
     Q = g["Q"]
     cells = sample_cells(g["chi"])
     M, nv = Q.shape[:2]
