@@ -149,7 +149,9 @@ mm_status mm_set_dt(mm_ctx *ctx, double dt);
  * its checkpoint when first needed.  The forward state after the recorded
  * run and the diagnostics are left as they were.  Pointers are host or
  * device per ptr_kind.  MM_ESTATE without a recorded step to reverse.
- * Synchronises the stream. */
+ * Synchronises the stream when host outputs are requested; otherwise the
+ * work is queued on the context's stream (host input arrays are copied
+ * before the call returns). */
 mm_status mm_adjoint_step(mm_ctx *ctx, const double *lamQ_in,
                           const double *lamPhi_in, const double *lamAlpha_in,
                           double *lamQ_out, double *lamPhi_out,

@@ -106,7 +106,8 @@ static void snap_save(mm_ctx* c, char* dst, int sidx) {
 // restore a stage snapshot into buffer sidx (with optional extra copies in
 // the same launch) and rebuild the classification and the tile list
 template <int D>
-static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = nullptr) {
+static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = nullptr,
+                      bool tiles = true) {
   const Params& P = c->P;
   SnapLayout L = snap_layout(P);
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
@@ -122,7 +123,7 @@ static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = null
   cp.add(c->B.vfc, src + L.vfc, nc * 2);
   cp.run(c);
   classify<D>(c);
-  build_tiles<D>(c, sidx, 0);
+  if (tiles) build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
 }
 
 static void ext_save(mm_ctx* c, char* dst) {
@@ -313,7 +314,7 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     else if (n + 1 == c->tape_n) next = c->final_snap;
     else if (n + 1 < c->seg_n1) next = seg_stage(c, rel + 1, 0, ns);
     else next = c->ckpt[(n + 1) / c->tape_K];
-    snap_load<D>(c, next, didx);
+    snap_load<D>(c, next, didx, nullptr, false);
     A.Qstar = (double*)seg_qstar(c, rel, s, ns);
     A.occstar = seg_qstar_occ(c, rel, s, ns);
     cpy(c, A.lQs, A.lQ, M * 4 * nc * 8);
@@ -336,7 +337,7 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
       ext_add(c, cp, seg_ext(c, rel, ns));
     }
     states_copies(c, cp, seg_qstar(c, rel, s, ns), false);
-    snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp);
+    snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp, false);
     use_tape_dt<D>(c, n);
     zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi
     LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
@@ -409,6 +410,8 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
     dQ = lamQ_in ? q0 : nullptr;
     dphi = lamPhi_in ? p0 : nullptr;
     dal = lamAlpha_in ? a0 : nullptr;
+    // the caller's arrays may be reused once this call returns
+    if (lamQ_in || lamPhi_in || lamAlpha_in) HIP_OK(c, hipStreamSynchronize(c->stream));
   }
   dim3 g = cell_grid(c), bl = cell_block(c);
   if (dQ || dphi || dal) {
@@ -453,7 +456,9 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
   cpy(c, c->B.scal, c->scal_save, 8 * sizeof(double));
   cpy(c, c->B.cons, c->cons_save, CONS_N * sizeof(double));
   HIP_OK(c, hipGetLastError());
-  HIP_OK(c, hipStreamSynchronize(c->stream));
+  // host outputs need the work done; otherwise the next call may queue
+  // behind this one
+  if (ptr_kind == MM_HOST && (lamQ_out || lamPhi_out)) HIP_OK(c, hipStreamSynchronize(c->stream));
   return MM_OK;
 }
 
