@@ -67,9 +67,10 @@ template <int D>
 __global__ void __launch_bounds__(256) k_a_mix(Params P, Bufs B, Adj A) {
   ADJ_CELL_LOOP
   double amix = P.amix;
-  // the sources of the forward mixing, from Q* and the new geometry
+  // the sources of the forward mixing, from Q* and the new geometry; one
+  // material per grid slice z
   if (!B.cut[k] && A.occstar[k] == (uint8_t)(1u << B.chi[k])) return;
-  for (int r = 0; r < P.M; r++) {
+  for (int r = blockIdx.z; r == (int)blockIdx.z; r++) {
     double as = alpha_at<D>(P, B, r, k);
     if (!(as < amix) && B.chi[k] == r) continue;
     if (!(as > 0.0)) {
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(256) k_a_geom(Params P, Bufs B, Adj A, double*
   }
   for (int r = 0; r < P.M; r++)
     if ((z >> r) & 1) lam[r] = 0.0;
-  for (int r = 0; r < P.M; r++) {
+  for (int r = blockIdx.z; r == (int)blockIdx.z; r++) {  // one material per grid slice z
     if (D == 1) {
       int kl = cid(P, i - 1, j), kr = cid(P, i + 1, j);
       if (lam[r] == 0.0) continue;
@@ -917,7 +918,7 @@ __global__ void __launch_bounds__(256) k_a_real(Params P, Bufs B, Adj A, int sid
   ADJ_CELL_LOOP
   const double* Q = B.Q[sidx];
   const uint8_t* occ = B.occ[sidx];
-  for (int r = 0; r < P.M; r++) {
+  for (int r = blockIdx.z; r == (int)blockIdx.z; r++) {  // one material per grid slice z
     bool real = (B.dcut[k] > 7 && B.chi[k] == r) || B.Wit[(size_t)r * P.NC + k] == 1;
     if (!real) continue;
     double lw[4];

@@ -298,6 +298,7 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
   double b[3], cc[3], w[3];
   int ns = rk_coefs(c->cfg, b, cc, w);
   dim3 g = cell_grid(c), bl = cell_block(c);
+  dim3 gm(g.x, g.y, P.M);  // one material per slice
   Adj& A = c->A;
   int64_t rel = n - c->seg_n0;
   zero(c, A.lQn, M * 4 * nc * 8);
@@ -320,9 +321,9 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     cpy(c, A.lQs, A.lQ, M * 4 * nc * 8);
     cpy(c, A.lphis, A.lphi, nc * 8);
     zero(c, A.lal, 5 * M * nc * 8);  // lal, lax, lay, lcx, lcy
-    LAUNCH(k_a_mix<D>, g, bl, P, c->B, A);
+    LAUNCH(k_a_mix<D>, gm, bl, P, c->B, A);
     if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
-    LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphis);
+    LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphis);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
     LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
     // phase 2: the stage's input with the states it read (kept by the
@@ -354,8 +355,8 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
     for (int sw = P.kext + 3; sw >= 0; sw--)
       LAUNCH(k_a_ext<D>, dim3(256), dim3(256), P, c->B, A, sidx, sw);
-    LAUNCH(k_a_real<D>, g, bl, P, c->B, A, sidx);
-    LAUNCH(k_a_geom<D>, g, bl, P, c->B, A, A.lphi);
+    LAUNCH(k_a_real<D>, gm, bl, P, c->B, A, sidx);
+    LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphi);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
     LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
   }
