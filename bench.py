@@ -25,6 +25,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_flux_bulk2_triple_point_896x384_hbm_counters.md")
+KERNEL_SOURCES = ("paper_1704_00519_amd/csrc/mmfv_kernels.h", "paper_1704_00519_amd/csrc/mmfv_math.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a plain copy), if
+    it was taken on the current kernel sources; else None."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    h = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
+    if not t or not h:
+        return None
+    d = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        d.update(open(os.path.join(ROOT, f), "rb").read())
+    return int(t.group(1)) if d.hexdigest() == h.group(1) else None
 
 
 def cpu_baseline(workload, steps):
@@ -135,6 +157,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -179,7 +203,8 @@ def main():
     bulk_s = prof["bulk_ms"] * 1e-3
     achieved = prof["bulk_bytes"] / bulk_s / 1e9 if bulk_s > 0 else 0.0
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(),
                     kernel="k_flux_bulk2",
                     launches=prof["bulk_launches"],
                     avg_launch_us=round(prof["bulk_ms"] * 1e3 / max(1, prof["bulk_launches"]), 2),
@@ -196,6 +221,14 @@ def main():
                            t_start=d0["t"], t_end=d1["t"],
                            wall_s=round(wall, 3)),
                roofline=roofline)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8,
+                                         "launches": 3}
     if not args.no_batch:
         out["batched"] = batched(pk, wl, stream, args.batch_steps)
     if not args.no_adjoint:
