@@ -9,9 +9,12 @@ initial data already resident on the GPU.  The unit of work is one active
 material-cell RK-substep update (a cell/material pair with alpha > 0,
 updated in one stage), counted on the device.
 
-Prints one JSON line.  Also reports the dominant kernel against the HBM
-roofline (HIP events around its launches on the stream it runs on) and the
-CPU oracle's rate on a bounded sample of the same workload.
+Prints one JSON line.  Also reports the dominant kernel (the bulk
+flux/update kernel) against its binding roof, the FP64 vector peak, with its
+HBM fraction beside it (HIP events around its launches on the stream it runs
+on), the same kernel on an 8192 x 2048 grid whose working set must stream
+from HBM, the batched form, the adjoint, and the CPU oracle's rate on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -25,6 +28,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak of the MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops
+# (fused multiply-add) x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# FP64 operations (add, subtract, multiply, divide, square root) of one bulk
+# 2D update, mean over the three SSP-RK3 stages: 2 faces x (8 WENO5 + 1 HLLC)
+# + the cell's primitive state + 4 RK combinations.  Counted from the
+# library's own point-wise templates by tests/opcount/op_count.cpp (a CPU
+# test keeps the two in step).
+FLOPS_PER_BULK_UPDATE_2D = 1320.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_flux_bulk2_triple_point_896x384_hbm_counters.md")
 KERNEL_SOURCES = ("paper_1704_00519_amd/csrc/mmfv_kernels.h", "paper_1704_00519_amd/csrc/mmfv_math.h")
 
@@ -47,6 +59,49 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         d.update(open(os.path.join(ROOT, f), "rb").read())
     return int(t.group(1)) if d.hexdigest() == h.group(1) else None
+
+
+def bulk_roofline(prof):
+    """Roofline of the bulk flux/update kernel from the library's event
+    timings: FP64 operations per second against the FP64 vector peak (the
+    binding roof: about 1.3k operations per update against 85 bytes), and
+    the algorithmic bytes per second against the HBM peak beside it."""
+    n = max(1, prof["bulk_launches"])
+    bulk_s = prof["bulk_ms"] * 1e-3
+    upd = prof["bulk_updates"]
+    tflops = FLOPS_PER_BULK_UPDATE_2D * upd / bulk_s / 1e12 if bulk_s > 0 else 0.0
+    gbs = prof["bulk_bytes"] / bulk_s / 1e9 if bulk_s > 0 else 0.0
+    return dict(bound="alu", achieved=round(tflops, 3), peak=FP64_VECTOR_PEAK_TFLOPS,
+                unit="TFLOP/s", frac=round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+                traffic=None, kernel="k_flux_bulk2",
+                flops_per_update=FLOPS_PER_BULK_UPDATE_2D,
+                updates_per_launch=upd / n,
+                hbm=dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(gbs / HBM_PEAK_GBS, 4)),
+                launches=prof["bulk_launches"],
+                avg_launch_us=round(prof["bulk_ms"] * 1e3 / n, 2),
+                bytes_per_launch=prof["bulk_bytes"] / n)
+
+
+def hbm_resident_leg(pk, wl, stream, nx=8192, ny=2048, warm=3, steps=10):
+    """The bulk kernel on the shock-bubble problem at 8192 x 2048 (working
+    set of several GB, far beyond the 256 MB last-level cache), where its
+    algorithmic bytes have to come from HBM."""
+    import torch
+    w = wl.shock_bubble(nx=nx, ny=ny)
+    s = pk.Solver(w["cfg"], stream=stream.cuda_stream)
+    s.init(w["phi"], w["chi"], w["W"])
+    del w
+    s.step(warm)
+    s.set_profiling(True)
+    s.step(steps)
+    prof = s.profile()
+    s.set_profiling(False)
+    torch.cuda.synchronize()
+    s.close()
+    r = bulk_roofline(prof)
+    r.update(workload=f"shock_bubble_{nx}x{ny}", steps=steps, warmup=warm)
+    return r
 
 
 def cpu_baseline(workload, steps):
@@ -157,6 +212,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -200,17 +256,10 @@ def main():
     prof = s.profile()
     s.set_profiling(False)
 
-    bulk_s = prof["bulk_ms"] * 1e-3
-    achieved = prof["bulk_bytes"] / bulk_s / 1e9 if bulk_s > 0 else 0.0
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(),
-                    kernel="k_flux_bulk2",
-                    launches=prof["bulk_launches"],
-                    avg_launch_us=round(prof["bulk_ms"] * 1e3 / max(1, prof["bulk_launches"]), 2),
-                    bytes_per_launch=prof["bulk_bytes"] / max(1, prof["bulk_launches"]),
-                    share_of_step=round(prof["bulk_ms"] / prof_steps / (ms / args.steps), 4),
-                    profiled_steps=prof_steps)
+    roofline = bulk_roofline(prof)
+    roofline["traffic"] = measured_traffic()
+    roofline["share_of_step"] = round(prof["bulk_ms"] / prof_steps / (ms / args.steps), 4)
+    roofline["profiled_steps"] = prof_steps
     out = dict(metric="material-cell RK-substep updates/sec (plain)",
                value=value, unit="updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms / args.steps,
@@ -229,6 +278,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8,
                                          "launches": 3}
+    if not args.no_hbm_leg:
+        out["roofline_hbm_resident"] = hbm_resident_leg(pk, wl, stream)
     if not args.no_batch:
         out["batched"] = batched(pk, wl, stream, args.batch_steps)
     if not args.no_adjoint:

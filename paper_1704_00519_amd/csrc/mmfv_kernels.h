@@ -1095,20 +1095,88 @@ __global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
 // Bulk update: cells with no cut cell within three cells and only their own
 // material present.  There alpha = A = 1 and the exchange term vanishes
 // (Sec. 2.4: the single-material block degenerates to standard finite
-// volumes).  The primitive states of a (TX+6) x (TY+6) tile are staged in LDS
-// once; each face flux is computed once and shared by its two cells.
-constexpr int TX = 32, TY = 8;
-__global__ void __launch_bounds__(256)
+// volumes).  A workgroup of NT threads updates a BX x BY tile: the primitive
+// states of the tile and a 3-cell frame are staged in LDS once; the x-face
+// fluxes are computed (each once), shared through LDS by the face's two
+// cells and reduced into per-cell sums, then the y-faces reuse the same LDS.
+template <int BX, int BY>
+struct BulkTile {
+  static constexpr int WX = BX + 6, WY = BY + 6;
+  static constexpr int NFX = (BX + 1) * BY, NFY = BX * (BY + 1);
+  static constexpr int NFM = NFX > NFY ? NFX : NFY;
+  double W[4][WY][WX];
+  double F[4][NFM];
+  uint8_t chi[WY][WX];
+  uint8_t bulk[BY + 2][BX + 2];
+};
+
+// flux across face (fi, fj) of the tile in direction dir (0: the left face of
+// tile cell (fi, fj), 1: its bottom face), rotated back to (rho, x, y, E)
+// momentum order; false when neither cell of the face is a bulk cell
+template <int BX, int BY>
+MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, int dir,
+                   int fi, int fj, double G[4]) {
+  // the two cells of the face in tile coordinates: (fi-1, fj) | (fi, fj)
+  // or (fi, fj-1) | (fi, fj); the bulk marks are offset by one
+  bool need = dir == 0 ? (sm.bulk[fj + 1][fi] || sm.bulk[fj + 1][fi + 1])
+                       : (sm.bulk[fj][fi + 1] || sm.bulk[fj + 1][fi + 1]);
+  if (!need) return false;
+  int m = dir == 0 ? (sm.bulk[fj + 1][fi + 1] ? sm.chi[fj + 3][fi + 3] : sm.chi[fj + 3][fi + 2])
+                   : (sm.bulk[fj + 1][fi + 1] ? sm.chi[fj + 3][fi + 3] : sm.chi[fj + 2][fi + 3]);
+  // stencil cell q (0..5: cells fi-3 .. fi+2 along dir) of component v in
+  // face-normal order (rho, normal velocity, tangential velocity, p), read
+  // from LDS where it is used so that few values stay live in registers
+  int bx = dir == 0 ? fi : fi + 3, by = dir == 0 ? fj + 3 : fj;
+  int sx = dir == 0 ? 1 : 0, sy = dir == 0 ? 0 : 1;
+  int vn = dir == 0 ? 1 : 2, vt = dir == 0 ? 2 : 1;
+  auto c = [&](int q, int v) -> double {
+    int comp = v == 1 ? vn : v == 2 ? vt : v;
+    return sm.W[comp][by + q * sy][bx + q * sx];
+  };
+  double pinf = P.pinf[m];
+  Prim L, R;
+  L.r = weno5(c(0, 0), c(1, 0), c(2, 0), c(3, 0), c(4, 0));
+  L.u = weno5(c(0, 1), c(1, 1), c(2, 1), c(3, 1), c(4, 1));
+  L.v = weno5(c(0, 2), c(1, 2), c(2, 2), c(3, 2), c(4, 2));
+  L.p = weno5(c(0, 3), c(1, 3), c(2, 3), c(3, 3), c(4, 3));
+  R.r = weno5(c(5, 0), c(4, 0), c(3, 0), c(2, 0), c(1, 0));
+  R.u = weno5(c(5, 1), c(4, 1), c(3, 1), c(2, 1), c(1, 1));
+  R.v = weno5(c(5, 2), c(4, 2), c(3, 2), c(2, 2), c(1, 2));
+  R.p = weno5(c(5, 3), c(4, 3), c(3, 3), c(2, 3), c(1, 3));
+  if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + pinf > 0.0) || !(R.p + pinf > 0.0)) {
+    atomicAdd(&B.ctr[C_POSFIX], 1ull);
+    L.r = c(2, 0); L.u = c(2, 1); L.v = c(2, 2); L.p = c(2, 3);
+    R.r = c(3, 0); R.u = c(3, 1); R.v = c(3, 2); R.p = c(3, 3);
+  }
+  double Gf[4];
+  hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], Gf);
+  G[0] = Gf[0];
+  G[1] = dir == 0 ? Gf[1] : Gf[2];
+  G[2] = dir == 0 ? Gf[2] : Gf[1];
+  G[3] = Gf[3];
+  return true;
+}
+
+// Tile of the bulk kernel: 28 x 16 cells (896 = 32 x 28 and 384 = 24 x 16
+// tile the 896 x 384 grid exactly), 512 threads so that both face sets
+// (29 x 16 and 28 x 17) take one pass; 40.7 KB of LDS.  The register budget
+// is left to the compiler: a tighter one spills to scratch, and the spill
+// traffic outweighs the extra waves.
+constexpr int BULK_BX = 28, BULK_BY = 16, BULK_NT = 512;
+
+template <int BX, int BY, int NT>
+__global__ void __launch_bounds__(NT)
 k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
              double ccoef, int stage0) {
-  __shared__ double sW[4][TY + 6][TX + 6];
-  __shared__ double sF[4][(TX + 1) * TY + TX * (TY + 1)];
-  __shared__ uint8_t sChi[TY + 6][TX + 6];
-  __shared__ uint8_t sBulk[TY + 2][TX + 2];
-  int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  using T = BulkTile<BX, BY>;
+  constexpr int WX = T::WX, WY = T::WY, NFX = T::NFX, NFY = T::NFY;
+  static_assert(NT >= BX * BY, "one thread per tile cell");
+  __shared__ T sm;
+  int tid = threadIdx.x;
+  int tx = tid % BX, ty = tid / BX;
+  int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
   int i = i0 + tx, j = j0 + ty;
-  bool inb = i < P.nx && j < P.ny;
+  bool inb = tid < BX * BY && i < P.nx && j < P.ny;
   int k = inb ? cid(P, i, j) : 0;
   bool isb = inb && B.bulk[k];
   int nb = __syncthreads_count(isb);
@@ -1118,121 +1186,115 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
     atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nb);
   }
   const double* Qs = B.Q[sidx];
+  const double* Qn = B.Q[nidx];
   // stage the tile + 3-cell frame: pure cells from Q, frame cells outside the
-  // domain from the boundary states
-  for (int q = tid; q < (TX + 6) * (TY + 6); q += 256) {
-    int ci = i0 - 3 + q % (TX + 6), cj = j0 - 3 + q / (TX + 6);
-    double r_ = 1.0, u_ = 0.0, v_ = 0.0, p_ = 1.0;
-    uint8_t ch = 0;
-    if (ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H) {
-      int kk = cid(P, ci, cj);
-      ch = B.chi[kk];
-      if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny) {
-        size_t o = (size_t)ch * 4 * P.NC + kk;
-        bool has = (B.occ[sidx][kk] >> ch) & 1;
-        double U0 = has ? Qs[o] / 1.0 : 0.0, U1 = has ? Qs[o + P.NC] / 1.0 : 0.0,
-               U2 = has ? Qs[o + 2 * (size_t)P.NC] / 1.0 : 0.0,
-               U3 = has ? Qs[o + 3 * (size_t)P.NC] / 1.0 : 0.0;
-        Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[ch], P.pinf[ch]);
-        r_ = w.r; u_ = w.u; v_ = w.v; p_ = w.p;
-      } else {
-        size_t o = (size_t)ch * 4 * P.NC + kk;
-        r_ = B.W[o];
-        u_ = B.W[o + P.NC];
-        v_ = B.W[o + 2 * (size_t)P.NC];
-        p_ = B.W[o + 3 * (size_t)P.NC];
-      }
-    }
-    int lx = q % (TX + 6), ly = q / (TX + 6);
-    sW[0][ly][lx] = r_;
-    sW[1][ly][lx] = u_;
-    sW[2][ly][lx] = v_;
-    sW[3][ly][lx] = p_;
-    sChi[ly][lx] = ch;
+  // domain from the boundary states.  Every load of the thread's cells (and
+  // of its own cell's Q^(s), Q^n for the update) is issued before any value
+  // is used, so that their latencies overlap.
+  constexpr int NS = (WX * WY + NT - 1) / NT;
+  constexpr int NB = ((BX + 2) * (BY + 2) + NT - 1) / NT;
+  int kk[NS];
+  uint8_t ch[NS], oc[NS], bf[NB];
+  bool inr[NS], ind[NS];
+#pragma unroll
+  for (int n = 0; n < NS; n++) {
+    int q = tid + n * NT;
+    int ci = i0 - 3 + q % WX, cj = j0 - 3 + q / WX;
+    inr[n] = q < WX * WY && ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H;
+    ind[n] = inr[n] && ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny;
+    kk[n] = inr[n] ? cid(P, ci, cj) : 0;
+    ch[n] = inr[n] ? B.chi[kk[n]] : 0;
+    oc[n] = ind[n] ? B.occ[sidx][kk[n]] : 0;
   }
-  for (int q = tid; q < (TX + 2) * (TY + 2); q += 256) {
-    int ci = i0 - 1 + q % (TX + 2), cj = j0 - 1 + q / (TX + 2);
-    uint8_t bf = 0;
-    if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny) bf = B.bulk[cid(P, ci, cj)];
-    sBulk[q / (TX + 2)][q % (TX + 2)] = bf;
+#pragma unroll
+  for (int n = 0; n < NB; n++) {
+    int q = tid + n * NT;
+    int ci = i0 - 1 + q % (BX + 2), cj = j0 - 1 + q / (BX + 2);
+    bool in = q < (BX + 2) * (BY + 2) && ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny;
+    bf[n] = in ? B.bulk[cid(P, ci, cj)] : 0;
+  }
+  int m = isb ? B.chi[k] : 0;
+  double U[NS][4];
+#pragma unroll
+  for (int n = 0; n < NS; n++) {
+    size_t o = (size_t)ch[n] * 4 * P.NC + kk[n];
+    bool has = (oc[n] >> ch[n]) & 1;
+    if (ind[n]) {
+      for (int v = 0; v < 4; v++) U[n][v] = has ? Qs[o + (size_t)v * P.NC] / 1.0 : 0.0;
+    } else if (inr[n]) {
+      for (int v = 0; v < 4; v++) U[n][v] = B.W[o + (size_t)v * P.NC];
+    } else {
+      U[n][0] = 1.0; U[n][1] = 0.0; U[n][2] = 0.0; U[n][3] = 1.0;
+    }
+  }
+  size_t om = (size_t)m * 4 * P.NC + k;
+  double qs_own[4], qn_own[4];
+  for (int v = 0; v < 4; v++) {
+    qs_own[v] = isb ? Qs[om + (size_t)v * P.NC] : 0.0;
+    qn_own[v] = isb && !stage0 ? Qn[om + (size_t)v * P.NC] : 0.0;
+  }
+#pragma unroll
+  for (int n = 0; n < NS; n++) {
+    int q = tid + n * NT;
+    if (q >= WX * WY) continue;
+    double r_ = U[n][0], u_ = U[n][1], v_ = U[n][2], p_ = U[n][3];
+    if (ind[n]) {
+      Prim w = prim_from_U(U[n][0], U[n][1], U[n][2], U[n][3], P.gamma[ch[n]], P.pinf[ch[n]]);
+      r_ = w.r; u_ = w.u; v_ = w.v; p_ = w.p;
+    }
+    int lx = q % WX, ly = q / WX;
+    sm.W[0][ly][lx] = r_;
+    sm.W[1][ly][lx] = u_;
+    sm.W[2][ly][lx] = v_;
+    sm.W[3][ly][lx] = p_;
+    sm.chi[ly][lx] = ch[n];
+  }
+#pragma unroll
+  for (int n = 0; n < NB; n++) {
+    int q = tid + n * NT;
+    if (q < (BX + 2) * (BY + 2)) sm.bulk[q / (BX + 2)][q % (BX + 2)] = bf[n];
   }
   __syncthreads();
-  // faces: x-faces f < (TX+1)*TY (left face of tile cell (fi, fj)), then
-  // y-faces (bottom face of tile cell (fi, fj))
-  const int NFX = (TX + 1) * TY, NF = NFX + TX * (TY + 1);
-  for (int f = tid; f < NF; f += 256) {
-    int dir, fi, fj;
-    if (f < NFX) {
-      dir = 0;
-      fi = f % (TX + 1);
-      fj = f / (TX + 1);
-    } else {
-      dir = 1;
-      fi = (f - NFX) % TX;
-      fj = (f - NFX) / TX;
-    }
-    // the two cells of the face in tile coordinates: (fi-1, fj) | (fi, fj)
-    // or (fi, fj-1) | (fi, fj); sBulk is offset by one
-    bool need = dir == 0 ? (sBulk[fj + 1][fi] || sBulk[fj + 1][fi + 1])
-                         : (sBulk[fj][fi + 1] || sBulk[fj + 1][fi + 1]);
-    if (!need) continue;
-    int m = dir == 0 ? (sBulk[fj + 1][fi + 1] ? sChi[fj + 3][fi + 3] : sChi[fj + 3][fi + 2])
-                     : (sBulk[fj + 1][fi + 1] ? sChi[fj + 3][fi + 3] : sChi[fj + 2][fi + 3]);
-    double c[6][4];
-    for (int q = 0; q < 6; q++) {
-      int lx = dir == 0 ? fi + q : fi + 3;      // cells fi-3 .. fi+2 (+3 offset)
-      int ly = dir == 0 ? fj + 3 : fj + q;
-      c[q][0] = sW[0][ly][lx];
-      c[q][1] = dir == 0 ? sW[1][ly][lx] : sW[2][ly][lx];
-      c[q][2] = dir == 0 ? sW[2][ly][lx] : sW[1][ly][lx];
-      c[q][3] = sW[3][ly][lx];
-    }
-    double pinf = P.pinf[m];
-    Prim L, R;
-    L.r = weno5(c[0][0], c[1][0], c[2][0], c[3][0], c[4][0]);
-    L.u = weno5(c[0][1], c[1][1], c[2][1], c[3][1], c[4][1]);
-    L.v = weno5(c[0][2], c[1][2], c[2][2], c[3][2], c[4][2]);
-    L.p = weno5(c[0][3], c[1][3], c[2][3], c[3][3], c[4][3]);
-    R.r = weno5(c[5][0], c[4][0], c[3][0], c[2][0], c[1][0]);
-    R.u = weno5(c[5][1], c[4][1], c[3][1], c[2][1], c[1][1]);
-    R.v = weno5(c[5][2], c[4][2], c[3][2], c[2][2], c[1][2]);
-    R.p = weno5(c[5][3], c[4][3], c[3][3], c[2][3], c[1][3]);
-    if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + pinf > 0.0) || !(R.p + pinf > 0.0)) {
-      atomicAdd(&B.ctr[C_POSFIX], 1ull);
-      L.r = c[2][0]; L.u = c[2][1]; L.v = c[2][2]; L.p = c[2][3];
-      R.r = c[3][0]; R.u = c[3][1]; R.v = c[3][2]; R.p = c[3][3];
-    }
+  double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+  // x-faces: face f is the left face of tile cell (f % (BX+1), f / (BX+1))
+#pragma unroll 1
+  for (int f = tid; f < NFX; f += NT) {
     double G[4];
-    hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], G);
-    sF[0][f] = G[0];
-    sF[1][f] = dir == 0 ? G[1] : G[2];
-    sF[2][f] = dir == 0 ? G[2] : G[1];
-    sF[3][f] = G[3];
+    if (bulk_face<BX, BY>(P, B, sm, 0, f % (BX + 1), f / (BX + 1), G))
+      for (int v = 0; v < 4; v++) sm.F[v][f] = G[v];
+  }
+  __syncthreads();
+  double acc[4];
+  if (isb) {
+    int fl = ty * (BX + 1) + tx, fr = fl + 1;
+    for (int v = 0; v < 4; v++) acc[v] = lx * (sm.F[v][fl] - sm.F[v][fr]);
+  }
+  __syncthreads();
+  // y-faces: face f is the bottom face of tile cell (f % BX, f / BX)
+#pragma unroll 1
+  for (int f = tid; f < NFY; f += NT) {
+    double G[4];
+    if (bulk_face<BX, BY>(P, B, sm, 1, f % BX, f / BX, G))
+      for (int v = 0; v < 4; v++) sm.F[v][f] = G[v];
   }
   __syncthreads();
   if (!isb) return;
-  int m = sChi[ty + 3][tx + 3];
   {
     Prim w;
-    w.r = sW[0][ty + 3][tx + 3];
-    w.u = sW[1][ty + 3][tx + 3];
-    w.v = sW[2][ty + 3][tx + 3];
-    w.p = sW[3][ty + 3][tx + 3];
+    w.r = sm.W[0][ty + 3][tx + 3];
+    w.u = sm.W[1][ty + 3][tx + 3];
+    w.v = sm.W[2][ty + 3][tx + 3];
+    w.p = sm.W[3][ty + 3][tx + 3];
     if (nonphys(w, P.pinf[m])) flag_error(P, B, i, j);
   }
-  double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
-  int fl = ty * (TX + 1) + tx, fr = fl + 1;
-  int fb = NFX + ty * TX + tx, ft = fb + TX;
-  size_t o = (size_t)m * 4 * P.NC + k;
-  const double* Qn = B.Q[nidx];
+  int fb = ty * BX + tx, ft = fb + BX;
   double* Qd = B.Q[didx];
   for (int v = 0; v < 4; v++) {
-    double rhs = lx * (sF[v][fl] - sF[v][fr]);
-    rhs = rhs + ly * (sF[v][fb] - sF[v][ft]);
+    double rhs = acc[v] + ly * (sm.F[v][fb] - sm.F[v][ft]);
     rhs = rhs + lv * 0.0;
-    double qs = Qs[o + (size_t)v * P.NC];
-    double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
-    Qd[o + (size_t)v * P.NC] = x;
+    double qs = qs_own[v];
+    double x = stage0 ? (qs + rhs) : (bcoef * qn_own[v] + ccoef * (qs + rhs));
+    Qd[om + (size_t)v * P.NC] = x;
   }
   B.occ[didx][k] = (uint8_t)(1u << m);
 }

@@ -336,8 +336,9 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   if (s == 0) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
   prof_mark(c);
   if (D == 2)
-    LAUNCH(k_flux_bulk2, dim3((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY), dim3(TX, TY), P,
-           c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
+    LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT>),
+           dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BY - 1) / BULK_BY), dim3(BULK_NT),
+           P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
   else
     LAUNCH(k_flux_bulk1, dim3((P.nx + T1 - 1) / T1), dim3(T1), P, c->B, sidx, nidx, didx, b,
            cc, s == 0 ? 1 : 0);

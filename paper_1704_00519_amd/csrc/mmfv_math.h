@@ -9,7 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef MMD
 #define MMD __device__ __forceinline__
+#endif
 
 namespace mmfv {
 
