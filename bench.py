@@ -37,21 +37,22 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # library's own point-wise templates by tests/opcount/op_count.cpp (a CPU
 # test keeps the two in step).
 FLOPS_PER_BULK_UPDATE_2D = 1320.0
-COUNTERS = os.path.join(ROOT, "profiles", "k_flux_bulk2_triple_point_896x384_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles",
+                        "k_flux_bulk2_counters_triple_point_896x384_shock_bubble_8192x2048.md")
 KERNEL_SOURCES = ("paper_1704_00519_amd/csrc/mmfv_kernels.h", "paper_1704_00519_amd/csrc/mmfv_math.h")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a plain copy), if
-    it was taken on the current kernel sources; else None."""
+def measured_traffic(grid="896x384"):
+    """HBM bytes per launch of the dominant kernel on the given grid from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on
+    a plain copy), if it was taken on the current kernel sources; else None."""
     import hashlib
     import re
     try:
         text = open(COUNTERS).read()
     except OSError:
         return None
-    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    t = re.search(r"traffic_bytes_per_launch_%s: (\d+)" % grid, text)
     h = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
     if not t or not h:
         return None
@@ -100,6 +101,7 @@ def hbm_resident_leg(pk, wl, stream, nx=8192, ny=2048, warm=3, steps=10):
     torch.cuda.synchronize()
     s.close()
     r = bulk_roofline(prof)
+    r["traffic"] = measured_traffic(f"{nx}x{ny}")
     r.update(workload=f"shock_bubble_{nx}x{ny}", steps=steps, warmup=warm)
     return r
 

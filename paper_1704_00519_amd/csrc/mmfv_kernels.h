@@ -61,6 +61,27 @@ MMD bool errored(const Bufs& B) { return B.ctr[C_ERR] != NO_ERR; }
 MMD void flag_error(const Params& P, const Bufs& B, int i, int j) {
   atomicMin(&B.ctr[C_ERR], (unsigned long long)j * P.nx + i);
 }
+// Counters bumped by many lanes at once go through one atomic per wavefront:
+// the values of the lanes active at the call are summed with ballots (v < 16)
+// and the lowest active lane adds the sum.
+MMD void wave_count(unsigned long long* c, unsigned v) {
+  unsigned long long act = __ballot(1);
+  unsigned long long sum = 0;
+  for (int b = 0; b < 4; b++) sum += (unsigned long long)__popcll(__ballot((v >> b) & 1)) << b;
+  if (sum && __lane_id() == __ffsll(act) - 1) atomicAdd(c, sum);
+}
+// slot in a device queue for each active lane with take set: one atomic per
+// wavefront reserves the wave's slots; returns the lane's slot (or -1)
+MMD long long wave_slot(unsigned long long* c, bool take) {
+  unsigned long long act = __ballot(1), m = __ballot(take);
+  int leader = __ffsll(act) - 1, lane = __lane_id();
+  unsigned long long base = 0;
+  if (m && lane == leader) base = atomicAdd(c, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  if (!take) return -1;
+  unsigned long long below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+  return (long long)(base + __popcll(below));
+}
 MMD bool nonphys(const Prim& w, double pinf) {
   return !(w.r > 0.0) || !(w.p + pinf > 0.0) || !isfinite(w.u) ||
          !isfinite(w.v) || !isfinite(w.r) || !isfinite(w.p);
@@ -402,11 +423,10 @@ MMD void b_near_col(const Params& P, const Bufs& B, int i, int j) {
   if (B.glist) {
     // queue the (cell, material) pairs of the ghost band that have no state
     for (int r = 0; r < P.M; r++) {
-      if (!((b >> r) & 1)) continue;
-      if (!B.cut[k] && B.chi[k] == r) continue;
-      if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
-      unsigned long long at = atomicAdd(&B.ctr[C_NGHOST], 1ull);
-      B.glist[at] = k * 8 + r;
+      bool take = (b >> r) & 1;
+      take = take && !(!B.cut[k] && B.chi[k] == r) && B.Wit[(size_t)r * P.NC + k] == 0;
+      long long at = wave_slot(&B.ctr[C_NGHOST], take);
+      if (take) B.glist[at] = k * 8 + r;
     }
   }
 }
@@ -789,7 +809,7 @@ MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int sta
   Prim Wa = Wget<D>(P, B, Q, occ, a, i, j, va);
   Prim Wb = Wget<D>(P, B, Q, occ, bb, i, j, vb);
   if (!va || !vb) {
-    atomicAdd(&B.ctr[C_IFSKIP], 1ull);
+    wave_count(&B.ctr[C_IFSKIP], 1);
     return;
   }
   double nrm = sqrt(cxa * cxa + cya * cya);
@@ -983,7 +1003,7 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
     if (!vc[q]) ok = false;
   }
   if (!vc[2] || !vc[3]) {
-    if (count) atomicAdd(&B.ctr[C_FLUXSKIP], 1ull);
+    wave_count(&B.ctr[C_FLUXSKIP], count ? 1 : 0);
     F[0] = F[1] = F[2] = F[3] = 0.0;
     return;
   }
@@ -1004,7 +1024,7 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
       ok = false;
   }
   if (!ok) {
-    if (count) atomicAdd(&B.ctr[C_POSFIX], 1ull);
+    wave_count(&B.ctr[C_POSFIX], count ? 1 : 0);
     L.r = Wc[2].r; L.u = nrm(Wc[2]); L.v = tng(Wc[2]); L.p = Wc[2].p;
     R.r = Wc[3].r; R.u = nrm(Wc[3]); R.v = tng(Wc[3]); R.p = Wc[3].p;
   }
@@ -1040,7 +1060,7 @@ MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int
   unsigned long long nact = 0;
   for (int r = 0; r < P.M; r++)
     if (alpha_at<D>(P, B, r, k) > 0.0) nact++;
-  if (nact) atomicAdd(&B.ctr[C_UPD], nact);
+  wave_count(&B.ctr[C_UPD], (unsigned)nact);
   for (int r = 0; r < P.M; r++) {
     double Fl[4] = {0, 0, 0, 0}, Fr[4] = {0, 0, 0, 0}, Fb[4] = {0, 0, 0, 0},
            Ft[4] = {0, 0, 0, 0};
@@ -1490,7 +1510,8 @@ __global__ void k_ls_commit(Params P, Bufs B) {
 // gather that applies them in place
 // ---------------------------------------------------------------------------
 template <int D>
-MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp) {
+MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp,
+                int r0, int r1) {
   int k = cid(P, i, j);
   (void)k;
   if (errored(B)) return;
@@ -1499,7 +1520,7 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   uint8_t own = (uint8_t)(1u << B.chi[k]);
   if (!B.cut[k] && occ[k] == own) return;
   double amix = P.amix;
-  for (int r = 0; r < P.M; r++) {
+  for (int r = r0; r < r1; r++) {
     double as = alpha_at<D>(P, B, r, k);
     if (!(as < amix) && B.chi[k] == r) continue;
     if (!(as > 0.0)) {
@@ -1508,7 +1529,7 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
         if (loadQ<D>(P, Q, occ, r, v, k) != 0.0) nz = true;
       if (!nz) continue;
     }
-    atomicAdd(&B.ctr[C_MIXSRC], 1ull);
+    wave_count(&B.ctr[C_MIXSRC], 1);
     double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
     double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
     int sx = gx > 0.0 ? 1 : (gx < 0.0 ? -1 : 0);
@@ -1555,7 +1576,7 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
           }
         }
       if (bt < 0) {
-        atomicAdd(&B.ctr[C_STRANDED], 1ull);
+        wave_count(&B.ctr[C_STRANDED], 1);
         continue;
       }
       tk[0] = bt;
@@ -1593,7 +1614,7 @@ __global__ void k_mix1(Params P, Bufs B, int didx) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
-  b_mix1<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP]);
+  b_mix1<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP], 0, P.M);
 }
 
 template <int D>
@@ -1723,73 +1744,73 @@ __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* ch
 template <int D>
 __global__ void __launch_bounds__(256) k_flux_list(Params P, Bufs B, int sidx, int nidx,
                                                    int didx, double bcoef, double ccoef) {
+  // threads are (cell, material, face): the aperture-scaled flux of one
+  // material across one face of one listed cell goes through LDS to the
+  // thread that combines the faces of (cell, material) into its update
   constexpr int FPC = D == 2 ? 4 : 2;  // faces per cell
-  constexpr int CPB = 256 / FPC;       // cells per block
-  __shared__ double sF[CPB][FPC][MAXM][4];
-  int tid = threadIdx.x, c = tid / FPC, f = tid % FPC;
+  __shared__ double sF[256][4];
+  __shared__ unsigned sOcc[256];
+  const int tpc = FPC * P.M, cpb = 256 / tpc;  // threads and cells per block
+  int tid = threadIdx.x, c = tid / tpc, rem = tid % tpc, r = rem / FPC, f = rem % FPC;
   int nb = (int)B.ctr[C_NBAND];
   if (errored(B)) return;
   const double* Qs = B.Q[sidx];
   const uint8_t* os = B.occ[sidx];
-  for (int base = blockIdx.x * CPB; base < nb; base += gridDim.x * CPB) {
+  for (int base = blockIdx.x * cpb; base < nb; base += gridDim.x * cpb) {
     int idx = base + c;
-    bool act = idx < nb;
+    bool act = c < cpb && idx < nb;
     int k = act ? B.blist[idx] : 0;
     int i = k % P.NX - H, j = k / P.NX - P.HY;
+    if (tid < cpb) sOcc[tid] = 0;
     if (act) {
-      for (int r = 0; r < P.M; r++) {
-        double A;
-        int fi, fj, dir;
-        bool count;
-        if (f == 0) { A = apx<D>(P, B, r, i - 1, j); fi = i - 1; fj = j; dir = 0; count = i == 0; }
-        else if (f == 1) { A = apx<D>(P, B, r, i, j); fi = i; fj = j; dir = 0; count = true; }
-        else if (f == 2) { A = apy(P, B, r, i, j - 1); fi = i; fj = j - 1; dir = 1; count = j == 0; }
-        else { A = apy(P, B, r, i, j); fi = i; fj = j; dir = 1; count = true; }
-        double F[4] = {0.0, 0.0, 0.0, 0.0};
-        if (A > 0.0) face_flux<D>(P, B, Qs, os, r, fi, fj, dir, count, F);
-        for (int v = 0; v < 4; v++) sF[c][f][r][v] = A > 0.0 ? A * F[v] : 0.0;
-      }
+      double A;
+      int fi, fj, dir;
+      bool count;
+      if (f == 0) { A = apx<D>(P, B, r, i - 1, j); fi = i - 1; fj = j; dir = 0; count = i == 0; }
+      else if (f == 1) { A = apx<D>(P, B, r, i, j); fi = i; fj = j; dir = 0; count = true; }
+      else if (f == 2) { A = apy(P, B, r, i, j - 1); fi = i; fj = j - 1; dir = 1; count = j == 0; }
+      else { A = apy(P, B, r, i, j); fi = i; fj = j; dir = 1; count = true; }
+      double F[4] = {0.0, 0.0, 0.0, 0.0};
+      if (A > 0.0) face_flux<D>(P, B, Qs, os, r, fi, fj, dir, count, F);
+      for (int v = 0; v < 4; v++) sF[tid][v] = A > 0.0 ? A * F[v] : 0.0;
     }
     __syncthreads();
     if (act && f == 0) {
       const double* Qn = B.Q[nidx];
       const uint8_t* on = B.occ[nidx];
       double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
-      if (!B.cut[k]) {
+      // non-cut cells are real cells of their material: checked by that
+      // material's thread
+      if (!B.cut[k] && r == B.chi[k]) {
         bool vd;
-        int r = B.chi[k];
         Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
         if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
       }
-      unsigned long long nact = 0;
-      unsigned occ = 0;
-      for (int r = 0; r < P.M; r++) {
-        if (alpha_at<D>(P, B, r, k) > 0.0) nact++;
-        double out[4];
-        bool nz = false;
-        for (int v = 0; v < 4; v++) {
-          if (D == 1 && v == 2) {
-            out[v] = 0.0;
-            continue;
-          }
-          double rhs = lx * (sF[c][0][r][v] - sF[c][1][r][v]);
-          if (D == 2) rhs = rhs + ly * (sF[c][2][r][v] - sF[c][FPC - 1][r][v]);
-          double X = B.cut[k] ? B.X[((size_t)r * 4 + v) * P.NC + k] : 0.0;
-          rhs = rhs + lv * X;
-          double qn = loadQ<D>(P, Qn, on, r, v, k);
-          double qs = loadQ<D>(P, Qs, os, r, v, k);
-          double x = bcoef * qn + ccoef * (qs + rhs);
-          out[v] = x;
-          if (x != 0.0) nz = true;
+      double out[4];
+      bool nz = false;
+      for (int v = 0; v < 4; v++) {
+        if (D == 1 && v == 2) {
+          out[v] = 0.0;
+          continue;
         }
-        if (nz) {
-          occ |= 1u << r;
-          for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[v]);
-        }
+        double rhs = lx * (sF[tid][v] - sF[tid + 1][v]);
+        if (D == 2) rhs = rhs + ly * (sF[tid + 2][v] - sF[tid + FPC - 1][v]);
+        double X = B.cut[k] ? B.X[((size_t)r * 4 + v) * P.NC + k] : 0.0;
+        rhs = rhs + lv * X;
+        double qn = loadQ<D>(P, Qn, on, r, v, k);
+        double qs = loadQ<D>(P, Qs, os, r, v, k);
+        double x = bcoef * qn + ccoef * (qs + rhs);
+        out[v] = x;
+        if (x != 0.0) nz = true;
       }
-      B.occ[didx][k] = (uint8_t)occ;
-      if (nact) atomicAdd(&B.ctr[C_UPD], nact);
+      if (nz) {
+        atomicOr(&sOcc[c], 1u << r);
+        for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[v]);
+      }
+      wave_count(&B.ctr[C_UPD], alpha_at<D>(P, B, r, k) > 0.0 ? 1u : 0u);
     }
+    __syncthreads();
+    if (tid < cpb && base + tid < nb) B.occ[didx][B.blist[base + tid]] = (uint8_t)sOcc[tid];
     __syncthreads();
   }
 }
@@ -2082,8 +2103,11 @@ TILE_KERNEL(t_ls_commit, b_ls_commit, )
 TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
 template <int D>
 __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
+  // one material per grid row: the sources of different materials are
+  // independent
   uint32_t st = (uint32_t)B.ctr[C_STAMP];
-  for_tiles(P, B, [&](int i, int j) { b_mix1<D>(P, B, i, j, didx, st); });
+  int r = blockIdx.y;
+  for_tiles(P, B, [&](int i, int j) { b_mix1<D>(P, B, i, j, didx, st, r, r + 1); });
 }
 template <int D>
 __global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx) {
@@ -2206,7 +2230,7 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       PHASE(b_classify<1>(P, B, i_, 0));
       PHASE(b_dist_row<1>(P, B, i_, 0));
       PHASE(b_geom<1>(P, B, i_, 0, didx, (const double*)nullptr));
-      PHASE(b_mix1<1>(P, B, i_, 0, didx, stamp));
+      PHASE(b_mix1<1>(P, B, i_, 0, didx, stamp, 0, P.M));
       PHASE(b_mix2<1>(P, B, i_, 0, didx, stamp));
       stamp++;
       sidx = didx;

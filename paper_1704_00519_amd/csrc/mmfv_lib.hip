@@ -344,7 +344,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
            cc, s == 0 ? 1 : 0);
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
-  LAUNCH(k_flux_list<D>, dim3(512), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
+  LAUNCH(k_flux_list<D>, dim3(2048), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
   LAUNCH(k_cons_part<D>, dim3(cons_blocks(P), P.M), dim3(256), P, c->B, sidx,
          cons_bnd_blocks(P));
   LAUNCH(k_cons_fin, dim3(1), dim3(64), P, c->B, cons_blocks(P), w);
@@ -372,7 +372,7 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
     (void)hipMemcpyAsync(save_occ, c->B.occ[didx], (size_t)P.NC, hipMemcpyDeviceToDevice,
                          c->stream);
   }
-  LAUNCH(t_mix1<D>, tg, tb, P, c->B, didx);
+  LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, tg, tb, P, c->B, didx);
 }
 
