@@ -46,7 +46,6 @@ def measured_traffic(grid="896x384"):
     """HBM bytes per launch of the dominant kernel on the given grid from the
     committed counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on
     a plain copy), if it was taken on the current kernel sources; else None."""
-    import hashlib
     import re
     try:
         text = open(COUNTERS).read()
@@ -56,10 +55,21 @@ def measured_traffic(grid="896x384"):
     h = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
     if not t or not h:
         return None
+    return int(t.group(1)) if bulk_kernel_sha256() == h.group(1) else None
+
+
+def bulk_kernel_sha256():
+    """Hash of the bulk kernel's source: its section of mmfv_kernels.h (from
+    the bulk-update comment to the 1D bulk tile) and the point-wise numerics
+    it calls (mmfv_math.h)."""
+    import hashlib
+    kern = open(os.path.join(ROOT, KERNEL_SOURCES[0]), "rb").read()
+    a = kern.index(b"// Bulk update: cells with no cut cell")
+    b = kern.index(b"// 1D bulk update of one tile")
     d = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        d.update(open(os.path.join(ROOT, f), "rb").read())
-    return int(t.group(1)) if d.hexdigest() == h.group(1) else None
+    d.update(kern[a:b])
+    d.update(open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb").read())
+    return d.hexdigest()
 
 
 def bulk_roofline(prof):
