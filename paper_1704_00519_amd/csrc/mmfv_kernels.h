@@ -375,6 +375,82 @@ __global__ void k_dist_col(Params P, Bufs B) {
   B.dcut[k] = (uint8_t)dc;
   B.dls[k] = (uint8_t)dl;
 }
+// 2D classification and both distance passes in one launch: a CX x CY block
+// of cells with a frame of RD - 1 cells (the reach of the distance scans)
+// classified in LDS from the material indicators (one more cell around) and
+// the level set, then the row and column scans of k_dist_row / k_dist_col
+// over the LDS flags.  Same results, one pass over global memory.
+constexpr int CX = 32, CY = 16, CF = RD - 1;
+struct ClassDistSmem {
+  uint8_t chi[CY + 2 * CF + 2][CX + 2 * CF + 2];
+  uint8_t fl[CY + 2 * CF][CX + 2 * CF];  // bit 0: cut, bit 1: level-set band
+  uint8_t rd[2][CY + 2 * CF][CX];        // row distances: cut, level-set band
+};
+__global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
+  __shared__ ClassDistSmem S;
+  constexpr int HX = CX + 2 * CF + 2, HY = CY + 2 * CF + 2;
+  constexpr int FX = CX + 2 * CF, FY = CY + 2 * CF;
+  int tid = threadIdx.x, i0 = blockIdx.x * CX, j0 = blockIdx.y * CY;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) B.ctr[C_NTILES] = 0;
+  // indicators of the frame cells that border a domain cell (-1..nx, -1..ny)
+  for (int q = tid; q < HX * HY; q += 256) {
+    int ci = i0 - CF - 1 + q % HX, cj = j0 - CF - 1 + q / HX;
+    bool in = ci >= -1 && ci <= P.nx && cj >= -1 && cj <= P.ny;
+    S.chi[q / HX][q % HX] = in ? B.chi[cid(P, ci, cj)] : 0;
+  }
+  __syncthreads();
+  // flags of the domain cells of the frame (zero outside the domain)
+  for (int q = tid; q < FX * FY; q += 256) {
+    int fx = q % FX, fy = q / FX;
+    int ci = i0 - CF + fx, cj = j0 - CF + fy;
+    uint8_t f = 0;
+    if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny) {
+      unsigned b = 0;
+      for (int dj = -1; dj <= 1; dj++)
+        for (int di = -1; di <= 1; di++) b |= 1u << S.chi[fy + 1 + dj][fx + 1 + di];
+      bool c = (b & (b - 1)) != 0;
+      int k = cid(P, ci, cj);
+      f = (uint8_t)((c ? 1 : 0) | ((c || B.phi[k] < P.bls) ? 2 : 0));
+      if (fx >= CF && fx < CF + CX && fy >= CF && fy < CF + CY) {
+        B.xs[k] = (uint8_t)b;
+        B.cut[k] = c;
+      }
+    }
+    S.fl[fy][fx] = f;
+  }
+  __syncthreads();
+  // row scans for every row of the frame, the block's columns
+  for (int q = tid; q < CX * FY; q += 256) {
+    int x = q % CX, y = q / CX;
+    int dc = RD, dl = RD;
+    for (int di = -RD + 1; di <= RD - 1; di++) {
+      uint8_t f = S.fl[y][x + CF + di];
+      int a = di < 0 ? -di : di;
+      if ((f & 1) && a < dc) dc = a;
+      if ((f & 2) && a < dl) dl = a;
+    }
+    S.rd[0][y][x] = (uint8_t)dc;
+    S.rd[1][y][x] = (uint8_t)dl;
+  }
+  __syncthreads();
+  // column scans: d = min over dj of max(|dj|, row distance)
+  for (int q = tid; q < CX * CY; q += 256) {
+    int x = q % CX, y = q / CX;
+    int i = i0 + x, j = j0 + y;
+    if (i >= P.nx || j >= P.ny) continue;
+    int dc = RD, dl = RD;
+    for (int dj = -RD + 1; dj <= RD - 1; dj++) {
+      int a = dj < 0 ? -dj : dj;
+      int c = S.rd[0][y + CF + dj][x] > a ? S.rd[0][y + CF + dj][x] : a;
+      int l = S.rd[1][y + CF + dj][x] > a ? S.rd[1][y + CF + dj][x] : a;
+      if (c < dc) dc = c;
+      if (l < dl) dl = l;
+    }
+    int k = cid(P, i, j);
+    B.dcut[k] = (uint8_t)dc;
+    B.dls[k] = (uint8_t)dl;
+  }
+}
 // next mixing stamp (device-resident so a captured step can be replayed)
 __global__ void k_stamp_next(Params P, Bufs B) { B.ctr[C_STAMP] += 1; }
 
@@ -1618,13 +1694,17 @@ __global__ void k_mix1(Params P, Bufs B, int didx) {
 }
 
 template <int D>
-MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp) {
+// materials r0 <= r < r1 of cell (i, j); with word_occ the occupancy bits
+// are set and cleared by atomics on the aligned 32-bit word that holds the
+// cell's byte (other materials of the cell may be updated at the same time)
+MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp,
+                int r0, int r1, bool word_occ) {
   int k = cid(P, i, j);
   double* Q = B.Q[didx];
   uint8_t* occp = B.occ[didx];
   unsigned occ = occp[k];
   bool touched = false;
-  for (int r = 0; r < P.M; r++) {
+  for (int r = r0; r < r1; r++) {
     bool src = B.srcStamp[(size_t)r * P.NC + k] == stamp;
     bool tgt = B.tgtStamp[(size_t)r * P.NC + k] == stamp;
     if (!src && !tgt) continue;
@@ -1677,15 +1757,23 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     } else {
       occ &= ~(1u << r);
     }
+    if (word_occ) {
+      unsigned* w = (unsigned*)(occp + (k & ~3));
+      unsigned bit = 1u << (8 * (k & 3) + r);
+      if (nz)
+        atomicOr(w, bit);
+      else
+        atomicAnd(w, ~bit);
+    }
   }
-  if (touched) occp[k] = (uint8_t)occ;
+  if (touched && !word_occ) occp[k] = (uint8_t)occ;
 }
 template <int D>
 __global__ void k_mix2(Params P, Bufs B, int didx) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
-  b_mix2<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP]);
+  b_mix2<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP], 0, P.M, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -2111,8 +2199,10 @@ __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
 }
 template <int D>
 __global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx) {
+  // one material per grid row, occupancy bits by word atomics
   uint32_t st = (uint32_t)B.ctr[C_STAMP];
-  for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st); });
+  int r = blockIdx.y;
+  for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st, r, r + 1, true); });
 }
 #undef TILE_KERNEL
 #undef COMMA
@@ -2231,7 +2321,7 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       PHASE(b_dist_row<1>(P, B, i_, 0));
       PHASE(b_geom<1>(P, B, i_, 0, didx, (const double*)nullptr));
       PHASE(b_mix1<1>(P, B, i_, 0, didx, stamp, 0, P.M));
-      PHASE(b_mix2<1>(P, B, i_, 0, didx, stamp));
+      PHASE(b_mix2<1>(P, B, i_, 0, didx, stamp, 0, P.M, false));
       stamp++;
       sidx = didx;
     }

@@ -216,7 +216,7 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   if (e == hipSuccess) e = dalloc(c, &(p), (n));
   for (int b = 0; b < 3; b++) {
     A(B.Q[b], M * nv * nc);
-    A(B.occ[b], nc);
+    A(B.occ[b], (nc + 255) & ~(size_t)255);  // whole 32-bit words for word atomics
   }
   A(B.phi, nc); A(B.ptmp, nc); A(B.phin, nc);
   A(B.chi, nc); A(B.ctmp, nc); A(B.chin, nc);
@@ -289,9 +289,13 @@ static void bc_ls(mm_ctx* c) {
 template <int D>
 static void classify(mm_ctx* c) {
   const Params& P = c->P;
-  LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B);
-  LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B);
-  if (D == 2) LAUNCH(k_dist_col, cell_grid(c), cell_block(c), P, c->B);
+  if (D == 2) {
+    LAUNCH(k_classify_dist2, dim3((P.nx + CX - 1) / CX, (P.ny + CY - 1) / CY), dim3(256), P,
+           c->B);
+  } else {
+    LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B);
+    LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B);
+  }
 }
 
 static int n_tiles(const Params& P) {
@@ -373,7 +377,7 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
                          c->stream);
   }
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
-  LAUNCH(t_mix2<D>, tg, tb, P, c->B, didx);
+  LAUNCH(t_mix2<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
 }
 
 template <int D>
