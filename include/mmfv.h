@@ -92,6 +92,10 @@ typedef struct {
   double sum_Q[MM_MAX_MAT][4];
   double bnd_in[MM_MAX_MAT][4];
   double exch[MM_MAX_MAT][4];
+  /* Sizes of the work lists of the last stage (2D; zero in the batched
+   * form): cells outside the bulk (updated by the general cut-cell code),
+   * queued ghost (cell, material) pairs, active 16 x 16 tiles. */
+  int64_t n_band, n_ghost, n_tiles;
 } mm_diag;
 
 typedef struct mm_ctx mm_ctx;

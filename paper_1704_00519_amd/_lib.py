@@ -50,7 +50,8 @@ class MMDiag(C.Structure):
                 ("n_mixsrc", C.c_int64), ("n_updates", C.c_int64),
                 ("err_cell", C.c_int64),
                 ("sum_Q", (C.c_double * 4) * 8), ("bnd_in", (C.c_double * 4) * 8),
-                ("exch", (C.c_double * 4) * 8)]
+                ("exch", (C.c_double * 4) * 8),
+                ("n_band", C.c_int64), ("n_ghost", C.c_int64), ("n_tiles", C.c_int64)]
 
 
 _DIAG_ARRAYS = ("sum_Q", "bnd_in", "exch")

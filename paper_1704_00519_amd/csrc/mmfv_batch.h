@@ -437,6 +437,7 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
     d.n_mixsrc = (int64_t)c[C_MIXSRC];
     d.n_updates = (int64_t)c[C_UPD];
     d.err_cell = c[C_ERR] == NO_ERR ? -1 : (int64_t)c[C_ERR];
+    d.n_band = d.n_ghost = d.n_tiles = 0;
     cons_to_diag(&cons[(size_t)q * CONS_N], b->M, &d);
   }
   return MM_OK;

@@ -161,6 +161,30 @@ MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
               const uint8_t* occs, int r, int i, int j, bool& valid) {
   int k = cid(P, i, j);
   bool in = interior(P, i, j);
+  if (D == 2) {
+    // branch-free form (the loads of several calls can be in flight
+    // together): Q and the state buffer share the [material][4][cell]
+    // layout in 2D, so one base pointer is chosen and the same words read
+    uint8_t dc = B.dcut[k], ch = B.chi[k], it = B.Wit[(size_t)r * P.NC + k], oc = occs[k];
+    bool far = in && dc > 7 && ch == r;
+    bool has = (oc >> r) & 1;
+    const double* base = far ? Qs : B.W;
+    size_t o = (size_t)r * 4 * P.NC + k;
+    double a0 = base[o], a1 = base[o + P.NC], a2 = base[o + 2 * (size_t)P.NC],
+           a3 = base[o + 3 * (size_t)P.NC];
+    valid = far || (it != 0 && (!in || dc <= 7));
+    if (far) {
+      double U0 = has ? a0 / 1.0 : 0.0, U1 = has ? a1 / 1.0 : 0.0, U2 = has ? a2 / 1.0 : 0.0,
+             U3 = has ? a3 / 1.0 : 0.0;
+      return prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+    }
+    Prim w;
+    w.r = a0;
+    w.u = a1;
+    w.v = a2;
+    w.p = a3;
+    return w;
+  }
   if (in && B.dcut[k] > 7 && B.chi[k] == r) {
     valid = true;
     double U0 = loadQ<D>(P, Qs, occs, r, 0, k) / 1.0;

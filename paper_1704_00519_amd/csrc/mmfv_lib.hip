@@ -277,6 +277,7 @@ static dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
 #define LAUNCH(kern, grid, block, ...) \
   hipLaunchKernelGGL(kern, grid, block, 0, c->stream, __VA_ARGS__)
 
+
 template <int D>
 static void bc_ls(mm_ctx* c) {
   const Params& P = c->P;
@@ -662,6 +663,9 @@ extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   out->n_mixsrc = (int64_t)ctr[C_MIXSRC];
   out->n_updates = (int64_t)ctr[C_UPD];
   out->err_cell = ctr[C_ERR] == NO_ERR ? -1 : (int64_t)ctr[C_ERR];
+  out->n_band = c->D == 2 ? (int64_t)ctr[C_NBAND] : 0;
+  out->n_ghost = c->D == 2 ? (int64_t)ctr[C_NGHOST] : 0;
+  out->n_tiles = c->D == 2 ? (int64_t)ctr[C_NTILES] : 0;
   cons_to_diag(cons.data(), c->P.M, out);
   return MM_OK;
 }
