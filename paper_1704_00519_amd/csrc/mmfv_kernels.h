@@ -409,7 +409,9 @@ struct ClassDistSmem {
   uint8_t chi[CY + 2 * CF + 2][CX + 2 * CF + 2];
   uint8_t fl[CY + 2 * CF][CX + 2 * CF];  // bit 0: cut, bit 1: level-set band
   uint8_t rd[2][CY + 2 * CF][CX];        // row distances: cut, level-set band
+  unsigned long long mrow[2][CY + 2 * CF];  // the flags of a frame row as bits
 };
+static_assert(CX + 2 * CF <= 64, "a frame row fits one 64-bit mask");
 __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
   __shared__ ClassDistSmem S;
   constexpr int HX = CX + 2 * CF + 2, HY = CY + 2 * CF + 2;
@@ -443,18 +445,31 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
     S.fl[fy][fx] = f;
   }
   __syncthreads();
-  // row scans for every row of the frame, the block's columns
-  for (int q = tid; q < CX * FY; q += 256) {
-    int x = q % CX, y = q / CX;
-    int dc = RD, dl = RD;
-    for (int di = -RD + 1; di <= RD - 1; di++) {
-      uint8_t f = S.fl[y][x + CF + di];
-      int a = di < 0 ? -di : di;
-      if ((f & 1) && a < dc) dc = a;
-      if ((f & 2) && a < dl) dl = a;
+  // row scans for every row of the frame, the block's columns: the nearest
+  // flag within RD - 1 cells, from the row's bit masks
+  for (int y = tid; y < FY; y += 256) {
+    unsigned long long m0 = 0, m1 = 0;
+    for (int x = 0; x < FX; x++) {
+      m0 |= (unsigned long long)(S.fl[y][x] & 1) << x;
+      m1 |= (unsigned long long)((S.fl[y][x] >> 1) & 1) << x;
     }
-    S.rd[0][y][x] = (uint8_t)dc;
-    S.rd[1][y][x] = (uint8_t)dl;
+    S.mrow[0][y] = m0;
+    S.mrow[1][y] = m1;
+  }
+  __syncthreads();
+  for (int q = tid; q < CX * FY; q += 256) {
+    int x = q % CX, y = q / CX, p = x + CF;
+    for (int b = 0; b < 2; b++) {
+      unsigned long long m = S.mrow[b][y];
+      unsigned long long lo = m & ((2ull << p) - 1), hi = m >> p;
+      int d = RD;
+      if (lo) d = p - (63 - __clzll(lo));
+      if (hi) {
+        int dh = __ffsll(hi) - 1;
+        if (dh < d) d = dh;
+      }
+      S.rd[b][y][x] = (uint8_t)(d <= RD - 1 ? d : RD);
+    }
   }
   __syncthreads();
   // column scans: d = min over dj of max(|dj|, row distance)
@@ -2228,6 +2243,176 @@ __global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx) {
   int r = blockIdx.y;
   for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st, r, r + 1, true); });
 }
+// All ghost-extension sweeps of one material on one active 16 x 16 tile in
+// one launch (2D).  A sweep reaches one cell further, so the tile and a frame
+// of EXR >= k_ext + 4 cells determine the tile's ghost states exactly: the
+// sweeps run in LDS over that region with the same stamps as the global
+// sweeps (a neighbour counts if it had a state before the sweep began), and
+// only the tile's own queued pairs are written back.  Frame cells whose
+// neighbours lie outside the region can come out differently; their effect
+// travels one cell per sweep and does not reach the tile.
+constexpr int EXR = 12, EXT = 16, EXW = EXT + 2 * EXR, EXG = EXW + 2;
+struct ExtSmem {
+  double W[4][EXW * EXW];
+  double lphi[EXG * EXG];  // local level set of the material, region + ring
+  uint8_t st[EXW * EXW];   // sweep stamp: 0 no state, 1 real, s + 2 sweep s
+  uint8_t pend[EXW * EXW]; // queued ghost pair
+  uint16_t list[EXW * EXW];  // the region's queued pairs
+  int nlist;
+};
+__global__ void __launch_bounds__(256) k_ext_tiles(Params P, Bufs B, int sidx) {
+  __shared__ ExtSmem S;
+  __shared__ int any;
+  const int r = blockIdx.y, tid = threadIdx.x, ntx = tiles_x(P);
+  if (errored(B)) return;
+  const int ntile = (int)B.ctr[C_NTILES], nsw = P.kext + 4;
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  // Other workgroups write back their tiles while this one reads its frame:
+  // a queued pair is recognised by its stamp not being 1 (real states have
+  // 1 throughout; queued pairs 0 until written back, then the sweep stamp),
+  // and its state is always recomputed here, never read.
+  auto pending = [&](int k) -> bool {
+    return B.dcut[k] <= 4 && ((B.near4[k] >> r) & 1) && !(!B.cut[k] && B.chi[k] == r) &&
+           B.Wit[(size_t)r * P.NC + k] != 1;
+  };
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    int tile = B.tiles[t];
+    int ti0 = (tile % ntx) * EXT, tj0 = (tile / ntx) * EXT;
+    int x0 = ti0 - EXR, y0 = tj0 - EXR;
+    if (tid == 0) {
+      any = 0;
+      S.nlist = 0;
+    }
+    __syncthreads();
+    {
+      int i = ti0 + tid % EXT, j = tj0 + tid / EXT;
+      if (i < P.nx && j < P.ny && pending(cid(P, i, j))) any = 1;
+    }
+    __syncthreads();
+    if (!any) continue;  // the same for the whole workgroup
+    for (int q = tid; q < EXW * EXW; q += 256) {
+      int ci = x0 + q % EXW, cj = y0 + q / EXW;
+      uint8_t st = 0, pd = 0;
+      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+      if (interior(P, ci, cj)) {
+        int k = cid(P, ci, cj);
+        if (B.dcut[k] > 7) {
+          if (B.chi[k] == r) {
+            st = 1;
+            double U0 = loadQ<2>(P, Q, occ, r, 0, k) / 1.0;
+            double U1 = loadQ<2>(P, Q, occ, r, 1, k) / 1.0;
+            double U2 = loadQ<2>(P, Q, occ, r, 2, k) / 1.0;
+            double U3 = loadQ<2>(P, Q, occ, r, 3, k) / 1.0;
+            Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+            w0 = w.r; w1 = w.u; w2 = w.v; w3 = w.p;
+          }
+        } else {
+          st = B.Wit[(size_t)r * P.NC + k] == 1 ? 1 : 0;
+          if (st) {
+            size_t o = (size_t)r * 4 * P.NC + k;
+            w0 = B.W[o];
+            w1 = B.W[o + P.NC];
+            w2 = B.W[o + 2 * (size_t)P.NC];
+            w3 = B.W[o + 3 * (size_t)P.NC];
+          }
+          pd = pending(k) ? 1 : 0;
+        }
+      }
+      S.st[q] = st;
+      S.pend[q] = pd;
+      S.W[0][q] = w0; S.W[1][q] = w1; S.W[2][q] = w2; S.W[3][q] = w3;
+      if (pd) S.list[atomicAdd(&S.nlist, 1)] = (uint16_t)q;
+    }
+    for (int q = tid; q < EXG * EXG; q += 256) {
+      int ci = x0 - 1 + q % EXG, cj = y0 - 1 + q / EXG;
+      bool in = ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H;
+      S.lphi[q] = in ? lsv(B.phi, B.chi, r, cid(P, ci, cj)) : 0.0;
+    }
+    __syncthreads();
+    // a region cell's state counts in sweep s if it had one before the sweep
+    auto valid = [&](int lx, int ly, int ci, int cj, int s) -> bool {
+      if (lx < 0 || lx >= EXW || ly < 0 || ly >= EXW || !interior(P, ci, cj)) return false;
+      int it = S.st[ly * EXW + lx];
+      return it != 0 && it <= s + 1;
+    };
+    const int nl = S.nlist;
+    for (int s = 0; s < nsw; s++) {
+      bool open = false;
+      for (int e = tid; e < nl; e += 256) {
+        int q = S.list[e];
+        if (S.st[q] != 0) continue;
+        open = true;
+        int lx = q % EXW, ly = q / EXW, ci = x0 + lx, cj = y0 + ly;
+        double out[4];
+        bool ok = false;
+        if (s < P.kext) {
+          int g = (ly + 1) * EXG + lx + 1;  // the cell in the ring-padded level set
+          double gx = S.lphi[g + 1] - S.lphi[g - 1];
+          double gy = S.lphi[g + EXG] - S.lphi[g - EXG];
+          int sx = 0, sy = 0;
+          bool hx = false, hy = false;
+          if (gx != 0.0) {
+            sx = gx > 0.0 ? 1 : -1;
+            hx = valid(lx + sx, ly, ci + sx, cj, s);
+          }
+          if (gy != 0.0) {
+            sy = gy > 0.0 ? 1 : -1;
+            hy = valid(lx, ly + sy, ci, cj + sy, s);
+          }
+          if (hx && hy) {
+            int a = ly * EXW + lx + sx, b = (ly + sy) * EXW + lx;
+            double wx = fabs(gx), wy = fabs(gy);
+            for (int c = 0; c < 4; c++) out[c] = (wx * S.W[c][a] + wy * S.W[c][b]) / (wx + wy);
+            ok = true;
+          } else if (hx || hy) {
+            int a = hx ? ly * EXW + lx + sx : (ly + sy) * EXW + lx;
+            for (int c = 0; c < 4; c++) out[c] = S.W[c][a];
+            ok = true;
+          }
+        } else {
+          double row[3][4];
+          int cnt = 0;
+          for (int dj = -1; dj <= 1; dj++) {
+            double a[3][4];
+            for (int di = -1; di <= 1; di++) {
+              bool use = (di != 0 || dj != 0) && valid(lx + di, ly + dj, ci + di, cj + dj, s);
+              int n = use ? (ly + dj) * EXW + lx + di : q;  // in range even when unused
+              for (int c = 0; c < 4; c++) a[di + 1][c] = use ? S.W[c][n] : 0.0;
+              cnt += use ? 1 : 0;
+            }
+            for (int c = 0; c < 4; c++) row[dj + 1][c] = (a[0][c] + a[2][c]) + a[1][c];
+          }
+          if (cnt > 0) {
+            for (int c = 0; c < 4; c++)
+              out[c] = ((row[0][c] + row[2][c]) + row[1][c]) / (double)cnt;
+            ok = true;
+          }
+        }
+        if (ok) {
+          for (int c = 0; c < 4; c++) S.W[c][q] = out[c];
+          S.st[q] = (uint8_t)(s + 2);
+        }
+      }
+      // once every queued pair of the region has a state, later sweeps
+      // change nothing
+      if (!__syncthreads_or(open)) break;
+    }
+    // the tile's own pairs go back to the state buffer
+    {
+      int lx = EXR + tid % EXT, ly = EXR + tid / EXT, i = x0 + lx, j = y0 + ly;
+      int q = ly * EXW + lx;
+      if (i < P.nx && j < P.ny && S.pend[q] && S.st[q] != 0) {
+        int k = cid(P, i, j);
+        size_t o = (size_t)r * 4 * P.NC + k;
+        for (int c = 0; c < 4; c++) B.W[o + (size_t)c * P.NC] = S.W[c][q];
+        B.Wit[(size_t)r * P.NC + k] = S.st[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 #undef TILE_KERNEL
 #undef COMMA
 

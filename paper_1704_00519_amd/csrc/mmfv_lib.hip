@@ -326,8 +326,12 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
   LAUNCH(t_near_row<D>, tg, tb, P, c->B);
   LAUNCH(t_near_col<D>, tg, tb, P, c->B);
-  for (int sw = 0; sw < P.kext + 4; sw++)
-    LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
+  if (D == 2 && P.kext + 4 <= EXR) {
+    LAUNCH(k_ext_tiles, dim3(tg.x, P.M), tb, P, c->B, sidx);
+  } else {
+    for (int sw = 0; sw < P.kext + 4; sw++)
+      LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
+  }
   LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
   if (D == 2)
     LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
@@ -386,29 +390,6 @@ static void stage(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, doub
                   double w, double* save_Q = nullptr, uint8_t* save_occ = nullptr) {
   stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w);
   stage_levelset<D>(c, didx, nidx, b, cc, true, save_Q, save_occ);
-}
-
-// the states a stage reads besides its fluxes, for the adjoint: real and
-// ghost primitive states with frames, and the interface exchange (at stage
-// 0 also the level-set velocity); no fluxes or update
-template <int D>
-static void stage_states(mm_ctx* c, int s, int sidx) {
-  const Params& P = c->P;
-  dim3 tg = tile_grid(c), tb(256);
-  LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
-  LAUNCH(t_near_row<D>, tg, tb, P, c->B);
-  LAUNCH(t_near_col<D>, tg, tb, P, c->B);
-  for (int sw = 0; sw < P.kext + 4; sw++)
-    LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
-  LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
-  if (D == 2)
-    LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
-  if (s == 0) LAUNCH(t_vreset<D>, tg, tb, P, c->B);
-  LAUNCH(t_iface<D>, tg, tb, P, c->B, sidx, s == 0 ? 1 : 0);
-  if (s == 0) {
-    for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
-    LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
-  }
 }
 
 // beta-form coefficients, and each stage's share w of the full step in the
