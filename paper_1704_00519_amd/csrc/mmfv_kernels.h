@@ -399,16 +399,15 @@ __global__ void k_dist_col(Params P, Bufs B) {
   B.dcut[k] = (uint8_t)dc;
   B.dls[k] = (uint8_t)dl;
 }
-// 2D classification and both distance passes in one launch: a CX x CY block
-// of cells with a frame of RD - 1 cells (the reach of the distance scans)
-// classified in LDS from the material indicators (one more cell around) and
-// the level set, then the row and column scans of k_dist_row / k_dist_col
-// over the LDS flags.  Same results, one pass over global memory.
+// 2D classification and distances in one launch: a CX x CY block of cells
+// with a frame of RD - 1 cells (the reach of the distances) classified in LDS
+// from the material indicators (one more cell around) and the level set; the
+// capped Chebyshev distances of k_dist_row / k_dist_col then come from bit
+// masks of the frame's rows.  Same results, one pass over global memory.
 constexpr int CX = 32, CY = 16, CF = RD - 1;
 struct ClassDistSmem {
   uint8_t chi[CY + 2 * CF + 2][CX + 2 * CF + 2];
   uint8_t fl[CY + 2 * CF][CX + 2 * CF];  // bit 0: cut, bit 1: level-set band
-  uint8_t rd[2][CY + 2 * CF][CX];        // row distances: cut, level-set band
   unsigned long long mrow[2][CY + 2 * CF];  // the flags of a frame row as bits
 };
 static_assert(CX + 2 * CF <= 64, "a frame row fits one 64-bit mask");
@@ -419,14 +418,37 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
   int tid = threadIdx.x, i0 = blockIdx.x * CX, j0 = blockIdx.y * CY;
   if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) B.ctr[C_NTILES] = 0;
   // indicators of the frame cells that border a domain cell (-1..nx, -1..ny)
-  for (int q = tid; q < HX * HY; q += 256) {
+  // and the level-set test of the frame's domain cells: every load of the
+  // thread is issued before the first is used
+  constexpr int N1 = (HX * HY + 255) / 256, N2 = (FX * FY + 255) / 256;
+  uint8_t cv[N1], lf[N2];
+#pragma unroll
+  for (int n = 0; n < N1; n++) {
+    int q = tid + n * 256;
     int ci = i0 - CF - 1 + q % HX, cj = j0 - CF - 1 + q / HX;
-    bool in = ci >= -1 && ci <= P.nx && cj >= -1 && cj <= P.ny;
-    S.chi[q / HX][q % HX] = in ? B.chi[cid(P, ci, cj)] : 0;
+    bool in = q < HX * HY && ci >= -1 && ci <= P.nx && cj >= -1 && cj <= P.ny;
+    uint8_t v = B.chi[in ? cid(P, ci, cj) : cid(P, 0, 0)];  // unconditional: no wait per load
+    cv[n] = in ? v : 0;
+  }
+#pragma unroll
+  for (int n = 0; n < N2; n++) {
+    int q = tid + n * 256;
+    int ci = i0 - CF + q % FX, cj = j0 - CF + q / FX;
+    bool in = q < FX * FY && ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny;
+    double ph = B.phi[in ? cid(P, ci, cj) : cid(P, 0, 0)];
+    lf[n] = in && ph < P.bls ? 1 : 0;
+  }
+#pragma unroll
+  for (int n = 0; n < N1; n++) {
+    int q = tid + n * 256;
+    if (q < HX * HY) S.chi[q / HX][q % HX] = cv[n];
   }
   __syncthreads();
   // flags of the domain cells of the frame (zero outside the domain)
-  for (int q = tid; q < FX * FY; q += 256) {
+#pragma unroll
+  for (int n = 0; n < N2; n++) {
+    int q = tid + n * 256;
+    if (q >= FX * FY) continue;
     int fx = q % FX, fy = q / FX;
     int ci = i0 - CF + fx, cj = j0 - CF + fy;
     uint8_t f = 0;
@@ -436,7 +458,7 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
         for (int di = -1; di <= 1; di++) b |= 1u << S.chi[fy + 1 + dj][fx + 1 + di];
       bool c = (b & (b - 1)) != 0;
       int k = cid(P, ci, cj);
-      f = (uint8_t)((c ? 1 : 0) | ((c || B.phi[k] < P.bls) ? 2 : 0));
+      f = (uint8_t)((c ? 1 : 0) | ((c || lf[n]) ? 2 : 0));
       if (fx >= CF && fx < CF + CX && fy >= CF && fy < CF + CY) {
         B.xs[k] = (uint8_t)b;
         B.cut[k] = c;
@@ -445,49 +467,41 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
     S.fl[fy][fx] = f;
   }
   __syncthreads();
-  // row scans for every row of the frame, the block's columns: the nearest
-  // flag within RD - 1 cells, from the row's bit masks
-  for (int y = tid; y < FY; y += 256) {
+  // the frame's rows as bit masks (four 16-cell pieces per row)
+  if (tid < 2 * FY) S.mrow[tid / FY][tid % FY] = 0;
+  __syncthreads();
+  for (int q = tid; q < 4 * FY; q += 256) {
+    int y = q >> 2, x0 = (q & 3) * 16;
     unsigned long long m0 = 0, m1 = 0;
-    for (int x = 0; x < FX; x++) {
+    for (int x = x0; x < x0 + 16 && x < FX; x++) {
       m0 |= (unsigned long long)(S.fl[y][x] & 1) << x;
       m1 |= (unsigned long long)((S.fl[y][x] >> 1) & 1) << x;
     }
-    S.mrow[0][y] = m0;
-    S.mrow[1][y] = m1;
+    atomicOr(&S.mrow[0][y], m0);
+    atomicOr(&S.mrow[1][y], m1);
   }
   __syncthreads();
-  for (int q = tid; q < CX * FY; q += 256) {
-    int x = q % CX, y = q / CX, p = x + CF;
-    for (int b = 0; b < 2; b++) {
-      unsigned long long m = S.mrow[b][y];
-      unsigned long long lo = m & ((2ull << p) - 1), hi = m >> p;
-      int d = RD;
-      if (lo) d = p - (63 - __clzll(lo));
-      if (hi) {
-        int dh = __ffsll(hi) - 1;
-        if (dh < d) d = dh;
-      }
-      S.rd[b][y][x] = (uint8_t)(d <= RD - 1 ? d : RD);
-    }
-  }
-  __syncthreads();
-  // column scans: d = min over dj of max(|dj|, row distance)
+  // Chebyshev distance to the nearest flag (RD when none within RD - 1):
+  // the smallest t whose (2t+1) x (2t+1) window holds a flag, the rows of
+  // the window OR-ed into one mask
   for (int q = tid; q < CX * CY; q += 256) {
     int x = q % CX, y = q / CX;
     int i = i0 + x, j = j0 + y;
     if (i >= P.nx || j >= P.ny) continue;
-    int dc = RD, dl = RD;
-    for (int dj = -RD + 1; dj <= RD - 1; dj++) {
-      int a = dj < 0 ? -dj : dj;
-      int c = S.rd[0][y + CF + dj][x] > a ? S.rd[0][y + CF + dj][x] : a;
-      int l = S.rd[1][y + CF + dj][x] > a ? S.rd[1][y + CF + dj][x] : a;
-      if (c < dc) dc = c;
-      if (l < dl) dl = l;
+    int p = x + CF, yy = y + CF;
+    int d[2] = {RD, RD};
+    for (int b = 0; b < 2; b++) {
+      unsigned long long m = S.mrow[b][yy];
+#pragma unroll
+      for (int t = 0; t < RD; t++) {  // no early exit: the row reads go out together
+        if (t > 0) m |= S.mrow[b][yy - t] | S.mrow[b][yy + t];
+        bool hit = ((m >> (p - t)) & ((2ull << (2 * t)) - 1)) != 0;
+        if (hit && d[b] == RD) d[b] = t;
+      }
     }
     int k = cid(P, i, j);
-    B.dcut[k] = (uint8_t)dc;
-    B.dls[k] = (uint8_t)dl;
+    B.dcut[k] = (uint8_t)d[0];
+    B.dls[k] = (uint8_t)d[1];
   }
 }
 // next mixing stamp (device-resident so a captured step can be replayed)
@@ -2105,15 +2119,15 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
 // interleaved running sums, then their sum) and add the stage totals,
 // weighted by w, to the running sums (one thread per material and quantity)
 __global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w) {
-  int x = threadIdx.x;
+  // one wavefront per (material, quantity): strided partial sums, then a
+  // butterfly whose lane 0 result has a fixed order (reproducible)
+  int x = blockIdx.x, t = threadIdx.x;
   if (x >= P.M * 8) return;
   int r = x / 8, v = x % 8;
-  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int b = 0;
-  for (; b + 8 <= nblk; b += 8)
-    for (int u = 0; u < 8; u++) s8[u] += B.cpart[((size_t)(b + u) * P.M + r) * 8 + v];
-  for (int u = 0; b + u < nblk; u++) s8[u] += B.cpart[((size_t)(b + u) * P.M + r) * 8 + v];
-  double a = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  double a = 0.0;
+  for (int b = t; b < nblk; b += 64) a += B.cpart[((size_t)b * P.M + r) * 8 + v];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (t != 0) return;
   if (v < 4)
     neumaier_add(&B.cons[(CONS_BND * MAXM + r) * 4 + v], &B.cons[(CONS_BNDC * MAXM + r) * 4 + v],
                  w * a);
@@ -2273,8 +2287,9 @@ __global__ void __launch_bounds__(256) k_ext_tiles(Params P, Bufs B, int sidx) {
   // 1 throughout; queued pairs 0 until written back, then the sweep stamp),
   // and its state is always recomputed here, never read.
   auto pending = [&](int k) -> bool {
-    return B.dcut[k] <= 4 && ((B.near4[k] >> r) & 1) && !(!B.cut[k] && B.chi[k] == r) &&
-           B.Wit[(size_t)r * P.NC + k] != 1;
+    uint8_t dc = B.dcut[k], n4 = B.near4[k], ct = B.cut[k], ch = B.chi[k],
+            it = B.Wit[(size_t)r * P.NC + k];  // all loads issued together
+    return dc <= 4 && ((n4 >> r) & 1) && !(!ct && ch == r) && it != 1;
   };
   for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
     int tile = B.tiles[t];
@@ -2291,32 +2306,65 @@ __global__ void __launch_bounds__(256) k_ext_tiles(Params P, Bufs B, int sidx) {
     }
     __syncthreads();
     if (!any) continue;  // the same for the whole workgroup
-    for (int q = tid; q < EXW * EXW; q += 256) {
+    // the region's states (loads of all the thread's cells in flight
+    // together): real states from the buffer, far pure cells from Q
+    constexpr int NQ = (EXW * EXW + 255) / 256, NG = (EXG * EXG + 255) / 256;
+    int kq[NQ];
+    uint8_t dcq[NQ], chq[NQ], itq[NQ], n4q[NQ], ctq[NQ], ocq[NQ];
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int q = tid + n * 256;
       int ci = x0 + q % EXW, cj = y0 + q / EXW;
+      bool in = q < EXW * EXW && interior(P, ci, cj);
+      int k = in ? cid(P, ci, cj) : -1, ks = in ? k : cid(P, 0, 0);
+      kq[n] = k;
+      // unconditional loads from an in-range cell, selected afterwards, so
+      // that no load waits for the previous one
+      uint8_t a0 = B.dcut[ks], a1 = B.chi[ks], a2 = B.Wit[(size_t)r * P.NC + ks],
+              a3 = B.near4[ks], a4 = B.cut[ks], a5 = occ[ks];
+      dcq[n] = in ? a0 : 0;
+      chq[n] = in ? a1 : 0;
+      itq[n] = in ? a2 : 0;
+      n4q[n] = in ? a3 : 0;
+      ctq[n] = in ? a4 : 0;
+      ocq[n] = in ? a5 : 0;
+    }
+    double U[NQ][4];
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int k = kq[n];
+      bool far = dcq[n] > 7 && chq[n] == r;
+      bool need = k >= 0 && (far || (dcq[n] <= 7 && itq[n] == 1));
+      const double* base = far ? Q : B.W;
+      size_t o = (size_t)r * 4 * P.NC + (k >= 0 ? k : cid(P, 0, 0));
+      for (int c = 0; c < 4; c++) {
+        double u = base[o + (size_t)c * P.NC];
+        U[n][c] = need ? u : 0.0;
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int q = tid + n * 256;
+      if (q >= EXW * EXW) continue;
+      int k = kq[n];
       uint8_t st = 0, pd = 0;
       double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-      if (interior(P, ci, cj)) {
-        int k = cid(P, ci, cj);
-        if (B.dcut[k] > 7) {
-          if (B.chi[k] == r) {
+      if (k >= 0) {
+        if (dcq[n] > 7) {
+          if (chq[n] == r) {
             st = 1;
-            double U0 = loadQ<2>(P, Q, occ, r, 0, k) / 1.0;
-            double U1 = loadQ<2>(P, Q, occ, r, 1, k) / 1.0;
-            double U2 = loadQ<2>(P, Q, occ, r, 2, k) / 1.0;
-            double U3 = loadQ<2>(P, Q, occ, r, 3, k) / 1.0;
+            bool has = (ocq[n] >> r) & 1;
+            double U0 = has ? U[n][0] / 1.0 : 0.0, U1 = has ? U[n][1] / 1.0 : 0.0,
+                   U2 = has ? U[n][2] / 1.0 : 0.0, U3 = has ? U[n][3] / 1.0 : 0.0;
             Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
             w0 = w.r; w1 = w.u; w2 = w.v; w3 = w.p;
           }
         } else {
-          st = B.Wit[(size_t)r * P.NC + k] == 1 ? 1 : 0;
+          st = itq[n] == 1 ? 1 : 0;
           if (st) {
-            size_t o = (size_t)r * 4 * P.NC + k;
-            w0 = B.W[o];
-            w1 = B.W[o + P.NC];
-            w2 = B.W[o + 2 * (size_t)P.NC];
-            w3 = B.W[o + 3 * (size_t)P.NC];
+            w0 = U[n][0]; w1 = U[n][1]; w2 = U[n][2]; w3 = U[n][3];
           }
-          pd = pending(k) ? 1 : 0;
+          pd = dcq[n] <= 4 && ((n4q[n] >> r) & 1) && !(!ctq[n] && chq[n] == r) && itq[n] != 1;
         }
       }
       S.st[q] = st;
@@ -2324,10 +2372,23 @@ __global__ void __launch_bounds__(256) k_ext_tiles(Params P, Bufs B, int sidx) {
       S.W[0][q] = w0; S.W[1][q] = w1; S.W[2][q] = w2; S.W[3][q] = w3;
       if (pd) S.list[atomicAdd(&S.nlist, 1)] = (uint16_t)q;
     }
-    for (int q = tid; q < EXG * EXG; q += 256) {
+    double ph[NG];
+    uint8_t pc[NG];
+#pragma unroll
+    for (int n = 0; n < NG; n++) {
+      int q = tid + n * 256;
       int ci = x0 - 1 + q % EXG, cj = y0 - 1 + q / EXG;
-      bool in = ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H;
-      S.lphi[q] = in ? lsv(B.phi, B.chi, r, cid(P, ci, cj)) : 0.0;
+      bool in = q < EXG * EXG && ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H;
+      int k = in ? cid(P, ci, cj) : cid(P, 0, 0);
+      double a = B.phi[k];
+      uint8_t b = B.chi[k];
+      ph[n] = in ? a : 0.0;
+      pc[n] = in ? b : (uint8_t)r;
+    }
+#pragma unroll
+    for (int n = 0; n < NG; n++) {
+      int q = tid + n * 256;
+      if (q < EXG * EXG) S.lphi[q] = pc[n] == r ? ph[n] : -ph[n];
     }
     __syncthreads();
     // a region cell's state counts in sweep s if it had one before the sweep

@@ -356,7 +356,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   LAUNCH(k_flux_list<D>, dim3(2048), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
   LAUNCH(k_cons_part<D>, dim3(cons_blocks(P), P.M), dim3(256), P, c->B, sidx,
          cons_bnd_blocks(P));
-  LAUNCH(k_cons_fin, dim3(1), dim3(64), P, c->B, cons_blocks(P), w);
+  LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w);
 }
 
 // second half: level-set stage and its frame, classification, geometry and
