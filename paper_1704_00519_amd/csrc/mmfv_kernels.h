@@ -123,34 +123,42 @@ MMD double alpha_at(const Params& P, const Bufs& B, int r, int k) {
 template <int D>
 MMD double apx(const Params& P, const Bufs& B, int r, int i, int j) {
   int kl = cid(P, i, j), kr = cid(P, i + 1, j);
-  int knc;
+  // every word read in any case (all in range), then chosen: the loads of a
+  // caller overlap; outside the domain the flags are not looked at
+  uint8_t cl = B.cut[kl], cr = B.cut[kr], hl = B.chi[kl], hr = B.chi[kr];
+  double a = B.ax[(size_t)r * P.NC + kl];
+  bool use;
+  int h;
   if (i < 0) {
-    if (B.cut[kr]) return B.ax[(size_t)r * P.NC + kl];
-    knc = kr;
+    use = cr;
+    h = hr;
   } else if (i >= P.nx - 1) {
-    if (B.cut[kl]) return B.ax[(size_t)r * P.NC + kl];
-    knc = kl;
+    use = cl;
+    h = hl;
   } else {
-    if (B.cut[kl] && B.cut[kr]) return B.ax[(size_t)r * P.NC + kl];
-    knc = B.cut[kl] ? kr : kl;
+    use = cl && cr;
+    h = cl ? hr : hl;
   }
-  return B.chi[knc] == r ? 1.0 : 0.0;
+  return use ? a : (h == r ? 1.0 : 0.0);
 }
 // aperture of the y-face j+1/2 of column i (j in [-1, ny-1])
 MMD double apy(const Params& P, const Bufs& B, int r, int i, int j) {
   int kb = cid(P, i, j), kt = cid(P, i, j + 1);
-  int knc;
+  uint8_t cb = B.cut[kb], ct = B.cut[kt], hb = B.chi[kb], ht = B.chi[kt];
+  double a = B.ay[(size_t)r * P.NC + kb];
+  bool use;
+  int h;
   if (j < 0) {
-    if (B.cut[kt]) return B.ay[(size_t)r * P.NC + kb];
-    knc = kt;
+    use = ct;
+    h = ht;
   } else if (j >= P.ny - 1) {
-    if (B.cut[kb]) return B.ay[(size_t)r * P.NC + kb];
-    knc = kb;
+    use = cb;
+    h = hb;
   } else {
-    if (B.cut[kb] && B.cut[kt]) return B.ay[(size_t)r * P.NC + kb];
-    knc = B.cut[kb] ? kt : kb;
+    use = cb && ct;
+    h = cb ? ht : hb;
   }
-  return B.chi[knc] == r ? 1.0 : 0.0;
+  return use ? a : (h == r ? 1.0 : 0.0);
 }
 
 // primitive state of material r at a cell: read from the real/ghost buffer
