@@ -550,8 +550,14 @@ MMD void a_face(const Params& P, const Bufs& B, const Adj& A, const double* Q,
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef, int dir) {
+// x-faces (threads t < nx0 faces) and, in 2D, the y-faces after them, in one
+// launch: twice the faces in flight
+__global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int n0 = (P.nx + 1) * P.ny;
+  int dir = t < n0 ? 0 : 1;
+  if (D == 1 && dir == 1) return;
+  if (dir == 1) t -= n0;
   int nfx = dir == 0 ? P.nx + 1 : P.nx, nfy = dir == 0 ? P.ny : P.ny + 1;
   if (t >= nfx * nfy) return;
   int i = t % nfx, j = t / nfx;

@@ -343,8 +343,8 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi
     LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
     LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);
-    LAUNCH(k_a_flux<D>, lin_grid(nfx0), dim3(256), P, c->B, A, sidx, cc[s], 0);
-    if (D == 2) LAUNCH(k_a_flux<D>, lin_grid(nfx1), dim3(256), P, c->B, A, sidx, cc[s], 1);
+    LAUNCH(k_a_flux<D>, lin_grid(D == 2 ? nfx0 + nfx1 : nfx0), dim3(256), P, c->B, A, sidx,
+           cc[s]);
     if (s == 0) {
       LAUNCH(k_a_vfill<D>, g, bl, P, c->B, A, sidx);
       for (int sw = 3; sw >= 0; sw--) LAUNCH(k_a_vext<D>, g, bl, P, c->B, A, sw);
