@@ -38,6 +38,7 @@ struct Adj {
   double* Qstar;     // [M][D+2][NC] copy of Q* (before mixing)
   uint8_t* occstar;  // its occupancy
   double* lalpha;    // [M][NC] adjoint of the step's output volume fractions
+  double* lW2;       // [M][4][NC] output buffer of the tile-wise ghost-state adjoint
 };
 
 MMD double& A4(const Params& P, double* a, int r, int v, int k) {
@@ -913,6 +914,204 @@ __global__ void __launch_bounds__(256) k_a_ext(Params P, Bufs B, Adj A, int sidx
             for (int c = 0; c < 4; c++) aadd(&A4(P, A.lW, r, c, ks), lo[c] / (double)cnt);
           }
     }
+  }
+}
+
+// The ghost-state sweeps in reverse, tile-wise (2D): one workgroup per
+// active tile and material loads the forward states, stamps and adjoints of
+// the tile and its 12-cell frame, runs the reverse sweeps in LDS (a pair's
+// adjoint goes to the neighbours it was computed from, as in k_a_ext) and
+// writes the tile's own adjoints to lW2; the level-set adjoint of the tile's
+// own pairs goes to lphi.  Adjoints reach a tile cell from at most 12 cells
+// away, so the tile's values are complete.  lW is only read (other
+// workgroups read it for their frames).
+struct AExtSmem {
+  double W[4][EXW * EXW];
+  double L[4][EXW * EXW];  // adjoints of the states
+  double lphi[EXG * EXG];
+  uint8_t st[EXW * EXW];
+  uint16_t list[EXW * EXW];
+  int nlist;
+};
+__global__ void __launch_bounds__(256) k_a_ext_tiles(Params P, Bufs B, Adj A, int sidx) {
+  __shared__ AExtSmem S;
+  const int r = blockIdx.y, tid = threadIdx.x, ntx = tiles_x(P);
+  const int ntile = (int)B.ctr[C_NTILES], nsw = P.kext + 4;
+  const double* Q = B.Q[sidx];
+  const uint8_t* occ = B.occ[sidx];
+  constexpr int NQ = (EXW * EXW + 255) / 256, NG = (EXG * EXG + 255) / 256;
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    int tile = B.tiles[t];
+    int ti0 = (tile % ntx) * EXT, tj0 = (tile / ntx) * EXT;
+    int x0 = ti0 - EXR, y0 = tj0 - EXR;
+    if (tid == 0) S.nlist = 0;
+    __syncthreads();
+    int kq[NQ];
+    uint8_t dcq[NQ], chq[NQ], itq[NQ], ocq[NQ];
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int q = tid + n * 256;
+      int ci = x0 + q % EXW, cj = y0 + q / EXW;
+      bool in = q < EXW * EXW && interior(P, ci, cj);
+      int k = in ? cid(P, ci, cj) : -1, ks = in ? k : cid(P, 0, 0);
+      kq[n] = k;
+      uint8_t a0 = B.dcut[ks], a1 = B.chi[ks], a2 = B.Wit[(size_t)r * P.NC + ks], a5 = occ[ks];
+      dcq[n] = in ? a0 : 0;
+      chq[n] = in ? a1 : 0;
+      itq[n] = in ? a2 : 0;
+      ocq[n] = in ? a5 : 0;
+    }
+    double U[NQ][4], Lq[NQ][4];
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int k = kq[n];
+      bool far = dcq[n] > 7 && chq[n] == r;
+      bool need = k >= 0 && (far || (dcq[n] <= 7 && itq[n] != 0));
+      const double* base = far ? Q : B.W;
+      size_t o = (size_t)r * 4 * P.NC + (k >= 0 ? k : cid(P, 0, 0));
+      for (int c = 0; c < 4; c++) {
+        double u = base[o + (size_t)c * P.NC], l = A.lW[o + (size_t)c * P.NC];
+        U[n][c] = need ? u : 0.0;
+        Lq[n][c] = k >= 0 ? l : 0.0;
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NQ; n++) {
+      int q = tid + n * 256;
+      if (q >= EXW * EXW) continue;
+      int k = kq[n];
+      uint8_t st = 0;
+      double w[4] = {0.0, 0.0, 0.0, 0.0};
+      if (k >= 0) {
+        if (dcq[n] > 7) {
+          if (chq[n] == r) {
+            st = 1;
+            bool has = (ocq[n] >> r) & 1;
+            double U0 = has ? U[n][0] / 1.0 : 0.0, U1 = has ? U[n][1] / 1.0 : 0.0,
+                   U2 = has ? U[n][2] / 1.0 : 0.0, U3 = has ? U[n][3] / 1.0 : 0.0;
+            Prim pw = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+            w[0] = pw.r; w[1] = pw.u; w[2] = pw.v; w[3] = pw.p;
+          }
+        } else {
+          st = itq[n];
+          if (st)
+            for (int c = 0; c < 4; c++) w[c] = U[n][c];
+          // a pair that got its state in a sweep (stamps 0/1 are no state / real)
+          if (dcq[n] <= 4 && st >= 2) S.list[atomicAdd(&S.nlist, 1)] = (uint16_t)q;
+        }
+      }
+      S.st[q] = st;
+      for (int c = 0; c < 4; c++) {
+        S.W[c][q] = w[c];
+        S.L[c][q] = Lq[n][c];
+      }
+    }
+    double ph[NG];
+    uint8_t pc[NG];
+#pragma unroll
+    for (int n = 0; n < NG; n++) {
+      int q = tid + n * 256;
+      int ci = x0 - 1 + q % EXG, cj = y0 - 1 + q / EXG;
+      bool in = q < EXG * EXG && ci >= -H && ci < P.nx + H && cj >= -H && cj < P.ny + H;
+      int k = in ? cid(P, ci, cj) : cid(P, 0, 0);
+      double a = B.phi[k];
+      uint8_t b = B.chi[k];
+      ph[n] = in ? a : 0.0;
+      pc[n] = in ? b : (uint8_t)r;
+    }
+#pragma unroll
+    for (int n = 0; n < NG; n++) {
+      int q = tid + n * 256;
+      if (q < EXG * EXG) S.lphi[q] = pc[n] == r ? ph[n] : -ph[n];
+    }
+    __syncthreads();
+    const int nl = S.nlist;
+    if (nl > 0) {
+      auto valid = [&](int lx, int ly, int ci, int cj, int s) -> bool {
+        if (lx < 0 || lx >= EXW || ly < 0 || ly >= EXW || !interior(P, ci, cj)) return false;
+        int it = S.st[ly * EXW + lx];
+        return it != 0 && it <= s + 1;
+      };
+      for (int s = nsw - 1; s >= 0; s--) {
+        for (int e = tid; e < nl; e += 256) {
+          int q = S.list[e];
+          if (S.st[q] != s + 2) continue;
+          double lo[4];
+          bool any = false;
+          for (int c = 0; c < 4; c++) {
+            lo[c] = S.L[c][q];
+            S.L[c][q] = 0.0;
+            if (lo[c] != 0.0) any = true;
+          }
+          if (!any) continue;
+          int lx = q % EXW, ly = q / EXW, ci = x0 + lx, cj = y0 + ly;
+          bool own = lx >= EXR && lx < EXR + EXT && ly >= EXR && ly < EXR + EXT;
+          if (s < P.kext) {
+            int g = (ly + 1) * EXG + lx + 1;
+            double gx = S.lphi[g + 1] - S.lphi[g - 1];
+            double gy = S.lphi[g + EXG] - S.lphi[g - EXG];
+            int sx = 0, sy = 0;
+            bool hx = false, hy = false;
+            if (gx != 0.0) {
+              sx = gx > 0.0 ? 1 : -1;
+              hx = valid(lx + sx, ly, ci + sx, cj, s);
+            }
+            if (gy != 0.0) {
+              sy = gy > 0.0 ? 1 : -1;
+              hy = valid(lx, ly + sy, ci, cj + sy, s);
+            }
+            if (hx && hy) {
+              int a = ly * EXW + lx + sx, b = (ly + sy) * EXW + lx;
+              double wx = fabs(gx), wy = fabs(gy), ws = wx + wy;
+              double lwx = 0.0, lwy = 0.0;
+              for (int c = 0; c < 4; c++) {
+                double av = S.W[c][a], bv = S.W[c][b];
+                double out = (wx * av + wy * bv) / ws;
+                atomicAdd(&S.L[c][a], lo[c] * wx / ws);
+                atomicAdd(&S.L[c][b], lo[c] * wy / ws);
+                lwx += lo[c] * (av - out) / ws;
+                lwy += lo[c] * (bv - out) / ws;
+              }
+              if (own) {
+                int kc = cid(P, ci, cj);
+                int kxp = kc + 1, kxm = kc - 1, kyp = kc + P.NX, kym = kc - P.NX;
+                double lgx = gx > 0.0 ? lwx : -lwx, lgy = gy > 0.0 ? lwy : -lwy;
+                aadd(&A.lphi[kxp], lgx * lsgn(B.chi, r, kxp));
+                aadd(&A.lphi[kxm], -lgx * lsgn(B.chi, r, kxm));
+                aadd(&A.lphi[kyp], lgy * lsgn(B.chi, r, kyp));
+                aadd(&A.lphi[kym], -lgy * lsgn(B.chi, r, kym));
+              }
+            } else if (hx || hy) {
+              int a = hx ? ly * EXW + lx + sx : (ly + sy) * EXW + lx;
+              for (int c = 0; c < 4; c++) atomicAdd(&S.L[c][a], lo[c]);
+            }
+          } else {
+            int cnt = 0;
+            for (int dj = -1; dj <= 1; dj++)
+              for (int di = -1; di <= 1; di++)
+                if ((di != 0 || dj != 0) && valid(lx + di, ly + dj, ci + di, cj + dj, s)) cnt++;
+            if (cnt == 0) continue;
+            for (int dj = -1; dj <= 1; dj++)
+              for (int di = -1; di <= 1; di++)
+                if ((di != 0 || dj != 0) && valid(lx + di, ly + dj, ci + di, cj + dj, s)) {
+                  int a = (ly + dj) * EXW + lx + di;
+                  for (int c = 0; c < 4; c++) atomicAdd(&S.L[c][a], lo[c] / (double)cnt);
+                }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // the tile's own adjoints (unchanged ones included) to the output buffer
+    {
+      int lx = EXR + tid % EXT, ly = EXR + tid / EXT, i = x0 + lx, j = y0 + ly;
+      int q = ly * EXW + lx;
+      if (i < P.nx && j < P.ny) {
+        size_t o = (size_t)r * 4 * P.NC + cid(P, i, j);
+        for (int c = 0; c < 4; c++) A.lW2[o + (size_t)c * P.NC] = S.L[c][q];
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -269,6 +269,7 @@ static mm_status adj_alloc(mm_ctx* c) {
     A.lphi = A.lcy + M * nc;
   }
   AA(A.lvx, nc); AA(A.lvy, nc);
+  if (P.dim == 2) AA(A.lW2, M * 4 * nc);
   AA(A.linflow, 4);
   AA(A.lalpha, M * nc);
   (void)nv;
@@ -353,8 +354,17 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     if (D == 2)
       LAUNCH(k_a_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, A);
     LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
-    for (int sw = P.kext + 3; sw >= 0; sw--)
-      LAUNCH(k_a_ext<D>, dim3(256), dim3(256), P, c->B, A, sidx, sw);
+    if (D == 2) {
+      // tile-wise, on the tiles of the stage's own level set (its snapshot was
+      // classified on loading); lW is read throughout, lW2 written
+      LAUNCH(k_tiles, dim3(n_tiles(P)), dim3(256), P, c->B, sidx, sidx);
+      cpy(c, A.lW2, A.lW, M * 4 * nc * 8);
+      LAUNCH(k_a_ext_tiles, dim3(tile_grid(c).x, P.M), dim3(256), P, c->B, A, sidx);
+      cpy(c, A.lW, A.lW2, M * 4 * nc * 8);
+    } else {
+      for (int sw = P.kext + 3; sw >= 0; sw--)
+        LAUNCH(k_a_ext<D>, dim3(256), dim3(256), P, c->B, A, sidx, sw);
+    }
     LAUNCH(k_a_real<D>, gm, bl, P, c->B, A, sidx);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphi);
     if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);

@@ -326,7 +326,8 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
   LAUNCH(t_near_row<D>, tg, tb, P, c->B);
   LAUNCH(t_near_col<D>, tg, tb, P, c->B);
-  if (D == 2 && P.kext + 4 <= EXR) {
+  static_assert(EXR >= 8 + 4, "the tile frame covers every sweep (k_ext <= 8)");
+  if (D == 2) {
     LAUNCH(k_ext_tiles, dim3(tg.x, P.M), tb, P, c->B, sidx);
   } else {
     for (int sw = 0; sw < P.kext + 4; sw++)

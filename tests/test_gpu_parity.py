@@ -100,6 +100,16 @@ def test_rk2_variant(pk):
     assert_parity(o, s, label="rk2")
 
 
+@pytest.mark.parametrize("k_ext", [0, 4])
+def test_ghost_sweep_counts(pk, k_ext):
+    """Other numbers of upwind ghost sweeps than the default 8 (the mean
+    sweeps then start earlier; with 0 there are only the 4 mean sweeps)."""
+    w = wl.triple_point(nx=70, ny=30)
+    w["cfg"]["k_ext"] = k_ext
+    o, s = run_both(pk, w, 40)
+    assert_parity(o, s, label=f"k_ext={k_ext}")
+
+
 def test_single_material_2d_random(pk):
     ny, nx = 37, 70
     rng = np.random.default_rng(3)
