@@ -391,26 +391,10 @@ __global__ void k_dist_row(Params P, Bufs B) {
   b_dist_row<D>(P, B, i, j);
 }
 // column pass: d = min over dj of max(|dj|, row distance)
-__global__ void k_dist_col(Params P, Bufs B) {
-  CELL_LOOP_2D
-  int dc = RD, dl = RD;
-  for (int dj = -RD + 1; dj <= RD - 1; dj++) {
-    int jj = j + dj;
-    if (jj < 0 || jj >= P.ny) continue;
-    int kk = cid(P, i, jj);
-    int a = dj < 0 ? -dj : dj;
-    int c = B.tdc[kk] > a ? B.tdc[kk] : a;
-    int l = B.tdl[kk] > a ? B.tdl[kk] : a;
-    if (c < dc) dc = c;
-    if (l < dl) dl = l;
-  }
-  B.dcut[k] = (uint8_t)dc;
-  B.dls[k] = (uint8_t)dl;
-}
 // 2D classification and distances in one launch: a CX x CY block of cells
 // with a frame of RD - 1 cells (the reach of the distances) classified in LDS
 // from the material indicators (one more cell around) and the level set; the
-// capped Chebyshev distances of k_dist_row / k_dist_col then come from bit
+// capped Chebyshev distances of the row and column scans come from bit
 // masks of the frame's rows.  Same results, one pass over global memory.
 constexpr int CX = 32, CY = 16, CF = RD - 1;
 struct ClassDistSmem {
@@ -513,7 +497,6 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
   }
 }
 // next mixing stamp (device-resident so a captured step can be replayed)
-__global__ void k_stamp_next(Params P, Bufs B) { B.ctr[C_STAMP] += 1; }
 
 // ghost-band membership: OR of the real-material bits within Chebyshev 4
 template <int D>
@@ -533,13 +516,6 @@ MMD void b_near_row(const Params& P, const Bufs& B, int i, int j) {
     if (alpha_at<D>(P, B, r, kk) > 0.0) b |= 1u << r;
   }
   B.nrow[k] = (uint8_t)b;
-}
-template <int D>
-__global__ void k_near_row(Params P, Bufs B) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_near_row<D>(P, B, i, j);
 }
 template <int D>
 MMD void b_near_col(const Params& P, const Bufs& B, int i, int j) {
@@ -566,13 +542,6 @@ MMD void b_near_col(const Params& P, const Bufs& B, int i, int j) {
       if (take) B.glist[at] = k * 8 + r;
     }
   }
-}
-template <int D>
-__global__ void k_near_col(Params P, Bufs B) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_near_col<D>(P, B, i, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -761,13 +730,6 @@ MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
   B.W[o + (size_t)3 * P.NC + k] = w.p;
   B.Wit[(size_t)r * P.NC + k] = 1;
 }
-template <int D>
-__global__ void k_real(Params P, Bufs B, int sidx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_real<D>(P, B, i, j, sidx);
-}
 
 // CFL step size from the time-n state: max over real cells of
 // max(|u| + c, |v| + c); positive doubles order like their bit patterns
@@ -792,22 +754,6 @@ MMD void dt_finish(const Params& P, const Bufs& B, double smax) {
   B.scal[S_LX] = dt / P.dx;
   B.scal[S_LY] = dt / P.dy;
   B.scal[S_LV] = D == 2 ? dt / (P.dx * P.dy) : dt / P.dx;
-}
-template <int D>
-__global__ void k_dt(Params P, Bufs B, int sidx) {
-  __shared__ double red[256];
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  double w = 0.0;
-  if (i < P.nx && j < P.ny) w = b_dt_cell<D>(P, B, i, j, sidx);
-  red[tid] = w;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) atomicMax(&B.ctr[C_SMAX], (unsigned long long)__double_as_longlong(red[0]));
 }
 template <int D>
 __global__ void k_dt_fin(Params P, Bufs B) {
@@ -909,13 +855,6 @@ MMD void b_ext(const Params& P, const Bufs& B, int i, int j, int sidx, int sweep
     ext_one<D>(P, B, i, j, r, sidx, sweep);
   }
 }
-template <int D>
-__global__ void k_ext(Params P, Bufs B, int sidx, int sweep) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_ext<D>(P, B, i, j, sidx, sweep);
-}
 
 // ---------------------------------------------------------------------------
 // Reduced interface interaction (Sec. 2.3.2) in cut cells
@@ -980,13 +919,6 @@ MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int sta
     B.vit[k] = 1;
   }
 }
-template <int D>
-__global__ void k_iface(Params P, Bufs B, int sidx, int stage0) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_iface<D>(P, B, i, j, sidx, stage0);
-}
 
 // ---------------------------------------------------------------------------
 // Level-set advection velocity v^n (stage 0)
@@ -998,13 +930,6 @@ MMD void b_vreset(const Params& P, const Bufs& B, int i, int j) {
   (void)k;
   if (B.dls[k] > RV) return;
   B.vit[k] = 0;
-}
-template <int D>
-__global__ void k_vreset(Params P, Bufs B) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_vreset<D>(P, B, i, j);
 }
 template <int D>
 MMD void b_vext(const Params& P, const Bufs& B, int i, int j, int sweep) {
@@ -1045,13 +970,6 @@ MMD void b_vext(const Params& P, const Bufs& B, int i, int j, int sweep) {
   B.vy[k] = oy;
   B.vit[k] = (uint8_t)(sweep + 2);
 }
-template <int D>
-__global__ void k_vext(Params P, Bufs B, int sweep) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_vext<D>(P, B, i, j, sweep);
-}
 // remaining cells: velocity of the cell's own material; also keep the
 // time-n level set for the whole reach of this step's band
 template <int D>
@@ -1066,13 +984,6 @@ MMD void b_vfill(const Params& P, const Bufs& B, int i, int j, int sidx) {
   Prim w = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], B.chi[k], i, j, valid);
   B.vx[k] = valid ? w.u : 0.0;
   B.vy[k] = valid ? w.v : 0.0;
-}
-template <int D>
-__global__ void k_vfill(Params P, Bufs B, int sidx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_vfill<D>(P, B, i, j, sidx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1239,14 +1150,6 @@ MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int
     if ((occ >> r) & 1)
       for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[r][v]);
   B.occ[didx][k] = (uint8_t)occ;
-}
-template <int D>
-__global__ void k_flux_band(Params P, Bufs B, int sidx, int nidx, int didx,
-                            double bcoef, double ccoef) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_flux_band<D>(P, B, i, j, sidx, nidx, didx, bcoef, ccoef);
 }
 
 // Bulk update: cells with no cut cell within three cells and only their own
@@ -1620,26 +1523,12 @@ MMD void b_ls(const Params& P, const Bufs& B, int i, int j, double bcoef, double
   B.ctmp[k] = (uint8_t)br;
 }
 template <int D>
-__global__ void k_ls(Params P, Bufs B, double bcoef, double ccoef) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_ls<D>(P, B, i, j, bcoef, ccoef);
-}
-template <int D>
 MMD void b_ls_commit(const Params& P, const Bufs& B, int i, int j) {
   int k = cid(P, i, j);
   (void)k;
   if (errored(B) || B.dls[k] > 3) return;
   B.phi[k] = B.ptmp[k];
   B.chi[k] = B.ctmp[k];
-}
-template <int D>
-__global__ void k_ls_commit(Params P, Bufs B) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_ls_commit<D>(P, B, i, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,13 +1635,6 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     }
   }
 }
-template <int D>
-__global__ void k_mix1(Params P, Bufs B, int didx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_mix1<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP], 0, P.M);
-}
 
 template <int D>
 // materials r0 <= r < r1 of cell (i, j); with word_occ the occupancy bits
@@ -1828,13 +1710,6 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     }
   }
   if (touched && !word_occ) occp[k] = (uint8_t)occ;
-}
-template <int D>
-__global__ void k_mix2(Params P, Bufs B, int didx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  b_mix2<D>(P, B, i, j, didx, (uint32_t)B.ctr[C_STAMP], 0, P.M, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -2187,7 +2062,6 @@ MMD int tile_w(const Params& P) { return P.dim == 2 ? 16 : 256; }
 MMD int tile_h(const Params& P) { return P.dim == 2 ? 16 : 1; }
 MMD int tiles_x(const Params& P) { return (P.nx + tile_w(P) - 1) / tile_w(P); }
 
-__global__ void k_tiles_reset(Params P, Bufs B) { B.ctr[C_NTILES] = 0; }
 
 __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
   int tw = tile_w(P), th = tile_h(P);
@@ -2239,14 +2113,10 @@ __global__ void __launch_bounds__(256) t_real(Params P, Bufs B, int sidx) {
 }
 TILE_KERNEL(t_near_row, b_near_row, )
 TILE_KERNEL(t_near_col, b_near_col, )
-TILE_KERNEL(t_ext, b_ext, COMMA int sidx COMMA int sweep, COMMA sidx COMMA sweep)
 TILE_KERNEL(t_vreset, b_vreset, )
 TILE_KERNEL(t_iface, b_iface, COMMA int sidx COMMA int stage0, COMMA sidx COMMA stage0)
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
-TILE_KERNEL(t_flux_band, b_flux_band,
-            COMMA int sidx COMMA int nidx COMMA int didx COMMA double bc COMMA double cc,
-            COMMA sidx COMMA nidx COMMA didx COMMA bc COMMA cc)
 TILE_KERNEL(t_ls, b_ls, COMMA double bc COMMA double cc, COMMA bc COMMA cc)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
 TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
