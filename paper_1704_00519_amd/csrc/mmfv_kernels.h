@@ -141,6 +141,28 @@ MMD double apx(const Params& P, const Bufs& B, int r, int i, int j) {
   }
   return use ? a : (h == r ? 1.0 : 0.0);
 }
+// aperture of the face between (i, j) and its +1 neighbour in direction dir
+// (0: x, as apx; 1: y, as apy) with the direction a value, so that lanes of
+// different directions run the same instructions
+MMD double apd(const Params& P, const Bufs& B, int r, int i, int j, int dir) {
+  int kl = cid(P, i, j), kr = dir == 0 ? cid(P, i + 1, j) : cid(P, i, j + 1);
+  int q = dir == 0 ? i : j, n = dir == 0 ? P.nx : P.ny;
+  uint8_t cl = B.cut[kl], cr = B.cut[kr], hl = B.chi[kl], hr = B.chi[kr];
+  double a = (dir == 0 ? B.ax : B.ay)[(size_t)r * P.NC + kl];
+  bool use;
+  int h;
+  if (q < 0) {
+    use = cr;
+    h = hr;
+  } else if (q >= n - 1) {
+    use = cl;
+    h = hl;
+  } else {
+    use = cl && cr;
+    h = cl ? hr : hl;
+  }
+  return use ? a : (h == r ? 1.0 : 0.0);
+}
 // aperture of the y-face j+1/2 of column i (j in [-1, ny-1])
 MMD double apy(const Params& P, const Bufs& B, int r, int i, int j) {
   int kb = cid(P, i, j), kt = cid(P, i, j + 1);
@@ -1787,13 +1809,10 @@ __global__ void __launch_bounds__(256) k_flux_list(Params P, Bufs B, int sidx, i
     int i = k % P.NX - H, j = k / P.NX - P.HY;
     if (tid < cpb) sOcc[tid] = 0;
     if (act) {
-      double A;
-      int fi, fj, dir;
-      bool count;
-      if (f == 0) { A = apx<D>(P, B, r, i - 1, j); fi = i - 1; fj = j; dir = 0; count = i == 0; }
-      else if (f == 1) { A = apx<D>(P, B, r, i, j); fi = i; fj = j; dir = 0; count = true; }
-      else if (f == 2) { A = apy(P, B, r, i, j - 1); fi = i; fj = j - 1; dir = 1; count = j == 0; }
-      else { A = apy(P, B, r, i, j); fi = i; fj = j; dir = 1; count = true; }
+      // face f: 0 low x, 1 high x, 2 low y, 3 high y
+      int dir = f >> 1, fi = f == 0 ? i - 1 : i, fj = f == 2 ? j - 1 : j;
+      bool count = f == 0 ? i == 0 : (f == 2 ? j == 0 : true);
+      double A = apd(P, B, r, fi, fj, dir);
       double F[4] = {0.0, 0.0, 0.0, 0.0};
       if (A > 0.0) face_flux<D>(P, B, Qs, os, r, fi, fj, dir, count, F);
       for (int v = 0; v < 4; v++) sF[tid][v] = A > 0.0 ? A * F[v] : 0.0;
