@@ -1239,12 +1239,17 @@ MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, i
   return true;
 }
 
-// Tile of the bulk kernel: 28 x 16 cells (896 = 32 x 28 and 384 = 24 x 16
-// tile the 896 x 384 grid exactly), 512 threads so that both face sets
-// (29 x 16 and 28 x 17) take one pass; 40.7 KB of LDS.  The register budget
-// is left to the compiler: a tighter one spills to scratch, and the spill
-// traffic outweighs the extra waves.
+// Tiles of the bulk kernel: 28 x 16 cells with 512 threads, so that both
+// face sets (29 x 16 and 28 x 17) take one pass (40.7 KB of LDS), for grids
+// of a few tiles per compute unit (896 x 384: three); 28 x 32 cells with
+// 1024 threads (73.6 KB) for larger grids, where the smaller frame overhead
+// wins once every CU has several tiles to work through (measured crossover
+// between 3 and 9 tiles of 28 x 16 per CU).  The register budget is left to
+// the compiler: a tighter one spills to scratch, and the spill traffic
+// outweighs the extra waves.
 constexpr int BULK_BX = 28, BULK_BY = 16, BULK_NT = 512;
+constexpr int BULK_BYW = 32, BULK_NTW = 1024;
+constexpr int BULK_WIDE_TILES_PER_CU = 6;
 
 template <int BX, int BY, int NT>
 __global__ void __launch_bounds__(NT)

@@ -32,6 +32,7 @@ struct mm_ctx {
   hipGraphExec_t step_x = nullptr;
   bool graph_off = false;
   std::vector<hipEvent_t> ev;  // pairs around bulk launches
+  bool bulk_wide = false;      // 28 x 32 bulk tiles (large grids)
   size_t ev_used = 0;
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
@@ -207,6 +208,14 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   c->stream = (hipStream_t)hip_stream;
   c->P = make_params(cfg);
   const Params& P = c->P;
+  {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    long tiles = (long)((P.nx + BULK_BX - 1) / BULK_BX) * ((P.ny + BULK_BY - 1) / BULK_BY);
+    c->bulk_wide = P.dim == 2 && tiles > (long)BULK_WIDE_TILES_PER_CU * (cus > 0 ? cus : 256);
+    (void)hipGetLastError();
+  }
 
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
   Bufs& B = c->B;
@@ -346,9 +355,14 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   if (s == 0) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
   prof_mark(c);
   if (D == 2)
-    LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT>),
-           dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BY - 1) / BULK_BY), dim3(BULK_NT),
-           P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
+    if (c->bulk_wide)
+      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BYW, BULK_NTW>),
+             dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BYW - 1) / BULK_BYW),
+             dim3(BULK_NTW), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
+    else
+      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT>),
+             dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BY - 1) / BULK_BY),
+             dim3(BULK_NT), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
   else
     LAUNCH(k_flux_bulk1, dim3((P.nx + T1 - 1) / T1), dim3(T1), P, c->B, sidx, nidx, didx, b,
            cc, s == 0 ? 1 : 0);
