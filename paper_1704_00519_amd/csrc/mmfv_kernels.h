@@ -41,7 +41,10 @@ struct Bufs {
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
-       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST, C_N };
+       C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST,
+       // workgroups of the current launch that have finished (the last one
+       // finishes the launch's work and sets the counter back to zero)
+       C_DTDONE, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 // book-keeping regions of MAXM x 4 doubles each: accumulated net boundary
 // inflow and its compensation, accumulated exchange and its compensation,
@@ -319,36 +322,70 @@ __global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
   if (t >= P.ny * 2 * H * P.M) return;
   b_bc_W_x<D>(P, B, t, sidx);
 }
-__global__ void k_bc_W_y(Params P, Bufs B, int sidx) {
+// state that the x-side frame gets at ghost cell (i, j) of material r, for
+// i outside [0, nx) and j inside [0, ny)
+MMD Prim bc_x_state(const Params& P, const Bufs& B, int sidx, int r, int i, int j,
+                    bool& valid) {
+  int type = i < 0 ? P.bc[0] : P.bc[1];
+  int si = i < 0 ? src_lo(i, type) : src_hi(i, P.nx, type);
+  Prim w;
+  if (type == 2 && r == P.inflow_mat) {
+    w.r = P.inflow_W[0];
+    w.u = P.inflow_W[1];
+    w.v = P.inflow_W[2];
+    w.p = P.inflow_W[3];
+    valid = true;
+    return w;
+  }
+  w = Wget<2>(P, B, B.Q[sidx], B.occ[sidx], r, si, j, valid);
+  w.u = w.u * (type == 1 ? -1.0 : 1.0);
+  return w;
+}
+// both frames of the state buffer in one launch (2D): threads below
+// ny * 2H * M take the x sides of rows [0, ny), the others the y sides of
+// columns [-H, nx + H).  A corner cell gets the y-side map applied to the
+// x-side state of its source row, the value an x pass followed by a y pass
+// leaves there; every source is an interior cell, so no thread reads what
+// another writes.
+__global__ void k_bc_W2(Params P, Bufs B, int sidx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int ncol = P.nx + 2 * H;
-  if (t >= ncol * 2 * H * P.M) return;
-  int r = t / (ncol * 2 * H);
-  int rem = t % (ncol * 2 * H);
-  int i = rem / (2 * H) - H, q = rem % (2 * H);
-  int j, sj, type;
-  if (q < H) {
-    j = -1 - q;
-    type = P.bc[2];
-    sj = src_lo(j, type);
+  if (t == 0) B.ctr[C_NBAND] = 0;  // the band list is rebuilt by k_bulkflag
+  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
+  if (t >= (nxs + nys) * P.M) return;
+  int r, i, j;
+  bool valid;
+  Prim w;
+  if (t < nxs * P.M) {
+    r = t / nxs;
+    int rem = t % nxs, q = rem % (2 * H);
+    j = rem / (2 * H);
+    i = q < H ? -1 - q : P.nx + (q - H);
+    w = bc_x_state(P, B, sidx, r, i, j, valid);
   } else {
-    j = P.ny + (q - H);
-    type = P.bc[3];
-    sj = src_hi(j, P.ny, type);
+    t -= nxs * P.M;
+    r = t / nys;
+    int rem = t % nys, q = rem % (2 * H);
+    i = rem / (2 * H) - H;
+    j = q < H ? -1 - q : P.ny + (q - H);
+    int type = q < H ? P.bc[2] : P.bc[3];
+    int sj = q < H ? src_lo(j, type) : src_hi(j, P.ny, type);
+    if (type == 2 && r == P.inflow_mat) {
+      w.r = P.inflow_W[0];
+      w.u = P.inflow_W[1];
+      w.v = P.inflow_W[2];
+      w.p = P.inflow_W[3];
+      valid = true;
+    } else {
+      w = i < 0 || i >= P.nx ? bc_x_state(P, B, sidx, r, i, sj, valid)
+                             : Wget<2>(P, B, B.Q[sidx], B.occ[sidx], r, i, sj, valid);
+      w.v = w.v * (type == 1 ? -1.0 : 1.0);
+    }
   }
   int k = cid(P, i, j);
   size_t o = (size_t)r * 4 * P.NC;
-  if (type == 2 && r == P.inflow_mat) {
-    for (int v = 0; v < 4; v++) B.W[o + (size_t)v * P.NC + k] = P.inflow_W[v];
-    B.Wit[(size_t)r * P.NC + k] = 1;
-    return;
-  }
-  bool valid;
-  Prim w = Wget<2>(P, B, B.Q[sidx], B.occ[sidx], r, i, sj, valid);
-  double sy = type == 1 ? -1.0 : 1.0;
   B.W[o + k] = w.r;
   B.W[o + (size_t)P.NC + k] = w.u;
-  B.W[o + (size_t)2 * P.NC + k] = w.v * sy;
+  B.W[o + (size_t)2 * P.NC + k] = w.v;
   B.W[o + (size_t)3 * P.NC + k] = w.p;
   B.Wit[(size_t)r * P.NC + k] = valid ? 1 : 0;
 }
@@ -783,7 +820,6 @@ __global__ void k_dt_fin(Params P, Bufs B) {
   B.ctr[C_SMAX] = 0;
   dt_finish<D>(P, B, smax);
 }
-__global__ void k_time_advance(Params P, Bufs B) { B.scal[S_T] += B.scal[S_DT]; }
 
 // ---------------------------------------------------------------------------
 // Ghost states: Jacobi sweeps over the ghost band of every material
@@ -1022,7 +1058,8 @@ MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int 
   B.bulk[k] = is_bulk<D>(P, B, k, sidx, nidx) ? 1 : 0;
 }
 // Bulk flags for the stage, the compact list of all other cells, and (at
-// stage 0) the CFL maximum.  Every thread reaches the barriers.
+// stage 0) the CFL maximum and from it, in the last workgroup to finish, the
+// step size.  Every thread reaches the barriers.
 template <int D>
 __global__ void __launch_bounds__(256) k_bulkflag(Params P, Bufs B, int sidx, int nidx,
                                                   int with_dt) {
@@ -1053,8 +1090,18 @@ __global__ void __launch_bounds__(256) k_bulkflag(Params P, Bufs B, int sidx, in
       if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
       __syncthreads();
     }
-    if (tid == 0)
+    if (tid == 0) {
       atomicMax(&B.ctr[C_SMAX], (unsigned long long)__double_as_longlong(red[0]));
+      // count this workgroup as finished; the last one sets the step size
+      __threadfence();
+      unsigned long long done = atomicAdd(&B.ctr[C_DTDONE], 1ull);
+      if (done + 1 == (unsigned long long)gridDim.x * gridDim.y) {
+        __threadfence();
+        double smax = __longlong_as_double((long long)atomicExch(&B.ctr[C_SMAX], 0ull));
+        B.ctr[C_DTDONE] = 0;
+        dt_finish<D>(P, B, smax);
+      }
+    }
   }
 }
 
@@ -1977,6 +2024,7 @@ MMD int cons_rows(const Params& P) { return P.dim == 2 ? P.ny + P.nx : 1; }
 // (exchange); y is the material.  Partials cpart[x][r][8]: net boundary
 // inflow, exchange.
 constexpr int CONS_ROWS = 128;
+
 template <int D>
 __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, int nbb) {
   __shared__ double red[4 * 8];
@@ -1986,6 +2034,7 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
   int r = blockIdx.y;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* part = B.cpart + ((size_t)blockIdx.x * P.M + r) * 8;
+  bool any = true;
   if ((int)blockIdx.x < nbb) {
     // thread t: face (side t & 1) of row/column q
     int t = threadIdx.x, row = t >> 1, side = t & 1;
@@ -2001,34 +2050,34 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
       for (int v = 0; v < 4; v++) acc[v] = l * (face[row][0][v] - face[row][1][v]);
     }
   } else {
-    long q0 = (long)(blockIdx.x - nbb) * CONS_CH, n = (long)P.nx * P.ny;
-    bool any = false;
+    // cell indices fit 32 bits (the cell count NC is an int)
+    int q0 = ((int)blockIdx.x - nbb) * CONS_CH, n = P.nx * P.ny;
+    bool mine = false;
     double lv = B.scal[S_LV];
     for (int m = threadIdx.x; m < CONS_CH; m += 256) {
-      long q = q0 + m;
+      int q = q0 + m;
       if (q >= n) break;
-      int k = cid(P, (int)(q % P.nx), (int)(q / P.nx));
+      int k = cid(P, q % P.nx, q / P.nx);
       if (!B.cut[k]) continue;
-      any = true;
+      mine = true;
       for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + k];
     }
-    if (!__syncthreads_or(any)) {
-      if (threadIdx.x < 8) part[threadIdx.x] = 0.0;
-      return;
-    }
+    any = __syncthreads_or(mine);
   }
-  block_sum8(acc, red);
+  if (any) block_sum8(acc, red);
   if (threadIdx.x == 0)
-    for (int v = 0; v < 8; v++) part[v] = acc[v];
+    for (int v = 0; v < 8; v++) part[v] = any ? acc[v] : 0.0;
 }
 
-// combine the partials of nblk workgroups in a fixed order (eight
-// interleaved running sums, then their sum) and add the stage totals,
-// weighted by w, to the running sums (one thread per material and quantity)
-__global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w) {
-  // one wavefront per (material, quantity): strided partial sums, then a
-  // butterfly whose lane 0 result has a fixed order (reproducible)
+// combine the partials of nblk workgroups in a fixed order and add the
+// stage totals, weighted by w, to the running sums; one wavefront per
+// material and quantity (64 interleaved running sums, then a butterfly whose
+// lane 0 result has a fixed order, so runs are reproducible).  With advance,
+// the time moves on by the step size (after the last stage of a step).
+__global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w,
+                                                 int advance) {
   int x = blockIdx.x, t = threadIdx.x;
+  if (advance && x == 0 && t == 0) B.scal[S_T] += B.scal[S_DT];
   if (x >= P.M * 8) return;
   int r = x / 8, v = x % 8;
   double a = 0.0;
@@ -2144,6 +2193,48 @@ TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 TILE_KERNEL(t_ls, b_ls, COMMA double bc COMMA double cc, COMMA bc COMMA cc)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
 TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
+
+// Commit of the new level set and its frame in one launch (2D).  Workgroups
+// below ntb commit the listed tiles; the others fill the ghost frame (x sides
+// of rows [0, ny), then y sides of columns [-H, nx + H), a corner from the
+// source cell of both maps) from the committed value of the source cell: the
+// new one where the commit writes it (band cells, dls <= 3, always inside a
+// listed tile), the old one elsewhere.  A frame thread therefore reads only
+// words that no commit thread writes.
+__global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb) {
+  if ((int)blockIdx.x < ntb) {
+    int ntile = (int)B.ctr[C_NTILES];
+    int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
+    for (int t = blockIdx.x; t < ntile; t += ntb) {
+      int tile = B.tiles[t];
+      int i = (tile % ntx) * tw + (int)threadIdx.x % tw;
+      int j = (tile / ntx) * th + (int)threadIdx.x / tw;
+      if (i < P.nx && j < P.ny) b_ls_commit<2>(P, B, i, j);
+    }
+    return;
+  }
+  int t = ((int)blockIdx.x - ntb) * (int)blockDim.x + (int)threadIdx.x;
+  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
+  if (t >= nxs + nys) return;
+  int i, j, si, sj;
+  if (t < nxs) {
+    int q = t % (2 * H);
+    j = sj = t / (2 * H);
+    i = q < H ? -1 - q : P.nx + (q - H);
+  } else {
+    t -= nxs;
+    int q = t % (2 * H);
+    i = si = t / (2 * H) - H;
+    j = q < H ? -1 - q : P.ny + (q - H);
+    sj = q < H ? src_lo(j, P.bc[2]) : src_hi(j, P.ny, P.bc[3]);
+  }
+  if (i < 0) si = src_lo(i, P.bc[0]);
+  if (i >= P.nx) si = src_hi(i, P.nx, P.bc[1]);
+  int k = cid(P, i, j), ks = cid(P, si, sj);
+  bool upd = !errored(B) && B.dls[ks] <= 3;
+  B.phi[k] = upd ? B.ptmp[ks] : B.phi[ks];
+  B.chi[k] = upd ? B.ctmp[ks] : B.chi[ks];
+}
 template <int D>
 __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
   // one material per grid row: the sources of different materials are

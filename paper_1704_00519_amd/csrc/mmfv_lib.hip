@@ -325,10 +325,10 @@ static void build_tiles(mm_ctx* c, int didx, int nidx) {
 
 // first half of a stage: real and ghost states, interface exchange (and at
 // stage 0 the level-set velocity and dt), fluxes and the RK update into
-// buffer didx, conservation book-keeping
+// buffer didx, conservation book-keeping (and with advance, the time)
 template <int D>
 static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
-                        double w) {
+                        double w, bool advance) {
   const Params& P = c->P;
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
@@ -342,9 +342,11 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
     for (int sw = 0; sw < P.kext + 4; sw++)
       LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
   }
-  LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
   if (D == 2)
-    LAUNCH(k_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, sidx);
+    LAUNCH(k_bc_W2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B,
+           sidx);
+  else
+    LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
   if (s == 0) LAUNCH(t_vreset<D>, tg, tb, P, c->B);
   LAUNCH(t_iface<D>, tg, tb, P, c->B, sidx, s == 0 ? 1 : 0);
   if (s == 0) {
@@ -352,7 +354,6 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
   LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx, s == 0 ? 1 : 0);
-  if (s == 0) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), P, c->B);
   prof_mark(c);
   if (D == 2)
     if (c->bulk_wide)
@@ -371,7 +372,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   LAUNCH(k_flux_list<D>, dim3(2048), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
   LAUNCH(k_cons_part<D>, dim3(cons_blocks(P), P.M), dim3(256), P, c->B, sidx,
          cons_bnd_blocks(P));
-  LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w);
+  LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w, advance ? 1 : 0);
 }
 
 // second half: level-set stage and its frame, classification, geometry and
@@ -385,8 +386,14 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
   dim3 tg = tile_grid(c), tb(256);
   LAUNCH(t_ls<D>, tg, tb, P, c->B, b, cc);
   if (!commit) return;
-  LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
-  bc_ls<D>(c);
+  if (D == 2) {
+    long nframe = ((long)P.ny + P.nx + 2 * H) * 2 * H;
+    LAUNCH(k_ls_commit_bc, dim3(tg.x + (unsigned)((nframe + 255) / 256)), tb, P, c->B,
+           (int)tg.x);
+  } else {
+    LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
+    bc_ls<D>(c);
+  }
   classify<D>(c);
   build_tiles<D>(c, didx, nidx);
   LAUNCH(t_geom<D>, tg, tb, P, c->B, didx, (const double*)nullptr);
@@ -402,8 +409,9 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
 
 template <int D>
 static void stage(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
-                  double w, double* save_Q = nullptr, uint8_t* save_occ = nullptr) {
-  stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w);
+                  double w, double* save_Q = nullptr, uint8_t* save_occ = nullptr,
+                  bool advance = false) {
+  stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w, advance);
   stage_levelset<D>(c, didx, nidx, b, cc, true, save_Q, save_occ);
 }
 
@@ -430,9 +438,10 @@ template <int D>
 static void one_step(mm_ctx* c) {
   double b[3], cc[3], w[3];
   int ns = rk_coefs(c->cfg, b, cc, w);
+  // the last stage's book-keeping also advances the time
   for (int s = 0; s < ns; s++)
-    stage<D>(c, s, stage_src(s), 0, stage_dst(s, ns), b[s], cc[s], w[s]);
-  hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(1), 0, c->stream, c->P, c->B);
+    stage<D>(c, s, stage_src(s), 0, stage_dst(s, ns), b[s], cc[s], w[s], nullptr, nullptr,
+             s == ns - 1);
 }
 
 static mm_status stage_inputs(mm_ctx* c, size_t bytes, const void* src, int ptr_kind,
