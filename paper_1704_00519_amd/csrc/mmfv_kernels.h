@@ -52,6 +52,7 @@ constexpr unsigned long long NO_ERR = ~0ull;
 enum { CONS_BND = 0, CONS_BNDC = 1, CONS_X = 2, CONS_XC = 3, CONS_Q = 4, CONS_N = 5 * MAXM * 4 };
 // cells (or boundary rows and columns) per workgroup of the partial sums
 constexpr int CONS_CH = 2048;
+static_assert(CONS_CH % 256 == 0, "cells of a book-keeping workgroup");
 
 MMD int cid(const Params& P, int i, int j) { return (j + P.HY) * P.NX + i + H; }
 MMD bool interior(const Params& P, int i, int j) {
@@ -2050,17 +2051,26 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
       for (int v = 0; v < 4; v++) acc[v] = l * (face[row][0][v] - face[row][1][v]);
     }
   } else {
-    // cell indices fit 32 bits (the cell count NC is an int)
+    // cell indices fit 32 bits (the cell count NC is an int); the cut flags
+    // of a thread's cells are all loaded before the first is tested
+    constexpr int NQ = CONS_CH / 256;
     int q0 = ((int)blockIdx.x - nbb) * CONS_CH, n = P.nx * P.ny;
+    int kq[NQ];
+    uint8_t cq[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; u++) {
+      int q = q0 + (int)threadIdx.x + u * 256;
+      bool ok = q < n;
+      kq[u] = cid(P, ok ? q % P.nx : 0, ok ? q / P.nx : 0);
+      cq[u] = B.cut[kq[u]] & (ok ? 0xff : 0);
+    }
     bool mine = false;
     double lv = B.scal[S_LV];
-    for (int m = threadIdx.x; m < CONS_CH; m += 256) {
-      int q = q0 + m;
-      if (q >= n) break;
-      int k = cid(P, q % P.nx, q / P.nx);
-      if (!B.cut[k]) continue;
+#pragma unroll
+    for (int u = 0; u < NQ; u++) {
+      if (!cq[u]) continue;
       mine = true;
-      for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + k];
+      for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + kq[u]];
     }
     any = __syncthreads_or(mine);
   }
