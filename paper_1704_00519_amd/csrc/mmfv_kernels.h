@@ -1841,8 +1841,8 @@ __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* ch
 // of the left face then combines them into the stage update.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(256) k_flux_list(Params P, Bufs B, int sidx, int nidx,
-                                                   int didx, double bcoef, double ccoef) {
+MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, int didx,
+                          double bcoef, double ccoef, int bx, int nbx) {
   // threads are (cell, material, face): the aperture-scaled flux of one
   // material across one face of one listed cell goes through LDS to the
   // thread that combines the faces of (cell, material) into its update
@@ -1855,7 +1855,7 @@ __global__ void __launch_bounds__(256) k_flux_list(Params P, Bufs B, int sidx, i
   if (errored(B)) return;
   const double* Qs = B.Q[sidx];
   const uint8_t* os = B.occ[sidx];
-  for (int base = blockIdx.x * cpb; base < nb; base += gridDim.x * cpb) {
+  for (int base = bx * cpb; base < nb; base += nbx * cpb) {
     int idx = base + c;
     bool act = c < cpb && idx < nb;
     int k = act ? B.blist[idx] : 0;
@@ -2020,26 +2020,25 @@ MMD void cons_boundary(const Params& P, const Bufs& B, const double* Qs, const u
 
 MMD int cons_rows(const Params& P) { return P.dim == 2 ? P.ny + P.nx : 1; }
 
-// Grid (nbb + ncb, M): workgroups x < nbb take 128 boundary rows/columns
-// each (one thread per boundary face), the others CONS_CH cells each
-// (exchange); y is the material.  Partials cpart[x][r][8]: net boundary
-// inflow, exchange.
+// Workgroup x of material r (x in [0, nbb + ncb)): x < nbb takes 128
+// boundary rows/columns (one thread per boundary face), the others CONS_CH
+// cells each (exchange).  Partials cpart[x][r][8]: net boundary inflow,
+// exchange.
 constexpr int CONS_ROWS = 128;
 
 template <int D>
-__global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, int nbb) {
+MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int bx, int r) {
   __shared__ double red[4 * 8];
   __shared__ double face[CONS_ROWS][2][4];
   const double* Qs = B.Q[sidx];
   const uint8_t* os = B.occ[sidx];
-  int r = blockIdx.y;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double* part = B.cpart + ((size_t)blockIdx.x * P.M + r) * 8;
+  double* part = B.cpart + ((size_t)bx * P.M + r) * 8;
   bool any = true;
-  if ((int)blockIdx.x < nbb) {
+  if (bx < nbb) {
     // thread t: face (side t & 1) of row/column q
     int t = threadIdx.x, row = t >> 1, side = t & 1;
-    long q = (long)blockIdx.x * CONS_ROWS + row;
+    long q = (long)bx * CONS_ROWS + row;
     bool ok = q < cons_rows(P);
     double f[4] = {0, 0, 0, 0};
     int dir = q < P.ny ? 0 : 1;
@@ -2054,7 +2053,7 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
     // cell indices fit 32 bits (the cell count NC is an int); the cut flags
     // of a thread's cells are all loaded before the first is tested
     constexpr int NQ = CONS_CH / 256;
-    int q0 = ((int)blockIdx.x - nbb) * CONS_CH, n = P.nx * P.ny;
+    int q0 = (bx - nbb) * CONS_CH, n = P.nx * P.ny;
     int kq[NQ];
     uint8_t cq[NQ];
 #pragma unroll
@@ -2077,6 +2076,22 @@ __global__ void __launch_bounds__(256) k_cons_part(Params P, Bufs B, int sidx, i
   if (any) block_sum8(acc, red);
   if (threadIdx.x == 0)
     for (int v = 0; v < 8; v++) part[v] = any ? acc[v] : 0.0;
+}
+
+// Band fluxes and updates together with the book-keeping partials, in one
+// launch: workgroups below ncons * M compute partials (workgroup x of
+// material r), the other nfb the band list.  The partials read only the
+// stage's source state, fluxes and exchange terms, none of which the band
+// update writes, so their latency hides behind the band work.
+template <int D>
+__global__ void __launch_bounds__(256) k_flux_list_cons(Params P, Bufs B, int sidx, int nidx,
+                                                        int didx, double bcoef, double ccoef,
+                                                        int nfb, int nbb, int ncons) {
+  int b = blockIdx.x, nc = ncons * P.M;
+  if (b < nc)
+    cons_part_block<D>(P, B, sidx, nbb, b % ncons, b / ncons);
+  else
+    flux_list_blocks<D>(P, B, sidx, nidx, didx, bcoef, ccoef, b - nc, nfb);
 }
 
 // combine the partials of nblk workgroups in a fixed order and add the

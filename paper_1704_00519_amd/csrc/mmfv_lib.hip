@@ -369,9 +369,9 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
            cc, s == 0 ? 1 : 0);
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
-  LAUNCH(k_flux_list<D>, dim3(2048), dim3(256), P, c->B, sidx, nidx, didx, b, cc);
-  LAUNCH(k_cons_part<D>, dim3(cons_blocks(P), P.M), dim3(256), P, c->B, sidx,
-         cons_bnd_blocks(P));
+  constexpr int FLUX_LIST_BLOCKS = 2048;
+  LAUNCH(k_flux_list_cons<D>, dim3(cons_blocks(P) * P.M + FLUX_LIST_BLOCKS), dim3(256), P, c->B,
+         sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P), cons_blocks(P));
   LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w, advance ? 1 : 0);
 }
 
