@@ -2078,43 +2078,31 @@ MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int 
     for (int v = 0; v < 8; v++) part[v] = any ? acc[v] : 0.0;
 }
 
-// Band fluxes and updates together with the book-keeping partials, in one
-// launch: workgroups below ncons * M compute partials (workgroup x of
-// material r), the other nfb the band list.  The partials read only the
-// stage's source state, fluxes and exchange terms, none of which the band
-// update writes, so their latency hides behind the band work.
-template <int D>
-__global__ void __launch_bounds__(256) k_flux_list_cons(Params P, Bufs B, int sidx, int nidx,
-                                                        int didx, double bcoef, double ccoef,
-                                                        int nfb, int nbb, int ncons) {
-  int b = blockIdx.x, nc = ncons * P.M;
-  if (b < nc)
-    cons_part_block<D>(P, B, sidx, nbb, b % ncons, b / ncons);
-  else
-    flux_list_blocks<D>(P, B, sidx, nidx, didx, bcoef, ccoef, b - nc, nfb);
-}
 
-// combine the partials of nblk workgroups in a fixed order and add the
-// stage totals, weighted by w, to the running sums; one wavefront per
-// material and quantity (64 interleaved running sums, then a butterfly whose
-// lane 0 result has a fixed order, so runs are reproducible).  With advance,
-// the time moves on by the step size (after the last stage of a step).
-__global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w,
-                                                 int advance) {
-  int x = blockIdx.x, t = threadIdx.x;
-  if (advance && x == 0 && t == 0) B.scal[S_T] += B.scal[S_DT];
-  if (x >= P.M * 8) return;
+// combine the partials of nblk workgroups for (material r, quantity v),
+// x = 8 r + v, in a fixed order (64 interleaved running sums, then a
+// butterfly whose lane 0 result has a fixed order, so runs are reproducible)
+// and add the stage total, weighted by w, to the running sums; one wavefront
+MMD void cons_fin_wave(const Params& P, const Bufs& B, int nblk, double w, int x, int lane) {
   int r = x / 8, v = x % 8;
   double a = 0.0;
-  for (int b = t; b < nblk; b += 64) a += B.cpart[((size_t)b * P.M + r) * 8 + v];
+  for (int b = lane; b < nblk; b += 64) a += B.cpart[((size_t)b * P.M + r) * 8 + v];
   for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-  if (t != 0) return;
+  if (lane != 0) return;
   if (v < 4)
     neumaier_add(&B.cons[(CONS_BND * MAXM + r) * 4 + v], &B.cons[(CONS_BNDC * MAXM + r) * 4 + v],
                  w * a);
   else
     neumaier_add(&B.cons[(CONS_X * MAXM + r) * 4 + v - 4],
                  &B.cons[(CONS_XC * MAXM + r) * 4 + v - 4], w * a);
+}
+// one wavefront per (material, quantity); with advance, the time moves on by
+// the step size (after the last stage of a step)
+__global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w,
+                                                 int advance) {
+  int x = blockIdx.x, t = threadIdx.x;
+  if (advance && x == 0 && t == 0) B.scal[S_T] += B.scal[S_DT];
+  if (x < P.M * 8) cons_fin_wave(P, B, nblk, w, x, t);
 }
 
 // this thread's part of the sums of Q (state buffer sidx) of material r over
@@ -2181,17 +2169,22 @@ __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int n
   }
 }
 
-// run body(i, j) over the cells of the listed tiles; 256 threads per block
+// run body(i, j) over the cells of the listed tiles, workgroup bx of nbx;
+// 256 threads per workgroup
 template <typename F>
-MMD void for_tiles(const Params& P, const Bufs& B, F body) {
+MMD void for_tiles_n(const Params& P, const Bufs& B, int bx, int nbx, F body) {
   int ntile = (int)B.ctr[C_NTILES];
   int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
-  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+  for (int t = bx; t < ntile; t += nbx) {
     int tile = B.tiles[t];
     int i = (tile % ntx) * tw + (int)threadIdx.x % tw;
     int j = (tile / ntx) * th + (int)threadIdx.x / tw;
     if (i < P.nx && j < P.ny) body(i, j);
   }
+}
+template <typename F>
+MMD void for_tiles(const Params& P, const Bufs& B, F body) {
+  for_tiles_n(P, B, (int)blockIdx.x, (int)gridDim.x, body);
 }
 
 #define TILE_KERNEL(name, body, decl, ...)                                   \
@@ -2200,33 +2193,49 @@ MMD void for_tiles(const Params& P, const Bufs& B, F body) {
     for_tiles(P, B, [&](int i, int j) { body<D>(P, B, i, j __VA_ARGS__); }); \
   }
 #define COMMA ,
+// Real states of the listed tiles (workgroups below ntb) and the row pass of
+// the ghost-band membership (the other ntb): the row pass reads only the
+// classification and the volume fractions, which the real states leave alone.
 template <int D>
-__global__ void __launch_bounds__(256) t_real(Params P, Bufs B, int sidx) {
+__global__ void __launch_bounds__(256) t_real_near_row(Params P, Bufs B, int sidx, int ntb) {
   // a new mixing stamp per stage (the previous stage's mixing is complete)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.ctr[C_STAMP] += 1;
     B.ctr[C_NGHOST] = 0;  // refilled by t_near_col
   }
-  for_tiles(P, B, [&](int i, int j) { b_real<D>(P, B, i, j, sidx); });
+  if ((int)blockIdx.x < ntb)
+    for_tiles_n(P, B, (int)blockIdx.x, ntb, [&](int i, int j) { b_real<D>(P, B, i, j, sidx); });
+  else
+    for_tiles_n(P, B, (int)blockIdx.x - ntb, ntb,
+                [&](int i, int j) { b_near_row<D>(P, B, i, j); });
 }
-TILE_KERNEL(t_near_row, b_near_row, )
 TILE_KERNEL(t_near_col, b_near_col, )
 TILE_KERNEL(t_vreset, b_vreset, )
 TILE_KERNEL(t_iface, b_iface, COMMA int sidx COMMA int stage0, COMMA sidx COMMA stage0)
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
-TILE_KERNEL(t_ls, b_ls, COMMA double bc COMMA double cc, COMMA bc COMMA cc)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
 TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
 
-// Commit of the new level set and its frame in one launch (2D).  Workgroups
-// below ntb commit the listed tiles; the others fill the ghost frame (x sides
+// Commit of the new level set and its frame in one launch (2D), with the
+// book-keeping totals of the stage in its last workgroups (from ntb + nfr
+// on).  Workgroups below ntb commit the listed tiles; the next nfr fill the
+// ghost frame (x sides
 // of rows [0, ny), then y sides of columns [-H, nx + H), a corner from the
 // source cell of both maps) from the committed value of the source cell: the
 // new one where the commit writes it (band cells, dls <= 3, always inside a
 // listed tile), the old one elsewhere.  A frame thread therefore reads only
 // words that no commit thread writes.
-__global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb) {
+__global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb, int nfr,
+                                                      int nblk, double w, int advance) {
+  if ((int)blockIdx.x >= ntb + nfr) {
+    // the book-keeping totals of the stage: one wavefront per (material,
+    // quantity), independent of the level set
+    int x = ((int)blockIdx.x - ntb - nfr) * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (advance && x == 0 && lane == 0) B.scal[S_T] += B.scal[S_DT];
+    if (x < P.M * 8) cons_fin_wave(P, B, nblk, w, x, lane);
+    return;
+  }
   if ((int)blockIdx.x < ntb) {
     int ntile = (int)B.ctr[C_NTILES];
     int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
@@ -2259,6 +2268,26 @@ __global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb)
   bool upd = !errored(B) && B.dls[ks] <= 3;
   B.phi[k] = upd ? B.ptmp[ks] : B.phi[ks];
   B.chi[k] = upd ? B.ctmp[ks] : B.chi[ks];
+}
+
+// Band fluxes and updates together with the book-keeping partials and the
+// level-set stage, in one launch: workgroups below ncons * M compute
+// partials (workgroup x of material r), the next nls the level-set stage of
+// the listed tiles, the other nfb the band list.  The partials read only the
+// stage's source state, fluxes and exchange terms, the level-set stage only
+// the level sets, the velocity and the step size: none of it is written by
+// the band update, so their latency hides behind the band work.
+template <int D>
+__global__ void __launch_bounds__(256) k_flux_list_cons(Params P, Bufs B, int sidx, int nidx,
+                                                        int didx, double bcoef, double ccoef,
+                                                        int nfb, int nbb, int ncons, int nls) {
+  int b = blockIdx.x, nc = ncons * P.M;
+  if (b < nc)
+    cons_part_block<D>(P, B, sidx, nbb, b % ncons, b / ncons);
+  else if (b < nc + nls)
+    for_tiles_n(P, B, b - nc, nls, [&](int i, int j) { b_ls<D>(P, B, i, j, bcoef, ccoef); });
+  else
+    flux_list_blocks<D>(P, B, sidx, nidx, didx, bcoef, ccoef, b - nc - nls, nfb);
 }
 template <int D>
 __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {

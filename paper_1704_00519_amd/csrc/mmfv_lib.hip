@@ -325,15 +325,15 @@ static void build_tiles(mm_ctx* c, int didx, int nidx) {
 
 // first half of a stage: real and ghost states, interface exchange (and at
 // stage 0 the level-set velocity and dt), fluxes and the RK update into
-// buffer didx, conservation book-keeping (and with advance, the time)
+// buffer didx beside the level-set stage, conservation book-keeping
+// partials (in 1D also the totals and, with advance, the time)
 template <int D>
 static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
                         double w, bool advance) {
   const Params& P = c->P;
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
-  LAUNCH(t_real<D>, tg, tb, P, c->B, sidx);
-  LAUNCH(t_near_row<D>, tg, tb, P, c->B);
+  LAUNCH(t_real_near_row<D>, dim3(2 * tg.x), tb, P, c->B, sidx, (int)tg.x);
   LAUNCH(t_near_col<D>, tg, tb, P, c->B);
   static_assert(EXR >= 8 + 4, "the tile frame covers every sweep (k_ext <= 8)");
   if (D == 2) {
@@ -369,27 +369,30 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
            cc, s == 0 ? 1 : 0);
   prof_mark(c);
   if (c->ev_used >= 4096) prof_collect(c);
+  // band update with the book-keeping partials and the level-set stage
   constexpr int FLUX_LIST_BLOCKS = 2048;
-  LAUNCH(k_flux_list_cons<D>, dim3(cons_blocks(P) * P.M + FLUX_LIST_BLOCKS), dim3(256), P, c->B,
-         sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P), cons_blocks(P));
-  LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w, advance ? 1 : 0);
+  LAUNCH(k_flux_list_cons<D>, dim3(cons_blocks(P) * P.M + tg.x + FLUX_LIST_BLOCKS), dim3(256),
+         P, c->B, sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P), cons_blocks(P),
+         (int)tg.x);
+  if (D == 1)
+    LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w, advance ? 1 : 0);
 }
 
-// second half: level-set stage and its frame, classification, geometry and
-// correction of the new level set, mixing (with save, Q* is copied before
-// the mixing for the adjoint)
+// second half: commit of the level-set stage (computed beside the band
+// update) and its frame, with the stage's book-keeping totals in 2D (and
+// with advance, the time), classification, geometry and correction of the
+// new level set, mixing (with save, Q* is copied before the mixing for the
+// adjoint)
 template <int D>
-static void stage_levelset(mm_ctx* c, int didx, int nidx, double b, double cc,
-                           bool commit = true, double* save_Q = nullptr,
-                           uint8_t* save_occ = nullptr) {
+static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance,
+                           double* save_Q, uint8_t* save_occ) {
   const Params& P = c->P;
   dim3 tg = tile_grid(c), tb(256);
-  LAUNCH(t_ls<D>, tg, tb, P, c->B, b, cc);
-  if (!commit) return;
   if (D == 2) {
     long nframe = ((long)P.ny + P.nx + 2 * H) * 2 * H;
-    LAUNCH(k_ls_commit_bc, dim3(tg.x + (unsigned)((nframe + 255) / 256)), tb, P, c->B,
-           (int)tg.x);
+    unsigned nfr = (unsigned)((nframe + 255) / 256), nfin = (unsigned)(P.M * 8 + 3) / 4;
+    LAUNCH(k_ls_commit_bc, dim3(tg.x + nfr + nfin), tb, P, c->B, (int)tg.x, (int)nfr,
+           cons_blocks(P), w, advance ? 1 : 0);
   } else {
     LAUNCH(t_ls_commit<D>, tg, tb, P, c->B);
     bc_ls<D>(c);
@@ -412,7 +415,7 @@ static void stage(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, doub
                   double w, double* save_Q = nullptr, uint8_t* save_occ = nullptr,
                   bool advance = false) {
   stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w, advance);
-  stage_levelset<D>(c, didx, nidx, b, cc, true, save_Q, save_occ);
+  stage_levelset<D>(c, didx, nidx, w, advance, save_Q, save_occ);
 }
 
 // beta-form coefficients, and each stage's share w of the full step in the
