@@ -319,7 +319,6 @@ MMD void b_bc_W_x(const Params& P, const Bufs& B, int t, int sidx) {
 template <int D>
 __global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) B.ctr[C_NBAND] = 0;  // the band list is rebuilt by k_bulkflag
   if (t >= P.ny * 2 * H * P.M) return;
   b_bc_W_x<D>(P, B, t, sidx);
 }
@@ -350,7 +349,6 @@ MMD Prim bc_x_state(const Params& P, const Bufs& B, int sidx, int r, int i, int 
 // another writes.
 __global__ void k_bc_W2(Params P, Bufs B, int sidx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) B.ctr[C_NBAND] = 0;  // the band list is rebuilt by k_bulkflag
   int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
   if (t >= (nxs + nys) * P.M) return;
   int r, i, j;
@@ -1058,17 +1056,18 @@ MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int 
   int k = cid(P, i, j);
   B.bulk[k] = is_bulk<D>(P, B, k, sidx, nidx) ? 1 : 0;
 }
-// Bulk flags for the stage, the compact list of all other cells, and (at
-// stage 0) the CFL maximum and from it, in the last workgroup to finish, the
-// step size.  Every thread reaches the barriers.
+// Bulk flags of a block of 256 cells (bw x 256 / bw; workgroup (bx, by) of
+// nblk), their compact list of all other cells, and (at stage 0) the CFL
+// maximum and from it, in the last workgroup to finish, the step size.  Every
+// thread reaches the barriers.
 template <int D>
-__global__ void __launch_bounds__(256) k_bulkflag(Params P, Bufs B, int sidx, int nidx,
-                                                  int with_dt) {
+MMD void bulkflag_block(const Params& P, const Bufs& B, int sidx, int nidx, int with_dt, int bx,
+                        int by, int bw, int nblk) {
   __shared__ int s_cnt, s_base;
   __shared__ double red[256];
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  int tid = threadIdx.x;
+  int i = bx * bw + tid % bw;
+  int j = by * (256 / bw) + tid / bw;
   bool inb = i < P.nx && j < P.ny;
   int k = inb ? cid(P, i, j) : 0;
   bool band = false;
@@ -1096,7 +1095,7 @@ __global__ void __launch_bounds__(256) k_bulkflag(Params P, Bufs B, int sidx, in
       // count this workgroup as finished; the last one sets the step size
       __threadfence();
       unsigned long long done = atomicAdd(&B.ctr[C_DTDONE], 1ull);
-      if (done + 1 == (unsigned long long)gridDim.x * gridDim.y) {
+      if (done + 1 == (unsigned long long)nblk) {
         __threadfence();
         double smax = __longlong_as_double((long long)atomicExch(&B.ctr[C_SMAX], 0ull));
         B.ctr[C_DTDONE] = 0;
@@ -2201,7 +2200,8 @@ __global__ void __launch_bounds__(256) t_real_near_row(Params P, Bufs B, int sid
   // a new mixing stamp per stage (the previous stage's mixing is complete)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.ctr[C_STAMP] += 1;
-    B.ctr[C_NGHOST] = 0;  // refilled by t_near_col
+    B.ctr[C_NGHOST] = 0;  // refilled by the column pass
+    B.ctr[C_NBAND] = 0;   // the band list is rebuilt with the bulk flags
   }
   if ((int)blockIdx.x < ntb)
     for_tiles_n(P, B, (int)blockIdx.x, ntb, [&](int i, int j) { b_real<D>(P, B, i, j, sidx); });
@@ -2209,8 +2209,27 @@ __global__ void __launch_bounds__(256) t_real_near_row(Params P, Bufs B, int sid
     for_tiles_n(P, B, (int)blockIdx.x - ntb, ntb,
                 [&](int i, int j) { b_near_row<D>(P, B, i, j); });
 }
-TILE_KERNEL(t_near_col, b_near_col, )
-TILE_KERNEL(t_vreset, b_vreset, )
+// Column pass of the ghost-band membership (with the ghost queue) and, at
+// stage 0, the reset of the level-set velocity validity, over the listed
+// tiles (workgroups below ntb), beside the bulk flags and band list of the
+// stage (the other gx * gy, blocks of bw x 256 / bw cells): the flags read
+// only the classification and the occupancy, and the step size the real
+// states, all complete before this launch.
+template <int D>
+__global__ void __launch_bounds__(256) t_near_col_flags(Params P, Bufs B, int sidx, int nidx,
+                                                        int stage0, int ntb, int gx, int gy,
+                                                        int bw) {
+  int b = blockIdx.x;
+  if (b < ntb) {
+    for_tiles_n(P, B, b, ntb, [&](int i, int j) {
+      if (stage0) b_vreset<D>(P, B, i, j);
+      b_near_col<D>(P, B, i, j);
+    });
+    return;
+  }
+  b -= ntb;
+  bulkflag_block<D>(P, B, sidx, nidx, stage0, b % gx, b / gx, bw, gx * gy);
+}
 TILE_KERNEL(t_iface, b_iface, COMMA int sidx COMMA int stage0, COMMA sidx COMMA stage0)
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)

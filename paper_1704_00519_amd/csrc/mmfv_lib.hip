@@ -334,7 +334,8 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
   LAUNCH(t_real_near_row<D>, dim3(2 * tg.x), tb, P, c->B, sidx, (int)tg.x);
-  LAUNCH(t_near_col<D>, tg, tb, P, c->B);
+  LAUNCH(t_near_col_flags<D>, dim3(tg.x + g.x * g.y), tb, P, c->B, sidx, nidx, s == 0 ? 1 : 0,
+         (int)tg.x, (int)g.x, (int)g.y, (int)bl.x);
   static_assert(EXR >= 8 + 4, "the tile frame covers every sweep (k_ext <= 8)");
   if (D == 2) {
     LAUNCH(k_ext_tiles, dim3(tg.x, P.M), tb, P, c->B, sidx);
@@ -347,13 +348,11 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
            sidx);
   else
     LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
-  if (s == 0) LAUNCH(t_vreset<D>, tg, tb, P, c->B);
   LAUNCH(t_iface<D>, tg, tb, P, c->B, sidx, s == 0 ? 1 : 0);
   if (s == 0) {
     for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
-  LAUNCH(k_bulkflag<D>, g, bl, P, c->B, sidx, nidx, s == 0 ? 1 : 0);
   prof_mark(c);
   if (D == 2)
     if (c->bulk_wide)
