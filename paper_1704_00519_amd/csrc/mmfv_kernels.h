@@ -316,12 +316,6 @@ MMD void b_bc_W_x(const Params& P, const Bufs& B, int t, int sidx) {
   B.W[o + (size_t)3 * P.NC + k] = w.p;
   B.Wit[(size_t)r * P.NC + k] = valid ? 1 : 0;
 }
-template <int D>
-__global__ void k_bc_W_x(Params P, Bufs B, int sidx) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P.ny * 2 * H * P.M) return;
-  b_bc_W_x<D>(P, B, t, sidx);
-}
 // state that the x-side frame gets at ghost cell (i, j) of material r, for
 // i outside [0, nx) and j inside [0, ny)
 MMD Prim bc_x_state(const Params& P, const Bufs& B, int sidx, int r, int i, int j,
@@ -341,14 +335,13 @@ MMD Prim bc_x_state(const Params& P, const Bufs& B, int sidx, int r, int i, int 
   w.u = w.u * (type == 1 ? -1.0 : 1.0);
   return w;
 }
-// both frames of the state buffer in one launch (2D): threads below
-// ny * 2H * M take the x sides of rows [0, ny), the others the y sides of
-// columns [-H, nx + H).  A corner cell gets the y-side map applied to the
+// both frames of the state buffer (2D), frame cell t: t below ny * 2H * M
+// takes the x sides of rows [0, ny), the others the y sides of columns
+// [-H, nx + H).  A corner cell gets the y-side map applied to the
 // x-side state of its source row, the value an x pass followed by a y pass
 // leaves there; every source is an interior cell, so no thread reads what
 // another writes.
-__global__ void k_bc_W2(Params P, Bufs B, int sidx) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+MMD void bc_W2_cell(const Params& P, const Bufs& B, int sidx, int t) {
   int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
   if (t >= (nxs + nys) * P.M) return;
   int r, i, j;
@@ -2230,7 +2223,24 @@ __global__ void __launch_bounds__(256) t_near_col_flags(Params P, Bufs B, int si
   b -= ntb;
   bulkflag_block<D>(P, B, sidx, nidx, stage0, b % gx, b / gx, bw, gx * gy);
 }
-TILE_KERNEL(t_iface, b_iface, COMMA int sidx COMMA int stage0, COMMA sidx COMMA stage0)
+// Interface exchange of the listed tiles (workgroups below ntb) beside the
+// frame of the state buffer (the others, one thread per frame cell): the
+// exchange reads the states of its own cut cell only, the frame neither the
+// exchange terms nor the velocities it writes.
+template <int D>
+__global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx, int stage0,
+                                                     int ntb) {
+  if ((int)blockIdx.x < ntb) {
+    for_tiles_n(P, B, (int)blockIdx.x, ntb,
+                [&](int i, int j) { b_iface<D>(P, B, i, j, sidx, stage0); });
+    return;
+  }
+  int t = ((int)blockIdx.x - ntb) * (int)blockDim.x + (int)threadIdx.x;
+  if (D == 2)
+    bc_W2_cell(P, B, sidx, t);
+  else if (t < P.ny * 2 * H * P.M)
+    b_bc_W_x<D>(P, B, t, sidx);
+}
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )

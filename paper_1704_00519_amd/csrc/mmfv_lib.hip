@@ -343,12 +343,9 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
     for (int sw = 0; sw < P.kext + 4; sw++)
       LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
   }
-  if (D == 2)
-    LAUNCH(k_bc_W2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B,
-           sidx);
-  else
-    LAUNCH(k_bc_W_x<D>, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, sidx);
-  LAUNCH(t_iface<D>, tg, tb, P, c->B, sidx, s == 0 ? 1 : 0);
+  long nframe = (D == 2 ? (long)P.ny + P.nx + 2 * H : (long)P.ny) * 2 * H * P.M;
+  LAUNCH(t_iface_frame<D>, dim3(tg.x + lin_grid(nframe).x), tb, P, c->B, sidx, s == 0 ? 1 : 0,
+         (int)tg.x);
   if (s == 0) {
     for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
