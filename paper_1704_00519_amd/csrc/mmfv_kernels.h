@@ -1602,6 +1602,20 @@ MMD void b_ls_commit(const Params& P, const Bufs& B, int i, int j) {
 // Mixing (Sec. 2.3.2, after each sub-step): exchanges from sources, then a
 // gather that applies them in place
 // ---------------------------------------------------------------------------
+// loadQ with the word read in any case (k in range), then chosen
+template <int D>
+MMD double loadQ_u(const Params& P, const double* Q, const uint8_t* occ, int r, int v, int k) {
+  int vv = D == 1 && v == 3 ? 2 : v;
+  double q = Q[((size_t)r * (D + 2) + vv) * P.NC + k];
+  bool has = (occ[k] >> r) & 1;
+  return has && !(D == 1 && v == 2) ? q : 0.0;
+}
+// alpha_at with every word read in any case (k in range), then chosen
+MMD double alpha_u(const Params& P, const Bufs& B, int r, int k) {
+  uint8_t c = B.cut[k], h = B.chi[k];
+  double a = B.al[(size_t)r * P.NC + k];
+  return c ? a : (h == r ? 1.0 : 0.0);
+}
 template <int D>
 MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t stamp,
                 int r0, int r1) {
@@ -1613,40 +1627,61 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   uint8_t own = (uint8_t)(1u << B.chi[k]);
   if (!B.cut[k] && occ[k] == own) return;
   double amix = P.amix;
+  // neighbour n = 3 (dj + 1) + di + 1 (4 is the cell itself; 1D: row dj = 0)
+  constexpr int NN = 9;
+  int kn[NN];
+  bool inn[NN];
+  for (int dj = -1; dj <= 1; dj++)
+    for (int di = -1; di <= 1; di++) {
+      int n = 3 * (dj + 1) + di + 1;
+      bool row = D == 2 || dj == 0;
+      kn[n] = row ? cid(P, i + di, j + dj) : k;
+      inn[n] = row && interior(P, i + di, j + dj);
+    }
+  uint8_t chk = B.chi[k];
   for (int r = r0; r < r1; r++) {
-    double as = alpha_at<D>(P, B, r, k);
-    if (!(as < amix) && B.chi[k] == r) continue;
+    // every load of this material that does not depend on a decision below,
+    // issued together: the cell's volume fraction and state, the level set
+    // of the four face neighbours, volume fraction and indicator of all eight
+    double as = alpha_u(P, B, r, k);
+    double qk[4];
+    for (int v = 0; v < 4; v++) qk[v] = loadQ_u<D>(P, Q, occ, r, v, k);
+    double an[NN];
+    uint8_t hn[NN];
+    double pn[NN];
+    for (int n = 0; n < NN; n++) {
+      an[n] = alpha_u(P, B, r, kn[n]);
+      hn[n] = B.chi[kn[n]];
+      pn[n] = B.phi[kn[n]];
+    }
+    if (!(as < amix) && chk == r) continue;
     if (!(as > 0.0)) {
       bool nz = false;
       for (int v = 0; v < 4; v++)
-        if (loadQ<D>(P, Q, occ, r, v, k) != 0.0) nz = true;
+        if (qk[v] != 0.0) nz = true;
       if (!nz) continue;
     }
     wave_count(&B.ctr[C_MIXSRC], 1);
-    double gx = lsv(B.phi, B.chi, r, cid(P, i + 1, j)) - lsv(B.phi, B.chi, r, cid(P, i - 1, j));
-    double gy = D == 2 ? lsv(B.phi, B.chi, r, cid(P, i, j + 1)) - lsv(B.phi, B.chi, r, cid(P, i, j - 1)) : 0.0;
+    auto lsn = [&](int n) { return hn[n] == r ? pn[n] : -pn[n]; };
+    double gx = lsn(5) - lsn(3);
+    double gy = D == 2 ? lsn(7) - lsn(1) : 0.0;
     int sx = gx > 0.0 ? 1 : (gx < 0.0 ? -1 : 0);
     int sy = gy > 0.0 ? 1 : (gy < 0.0 ? -1 : 0);
-    int tk[3] = {-1, -1, -1};
+    int tn[3] = {-1, -1, -1};
     double w[3] = {0.0, 0.0, 0.0};
-    auto eligible = [&](int ii, int jj, double& at) -> bool {
-      if (!interior(P, ii, jj)) return false;
-      int t = cid(P, ii, jj);
-      at = alpha_at<D>(P, B, r, t);
-      return at >= amix && B.chi[t] == r;
-    };
-    double at;
-    if (sx != 0 && eligible(i + sx, j, at)) {
-      tk[0] = cid(P, i + sx, j);
-      w[0] = gx * gx * at;
+    auto eligible = [&](int n) -> bool { return inn[n] && an[n] >= amix && hn[n] == r; };
+    int nx_ = 4 + sx, ny_ = 4 + 3 * sy, nxy = 4 + sx + 3 * sy;
+    if (sx != 0 && eligible(nx_)) {
+      tn[0] = nx_;
+      w[0] = gx * gx * an[nx_];
     }
-    if (sy != 0 && eligible(i, j + sy, at)) {
-      tk[1] = cid(P, i, j + sy);
-      w[1] = gy * gy * at;
+    if (sy != 0 && eligible(ny_)) {
+      tn[1] = ny_;
+      w[1] = gy * gy * an[ny_];
     }
-    if (sx != 0 && sy != 0 && eligible(i + sx, j + sy, at)) {
-      tk[2] = cid(P, i + sx, j + sy);
-      w[2] = fabs(gx * gy) * at;
+    if (sx != 0 && sy != 0 && eligible(nxy)) {
+      tn[2] = nxy;
+      w[2] = fabs(gx * gy) * an[nxy];
     }
     double wsum = (w[0] + w[1]) + w[2];
     double beta[3] = {0.0, 0.0, 0.0};
@@ -1655,27 +1690,34 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
         if (w[q] > 0.0)
           beta[q] = w[q] / wsum;
         else
-          tk[q] = -1;
+          tn[q] = -1;
     } else {
-      tk[0] = tk[1] = tk[2] = -1;
+      tn[0] = tn[1] = tn[2] = -1;
       double bestA = -1.0;
       int bt = -1;
       for (int dj = -(D == 2); dj <= (D == 2); dj++)
         for (int di = -1; di <= 1; di++) {
           if (di == 0 && dj == 0) continue;
-          if (eligible(i + di, j + dj, at) && at > bestA) {
-            bestA = at;
-            bt = cid(P, i + di, j + dj);
+          int n = 3 * (dj + 1) + di + 1;
+          if (eligible(n) && an[n] > bestA) {
+            bestA = an[n];
+            bt = n;
           }
         }
       if (bt < 0) {
         wave_count(&B.ctr[C_STRANDED], 1);
         continue;
       }
-      tk[0] = bt;
+      tn[0] = bt;
       beta[0] = 1.0;
     }
-    int last = -1;
+    int tk[3], last = -1;
+    for (int q = 0; q < 3; q++) tk[q] = tn[q] >= 0 ? kn[tn[q]] : -1;
+    // states of the targets (needed only where the cell holds material r)
+    double qt[3][4];
+    for (int q = 0; q < 3; q++)
+      for (int v = 0; v < 4; v++)
+        qt[q][v] = as > 0.0 && tk[q] >= 0 ? loadQ_u<D>(P, Q, occ, r, v, tk[q]) : 0.0;
     for (int q = 0; q < 3; q++) {
       B.mixT[((size_t)r * 3 + q) * P.NC + k] = tk[q];
       if (tk[q] >= 0) {
@@ -1685,13 +1727,13 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     }
     B.srcStamp[(size_t)r * P.NC + k] = stamp;
     for (int v = 0; v < 4; v++) {
-      double Qs = loadQ<D>(P, Q, occ, r, v, k), acc = Qs;
+      double Qs = qk[v], acc = Qs;
       for (int q = 0; q < 3; q++) {
         if (tk[q] < 0) continue;
         double m;
         if (as > 0.0) {
-          double at2 = alpha_at<D>(P, B, r, tk[q]);
-          double Qt = loadQ<D>(P, Q, occ, r, v, tk[q]);
+          double at2 = an[tn[q]];
+          double Qt = qt[q][v];
           m = beta[q] * ((as * Qt - at2 * Qs) / (as + at2));
         } else {
           m = q == last ? -acc : -(beta[q] * Qs);
