@@ -2183,9 +2183,8 @@ MMD int tile_h(const Params& P) { return P.dim == 2 ? 16 : 1; }
 MMD int tiles_x(const Params& P) { return (P.nx + tile_w(P) - 1) / tile_w(P); }
 
 
-__global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
+MMD void tile_flag(const Params& P, const Bufs& B, int didx, int nidx, int tile) {
   int tw = tile_w(P), th = tile_h(P);
-  int tile = blockIdx.x;
   int i0 = (tile % tiles_x(P)) * tw, j0 = (tile / tiles_x(P)) * th;
   int ew = tw + 2, eh = P.dim == 2 ? th + 2 : 1;
   bool f = false;
@@ -2201,6 +2200,28 @@ __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int n
     unsigned long long at = atomicAdd(&B.ctr[C_NTILES], 1ull);
     B.tiles[at] = tile;
   }
+}
+__global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
+  tile_flag(P, B, didx, nidx, (int)blockIdx.x);
+}
+// Tile list (workgroups below nt, one per tile) beside the geometry and
+// volume-fraction correction of every cut cell (the other nt, one per tile,
+// without the list: every cut cell lies in a listed tile).  The geometry reads
+// the level set and the densities, the list the distances and occupancy,
+// and neither writes what the other reads.
+template <int D>
+__global__ void __launch_bounds__(256) k_tiles_geom(Params P, Bufs B, int didx, int nidx,
+                                                    int nt) {
+  int b = blockIdx.x;
+  if (b < nt) {
+    tile_flag(P, B, didx, nidx, b);
+    return;
+  }
+  b -= nt;
+  int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
+  int i = (b % ntx) * tw + (int)threadIdx.x % tw;
+  int j = (b / ntx) * th + (int)threadIdx.x / tw;
+  if (i < P.nx && j < P.ny) b_geom<D>(P, B, i, j, didx, nullptr);
 }
 
 // run body(i, j) over the cells of the listed tiles, workgroup bx of nbx;
@@ -2286,7 +2307,6 @@ __global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx,
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
-TILE_KERNEL(t_geom, b_geom, COMMA int midx COMMA const double* Win, COMMA midx COMMA Win)
 
 // Commit of the new level set and its frame in one launch (2D), with the
 // book-keeping totals of the stage in its last workgroups (from ntb + nfr

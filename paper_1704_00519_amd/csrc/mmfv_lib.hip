@@ -394,8 +394,8 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
     bc_ls<D>(c);
   }
   classify<D>(c);
-  build_tiles<D>(c, didx, nidx);
-  LAUNCH(t_geom<D>, tg, tb, P, c->B, didx, (const double*)nullptr);
+  int nt = n_tiles(P);
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nt), tb, P, c->B, didx, nidx, nt);
   if (save_Q) {
     (void)hipMemcpyAsync(save_Q, c->B.Q[didx], (size_t)P.M * (D + 2) * P.NC * sizeof(double),
                          hipMemcpyDeviceToDevice, c->stream);
