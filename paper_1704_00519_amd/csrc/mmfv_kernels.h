@@ -2305,6 +2305,116 @@ __global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx,
     b_bc_W_x<D>(P, B, t, sidx);
 }
 TILE_KERNEL(t_vext, b_vext, COMMA int sweep, COMMA sweep)
+
+// Level-set velocity of one listed tile at stage 0 (2D): the four sweeps of
+// b_vext in LDS over the tile and a frame of four cells (the reach of four
+// sweeps), then the fill of b_vfill for the tile's own cells; only the own
+// cells are written back.  Other workgroups write back their tiles while
+// this one reads its frame, so a cell enters with stamp 1 (interface
+// velocities, final before this launch) or 0, and every swept velocity is
+// computed here, never read.  Near the frame's outer edge the sweeps miss
+// neighbours outside it; that reaches the own cells only after the fourth
+// sweep.
+constexpr int VF = 4, VT = 16, VW = VT + 2 * VF, VP = VW + 2;
+struct VextSmem {
+  double vx[VW * VW], vy[VW * VW], phi[VP * VP];
+  uint8_t vit[VW * VW], vit0[VW * VW], cand[VW * VW];
+};
+__global__ void __launch_bounds__(256) k_vext_tiles(Params P, Bufs B, int sidx) {
+  __shared__ VextSmem S;
+  int ntile = (int)B.ctr[C_NTILES], ntx = tiles_x(P);
+  bool err = errored(B);
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    int tile = B.tiles[t];
+    int i0 = (tile % ntx) * VT - VF, j0 = (tile / ntx) * VT - VF;
+    // level set over the region and one more cell (clamped into the frame:
+    // only interior cells take differences of it)
+    for (int q = threadIdx.x; q < VP * VP; q += blockDim.x) {
+      int gi = i0 - 1 + q % VP, gj = j0 - 1 + q / VP;
+      gi = gi < -1 ? -1 : (gi > P.nx ? P.nx : gi);
+      gj = gj < -1 ? -1 : (gj > P.ny ? P.ny : gj);
+      S.phi[q] = B.phi[cid(P, gi, gj)];
+    }
+    for (int q = threadIdx.x; q < VW * VW; q += blockDim.x) {
+      int gi = i0 + q % VW, gj = j0 + q / VW;
+      bool in = interior(P, gi, gj);
+      int k = cid(P, in ? gi : 0, in ? gj : 0);
+      uint8_t it = B.vit[k], dl = B.dls[k];
+      double vx = B.vx[k], vy = B.vy[k];
+      S.vit[q] = S.vit0[q] = in && it == 1 ? 1 : 0;
+      S.vx[q] = vx;
+      S.vy[q] = vy;
+      S.cand[q] = in && !err && dl == 0;
+    }
+    __syncthreads();
+    for (int sw = 0; sw < 4; sw++) {
+      for (int q = threadIdx.x; q < VW * VW; q += blockDim.x) {
+        int x = q % VW, y = q / VW, pq = (y + 1) * VP + x + 1;
+        if (!S.cand[q] || !(S.phi[pq] < P.bls) || S.vit[q] != 0) continue;
+        // a state of an earlier sweep (stamps of this sweep are sw + 2); a
+        // cell with one is never written again, so its values are final
+        auto valid_prev = [&](int xx, int yy) -> bool {
+          if (xx < 0 || xx >= VW || yy < 0 || yy >= VW) return false;
+          uint8_t it = S.vit[yy * VW + xx];
+          return it != 0 && it <= sw + 1;
+        };
+        double gx = S.phi[pq + 1] - S.phi[pq - 1];
+        double gy = S.phi[pq + VP] - S.phi[pq - VP];
+        int kx = -1, ky = -1;
+        if (gx != 0.0) {
+          int xx = x - (gx > 0.0 ? 1 : -1);
+          if (valid_prev(xx, y)) kx = y * VW + xx;
+        }
+        if (gy != 0.0) {
+          int yy = y - (gy > 0.0 ? 1 : -1);
+          if (valid_prev(x, yy)) ky = yy * VW + x;
+        }
+        double ox, oy;
+        if (kx >= 0 && ky >= 0) {
+          double wx = fabs(gx), wy = fabs(gy);
+          ox = (wx * S.vx[kx] + wy * S.vx[ky]) / (wx + wy);
+          oy = (wx * S.vy[kx] + wy * S.vy[ky]) / (wx + wy);
+        } else if (kx >= 0) {
+          ox = S.vx[kx];
+          oy = S.vy[kx];
+        } else if (ky >= 0) {
+          ox = S.vx[ky];
+          oy = S.vy[ky];
+        } else {
+          continue;
+        }
+        S.vx[q] = ox;
+        S.vy[q] = oy;
+        S.vit[q] = (uint8_t)(sw + 2);
+      }
+      __syncthreads();
+    }
+    // own cells: the swept states, then the fill and the time-n level set
+    {
+      int x = VF + (int)threadIdx.x % VT, y = VF + (int)threadIdx.x / VT;
+      int i = i0 + x, j = j0 + y, q = y * VW + x;
+      if (threadIdx.x < VT * VT && i < P.nx && j < P.ny) {
+        int k = cid(P, i, j);
+        if (S.vit[q] != S.vit0[q]) {
+          B.vx[k] = S.vx[q];
+          B.vy[k] = S.vy[q];
+          B.vit[k] = S.vit[q];
+        }
+        if (B.dls[k] <= RV) {
+          B.phin[k] = B.phi[k];
+          B.chin[k] = B.chi[k];
+          if (S.vit[q] == 0) {
+            bool valid;
+            Prim w = Wget<2>(P, B, B.Q[sidx], B.occ[sidx], B.chi[k], i, j, valid);
+            B.vx[k] = valid ? w.u : 0.0;
+            B.vy[k] = valid ? w.v : 0.0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
 

@@ -346,7 +346,9 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   long nframe = (D == 2 ? (long)P.ny + P.nx + 2 * H : (long)P.ny) * 2 * H * P.M;
   LAUNCH(t_iface_frame<D>, dim3(tg.x + lin_grid(nframe).x), tb, P, c->B, sidx, s == 0 ? 1 : 0,
          (int)tg.x);
-  if (s == 0) {
+  if (s == 0 && D == 2) {
+    LAUNCH(k_vext_tiles, tg, tb, P, c->B, sidx);
+  } else if (s == 0) {
     for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
