@@ -40,58 +40,15 @@ static void cpy(mm_ctx* c, void* dst, const void* src, size_t n) {
   (void)hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, c->stream);
 }
 
-// Several device-to-device copies in one launch (grid y = copy index);
-// every buffer starts 8-byte aligned.
-constexpr int MAXCOPY = 24;
-struct CopyList {
-  const char* src[MAXCOPY];
-  char* dst[MAXCOPY];
-  size_t bytes[MAXCOPY];
-  int n;
-};
-__global__ void __launch_bounds__(256) k_copy_multi(CopyList L) {
-  int e = blockIdx.y;
-  if (e >= L.n) return;
-  size_t words = L.bytes[e] / 8, tail = L.bytes[e] % 8;
-  const double* s8 = (const double*)L.src[e];
-  double* d8 = (double*)L.dst[e];
-  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
-       w += (size_t)gridDim.x * blockDim.x)
-    d8[w] = s8[w];
-  if (blockIdx.x == 0 && threadIdx.x < tail)
-    L.dst[e][words * 8 + threadIdx.x] = L.src[e][words * 8 + threadIdx.x];
-}
-struct Copies {
-  CopyList L;
-  size_t maxw = 0;
-  Copies() { L.n = 0; }
-  void add(void* dst, const void* src, size_t bytes) {
-    L.src[L.n] = (const char*)src;
-    L.dst[L.n] = (char*)dst;
-    L.bytes[L.n] = bytes;
-    L.n++;
-    if (bytes / 8 > maxw) maxw = bytes / 8;
-  }
-  void run(mm_ctx* c) {
-    if (!L.n) return;
-    unsigned gx = (unsigned)((maxw + 255) / 256);
-    if (gx > 512) gx = 512;
-    if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_copy_multi, dim3(gx, L.n), dim3(256), 0, c->stream, L);
-    L.n = 0;
-    maxw = 0;
-  }
-};
 
 static void geo_ptrs(mm_ctx* c, double* g[5]) {
   g[0] = c->B.al; g[1] = c->B.ax; g[2] = c->B.ay; g[3] = c->B.cx; g[4] = c->B.cy;
 }
 
-static void snap_save(mm_ctx* c, char* dst, int sidx) {
+static void snap_save(mm_ctx* c, char* dst, int sidx, Copies& cp) {
   const Params& P = c->P;
   SnapLayout L = snap_layout(P);
   size_t nc = P.NC, M = P.M, nv = P.dim + 2;
-  Copies cp;
   cp.add(dst + L.q, c->B.Q[sidx], M * nv * nc * 8);
   cp.add(dst + L.phi, c->B.phi, nc * 8);
   double* g[5];
@@ -100,7 +57,6 @@ static void snap_save(mm_ctx* c, char* dst, int sidx) {
   cp.add(dst + L.occ, c->B.occ[sidx], nc);
   cp.add(dst + L.chi, c->B.chi, nc);
   cp.add(dst + L.vfc, c->B.vfc, nc * 2);
-  cp.run(c);
 }
 
 // restore a stage snapshot into buffer sidx (with optional extra copies in
@@ -126,15 +82,13 @@ static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = null
   if (tiles) build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
 }
 
-static void ext_save(mm_ctx* c, char* dst) {
+static void ext_save(mm_ctx* c, char* dst, Copies& cp) {
   SnapLayout L = snap_layout(c->P);
   size_t nc = c->P.NC;
-  Copies cp;
   cp.add(dst + L.vx, c->B.vx, nc * 8);
   cp.add(dst + L.vy, c->B.vy, nc * 8);
   cp.add(dst + L.phin, c->B.phin, nc * 8);
   cp.add(dst + L.chin, c->B.chin, nc);
-  cp.run(c);
 }
 static void ext_add(mm_ctx* c, Copies& cp, const char* src) {
   SnapLayout L = snap_layout(c->P);
@@ -143,13 +97,6 @@ static void ext_add(mm_ctx* c, Copies& cp, const char* src) {
   cp.add(c->B.vy, src + L.vy, nc * 8);
   cp.add(c->B.phin, src + L.phin, nc * 8);
   cp.add(c->B.chin, src + L.chin, nc);
-}
-
-// fixed step size of recorded step n for the recomputation
-template <int D>
-static void use_tape_dt(mm_ctx* c, int64_t n) {
-  cpy(c, c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
-  LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
 }
 
 // Per stage, besides the snapshot: Q* (after the update, before mixing)
@@ -225,19 +172,23 @@ static void load_segment(mm_ctx* c, int64_t n0, int64_t n1) {
   double b[3], cc[3], w[3];
   int ns = rk_coefs(c->cfg, b, cc, w);
   snap_load<D>(c, c->ckpt[n0 / c->tape_K], 0);
+  // the copies between two stages go out in one launch: what the last stage
+  // read, the snapshot of the next one and, before a step, its recorded step
+  // size (stage 0 takes it over as the step size)
+  Copies cp;
   for (int64_t n = n0; n < n1; n++) {
-    use_tape_dt<D>(c, n);
+    cp.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
     for (int s = 0; s < ns; s++) {
       int sidx = stage_src(s), didx = stage_dst(s, ns);
-      snap_save(c, seg_stage(c, n - n0, s, ns), sidx);
+      snap_save(c, seg_stage(c, n - n0, s, ns), sidx, cp);
+      cp.run(c);
       stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s], (double*)seg_qstar(c, n - n0, s, ns),
                seg_qstar_occ(c, n - n0, s, ns));
-      Copies cp;
       states_copies(c, cp, seg_qstar(c, n - n0, s, ns), true);
-      cp.run(c);
-      if (s == 0) ext_save(c, seg_ext(c, n - n0, ns));
+      if (s == 0) ext_save(c, seg_ext(c, n - n0, ns), cp);
     }
   }
+  cp.run(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,10 +253,12 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
   dim3 gm(g.x, g.y, P.M);  // one material per slice
   Adj& A = c->A;
   int64_t rel = n - c->seg_n0;
-  zero(c, A.lQn, M * 4 * nc * 8);
-  zero(c, A.lphin, nc * 8);
-  zero(c, A.lvx, nc * 8);
-  zero(c, A.lvy, nc * 8);
+  Copies z;
+  z.fill0(A.lQn, M * 4 * nc * 8);
+  z.fill0(A.lphin, nc * 8);
+  z.fill0(A.lvx, nc * 8);
+  z.fill0(A.lvy, nc * 8);
+  z.run(c);
   int nfx0 = (P.nx + 1) * P.ny, nfx1 = P.nx * (P.ny + 1);
   for (int s = ns - 1; s >= 0; s--) {
     int sidx = stage_src(s), didx = stage_dst(s, ns);
@@ -316,12 +269,16 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     else if (n + 1 == c->tape_n) next = c->final_snap;
     else if (n + 1 < c->seg_n1) next = seg_stage(c, rel + 1, 0, ns);
     else next = c->ckpt[(n + 1) / c->tape_K];
-    snap_load<D>(c, next, didx, nullptr, false);
+    // with the snapshot's copies: the adjoints of the stage's output become
+    // those of Q* and of the new level set, and the geometry adjoints start
+    // from zero (lal, lax, lay, lcx, lcy)
+    Copies c1;
+    c1.add(A.lQs, A.lQ, M * 4 * nc * 8);
+    c1.add(A.lphis, A.lphi, nc * 8);
+    c1.fill0(A.lal, 5 * M * nc * 8);
+    snap_load<D>(c, next, didx, &c1, false);
     A.Qstar = (double*)seg_qstar(c, rel, s, ns);
     A.occstar = seg_qstar_occ(c, rel, s, ns);
-    cpy(c, A.lQs, A.lQ, M * 4 * nc * 8);
-    cpy(c, A.lphis, A.lphi, nc * 8);
-    zero(c, A.lal, 5 * M * nc * 8);  // lal, lax, lay, lcx, lcy
     LAUNCH(k_a_mix<D>, gm, bl, P, c->B, A);
     if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphis);
@@ -339,9 +296,12 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
       ext_add(c, cp, seg_ext(c, rel, ns));
     }
     states_copies(c, cp, seg_qstar(c, rel, s, ns), false);
+    // the recorded step size, and the adjoints of the stage's input from zero
+    cp.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
+    cp.fill0(A.lW, M * 4 * nc * 8);
+    cp.fill0(A.lal, (5 * M + 1) * nc * 8);  // lal..lcy, lphi
     snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp, false);
-    use_tape_dt<D>(c, n);
-    zero(c, A.lW, (M * 4 + 5 * M + 1) * nc * 8);  // lW, lal..lcy, lphi
+    LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
     LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
     LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);
     LAUNCH(k_a_flux<D>, lin_grid(D == 2 ? nfx0 + nfx1 : nfx0), dim3(256), P, c->B, A, sidx,
@@ -360,7 +320,7 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
       LAUNCH(k_tiles, dim3(n_tiles(P)), dim3(256), P, c->B, sidx, sidx);
       cpy(c, A.lW2, A.lW, M * 4 * nc * 8);
       LAUNCH(k_a_ext_tiles, dim3(tile_grid(c).x, P.M), dim3(256), P, c->B, A, sidx);
-      cpy(c, A.lW, A.lW2, M * 4 * nc * 8);
+      std::swap(A.lW, A.lW2);  // the written buffer holds the result
     } else {
       for (int sw = P.kext + 3; sw >= 0; sw--)
         LAUNCH(k_a_ext<D>, dim3(256), dim3(256), P, c->B, A, sidx, sw);
@@ -390,10 +350,12 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
   // first reverse call: keep the forward state after the last recorded step
   if (c->tape_rev == c->tape_n) {
     HIP_OK(c, grow(c, &c->final_snap, &c->final_cap, L.bytes));
-    snap_save(c, c->final_snap, 0);
-    zero(c, A.linflow, 4 * 8);
-    zero(c, A.lQ, (size_t)P.M * 4 * P.NC * 8);
-    zero(c, A.lphi, (size_t)P.NC * 8);
+    Copies cp;
+    snap_save(c, c->final_snap, 0, cp);
+    cp.fill0(A.linflow, 4 * 8);
+    cp.fill0(A.lQ, (size_t)P.M * 4 * P.NC * 8);
+    cp.fill0(A.lphi, (size_t)P.NC * 8);
+    cp.run(c);
   }
   cpy(c, c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
   cpy(c, c->scal_save, c->B.scal, 8 * sizeof(double));

@@ -286,6 +286,63 @@ static dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
 #define LAUNCH(kern, grid, block, ...) \
   hipLaunchKernelGGL(kern, grid, block, 0, c->stream, __VA_ARGS__)
 
+// Several device-to-device copies (and fills with zeros: no source) in one
+// launch (grid y = entry index); every buffer starts 8-byte aligned.
+constexpr int MAXCOPY = 32;
+struct CopyList {
+  const char* src[MAXCOPY];
+  char* dst[MAXCOPY];
+  size_t bytes[MAXCOPY];
+  int n;
+};
+__global__ void __launch_bounds__(256) k_copy_multi(CopyList L) {
+  int e = blockIdx.y;
+  if (e >= L.n) return;
+  size_t words = L.bytes[e] / 8, tail = L.bytes[e] % 8;
+  const double* s8 = (const double*)L.src[e];
+  double* d8 = (double*)L.dst[e];
+  bool fill = s8 == nullptr;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+       w += (size_t)gridDim.x * blockDim.x)
+    d8[w] = fill ? 0.0 : s8[w];
+  if (blockIdx.x == 0 && threadIdx.x < tail)
+    L.dst[e][words * 8 + threadIdx.x] = fill ? 0 : L.src[e][words * 8 + threadIdx.x];
+}
+struct Copies {
+  // entries of one batch are independent: a full list is launched on its own
+  std::vector<std::pair<CopyList, size_t>> full;
+  CopyList L;
+  size_t maxw = 0;
+  Copies() { L.n = 0; }
+  void add(void* dst, const void* src, size_t bytes) {
+    if (L.n == MAXCOPY) {
+      full.emplace_back(L, maxw);
+      L.n = 0;
+      maxw = 0;
+    }
+    L.src[L.n] = (const char*)src;
+    L.dst[L.n] = (char*)dst;
+    L.bytes[L.n] = bytes;
+    L.n++;
+    if (bytes / 8 > maxw) maxw = bytes / 8;
+  }
+  void fill0(void* dst, size_t bytes) { add(dst, nullptr, bytes); }
+  static void launch(mm_ctx* c, const CopyList& l, size_t mw) {
+    unsigned gx = (unsigned)((mw + 255) / 256);
+    if (gx > 512) gx = 512;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_copy_multi, dim3(gx, l.n), dim3(256), 0, c->stream, l);
+  }
+  void run(mm_ctx* c) {
+    for (auto& f : full) launch(c, f.first, f.second);
+    full.clear();
+    if (L.n) launch(c, L, maxw);
+    L.n = 0;
+    maxw = 0;
+  }
+};
+
+
 
 template <int D>
 static void bc_ls(mm_ctx* c) {
@@ -399,10 +456,10 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
   int nt = n_tiles(P);
   LAUNCH(k_tiles_geom<D>, dim3(2 * nt), tb, P, c->B, didx, nidx, nt);
   if (save_Q) {
-    (void)hipMemcpyAsync(save_Q, c->B.Q[didx], (size_t)P.M * (D + 2) * P.NC * sizeof(double),
-                         hipMemcpyDeviceToDevice, c->stream);
-    (void)hipMemcpyAsync(save_occ, c->B.occ[didx], (size_t)P.NC, hipMemcpyDeviceToDevice,
-                         c->stream);
+    Copies cp;
+    cp.add(save_Q, c->B.Q[didx], (size_t)P.M * (D + 2) * P.NC * sizeof(double));
+    cp.add(save_occ, c->B.occ[didx], (size_t)P.NC);
+    cp.run(c);
   }
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
@@ -749,7 +806,9 @@ static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_ou
         HIP_OK(c, hipMalloc((void**)&p, L.bytes));
         c->ckpt.push_back(p);
       }
-      snap_save(c, c->ckpt[q], 0);
+      Copies cp;
+      snap_save(c, c->ckpt[q], 0, cp);
+      cp.run(c);
     }
     mm_status st = launch_steps(c, 1);
     if (st != MM_OK) return st;
