@@ -11,7 +11,7 @@
 // the level-set velocity and the time-n level set.
 // ---------------------------------------------------------------------------
 struct SnapLayout {
-  size_t q, phi, geo, occ, chi, vfc, bytes;  // stage snapshot offsets
+  size_t q, phi, geo, occ, chi, vfc, cls, bytes;  // stage snapshot offsets
   size_t vx, vy, phin, chin, ext_bytes;      // step extras offsets
 };
 
@@ -26,6 +26,7 @@ static SnapLayout snap_layout(const Params& P) {
   L.occ = at; at = align256(at + nc);
   L.chi = at; at = align256(at + nc);
   L.vfc = at; at = align256(at + nc * 2);
+  L.cls = at; at = align256(at + 4 * nc);  // classification: cut, xs, dcut, dls
   L.bytes = at;
   at = 0;
   L.vx = at; at = align256(at + nc * 8);
@@ -57,10 +58,14 @@ static void snap_save(mm_ctx* c, char* dst, int sidx, Copies& cp) {
   cp.add(dst + L.occ, c->B.occ[sidx], nc);
   cp.add(dst + L.chi, c->B.chi, nc);
   cp.add(dst + L.vfc, c->B.vfc, nc * 2);
+  uint8_t* cls[4] = {c->B.cut, c->B.xs, c->B.dcut, c->B.dls};
+  for (int q = 0; q < 4; q++) cp.add(dst + L.cls + q * nc, cls[q], nc);
 }
 
 // restore a stage snapshot into buffer sidx (with optional extra copies in
-// the same launch) and rebuild the classification and the tile list
+// the same launch) with its classification (a function of the level set and
+// the indicator, kept with the snapshot); with tiles the classification is
+// recomputed and the tile list rebuilt, else the list is emptied
 template <int D>
 static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = nullptr,
                       bool tiles = true) {
@@ -77,9 +82,16 @@ static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = null
   cp.add(c->B.occ[sidx], src + L.occ, nc);
   cp.add(c->B.chi, src + L.chi, nc);
   cp.add(c->B.vfc, src + L.vfc, nc * 2);
+  if (tiles) {
+    cp.run(c);
+    classify<D>(c);
+    build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
+    return;
+  }
+  uint8_t* cls[4] = {c->B.cut, c->B.xs, c->B.dcut, c->B.dls};
+  for (int q = 0; q < 4; q++) cp.add(cls[q], src + L.cls + q * nc, nc);
+  cp.fill0(&c->B.ctr[C_NTILES], sizeof(unsigned long long));
   cp.run(c);
-  classify<D>(c);
-  if (tiles) build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
 }
 
 static void ext_save(mm_ctx* c, char* dst, Copies& cp) {
