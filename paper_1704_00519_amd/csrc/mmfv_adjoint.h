@@ -317,26 +317,8 @@ __global__ void __launch_bounds__(256) k_a_geom(Params P, Bufs B, Adj A, double*
 
 // ---------------------------------------------------------------------------
 // Frames of the level set: every frame cell is a copy of an inside cell, so
-// its adjoint is added to that cell (y sides first, the reverse of the fill).
+// its adjoint is added to that cell.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_a_bc_ls_y(Params P, double* l) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int ncol = P.nx + 2 * H;
-  if (t >= ncol * 2 * H) return;
-  int i = t / (2 * H) - H, q = t % (2 * H);
-  int jj, sj;
-  if (q < H) {
-    jj = -1 - q;
-    sj = src_lo(jj, P.bc[2]);
-  } else {
-    jj = P.ny + (q - H);
-    sj = src_hi(jj, P.ny, P.bc[3]);
-  }
-  int k = cid(P, i, jj), ks = cid(P, i, sj);
-  double x = l[k];
-  l[k] = 0.0;
-  aadd(&l[ks], x);
-}
 __global__ void __launch_bounds__(256) k_a_bc_ls_x(Params P, double* l) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.ny * 2 * H) return;
@@ -353,6 +335,44 @@ __global__ void __launch_bounds__(256) k_a_bc_ls_x(Params P, double* l) {
   double x = l[k];
   l[k] = 0.0;
   aadd(&l[ks], x);
+}
+// both sides in one launch (2D): every frame cell passes its adjoint to the
+// interior source of the two maps composed (a corner to the source of the
+// x side of its source row), the sum the two passes in sequence deliver
+__global__ void __launch_bounds__(256) k_a_bc_ls2(Params P, double* l) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
+  if (t >= nxs + nys) return;
+  int i, j, si, sj;
+  if (t < nxs) {
+    int q = t % (2 * H);
+    j = sj = t / (2 * H);
+    i = q < H ? -1 - q : P.nx + (q - H);
+  } else {
+    t -= nxs;
+    int q = t % (2 * H);
+    i = si = t / (2 * H) - H;
+    j = q < H ? -1 - q : P.ny + (q - H);
+    sj = q < H ? src_lo(j, P.bc[2]) : src_hi(j, P.ny, P.bc[3]);
+  }
+  if (i < 0) si = src_lo(i, P.bc[0]);
+  if (i >= P.nx) si = src_hi(i, P.nx, P.bc[1]);
+  int k = cid(P, i, j), ks = cid(P, si, sj);
+  double x = l[k];
+  l[k] = 0.0;
+  aadd(&l[ks], x);
+}
+
+// ---------------------------------------------------------------------------
+// RK stage update Q* = b Q^n + c (Q^(s) + rhs): lQn += b lQs, lQ = c lQs.
+// ---------------------------------------------------------------------------
+MMD void a_update_cell(const Params& P, const Adj& A, int k, double bcoef, double ccoef) {
+  for (int r = 0; r < P.M; r++)
+    for (int v = 0; v < 4; v++) {
+      double l = A4(P, A.lQs, r, v, k);
+      if (bcoef != 0.0) A4(P, A.lQn, r, v, k) += bcoef * l;
+      A4(P, A.lQ, r, v, k) = ccoef * l;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -392,9 +412,15 @@ MMD void a_hj(const Params& P, const Bufs& B, const Adj& A, int r, int i, int j,
   }
 }
 
+// grid z = 0: the level-set stage; z = 1: the RK update of Q (independent:
+// they share no adjoint)
 template <int D>
 __global__ void __launch_bounds__(256) k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef) {
   ADJ_CELL_LOOP
+  if (blockIdx.z == 1) {
+    a_update_cell(P, A, k, bcoef, ccoef);
+    return;
+  }
   double lp = A.lphis[k];
   if (B.dls[k] > 3) {
     aadd(&A.lphi[k], lp);
@@ -439,21 +465,6 @@ __global__ void __launch_bounds__(256) k_a_ls(Params P, Bufs B, Adj A, double bc
   }
 }
 
-// ---------------------------------------------------------------------------
-// RK stage update Q* = b Q^n + c (Q^(s) + rhs): lQn += b lQs, lQ = c lQs.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_a_update(Params P, Adj A, double bcoef, double ccoef) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= P.nx || j >= P.ny) return;
-  int k = cid(P, i, j);
-  for (int r = 0; r < P.M; r++)
-    for (int v = 0; v < 4; v++) {
-      double l = A4(P, A.lQs, r, v, k);
-      if (bcoef != 0.0) A4(P, A.lQn, r, v, k) += bcoef * l;
-      A4(P, A.lQ, r, v, k) = ccoef * l;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Aperture-weighted face fluxes (Eq. discretized_equ).  One thread per face
@@ -757,41 +768,8 @@ __global__ void __launch_bounds__(256) k_a_iface(Params P, Bufs B, Adj A, int si
 // ---------------------------------------------------------------------------
 // Frames of the primitive states: a frame state is a copy (normal velocity
 // negated at a reflective side) of a state next to the boundary, or the
-// fixed inflow state.  y sides first, the reverse of the fill.
+// fixed inflow state.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_a_bc_W_y(Params P, Bufs B, Adj A) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int ncol = P.nx + 2 * H;
-  if (t >= ncol * 2 * H * P.M) return;
-  int r = t / (ncol * 2 * H);
-  int rem = t % (ncol * 2 * H);
-  int i = rem / (2 * H) - H, q = rem % (2 * H);
-  int jj, sj, type;
-  if (q < H) {
-    jj = -1 - q;
-    type = P.bc[2];
-    sj = src_lo(jj, type);
-  } else {
-    jj = P.ny + (q - H);
-    type = P.bc[3];
-    sj = src_hi(jj, P.ny, type);
-  }
-  int k = cid(P, i, jj), ks = cid(P, i, sj);
-  double l[4];
-  for (int v = 0; v < 4; v++) {
-    l[v] = A4(P, A.lW, r, v, k);
-    A4(P, A.lW, r, v, k) = 0.0;
-  }
-  if (type == 2 && r == P.inflow_mat) {
-    for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
-    return;
-  }
-  double sy = type == 1 ? -1.0 : 1.0;
-  aadd(&A4(P, A.lW, r, 0, ks), l[0]);
-  aadd(&A4(P, A.lW, r, 1, ks), l[1]);
-  aadd(&A4(P, A.lW, r, 2, ks), l[2] * sy);
-  aadd(&A4(P, A.lW, r, 3, ks), l[3]);
-}
 __global__ void __launch_bounds__(256) k_a_bc_W_x(Params P, Bufs B, Adj A) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.ny * 2 * H * P.M) return;
@@ -823,6 +801,61 @@ __global__ void __launch_bounds__(256) k_a_bc_W_x(Params P, Bufs B, Adj A) {
   aadd(&A4(P, A.lW, r, 1, ks), l[1] * sx);
   aadd(&A4(P, A.lW, r, 2, ks), l[2]);
   aadd(&A4(P, A.lW, r, 3, ks), l[3]);
+}
+
+// both sides in one launch (2D): x-side frame cells of rows [0, ny) as in
+// the x pass; a y-side frame cell takes its side's map (inflow, or the
+// source row with the normal velocity negated at a reflective side), and
+// where that source is an x-side frame cell (a corner), the x side's map on
+// top: the sum the two passes in sequence deliver
+MMD void a_bc_W_to(const Params& P, const Adj& A, int r, int side_type, int ks, int flip,
+                   double sgn, const double l[4]) {
+  if (side_type == 2 && r == P.inflow_mat) {
+    for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
+    return;
+  }
+  for (int v = 0; v < 4; v++) aadd(&A4(P, A.lW, r, v, ks), v == flip ? l[v] * sgn : l[v]);
+}
+__global__ void __launch_bounds__(256) k_a_bc_W2(Params P, Bufs B, Adj A) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
+  if (t >= (nxs + nys) * P.M) return;
+  int r, i, j, ytype = -1, sj = 0;
+  if (t < nxs * P.M) {
+    r = t / nxs;
+    int rem = t % nxs, q = rem % (2 * H);
+    j = rem / (2 * H);
+    i = q < H ? -1 - q : P.nx + (q - H);
+  } else {
+    t -= nxs * P.M;
+    r = t / nys;
+    int rem = t % nys, q = rem % (2 * H);
+    i = rem / (2 * H) - H;
+    j = q < H ? -1 - q : P.ny + (q - H);
+    ytype = q < H ? P.bc[2] : P.bc[3];
+    sj = q < H ? src_lo(j, ytype) : src_hi(j, P.ny, ytype);
+  }
+  int k = cid(P, i, j);
+  double l[4];
+  for (int v = 0; v < 4; v++) {
+    l[v] = A4(P, A.lW, r, v, k);
+    A4(P, A.lW, r, v, k) = 0.0;
+  }
+  if (ytype >= 0) {
+    if (ytype == 2 && r == P.inflow_mat) {
+      for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
+      return;
+    }
+    l[2] = l[2] * (ytype == 1 ? -1.0 : 1.0);
+    if (i >= 0 && i < P.nx) {
+      a_bc_W_to(P, A, r, -1, cid(P, i, sj), -1, 1.0, l);
+      return;
+    }
+    j = sj;  // corner: on to the x side's source of row sj
+  }
+  int xtype = i < 0 ? P.bc[0] : P.bc[1];
+  int si = i < 0 ? src_lo(i, xtype) : src_hi(i, P.nx, xtype);
+  a_bc_W_to(P, A, r, xtype, cid(P, si, j), 1, xtype == 1 ? -1.0 : 1.0, l);
 }
 
 // ---------------------------------------------------------------------------

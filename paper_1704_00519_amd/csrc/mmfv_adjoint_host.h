@@ -294,8 +294,10 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     LAUNCH(k_a_mix<D>, gm, bl, P, c->B, A);
     if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphis);
-    if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
-    LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
+    if (D == 2)
+      LAUNCH(k_a_bc_ls2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphis);
+    else
+      LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphis);
     // phase 2: the stage's input with the states it read (kept by the
     // segment recompute); for s > 0 also the time-n state in buffer 0, the
     // velocity and the time-n level set
@@ -314,8 +316,7 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     cp.fill0(A.lal, (5 * M + 1) * nc * 8);  // lal..lcy, lphi
     snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp, false);
     LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
-    LAUNCH(k_a_ls<D>, g, bl, P, c->B, A, b[s], cc[s]);
-    LAUNCH(k_a_update, g, bl, P, A, b[s], cc[s]);
+    LAUNCH(k_a_ls<D>, dim3(g.x, g.y, 2), bl, P, c->B, A, b[s], cc[s]);  // and the update
     LAUNCH(k_a_flux<D>, lin_grid(D == 2 ? nfx0 + nfx1 : nfx0), dim3(256), P, c->B, A, sidx,
            cc[s]);
     if (s == 0) {
@@ -324,8 +325,10 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     }
     LAUNCH(k_a_iface<D>, g, bl, P, c->B, A, sidx, cc[s], s == 0 ? 1 : 0);
     if (D == 2)
-      LAUNCH(k_a_bc_W_y, lin_grid((long)(P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B, A);
-    LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
+      LAUNCH(k_a_bc_W2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B,
+             A);
+    else
+      LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
     if (D == 2) {
       // tile-wise, on the tiles of the stage's own level set (its snapshot was
       // classified on loading); lW is read throughout, lW2 written
@@ -339,8 +342,10 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     }
     LAUNCH(k_a_real<D>, gm, bl, P, c->B, A, sidx);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphi);
-    if (D == 2) LAUNCH(k_a_bc_ls_y, lin_grid((long)(P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
-    LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
+    if (D == 2)
+      LAUNCH(k_a_bc_ls2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
+    else
+      LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
   }
   LAUNCH(k_a_finish, g, bl, P, A);
 }
