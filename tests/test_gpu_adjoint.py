@@ -174,3 +174,31 @@ def test_centroid_gradient_against_tangent_and_differences(pk):
         fd = (Jp - Jm) / (2 * h)
         print("param", q, "fd", fd, "adjoint", g[q])
         assert abs(fd - g[q]) <= 1e-4 * max(abs(g[q]), 1e-3 * np.abs(g).max())
+
+
+@pytest.mark.skip(reason="capturing the reverse calls as graphs (executable graph updated "
+                  "in place between calls) faulted the GPU twice, also with every update "
+                  "waiting for the graph's previous launch; that path is switched off and "
+                  "reverse calls launch their kernels directly")
+def test_reverse_graph_matches_direct(pk):
+    """Reverse calls without inputs or outputs on a stream are captured as
+    graphs (the executable graph updated in place from call to call, and
+    rebuilt where a segment of another length is recomputed); the gradient
+    equals that of direct launches on the null stream up to the order of the
+    atomic sums."""
+    from paper_1704_00519_amd import adjoint as ad
+    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32))
+    params = np.array([0.138, 3.15, 1.22])
+    steps, K = 40, 16  # segments of 16, 16 and 8 steps
+    grads = []
+    for stream in (None, torch.cuda.Stream()):
+        kw = {} if stream is None else {"stream": stream.cuda_stream}
+        s = prob.solver(params, **kw)
+        alpha0 = s.get()["alpha"]
+        s.step(steps, record=K)
+        grads.append(ad.reverse_gradient(prob, s, alpha0, steps, params))
+        torch.cuda.synchronize()
+    g0, g1 = grads
+    print("direct", g0, "graph", g1)
+    assert np.all(np.isfinite(g1))
+    assert np.all(np.abs(g1 - g0) <= 1e-10 * np.abs(g0).max())
