@@ -364,19 +364,20 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
   size_t nQ = (size_t)P.M * nv * plane, nA = (size_t)P.M * plane;
   Adj& A = c->A;
   SnapLayout L = snap_layout(P);
-  // first reverse call: keep the forward state after the last recorded step
+  // first reverse call: keep the forward state after the last recorded step;
+  // every call: keep the counters, scalars and sums (restored at the end)
+  Copies sv;
   if (c->tape_rev == c->tape_n) {
     HIP_OK(c, grow(c, &c->final_snap, &c->final_cap, L.bytes));
-    Copies cp;
-    snap_save(c, c->final_snap, 0, cp);
-    cp.fill0(A.linflow, 4 * 8);
-    cp.fill0(A.lQ, (size_t)P.M * 4 * P.NC * 8);
-    cp.fill0(A.lphi, (size_t)P.NC * 8);
-    cp.run(c);
+    snap_save(c, c->final_snap, 0, sv);
+    sv.fill0(A.linflow, 4 * 8);
+    sv.fill0(A.lQ, (size_t)P.M * 4 * P.NC * 8);
+    sv.fill0(A.lphi, (size_t)P.NC * 8);
   }
-  cpy(c, c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
-  cpy(c, c->scal_save, c->B.scal, 8 * sizeof(double));
-  cpy(c, c->cons_save, c->B.cons, CONS_N * sizeof(double));
+  sv.add(c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
+  sv.add(c->scal_save, c->B.scal, 8 * sizeof(double));
+  sv.add(c->cons_save, c->B.cons, CONS_N * sizeof(double));
+  sv.run(c);
   // inputs (device copies of host arrays in the staging buffer)
   const double *dQ = lamQ_in, *dphi = lamPhi_in, *dal = lamAlpha_in;
   if (ptr_kind == MM_HOST && (lamQ_in || lamPhi_in || lamAlpha_in || lamQ_out || lamPhi_out)) {
@@ -439,12 +440,13 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
     }
   }
   // the forward state after the recorded run, and the diagnostics, as they were
-  if (c->D == 2) snap_load<2>(c, c->final_snap, 0);
-  else snap_load<1>(c, c->final_snap, 0);
+  Copies rs;
+  rs.add(c->B.scal, c->scal_save, 8 * sizeof(double));
+  rs.add(c->B.cons, c->cons_save, CONS_N * sizeof(double));
+  if (c->D == 2) snap_load<2>(c, c->final_snap, 0, &rs);
+  else snap_load<1>(c, c->final_snap, 0, &rs);
   hipLaunchKernelGGL(k_restore_ctr, dim3(1), dim3(64), 0, c->stream, c->B.ctr,
                      (const unsigned long long*)c->ctr_save);
-  cpy(c, c->B.scal, c->scal_save, 8 * sizeof(double));
-  cpy(c, c->B.cons, c->cons_save, CONS_N * sizeof(double));
   HIP_OK(c, hipGetLastError());
   // host outputs need the work done; otherwise the next call may queue
   // behind this one

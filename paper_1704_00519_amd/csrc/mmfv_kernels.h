@@ -2209,12 +2209,25 @@ __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int n
 // without the list: every cut cell lies in a listed tile).  The geometry reads
 // the level set and the densities, the list the distances and occupancy,
 // and neither writes what the other reads.
+// With save_Q (the adjoint's recompute), workgroups from 2 nt on copy the
+// updated state and its occupancy, before the mixing changes them, to
+// save_Q / save_occ.
 template <int D>
 __global__ void __launch_bounds__(256) k_tiles_geom(Params P, Bufs B, int didx, int nidx,
-                                                    int nt) {
+                                                    int nt, double* save_Q, uint8_t* save_occ) {
   int b = blockIdx.x;
   if (b < nt) {
     tile_flag(P, B, didx, nidx, b);
+    return;
+  }
+  if (b >= 2 * nt) {
+    size_t nq = (size_t)P.M * (D + 2) * P.NC, nthr = (size_t)(gridDim.x - 2 * nt) * blockDim.x;
+    const double* Q = B.Q[didx];
+    for (size_t w = (size_t)(b - 2 * nt) * blockDim.x + threadIdx.x; w < nq + P.NC; w += nthr)
+      if (w < nq)
+        save_Q[w] = Q[w];
+      else
+        save_occ[w - nq] = B.occ[didx][w - nq];
     return;
   }
   b -= nt;

@@ -454,13 +454,9 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
   }
   classify<D>(c);
   int nt = n_tiles(P);
-  LAUNCH(k_tiles_geom<D>, dim3(2 * nt), tb, P, c->B, didx, nidx, nt);
-  if (save_Q) {
-    Copies cp;
-    cp.add(save_Q, c->B.Q[didx], (size_t)P.M * (D + 2) * P.NC * sizeof(double));
-    cp.add(save_occ, c->B.occ[didx], (size_t)P.NC);
-    cp.run(c);
-  }
+  // with save_Q, Q* and its occupancy are copied by extra workgroups
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nt + (save_Q ? 512 : 0)), tb, P, c->B, didx, nidx, nt,
+         save_Q, save_occ);
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
 }
