@@ -413,9 +413,19 @@ MMD void a_hj(const Params& P, const Bufs& B, const Adj& A, int r, int i, int j,
 }
 
 // grid z = 0: the level-set stage; z = 1: the RK update of Q (independent:
-// they share no adjoint)
+// they share no adjoint); z = 2 (with tiles): the tile list of the stage's
+// own level set for the ghost-extension adjoint (its counter was cleared
+// before), over all workgroups of the slice
 template <int D>
-__global__ void __launch_bounds__(256) k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef) {
+__global__ void __launch_bounds__(256) k_a_ls(Params P, Bufs B, Adj A, double bcoef, double ccoef,
+                                              int sidx) {
+  if (blockIdx.z == 2) {
+    int nb = gridDim.x * gridDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
+    int nt = tiles_x(P) * ((P.ny + tile_h(P) - 1) / tile_h(P));
+    for (int t = blockIdx.y * gridDim.x + blockIdx.x; t < nt; t += nb)
+      tile_flag(P, B, sidx, sidx, t, tid, blockDim.x * blockDim.y);
+    return;
+  }
   ADJ_CELL_LOOP
   if (blockIdx.z == 1) {
     a_update_cell(P, A, k, bcoef, ccoef);

@@ -315,8 +315,10 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     cp.fill0(A.lW, M * 4 * nc * 8);
     cp.fill0(A.lal, (5 * M + 1) * nc * 8);  // lal..lcy, lphi
     snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp, false);
-    LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
-    LAUNCH(k_a_ls<D>, dim3(g.x, g.y, 2), bl, P, c->B, A, b[s], cc[s]);  // and the update
+    // the step size of step n (the same for all its stages)
+    if (s == ns - 1) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
+    // with the update and (2D) the tile list of the stage's own level set
+    LAUNCH(k_a_ls<D>, dim3(g.x, g.y, D == 2 ? 3 : 2), bl, P, c->B, A, b[s], cc[s], sidx);
     LAUNCH(k_a_flux<D>, lin_grid(D == 2 ? nfx0 + nfx1 : nfx0), dim3(256), P, c->B, A, sidx,
            cc[s]);
     if (s == 0) {
@@ -332,7 +334,6 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     if (D == 2) {
       // tile-wise, on the tiles of the stage's own level set (its snapshot was
       // classified on loading); lW is read throughout, lW2 written
-      LAUNCH(k_tiles, dim3(n_tiles(P)), dim3(256), P, c->B, sidx, sidx);
       cpy(c, A.lW2, A.lW, M * 4 * nc * 8);
       LAUNCH(k_a_ext_tiles, dim3(tile_grid(c).x, P.M), dim3(256), P, c->B, A, sidx);
       std::swap(A.lW, A.lW2);  // the written buffer holds the result

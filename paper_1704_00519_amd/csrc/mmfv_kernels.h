@@ -2183,12 +2183,13 @@ MMD int tile_h(const Params& P) { return P.dim == 2 ? 16 : 1; }
 MMD int tiles_x(const Params& P) { return (P.nx + tile_w(P) - 1) / tile_w(P); }
 
 
-MMD void tile_flag(const Params& P, const Bufs& B, int didx, int nidx, int tile) {
+MMD void tile_flag(const Params& P, const Bufs& B, int didx, int nidx, int tile, int tid,
+                   int nthr) {
   int tw = tile_w(P), th = tile_h(P);
   int i0 = (tile % tiles_x(P)) * tw, j0 = (tile / tiles_x(P)) * th;
   int ew = tw + 2, eh = P.dim == 2 ? th + 2 : 1;
   bool f = false;
-  for (int q = threadIdx.x; q < ew * eh; q += blockDim.x) {
+  for (int q = tid; q < ew * eh; q += nthr) {
     int i = i0 - 1 + q % ew, j = P.dim == 2 ? j0 - 1 + q / ew : 0;
     if (!interior(P, i, j)) continue;
     int k = cid(P, i, j);
@@ -2196,13 +2197,13 @@ MMD void tile_flag(const Params& P, const Bufs& B, int didx, int nidx, int tile)
     if (B.dcut[k] <= 8 || B.dls[k] <= RV || B.occ[didx][k] != own || B.occ[nidx][k] != own)
       f = true;
   }
-  if (__syncthreads_or(f) && threadIdx.x == 0) {
+  if (__syncthreads_or(f) && tid == 0) {
     unsigned long long at = atomicAdd(&B.ctr[C_NTILES], 1ull);
     B.tiles[at] = tile;
   }
 }
 __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
-  tile_flag(P, B, didx, nidx, (int)blockIdx.x);
+  tile_flag(P, B, didx, nidx, (int)blockIdx.x, (int)threadIdx.x, (int)blockDim.x);
 }
 // Tile list (workgroups below nt, one per tile) beside the geometry and
 // volume-fraction correction of every cut cell (the other nt, one per tile,
@@ -2217,7 +2218,7 @@ __global__ void __launch_bounds__(256) k_tiles_geom(Params P, Bufs B, int didx, 
                                                     int nt, double* save_Q, uint8_t* save_occ) {
   int b = blockIdx.x;
   if (b < nt) {
-    tile_flag(P, B, didx, nidx, b);
+    tile_flag(P, B, didx, nidx, b, (int)threadIdx.x, (int)blockDim.x);
     return;
   }
   if (b >= 2 * nt) {
