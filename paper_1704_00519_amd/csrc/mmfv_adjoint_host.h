@@ -343,10 +343,15 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     }
     LAUNCH(k_a_real<D>, gm, bl, P, c->B, A, sidx);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphi);
-    if (D == 2)
-      LAUNCH(k_a_bc_ls2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
-    else
-      LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
+    // the frame's level-set adjoint goes to the inside cells here only at
+    // the step's first stage; before, the next stage copies it along and
+    // passes it on with its own (the pass is linear)
+    if (s == 0) {
+      if (D == 2)
+        LAUNCH(k_a_bc_ls2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
+      else
+        LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
+    }
   }
   LAUNCH(k_a_finish, g, bl, P, A);
 }
