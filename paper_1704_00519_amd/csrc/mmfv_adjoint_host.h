@@ -64,8 +64,8 @@ static void snap_save(mm_ctx* c, char* dst, int sidx, Copies& cp) {
 
 // restore a stage snapshot into buffer sidx (with optional extra copies in
 // the same launch) with its classification (a function of the level set and
-// the indicator, kept with the snapshot); with tiles the classification is
-// recomputed and the tile list rebuilt, else the list is emptied
+// the indicator, kept with the snapshot); the tile list is emptied and, with
+// tiles, rebuilt
 template <int D>
 static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = nullptr,
                       bool tiles = true) {
@@ -82,16 +82,11 @@ static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = null
   cp.add(c->B.occ[sidx], src + L.occ, nc);
   cp.add(c->B.chi, src + L.chi, nc);
   cp.add(c->B.vfc, src + L.vfc, nc * 2);
-  if (tiles) {
-    cp.run(c);
-    classify<D>(c);
-    build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
-    return;
-  }
   uint8_t* cls[4] = {c->B.cut, c->B.xs, c->B.dcut, c->B.dls};
   for (int q = 0; q < 4; q++) cp.add(cls[q], src + L.cls + q * nc, nc);
   cp.fill0(&c->B.ctr[C_NTILES], sizeof(unsigned long long));
   cp.run(c);
+  if (tiles) build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
 }
 
 static void ext_save(mm_ctx* c, char* dst, Copies& cp) {
@@ -247,10 +242,6 @@ static void zero(mm_ctx* c, void* p, size_t bytes) {
   (void)hipMemsetAsync(p, 0, bytes, c->stream);
 }
 
-__global__ void k_restore_ctr(unsigned long long* ctr, const unsigned long long* save) {
-  int t = threadIdx.x;
-  if (t < C_N && t != C_STAMP) ctr[t] = save[t];
-}
 
 // reverse of recorded step n: on entry A.lQ / A.lphi hold the adjoint of the
 // state after step n (and A.lalpha that of its volume fractions), on exit
@@ -446,13 +437,17 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
     }
   }
   // the forward state after the recorded run, and the diagnostics, as they were
+  // counters as they were, but the mixing stamp (it only grows) and the tile
+  // count (the tile list is rebuilt)
+  static_assert(C_STAMP + 1 == C_NTILES, "counters restored in two ranges");
   Copies rs;
   rs.add(c->B.scal, c->scal_save, 8 * sizeof(double));
   rs.add(c->B.cons, c->cons_save, CONS_N * sizeof(double));
+  rs.add(c->B.ctr, c->ctr_save, C_STAMP * sizeof(unsigned long long));
+  rs.add(c->B.ctr + C_NTILES + 1, c->ctr_save + C_NTILES + 1,
+         (C_N - C_NTILES - 1) * sizeof(unsigned long long));
   if (c->D == 2) snap_load<2>(c, c->final_snap, 0, &rs);
   else snap_load<1>(c, c->final_snap, 0, &rs);
-  hipLaunchKernelGGL(k_restore_ctr, dim3(1), dim3(64), 0, c->stream, c->B.ctr,
-                     (const unsigned long long*)c->ctr_save);
   HIP_OK(c, hipGetLastError());
   // host outputs need the work done; otherwise the next call may queue
   // behind this one
