@@ -339,8 +339,7 @@ __global__ void __launch_bounds__(256) k_a_bc_ls_x(Params P, double* l) {
 // both sides in one launch (2D): every frame cell passes its adjoint to the
 // interior source of the two maps composed (a corner to the source of the
 // x side of its source row), the sum the two passes in sequence deliver
-__global__ void __launch_bounds__(256) k_a_bc_ls2(Params P, double* l) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+MMD void a_bc_ls2_cell(const Params& P, double* l, int t) {
   int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
   if (t >= nxs + nys) return;
   int i, j, si, sj;
@@ -361,6 +360,9 @@ __global__ void __launch_bounds__(256) k_a_bc_ls2(Params P, double* l) {
   double x = l[k];
   l[k] = 0.0;
   aadd(&l[ks], x);
+}
+__global__ void __launch_bounds__(256) k_a_bc_ls2(Params P, double* l) {
+  a_bc_ls2_cell(P, l, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,10 +573,35 @@ MMD void a_face(const Params& P, const Bufs& B, const Adj& A, const double* Q,
   }
 }
 
+// own-material velocity of the remaining band cells (stage 0), reversed
+template <int D>
+MMD void a_vfill_cell(const Params& P, const Bufs& B, const Adj& A, int sidx, int i, int j) {
+  int k = cid(P, i, j);
+  if (B.dls[k] > RV || B.vit[k] != 0) return;
+  double lx = A.lvx[k], ly = A.lvy[k];
+  A.lvx[k] = 0.0;
+  A.lvy[k] = 0.0;
+  if (lx == 0.0 && ly == 0.0) return;
+  bool valid;
+  int r = B.chi[k];
+  Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
+  if (!valid) return;
+  aadd(&A4(P, A.lW, r, 1, k), lx);
+  if (D == 2) aadd(&A4(P, A.lW, r, 2, k), ly);
+}
+
 template <int D>
 // x-faces (threads t < nx0 faces) and, in 2D, the y-faces after them, in one
-// launch: twice the faces in flight
-__global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef) {
+// launch: twice the faces in flight; workgroups from nfb on (stage 0) reverse
+// the velocity fill, one thread per cell (it shares no adjoint with the
+// fluxes but the state adjoints, which both add to with atomics)
+__global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sidx, double ccoef,
+                                                int nfb) {
+  if ((int)blockIdx.x >= nfb) {
+    int q = ((int)blockIdx.x - nfb) * blockDim.x + threadIdx.x;
+    if (q < P.nx * P.ny) a_vfill_cell<D>(P, B, A, sidx, q % P.nx, q / P.nx);
+    return;
+  }
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int n0 = (P.nx + 1) * P.ny;
   int dir = t < n0 ? 0 : 1;
@@ -627,21 +654,6 @@ __global__ void __launch_bounds__(256) k_a_flux(Params P, Bufs B, Adj A, int sid
 // Level-set velocity v^n (stage 0): own-material velocity in the remaining
 // band cells, then the extension sweeps in reverse.
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ void __launch_bounds__(256) k_a_vfill(Params P, Bufs B, Adj A, int sidx) {
-  ADJ_CELL_LOOP
-  if (B.dls[k] > RV || B.vit[k] != 0) return;
-  double lx = A.lvx[k], ly = A.lvy[k];
-  A.lvx[k] = 0.0;
-  A.lvy[k] = 0.0;
-  if (lx == 0.0 && ly == 0.0) return;
-  bool valid;
-  int r = B.chi[k];
-  Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
-  if (!valid) return;
-  A4(P, A.lW, r, 1, k) += lx;
-  if (D == 2) A4(P, A.lW, r, 2, k) += ly;
-}
 
 template <int D>
 __global__ void __launch_bounds__(256) k_a_vext(Params P, Bufs B, Adj A, int sweep) {
@@ -700,8 +712,74 @@ __global__ void __launch_bounds__(256) k_a_vext(Params P, Bufs B, Adj A, int swe
 // Reduced interface exchange (Sec. 2.3.2) in cut cells; at stage 0 also the
 // interface velocity S_M n.  Out: A.lW of the pair, A.lcx / A.lcy of a.
 // ---------------------------------------------------------------------------
+// both sides at once (2D), frame cell t: x-side frame cells of rows [0, ny) as in
+// the x pass; a y-side frame cell takes its side's map (inflow, or the
+// source row with the normal velocity negated at a reflective side), and
+// where that source is an x-side frame cell (a corner), the x side's map on
+// top: the sum the two passes in sequence deliver
+MMD void a_bc_W_to(const Params& P, const Adj& A, int r, int side_type, int ks, int flip,
+                   double sgn, const double l[4]) {
+  if (side_type == 2 && r == P.inflow_mat) {
+    for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
+    return;
+  }
+  for (int v = 0; v < 4; v++) aadd(&A4(P, A.lW, r, v, ks), v == flip ? l[v] * sgn : l[v]);
+}
+MMD void a_bc_W2_cell(const Params& P, const Adj& A, int t) {
+  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
+  if (t >= (nxs + nys) * P.M) return;
+  int r, i, j, ytype = -1, sj = 0;
+  if (t < nxs * P.M) {
+    r = t / nxs;
+    int rem = t % nxs, q = rem % (2 * H);
+    j = rem / (2 * H);
+    i = q < H ? -1 - q : P.nx + (q - H);
+  } else {
+    t -= nxs * P.M;
+    r = t / nys;
+    int rem = t % nys, q = rem % (2 * H);
+    i = rem / (2 * H) - H;
+    j = q < H ? -1 - q : P.ny + (q - H);
+    ytype = q < H ? P.bc[2] : P.bc[3];
+    sj = q < H ? src_lo(j, ytype) : src_hi(j, P.ny, ytype);
+  }
+  int k = cid(P, i, j);
+  double l[4];
+  for (int v = 0; v < 4; v++) {
+    l[v] = A4(P, A.lW, r, v, k);
+    A4(P, A.lW, r, v, k) = 0.0;
+  }
+  if (ytype >= 0) {
+    if (ytype == 2 && r == P.inflow_mat) {
+      for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
+      return;
+    }
+    l[2] = l[2] * (ytype == 1 ? -1.0 : 1.0);
+    if (i >= 0 && i < P.nx) {
+      a_bc_W_to(P, A, r, -1, cid(P, i, sj), -1, 1.0, l);
+      return;
+    }
+    j = sj;  // corner: on to the x side's source of row sj
+  }
+  int xtype = i < 0 ? P.bc[0] : P.bc[1];
+  int si = i < 0 ? src_lo(i, xtype) : src_hi(i, P.nx, xtype);
+  a_bc_W_to(P, A, r, xtype, cid(P, si, j), 1, xtype == 1 ? -1.0 : 1.0, l);
+}
+
+// grid z = 1 (2D): the frames of the primitive states, one thread per frame
+// cell and material over all workgroups of the slice; the exchange adds to
+// the state adjoints of cut cells with atomics, as the frames do to the cells
+// next to the boundary
 template <int D>
 __global__ void __launch_bounds__(256) k_a_iface(Params P, Bufs B, Adj A, int sidx, double ccoef, int stage0) {
+  if (blockIdx.z == 1) {
+    int nb = gridDim.x * gridDim.y, nt = blockDim.x * blockDim.y;
+    int nfr = (P.ny + P.nx + 2 * H) * 2 * H * P.M;
+    for (int t = (blockIdx.y * gridDim.x + blockIdx.x) * nt + threadIdx.y * blockDim.x + threadIdx.x;
+         t < nfr; t += nb * nt)
+      a_bc_W2_cell(P, A, t);
+    return;
+  }
   ADJ_CELL_LOOP
   if (!B.cut[k]) return;
   unsigned b = B.xs[k];
@@ -768,8 +846,8 @@ __global__ void __launch_bounds__(256) k_a_iface(Params P, Bufs B, Adj A, int si
     g[q] = lX[1] * X1.d[q] + lX[2] * X2.d[q] + lX[3] * X3.d[q] + lvx * ovx.d[q] + lvy * ovy.d[q];
   for (int c = 0; c < 4; c++) {
     if (D == 1 && c == 2) continue;
-    A4(P, A.lW, bb, c, k) += g[c];
-    A4(P, A.lW, a, c, k) += g[4 + c];
+    aadd(&A4(P, A.lW, bb, c, k), g[c]);
+    aadd(&A4(P, A.lW, a, c, k), g[4 + c]);
   }
   A1(P, A.lcx, a, k) += g[8];
   if (D == 2) A1(P, A.lcy, a, k) += g[9];
@@ -813,60 +891,6 @@ __global__ void __launch_bounds__(256) k_a_bc_W_x(Params P, Bufs B, Adj A) {
   aadd(&A4(P, A.lW, r, 3, ks), l[3]);
 }
 
-// both sides in one launch (2D): x-side frame cells of rows [0, ny) as in
-// the x pass; a y-side frame cell takes its side's map (inflow, or the
-// source row with the normal velocity negated at a reflective side), and
-// where that source is an x-side frame cell (a corner), the x side's map on
-// top: the sum the two passes in sequence deliver
-MMD void a_bc_W_to(const Params& P, const Adj& A, int r, int side_type, int ks, int flip,
-                   double sgn, const double l[4]) {
-  if (side_type == 2 && r == P.inflow_mat) {
-    for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
-    return;
-  }
-  for (int v = 0; v < 4; v++) aadd(&A4(P, A.lW, r, v, ks), v == flip ? l[v] * sgn : l[v]);
-}
-__global__ void __launch_bounds__(256) k_a_bc_W2(Params P, Bufs B, Adj A) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int nxs = P.ny * 2 * H, nys = (P.nx + 2 * H) * 2 * H;
-  if (t >= (nxs + nys) * P.M) return;
-  int r, i, j, ytype = -1, sj = 0;
-  if (t < nxs * P.M) {
-    r = t / nxs;
-    int rem = t % nxs, q = rem % (2 * H);
-    j = rem / (2 * H);
-    i = q < H ? -1 - q : P.nx + (q - H);
-  } else {
-    t -= nxs * P.M;
-    r = t / nys;
-    int rem = t % nys, q = rem % (2 * H);
-    i = rem / (2 * H) - H;
-    j = q < H ? -1 - q : P.ny + (q - H);
-    ytype = q < H ? P.bc[2] : P.bc[3];
-    sj = q < H ? src_lo(j, ytype) : src_hi(j, P.ny, ytype);
-  }
-  int k = cid(P, i, j);
-  double l[4];
-  for (int v = 0; v < 4; v++) {
-    l[v] = A4(P, A.lW, r, v, k);
-    A4(P, A.lW, r, v, k) = 0.0;
-  }
-  if (ytype >= 0) {
-    if (ytype == 2 && r == P.inflow_mat) {
-      for (int v = 0; v < 4; v++) aadd(&A.linflow[v], l[v]);
-      return;
-    }
-    l[2] = l[2] * (ytype == 1 ? -1.0 : 1.0);
-    if (i >= 0 && i < P.nx) {
-      a_bc_W_to(P, A, r, -1, cid(P, i, sj), -1, 1.0, l);
-      return;
-    }
-    j = sj;  // corner: on to the x side's source of row sj
-  }
-  int xtype = i < 0 ? P.bc[0] : P.bc[1];
-  int si = i < 0 ? src_lo(i, xtype) : src_hi(i, P.nx, xtype);
-  a_bc_W_to(P, A, r, xtype, cid(P, si, j), 1, xtype == 1 ? -1.0 : 1.0, l);
-}
 
 // ---------------------------------------------------------------------------
 // Ghost extension: the (cell, material) pairs filled in sweep `sweep` pass
@@ -1248,6 +1272,21 @@ __global__ void __launch_bounds__(256) k_a_finish(Params P, Adj A) {
   for (int r = 0; r < P.M; r++)
     for (int v = 0; v < 4; v++) A4(P, A.lQ, r, v, k) += A4(P, A.lQn, r, v, k);
   A.lphi[k] += A.lphin[k];
+}
+// 2D: the level-set frame pass of the step's first stage (workgroups below
+// nfrb) beside the finish (the others, one thread per cell; its level-set
+// add is atomic, as the frame's adds to the cells next to the boundary)
+__global__ void __launch_bounds__(256) k_a_bc_ls2_finish(Params P, Adj A, int nfrb) {
+  if ((int)blockIdx.x < nfrb) {
+    a_bc_ls2_cell(P, A.lphi, blockIdx.x * blockDim.x + threadIdx.x);
+    return;
+  }
+  int q = ((int)blockIdx.x - nfrb) * blockDim.x + threadIdx.x;
+  if (q >= P.nx * P.ny) return;
+  int k = cid(P, q % P.nx, q / P.nx);
+  for (int r = 0; r < P.M; r++)
+    for (int v = 0; v < 4; v++) A4(P, A.lQ, r, v, k) += A4(P, A.lQn, r, v, k);
+  aadd(&A.lphi[k], A.lphin[k]);
 }
 
 }  // namespace mmfv

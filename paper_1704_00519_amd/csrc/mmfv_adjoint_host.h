@@ -310,18 +310,17 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     if (s == ns - 1) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
     // with the update and (2D) the tile list of the stage's own level set
     LAUNCH(k_a_ls<D>, dim3(g.x, g.y, D == 2 ? 3 : 2), bl, P, c->B, A, b[s], cc[s], sidx);
-    LAUNCH(k_a_flux<D>, lin_grid(D == 2 ? nfx0 + nfx1 : nfx0), dim3(256), P, c->B, A, sidx,
-           cc[s]);
+    // at stage 0 with the velocity fill reversed in extra workgroups
+    unsigned nfb = lin_grid(D == 2 ? nfx0 + nfx1 : nfx0).x;
+    unsigned nvb = s == 0 ? lin_grid((long)P.nx * P.ny).x : 0;
+    LAUNCH(k_a_flux<D>, dim3(nfb + nvb), dim3(256), P, c->B, A, sidx, cc[s], (int)nfb);
     if (s == 0) {
-      LAUNCH(k_a_vfill<D>, g, bl, P, c->B, A, sidx);
       for (int sw = 3; sw >= 0; sw--) LAUNCH(k_a_vext<D>, g, bl, P, c->B, A, sw);
     }
-    LAUNCH(k_a_iface<D>, g, bl, P, c->B, A, sidx, cc[s], s == 0 ? 1 : 0);
-    if (D == 2)
-      LAUNCH(k_a_bc_W2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H * P.M), dim3(256), P, c->B,
-             A);
-    else
-      LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
+    // 2D: with the frames of the primitive states in grid slice z = 1
+    LAUNCH(k_a_iface<D>, dim3(g.x, g.y, D == 2 ? 2 : 1), bl, P, c->B, A, sidx, cc[s],
+           s == 0 ? 1 : 0);
+    if (D == 1) LAUNCH(k_a_bc_W_x, lin_grid((long)P.ny * 2 * H * P.M), dim3(256), P, c->B, A);
     if (D == 2) {
       // tile-wise, on the tiles of the stage's own level set (its snapshot was
       // classified on loading); lW is read throughout, lW2 written
@@ -337,14 +336,18 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     // the frame's level-set adjoint goes to the inside cells here only at
     // the step's first stage; before, the next stage copies it along and
     // passes it on with its own (the pass is linear)
+    // (2D with the finish of the step in the same launch)
     if (s == 0) {
-      if (D == 2)
-        LAUNCH(k_a_bc_ls2, lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H), dim3(256), P, A.lphi);
-      else
+      if (D == 2) {
+        unsigned nfrb = lin_grid(((long)P.ny + P.nx + 2 * H) * 2 * H).x;
+        LAUNCH(k_a_bc_ls2_finish, dim3(nfrb + lin_grid((long)P.nx * P.ny).x), dim3(256), P, A,
+               (int)nfrb);
+      } else {
         LAUNCH(k_a_bc_ls_x, lin_grid((long)P.ny * 2 * H), dim3(256), P, A.lphi);
+      }
     }
   }
-  LAUNCH(k_a_finish, g, bl, P, A);
+  if (D == 1) LAUNCH(k_a_finish, g, bl, P, A);
 }
 
 extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const double* lamPhi_in,
