@@ -64,8 +64,19 @@ MMD void aadd(double* p, double x) {
 // A.lQs); out: A.lQs, A.lal (new geometry), A.lphis (through the normal
 // directions).
 // ---------------------------------------------------------------------------
+// Grid slice z = M (the step's first reversed stage only): one thread sets
+// the step size of the step from the recorded one (no kernel of this phase
+// reads it).
 template <int D>
 __global__ void __launch_bounds__(256) k_a_mix(Params P, Bufs B, Adj A) {
+  if ((int)blockIdx.z == P.M) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+      double smax = __longlong_as_double((long long)B.ctr[C_SMAX]);
+      B.ctr[C_SMAX] = 0;
+      dt_finish<D>(P, B, smax);
+    }
+    return;
+  }
   ADJ_CELL_LOOP
   double amix = P.amix;
   // the sources of the forward mixing, from Q* and the new geometry; one

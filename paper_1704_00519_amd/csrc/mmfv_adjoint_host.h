@@ -279,10 +279,13 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
     c1.add(A.lQs, A.lQ, M * 4 * nc * 8);
     c1.add(A.lphis, A.lphi, nc * 8);
     c1.fill0(A.lal, 5 * M * nc * 8);
+    // the step's first reversed stage sets the recorded step size (grid
+    // slice z = M of the mixing adjoint); it holds for all stages of the step
+    if (s == ns - 1) c1.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
     snap_load<D>(c, next, didx, &c1, false);
     A.Qstar = (double*)seg_qstar(c, rel, s, ns);
     A.occstar = seg_qstar_occ(c, rel, s, ns);
-    LAUNCH(k_a_mix<D>, gm, bl, P, c->B, A);
+    LAUNCH(k_a_mix<D>, dim3(g.x, g.y, P.M + (s == ns - 1 ? 1 : 0)), bl, P, c->B, A);
     if (s == ns - 1 && with_alpha) LAUNCH(k_a_add_alpha, g, bl, P, c->B, A);
     LAUNCH(k_a_geom<D>, gm, bl, P, c->B, A, A.lphis);
     if (D == 2)
@@ -301,13 +304,10 @@ static void reverse_step(mm_ctx* c, int64_t n, bool with_alpha) {
       ext_add(c, cp, seg_ext(c, rel, ns));
     }
     states_copies(c, cp, seg_qstar(c, rel, s, ns), false);
-    // the recorded step size, and the adjoints of the stage's input from zero
-    cp.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
+    // the adjoints of the stage's input from zero
     cp.fill0(A.lW, M * 4 * nc * 8);
     cp.fill0(A.lal, (5 * M + 1) * nc * 8);  // lal..lcy, lphi
     snap_load<D>(c, seg_stage(c, rel, s, ns), sidx, &cp, false);
-    // the step size of step n (the same for all its stages)
-    if (s == ns - 1) LAUNCH(k_dt_fin<D>, dim3(1), dim3(1), c->P, c->B);
     // with the update and (2D) the tile list of the stage's own level set
     LAUNCH(k_a_ls<D>, dim3(g.x, g.y, D == 2 ? 3 : 2), bl, P, c->B, A, b[s], cc[s], sidx);
     // at stage 0 with the velocity fill reversed in extra workgroups
