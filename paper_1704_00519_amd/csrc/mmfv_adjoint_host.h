@@ -179,23 +179,26 @@ static void load_segment(mm_ctx* c, int64_t n0, int64_t n1) {
   double b[3], cc[3], w[3];
   int ns = rk_coefs(c->cfg, b, cc, w);
   snap_load<D>(c, c->ckpt[n0 / c->tape_K], 0);
-  // the copies between two stages go out in one launch: what the last stage
-  // read, the snapshot of the next one and, before a step, its recorded step
-  // size (stage 0 takes it over as the step size)
-  Copies cp;
+  // the copies ride on the stage's own launches: its input snapshot (and,
+  // before a step, the recorded step size, which stage 0 takes over) on the
+  // first, what it read (and after stage 0 the level-set velocity) on the
+  // last; a list too long for that goes out on its own
   for (int64_t n = n0; n < n1; n++) {
-    cp.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
     for (int s = 0; s < ns; s++) {
       int sidx = stage_src(s), didx = stage_dst(s, ns);
-      snap_save(c, seg_stage(c, n - n0, s, ns), sidx, cp);
-      cp.run(c);
+      Copies pre, post;
+      if (s == 0) pre.add(c->B.scal + S_DTFIX, c->tape_dt + n, sizeof(double));
+      snap_save(c, seg_stage(c, n - n0, s, ns), sidx, pre);
+      states_copies(c, post, seg_qstar(c, n - n0, s, ns), true);
+      if (s == 0) ext_save(c, seg_ext(c, n - n0, ns), post);
+      bool fit = pre.full.empty() && post.full.empty();
+      if (!fit) pre.run(c);
       stage<D>(c, s, sidx, 0, didx, b[s], cc[s], w[s], (double*)seg_qstar(c, n - n0, s, ns),
-               seg_qstar_occ(c, n - n0, s, ns));
-      states_copies(c, cp, seg_qstar(c, n - n0, s, ns), true);
-      if (s == 0) ext_save(c, seg_ext(c, n - n0, ns), cp);
+               seg_qstar_occ(c, n - n0, s, ns), false, fit ? pre.L : kNoCopies,
+               fit ? post.L : kNoCopies);
+      if (!fit) post.run(c);
     }
   }
-  cp.run(c);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,30 @@ struct Bufs {
 };
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
+
+// Device-to-device copies (and fills with zeros: no source), every buffer
+// 8-byte aligned: for a launch of their own, or for extra workgroups of a
+// kernel whose work touches none of them
+constexpr int MAXCOPY = 32;
+struct CopyList {
+  const char* src[MAXCOPY];
+  char* dst[MAXCOPY];
+  size_t bytes[MAXCOPY];
+  int n;
+};
+// workgroup b of nb: its share of every entry (strided over the words)
+MMD void copy_list_part(const CopyList& L, int b, int nb) {
+  for (int e = 0; e < L.n; e++) {
+    size_t words = L.bytes[e] / 8, tail = L.bytes[e] % 8;
+    const double* s8 = (const double*)L.src[e];
+    double* d8 = (double*)L.dst[e];
+    bool fill = s8 == nullptr;
+    for (size_t w = (size_t)b * blockDim.x + threadIdx.x; w < words; w += (size_t)nb * blockDim.x)
+      d8[w] = fill ? 0.0 : s8[w];
+    if (b == 0 && threadIdx.x < tail)
+      L.dst[e][words * 8 + threadIdx.x] = fill ? 0 : L.src[e][words * 8 + threadIdx.x];
+  }
+}
 enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
        C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST,
        // workgroups of the current launch that have finished (the last one
@@ -2265,8 +2289,15 @@ MMD void for_tiles(const Params& P, const Bufs& B, F body) {
 // Real states of the listed tiles (workgroups below ntb) and the row pass of
 // the ghost-band membership (the other ntb): the row pass reads only the
 // classification and the volume fractions, which the real states leave alone.
+// Workgroups from 2 ntb on run the copies of cl (the adjoint's recompute: the
+// stage's input snapshot, which neither part writes).
 template <int D>
-__global__ void __launch_bounds__(256) t_real_near_row(Params P, Bufs B, int sidx, int ntb) {
+__global__ void __launch_bounds__(256) t_real_near_row(Params P, Bufs B, int sidx, int ntb,
+                                                       CopyList cl) {
+  if ((int)blockIdx.x >= 2 * ntb) {
+    copy_list_part(cl, (int)blockIdx.x - 2 * ntb, (int)gridDim.x - 2 * ntb);
+    return;
+  }
   // a new mixing stamp per stage (the previous stage's mixing is complete)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.ctr[C_STAMP] += 1;
@@ -2513,7 +2544,13 @@ __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
   for_tiles(P, B, [&](int i, int j) { b_mix1<D>(P, B, i, j, didx, st, r, r + 1); });
 }
 template <int D>
-__global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx) {
+__global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx, CopyList cl) {
+  // grid slice z = 1: the copies of cl (the adjoint's recompute: states the
+  // stage read, which the mixing leaves alone)
+  if (blockIdx.z == 1) {
+    copy_list_part(cl, (int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    return;
+  }
   // one material per grid row, occupancy bits by word atomics
   uint32_t st = (uint32_t)B.ctr[C_STAMP];
   int r = blockIdx.y;

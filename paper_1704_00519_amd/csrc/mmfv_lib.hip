@@ -286,15 +286,8 @@ static dim3 lin_grid(long n) { return dim3((unsigned)((n + 255) / 256)); }
 #define LAUNCH(kern, grid, block, ...) \
   hipLaunchKernelGGL(kern, grid, block, 0, c->stream, __VA_ARGS__)
 
-// Several device-to-device copies (and fills with zeros: no source) in one
-// launch (grid y = entry index); every buffer starts 8-byte aligned.
-constexpr int MAXCOPY = 32;
-struct CopyList {
-  const char* src[MAXCOPY];
-  char* dst[MAXCOPY];
-  size_t bytes[MAXCOPY];
-  int n;
-};
+// Several device-to-device copies (and fills) in one launch (grid y = entry
+// index)
 __global__ void __launch_bounds__(256) k_copy_multi(CopyList L) {
   int e = blockIdx.y;
   if (e >= L.n) return;
@@ -386,11 +379,12 @@ static void build_tiles(mm_ctx* c, int didx, int nidx) {
 // partials (in 1D also the totals and, with advance, the time)
 template <int D>
 static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
-                        double w, bool advance) {
+                        double w, bool advance, const CopyList& pre) {
   const Params& P = c->P;
   dim3 g = cell_grid(c), bl = cell_block(c);
   dim3 tg = tile_grid(c), tb(256);
-  LAUNCH(t_real_near_row<D>, dim3(2 * tg.x), tb, P, c->B, sidx, (int)tg.x);
+  LAUNCH(t_real_near_row<D>, dim3(2 * tg.x + (pre.n ? 256 : 0)), tb, P, c->B, sidx, (int)tg.x,
+         pre);
   LAUNCH(t_near_col_flags<D>, dim3(tg.x + g.x * g.y), tb, P, c->B, sidx, nidx, s == 0 ? 1 : 0,
          (int)tg.x, (int)g.x, (int)g.y, (int)bl.x);
   static_assert(EXR >= 8 + 4, "the tile frame covers every sweep (k_ext <= 8)");
@@ -440,7 +434,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
 // adjoint)
 template <int D>
 static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance,
-                           double* save_Q, uint8_t* save_occ) {
+                           double* save_Q, uint8_t* save_occ, const CopyList& post) {
   const Params& P = c->P;
   dim3 tg = tile_grid(c), tb(256);
   if (D == 2) {
@@ -458,15 +452,19 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
   LAUNCH(k_tiles_geom<D>, dim3(2 * nt + (save_Q ? 512 : 0)), tb, P, c->B, didx, nidx, nt,
          save_Q, save_occ);
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
-  LAUNCH(t_mix2<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
+  LAUNCH(t_mix2<D>, dim3(tg.x, P.M, post.n ? 2 : 1), tb, P, c->B, didx, post);
 }
 
+// pre / post: copies run by extra workgroups of the stage's first and last
+// launches (the adjoint's recompute), none for a plain step
+static const CopyList kNoCopies = {{}, {}, {}, 0};
 template <int D>
 static void stage(mm_ctx* c, int s, int sidx, int nidx, int didx, double b, double cc,
                   double w, double* save_Q = nullptr, uint8_t* save_occ = nullptr,
-                  bool advance = false) {
-  stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w, advance);
-  stage_levelset<D>(c, didx, nidx, w, advance, save_Q, save_occ);
+                  bool advance = false, const CopyList& pre = kNoCopies,
+                  const CopyList& post = kNoCopies) {
+  stage_fluid<D>(c, s, sidx, nidx, didx, b, cc, w, advance, pre);
+  stage_levelset<D>(c, didx, nidx, w, advance, save_Q, save_occ, post);
 }
 
 // beta-form coefficients, and each stage's share w of the full step in the
