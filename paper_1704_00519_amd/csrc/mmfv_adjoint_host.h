@@ -377,10 +377,14 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
     sv.fill0(A.lQ, (size_t)P.M * 4 * P.NC * 8);
     sv.fill0(A.lphi, (size_t)P.NC * 8);
   }
-  sv.add(c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
-  sv.add(c->scal_save, c->B.scal, 8 * sizeof(double));
-  sv.add(c->cons_save, c->B.cons, CONS_N * sizeof(double));
+  // (the saved copies still hold them right after another reverse call)
+  if (!c->adj_clean || c->tape_rev == c->tape_n) {
+    sv.add(c->ctr_save, c->B.ctr, C_N * sizeof(unsigned long long));
+    sv.add(c->scal_save, c->B.scal, 8 * sizeof(double));
+    sv.add(c->cons_save, c->B.cons, CONS_N * sizeof(double));
+  }
   sv.run(c);
+  c->adj_clean = false;
   // inputs (device copies of host arrays in the staging buffer)
   const double *dQ = lamQ_in, *dphi = lamPhi_in, *dal = lamAlpha_in;
   if (ptr_kind == MM_HOST && (lamQ_in || lamPhi_in || lamAlpha_in || lamQ_out || lamPhi_out)) {
@@ -452,9 +456,12 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
   rs.add(c->B.ctr, c->ctr_save, C_STAMP * sizeof(unsigned long long));
   rs.add(c->B.ctr + C_NTILES + 1, c->ctr_save + C_NTILES + 1,
          (C_N - C_NTILES - 1) * sizeof(unsigned long long));
-  if (c->D == 2) snap_load<2>(c, c->final_snap, 0, &rs);
-  else snap_load<1>(c, c->final_snap, 0, &rs);
+  // (the forward tile list is rebuilt when next needed)
+  if (c->D == 2) snap_load<2>(c, c->final_snap, 0, &rs, false);
+  else snap_load<1>(c, c->final_snap, 0, &rs, false);
+  c->tiles_stale = true;
   HIP_OK(c, hipGetLastError());
+  c->adj_clean = true;
   // host outputs need the work done; otherwise the next call may queue
   // behind this one
   if (ptr_kind == MM_HOST && (lamQ_out || lamPhi_out)) HIP_OK(c, hipStreamSynchronize(c->stream));

@@ -33,6 +33,11 @@ struct mm_ctx {
   bool graph_off = false;
   std::vector<hipEvent_t> ev;  // pairs around bulk launches
   bool bulk_wide = false;      // 28 x 32 bulk tiles (large grids)
+  // after a reverse call: the counters, scalars and sums equal their saved
+  // copies (until another entry point runs), and the forward tile list is
+  // to be rebuilt before it is next needed
+  bool adj_clean = false;
+  bool tiles_stale = false;
   size_t ev_used = 0;
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
@@ -373,6 +378,17 @@ static void build_tiles(mm_ctx* c, int didx, int nidx) {
   LAUNCH(k_tiles, dim3(n_tiles(c->P)), dim3(256), c->P, c->B, didx, nidx);
 }
 
+// the forward tile list after reverse calls emptied it
+static void ensure_tiles(mm_ctx* c) {
+  if (!c->tiles_stale) return;
+  Copies z;
+  z.fill0(&c->B.ctr[C_NTILES], sizeof(unsigned long long));
+  z.run(c);
+  if (c->D == 2) build_tiles<2>(c, 0, 0);
+  else build_tiles<1>(c, 0, 0);
+  c->tiles_stale = false;
+}
+
 // first half of a stage: real and ghost states, interface exchange (and at
 // stage 0 the level-set velocity and dt), fluxes and the RK update into
 // buffer didx beside the level-set stage, conservation book-keeping
@@ -508,6 +524,8 @@ static mm_status stage_inputs(mm_ctx* c, size_t bytes, const void* src, int ptr_
 extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* chi,
                                    const double* W, int32_t ptr_kind) {
   if (!c) return MM_EINVAL;
+  c->adj_clean = false;
+  c->tiles_stale = false;
   if (!phi || !chi || !W) return fail(c, MM_EINVAL, "NULL input array");
   if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
   const Params& P = c->P;
@@ -628,6 +646,8 @@ static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_ou
 
 extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, double* t_out) {
   if (!c) return MM_EINVAL;
+  c->adj_clean = false;
+  ensure_tiles(c);
   if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
   if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
   if (record_tape < 0) return fail(c, MM_EINVAL, "record_tape < 0");
@@ -643,6 +663,7 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
 extern "C" mm_status mm_get_conserved(mm_ctx* c, double* Q, double* alpha, double* phi,
                                       int32_t* chi, int32_t ptr_kind) {
   if (!c) return MM_EINVAL;
+  c->adj_clean = false;
   if (!Q) return fail(c, MM_EINVAL, "Q must not be NULL");
   if (!c->ready && c->steps == 0) return fail(c, MM_ESTATE, "no state");
   if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
@@ -697,6 +718,8 @@ static void cons_to_diag(const double* cons, int M, mm_diag* out) {
 
 extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   if (!c || !out) return MM_EINVAL;
+  c->adj_clean = false;
+  ensure_tiles(c);
   unsigned long long ctr[C_N];
   double scal[8];
   std::vector<double> cons(CONS_N);
@@ -729,6 +752,7 @@ extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
 
 extern "C" mm_status mm_set_dt(mm_ctx* c, double dt) {
   if (!c) return MM_EINVAL;
+  c->adj_clean = false;
   double v = dt > 0.0 ? dt : 0.0;
   HIP_OK(c, hipMemcpyAsync(c->B.scal + S_DTFIX, &v, sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
@@ -738,6 +762,7 @@ extern "C" mm_status mm_set_dt(mm_ctx* c, double dt) {
 
 extern "C" mm_status mm_set_profiling(mm_ctx* c, int32_t enable) {
   if (!c) return MM_EINVAL;
+  c->adj_clean = false;
   HIP_OK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
   unsigned long long ctr[C_N];
@@ -752,6 +777,7 @@ extern "C" mm_status mm_set_profiling(mm_ctx* c, int32_t enable) {
 
 extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
   if (!c || !out) return MM_EINVAL;
+  c->adj_clean = false;
   HIP_OK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
   unsigned long long ctr[C_N];
