@@ -241,11 +241,6 @@ static mm_status adj_alloc(mm_ctx* c) {
   return MM_OK;
 }
 
-static void zero(mm_ctx* c, void* p, size_t bytes) {
-  (void)hipMemsetAsync(p, 0, bytes, c->stream);
-}
-
-
 // reverse of recorded step n: on entry A.lQ / A.lphi hold the adjoint of the
 // state after step n (and A.lalpha that of its volume fractions), on exit
 // that of the state before it

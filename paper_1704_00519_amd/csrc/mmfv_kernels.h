@@ -830,12 +830,6 @@ MMD void dt_finish(const Params& P, const Bufs& B, double smax) {
   B.scal[S_LY] = dt / P.dy;
   B.scal[S_LV] = D == 2 ? dt / (P.dx * P.dy) : dt / P.dx;
 }
-template <int D>
-__global__ void k_dt_fin(Params P, Bufs B) {
-  double smax = __longlong_as_double((long long)B.ctr[C_SMAX]);
-  B.ctr[C_SMAX] = 0;
-  dt_finish<D>(P, B, smax);
-}
 
 // ---------------------------------------------------------------------------
 // Ghost states: Jacobi sweeps over the ghost band of every material
