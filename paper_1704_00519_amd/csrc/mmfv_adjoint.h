@@ -407,17 +407,16 @@ MMD void a_hj(const Params& P, const Bufs& B, const Adj& A, int r, int i, int j,
   double d[6];
   for (int q = 0; q < 6; q++)
     d[q] = (lsv(B.phi, B.chi, r, kk[q + 1]) - lsv(B.phi, B.chi, r, kk[q])) * ih;
-  Dn<5> x[5];
   int map[5];
   if (vel > 0.0) {
     for (int q = 0; q < 5; q++) map[q] = q;
   } else {
     for (int q = 0; q < 5; q++) map[q] = 5 - q;
   }
-  for (int q = 0; q < 5; q++) x[q] = dn_seed<5>(d[map[q]], q);
-  Dn<5> y = weno5(x[0], x[1], x[2], x[3], x[4]);
+  double gq[5];
+  weno5_grad(d[map[0]], d[map[1]], d[map[2]], d[map[3]], d[map[4]], gq);
   for (int q = 0; q < 5; q++) {
-    double ld = lg * y.d[q] * ih;
+    double ld = lg * gq[q] * ih;
     if (ld == 0.0) continue;
     int m = map[q];
     aadd(&A.lphi[kk[m + 1]], ld * lsgn(B.chi, r, kk[m + 1]));
@@ -564,13 +563,13 @@ MMD void a_face(const Params& P, const Bufs& B, const Adj& A, const double* Q,
     if (D == 1 && c == 2) continue;
     double lL = lLR[c], lR = lLR[4 + c];
     if (ok) {
-      Dn<5> x[5];
-      for (int q = 0; q < 5; q++) x[q] = dn_seed<5>(comp(Wc[q], c), q);
-      Dn<5> y = weno5(x[0], x[1], x[2], x[3], x[4]);
-      for (int q = 0; q < 5; q++) lWc[q][c] += lL * y.d[q];
-      for (int q = 0; q < 5; q++) x[q] = dn_seed<5>(comp(Wc[5 - q], c), q);
-      y = weno5(x[0], x[1], x[2], x[3], x[4]);
-      for (int q = 0; q < 5; q++) lWc[5 - q][c] += lR * y.d[q];
+      double gq[5];
+      weno5_grad(comp(Wc[0], c), comp(Wc[1], c), comp(Wc[2], c), comp(Wc[3], c), comp(Wc[4], c),
+                 gq);
+      for (int q = 0; q < 5; q++) lWc[q][c] += lL * gq[q];
+      weno5_grad(comp(Wc[5], c), comp(Wc[4], c), comp(Wc[3], c), comp(Wc[2], c), comp(Wc[1], c),
+                 gq);
+      for (int q = 0; q < 5; q++) lWc[5 - q][c] += lR * gq[q];
     } else {
       lWc[2][c] += lL;
       lWc[3][c] += lR;
