@@ -159,44 +159,6 @@ MMD T weno5(T v1, T v2, T v3, T v4, T v5) {
   return (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * (a0 + a1 + a2));
 }
 
-// weno5 of doubles and its gradient g[q] = d weno5 / d v_{q+1}, in one
-// forward and one reverse pass over the formula above (the derivative of
-// each of its steps, taken in reverse order)
-MMD double weno5_grad(double v1, double v2, double v3, double v4, double v5, double g[5]) {
-  const double c13 = 13.0 / 12.0;
-  double t0 = v1 - 2.0 * v2 + v3, u0 = v1 - 4.0 * v2 + 3.0 * v3;
-  double t1 = v2 - 2.0 * v3 + v4, u1 = v2 - v4;
-  double t2 = v3 - 2.0 * v4 + v5, u2 = 3.0 * v3 - 4.0 * v4 + v5;
-  double s0 = 1e-6 + (c13 * (t0 * t0) + 0.25 * (u0 * u0));
-  double s1 = 1e-6 + (c13 * (t1 * t1) + 0.25 * (u1 * u1));
-  double s2 = 1e-6 + (c13 * (t2 * t2) + 0.25 * (u2 * u2));
-  double e0 = s0 * s0, e1 = s1 * s1, e2 = s2 * s2;
-  double a0 = 0.1 * (e1 * e2), a1 = 0.6 * (e0 * e2), a2 = 0.3 * (e0 * e1);
-  double q0 = 2.0 * v1 - 7.0 * v2 + 11.0 * v3;
-  double q1 = -v2 + 5.0 * v3 + 2.0 * v4;
-  double q2 = 2.0 * v3 + 5.0 * v4 - v5;
-  double S = a0 + a1 + a2;
-  double y = (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * S);
-  // y = N / (6 S): dN = 1 / (6 S), dS = -y / S
-  double dN = 1.0 / (6.0 * S), dS = -y / S;
-  double da0 = q0 * dN + dS, da1 = q1 * dN + dS, da2 = q2 * dN + dS;
-  double dq0 = a0 * dN, dq1 = a1 * dN, dq2 = a2 * dN;
-  double de0 = 0.6 * e2 * da1 + 0.3 * e1 * da2;
-  double de1 = 0.1 * e2 * da0 + 0.3 * e0 * da2;
-  double de2 = 0.1 * e1 * da0 + 0.6 * e0 * da1;
-  // e_k = s_k^2, s_k = eps + c13 t_k^2 + u_k^2 / 4
-  double ds0 = 2.0 * s0 * de0, ds1 = 2.0 * s1 * de1, ds2 = 2.0 * s2 * de2;
-  double dt0 = 2.0 * c13 * t0 * ds0, du0 = 0.5 * u0 * ds0;
-  double dt1 = 2.0 * c13 * t1 * ds1, du1 = 0.5 * u1 * ds1;
-  double dt2 = 2.0 * c13 * t2 * ds2, du2 = 0.5 * u2 * ds2;
-  g[0] = 2.0 * dq0 + dt0 + du0;
-  g[1] = -7.0 * dq0 - dq1 - 2.0 * dt0 - 4.0 * du0 + dt1 + du1;
-  g[2] = 11.0 * dq0 + 5.0 * dq1 + 2.0 * dq2 + dt0 + 3.0 * du0 - 2.0 * dt1 + dt2 + 3.0 * du2;
-  g[3] = 2.0 * dq1 + 5.0 * dq2 + dt1 - du1 - 2.0 * dt2 - 4.0 * du2;
-  g[4] = -dq2 + dt2 + du2;
-  return y;
-}
-
 // ---------------------------------------------------------------------------
 // Cut-cell geometry primitives (Sec. 2.3).  A point is inside material r if
 // its local level-set value is positive, or zero while r owns the point (the
