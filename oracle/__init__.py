@@ -100,6 +100,10 @@ def lib(tangent=False):
         L.or_t_weno5.argtypes = [d, d, d, d, d]
         L.or_t_hllc.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
+        up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.or_t_mixing.argtypes = [vp, dp, dp, dp, ip, dp]
+        L.or_t_extension.argtypes = [vp, dp, ip, dp, up, dp, up]
+        L.or_t_ls_velocity.argtypes = [vp, dp, ip, dp, up, dp, up, dp]
         if tangent:
             L.or_init_tangent.argtypes = [vp, dp, ip, dp, dp]
             L.or_set_inflow_tangent.argtypes = [vp, dp]
@@ -162,6 +166,49 @@ class Oracle:
         self._L.or_t_iface(self._h, int(mL), np.ascontiguousarray(WL, float),
                          int(mR), np.ascontiguousarray(WR, float), out)
         return dict(SL=out[0], SR=out[1], SM=out[2], pstar=out[3])
+
+    # -- single operators, for the oracle's own unit pins ---------------------
+    def _plane(self, a, dtype=np.float64, lead=()):
+        return np.ascontiguousarray(a, dtype=dtype).reshape(lead + (self.ny, self.nx))
+
+    def mix(self, Qt, alpha, phi, chi):
+        """Mixing alone: the state ``Qt`` after the stage update, volume
+        fractions ``alpha`` and level set (phi, chi) of the new stage; returns
+        the mixed state."""
+        Qt = self._plane(Qt, lead=(self.M, self.nv))
+        al = self._plane(alpha, lead=(self.M,))
+        out = np.zeros((self.M, self.nv, self.ny, self.nx))
+        rc = self._L.or_t_mixing(self._h, Qt, al, self._plane(phi),
+                                 self._plane(chi, np.int32), out)
+        if rc:
+            raise ValueError(f"or_t_mixing: {rc}")
+        return out
+
+    def extend(self, phi, chi, W, valid):
+        """Ghost-state extension alone: W [n_mat][4] (rho, u, v, p) and its
+        validity before; returns (W, valid) after."""
+        W = self._plane(W, lead=(self.M, 4))
+        v = self._plane(valid, np.uint8, lead=(self.M,))
+        Wo = np.zeros_like(W)
+        vo = np.zeros_like(v)
+        rc = self._L.or_t_extension(self._h, self._plane(phi), self._plane(chi, np.int32),
+                                    W, v, Wo, vo)
+        if rc:
+            raise ValueError(f"or_t_extension: {rc}")
+        return Wo, vo
+
+    def ls_velocity(self, phi, chi, vel, vok, W, valid):
+        """Level-set advection velocity alone: the velocities ``vel`` [2]
+        already set where ``vok``, material states W [n_mat][4] with their
+        validity; returns the velocity field [2][ny][nx]."""
+        out = np.zeros((2, self.ny, self.nx))
+        rc = self._L.or_t_ls_velocity(
+            self._h, self._plane(phi), self._plane(chi, np.int32),
+            self._plane(vel, lead=(2,)), self._plane(vok, np.uint8),
+            self._plane(W, lead=(self.M, 4)), self._plane(valid, np.uint8, lead=(self.M,)), out)
+        if rc:
+            raise ValueError(f"or_t_ls_velocity: {rc}")
+        return out
 
     def err_cell(self):
         return self._L.or_err_cell(self._h)

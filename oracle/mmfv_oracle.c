@@ -1579,6 +1579,125 @@ int or_get_closure(const St *s, double *cx, double *cy) {
   return OR_OK;
 }
 
+/* Interior cells of a [ny][nx] input into a padded field (frame left zero). */
+static void load_plane_d(St *s, real *f, const double *in) {
+  int nx = s->c.nx, ny = s->c.ny;
+  memset(f, 0, (size_t)s->NC * sizeof(real));
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) f[ID(s, i, j)] = in[(size_t)j * nx + i];
+}
+
+/* The level set (phi, chi) [ny][nx] into the given padded fields, with its
+ * boundary frame. */
+static int load_ls(St *s, real *phi, int *chi, const double *ph, const int32_t *ch) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t q = (size_t)j * nx + i;
+      if (ch[q] < 0 || ch[q] >= s->M || !(ph[q] >= 0.0)) return OR_EINVAL;
+      phi[ID(s, i, j)] = ph[q];
+      chi[ID(s, i, j)] = ch[q];
+    }
+  fill_ls(s, phi, chi);
+  return OR_OK;
+}
+
+/* Mixing alone (Sec. 2.3.2, the step after each Runge-Kutta sub-step).
+ * Qt [n_mat][dim+2][ny][nx] is the state after the stage update, alpha
+ * [n_mat][ny][nx] the volume fractions and (phi, chi) [ny][nx] the level set
+ * of the new stage (alpha need not be the geometry of phi: the unit pins
+ * choose both); Q [n_mat][dim+2][ny][nx] receives the mixed state.  The
+ * source and stranded-source counters of or_diag are advanced. */
+int or_t_mixing(St *s, const double *Qt, const double *alpha, const double *phi,
+                const int32_t *chi, double *Q) {
+  int nx = s->c.nx, ny = s->c.ny, nv = s->c.dim + 2;
+  size_t plane = (size_t)nx * ny;
+  if (load_ls(s, s->phit, s->chit, phi, chi)) return OR_EINVAL;
+  memset(s->Qt, 0, (size_t)s->M * 4 * s->NC * sizeof(real));
+  for (int r = 0; r < s->M; r++) {
+    load_plane_d(s, &M1(s, s->al, r, 0), alpha + (size_t)r * plane);
+    int src[4] = {0, 1, nv == 4 ? 2 : -1, nv - 1};
+    for (int v = 0; v < 4; v++)
+      if (src[v] >= 0)
+        load_plane_d(s, &M4(s, s->Qt, r, v, 0), Qt + ((size_t)r * nv + src[v]) * plane);
+  }
+  mixing(s);
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        size_t q = (size_t)j * nx + i;
+        int k = ID(s, i, j);
+        Q[((size_t)r * nv + 0) * plane + q] = RV(M4(s, s->Q, r, 0, k));
+        Q[((size_t)r * nv + 1) * plane + q] = RV(M4(s, s->Q, r, 1, k));
+        if (nv == 4) Q[((size_t)r * nv + 2) * plane + q] = RV(M4(s, s->Q, r, 2, k));
+        Q[((size_t)r * nv + nv - 1) * plane + q] = RV(M4(s, s->Q, r, 3, k));
+      }
+  return OR_OK;
+}
+
+/* Ghost-state extension alone (Sec. 2.3.2, the ghost state of a material
+ * outside its region).  (phi, chi) [ny][nx] is the level set; W
+ * [n_mat][4][ny][nx] (rho, u, v, p) and valid [n_mat][ny][nx] the states
+ * present before the extension (real cells); Wout and vout receive the
+ * states and validity after it. */
+int or_t_extension(St *s, const double *phi, const int32_t *chi, const double *W,
+                   const unsigned char *valid, double *Wout, unsigned char *vout) {
+  int nx = s->c.nx, ny = s->c.ny;
+  size_t plane = (size_t)nx * ny;
+  if (load_ls(s, s->phi, s->chi, phi, chi)) return OR_EINVAL;
+  memset(s->Wv, 0, (size_t)s->M * s->NC);
+  for (int r = 0; r < s->M; r++) {
+    for (int v = 0; v < 4; v++)
+      load_plane_d(s, &M4(s, s->W, r, v, 0), W + ((size_t)r * 4 + v) * plane);
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++)
+        M1(s, s->Wv, r, ID(s, i, j)) = valid[(size_t)r * plane + (size_t)j * nx + i] ? 1 : 0;
+  }
+  extension(s);
+  for (int r = 0; r < s->M; r++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        size_t q = (size_t)j * nx + i;
+        int k = ID(s, i, j);
+        for (int v = 0; v < 4; v++) Wout[((size_t)r * 4 + v) * plane + q] = RV(M4(s, s->W, r, v, k));
+        vout[(size_t)r * plane + q] = M1(s, s->Wv, r, k);
+      }
+  return OR_OK;
+}
+
+/* Level-set advection velocity alone (Eq. local-advection's v^n).  (phi,
+ * chi) [ny][nx] is the level set; v [2][ny][nx] and vok [ny][nx] the
+ * velocities already set (the interface cells' S_M n); W [n_mat][4][ny][nx]
+ * and valid [n_mat][ny][nx] the material states.  vout [2][ny][nx] receives
+ * the velocity field. */
+int or_t_ls_velocity(St *s, const double *phi, const int32_t *chi, const double *v,
+                     const unsigned char *vok, const double *W, const unsigned char *valid,
+                     double *vout) {
+  int nx = s->c.nx, ny = s->c.ny;
+  size_t plane = (size_t)nx * ny;
+  if (load_ls(s, s->phi, s->chi, phi, chi)) return OR_EINVAL;
+  load_plane_d(s, s->vx, v);
+  load_plane_d(s, s->vy, v + plane);
+  memset(s->vok, 0, (size_t)s->NC);
+  memset(s->Wv, 0, (size_t)s->M * s->NC);
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) s->vok[ID(s, i, j)] = vok[(size_t)j * nx + i] ? 1 : 0;
+  for (int r = 0; r < s->M; r++) {
+    for (int c = 0; c < 4; c++)
+      load_plane_d(s, &M4(s, s->W, r, c, 0), W + ((size_t)r * 4 + c) * plane);
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++)
+        M1(s, s->Wv, r, ID(s, i, j)) = valid[(size_t)r * plane + (size_t)j * nx + i] ? 1 : 0;
+  }
+  ls_velocity(s);
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      vout[(size_t)j * nx + i] = RV(s->vx[ID(s, i, j)]);
+      vout[plane + (size_t)j * nx + i] = RV(s->vy[ID(s, i, j)]);
+    }
+  return OR_OK;
+}
+
 #ifdef OR_TANGENT
 /* ------------------------------------------------------------------------ */
 /* Tangent build only: directional derivatives of the discrete step         */
