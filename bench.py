@@ -3,18 +3,23 @@
 
 One "step" is one full time step of the method (all Runge-Kutta stages of
 geometry, ghost states, interface exchange, fluxes, level set and mixing)
-on the 2D triple-point problem (Case III of the paper, 7 x 3 box, 896 x 384
-uniform cells, three ideal gases, reflective walls), FP64, synthetic analytic
-initial data already resident on the GPU.  The unit of work is one active
-material-cell RK-substep update (a cell/material pair with alpha > 0,
-updated in one stage), counted on the device.
+on the 2D nested shock-bubble problem (4 x 1 box, 2048 x 512 uniform cells,
+Mach 1.22 shock into a two-material bubble, three ideal gases, inflow /
+outflow / reflective boundaries), FP64, synthetic analytic initial data
+already resident on the GPU.  The unit of work is one active material-cell
+RK-substep update (a cell/material pair with alpha > 0, updated in one
+stage), counted on the device.  The K timed steps are a window centred in
+the workload's full run (the whole run when K is its full length), reached
+by untimed steps from t = 0 after the warm-up.
 
 Prints one JSON line.  Also reports the dominant kernel (the bulk
-flux/update kernel) against its binding roof, the FP64 vector peak, with its
-HBM fraction beside it (HIP events around its launches on the stream it runs
-on), the same kernel on an 8192 x 2048 grid whose working set must stream
-from HBM, the batched form, the adjoint, and the CPU oracle's rate on a
-bounded sample of the same workload.
+flux/update kernel) against the HBM roof from its algorithmic bytes (HIP
+events around its launches on the stream it runs on), with its FP64
+operation rate against the FP64 vector issue rate beside it, the whole
+step's HBM fraction, the same workload at 8192 x 2048 (working set far
+beyond the 256 MB last-level cache), the triple point at 896 x 384, the
+batched form, the adjoint, and the CPU oracle's rate on a bounded sample of
+the same workload.
 """
 import argparse
 import json
@@ -29,8 +34,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # FP64 vector peak of the MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops
-# (fused multiply-add) x 2.4 GHz
+# (fused multiply-add) x 2.4 GHz; the path is compiled without contraction
+# (bitwise parity with the oracle), so each lane issues at most one FP64
+# add / multiply / divide step per clock: half of that, 39.3 T operations/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP64_NOFMA_PEAK_TOPS = 39.3
+# algorithmic HBM bytes of one 2D update: read Q^(s) 32 + write Q^(s+1) 32 +
+# read Q^n in two of three stages 21.3
+BYTES_PER_UPDATE_2D = 32.0 + 32.0 + 2.0 / 3.0 * 32.0
+# the main workload and its full length
+WORKLOAD = dict(name="shock_bubble", nx=2048, ny=512)
+FULL_STEPS = 2000
 # FP64 operations (add, subtract, multiply, divide, square root) of one bulk
 # 2D update, mean over the three SSP-RK3 stages: 2 faces x (8 WENO5 + 1 HLLC)
 # + the cell's primitive state + 4 RK combinations.  Counted from the
@@ -38,11 +52,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # test keeps the two in step).
 FLOPS_PER_BULK_UPDATE_2D = 1320.0
 COUNTERS = os.path.join(ROOT, "profiles",
-                        "k_flux_bulk2_counters_triple_point_896x384_shock_bubble_8192x2048.md")
+                        "k_flux_bulk2_counters_shock_bubble_2048x512_8192x2048.md")
 KERNEL_SOURCES = ("paper_1704_00519_amd/csrc/mmfv_kernels.h", "paper_1704_00519_amd/csrc/mmfv_math.h")
 
 
-def measured_traffic(grid="896x384"):
+def measured_traffic(grid="2048x512"):
     """HBM bytes per launch of the dominant kernel on the given grid from the
     committed counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on
     a plain copy), if it was taken on the current kernel sources; else None."""
@@ -74,62 +88,138 @@ def bulk_kernel_sha256():
 
 def bulk_roofline(prof):
     """Roofline of the bulk flux/update kernel from the library's event
-    timings: FP64 operations per second against the FP64 vector peak (the
-    binding roof: about 1.3k operations per update against 85 bytes), and
-    the algorithmic bytes per second against the HBM peak beside it."""
+    timings: its algorithmic bytes per second against the HBM peak, and its
+    FP64 operations per second against the FP64 issue rate without fused
+    multiply-adds beside it (about 1.3k operations per update against 85
+    bytes: the operation count, not the bytes, sets its floor)."""
     n = max(1, prof["bulk_launches"])
     bulk_s = prof["bulk_ms"] * 1e-3
     upd = prof["bulk_updates"]
-    tflops = FLOPS_PER_BULK_UPDATE_2D * upd / bulk_s / 1e12 if bulk_s > 0 else 0.0
+    tops = FLOPS_PER_BULK_UPDATE_2D * upd / bulk_s / 1e12 if bulk_s > 0 else 0.0
     gbs = prof["bulk_bytes"] / bulk_s / 1e9 if bulk_s > 0 else 0.0
-    return dict(bound="alu", achieved=round(tflops, 3), peak=FP64_VECTOR_PEAK_TFLOPS,
-                unit="TFLOP/s", frac=round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
-                traffic=None, kernel="k_flux_bulk2",
-                flops_per_update=FLOPS_PER_BULK_UPDATE_2D,
-                updates_per_launch=upd / n,
-                hbm=dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                         frac=round(gbs / HBM_PEAK_GBS, 4)),
-                launches=prof["bulk_launches"],
-                avg_launch_us=round(prof["bulk_ms"] * 1e3 / n, 2),
-                bytes_per_launch=prof["bulk_bytes"] / n)
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_flux_bulk2",
+                bytes_per_update=round(BYTES_PER_UPDATE_2D, 3),
+                updates_per_launch=upd / n, bytes_per_launch=prof["bulk_bytes"] / n,
+                launches=prof["bulk_launches"], avg_launch_us=round(prof["bulk_ms"] * 1e3 / n, 2),
+                alu=dict(achieved=round(tops, 3), peak=FP64_NOFMA_PEAK_TOPS,
+                         unit="T FP64 op/s (no FMA)", frac=round(tops / FP64_NOFMA_PEAK_TOPS, 4),
+                         ops_per_update=FLOPS_PER_BULK_UPDATE_2D,
+                         frac_of_fma_peak=round(tops / FP64_VECTOR_PEAK_TFLOPS, 4)))
 
 
-def hbm_resident_leg(pk, wl, stream, nx=8192, ny=2048, warm=3, steps=10):
-    """The bulk kernel on the shock-bubble problem at 8192 x 2048 (working
-    set of several GB, far beyond the 256 MB last-level cache), where its
-    algorithmic bytes have to come from HBM."""
+def whole_step_hbm(rate):
+    """Whole-step rate as a fraction of the HBM roof (algorithmic bytes)."""
+    gbs = rate * BYTES_PER_UPDATE_2D / 1e9
+    return dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def timed_run(pk, w, stream, steps, warmup, start):
+    """Warm-up on a throwaway context (graph capture, first touch), then a
+    fresh context from t = 0: `start` untimed steps, then exactly `steps`
+    timed steps (events on the solver's stream around the graph replays)."""
     import torch
-    w = wl.shock_bubble(nx=nx, ny=ny)
+    if warmup:
+        s = pk.Solver(w["cfg"], stream=stream.cuda_stream)
+        s.init(w["phi"], w["chi"], w["W"])
+        s.step(warmup)
+        s.close()
     s = pk.Solver(w["cfg"], stream=stream.cuda_stream)
     s.init(w["phi"], w["chi"], w["W"])
-    del w
-    s.step(warm)
+    s.step(start) if start else s.step(0)  # step(0) captures the step graph
+    torch.cuda.synchronize()
+    d0 = s.diag()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    d1 = s.diag()
+    updates = d1["n_updates"] - d0["n_updates"]
+    return s, dict(ms=ms, wall=wall, updates=updates, rate=updates / (ms * 1e-3),
+                   t_start=d0["t"], t_end=d1["t"], step_start=d0["steps"],
+                   n_band=d1["n_band"], n_tiles=d1["n_tiles"])
+
+
+def profile_bulk(s, steps):
+    """The bulk kernel's launches bracketed by HIP events (graph replay off
+    while they are recorded) over `steps` further steps."""
     s.set_profiling(True)
     s.step(steps)
     prof = s.profile()
     s.set_profiling(False)
+    return prof
+
+
+def hbm_resident_leg(pk, wl, stream, nx=8192, ny=2048, warm=3, steps=20):
+    """The shock-bubble problem at 8192 x 2048 (the effective resolution of
+    the paper's Case V; working set of several GB, far beyond the 256 MB
+    last-level cache): whole steps timed, and the bulk kernel against the
+    HBM roof, where its algorithmic bytes have to come from HBM."""
+    import torch
+    w = wl.shock_bubble(nx=nx, ny=ny)
+    s, r = timed_run(pk, w, stream, steps, 0, warm)
+    del w
+    prof = profile_bulk(s, 10)
     torch.cuda.synchronize()
     s.close()
-    r = bulk_roofline(prof)
-    r["traffic"] = measured_traffic(f"{nx}x{ny}")
-    r.update(workload=f"shock_bubble_{nx}x{ny}", steps=steps, warmup=warm)
-    return r
+    roof = bulk_roofline(prof)
+    roof["traffic"] = measured_traffic(f"{nx}x{ny}")
+    return dict(workload=f"shock_bubble_{nx}x{ny}", value=r["rate"], unit="updates/s",
+                steps=steps, warmup=warm, ms_per_step=r["ms"] / steps,
+                hbm_whole_step=whole_step_hbm(r["rate"]), roofline=roof)
 
 
-def cpu_baseline(workload, steps):
+def triple_point_leg(pk, wl, stream, steps=300, warm=10):
+    """Case III at 896 x 384 (whole steps after a warm-up), for comparison
+    with the earlier figures of this workload."""
+    w = wl.triple_point()
+    s, r = timed_run(pk, w, stream, steps, 0, warm)
+    s.close()
+    return dict(workload="triple_point_896x384", value=r["rate"], unit="updates/s",
+                steps=steps, warmup=warm, ms_per_step=r["ms"] / steps,
+                t_start=r["t_start"], t_end=r["t_end"])
+
+
+def host_cpu():
+    """Host core count and model of the machine the oracle runs on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(workload, steps, runs=5):
+    """The oracle (plain single-threaded C, one core) on the same workload:
+    `runs` runs of the first `steps` steps from t = 0, median rate."""
     import oracle
-    o = oracle.Oracle(workload["cfg"])
-    assert o.init(workload["phi"], workload["chi"], workload["W"]) == 0
-    t0 = time.perf_counter()
-    rc = o.step(steps)
-    el = time.perf_counter() - t0
-    if rc:
-        return None
-    d = o.diag()
-    return dict(value=d["n_updates"] / el, unit="updates/s", cores=1, kind="oracle",
-                sample=f"{workload['name']} {workload['cfg']['nx']}x{workload['cfg']['ny']}, "
-                       f"first {steps} steps from t=0, single-threaded C oracle "
-                       f"({d['n_updates']} updates in {el:.2f} s)")
+    rates = []
+    for _ in range(runs):
+        o = oracle.Oracle(workload["cfg"])
+        assert o.init(workload["phi"], workload["chi"], workload["W"]) == 0
+        t0 = time.perf_counter()
+        rc = o.step(steps)
+        el = time.perf_counter() - t0
+        if rc:
+            return None
+        rates.append(o.diag()["n_updates"] / el)
+        del o
+    ncpu, model = host_cpu()
+    cfg = workload["cfg"]
+    return dict(value=float(np.median(rates)), unit="updates/s", cores=1, kind="oracle",
+                sample=f"{workload['name']} {cfg['nx']}x{cfg['ny']}, first {steps} steps "
+                       f"from t=0, single-threaded C oracle, median of {runs} runs",
+                runs=[round(r) for r in rates], host_nproc=ncpu, host_cpu=model)
 
 
 def batched(pk, wl, stream, steps, ref_inst=8, ref_steps=30):
@@ -217,14 +307,18 @@ def adjoint_leg(pk, wl, stream, steps=300, K=30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=FULL_STEPS)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--start", type=int, default=None,
+                    help="first timed step (default: the K-step window centred in the full run)")
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-hbm-leg", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the main workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -237,51 +331,31 @@ def main():
     import paper_1704_00519_amd as pk
     import workloads as wl
 
-    w = wl.triple_point()
+    w = wl.shock_bubble(nx=WORKLOAD["nx"], ny=WORKLOAD["ny"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # a real stream: time steps replay a captured graph
     torch.cuda.set_stream(stream)
-    s = pk.Solver(w["cfg"], stream=stream.cuda_stream)
-    s.init(w["phi"], w["chi"], w["W"])
-    if args.warmup:
-        s.step(args.warmup)
-    torch.cuda.synchronize()
-    d0 = s.diag()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    d1 = s.diag()
-    updates = d1["n_updates"] - d0["n_updates"]
-    value = updates / (ms * 1e-3)
-    # dominant kernel: its launches bracketed by HIP events on the same
-    # stream (graph replay is off while the events are recorded), over a
-    # further stretch of the same run
-    prof_steps = max(1, min(args.steps, 50))
-    s.set_profiling(True)
-    s.step(prof_steps)
-    prof = s.profile()
-    s.set_profiling(False)
-
+    start = args.start if args.start is not None else max(0, (FULL_STEPS - args.steps) // 2)
+    s, r = timed_run(pk, w, stream, args.steps, args.warmup, start)
+    value = r["rate"]
+    prof = profile_bulk(s, max(1, min(args.steps, 20)))
+    s.close()
     roofline = bulk_roofline(prof)
     roofline["traffic"] = measured_traffic()
-    roofline["share_of_step"] = round(prof["bulk_ms"] / prof_steps / (ms / args.steps), 4)
-    roofline["profiled_steps"] = prof_steps
+    roofline["share_of_step"] = round(prof["bulk_ms"] / max(1, min(args.steps, 20)) /
+                                      (r["ms"] / args.steps), 4)
+    nx, ny = WORKLOAD["nx"], WORKLOAD["ny"]
     out = dict(metric="material-cell RK-substep updates/sec (plain)",
                value=value, unit="updates/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms / args.steps,
+               warmup=args.warmup, ms_per_step=r["ms"] / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f64", data="synthetic",
-               config=dict(workload="triple_point_896x384", grid=[896, 384],
-                           materials=3, rk_stages=3, cfl=0.6,
-                           t_start=d0["t"], t_end=d1["t"],
-                           wall_s=round(wall, 3)),
-               roofline=roofline)
+               config=dict(workload=f"shock_bubble_{nx}x{ny}", grid=[nx, ny],
+                           materials=3, rk_stages=3, cfl=0.6, full_steps=FULL_STEPS,
+                           step_start=r["step_start"], t_start=r["t_start"],
+                           t_end=r["t_end"], band_cells_last_stage=r["n_band"],
+                           wall_s=round(r["wall"], 3)),
+               roofline=roofline, hbm_whole_step=whole_step_hbm(value))
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -290,14 +364,16 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8,
                                          "launches": 3}
-    if not args.no_hbm_leg:
-        out["roofline_hbm_resident"] = hbm_resident_leg(pk, wl, stream)
-    if not args.no_batch:
-        out["batched"] = batched(pk, wl, stream, args.batch_steps)
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg(pk, wl, stream)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    if not args.no_extra:
+        if not args.no_hbm_leg:
+            out["hbm_resident"] = hbm_resident_leg(pk, wl, stream)
+        out["triple_point"] = triple_point_leg(pk, wl, stream)
+        if not args.no_batch:
+            out["batched"] = batched(pk, wl, stream, args.batch_steps)
+        if not args.no_adjoint:
+            out["adjoint"] = adjoint_leg(pk, wl, stream)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out))
 
 
