@@ -218,6 +218,31 @@ mm_status mm_batch_get_threads(mm_batch *b, int32_t *threads, float *tune_ms);
 mm_status mm_batch_destroy(mm_batch *b);
 const char *mm_batch_last_error(const mm_batch *b);
 
+/* ---- Batched run without device allocation ------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one call
+ * initialises n_inst 1D instances from (phi, chi, W) as mm_batch_init_state
+ * does, advances them n_steps steps with the kernel of mm_batch_step
+ * (workgroup size `threads`: 64, 128, 256, 512 or 1024; 0 = 256; no
+ * tuning), and writes the final state to Q (required), alpha, phi_out and
+ * chi_out (nullable) in mm_batch_get_conserved's layout.  Every pointer is
+ * device memory of the current device; results are bitwise those of
+ * mm_batch_create / mm_batch_init_state / mm_batch_set_threads(threads) /
+ * mm_batch_step / mm_batch_get_conserved.  All work buffers live in one
+ * fixed device array of MM_NOALLOC_BYTES per GPU, held until the process
+ * ends: no hipMalloc or hipFree is called.  MM_EINVAL (nothing run) if
+ * n_inst exceeds MM_NOALLOC_MAX_INST or the instances need more than that
+ * array; MM_ENONPHYS if an instance met a non-physical state.  Every call
+ * on a GPU shares that GPU's array and clears it first: calls that overlap
+ * on one GPU (other threads or streams) race.  Synchronises hip_stream
+ * (NULL = the null stream).  mm_last_error(NULL) gives the message. */
+#define MM_NOALLOC_BYTES (64u << 20)
+#define MM_NOALLOC_MAX_INST 64
+mm_status mm_batch_run_noalloc(const mm_config *cfgs, int32_t n_inst, void *hip_stream,
+                               const double *phi, const int32_t *chi, const double *W,
+                               int32_t n_steps, int32_t threads, double *Q, double *alpha,
+                               double *phi_out, int32_t *chi_out);
+
 /* Release every device buffer of the context. */
 mm_status mm_destroy(mm_ctx *ctx);
 

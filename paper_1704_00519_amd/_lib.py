@@ -28,7 +28,7 @@ EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
            "mm_batch_create", "mm_batch_init_state", "mm_batch_step",
            "mm_batch_get_conserved", "mm_batch_get_diagnostics",
            "mm_batch_set_threads", "mm_batch_get_threads", "mm_batch_destroy",
-           "mm_batch_last_error")
+           "mm_batch_last_error", "mm_batch_run_noalloc")
 
 
 class MMConfig(C.Structure):
@@ -117,6 +117,8 @@ def load():
                      "mm_batch_set_threads", "mm_batch_get_threads",
                      "mm_batch_destroy"):
             getattr(L, name).restype = i32
+        L.mm_batch_run_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.mm_batch_run_noalloc.restype = i32
         L.mm_last_error.argtypes = [vp]
         L.mm_last_error.restype = C.c_char_p
         for name in ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
@@ -337,3 +339,36 @@ class Batch:
         arr = (MMDiag * self.n)()
         self._check(load().mm_batch_get_diagnostics(self._h, arr))
         return [_diag_dict(d, self.M) for d in arr]
+
+
+def batch_run_noalloc(cfgs, phi, chi, W, n_steps, threads, Q, alpha=None, phi_out=None,
+                      chi_out=None, stream=None):
+    """mm_batch_run_noalloc: initialise and advance 1D instances with no
+    device allocation.  ``cfgs``: list of config dicts; phi, chi, W and the
+    outputs are torch tensors on the current GPU in mm_batch_init_state /
+    mm_batch_get_conserved's packed layouts (float64, int32 for chi)."""
+    L = load()
+    n = len(cfgs)
+    arr = (MMConfig * n)(*[make_config(c) for c in cfgs])
+    ncell = sum(int(c["nx"]) for c in cfgs)
+    M = int(cfgs[0]["n_mat"])
+
+    def dev(a, dtype, numel, name):
+        if a is None:
+            return None
+        if not (_is_torch(a) and a.is_cuda):
+            raise TypeError(f"{name}: a CUDA tensor is required")
+        if str(a.dtype) != dtype or not a.is_contiguous() or a.numel() != numel:
+            raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {numel} elements")
+        return C.c_void_p(a.data_ptr())
+
+    args = (dev(phi, "torch.float64", ncell, "phi"), dev(chi, "torch.int32", ncell, "chi"),
+            dev(W, "torch.float64", M * 3 * ncell, "W"))
+    outs = (dev(Q, "torch.float64", M * 3 * ncell, "Q"),
+            dev(alpha, "torch.float64", M * ncell, "alpha"),
+            dev(phi_out, "torch.float64", ncell, "phi_out"),
+            dev(chi_out, "torch.int32", ncell, "chi_out"))
+    st = L.mm_batch_run_noalloc(arr, n, C.c_void_p(stream or 0), *args, int(n_steps),
+                                int(threads), *outs)
+    if st != MM_OK:
+        raise MMError(st, L.mm_last_error(None).decode())

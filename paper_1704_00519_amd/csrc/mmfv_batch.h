@@ -2,7 +2,9 @@
 // instances of uneven size advanced by one persistent launch.  Included once,
 // at the end of mmfv_lib.hip.
 #pragma once
+#include <algorithm>
 #include <map>
+#include <mutex>
 
 struct mm_batch {
   int n = 0, M = 0, rk = 3;
@@ -440,5 +442,149 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
     d.n_band = d.n_ghost = d.n_tiles = 0;
     cons_to_diag(&cons[(size_t)q * CONS_N], b->M, &d);
   }
+  return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched run with no device allocation (mm_batch_run_noalloc)
+// ---------------------------------------------------------------------------
+// Every buffer of the run (instance parameters and buffer tables, offsets,
+// error words and the instances' state and work buffers) lives in one
+// file-scope device array.  Host code never passes the array's name to a
+// kernel or copy: it uses the device address obtained once per device with
+// hipGetSymbolAddress.  Calls on one GPU share the array, so calls that
+// overlap on one GPU race.
+static __device__ __align__(256) char scratch[MM_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+// device address of this device's scratch array (looked up once per device)
+static hipError_t scratch_address(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+__global__ void __launch_bounds__(256) k_fill0(char* p, size_t bytes) {
+  size_t words = bytes / 8;
+  double* d = (double*)p;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+       w += (size_t)gridDim.x * blockDim.x)
+    d[w] = 0.0;
+}
+
+// the lowest failing instance (n_inst if none) and its error word
+__global__ void k_batch_first_err(const Bufs* Ba, int n, unsigned long long* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  out[0] = (unsigned long long)n;
+  out[1] = NO_ERR;
+  for (int q = 0; q < n; q++)
+    if (Ba[q].ctr[C_ERR] != NO_ERR) {
+      out[0] = (unsigned long long)q;
+      out[1] = Ba[q].ctr[C_ERR];
+      return;
+    }
+}
+
+static size_t na_align(size_t n) { return (n + 255) & ~(size_t)255; }
+
+extern "C" mm_status mm_batch_run_noalloc(const mm_config* cfgs, int32_t n_inst,
+                                          void* hip_stream, const double* phi,
+                                          const int32_t* chi, const double* W, int32_t n_steps,
+                                          int32_t threads, double* Q, double* alpha,
+                                          double* phi_out, int32_t* chi_out) {
+  if (!cfgs || !phi || !chi || !W || !Q)
+    return bfail(nullptr, MM_EINVAL, "noalloc: NULL argument");
+  if (n_inst < 1 || n_inst > MM_NOALLOC_MAX_INST)
+    return bfail(nullptr, MM_EINVAL, "noalloc: n_inst must be in [1, MM_NOALLOC_MAX_INST]");
+  if (n_steps < 0) return bfail(nullptr, MM_EINVAL, "noalloc: n_steps < 0");
+  if (threads == 0) threads = 256;
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return bfail(nullptr, MM_EINVAL, "noalloc: threads must be 0 or 64..1024, a power of two");
+  std::string why;
+  for (int q = 0; q < n_inst; q++) {
+    if (!valid_config(&cfgs[q], why)) return bfail(nullptr, MM_EINVAL, "noalloc: " + why);
+    if (cfgs[q].dim != 1) return bfail(nullptr, MM_EINVAL, "noalloc: instances must be 1D");
+    if (cfgs[q].n_mat != cfgs[0].n_mat || cfgs[q].rk_order != cfgs[0].rk_order)
+      return bfail(nullptr, MM_EINVAL, "noalloc: instances must share n_mat and rk_order");
+  }
+  // host-side tables in fixed storage (no allocation); one caller at a time
+  // per thread
+  static thread_local Params hP[MM_NOALLOC_MAX_INST];
+  static thread_local Bufs hB[MM_NOALLOC_MAX_INST];
+  static thread_local int64_t hoff[MM_NOALLOC_MAX_INST + 1];
+  size_t at_P = 0, at_B = na_align(at_P + sizeof(Params) * n_inst);
+  size_t at_off = na_align(at_B + sizeof(Bufs) * n_inst);
+  size_t at_err = na_align(at_off + sizeof(int64_t) * (n_inst + 1));
+  size_t at_pool = na_align(at_err + 2 * sizeof(unsigned long long));
+  size_t pool = 0;
+  hoff[0] = 0;
+  for (int q = 0; q < n_inst; q++) {
+    hP[q] = make_params(&cfgs[q]);
+    pool += layout_bufs(hP[q], hB[q], nullptr);
+    hoff[q + 1] = hoff[q] + cfgs[q].nx;
+  }
+  if (at_pool + pool > (size_t)MM_NOALLOC_BYTES)
+    return bfail(nullptr, MM_EINVAL,
+                 "noalloc: the instances need " + std::to_string(at_pool + pool) +
+                     " bytes of work memory, more than MM_NOALLOC_BYTES");
+  char* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess)
+    return bfail(nullptr, MM_EDEVICE, std::string("noalloc: scratch address: ") +
+                                          hipGetErrorString(e));
+  size_t at = at_pool;
+  for (int q = 0; q < n_inst; q++) at += layout_bufs(hP[q], hB[q], base + at);
+  hipStream_t s = (hipStream_t)hip_stream;
+  Params* dP = (Params*)(base + at_P);
+  Bufs* dB = (Bufs*)(base + at_B);
+  int64_t* doff = (int64_t*)(base + at_off);
+  unsigned long long* derr = (unsigned long long*)(base + at_err);
+#define NHIP(call)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return bfail(nullptr, MM_EDEVICE, std::string("noalloc: " #call ": ") +              \
+                                            hipGetErrorString(e_));                        \
+  } while (0)
+  // the work buffers start at zero, as after mm_batch_init_state's clear
+  unsigned gfill = (unsigned)std::min<size_t>(2048, (pool / 8 + 255) / 256 + 1);
+  hipLaunchKernelGGL(k_fill0, dim3(gfill), dim3(256), 0, s, base + at_pool, pool);
+  NHIP(hipMemcpyAsync(dP, hP, sizeof(Params) * n_inst, hipMemcpyHostToDevice, s));
+  NHIP(hipMemcpyAsync(dB, hB, sizeof(Bufs) * n_inst, hipMemcpyHostToDevice, s));
+  NHIP(hipMemcpyAsync(doff, hoff, sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_batch_ctr_init, dim3((n_inst + 255) / 256), dim3(256), 0, s, dB, n_inst);
+  hipLaunchKernelGGL(k_batch1d_init, dim3(n_inst), dim3(threads), 0, s, (const Params*)dP,
+                     (const Bufs*)dB, phi, chi, W, (const int64_t*)doff);
+  if (n_steps > 0) {
+    auto kern = threads <= 256 ? k_batch1d<256> : (threads <= 512 ? k_batch1d<512> : k_batch1d<1024>);
+    hipLaunchKernelGGL(kern, dim3(n_inst), dim3(threads), 0, s, (const Params*)dP,
+                       (const Bufs*)dB, n_steps, cfgs[0].rk_order);
+  }
+  hipLaunchKernelGGL(k_batch1d_pack, dim3(n_inst), dim3(threads), 0, s, (const Params*)dP,
+                     (const Bufs*)dB, Q, alpha, phi_out, chi_out, (const int64_t*)doff);
+  hipLaunchKernelGGL(k_batch_first_err, dim3(1), dim3(64), 0, s, (const Bufs*)dB, n_inst, derr);
+  NHIP(hipGetLastError());
+  unsigned long long herr[2] = {0, 0};
+  NHIP(hipMemcpyAsync(herr, derr, sizeof(herr), hipMemcpyDeviceToHost, s));
+  NHIP(hipStreamSynchronize(s));
+#undef NHIP
+  if (herr[0] != (unsigned long long)n_inst)
+    return bfail(nullptr, MM_ENONPHYS, "noalloc: instance " + std::to_string(herr[0]) +
+                                           ": non-physical cell " + std::to_string(herr[1]));
   return MM_OK;
 }
