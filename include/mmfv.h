@@ -96,6 +96,9 @@ typedef struct {
    * form): cells outside the bulk (updated by the general cut-cell code),
    * queued ghost (cell, material) pairs, active 16 x 16 tiles. */
   int64_t n_band, n_ghost, n_tiles;
+  /* Step (counted from 1 since mm_init_state) in which the non-physical
+   * state of err_cell was found, -1 if none. */
+  int64_t err_step;
 } mm_diag;
 
 typedef struct mm_ctx mm_ctx;
@@ -122,8 +125,11 @@ mm_status mm_init_state(mm_ctx *ctx, const double *phi, const int32_t *chi,
  * (a new tape starts unless the previous call recorded with the same K and
  * no step has been reversed since); record_tape = 0 ends any tape.  If t_out
  * is not NULL it receives the time reached.  Synchronises the stream once
- * and returns MM_ENONPHYS if a non-physical real state appeared (the state
- * is then undefined; err_cell in the diagnostics names the cell). */
+ * and returns MM_ENONPHYS if a non-physical real state appeared; err_cell
+ * and err_step in the diagnostics name the cell and the step.  With the
+ * guard on (mm_set_guard) and record_tape = 0, the state is then that after
+ * the last step that completed, and the context can step on (for instance
+ * with a smaller step size); otherwise the state is undefined. */
 mm_status mm_step(mm_ctx *ctx, int32_t n_steps, int32_t record_tape,
                   double *t_out);
 
@@ -137,6 +143,22 @@ mm_status mm_get_diagnostics(mm_ctx *ctx, mm_diag *out);
 
 /* Replay a fixed step size instead of the CFL one; dt <= 0 restores CFL. */
 mm_status mm_set_dt(mm_ctx *ctx, double dt);
+
+/* Step-size schedule (Sec. 2.3: Delta t from the CFL condition; the
+ * derivative of a run, and its finite-difference check, hold the step sizes
+ * of a reference run fixed): the next n steps use dt[0], ..., dt[n-1] (host
+ * array, copied), one per step, inside the captured step; afterwards the CFL
+ * step size applies again.  A fixed step size (mm_set_dt) takes precedence
+ * while set.  mm_init_state ends a schedule; n = 0 ends it now.  MM_EINVAL
+ * if an entry is not positive and finite (nothing changed). */
+mm_status mm_set_dt_schedule(mm_ctx *ctx, const double *dt, int32_t n);
+
+/* Guard of plain steps (record_tape = 0): with enable != 0, each mm_step
+ * call keeps the state it starts from (one copy of the state per call); if
+ * a step of the call meets a non-physical state, the call goes back to that
+ * copy and replays the steps that completed (bit for bit the same), and
+ * returns MM_ENONPHYS with the state after the last completed step. */
+mm_status mm_set_guard(mm_ctx *ctx, int32_t enable);
 
 /* Differentiation (Sec. 2.3, Eq. discretized_equ, Eq. local-advection; the
  * method's step, transposed).  Reverses the last recorded step that has not

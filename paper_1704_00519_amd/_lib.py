@@ -22,7 +22,8 @@ STATUS = {0: "MM_OK", 1: "MM_EINVAL", 2: "MM_ENOMEM", 3: "MM_EDEVICE",
           4: "MM_ENONPHYS", 5: "MM_ESTATE", 6: "MM_ENOTIMPL"}
 
 EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
-           "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step", "mm_adjoint_inflow",
+           "mm_get_diagnostics", "mm_set_dt", "mm_set_dt_schedule", "mm_set_guard",
+           "mm_adjoint_step", "mm_adjoint_inflow",
            "mm_tape_info", "mm_destroy",
            "mm_last_error", "mm_set_profiling", "mm_get_profile",
            "mm_batch_create", "mm_batch_init_state", "mm_batch_step",
@@ -51,7 +52,8 @@ class MMDiag(C.Structure):
                 ("err_cell", C.c_int64),
                 ("sum_Q", (C.c_double * 4) * 8), ("bnd_in", (C.c_double * 4) * 8),
                 ("exch", (C.c_double * 4) * 8),
-                ("n_band", C.c_int64), ("n_ghost", C.c_int64), ("n_tiles", C.c_int64)]
+                ("n_band", C.c_int64), ("n_ghost", C.c_int64), ("n_tiles", C.c_int64),
+                ("err_step", C.c_int64)]
 
 
 _DIAG_ARRAYS = ("sum_Q", "bnd_in", "exch")
@@ -96,6 +98,8 @@ def load():
         L.mm_get_conserved.argtypes = [vp, vp, vp, vp, vp, i32]
         L.mm_get_diagnostics.argtypes = [vp, C.POINTER(MMDiag)]
         L.mm_set_dt.argtypes = [vp, dbl]
+        L.mm_set_dt_schedule.argtypes = [vp, vp, i32]
+        L.mm_set_guard.argtypes = [vp, i32]
         L.mm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
         L.mm_adjoint_inflow.argtypes = [vp, vp]
         L.mm_tape_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
@@ -122,7 +126,8 @@ def load():
         L.mm_last_error.argtypes = [vp]
         L.mm_last_error.restype = C.c_char_p
         for name in ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
-                     "mm_get_diagnostics", "mm_set_dt", "mm_adjoint_step",
+                     "mm_get_diagnostics", "mm_set_dt", "mm_set_dt_schedule",
+                     "mm_set_guard", "mm_adjoint_step",
                      "mm_adjoint_inflow", "mm_tape_info",
                      "mm_destroy", "mm_set_profiling", "mm_get_profile"):
             getattr(L, name).restype = i32
@@ -148,6 +153,20 @@ def make_config(cfg):
 
 def _is_torch(a):
     return type(a).__module__.startswith("torch")
+
+
+def _device_arg(a, dtype, numel, name):
+    """Device pointer of a torch tensor after checking that it lives on
+    the GPU, has the expected dtype, is contiguous and has numel elements."""
+    if not (_is_torch(a) and getattr(a, "is_cuda", False)):
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if str(a.dtype) != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {a.dtype}")
+    if not a.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if a.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {a.numel()}")
+    return C.c_void_p(a.data_ptr())
 
 
 class Solver:
@@ -178,10 +197,12 @@ class Solver:
     __del__ = close
 
     def init(self, phi, chi, W):
-        if _is_torch(phi):
-            st = load().mm_init_state(self._h, C.c_void_p(phi.data_ptr()),
-                                      C.c_void_p(chi.data_ptr()),
-                                      C.c_void_p(W.data_ptr()), MM_DEVICE)
+        if _is_torch(phi) or _is_torch(chi) or _is_torch(W):
+            n = self.nx * self.ny
+            st = load().mm_init_state(
+                self._h, _device_arg(phi, "torch.float64", n, "phi"),
+                _device_arg(chi, "torch.int32", n, "chi"),
+                _device_arg(W, "torch.float64", self.M * self.nv * n, "W"), MM_DEVICE)
         else:
             phi = np.ascontiguousarray(phi, np.float64)
             chi = np.ascontiguousarray(chi, np.int32)
@@ -238,6 +259,16 @@ class Solver:
     def set_dt(self, dt):
         self._check(load().mm_set_dt(self._h, float(dt)))
 
+    def set_dt_schedule(self, dts):
+        """The next len(dts) steps use these step sizes, one per step."""
+        a = np.ascontiguousarray(dts, np.float64).ravel()
+        self._check(load().mm_set_dt_schedule(self._h, a.ctypes.data if a.size else None,
+                                              int(a.size)))
+
+    def set_guard(self, on=True):
+        """Keep the state of the last completed step when a step fails."""
+        self._check(load().mm_set_guard(self._h, 1 if on else 0))
+
     def get(self):
         Q = np.zeros((self.M, self.nv, self.ny, self.nx))
         al = np.zeros((self.M, self.ny, self.nx))
@@ -250,9 +281,12 @@ class Solver:
 
     def get_device(self, Q, alpha=None, phi=None, chi=None):
         """Write the state into torch tensors on the device (no host copy)."""
-        p = lambda a: C.c_void_p(a.data_ptr()) if a is not None else None
-        self._check(load().mm_get_conserved(self._h, p(Q), p(alpha), p(phi),
-                                            p(chi), MM_DEVICE))
+        n = self.nx * self.ny
+        args = (_device_arg(Q, "torch.float64", self.M * self.nv * n, "Q"),
+                None if alpha is None else _device_arg(alpha, "torch.float64", self.M * n, "alpha"),
+                None if phi is None else _device_arg(phi, "torch.float64", n, "phi"),
+                None if chi is None else _device_arg(chi, "torch.int32", n, "chi"))
+        self._check(load().mm_get_conserved(self._h, *args, MM_DEVICE))
 
     def set_profiling(self, on=True):
         self._check(load().mm_set_profiling(self._h, 1 if on else 0))
@@ -354,13 +388,7 @@ def batch_run_noalloc(cfgs, phi, chi, W, n_steps, threads, Q, alpha=None, phi_ou
     M = int(cfgs[0]["n_mat"])
 
     def dev(a, dtype, numel, name):
-        if a is None:
-            return None
-        if not (_is_torch(a) and a.is_cuda):
-            raise TypeError(f"{name}: a CUDA tensor is required")
-        if str(a.dtype) != dtype or not a.is_contiguous() or a.numel() != numel:
-            raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {numel} elements")
-        return C.c_void_p(a.data_ptr())
+        return None if a is None else _device_arg(a, dtype, numel, name)
 
     args = (dev(phi, "torch.float64", ncell, "phi"), dev(chi, "torch.int32", ncell, "chi"),
             dev(W, "torch.float64", M * 3 * ncell, "W"))

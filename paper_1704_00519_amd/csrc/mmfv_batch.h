@@ -87,6 +87,7 @@ __global__ void k_batch_ctr_init(const Bufs* Ba, int n) {
   if (q >= n) return;
   for (int c = 0; c < C_N; c++) Ba[q].ctr[c] = 0;
   Ba[q].ctr[C_ERR] = NO_ERR;
+  Ba[q].ctr[C_ERRSTEP] = NO_ERR;
   Ba[q].ctr[C_STAMP] = 1;  // stamp arrays start zeroed
   for (int c = 0; c < 8; c++) Ba[q].scal[c] = 0.0;
   for (int c = 0; c < CONS_N; c++) Ba[q].cons[c] = 0.0;
@@ -95,6 +96,11 @@ __global__ void k_batch_err(const Bufs* Ba, int n, unsigned long long* out) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   out[q] = Ba[q].ctr[C_ERR];
+}
+__global__ void k_batch_badin(const Bufs* Ba, int n, unsigned long long* out) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  out[q] = Ba[q].ctr[C_BADIN];
 }
 __global__ void k_batch_diag(const Bufs* Ba, int n, unsigned long long* ctr, double* scal,
                              double* cons) {
@@ -226,9 +232,22 @@ extern "C" mm_status mm_batch_init_state(mm_batch* b, const double* phi, const i
   hipLaunchKernelGGL(k_batch1d_init, dim3(b->n), dim3(batch_threads_for(b)), 0, b->stream, b->dP,
                      b->dB, dphi, dchi, dW, (const int64_t*)b->doff);
   BHIP_OK(b, hipGetLastError());
+  std::vector<unsigned long long> err(b->n);
+  if (ptr_kind == MM_DEVICE) {
+    hipLaunchKernelGGL(k_batch_badin, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->dB,
+                       b->n, b->d_err);
+    BHIP_OK(b, hipMemcpyAsync(err.data(), b->d_err, sizeof(unsigned long long) * b->n,
+                              hipMemcpyDeviceToHost, b->stream));
+    BHIP_OK(b, hipStreamSynchronize(b->stream));
+    for (int q = 0; q < b->n; q++)
+      if (err[q] != 0) {
+        b->ready = false;
+        return bfail(b, MM_EINVAL, "instance " + std::to_string(q) +
+                                       ": chi out of range or phi negative");
+      }
+  }
   hipLaunchKernelGGL(k_batch_err, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->dB, b->n,
                      b->d_err);
-  std::vector<unsigned long long> err(b->n);
   BHIP_OK(b, hipMemcpyAsync(err.data(), b->d_err, sizeof(unsigned long long) * b->n,
                             hipMemcpyDeviceToHost, b->stream));
   BHIP_OK(b, hipStreamSynchronize(b->stream));
@@ -439,6 +458,7 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
     d.n_mixsrc = (int64_t)c[C_MIXSRC];
     d.n_updates = (int64_t)c[C_UPD];
     d.err_cell = c[C_ERR] == NO_ERR ? -1 : (int64_t)c[C_ERR];
+    d.err_step = c[C_ERRSTEP] == NO_ERR ? -1 : (int64_t)c[C_ERRSTEP] + 1;
     d.n_band = d.n_ghost = d.n_tiles = 0;
     cons_to_diag(&cons[(size_t)q * CONS_N], b->M, &d);
   }

@@ -35,11 +35,13 @@ struct Bufs {
                            // byte: materials set to zero)
   double* cons;            // conservation book-keeping, CONS_N doubles
   double* cpart;           // per-workgroup partial sums of the book-keeping
-  double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t
+  double* scal;            // dt, dt/dx, dt/dy, dt/(dx dy) or dt/dx, dt_fixed, t,
+                           // replay position and length of the step-size schedule
   unsigned long long* ctr; // smax bits, error cell, counters
+  const double* dts;       // step-size schedule (replayed while position < length)
 };
 
-enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T };
+enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T, S_SPOS, S_SN };
 
 // Device-to-device copies (and fills with zeros: no source), every buffer
 // 8-byte aligned: for a launch of their own, or for extra workgroups of a
@@ -68,7 +70,13 @@ enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
        C_UPD, C_UPDB0, C_UPDB1, C_STAMP, C_NTILES, C_NBAND, C_NGHOST,
        // workgroups of the current launch that have finished (the last one
        // finishes the launch's work and sets the counter back to zero)
-       C_DTDONE, C_N };
+       C_DTDONE,
+       // time steps completed since the initial state, and the lowest value
+       // of that count at which a non-physical state was flagged
+       C_STEPNO, C_ERRSTEP,
+       // cells of an initial state given in device memory with chi outside
+       // [0, n_mat) or phi negative or not a number
+       C_BADIN, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 // book-keeping regions of MAXM x 4 doubles each: accumulated net boundary
 // inflow and its compensation, accumulated exchange and its compensation,
@@ -88,6 +96,7 @@ MMD double lsv(const double* phi, const uint8_t* chi, int r, int k) {
 MMD bool errored(const Bufs& B) { return B.ctr[C_ERR] != NO_ERR; }
 MMD void flag_error(const Params& P, const Bufs& B, int i, int j) {
   atomicMin(&B.ctr[C_ERR], (unsigned long long)j * P.nx + i);
+  atomicMin(&B.ctr[C_ERRSTEP], B.ctr[C_STEPNO]);
 }
 // Counters bumped by many lanes at once go through one atomic per wavefront:
 // the values of the lanes active at the call are summed with ballots (v < 16)
@@ -824,7 +833,16 @@ MMD double b_dt_cell(const Params& P, const Bufs& B, int i, int j, int sidx) {
 }
 template <int D>
 MMD void dt_finish(const Params& P, const Bufs& B, double smax) {
-  double dt = B.scal[S_DTFIX] > 0.0 ? B.scal[S_DTFIX] : P.cfl * P.h / smax;
+  // a fixed step size first, then the schedule's next entry, else CFL
+  double dt;
+  if (B.scal[S_DTFIX] > 0.0) {
+    dt = B.scal[S_DTFIX];
+  } else if (B.scal[S_SPOS] < B.scal[S_SN]) {
+    dt = B.dts[(long long)B.scal[S_SPOS]];
+    B.scal[S_SPOS] += 1.0;
+  } else {
+    dt = P.cfl * P.h / smax;
+  }
   B.scal[S_DT] = dt;
   B.scal[S_LX] = dt / P.dx;
   B.scal[S_LY] = dt / P.dy;
@@ -1876,8 +1894,16 @@ MMD void b_load_ls(const Params& P, const Bufs& B, int i, int j, const double* p
                    const int32_t* chi) {
   int k = cid(P, i, j);
   size_t q = (size_t)j * P.nx + i;
-  B.phi[k] = phi[q];
-  B.chi[k] = (uint8_t)chi[q];
+  double p = phi[q];
+  int32_t c = chi[q];
+  if (c < 0 || c >= P.M || !(p >= 0.0)) {
+    // counted (the call then fails); the stored values stay in range
+    atomicAdd(&B.ctr[C_BADIN], 1ull);
+    c = 0;
+    p = 0.0;
+  }
+  B.phi[k] = p;
+  B.chi[k] = (uint8_t)c;
 }
 __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* chi) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2153,7 +2179,10 @@ MMD void cons_fin_wave(const Params& P, const Bufs& B, int nblk, double w, int x
 __global__ void __launch_bounds__(64) k_cons_fin(Params P, Bufs B, int nblk, double w,
                                                  int advance) {
   int x = blockIdx.x, t = threadIdx.x;
-  if (advance && x == 0 && t == 0) B.scal[S_T] += B.scal[S_DT];
+  if (advance && x == 0 && t == 0) {
+    B.scal[S_T] += B.scal[S_DT];
+    B.ctr[C_STEPNO] += 1;
+  }
   if (x < P.M * 8) cons_fin_wave(P, B, nblk, w, x, t);
 }
 
@@ -2472,7 +2501,10 @@ __global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb,
     // the book-keeping totals of the stage: one wavefront per (material,
     // quantity), independent of the level set
     int x = ((int)blockIdx.x - ntb - nfr) * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (advance && x == 0 && lane == 0) B.scal[S_T] += B.scal[S_DT];
+    if (advance && x == 0 && lane == 0) {
+      B.scal[S_T] += B.scal[S_DT];
+      B.ctr[C_STEPNO] += 1;
+    }
     if (x < P.M * 8) cons_fin_wave(P, B, nblk, w, x, lane);
     return;
   }
@@ -2888,7 +2920,10 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       stamp++;
       sidx = didx;
     }
-    if (tid == 0) B.scal[S_T] += B.scal[S_DT];
+    if (tid == 0) {
+      B.scal[S_T] += B.scal[S_DT];
+      B.ctr[C_STEPNO] += 1;
+    }
   }
   __syncthreads();
   if (tid == 0) B.ctr[C_STAMP] = stamp;

@@ -2,6 +2,7 @@
 // buffers, and the fixed order of kernels in one time step.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -59,6 +60,19 @@ struct mm_ctx {
   unsigned long long* ctr_save = nullptr;
   double* scal_save = nullptr;
   double* cons_save = nullptr;
+  // step-size schedule (mm_set_dt_schedule)
+  double* dts = nullptr;
+  size_t dts_cap = 0;
+  // with the guard on, each plain mm_step call keeps the state it starts
+  // from; a failing call goes back to it and replays the completed steps
+  bool guard = false;
+  char* guard_snap = nullptr;
+  size_t guard_cap = 0;
+  unsigned long long* guard_ctr = nullptr;
+  double* guard_scal = nullptr;
+  double* guard_cons = nullptr;
+  int64_t err_step = -1;   // failing step (1-based) of the last failure
+  int64_t err_cell = -1;   // its lowest non-physical cell
 };
 
 static void prof_mark(mm_ctx* c) {
@@ -121,12 +135,18 @@ static void free_all(mm_ctx* c) {
   c->allocs.clear();
   for (char* p : c->ckpt) (void)hipFree(p);
   c->ckpt.clear();
-  void* extra[] = {c->tape_dt, c->seg, c->final_snap};
+  void* extra[] = {c->tape_dt, c->seg, c->final_snap, c->dts, c->guard_snap, c->guard_ctr,
+                   c->guard_scal, c->guard_cons};
   for (void* p : extra)
     if (p) (void)hipFree(p);
   c->tape_dt = nullptr;
   c->seg = nullptr;
   c->final_snap = nullptr;
+  c->dts = nullptr;
+  c->guard_snap = nullptr;
+  c->guard_ctr = nullptr;
+  c->guard_scal = nullptr;
+  c->guard_cons = nullptr;
   c->adj_ready = false;
   if (c->d_in) (void)hipFree(c->d_in);
   c->d_in = nullptr;
@@ -259,6 +279,7 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   }
   unsigned long long init_ctr[C_N] = {0};
   init_ctr[C_ERR] = NO_ERR;
+  init_ctr[C_ERRSTEP] = NO_ERR;
   init_ctr[C_STAMP] = 1;
   if (hipMemcpy(B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice) != hipSuccess) {
     free_all(c);
@@ -557,6 +578,7 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   }
   unsigned long long init_ctr[C_N] = {0};
   init_ctr[C_ERR] = NO_ERR;
+  init_ctr[C_ERRSTEP] = NO_ERR;
   init_ctr[C_STAMP] = 1;
   HIP_OK(c, hipMemcpyAsync(c->B.ctr, init_ctr, sizeof(init_ctr), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemsetAsync(c->B.scal, 0, 8 * sizeof(double), c->stream));
@@ -583,6 +605,12 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   HIP_OK(c, hipMemcpy(ctr, c->B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
   c->steps = 0;
   c->ready = true;
+  c->err_cell = c->err_step = -1;
+  if (ctr[C_BADIN] != 0) {
+    c->ready = false;
+    return fail(c, MM_EINVAL, std::to_string(ctr[C_BADIN]) +
+                                  " cells with chi out of range or phi negative");
+  }
   if (ctr[C_ERR] != NO_ERR) {
     c->ready = false;
     return fail(c, MM_ENONPHYS, "non-physical initial state at cell " + std::to_string(ctr[C_ERR]));
@@ -625,19 +653,38 @@ static mm_status launch_steps(mm_ctx* c, int32_t n_steps) {
   return MM_OK;
 }
 
+static mm_status guard_save(mm_ctx* c);
+static mm_status guard_rollback(mm_ctx* c, int64_t steps0, int64_t done);
+
 // after a batch of steps: optional time output, then the error check (the
-// one synchronisation)
-static mm_status finish_steps(mm_ctx* c, double* t_out) {
+// one synchronisation).  With guard_from >= 0 (the step count at the start
+// of a guarded call) a failure rolls back to the last completed step.
+static mm_status finish_steps(mm_ctx* c, double* t_out, int64_t guard_from = -1) {
   if (t_out) {
     HIP_OK(c, hipMemcpyAsync(t_out, c->B.scal + S_T, sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
   }
-  unsigned long long err = 0;
+  unsigned long long err = 0, errstep = 0;
   HIP_OK(c, hipMemcpyAsync(&err, c->B.ctr + C_ERR, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipMemcpyAsync(&errstep, c->B.ctr + C_ERRSTEP, sizeof(errstep),
+                           hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (err != NO_ERR) {
+    c->err_cell = (int64_t)err;
+    c->err_step = errstep == NO_ERR ? -1 : (int64_t)errstep + 1;
+    if (guard_from >= 0 && errstep != NO_ERR && (int64_t)errstep >= guard_from) {
+      mm_status st = guard_rollback(c, guard_from, (int64_t)errstep - guard_from);
+      if (st != MM_OK) return st;
+      if (t_out)
+        HIP_OK(c, hipMemcpy(t_out, c->B.scal + S_T, sizeof(double), hipMemcpyDeviceToHost));
+      return fail(c, MM_ENONPHYS, "non-physical state at cell " + std::to_string(err) +
+                                      " in step " + std::to_string(c->err_step) +
+                                      "; the state after step " + std::to_string(c->steps) +
+                                      " is kept");
+    }
     c->ready = false;
-    return fail(c, MM_ENONPHYS, "non-physical state at cell " + std::to_string(err));
+    return fail(c, MM_ENONPHYS, "non-physical state at cell " + std::to_string(err) +
+                                    " in step " + std::to_string(c->err_step));
   }
   return MM_OK;
 }
@@ -655,9 +702,14 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
   c->tape_K = 0;  // plain steps end any tape
   c->tape_n = c->tape_rev = 0;
   c->seg_n0 = -1;
+  int64_t steps0 = c->steps;
+  if (c->guard && n_steps > 0) {
+    mm_status st = guard_save(c);
+    if (st != MM_OK) return st;
+  }
   mm_status st = launch_steps(c, n_steps);
   if (st != MM_OK) return st;
-  return finish_steps(c, t_out);
+  return finish_steps(c, t_out, c->guard ? steps0 : -1);
 }
 
 extern "C" mm_status mm_get_conserved(mm_ctx* c, double* Q, double* alpha, double* phi,
@@ -742,7 +794,8 @@ extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   out->n_stranded = (int64_t)ctr[C_STRANDED];
   out->n_mixsrc = (int64_t)ctr[C_MIXSRC];
   out->n_updates = (int64_t)ctr[C_UPD];
-  out->err_cell = ctr[C_ERR] == NO_ERR ? -1 : (int64_t)ctr[C_ERR];
+  out->err_cell = ctr[C_ERR] == NO_ERR ? c->err_cell : (int64_t)ctr[C_ERR];
+  out->err_step = ctr[C_ERRSTEP] == NO_ERR ? c->err_step : (int64_t)ctr[C_ERRSTEP] + 1;
   out->n_band = c->D == 2 ? (int64_t)ctr[C_NBAND] : 0;
   out->n_ghost = c->D == 2 ? (int64_t)ctr[C_NGHOST] : 0;
   out->n_tiles = c->D == 2 ? (int64_t)ctr[C_NTILES] : 0;
@@ -757,6 +810,43 @@ extern "C" mm_status mm_set_dt(mm_ctx* c, double dt) {
   HIP_OK(c, hipMemcpyAsync(c->B.scal + S_DTFIX, &v, sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_set_dt_schedule(mm_ctx* c, const double* dt, int32_t n) {
+  if (!c) return MM_EINVAL;
+  c->adj_clean = false;
+  if (n < 0 || (n > 0 && !dt)) return fail(c, MM_EINVAL, "bad schedule");
+  for (int32_t q = 0; q < n; q++)
+    if (!(dt[q] > 0.0) || !std::isfinite(dt[q]))
+      return fail(c, MM_EINVAL, "schedule entries must be positive and finite");
+  if ((size_t)n > c->dts_cap) {
+    // the captured step holds the buffer table by value: capture again
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    double* nd = nullptr;
+    HIP_OK(c, hipMalloc((void**)&nd, (size_t)n * sizeof(double)));
+    if (c->dts) (void)hipFree(c->dts);
+    c->dts = nd;
+    c->dts_cap = (size_t)n;
+    c->B.dts = nd;
+    if (c->step_x) (void)hipGraphExecDestroy(c->step_x);
+    if (c->step_g) (void)hipGraphDestroy(c->step_g);
+    c->step_x = nullptr;
+    c->step_g = nullptr;
+  }
+  if (n > 0)
+    HIP_OK(c, hipMemcpyAsync(c->dts, dt, (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+  double pos[2] = {0.0, (double)n};
+  HIP_OK(c, hipMemcpyAsync(c->B.scal + S_SPOS, pos, sizeof(pos), hipMemcpyHostToDevice,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+extern "C" mm_status mm_set_guard(mm_ctx* c, int32_t enable) {
+  if (!c) return MM_EINVAL;
+  c->guard = enable != 0;
   return MM_OK;
 }
 
@@ -838,4 +928,51 @@ static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_ou
   }
   c->seg_n0 = -1;
   return finish_steps(c, t_out);
+}
+
+// Guard of plain steps: the state a call starts from (snapshot with counters,
+// scalars and sums); on a failure it is restored and the completed steps are
+// replayed (the steps are deterministic, so the replay reproduces them bit for
+// bit), leaving the state after the last completed step.
+static mm_status guard_save(mm_ctx* c) {
+  SnapLayout L = snap_layout(c->P);
+  HIP_OK(c, grow(c, &c->guard_snap, &c->guard_cap, L.bytes));
+  if (!c->guard_ctr) {
+    HIP_OK(c, hipMalloc((void**)&c->guard_ctr, C_N * sizeof(unsigned long long)));
+    HIP_OK(c, hipMalloc((void**)&c->guard_scal, 8 * sizeof(double)));
+    HIP_OK(c, hipMalloc((void**)&c->guard_cons, CONS_N * sizeof(double)));
+  }
+  Copies cp;
+  snap_save(c, c->guard_snap, 0, cp);
+  cp.add(c->guard_ctr, c->B.ctr, C_N * sizeof(unsigned long long));
+  cp.add(c->guard_scal, c->B.scal, 8 * sizeof(double));
+  cp.add(c->guard_cons, c->B.cons, CONS_N * sizeof(double));
+  cp.run(c);
+  HIP_OK(c, hipGetLastError());
+  return MM_OK;
+}
+
+static mm_status guard_rollback(mm_ctx* c, int64_t steps0, int64_t done) {
+  // counters as at the start of the call, but the mixing stamp (it only
+  // grows) and the tile count (the tile list is rebuilt)
+  static_assert(C_STAMP + 1 == C_NTILES, "counters restored in two ranges");
+  Copies rs;
+  rs.add(c->B.scal, c->guard_scal, 8 * sizeof(double));
+  rs.add(c->B.cons, c->guard_cons, CONS_N * sizeof(double));
+  rs.add(c->B.ctr, c->guard_ctr, C_STAMP * sizeof(unsigned long long));
+  rs.add(c->B.ctr + C_NTILES + 1, c->guard_ctr + C_NTILES + 1,
+         (C_N - C_NTILES - 1) * sizeof(unsigned long long));
+  if (c->D == 2) snap_load<2>(c, c->guard_snap, 0, &rs, true);
+  else snap_load<1>(c, c->guard_snap, 0, &rs, true);
+  c->steps = steps0;
+  mm_status st = launch_steps(c, (int32_t)done);
+  if (st != MM_OK) return st;
+  unsigned long long err = 0;
+  HIP_OK(c, hipMemcpyAsync(&err, c->B.ctr + C_ERR, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (err != NO_ERR) {
+    c->ready = false;
+    return fail(c, MM_ENONPHYS, "the replay of the completed steps failed");
+  }
+  return MM_OK;
 }

@@ -60,3 +60,14 @@ def test_gamma_must_exceed_one():
     cfg["gamma"] = [1.0, 1.4, 1.4]
     with pytest.raises(pk.MMError):
         pk.Solver(cfg)
+
+
+def test_device_arguments_checked_before_the_call():
+    """The binding refuses device-pointer arguments that are not contiguous
+    CUDA tensors of the expected dtype and size (before any library call)."""
+    import torch
+    from paper_1704_00519_amd import _lib
+    with pytest.raises(TypeError):
+        _lib._device_arg(torch.zeros(4, dtype=torch.float64), "torch.float64", 4, "x")
+    with pytest.raises(TypeError):
+        _lib._device_arg(__import__("numpy").zeros(4), "torch.float64", 4, "x")
