@@ -11,7 +11,9 @@ Every time step and every reverse (adjoint) step runs in the library
 (``mm_step`` with a tape, ``mm_adjoint_step``).  Only the map from the three
 parameters to the initial primitive fields and the inflow state (the normal
 shock relations) and from those to Q^0 = alpha^0 U(W) is differentiated here,
-with torch on the host.  Step sizes are those of the forward run, held fixed.
+with torch on the host.  The step sizes are a fixed schedule (those of a
+reference run), replayed by the library; the gradient is that of J at fixed
+step sizes.
 """
 from __future__ import annotations
 
@@ -103,16 +105,14 @@ class NestedBubble:
 
     def run(self, params, steps, record=0, dts=None, stream=None):
         """Forward run; returns (J, solver, alpha^0).  With dts, step n uses
-        the fixed size dts[n] (replay of a recorded schedule)."""
+        the fixed size dts[n] (the library replays the schedule)."""
         s = self.solver(params, stream)
         alpha0 = s.get()["alpha"]
-        if dts is None:
-            s.step(steps, record=record)
-        else:
-            for n in range(steps):
-                s.set_dt(float(dts[n]))
-                s.step(1, record=record)
-            s.set_dt(0.0)
+        if dts is not None:
+            if len(dts) < steps:
+                raise ValueError("the schedule is shorter than the run")
+            s.set_dt_schedule(np.asarray(dts[:steps], np.float64))
+        s.step(steps, record=record)
         J, _ = centroid(s.get()["alpha"], self.x)
         return J, s, alpha0
 
@@ -130,13 +130,26 @@ class NestedBubble:
         return g.numpy()
 
 
+def nominal_schedule(problem, params, steps, stream=None):
+    """Step sizes of the CFL run at ``params`` (the schedule a gradient
+    study holds fixed)."""
+    _, s, _ = problem.run(params, steps, record=1, stream=stream)
+    dts = s.tape()[2]
+    s.close()
+    return dts
+
+
 class CentroidGradient(torch.autograd.Function):
-    """J(params) of a NestedBubble over a fixed number of steps, with the
-    gradient from the library's reverse steps (a checkpoint every K steps)."""
+    """J(params) of a NestedBubble after ``steps`` steps of the fixed step
+    sizes ``dts`` (a schedule, e.g. ``nominal_schedule`` at a reference
+    point), with the gradient from the library's reverse steps (a checkpoint
+    every K steps).  The step sizes are inputs held fixed, not functions of
+    params, so forward and backward are derivatives of the same function:
+    J(params) = centroid after the scheduled steps."""
 
     @staticmethod
-    def forward(ctx, params, problem, steps, K):
-        J, s, alpha0 = problem.run(params.detach().numpy(), steps, record=K)
+    def forward(ctx, params, problem, steps, K, dts):
+        J, s, alpha0 = problem.run(params.detach().numpy(), steps, record=K, dts=dts)
         ctx.problem, ctx.steps, ctx.solver, ctx.alpha0 = problem, steps, s, alpha0
         ctx.save_for_backward(params)
         return torch.tensor(J, dtype=torch.float64)
@@ -146,7 +159,7 @@ class CentroidGradient(torch.autograd.Function):
         (params,) = ctx.saved_tensors
         g = reverse_gradient(ctx.problem, ctx.solver, ctx.alpha0, ctx.steps,
                              params.detach().numpy())
-        return gJ * torch.tensor(g), None, None, None
+        return gJ * torch.tensor(g), None, None, None, None
 
 
 def reverse_gradient(problem, solver, alpha0, steps, params):

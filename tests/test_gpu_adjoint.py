@@ -152,28 +152,81 @@ def tangent_gradient(prob, params, steps):
     return g
 
 
+def branch_signature(s):
+    """Counters and indicator field of a run: a change between the runs of
+    a central difference means a branch of the step switched."""
+    d = s.diag()
+    return (d["n_mixsrc"], d["n_stranded"], d["n_posfix"], d["n_ifskip"], d["n_updates"],
+            s.get()["chi"].tobytes())
+
+
+def central_differences(prob, params, steps, K, dts, g):
+    """Central differences of CentroidGradient.apply itself (same fixed
+    schedule), h = 1e-6 |p_q|; a parameter whose +-h runs take another
+    branch pattern than the nominal run is reported and not compared."""
+    from paper_1704_00519_amd import adjoint as ad
+    base = branch_signature(prob.run(params, steps, dts=dts)[1])
+    fds = []
+    for q in range(3):
+        h = 1e-6 * abs(params[q])
+        Js, same = [], True
+        for sgn in (1.0, -1.0):
+            pq = torch.tensor(params + sgn * h * np.eye(3)[q])
+            Js.append(float(ad.CentroidGradient.apply(pq, prob, steps, K, dts)))
+            same &= branch_signature(prob.run(params + sgn * h * np.eye(3)[q], steps,
+                                              dts=dts)[1]) == base
+        fd = (Js[0] - Js[1]) / (2 * h)
+        print("param", q, "fd", fd, "adjoint", g[q], "same branches", same)
+        fds.append((fd, same))
+    return fds
+
+
 def test_centroid_gradient_against_tangent_and_differences(pk):
     from paper_1704_00519_amd import adjoint as ad
     prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32))
     params = np.array([0.138, 3.15, 1.22])
     steps, K = 70, 16  # past the first contact of the shock with the shell
+    dts = ad.nominal_schedule(prob, params, steps)
     p = torch.tensor(params, requires_grad=True)
-    J = ad.CentroidGradient.apply(p, prob, steps, K)
+    J = ad.CentroidGradient.apply(p, prob, steps, K, dts)
     J.backward()
     g = p.grad.numpy()
     gt = tangent_gradient(prob, params, steps)
     print("adjoint", g, "tangent", gt)
     assert np.all(np.abs(g - gt) <= 1e-8 * np.abs(gt).max())
-    # central differences of the library, step sizes of the nominal run
+    for q, (fd, same) in enumerate(central_differences(prob, params, steps, K, dts, g)):
+        if same:
+            assert abs(fd - g[q]) <= 1e-4 * max(abs(g[q]), 1e-3 * np.abs(g).max())
+
+
+def test_gradient_study_size_against_stored_tangent(pk):
+    """The gradient study at its own size (512 x 128, 300 steps, checkpoint
+    every 30): step sizes, J and update count against the oracle's nominal
+    run, the gradient against the oracle's tangent build (stored by
+    tests/golden/make_gradient_512.py, 1e-8), and against central
+    differences of the function itself (1e-4)."""
+    import os
+    from paper_1704_00519_amd import adjoint as ad
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden",
+                                "gradient_nested_bubble_512.npz"))
+    params = gold["params"]
+    steps, K = int(gold["steps"]), 30
+    prob = ad.NestedBubble(wl.shock_bubble(nx=512, ny=128))
     _, s, _ = prob.run(params, steps, record=1)
-    dts = s.tape()[2]
-    for q in range(3):
-        h = 1e-6 * abs(params[q])
-        Jp = prob.run(params + h * np.eye(3)[q], steps, dts=dts)[0]
-        Jm = prob.run(params - h * np.eye(3)[q], steps, dts=dts)[0]
-        fd = (Jp - Jm) / (2 * h)
-        print("param", q, "fd", fd, "adjoint", g[q])
-        assert abs(fd - g[q]) <= 1e-4 * max(abs(g[q]), 1e-3 * np.abs(g).max())
+    assert np.array_equal(s.tape()[2], gold["dts"])
+    assert s.diag()["n_updates"] == int(gold["n_updates"])
+    s.close()
+    dts = gold["dts"]
+    p = torch.tensor(params, requires_grad=True)
+    J = ad.CentroidGradient.apply(p, prob, steps, K, dts)
+    J.backward()
+    g = p.grad.numpy()
+    print("J", float(J), gold["J"], "adjoint", g, "tangent", gold["grad"])
+    assert abs(float(J) - float(gold["J"])) <= 1e-14 * abs(float(gold["J"]))
+    assert np.all(np.abs(g - gold["grad"]) <= 1e-8 * np.abs(gold["grad"]).max())
+    for q, (fd, same) in enumerate(central_differences(prob, params, steps, K, dts, g)):
+        if same:
+            assert abs(fd - g[q]) <= 1e-4 * max(abs(g[q]), 1e-3 * np.abs(g).max())
 
 
 @pytest.mark.skip(reason="capturing the reverse calls as graphs (executable graph updated "

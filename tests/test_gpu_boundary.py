@@ -1,0 +1,209 @@
+"""GPU checks of the boundary's run-control calls and of the unit of work:
+
+* mm_set_dt_schedule replays given step sizes inside the captured step
+  (equal, bit for bit, to the oracle stepped with the same sizes), then
+  falls back to the CFL step size;
+* mm_set_guard: a run that meets a non-physical state returns MM_ENONPHYS
+  with the failing step in the diagnostics and the state after the last
+  completed step (bit for bit that of a run stopped there), and can go on;
+* an initial state in device memory (torch tensors) gives the same state as
+  host arrays, and invalid device inputs are rejected with MM_EINVAL;
+* the device-counted update count (the unit of the throughput figures)
+  equals the oracle's count on the 1D tube and the triple point;
+* the ragged batch of 256 tubes after 500 steps against the oracle's stored
+  results, instance by instance.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1704_00519_amd as pk
+    pk.load()
+    return pk
+
+
+def same_state(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("Q", "alpha", "phi", "chi"))
+
+
+@pytest.mark.parametrize("captured", [False, True])
+def test_dt_schedule_matches_oracle_fixed_steps(pk, captured):
+    w = wl.shock_bubble(nx=128, ny=32)
+    print("schedule case, captured =", captured, flush=True)
+    rng = np.random.default_rng(5)
+    dts = (0.6 + 0.3 * rng.random(12)) * 0.6 / 32 / 2.0
+    stream = torch.cuda.Stream() if captured else None
+    s = pk.Solver(w["cfg"], stream=stream.cuda_stream if stream else None)
+    s.init(w["phi"], w["chi"], w["W"])
+    s.step(3)  # CFL steps, then the schedule (captured step reused)
+    s.set_dt_schedule(dts)
+    s.step(12)
+    d = s.diag()
+    o = oracle.run(w, steps=3)
+    for dt in dts:
+        o.set_dt(float(dt))
+        assert o.step(1) == 0
+    assert same_state(s.get(), o.get())
+    assert d["dt"] == dts[-1]
+    # after the schedule: CFL again
+    s.step(2)
+    o.set_dt(0.0)
+    assert o.step(2) == 0
+    assert same_state(s.get(), o.get())
+    assert s.diag()["dt"] == o.diag()["dt"]
+
+
+def test_dt_schedule_rejects_bad_entries(pk):
+    w = wl.shock_tube_1d(n=80)
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    for bad in ([1e-4, -1e-4], [np.nan], [np.inf]):
+        with pytest.raises(pk.MMError) as e:
+            s.set_dt_schedule(np.array(bad))
+        assert e.value.status == 1
+
+
+def test_guard_keeps_last_completed_step(pk):
+    """The 512 x 128 nested bubble meets a non-physical state a few hundred
+    steps in (the same cell and step as the oracle; see the long-run
+    tests).  With the guard on, the failing call returns the state after the
+    last completed step."""
+    w = wl.shock_bubble(nx=512, ny=128)
+    ref = pk.Solver(w["cfg"])
+    ref.init(w["phi"], w["chi"], w["W"])
+    # one step per call, so that no step runs after the failing one
+    with pytest.raises(pk.MMError) as e:
+        for _ in range(700):
+            ref.step(1)
+    assert e.value.status == 4
+    fail_step = ref.diag()["err_step"]
+    fail_cell = ref.diag()["err_cell"]
+    print("unguarded run fails in step", fail_step, "cell", fail_cell, flush=True)
+    assert 100 < fail_step <= 700
+    ref.close()
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    s.set_guard(True)
+    s.step(fail_step - 40)
+    with pytest.raises(pk.MMError) as e:
+        s.step(40)  # ends with the failing step
+    assert e.value.status == 4
+    d = s.diag()
+    assert d["err_step"] == fail_step and d["err_cell"] == fail_cell
+    assert d["steps"] == fail_step - 1
+    good = pk.Solver(w["cfg"])
+    good.init(w["phi"], w["chi"], w["W"])
+    good.step(fail_step - 1)
+    assert same_state(s.get(), good.get())
+    assert s.diag()["t"] == good.diag()["t"]
+    # the context steps on from the kept state (here with a smaller step);
+    # should that step fail as well, the guard keeps the state again
+    s.set_dt(0.25 * d["dt"])
+    try:
+        s.step(1)
+        assert s.diag()["steps"] == fail_step
+    except pk.MMError as e2:
+        assert e2.status == 4
+        assert s.diag()["steps"] == fail_step - 1
+        assert same_state(s.get(), good.get())
+
+
+def test_device_initial_state(pk):
+    w = wl.triple_point(nx=112, ny=48)
+    dev = torch.device("cuda:0")
+    a = pk.Solver(w["cfg"])
+    a.init(w["phi"], w["chi"], w["W"])
+    b = pk.Solver(w["cfg"])
+    phi = torch.tensor(w["phi"], dtype=torch.float64, device=dev)
+    chi = torch.tensor(w["chi"], dtype=torch.int32, device=dev)
+    W = torch.tensor(w["W"], dtype=torch.float64, device=dev)
+    b.init(phi, chi, W)
+    assert same_state(a.get(), b.get())
+    a.step(5)
+    b.step(5)
+    assert same_state(a.get(), b.get())
+    # invalid device inputs: rejected by the binding before the call ...
+    with pytest.raises(TypeError):
+        b.init(phi, chi.to(torch.int64), W)
+    with pytest.raises(TypeError):
+        b.init(phi.cpu(), chi, W)
+    with pytest.raises(ValueError):
+        b.init(phi[:, :10], chi, W)
+    # ... or by the library (indicator out of range, negative distance)
+    bad = chi.clone()
+    bad[3, 7] = 9
+    with pytest.raises(pk.MMError) as e:
+        b.init(phi, bad, W)
+    assert e.value.status == 1
+    neg = phi.clone()
+    neg[0, 0] = -1.0
+    with pytest.raises(pk.MMError) as e:
+        b.init(neg, chi, W)
+    assert e.value.status == 1
+    # a valid state again afterwards
+    b.init(phi, chi, W)
+    b.step(5)
+    assert same_state(a.get(), b.get())
+
+
+@pytest.mark.parametrize("name,steps", [("shock_tube_1d", 200), ("triple_point", 20)])
+def test_update_count_equals_oracle(pk, name, steps):
+    """The device-counted updates (active material-cell RK sub-steps, the
+    unit of every throughput figure) equal the oracle's count."""
+    w = wl.workload(name)
+    print("update count", name, steps, flush=True)
+    s = pk.Solver(w["cfg"])
+    s.init(w["phi"], w["chi"], w["W"])
+    s.step(steps)
+    o = oracle.run(w, steps=steps)
+    assert s.diag()["n_updates"] == o.diag()["n_updates"]
+    assert same_state(s.get(), o.get())
+
+
+def _state_hash(Q, alpha, phi, chi):
+    h = hashlib.sha256()
+    for a, dt in ((Q, "<f8"), (alpha, "<f8"), (phi, "<f8"), (chi, "<i4")):
+        h.update(np.ascontiguousarray(a, dtype=dt).tobytes())
+    return h.hexdigest()
+
+
+def test_batched_full_size_against_stored_oracle(pk):
+    """All 256 ragged tubes, 500 steps, one persistent launch per call: each
+    instance's final state hashes to the oracle's (bit for bit), with the
+    update count and time; the stored sampled cells and sums bound the
+    difference where a hash differs (1e-9 relative)."""
+    gold = np.load(os.path.join(HERE, "golden", "batched_tubes_500.npz"))
+    insts = wl.batched_tubes(steps=int(gold["steps"]))
+    b = pk.Batch(insts)
+    b.init(insts)
+    b.step(int(gold["steps"]))
+    out = b.get()
+    diag = b.diag()
+    mismatched = []
+    for q, r in enumerate(out):
+        h = _state_hash(r["Q"], r["alpha"], r["phi"], r["chi"])
+        if h != str(gold["hashes"][q]):
+            mismatched.append(q)
+        assert diag[q]["n_updates"] == int(gold["n_updates"][q]), q
+        assert diag[q]["t"] == float(gold["t"][q]), q
+        lo, hi = int(gold["cell_off"][q]), int(gold["cell_off"][q + 1])
+        cells = gold["cells"][lo:hi]
+        Q = r["Q"].reshape(3, 3, -1)[:, :, cells]
+        ref = gold["Q"][:, :, lo:hi]
+        assert np.abs(Q - ref).sum() <= 1e-9 * np.abs(ref).sum(), q
+        sums = r["Q"].reshape(3, 3, -1).sum(axis=-1)
+        assert np.allclose(sums, gold["sums"][q], rtol=1e-12, atol=1e-12), q
+    print("instances whose state hash differs:", mismatched)
+    assert not mismatched

@@ -147,6 +147,46 @@ def shock_bubble(nx=2048, ny=512, mach=1.22, rho_outer=0.138, rho_inner=3.15,
                 name="shock_bubble")
 
 
+def rankine_hugoniot_dmach(mach, gamma, rho0, p0):
+    """Derivatives with respect to the Mach number of the post-shock state
+    of ``rankine_hugoniot`` (gas at rest ahead of the shock): returns
+    (drho1, du1, dp1), from differentiating the closed forms."""
+    g = gamma
+    c0 = math.sqrt(g * p0 / rho0)
+    m2 = mach * mach
+    den = (g - 1.0) * m2 + 2.0
+    rho1 = rho0 * (g + 1.0) * m2 / den
+    drho1 = rho0 * (g + 1.0) * 4.0 * mach / (den * den)
+    dp1 = p0 * 4.0 * g * mach / (g + 1.0)
+    s = mach * c0
+    # u1 = s (1 - rho0 / rho1)
+    du1 = c0 * (1.0 - rho0 / rho1) + s * rho0 * drho1 / (rho1 * rho1)
+    return drho1, du1, dp1
+
+
+def shock_bubble_tangent(w, q, mach=1.22, x_shock=0.5):
+    """Derivative of the primitive fields and inflow state of a
+    ``shock_bubble`` workload ``w`` with respect to parameter q of
+    (rho_outer, rho_inner, mach): returns (dW, dinflow)."""
+    cfg = w["cfg"]
+    nx, ny = cfg["nx"], cfg["ny"]
+    dW = np.zeros_like(w["W"])
+    dinf = np.zeros(4)
+    if q == 0:
+        dW[1, 0] = 1.0
+    elif q == 1:
+        dW[2, 0] = 1.0
+    else:
+        x, _ = _centres(nx, cfg["x0"], cfg["x1"])
+        post = np.broadcast_to(x < x_shock, (ny, nx))
+        dr, du, dp = rankine_hugoniot_dmach(mach, cfg["gamma"][0], 1.0, 1.0)
+        dW[0, 0][post] = dr
+        dW[0, 1][post] = du
+        dW[0, 3][post] = dp
+        dinf[:] = [dr, du, 0.0, dp]
+    return dW, dinf
+
+
 BATCH_SEED = 1704005190
 
 
