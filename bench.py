@@ -319,6 +319,8 @@ def main():
     ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the main workload (for profiler runs)")
+    ap.add_argument("--grid", default=f"{WORKLOAD['nx']}x{WORKLOAD['ny']}",
+                    help="grid of the shock-bubble workload (profiler runs at other sizes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -331,7 +333,8 @@ def main():
     import paper_1704_00519_amd as pk
     import workloads as wl
 
-    w = wl.shock_bubble(nx=WORKLOAD["nx"], ny=WORKLOAD["ny"])
+    nx, ny = (int(v) for v in args.grid.split("x"))
+    w = wl.shock_bubble(nx=nx, ny=ny)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # a real stream: time steps replay a captured graph
     torch.cuda.set_stream(stream)
@@ -341,10 +344,9 @@ def main():
     prof = profile_bulk(s, max(1, min(args.steps, 20)))
     s.close()
     roofline = bulk_roofline(prof)
-    roofline["traffic"] = measured_traffic()
+    roofline["traffic"] = measured_traffic(f"{nx}x{ny}")
     roofline["share_of_step"] = round(prof["bulk_ms"] / max(1, min(args.steps, 20)) /
                                       (r["ms"] / args.steps), 4)
-    nx, ny = WORKLOAD["nx"], WORKLOAD["ny"]
     out = dict(metric="material-cell RK-substep updates/sec (plain)",
                value=value, unit="updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=r["ms"] / args.steps,
