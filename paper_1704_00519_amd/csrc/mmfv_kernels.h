@@ -39,6 +39,7 @@ struct Bufs {
                            // replay position and length of the step-size schedule
   unsigned long long* ctr; // smax bits, error cell, counters
   const double* dts;       // step-size schedule (replayed while position < length)
+  double* dtpart;          // per-workgroup maxima of the wave speeds (step size)
 };
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T, S_SPOS, S_SN };
@@ -448,7 +449,7 @@ __global__ void k_classify(Params P, Bufs B) {
   b_classify<D>(P, B, i, j);
 }
 
-constexpr int RD = 15;  // distance cap
+constexpr int RD = 13;  // distance cap (consumers test <= 8 and <= 12)
 template <int D>
 MMD void b_dist_row(const Params& P, const Bufs& B, int i, int j) {
   int k = cid(P, i, j);
@@ -480,7 +481,7 @@ __global__ void k_dist_row(Params P, Bufs B) {
 // from the material indicators (one more cell around) and the level set; the
 // capped Chebyshev distances of the row and column scans come from bit
 // masks of the frame's rows.  Same results, one pass over global memory.
-constexpr int CX = 32, CY = 16, CF = RD - 1;
+constexpr int CX = 40, CY = 24, CF = RD - 1;
 struct ClassDistSmem {
   uint8_t chi[CY + 2 * CF + 2][CX + 2 * CF + 2];
   uint8_t fl[CY + 2 * CF][CX + 2 * CF];  // bit 0: cut, bit 1: level-set band
@@ -1091,7 +1092,7 @@ MMD void b_bulkflag(const Params& P, const Bufs& B, int i, int j, int sidx, int 
 // thread reaches the barriers.
 template <int D>
 MMD void bulkflag_block(const Params& P, const Bufs& B, int sidx, int nidx, int with_dt, int bx,
-                        int by, int bw, int nblk) {
+                        int by, int bw, int gx) {
   __shared__ int s_cnt, s_base;
   __shared__ double red[256];
   int tid = threadIdx.x;
@@ -1113,25 +1114,33 @@ MMD void bulkflag_block(const Params& P, const Bufs& B, int sidx, int nidx, int 
   __syncthreads();
   if (band) B.blist[s_base + my] = k;
   if (with_dt) {
+    // the workgroup's maximum wave speed; a workgroup of the next launch
+    // combines them into the step size (a maximum: order-independent)
     red[tid] = inb ? b_dt_cell<D>(P, B, i, j, sidx) : 0.0;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
       if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
       __syncthreads();
     }
-    if (tid == 0) {
-      atomicMax(&B.ctr[C_SMAX], (unsigned long long)__double_as_longlong(red[0]));
-      // count this workgroup as finished; the last one sets the step size
-      __threadfence();
-      unsigned long long done = atomicAdd(&B.ctr[C_DTDONE], 1ull);
-      if (done + 1 == (unsigned long long)nblk) {
-        __threadfence();
-        double smax = __longlong_as_double((long long)atomicExch(&B.ctr[C_SMAX], 0ull));
-        B.ctr[C_DTDONE] = 0;
-        dt_finish<D>(P, B, smax);
-      }
-    }
+    if (tid == 0) B.dtpart[by * gx + bx] = red[0];
   }
+}
+
+// step size from the workgroup maxima of bulkflag_block (one workgroup of
+// 256 threads)
+template <int D>
+MMD void dt_reduce_block(const Params& P, const Bufs& B, int nblk) {
+  __shared__ double red[256];
+  int tid = threadIdx.x;
+  double m = 0.0;
+  for (int q = tid; q < nblk; q += 256) m = fmax(m, B.dtpart[q]);
+  red[tid] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  if (tid == 0) dt_finish<D>(P, B, red[0]);
 }
 
 // flux of material r across the face between cell (i, j) and its +1
@@ -2252,37 +2261,40 @@ MMD void tile_flag(const Params& P, const Bufs& B, int didx, int nidx, int tile,
 __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int nidx) {
   tile_flag(P, B, didx, nidx, (int)blockIdx.x, (int)threadIdx.x, (int)blockDim.x);
 }
-// Tile list (workgroups below nt, one per tile) beside the geometry and
-// volume-fraction correction of every cut cell (the other nt, one per tile,
-// without the list: every cut cell lies in a listed tile).  The geometry reads
-// the level set and the densities, the list the distances and occupancy,
-// and neither writes what the other reads.
-// With save_Q (the adjoint's recompute), workgroups from 2 nt on copy the
-// updated state and its occupancy, before the mixing changes them, to
-// save_Q / save_occ.
+// Tile list (workgroups below nb, each flagging every nb-th of the nt tiles)
+// beside the geometry and volume-fraction correction of every cut cell (the
+// next nb workgroups, likewise over all tiles, without the list: every cut
+// cell lies in a listed tile).  The geometry reads the level set and the
+// densities, the list the distances and occupancy, and neither writes what
+// the other reads.  With save_Q (the adjoint's recompute), workgroups from
+// 2 nb on copy the updated state and its occupancy, before the mixing
+// changes them, to save_Q / save_occ.
 template <int D>
 __global__ void __launch_bounds__(256) k_tiles_geom(Params P, Bufs B, int didx, int nidx,
-                                                    int nt, double* save_Q, uint8_t* save_occ) {
+                                                    int nt, int nb, double* save_Q,
+                                                    uint8_t* save_occ) {
   int b = blockIdx.x;
-  if (b < nt) {
-    tile_flag(P, B, didx, nidx, b, (int)threadIdx.x, (int)blockDim.x);
+  if (b < nb) {
+    for (int t = b; t < nt; t += nb) tile_flag(P, B, didx, nidx, t, (int)threadIdx.x, (int)blockDim.x);
     return;
   }
-  if (b >= 2 * nt) {
-    size_t nq = (size_t)P.M * (D + 2) * P.NC, nthr = (size_t)(gridDim.x - 2 * nt) * blockDim.x;
+  if (b >= 2 * nb) {
+    size_t nq = (size_t)P.M * (D + 2) * P.NC, nthr = (size_t)(gridDim.x - 2 * nb) * blockDim.x;
     const double* Q = B.Q[didx];
-    for (size_t w = (size_t)(b - 2 * nt) * blockDim.x + threadIdx.x; w < nq + P.NC; w += nthr)
+    for (size_t w = (size_t)(b - 2 * nb) * blockDim.x + threadIdx.x; w < nq + P.NC; w += nthr)
       if (w < nq)
         save_Q[w] = Q[w];
       else
         save_occ[w - nq] = B.occ[didx][w - nq];
     return;
   }
-  b -= nt;
+  b -= nb;
   int tw = tile_w(P), th = tile_h(P), ntx = tiles_x(P);
-  int i = (b % ntx) * tw + (int)threadIdx.x % tw;
-  int j = (b / ntx) * th + (int)threadIdx.x / tw;
-  if (i < P.nx && j < P.ny) b_geom<D>(P, B, i, j, didx, nullptr);
+  for (int t = b; t < nt; t += nb) {
+    int i = (t % ntx) * tw + (int)threadIdx.x % tw;
+    int j = (t / ntx) * th + (int)threadIdx.x / tw;
+    if (i < P.nx && j < P.ny) b_geom<D>(P, B, i, j, didx, nullptr);
+  }
 }
 
 // run body(i, j) over the cells of the listed tiles, workgroup bx of nbx;
@@ -2352,7 +2364,7 @@ __global__ void __launch_bounds__(256) t_near_col_flags(Params P, Bufs B, int si
     return;
   }
   b -= ntb;
-  bulkflag_block<D>(P, B, sidx, nidx, stage0, b % gx, b / gx, bw, gx * gy);
+  bulkflag_block<D>(P, B, sidx, nidx, stage0, b % gx, b / gx, bw, gx);
 }
 // Interface exchange of the listed tiles (workgroups below ntb) beside the
 // frame of the state buffer (the others, one thread per frame cell): the
@@ -2360,7 +2372,13 @@ __global__ void __launch_bounds__(256) t_near_col_flags(Params P, Bufs B, int si
 // exchange terms nor the velocities it writes.
 template <int D>
 __global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx, int stage0,
-                                                     int ntb) {
+                                                     int ntb, int ndt) {
+  // with ndt > 0 the last workgroup sets the step size from the ndt wave-speed
+  // maxima of the bulk-flag workgroups (nothing else in this launch reads it)
+  if (ndt > 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
+    dt_reduce_block<D>(P, B, ndt);
+    return;
+  }
   if ((int)blockIdx.x < ntb) {
     for_tiles_n(P, B, (int)blockIdx.x, ntb,
                 [&](int i, int j) { b_iface<D>(P, B, i, j, sidx, stage0); });

@@ -223,6 +223,12 @@ static Params make_params(const mm_config* cfg) {
   return P;
 }
 
+// workgroups of the per-cell launches (cell_grid below, from the parameters)
+static dim3 cell_grid_of(const Params& P) {
+  dim3 b = P.dim == 2 ? dim3(64, 4) : dim3(256, 1);
+  return dim3((P.nx + b.x - 1) / b.x, (P.ny + b.y - 1) / b.y);
+}
+
 extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** out) {
   if (!cfg || !out) return fail(nullptr, MM_EINVAL, "NULL argument");
   std::string why;
@@ -269,6 +275,10 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.scal, 8); A(B.ctr, C_N);
   A(B.vfc, nc);
   A(B.cons, CONS_N);
+  {
+    dim3 gb = cell_grid_of(P);
+    A(B.dtpart, (size_t)gb.x * gb.y);
+  }
   A(B.cpart, (size_t)cons_blocks(P) * M * 8);
 #undef A
   if (e != hipSuccess) {
@@ -432,8 +442,9 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
       LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
   }
   long nframe = (D == 2 ? (long)P.ny + P.nx + 2 * H : (long)P.ny) * 2 * H * P.M;
-  LAUNCH(t_iface_frame<D>, dim3(tg.x + lin_grid(nframe).x), tb, P, c->B, sidx, s == 0 ? 1 : 0,
-         (int)tg.x);
+  int ndt = s == 0 ? (int)(g.x * g.y) : 0;  // stage 0: one more workgroup sets the step size
+  LAUNCH(t_iface_frame<D>, dim3(tg.x + lin_grid(nframe).x + (ndt ? 1 : 0)), tb, P, c->B, sidx,
+         s == 0 ? 1 : 0, (int)tg.x, ndt);
   if (s == 0 && D == 2) {
     LAUNCH(k_vext_tiles, tg, tb, P, c->B, sidx);
   } else if (s == 0) {
@@ -486,7 +497,8 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
   classify<D>(c);
   int nt = n_tiles(P);
   // with save_Q, Q* and its occupancy are copied by extra workgroups
-  LAUNCH(k_tiles_geom<D>, dim3(2 * nt + (save_Q ? 512 : 0)), tb, P, c->B, didx, nidx, nt,
+  int nb = nt;  // one workgroup per tile and part (measured faster than fewer, longer ones)
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nb + (save_Q ? 512 : 0)), tb, P, c->B, didx, nidx, nt, nb,
          save_Q, save_occ);
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, dim3(tg.x, P.M, post.n ? 2 : 1), tb, P, c->B, didx, post);
