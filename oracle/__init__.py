@@ -51,7 +51,10 @@ class Config(C.Structure):
                 ("bc", C.c_int32 * 4), ("inflow_W", C.c_double * 4),
                 ("inflow_mat", C.c_int32), ("rk_order", C.c_int32),
                 ("cfl", C.c_double), ("alpha_mix", C.c_double),
-                ("k_ext", C.c_int32), ("band_ls", C.c_int32)]
+                ("k_ext", C.c_int32), ("band_ls", C.c_int32),
+                ("eos", C.c_int32 * MAXM), ("rho0", C.c_double * MAXM),
+                ("tait_B", C.c_double * MAXM), ("p0", C.c_double * MAXM),
+                ("flux", C.c_int32)]
 
 
 def make_config(cfg):
@@ -64,6 +67,11 @@ def make_config(cfg):
     for m in range(cfg["n_mat"]):
         c.gamma[m] = float(cfg["gamma"][m])
         c.pinf[m] = float(cfg["pinf"][m])
+        c.eos[m] = int(cfg.get("eos", [0] * cfg["n_mat"])[m])
+        c.rho0[m] = float(cfg.get("rho0", [0.0] * cfg["n_mat"])[m])
+        c.tait_B[m] = float(cfg.get("tait_B", [0.0] * cfg["n_mat"])[m])
+        c.p0[m] = float(cfg.get("p0", [0.0] * cfg["n_mat"])[m])
+    c.flux = int(cfg.get("flux", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])

@@ -63,6 +63,11 @@ typedef struct {
   int32_t inflow_mat, rk_order;
   double cfl, alpha_mix;
   int32_t k_ext, band_ls;
+  /* Tait materials (Sec. 2.1, Tait's equation for water-like fluids):
+     eos = 1 gives p = B (rho/rho0)^gamma - B + p0; eos = 0 the stiffened gas */
+  int32_t eos[OR_MAXM];
+  double rho0[OR_MAXM], tait_B[OR_MAXM], p0[OR_MAXM];
+  int32_t flux;
 } or_config;
 
 typedef struct {
@@ -70,6 +75,10 @@ typedef struct {
   int M, NX, NY, HY, NC;
   double dx, dy, h, bls, idx, idy;
   double igm1[OR_MAXM];
+  /* p_inf of the energy relation: the stiffened gas's own, B - p0 for a Tait
+     material (see energy()) */
+  double pinfe[OR_MAXM];
+  int tait[OR_MAXM];
   /* regional level set: current stage, time n, next stage */
   real *phi, *phin, *phit;
   int *chi, *chin, *chit;
@@ -121,9 +130,11 @@ static void neumaier(real *sum, real *comp, real x) {
 /* Thermodynamics (Sec. 2.1; general-EOS sound speed, Sec. 2.3.2)            */
 /* ------------------------------------------------------------------------ */
 
-/* primitive (rho, u, v, p) from conserved cell averages U (not alpha U) */
+/* primitive (rho, u, v, p) from conserved cell averages U (not alpha U).
+ * Stiffened gas: p = (gamma-1)(rho E - rho |u|^2/2) - gamma p_inf.  Tait
+ * (Sec. 2.1): p = B (rho/rho0)^gamma - B + p0, a function of density alone. */
 static void prim(const St *s, int m, const real *U, real *W) {
-  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  double g = s->c.gamma[m], pinf = s->pinfe[m];
   real rho = U[0];
   real u = U[1] / rho;
   real v = U[2] / rho;
@@ -131,13 +142,20 @@ static void prim(const St *s, int m, const real *U, real *W) {
   W[0] = rho;
   W[1] = u;
   W[2] = v;
-  W[3] = (g - 1.0) * (U[3] - ke) - g * pinf;
+  if (s->tait[m])
+    W[3] = s->c.tait_B[m] * pow(rho / s->c.rho0[m], g) - pinf;
+  else
+    W[3] = (g - 1.0) * (U[3] - ke) - g * pinf;
 }
 
-/* total energy density rho E of a primitive state */
+/* total energy density rho E of a primitive state.  Reading for a Tait
+ * material (the paper gives no energy relation for it): the internal energy
+ * of the stiffened gas with the same gamma and p_inf = B - p0, so that
+ * rho E is defined and c^2 = gamma (p + B - p0)/rho as for that gas; the
+ * pressure itself never depends on the energy. */
 static real energy(const St *s, int m, real rho, real u, real v,
                      real p) {
-  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  double g = s->c.gamma[m], pinf = s->pinfe[m];
   return (p + g * pinf) * s->igm1[m] + 0.5 * rho * (u * u + v * v);
 }
 
@@ -146,15 +164,17 @@ static real energy(const St *s, int m, real rho, real u, real v,
  * Psi, Upsilon and p/rho).  Stiffened gas: Psi = (p + gamma p_inf)/rho,
  * Upsilon = gamma - 1, so c^2 = Psi + Upsilon p/rho = gamma (p + p_inf)/rho.
  * States are (rho, u_normal, u_tangential, p). */
-static void wave_speeds(const real *WL, double gL, double piL,
-                        const real *WR, double gR, double piR, real *SL,
+static void wave_speeds(const real *WL, double gL, double piL, int tL,
+                        const real *WR, double gR, double piR, int tR, real *SL,
                         real *SR) {
   real rL = WL[0], uL = WL[1], pL = WL[3];
   real rR = WR[0], uR = WR[1], pR = WR[3];
   real irL = 1.0 / rL, irR = 1.0 / rR;
   real porL = pL * irL, porR = pR * irR;
-  real psiL = (pL + gL * piL) * irL, psiR = (pR + gR * piR) * irR;
-  real upsL = gL - 1.0, upsR = gR - 1.0;
+  /* Tait: Psi = dp/drho = gamma (p + B - p0)/rho, Upsilon = 0 */
+  real psiL = tL ? gL * (pL + piL) * irL : (pL + gL * piL) * irL;
+  real psiR = tR ? gR * (pR + piR) * irR : (pR + gR * piR) * irR;
+  double upsL = tL ? 0.0 : gL - 1.0, upsR = tR ? 0.0 : gR - 1.0;
   real cL = sqrt(psiL + upsL * porL);
   real cR = sqrt(psiR + upsR * porR);
   real sL = sqrt(rL), sR = sqrt(rR);
@@ -186,9 +206,10 @@ static real contact_speed(const real *WL, const real *WR, real SL,
  * energy). */
 static void hllc_flux(const St *s, int m, const real *WL, const real *WR,
                       real *F) {
-  double g = s->c.gamma[m], pinf = s->c.pinf[m];
+  double g = s->c.gamma[m], pinf = s->pinfe[m];
+  int t = s->tait[m];
   real SL, SR;
-  wave_speeds(WL, g, pinf, WR, g, pinf, &SL, &SR);
+  wave_speeds(WL, g, pinf, t, WR, g, pinf, t, &SL, &SR);
   real SM = contact_speed(WL, WR, SL, SR);
   const real *Wk;
   real Sk;
@@ -588,7 +609,7 @@ static void real_states(St *s) {
       real U[4], W[4];
       for (int v = 0; v < 4; v++) U[v] = M4(s, s->Q, r, v, k) / a;
       prim(s, r, U, W);
-      if (!(W[0] > 0.0) || !(W[3] + s->c.pinf[r] > 0.0) || !isfinite(W[1]) ||
+      if (!(W[0] > 0.0) || !(W[3] + s->pinfe[r] > 0.0) || !isfinite(W[1]) ||
           !isfinite(W[2]) || !isfinite(W[0]) || !isfinite(W[3]))
         record_err(s, OR_ENONPHYS, i, j);
       for (int v = 0; v < 4; v++) M4(s, s->W, r, v, k) = W[v];
@@ -708,7 +729,7 @@ static real cfl_dt(St *s) {
       if (!M1(s, s->Wv, r, k)) continue;
       real rho = M4(s, s->W, r, 0, k), u = M4(s, s->W, r, 1, k),
              v = M4(s, s->W, r, 2, k), p = M4(s, s->W, r, 3, k);
-      real c = sqrt(s->c.gamma[r] * (p + s->c.pinf[r]) / rho);
+      real c = sqrt(s->c.gamma[r] * (p + s->pinfe[r]) / rho);
       real a = fabs(u) + c, b = fabs(v) + c;
       real w = a > b ? a : b;
       if (w > smax) smax = w;
@@ -772,7 +793,8 @@ static void interface_exchange(St *s, int stage) {
       WR[2] = 0.0;
       WR[3] = M4(s, s->W, a, 3, k);
       real SL, SR;
-      wave_speeds(WL, s->c.gamma[bb], s->c.pinf[bb], WR, s->c.gamma[a], s->c.pinf[a], &SL, &SR);
+      wave_speeds(WL, s->c.gamma[bb], s->pinfe[bb], s->tait[bb], WR, s->c.gamma[a], s->pinfe[a],
+                  s->tait[a], &SL, &SR);
       real SM = contact_speed(WL, WR, SL, SR);
       real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
       real ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
@@ -819,7 +841,7 @@ static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
       WL[v] = weno5(Wc[0][c], Wc[1][c], Wc[2][c], Wc[3][c], Wc[4][c]);
       WR[v] = weno5(Wc[5][c], Wc[4][c], Wc[3][c], Wc[2][c], Wc[1][c]);
     }
-    double pinf = s->c.pinf[r];
+    double pinf = s->pinfe[r];
     if (!(WL[0] > 0.0) || !(WR[0] > 0.0) || !(WL[3] + pinf > 0.0) ||
         !(WR[3] + pinf > 0.0))
       ok = 0;
@@ -1269,6 +1291,11 @@ St *or_create(const or_config *c) {
   if (!c || (c->dim != 1 && c->dim != 2) || c->nx < 1 || c->ny < 1 ||
       (c->dim == 1 && c->ny != 1) || c->n_mat < 1 || c->n_mat > OR_MAXM)
     return NULL;
+  for (int m = 0; m < c->n_mat; m++)
+    if (c->eos[m] < 0 || c->eos[m] > 1 ||
+        (c->eos[m] == 1 && !(c->rho0[m] > 0.0 && c->tait_B[m] > 0.0)))
+      return NULL;
+  if (c->flux < 0 || c->flux > 1) return NULL;
   St *s = (St *)zalloc(sizeof(St));
   s->c = *c;
   s->M = c->n_mat;
@@ -1282,7 +1309,11 @@ St *or_create(const or_config *c) {
   s->bls = c->band_ls * s->h;
   s->idx = 1.0 / s->dx;
   s->idy = 1.0 / s->dy;
-  for (int m = 0; m < s->M; m++) s->igm1[m] = 1.0 / (c->gamma[m] - 1.0);
+  for (int m = 0; m < s->M; m++) {
+    s->igm1[m] = 1.0 / (c->gamma[m] - 1.0);
+    s->tait[m] = c->eos[m] == 1;
+    s->pinfe[m] = s->tait[m] ? c->tait_B[m] - c->p0[m] : c->pinf[m];
+  }
   size_t nc = s->NC, M = s->M, R = sizeof(real);
   s->phi = (real *)zalloc(nc * R); s->phin = (real *)zalloc(nc * R);
   s->phit = (real *)zalloc(nc * R);
@@ -1360,7 +1391,7 @@ static int init_impl(St *s, const double *phi, const int32_t *chi, const double 
         w[1] = w_in(W, dW, ((size_t)r * nv + 1) * plane + q);
         w[2] = nv == 4 ? w_in(W, dW, ((size_t)r * nv + 2) * plane + q) : (real)0.0;
         w[3] = w_in(W, dW, ((size_t)r * nv + nv - 1) * plane + q);
-        if (a > 0.0 && (!(w[0] > 0.0) || !(w[3] + s->c.pinf[r] > 0.0) ||
+        if (a > 0.0 && (!(w[0] > 0.0) || !(w[3] + s->pinfe[r] > 0.0) ||
                         !isfinite(w[1]) || !isfinite(w[2])))
           record_err(s, OR_ENONPHYS, i, j);
         real U[4];
@@ -1557,7 +1588,8 @@ void or_t_iface(const St *s, int mL, const double *WLd, int mR, const double *WR
     WR[v] = WRd[v];
   }
   real SL, SR;
-  wave_speeds(WL, s->c.gamma[mL], s->c.pinf[mL], WR, s->c.gamma[mR], s->c.pinf[mR], &SL, &SR);
+  wave_speeds(WL, s->c.gamma[mL], s->pinfe[mL], s->tait[mL], WR, s->c.gamma[mR], s->pinfe[mR],
+              s->tait[mR], &SL, &SR);
   real SM = contact_speed(WL, WR, SL, SR);
   real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
   out[0] = RV(SL);

@@ -73,6 +73,11 @@ static inline or_dual sqrt(const or_dual& a) {
   return or_dual(r, a.d / (2.0 * r));
 }
 static inline or_dual fabs(const or_dual& a) { return a.v < 0.0 ? -a : a; }
+/* x^e for a constant exponent: d(x^e) = e x^(e-1) dx */
+static inline or_dual pow(const or_dual& a, double e) {
+  double r = pow(a.v, e);
+  return or_dual(r, e * pow(a.v, e - 1.0) * a.d);
+}
 /* C's fmin/fmax on values; the selected operand supplies the derivative
    (the first one when the values are equal) */
 static inline or_dual fmin(const or_dual& a, const or_dual& b) { return b.v < a.v ? b : a; }

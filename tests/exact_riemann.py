@@ -1,4 +1,5 @@
-"""Exact solution of the 1D Riemann problem between two stiffened gases.
+"""Exact solution of the 1D Riemann problem between two stiffened gases
+(or a stiffened gas and a Tait liquid).
 
 Independent check of the oracle: Toro's exact solver (Riemann Solvers and
 Numerical Methods for Fluid Dynamics, ch. 4) with each side's pressure
@@ -30,6 +31,62 @@ class Side:
         return 2.0 * self.c / (g - 1.0) * ((psb / pb) ** ((g - 1.0) / (2.0 * g)) - 1.0)
 
 
+class TaitSide:
+    """A barotropic Tait liquid, p = B (rho/rho0)^gamma - B + p0: across a
+    shock only mass and momentum jump conditions apply, (u_* - u)^2 =
+    (p_* - p)(1/rho - 1/rho_*); a rarefaction keeps u -+ 2c/(gamma-1)
+    constant, with c^2 = dp/drho = gamma (p + B - p0)/rho proportional to
+    rho^(gamma-1)."""
+
+    def __init__(self, rho, u, p_unused, gamma, B, rho0, p0):
+        self.g, self.B, self.rho0, self.p0 = gamma, B, rho0, p0
+        self.rho, self.u = rho, u
+        self.p = self.pressure(rho)
+        self.pinf = B - p0
+        self.c = self.sound(rho)
+
+    def pressure(self, rho):
+        return self.B * (rho / self.rho0) ** self.g - self.B + self.p0
+
+    def density(self, p):
+        return self.rho0 * ((p - self.p0 + self.B) / self.B) ** (1.0 / self.g)
+
+    def sound(self, rho):
+        return math.sqrt(self.g * self.B / self.rho0 * (rho / self.rho0) ** (self.g - 1.0))
+
+    def f(self, ps):
+        rs = self.density(ps)
+        if ps > self.p:
+            return math.sqrt((ps - self.p) * (1.0 / self.rho - 1.0 / rs))
+        return 2.0 / (self.g - 1.0) * (self.sound(rs) - self.c)
+
+    def edges(self, ps, us, sgn):
+        rs = self.density(ps)
+        if ps > self.p:
+            m = math.sqrt((ps - self.p) / (1.0 / self.rho - 1.0 / rs))
+            sh = self.u + sgn * m / self.rho
+            return sh, sh
+        return self.u + sgn * self.c, us + sgn * self.sound(rs)
+
+    def state(self, s, ps, us, sgn):
+        head, tail = self.edges(ps, us, sgn)
+        if (s - head) * sgn >= 0.0:
+            return self.rho, self.u, self.p
+        if ps > self.p or (s - tail) * sgn <= 0.0:
+            rs = self.density(ps)
+            return rs, us, ps
+        g = self.g
+        if sgn > 0:
+            c = (g - 1.0) / (g + 1.0) * (s - self.u) + 2.0 * self.c / (g + 1.0)
+            uu = s - c
+        else:
+            c = (g - 1.0) / (g + 1.0) * (self.u - s) + 2.0 * self.c / (g + 1.0)
+            uu = s + c
+        c0 = math.sqrt(g * self.B / self.rho0)
+        rr = self.rho0 * (c / c0) ** (2.0 / (g - 1.0))
+        return rr, uu, self.pressure(rr)
+
+
 def star_state(L: Side, R: Side):
     """Star pressure and contact velocity."""
     fn = lambda p: L.f(p) + R.f(p) + (R.u - L.u)
@@ -48,6 +105,10 @@ def wave_speeds(L: Side, R: Side):
     ps, us = star_state(L, R)
     out = {}
     for S, sgn, key in ((L, -1.0, "left"), (R, 1.0, "right")):
+        if hasattr(S, "edges"):
+            a, b = S.edges(ps, us, sgn)
+            out[key] = (a, b)
+            continue
         g, pb, psb = S.g, S.p + S.pinf, ps + S.pinf
         if ps > S.p:
             sh = S.u + sgn * S.c * math.sqrt((g + 1.0) / (2.0 * g) * psb / pb
@@ -71,6 +132,9 @@ def sample(L: Side, R: Side, xi):
             S, sgn = L, -1.0
         else:
             S, sgn = R, 1.0
+        if hasattr(S, "state"):
+            rho.flat[n], u.flat[n], p.flat[n] = S.state(s, ps, us, sgn)
+            continue
         g, pinf, pb, psb = S.g, S.pinf, S.p + S.pinf, ps + S.pinf
         if ps > S.p:  # shock
             sh = S.u + sgn * S.c * math.sqrt((g + 1.0) / (2.0 * g) * psb / pb

@@ -187,6 +187,81 @@ def shock_bubble_tangent(w, q, mach=1.22, x_shock=0.5):
     return dW, dinf
 
 
+# Water of Case VI (Table 2: rho0 = 1000, gamma = 7.15, p = 1 with the
+# ambient air at rho = 1, p = 1).  The paper gives no value of B; B = 3310
+# is the usual Tait constant of water (3.31e8 Pa) in units of an ambient
+# pressure of 1e5 Pa.
+WATER = dict(gamma=7.15, rho0=1000.0, B=3310.0, p0=1.0)
+
+
+def tait_config(cfg, mats, water=WATER):
+    """Mark the materials ``mats`` of a configuration as Tait water."""
+    M = cfg["n_mat"]
+    cfg["eos"] = [1 if m in mats else 0 for m in range(M)]
+    cfg["rho0"] = [water["rho0"] if m in mats else 0.0 for m in range(M)]
+    cfg["tait_B"] = [water["B"] if m in mats else 0.0 for m in range(M)]
+    cfg["p0"] = [water["p0"] if m in mats else 0.0 for m in range(M)]
+    for m in mats:
+        cfg["gamma"][m] = water["gamma"]
+        cfg["pinf"][m] = 0.0
+    return cfg
+
+
+def tait_pressure(rho, water=WATER):
+    """Pressure of Tait water at density rho (for building consistent inputs)."""
+    return water["B"] * (np.asarray(rho) / water["rho0"]) ** water["gamma"] - water["B"] + water["p0"]
+
+
+def air_water_tube_1d(n=400, x_if=None, air=(50.0, 0.0, 1000.0), water_rho=1000.0,
+                      steps=100):
+    """Two-material tube on [0, 1]: compressed air (gamma 1.4) left of x_if,
+    Tait water at rest right of it; transmissive ends.  The interface sits
+    inside a cell (0.3 cell past the middle face) by default."""
+    x, dx = _centres(n, 0.0, 1.0)
+    if x_if is None:
+        x_if = 0.5 + 0.3 * dx
+    cfg = base_config(dim=1, nx=n, ny=1, n_mat=2, gamma=[1.4, 1.4], pinf=[0.0, 0.0],
+                      bc=[BC_TRANSMISSIVE] * 4)
+    tait_config(cfg, [1])
+    phi = np.minimum(np.abs(x - x_if), cfg["band_ls"] * dx)
+    chi = (x >= x_if).astype(np.int32)
+    pw = float(tait_pressure(water_rho))
+    W = _fill_W(2, 1, (n,), [air, (water_rho, 0.0, pw)])
+    return dict(cfg=cfg, phi=phi.reshape(1, n), chi=chi.reshape(1, n),
+                W=W.reshape(2, 3, 1, n), steps=steps, name="air_water_tube_1d")
+
+
+def shock_helium_water(nx=512, ny=128, steps=200, x_shock=0.5, bubble=(1.1, 0.5, 0.25),
+                       column=(2.0, 0.5, 0.2)):
+    """Case VI set-up (Table 2): a Mach 6 shock in air (post-shock state from
+    the normal-shock relations; Table 2 prints (5.268, 5.752, 41.83)) hits a
+    helium bubble (gamma 1.667, rho 0.138) that then meets a water column
+    (Tait water, rho0 = 1000).  The figure with the geometry is not in the
+    text: bubble of radius 0.25 at (1.1, 0.5), circular water column of
+    radius 0.2 at (2.0, 0.5), 4 x 1 domain, inflow left, outflow right,
+    reflective top and bottom (as Case V)."""
+    x, dx = _centres(nx, 0.0, 4.0)
+    y, dy = _centres(ny, 0.0, 1.0)
+    X, Y = np.meshgrid(x, y)
+    rho1, u1, p1, _ = rankine_hugoniot(6.0, 1.4, 1.0, 1.0)
+    cfg = base_config(dim=2, nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
+                      gamma=[1.4, 1.667, 1.4], pinf=[0.0, 0.0, 0.0],
+                      bc=[BC_INFLOW, BC_OUTFLOW, BC_REFLECTIVE, BC_REFLECTIVE],
+                      inflow_W=[rho1, u1, 0.0, p1], inflow_mat=0)
+    tait_config(cfg, [2])
+    db = np.sqrt((X - bubble[0]) ** 2 + (Y - bubble[1]) ** 2) - bubble[2]
+    dc = np.sqrt((X - column[0]) ** 2 + (Y - column[1]) ** 2) - column[2]
+    phi = np.minimum(np.minimum(np.abs(db), np.abs(dc)), cfg["band_ls"] * min(dx, dy))
+    chi = np.where(db <= 0.0, 1, np.where(dc <= 0.0, 2, 0)).astype(np.int32)
+    W = _fill_W(3, 2, (ny, nx), [(1.0, 0.0, 0.0, 1.0), (0.138, 0.0, 0.0, 1.0),
+                                 (1000.0, 0.0, 0.0, float(tait_pressure(1000.0)))])
+    post = X < x_shock
+    W[0, 0][post] = rho1
+    W[0, 1][post] = u1
+    W[0, 3][post] = p1
+    return dict(cfg=cfg, phi=phi, chi=chi, W=W, steps=steps, name="shock_helium_water")
+
+
 BATCH_SEED = 1704005190
 
 
