@@ -107,6 +107,7 @@ def lib(tangent=False):
         L.or_t_weno5.restype = d
         L.or_t_weno5.argtypes = [d, d, d, d, d]
         L.or_t_hllc.argtypes = [vp, C.c_int, dp, dp, dp]
+        L.or_t_roe.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         L.or_t_mixing.argtypes = [vp, dp, dp, dp, ip, dp]
@@ -167,6 +168,12 @@ class Oracle:
         F = np.zeros(4)
         self._L.or_t_hllc(self._h, int(m), np.ascontiguousarray(WL, float),
                         np.ascontiguousarray(WR, float), F)
+        return F
+
+    def roe(self, m, WL, WR):
+        F = np.zeros(4)
+        self._L.or_t_roe(self._h, int(m), np.ascontiguousarray(WL, float),
+                         np.ascontiguousarray(WR, float), F)
         return F
 
     def iface(self, mL, WL, mR, WR):

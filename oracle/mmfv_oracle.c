@@ -820,6 +820,154 @@ static void interface_exchange(St *s, int stage) {
  * the same routine on the mirrored stencil), then HLLC.  Reading (guards): if
  * a reconstructed density or p + p_inf is not positive, or a stencil cell has
  * no state, the first-order states of the two face cells are used. */
+/* ------------------------------------------------------------------------ */
+/* Roe flux with characteristic-wise WENO5 (the variant of the face flux;    */
+/* Sec. 3 uses a 5th-order WENO scheme; the Roe solver and the projection  */
+/* onto characteristic fields are the classical ones)                      */
+/* ------------------------------------------------------------------------ */
+/* Conserved (rho, rho u_n, rho u_t, rho E) of a primitive state (rho, u_n,
+ * u_t, p) of material m. */
+static void cons_of(const St *s, int m, const real *W, real *U) {
+  U[0] = W[0];
+  U[1] = W[0] * W[1];
+  U[2] = W[0] * W[2];
+  U[3] = energy(s, m, W[0], W[1], W[2], W[3]);
+}
+
+/* Roe average of two states of one stiffened gas (normal direction first):
+ * velocity, enthalpy and sound speed, c^2 = (gamma-1)(H - |u|^2/2). */
+static void roe_avg(const St *s, int m, const real *WL, const real *WR, real *u,
+                    real *v, real *Hr, real *c) {
+  real sL = sqrt(WL[0]), sR = sqrt(WR[0]);
+  real iw = 1.0 / (sL + sR);
+  real HL = (energy(s, m, WL[0], WL[1], WL[2], WL[3]) + WL[3]) / WL[0];
+  real HR = (energy(s, m, WR[0], WR[1], WR[2], WR[3]) + WR[3]) / WR[0];
+  *u = (sL * WL[1] + sR * WR[1]) * iw;
+  *v = (sL * WL[2] + sR * WR[2]) * iw;
+  *Hr = (sL * HL + sR * HR) * iw;
+  *c = sqrt((s->c.gamma[m] - 1.0) * (*Hr - 0.5 * (*u * *u + *v * *v)));
+}
+
+/* Left (L[k][.]) and right (R[.][k]) eigenvectors of the Euler flux
+ * Jacobian in the normal direction at (u, v, H, c): eigenvalues u - c, u,
+ * u (shear), u + c. */
+static void eigvecs(double g, real u, real v, real Hr, real c, real L[4][4], real R[4][4]) {
+  real q2 = 0.5 * (u * u + v * v);
+  real b1 = (g - 1.0) / (c * c), b2 = q2 * b1;
+  R[0][0] = 1.0; R[1][0] = u - c; R[2][0] = v; R[3][0] = Hr - u * c;
+  R[0][1] = 1.0; R[1][1] = u;     R[2][1] = v; R[3][1] = q2;
+  R[0][2] = 0.0; R[1][2] = 0.0;   R[2][2] = 1.0; R[3][2] = v;
+  R[0][3] = 1.0; R[1][3] = u + c; R[2][3] = v; R[3][3] = Hr + u * c;
+  L[0][0] = 0.5 * (b2 + u / c); L[0][1] = -0.5 * (b1 * u + 1.0 / c);
+  L[0][2] = -0.5 * (b1 * v); L[0][3] = 0.5 * b1;
+  L[1][0] = 1.0 - b2; L[1][1] = b1 * u; L[1][2] = b1 * v; L[1][3] = -b1;
+  L[2][0] = -v; L[2][1] = 0.0; L[2][2] = 1.0; L[2][3] = 0.0;
+  L[3][0] = 0.5 * (b2 - u / c); L[3][1] = -0.5 * (b1 * u - 1.0 / c);
+  L[3][2] = -0.5 * (b1 * v); L[3][3] = 0.5 * b1;
+}
+
+static void matvec(real A[4][4], const real *x, real *y) {
+  for (int k = 0; k < 4; k++) y[k] = ((A[k][0] * x[0] + A[k][1] * x[1]) + A[k][2] * x[2]) + A[k][3] * x[3];
+}
+
+/* Physical flux of a conserved state in the normal direction. */
+static void euler_flux(const St *s, int m, const real *U, real *F, real *p_out) {
+  real rho = U[0], un = U[1] / rho, ut = U[2] / rho;
+  real p = (s->c.gamma[m] - 1.0) * (U[3] - 0.5 * rho * (un * un + ut * ut)) - s->c.gamma[m] * s->pinfe[m];
+  F[0] = U[1];
+  F[1] = U[1] * un + p;
+  F[2] = U[1] * ut;
+  F[3] = un * (U[3] + p);
+  *p_out = p;
+}
+
+/* Speed u_n -+ c of a conserved state (sign -1: the left acoustic field,
+ * +1 the right one); 0 with ok = 0 if the state is not physical. */
+static real acoustic_speed(const St *s, int m, const real *U, int sign, int *ok) {
+  real rho = U[0];
+  real un = U[1] / rho, ut = U[2] / rho;
+  real p = (s->c.gamma[m] - 1.0) * (U[3] - 0.5 * rho * (un * un + ut * ut)) - s->c.gamma[m] * s->pinfe[m];
+  *ok = rho > 0.0 && p + s->pinfe[m] > 0.0;
+  if (!*ok) return 0.0;
+  real c = sqrt(s->c.gamma[m] * (p + s->pinfe[m]) / rho);
+  return sign < 0 ? un - c : un + c;
+}
+
+/* Roe's flux between the states WL, WR, with the Harten-Hyman entropy fix
+ * on the two acoustic fields: with lambda_a, lambda_b the field's speeds in
+ * the states on either side of that wave of the linearised solution (U_L
+ * and U_L + a_1 r_1 for the left field, U_R - a_4 r_4 and U_R for the right
+ * one) and delta = max(0, lambda~ - lambda_a, lambda_b - lambda~), |lambda~|
+ * below delta is replaced by (lambda~^2 + delta^2)/(2 delta).  Only a
+ * transonic rarefaction has delta > 0; shocks keep Roe's exact resolution. */
+static void roe_flux(const St *s, int m, const real *WL, const real *WR, real *G) {
+  real UL[4], UR[4], FL[4], FR[4], pL, pR;
+  cons_of(s, m, WL, UL);
+  cons_of(s, m, WR, UR);
+  euler_flux(s, m, UL, FL, &pL);
+  euler_flux(s, m, UR, FR, &pR);
+  real u, v, Hr, c, L[4][4], R[4][4];
+  roe_avg(s, m, WL, WR, &u, &v, &Hr, &c);
+  eigvecs(s->c.gamma[m], u, v, Hr, c, L, R);
+  real dU[4], a[4];
+  for (int k = 0; k < 4; k++) dU[k] = UR[k] - UL[k];
+  matvec(L, dU, a);
+  real lam[4] = {u - c, u, u, u + c};
+  /* states on either side of the two acoustic waves */
+  real Ua[4], Ub[4];
+  for (int q = 0; q < 4; q++) {
+    Ua[q] = UL[q] + a[0] * R[q][0];
+    Ub[q] = UR[q] - a[3] * R[q][3];
+  }
+  for (int k = 0; k < 4; k++) {
+    real l = fabs(lam[k]);
+    if (k == 0 || k == 3) {
+      int oka, okb;
+      real la = k == 0 ? acoustic_speed(s, m, UL, -1, &oka) : acoustic_speed(s, m, Ub, 1, &oka);
+      real lb = k == 0 ? acoustic_speed(s, m, Ua, -1, &okb) : acoustic_speed(s, m, UR, 1, &okb);
+      if (oka && okb) {
+        real d1 = lam[k] - la, d2 = lb - lam[k];
+        real delta = d1 > d2 ? d1 : d2;
+        if (delta > 0.0 && l < delta) l = (lam[k] * lam[k] + delta * delta) / (2.0 * delta);
+      }
+    }
+    a[k] = l * a[k];
+  }
+  for (int q = 0; q < 4; q++) {
+    real d = ((R[q][0] * a[0] + R[q][1] * a[1]) + R[q][2] * a[2]) + R[q][3] * a[3];
+    G[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * d;
+  }
+}
+
+/* Characteristic-wise WENO5 at a face: the six cells' conserved states are
+ * projected onto the characteristic fields of the Roe average of the two
+ * face cells, reconstructed field by field (left-biased from cells 0..4,
+ * right-biased from 5..1) and projected back; returns the primitive states
+ * (rho, u_n, u_t, p) on both sides. */
+static void char_weno(const St *s, int m, real Wc[6][4], const int *perm, real *WL, real *WR) {
+  real Ws[6][4], U[6][4], w[6][4];
+  for (int q = 0; q < 6; q++) {
+    for (int v = 0; v < 4; v++) Ws[q][v] = Wc[q][perm[v]];
+    cons_of(s, m, Ws[q], U[q]);
+  }
+  real u, v, Hr, c, L[4][4], R[4][4];
+  roe_avg(s, m, Ws[2], Ws[3], &u, &v, &Hr, &c);
+  eigvecs(s->c.gamma[m], u, v, Hr, c, L, R);
+  for (int q = 0; q < 6; q++) matvec(L, U[q], w[q]);
+  real cl[4], cr[4], UL[4], UR[4];
+  for (int k = 0; k < 4; k++) {
+    cl[k] = weno5(w[0][k], w[1][k], w[2][k], w[3][k], w[4][k]);
+    cr[k] = weno5(w[5][k], w[4][k], w[3][k], w[2][k], w[1][k]);
+  }
+  matvec(R, cl, UL);
+  matvec(R, cr, UR);
+  real pL, pR, FL[4];
+  euler_flux(s, m, UL, FL, &pL);
+  euler_flux(s, m, UR, FL, &pR);
+  WL[0] = UL[0]; WL[1] = UL[1] / UL[0]; WL[2] = UL[2] / UL[0]; WL[3] = pL;
+  WR[0] = UR[0]; WR[1] = UR[1] / UR[0]; WR[2] = UR[2] / UR[0]; WR[3] = pR;
+}
+
 static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
                      real *F) {
   real WL[4], WR[4], Wc[6][4];
@@ -835,11 +983,16 @@ static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
   }
   /* component order: rho, normal velocity, tangential velocity, p */
   int perm[4] = {0, normal == 0 ? 1 : 2, normal == 0 ? 2 : 1, 3};
+  int roe = s->c.flux == 1;
   if (ok) {
-    for (int v = 0; v < 4; v++) {
-      int c = perm[v];
-      WL[v] = weno5(Wc[0][c], Wc[1][c], Wc[2][c], Wc[3][c], Wc[4][c]);
-      WR[v] = weno5(Wc[5][c], Wc[4][c], Wc[3][c], Wc[2][c], Wc[1][c]);
+    if (roe) {
+      char_weno(s, r, Wc, perm, WL, WR);
+    } else {
+      for (int v = 0; v < 4; v++) {
+        int c = perm[v];
+        WL[v] = weno5(Wc[0][c], Wc[1][c], Wc[2][c], Wc[3][c], Wc[4][c]);
+        WR[v] = weno5(Wc[5][c], Wc[4][c], Wc[3][c], Wc[2][c], Wc[1][c]);
+      }
     }
     double pinf = s->pinfe[r];
     if (!(WL[0] > 0.0) || !(WR[0] > 0.0) || !(WL[3] + pinf > 0.0) ||
@@ -854,7 +1007,10 @@ static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
     }
   }
   real G[4];
-  hllc_flux(s, r, WL, WR, G);
+  if (roe)
+    roe_flux(s, r, WL, WR, G);
+  else
+    hllc_flux(s, r, WL, WR, G);
   F[0] = G[0];
   F[1 + (normal == 0 ? 0 : 1)] = G[1];
   F[1 + (normal == 0 ? 1 : 0)] = G[2];
@@ -1296,6 +1452,8 @@ St *or_create(const or_config *c) {
         (c->eos[m] == 1 && !(c->rho0[m] > 0.0 && c->tait_B[m] > 0.0)))
       return NULL;
   if (c->flux < 0 || c->flux > 1) return NULL;
+  for (int m = 0; m < c->n_mat; m++)
+    if (c->flux == 1 && c->eos[m] == 1) return NULL; /* Roe variant: stiffened gases */
   St *s = (St *)zalloc(sizeof(St));
   s->c = *c;
   s->M = c->n_mat;
@@ -1575,6 +1733,17 @@ void or_t_hllc(const St *s, int m, const double *WL, const double *WR, double *F
     R[v] = WR[v];
   }
   hllc_flux(s, m, L, R, G);
+  for (int v = 0; v < 4; v++) F[v] = RV(G[v]);
+}
+
+/* Roe face flux of material m between primitive states (rho, un, ut, p). */
+void or_t_roe(St *s, int m, const double *WL, const double *WR, double *F) {
+  real L[4], R[4], G[4];
+  for (int v = 0; v < 4; v++) {
+    L[v] = WL[v];
+    R[v] = WR[v];
+  }
+  roe_flux(s, m, L, R, G);
   for (int v = 0; v < 4; v++) F[v] = RV(G[v]);
 }
 
