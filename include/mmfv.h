@@ -67,7 +67,19 @@ typedef struct {
   double cfl, alpha_mix;         /* CFL number (0.6); mixing threshold 0.5  */
   int32_t k_ext, band_ls;        /* upwind ghost sweeps (8); band width in  */
                                  /* cells of the level set (8)              */
+  /* Tait materials (Sec. 2.1, Tait's equation for water-like fluids):
+   * eos[m] = MM_EOS_TAIT gives p = B (rho/rho0)^gamma - B + p0 (pressure
+   * from density alone; gamma[m] is the Tait exponent, pinf[m] unused) with
+   * the energy relation of the stiffened gas of the same gamma and
+   * p_inf = B - p0.  All zero: every material a stiffened gas. */
+  int32_t eos[MM_MAX_MAT];
+  double rho0[MM_MAX_MAT], tait_B[MM_MAX_MAT], p0[MM_MAX_MAT];
+  int32_t flux;                  /* MM_FLUX_HLLC (0): component-wise WENO5 + */
+                                 /* HLLC; MM_FLUX_ROE (1): characteristic-  */
+                                 /* wise WENO5 + Roe                        */
 } mm_config;
+enum { MM_EOS_STIFFENED = 0, MM_EOS_TAIT = 1 };
+enum { MM_FLUX_HLLC = 0, MM_FLUX_ROE = 1 };
 
 /* Diagnostics of a context (mm_get_diagnostics). */
 typedef struct {

@@ -41,7 +41,10 @@ class MMConfig(C.Structure):
                 ("bc", C.c_int32 * 4), ("inflow_W", C.c_double * 4),
                 ("inflow_mat", C.c_int32), ("rk_order", C.c_int32),
                 ("cfl", C.c_double), ("alpha_mix", C.c_double),
-                ("k_ext", C.c_int32), ("band_ls", C.c_int32)]
+                ("k_ext", C.c_int32), ("band_ls", C.c_int32),
+                ("eos", C.c_int32 * MAX_MAT), ("rho0", C.c_double * MAX_MAT),
+                ("tait_B", C.c_double * MAX_MAT), ("p0", C.c_double * MAX_MAT),
+                ("flux", C.c_int32)]
 
 
 class MMDiag(C.Structure):
@@ -142,9 +145,15 @@ def make_config(cfg):
         setattr(c, k, int(cfg[k]))
     for k in ("x0", "x1", "y0", "y1", "cfl", "alpha_mix"):
         setattr(c, k, float(cfg[k]))
-    for m in range(int(cfg["n_mat"])):
+    M = int(cfg["n_mat"])
+    for m in range(M):
         c.gamma[m] = float(cfg["gamma"][m])
         c.pinf[m] = float(cfg["pinf"][m])
+        c.eos[m] = int(cfg.get("eos", [0] * M)[m])
+        c.rho0[m] = float(cfg.get("rho0", [0.0] * M)[m])
+        c.tait_B[m] = float(cfg.get("tait_B", [0.0] * M)[m])
+        c.p0[m] = float(cfg.get("p0", [0.0] * M)[m])
+    c.flux = int(cfg.get("flux", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])

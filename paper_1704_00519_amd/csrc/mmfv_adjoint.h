@@ -582,7 +582,7 @@ MMD void a_face(const Params& P, const Bufs& B, const Adj& A, const double* Q,
   DR.v = dn_seed<8>(R[2], 6);
   DR.p = dn_seed<8>(R[3], 7);
   Dn<8> G[4];
-  hllc_flux(DL, DR, P.gamma[r], pinf, P.igm1[r], G);
+  hllc_flux(DL, DR, eos_of(P, r), P.igm1[r], G);
   // face flux F in grid order from G in face order
   double Fv[4] = {G[0].v, dir == 0 ? G[1].v : G[2].v, dir == 0 ? G[2].v : G[1].v, G[3].v};
   for (int v = 0; v < 4; v++) lAF += Fv[v] * lF[v];  // (times A applied by the caller)
@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(256) k_a_iface(Params P, Bufs B, Adj A, int si
   R.v = T(0.0);
   R.p = Da.p;
   T SL, SR;
-  wave_speeds(L, P.gamma[bb], P.pinf[bb], R, P.gamma[a], P.pinf[a], SL, SR);
+  wave_speeds(L, eos_of(P, bb), R, eos_of(P, a), SL, SR);
   T SM = contact_speed(L, R, SL, SR);
   T ps = 0.5 * ((L.p + L.r * (SL - L.u) * (SM - L.u)) + (R.p + R.r * (SR - R.u) * (SM - R.u)));
   T X1 = ps * cx, X2 = ps * cy, X3 = ps * SM * nrm;
@@ -1104,7 +1104,7 @@ __global__ void __launch_bounds__(256) k_a_ext_tiles(Params P, Bufs B, Adj A, in
             bool has = (ocq[n] >> r) & 1;
             double U0 = has ? U[n][0] / 1.0 : 0.0, U1 = has ? U[n][1] / 1.0 : 0.0,
                    U2 = has ? U[n][2] / 1.0 : 0.0, U3 = has ? U[n][3] / 1.0 : 0.0;
-            Prim pw = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+            Prim pw = prim_from_U(U0, U1, U2, U3, eos_of(P, r));
             w[0] = pw.r; w[1] = pw.u; w[2] = pw.v; w[3] = pw.p;
           }
         } else {
@@ -1256,7 +1256,7 @@ __global__ void __launch_bounds__(256) k_a_real(Params P, Bufs B, Adj A, int sid
     }
     Dn<4> u0 = dn_seed<4>(U[0], 0), u1 = dn_seed<4>(U[1], 1), u2 = dn_seed<4>(U[2], 2),
           u3 = dn_seed<4>(U[3], 3);
-    PrimT<Dn<4>> w = prim_from_U(u0, u1, u2, u3, P.gamma[r], P.pinf[r]);
+    PrimT<Dn<4>> w = prim_from_U(u0, u1, u2, u3, eos_of(P, r));
     double lU[4];
     for (int q = 0; q < 4; q++)
       lU[q] = lw[0] * w.r.d[q] + lw[1] * w.u.d[q] + (D == 2 ? lw[2] * w.v.d[q] : 0.0) +

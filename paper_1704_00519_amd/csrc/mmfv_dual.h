@@ -149,6 +149,15 @@ template <int N>
 MMD Dn<N> fabs(const Dn<N>& a) {
   return a.v < 0.0 ? -a : a;
 }
+// x^e for a constant exponent: d(x^e) = e x^(e-1) dx
+template <int N>
+MMD Dn<N> pow(const Dn<N>& a, double e) {
+  Dn<N> r;
+  r.v = ::pow(a.v, e);
+  double s = e * ::pow(a.v, e - 1.0);
+  for (int i = 0; i < N; i++) r.d[i] = a.d[i] * s;
+  return r;
+}
 // the selected operand supplies the gradient (the first one on a tie)
 template <int N>
 MMD Dn<N> fmin(const Dn<N>& a, const Dn<N>& b) {

@@ -244,7 +244,7 @@ MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
     if (far) {
       double U0 = has ? a0 / 1.0 : 0.0, U1 = has ? a1 / 1.0 : 0.0, U2 = has ? a2 / 1.0 : 0.0,
              U3 = has ? a3 / 1.0 : 0.0;
-      return prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+      return prim_from_U(U0, U1, U2, U3, eos_of(P, r));
     }
     Prim w;
     w.r = a0;
@@ -259,7 +259,7 @@ MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
     double U1 = loadQ<D>(P, Qs, occs, r, 1, k) / 1.0;
     double U2 = loadQ<D>(P, Qs, occs, r, 2, k) / 1.0;
     double U3 = loadQ<D>(P, Qs, occs, r, 3, k) / 1.0;
-    return prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+    return prim_from_U(U0, U1, U2, U3, eos_of(P, r));
   }
   // buffer states are refreshed each stage within seven cells of a cut cell
   // (and in the frame); anything older is stale
@@ -805,7 +805,7 @@ MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
   double U1 = loadQ<D>(P, Q, occ, r, 1, k) / a;
   double U2 = loadQ<D>(P, Q, occ, r, 2, k) / a;
   double U3 = loadQ<D>(P, Q, occ, r, 3, k) / a;
-  Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+  Prim w = prim_from_U(U0, U1, U2, U3, eos_of(P, r));
   // pure cells are checked where they are updated; cut cells here
   if (B.cut[k] && nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
   size_t o = (size_t)r * 4 * P.NC;
@@ -987,7 +987,7 @@ MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int sta
   R.v = 0.0;
   R.p = Wa.p;
   double SL, SR;
-  wave_speeds(L, P.gamma[bb], P.pinf[bb], R, P.gamma[a], P.pinf[a], SL, SR);
+  wave_speeds(L, eos_of(P, bb), R, eos_of(P, a), SL, SR);
   double SM = contact_speed(L, R, SL, SR);
   double ps = 0.5 * ((L.p + L.r * (SL - L.u) * (SM - L.u)) +
                      (R.p + R.r * (SR - R.u) * (SM - R.u)));
@@ -1184,7 +1184,7 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
     R.r = Wc[3].r; R.u = nrm(Wc[3]); R.v = tng(Wc[3]); R.p = Wc[3].p;
   }
   double G[4];
-  hllc_flux(L, R, P.gamma[r], pinf, P.igm1[r], G);
+  hllc_flux(L, R, eos_of(P, r), P.igm1[r], G);
   F[0] = G[0];
   F[1] = dir == 0 ? G[1] : G[2];
   F[2] = dir == 0 ? G[2] : G[1];
@@ -1316,7 +1316,7 @@ MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, i
     R.r = c(3, 0); R.u = c(3, 1); R.v = c(3, 2); R.p = c(3, 3);
   }
   double Gf[4];
-  hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], Gf);
+  hllc_flux(L, R, eos_of(P, m), P.igm1[m], Gf);
   G[0] = Gf[0];
   G[1] = dir == 0 ? Gf[1] : Gf[2];
   G[2] = dir == 0 ? Gf[2] : Gf[1];
@@ -1411,7 +1411,7 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
     if (q >= WX * WY) continue;
     double r_ = U[n][0], u_ = U[n][1], v_ = U[n][2], p_ = U[n][3];
     if (ind[n]) {
-      Prim w = prim_from_U(U[n][0], U[n][1], U[n][2], U[n][3], P.gamma[ch[n]], P.pinf[ch[n]]);
+      Prim w = prim_from_U(U[n][0], U[n][1], U[n][2], U[n][3], eos_of(P, ch[n]));
       r_ = w.r; u_ = w.u; v_ = w.v; p_ = w.p;
     }
     int lx = q % WX, ly = q / WX;
@@ -1507,7 +1507,7 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
         bool has = (B.occ[sidx][kk] >> ch) & 1;
         double U0 = has ? Qs[o] / 1.0 : 0.0, U1 = has ? Qs[o + P.NC] / 1.0 : 0.0,
                U3 = has ? Qs[o + 2 * (size_t)P.NC] / 1.0 : 0.0;
-        Prim w = prim_from_U(U0, U1, 0.0, U3, P.gamma[ch], P.pinf[ch]);
+        Prim w = prim_from_U(U0, U1, 0.0, U3, eos_of(P, ch));
         r_ = w.r; u_ = w.u; p_ = w.p;
       } else {
         size_t o = (size_t)ch * 4 * P.NC + kk;
@@ -1549,7 +1549,7 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
       R.r = R0[f + 3]; R.u = U0[f + 3]; R.p = P0[f + 3];
     }
     double G[4];
-    hllc_flux(L, R, P.gamma[m], pinf, P.igm1[m], G);
+    hllc_flux(L, R, eos_of(P, m), P.igm1[m], G);
     S.F[0][f] = G[0];
     S.F[1][f] = G[1];
     S.F[2][f] = G[3];
@@ -2699,7 +2699,7 @@ __global__ void __launch_bounds__(256) k_ext_tiles(Params P, Bufs B, int sidx) {
             bool has = (ocq[n] >> r) & 1;
             double U0 = has ? U[n][0] / 1.0 : 0.0, U1 = has ? U[n][1] / 1.0 : 0.0,
                    U2 = has ? U[n][2] / 1.0 : 0.0, U3 = has ? U[n][3] / 1.0 : 0.0;
-            Prim w = prim_from_U(U0, U1, U2, U3, P.gamma[r], P.pinf[r]);
+            Prim w = prim_from_U(U0, U1, U2, U3, eos_of(P, r));
             w0 = w.r; w1 = w.u; w2 = w.v; w3 = w.p;
           }
         } else {

@@ -163,9 +163,16 @@ static bool valid_config(const mm_config* c, std::string& why) {
   if (c->n_mat < 1 || c->n_mat > MM_MAX_MAT) return why = "n_mat out of range", false;
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0)))
     return why = "empty domain", false;
-  for (int m = 0; m < c->n_mat; m++)
+  for (int m = 0; m < c->n_mat; m++) {
     if (!(c->gamma[m] > 1.0) || !(c->pinf[m] >= 0.0))
       return why = "gamma must exceed 1 and p_inf be >= 0", false;
+    if (c->eos[m] != MM_EOS_STIFFENED && c->eos[m] != MM_EOS_TAIT)
+      return why = "bad eos code", false;
+    if (c->eos[m] == MM_EOS_TAIT && !(c->rho0[m] > 0.0 && c->tait_B[m] > 0.0 &&
+                                       std::isfinite(c->p0[m]) && c->tait_B[m] - c->p0[m] >= 0.0))
+      return why = "Tait material needs rho0 > 0, B > 0 and B >= p0", false;
+  }
+  if (c->flux != MM_FLUX_HLLC) return why = "flux variant not available", false;
   for (int q = 0; q < 4; q++)
     if (c->bc[q] < 0 || c->bc[q] > 3) return why = "bad boundary code", false;
   if (c->inflow_mat < 0 || c->inflow_mat >= c->n_mat) return why = "bad inflow_mat", false;
@@ -212,7 +219,10 @@ static Params make_params(const mm_config* cfg) {
   P.cfl = cfg->cfl;
   for (int m = 0; m < P.M; m++) {
     P.gamma[m] = cfg->gamma[m];
-    P.pinf[m] = cfg->pinf[m];
+    P.tait[m] = cfg->eos[m] == MM_EOS_TAIT ? 1 : 0;
+    P.taitB[m] = cfg->tait_B[m];
+    P.rho0[m] = cfg->rho0[m];
+    P.pinf[m] = P.tait[m] ? cfg->tait_B[m] - cfg->p0[m] : cfg->pinf[m];
     P.igm1[m] = 1.0 / (cfg->gamma[m] - 1.0);
   }
   for (int q = 0; q < 4; q++) {

@@ -22,12 +22,30 @@ struct Params {
   int dim, nx, ny, NX, NY, HY, NC, M;
   double dx, dy, h, bls, idx, idy, amix;
   int kext;
+  // pinf: the p_inf of the energy relation (a Tait material's B - p0)
   double gamma[MAXM], pinf[MAXM], igm1[MAXM];
   int bc[4];
   double inflow_W[4];
   int inflow_mat;
   double cfl;
+  int tait[MAXM];                 // 1: Tait material (pressure from density)
+  double taitB[MAXM], rho0[MAXM];
 };
+
+// EOS of one material, as the point-wise functions take it
+struct Eos {
+  double g, pinf, B, rho0;
+  bool tait;
+};
+MMD Eos eos_of(const Params& P, int m) {
+  Eos e;
+  e.g = P.gamma[m];
+  e.pinf = P.pinf[m];
+  e.B = P.taitB[m];
+  e.rho0 = P.rho0[m];
+  e.tait = P.tait[m] != 0;
+  return e;
+}
 
 // ---------------------------------------------------------------------------
 // The point-wise functions below are templates on the scalar type T.  The
@@ -37,7 +55,11 @@ struct Params {
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------------------
-// Stiffened-gas EOS (Sec. 2.1): p = (gamma-1) rho e - gamma p_inf.
+// EOS (Sec. 2.1).  Stiffened gas: p = (gamma-1) rho e - gamma p_inf.  Tait
+// (water-like fluids): p = B (rho/rho0)^gamma - B + p0, a function of the
+// density alone; its energy relation is that of the stiffened gas with the
+// same gamma and p_inf = B - p0 (so rho E is defined and
+// c^2 = gamma (p + B - p0)/rho).
 // ---------------------------------------------------------------------------
 template <class T>
 struct PrimT {
@@ -46,13 +68,16 @@ struct PrimT {
 using Prim = PrimT<double>;
 
 template <class T>
-MMD PrimT<T> prim_from_U(T U0, T U1, T U2, T U3, double g, double pinf) {
+MMD PrimT<T> prim_from_U(T U0, T U1, T U2, T U3, const Eos& e) {
   PrimT<T> w;
   w.r = U0;
   w.u = U1 / U0;
   w.v = U2 / U0;
   T ke = 0.5 * w.r * (w.u * w.u + w.v * w.v);
-  w.p = (g - 1.0) * (U3 - ke) - g * pinf;
+  if (e.tait)
+    w.p = e.B * pow(U0 / e.rho0, e.g) - e.pinf;
+  else
+    w.p = (e.g - 1.0) * (U3 - ke) - e.g * e.pinf;
   return w;
 }
 
@@ -66,12 +91,15 @@ MMD T total_energy(T r, T u, T v, T p, double g, double pinf, double igm1) {
 // States are (rho, u_normal, u_tangential, p).
 // ---------------------------------------------------------------------------
 template <class T>
-MMD void wave_speeds(const PrimT<T>& L, double gL, double piL, const PrimT<T>& R,
-                     double gR, double piR, T& SL, T& SR) {
+MMD void wave_speeds(const PrimT<T>& L, const Eos& eL, const PrimT<T>& R, const Eos& eR,
+                     T& SL, T& SR) {
+  double gL = eL.g, piL = eL.pinf, gR = eR.g, piR = eR.pinf;
   T irL = 1.0 / L.r, irR = 1.0 / R.r;
   T porL = L.p * irL, porR = R.p * irR;
-  T psiL = (L.p + gL * piL) * irL, psiR = (R.p + gR * piR) * irR;
-  double upsL = gL - 1.0, upsR = gR - 1.0;
+  // Tait: Psi = dp/drho = gamma (p + B - p0)/rho, Upsilon = 0
+  T psiL = eL.tait ? gL * (L.p + piL) * irL : (L.p + gL * piL) * irL;
+  T psiR = eR.tait ? gR * (R.p + piR) * irR : (R.p + gR * piR) * irR;
+  double upsL = eL.tait ? 0.0 : gL - 1.0, upsR = eR.tait ? 0.0 : gR - 1.0;
   T cL = sqrt(psiL + upsL * porL);
   T cR = sqrt(psiR + upsR * porR);
   T sL = sqrt(L.r), sR = sqrt(R.r);
@@ -96,10 +124,10 @@ MMD T contact_speed(const PrimT<T>& L, const PrimT<T>& R, T SL, T SR) {
 // HLLC face flux inside one material: F = (mass, normal mom, tangential mom,
 // energy).
 template <class T>
-MMD void hllc_flux(const PrimT<T>& L, const PrimT<T>& R, double g, double pinf,
-                   double igm1, T F[4]) {
+MMD void hllc_flux(const PrimT<T>& L, const PrimT<T>& R, const Eos& e, double igm1, T F[4]) {
+  double g = e.g, pinf = e.pinf;
   T SL, SR;
-  wave_speeds(L, g, pinf, R, g, pinf, SL, SR);
+  wave_speeds(L, e, R, e, SL, SR);
   T SM = contact_speed(L, R, SL, SR);
   // upwind choice: F_L if S_L >= 0, else F*_L if S_M >= 0, else F*_R if
   // S_R > 0, else F_R
