@@ -135,7 +135,8 @@ mm_status mm_init_state(mm_ctx *ctx, const double *phi, const int32_t *chi,
  * mm_set_dt).  record_tape = K > 0 keeps a tape for mm_adjoint_step: a
  * checkpoint of the state every K steps and the step size of every step
  * (a new tape starts unless the previous call recorded with the same K and
- * no step has been reversed since); record_tape = 0 ends any tape.  If t_out
+ * no step has been reversed since; MM_ENOTIMPL with the Roe face flux, for
+ * which no adjoint is built); record_tape = 0 ends any tape.  If t_out
  * is not NULL it receives the time reached.  Synchronises the stream once
  * and returns MM_ENONPHYS if a non-physical real state appeared; err_cell
  * and err_step in the diagnostics name the cell and the step.  With the

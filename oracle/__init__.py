@@ -108,6 +108,7 @@ def lib(tangent=False):
         L.or_t_weno5.argtypes = [d, d, d, d, d]
         L.or_t_hllc.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_roe.argtypes = [vp, C.c_int, dp, dp, dp]
+        L.or_t_char_weno.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         L.or_t_mixing.argtypes = [vp, dp, dp, dp, ip, dp]
@@ -175,6 +176,13 @@ class Oracle:
         self._L.or_t_roe(self._h, int(m), np.ascontiguousarray(WL, float),
                          np.ascontiguousarray(WR, float), F)
         return F
+
+    def char_weno(self, m, Wc):
+        """Characteristic-wise WENO5 face states from the six stencil states
+        (rows: cells i-2 .. i+3; columns rho, u_n, u_t, p)."""
+        WL, WR = np.zeros(4), np.zeros(4)
+        self._L.or_t_char_weno(self._h, int(m), np.ascontiguousarray(Wc, float).ravel(), WL, WR)
+        return WL, WR
 
     def iface(self, mL, WL, mR, WR):
         out = np.zeros(4)

@@ -1747,6 +1747,20 @@ void or_t_roe(St *s, int m, const double *WL, const double *WR, double *F) {
   for (int v = 0; v < 4; v++) F[v] = RV(G[v]);
 }
 
+/* Characteristic-wise WENO5 states at a face from six stencil states
+ * Wc[q] = (rho, u_n, u_t, p), q = 0..5 (cells i-2 .. i+3 of face i+1/2). */
+void or_t_char_weno(St *s, int m, const double *Wc, double *WL, double *WR) {
+  real W6[6][4], L[4], R[4];
+  int perm[4] = {0, 1, 2, 3};
+  for (int q = 0; q < 6; q++)
+    for (int v = 0; v < 4; v++) W6[q][v] = Wc[q * 4 + v];
+  char_weno(s, m, W6, perm, L, R);
+  for (int v = 0; v < 4; v++) {
+    WL[v] = RV(L[v]);
+    WR[v] = RV(R[v]);
+  }
+}
+
 /* Interface Riemann problem between material mL (left state) and mR (right
  * state), states (rho, un, ut, p); out = (S_L, S_R, S_M, p*). */
 void or_t_iface(const St *s, int mL, const double *WLd, int mR, const double *WRd,

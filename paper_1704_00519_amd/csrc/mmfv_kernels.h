@@ -1166,6 +1166,23 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
   Prim L, R;
   auto nrm = [&](const Prim& w) { return dir == 0 ? w.u : w.v; };
   auto tng = [&](const Prim& w) { return dir == 0 ? w.v : w.u; };
+  if (P.flux == FLUX_ROE) {
+    Prim Ws[6];
+    for (int q = 0; q < 6; q++) {
+      Ws[q].r = Wc[q].r;
+      Ws[q].u = nrm(Wc[q]);
+      Ws[q].v = D == 2 ? tng(Wc[q]) : 0.0;
+      Ws[q].p = Wc[q].p;
+    }
+    double G[4];
+    bool good = roe_face(Ws, ok, eos_of(P, r), P.igm1[r], G);
+    wave_count(&B.ctr[C_POSFIX], count && !good ? 1 : 0);
+    F[0] = G[0];
+    F[1] = dir == 0 ? G[1] : G[2];
+    F[2] = dir == 0 ? G[2] : G[1];
+    F[3] = G[3];
+    return;
+  }
   if (ok) {
     L.r = weno5(Wc[0].r, Wc[1].r, Wc[2].r, Wc[3].r, Wc[4].r);
     L.u = weno5(nrm(Wc[0]), nrm(Wc[1]), nrm(Wc[2]), nrm(Wc[3]), nrm(Wc[4]));
@@ -1280,7 +1297,7 @@ struct BulkTile {
 // flux across face (fi, fj) of the tile in direction dir (0: the left face of
 // tile cell (fi, fj), 1: its bottom face), rotated back to (rho, x, y, E)
 // momentum order; false when neither cell of the face is a bulk cell
-template <int BX, int BY>
+template <int BX, int BY, int FLUX>
 MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, int dir,
                    int fi, int fj, double G[4]) {
   // the two cells of the face in tile coordinates: (fi-1, fj) | (fi, fj)
@@ -1300,6 +1317,22 @@ MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, i
     int comp = v == 1 ? vn : v == 2 ? vt : v;
     return sm.W[comp][by + q * sy][bx + q * sx];
   };
+  if (FLUX == FLUX_ROE) {
+    Prim Ws[6];
+    for (int q = 0; q < 6; q++) {
+      Ws[q].r = c(q, 0);
+      Ws[q].u = c(q, 1);
+      Ws[q].v = c(q, 2);
+      Ws[q].p = c(q, 3);
+    }
+    double Gf[4];
+    if (!roe_face(Ws, true, eos_of(P, m), P.igm1[m], Gf)) atomicAdd(&B.ctr[C_POSFIX], 1ull);
+    G[0] = Gf[0];
+    G[1] = dir == 0 ? Gf[1] : Gf[2];
+    G[2] = dir == 0 ? Gf[2] : Gf[1];
+    G[3] = Gf[3];
+    return true;
+  }
   double pinf = P.pinf[m];
   Prim L, R;
   L.r = weno5(c(0, 0), c(1, 0), c(2, 0), c(3, 0), c(4, 0));
@@ -1336,7 +1369,7 @@ constexpr int BULK_BX = 28, BULK_BY = 16, BULK_NT = 512;
 constexpr int BULK_BYW = 32, BULK_NTW = 1024;
 constexpr int BULK_WIDE_TILES_PER_CU = 6;
 
-template <int BX, int BY, int NT>
+template <int BX, int BY, int NT, int FLUX>
 __global__ void __launch_bounds__(NT)
 k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
              double ccoef, int stage0) {
@@ -1432,7 +1465,7 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
 #pragma unroll 1
   for (int f = tid; f < NFX; f += NT) {
     double G[4];
-    if (bulk_face<BX, BY>(P, B, sm, 0, f % (BX + 1), f / (BX + 1), G))
+    if (bulk_face<BX, BY, FLUX>(P, B, sm, 0, f % (BX + 1), f / (BX + 1), G))
       for (int v = 0; v < 4; v++) sm.F[v][f] = G[v];
   }
   __syncthreads();
@@ -1446,7 +1479,7 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
 #pragma unroll 1
   for (int f = tid; f < NFY; f += NT) {
     double G[4];
-    if (bulk_face<BX, BY>(P, B, sm, 1, f % BX, f / BX, G))
+    if (bulk_face<BX, BY, FLUX>(P, B, sm, 1, f % BX, f / BX, G))
       for (int v = 0; v < 4; v++) sm.F[v][f] = G[v];
   }
   __syncthreads();
@@ -1534,6 +1567,21 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
     const double* R0 = S.W[0];
     const double* U0 = S.W[1];
     const double* P0 = S.W[2];
+    if (P.flux == FLUX_ROE) {
+      Prim Ws[6];
+      for (int q = 0; q < 6; q++) {
+        Ws[q].r = R0[f + q];
+        Ws[q].u = U0[f + q];
+        Ws[q].v = 0.0;
+        Ws[q].p = P0[f + q];
+      }
+      double G[4];
+      if (!roe_face(Ws, true, eos_of(P, m), P.igm1[m], G)) atomicAdd(&B.ctr[C_POSFIX], 1ull);
+      S.F[0][f] = G[0];
+      S.F[1][f] = G[1];
+      S.F[2][f] = G[3];
+      continue;
+    }
     Prim L, R;
     L.r = weno5(R0[f], R0[f + 1], R0[f + 2], R0[f + 3], R0[f + 4]);
     L.u = weno5(U0[f], U0[f + 1], U0[f + 2], U0[f + 3], U0[f + 4]);

@@ -172,7 +172,10 @@ static bool valid_config(const mm_config* c, std::string& why) {
                                        std::isfinite(c->p0[m]) && c->tait_B[m] - c->p0[m] >= 0.0))
       return why = "Tait material needs rho0 > 0, B > 0 and B >= p0", false;
   }
-  if (c->flux != MM_FLUX_HLLC) return why = "flux variant not available", false;
+  if (c->flux != MM_FLUX_HLLC && c->flux != MM_FLUX_ROE) return why = "bad flux code", false;
+  if (c->flux == MM_FLUX_ROE)
+    for (int m = 0; m < c->n_mat; m++)
+      if (c->eos[m] == MM_EOS_TAIT) return why = "the Roe flux takes stiffened gases only", false;
   for (int q = 0; q < 4; q++)
     if (c->bc[q] < 0 || c->bc[q] > 3) return why = "bad boundary code", false;
   if (c->inflow_mat < 0 || c->inflow_mat >= c->n_mat) return why = "bad inflow_mat", false;
@@ -225,6 +228,7 @@ static Params make_params(const mm_config* cfg) {
     P.pinf[m] = P.tait[m] ? cfg->tait_B[m] - cfg->p0[m] : cfg->pinf[m];
     P.igm1[m] = 1.0 / (cfg->gamma[m] - 1.0);
   }
+  P.flux = cfg->flux == MM_FLUX_ROE ? FLUX_ROE : FLUX_HLLC;
   for (int q = 0; q < 4; q++) {
     P.bc[q] = cfg->bc[q];
     P.inflow_W[q] = cfg->inflow_W[q];
@@ -462,13 +466,19 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
     LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
   }
   prof_mark(c);
-  if (D == 2)
+  if (D == 2 && P.flux == FLUX_ROE)
+    // the characteristic projection needs more registers than the 1024-thread
+    // tile leaves a thread: the 512-thread tile at any grid size
+    LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT, FLUX_ROE>),
+           dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BY - 1) / BULK_BY),
+           dim3(BULK_NT), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
+  else if (D == 2)
     if (c->bulk_wide)
-      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BYW, BULK_NTW>),
+      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BYW, BULK_NTW, FLUX_HLLC>),
              dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BYW - 1) / BULK_BYW),
              dim3(BULK_NTW), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
     else
-      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT>),
+      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT, FLUX_HLLC>),
              dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BY - 1) / BULK_BY),
              dim3(BULK_NT), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
   else
@@ -720,6 +730,8 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
   if (!c->ready) return fail(c, MM_ESTATE, "mm_step before mm_init_state");
   if (n_steps < 0) return fail(c, MM_EINVAL, "n_steps < 0");
   if (record_tape < 0) return fail(c, MM_EINVAL, "record_tape < 0");
+  if (record_tape > 0 && c->P.flux != FLUX_HLLC)
+    return fail(c, MM_ENOTIMPL, "the adjoint is built for the HLLC face flux only");
   if (record_tape > 0) return step_record(c, n_steps, record_tape, t_out);
   c->tape_K = 0;  // plain steps end any tape
   c->tape_n = c->tape_rev = 0;

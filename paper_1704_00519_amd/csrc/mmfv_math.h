@@ -30,7 +30,9 @@ struct Params {
   double cfl;
   int tait[MAXM];                 // 1: Tait material (pressure from density)
   double taitB[MAXM], rho0[MAXM];
+  int flux;                       // FLUX_HLLC or FLUX_ROE
 };
+enum { FLUX_HLLC = 0, FLUX_ROE = 1 };
 
 // EOS of one material, as the point-wise functions take it
 struct Eos {
@@ -155,6 +157,166 @@ MMD void hllc_flux(const PrimT<T>& L, const PrimT<T>& R, const Eos& e, double ig
     F[2] = F[2] + Sk * (Us2 - r * v);
     F[3] = F[3] + Sk * (Us3 - E);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Roe flux with characteristic-wise WENO5 (the second face-flux variant,
+// stiffened gases only).  Same expressions, in the same order, as the CPU
+// reference, so both round alike.
+// ---------------------------------------------------------------------------
+// conserved (rho, rho u_n, rho u_t, rho E) of a primitive state
+template <class T>
+MMD void roe_cons(const PrimT<T>& w, const Eos& e, double igm1, T U[4]) {
+  U[0] = w.r;
+  U[1] = w.r * w.u;
+  U[2] = w.r * w.v;
+  U[3] = total_energy(w.r, w.u, w.v, w.p, e.g, e.pinf, igm1);
+}
+// Roe average of two states: normal and tangential velocity, enthalpy and
+// sound speed, c^2 = (gamma-1)(H - |u|^2/2)
+template <class T>
+MMD void roe_average(const PrimT<T>& L, const PrimT<T>& R, const Eos& e, double igm1, T& u,
+                     T& v, T& Hr, T& c) {
+  T sL = sqrt(L.r), sR = sqrt(R.r);
+  T iw = 1.0 / (sL + sR);
+  T HL = (total_energy(L.r, L.u, L.v, L.p, e.g, e.pinf, igm1) + L.p) / L.r;
+  T HR = (total_energy(R.r, R.u, R.v, R.p, e.g, e.pinf, igm1) + R.p) / R.r;
+  u = (sL * L.u + sR * R.u) * iw;
+  v = (sL * L.v + sR * R.v) * iw;
+  Hr = (sL * HL + sR * HR) * iw;
+  c = sqrt((e.g - 1.0) * (Hr - 0.5 * (u * u + v * v)));
+}
+// left (Lm[k][.]) and right (Rm[.][k]) eigenvectors of the normal flux
+// Jacobian: eigenvalues u - c, u, u (shear), u + c
+template <class T>
+MMD void roe_eig(double g, T u, T v, T Hr, T c, T Lm[4][4], T Rm[4][4]) {
+  T q2 = 0.5 * (u * u + v * v);
+  T b1 = (g - 1.0) / (c * c), b2 = q2 * b1;
+  Rm[0][0] = 1.0; Rm[1][0] = u - c; Rm[2][0] = v; Rm[3][0] = Hr - u * c;
+  Rm[0][1] = 1.0; Rm[1][1] = u;     Rm[2][1] = v; Rm[3][1] = q2;
+  Rm[0][2] = 0.0; Rm[1][2] = 0.0;   Rm[2][2] = 1.0; Rm[3][2] = v;
+  Rm[0][3] = 1.0; Rm[1][3] = u + c; Rm[2][3] = v; Rm[3][3] = Hr + u * c;
+  Lm[0][0] = 0.5 * (b2 + u / c); Lm[0][1] = -0.5 * (b1 * u + 1.0 / c);
+  Lm[0][2] = -0.5 * (b1 * v); Lm[0][3] = 0.5 * b1;
+  Lm[1][0] = 1.0 - b2; Lm[1][1] = b1 * u; Lm[1][2] = b1 * v; Lm[1][3] = -b1;
+  Lm[2][0] = -v; Lm[2][1] = 0.0; Lm[2][2] = 1.0; Lm[2][3] = 0.0;
+  Lm[3][0] = 0.5 * (b2 - u / c); Lm[3][1] = -0.5 * (b1 * u - 1.0 / c);
+  Lm[3][2] = -0.5 * (b1 * v); Lm[3][3] = 0.5 * b1;
+}
+template <class T>
+MMD void roe_mv(const T A[4][4], const T x[4], T y[4]) {
+  for (int k = 0; k < 4; k++) y[k] = ((A[k][0] * x[0] + A[k][1] * x[1]) + A[k][2] * x[2]) + A[k][3] * x[3];
+}
+// normal flux and pressure of a conserved state
+template <class T>
+MMD void roe_phys(const T U[4], const Eos& e, T F[4], T& p) {
+  T rho = U[0], un = U[1] / rho, ut = U[2] / rho;
+  p = (e.g - 1.0) * (U[3] - 0.5 * rho * (un * un + ut * ut)) - e.g * e.pinf;
+  F[0] = U[1];
+  F[1] = U[1] * un + p;
+  F[2] = U[1] * ut;
+  F[3] = un * (U[3] + p);
+}
+// u_n -+ c of a conserved state; ok = false if it is not physical
+template <class T>
+MMD T roe_acoustic(const T U[4], const Eos& e, int sign, bool& ok) {
+  T rho = U[0];
+  T un = U[1] / rho, ut = U[2] / rho;
+  T p = (e.g - 1.0) * (U[3] - 0.5 * rho * (un * un + ut * ut)) - e.g * e.pinf;
+  ok = rho > 0.0 && p + e.pinf > 0.0;
+  if (!ok) return T(0.0);
+  T c = sqrt(e.g * (p + e.pinf) / rho);
+  return sign < 0 ? un - c : un + c;
+}
+// Roe flux with the Harten-Hyman entropy fix on the acoustic fields (the
+// speeds on either side of each acoustic wave of the linearised solution)
+template <class T>
+MMD void roe_flux(const PrimT<T>& WL, const PrimT<T>& WR, const Eos& e, double igm1, T G[4]) {
+  T UL[4], UR[4], FL[4], FR[4], pL, pR;
+  roe_cons(WL, e, igm1, UL);
+  roe_cons(WR, e, igm1, UR);
+  roe_phys(UL, e, FL, pL);
+  roe_phys(UR, e, FR, pR);
+  T u, v, Hr, c, Lm[4][4], Rm[4][4];
+  roe_average(WL, WR, e, igm1, u, v, Hr, c);
+  roe_eig(e.g, u, v, Hr, c, Lm, Rm);
+  T dU[4], a[4];
+  for (int k = 0; k < 4; k++) dU[k] = UR[k] - UL[k];
+  roe_mv(Lm, dU, a);
+  T lam[4] = {u - c, u, u, u + c};
+  T Ua[4], Ub[4];
+  for (int q = 0; q < 4; q++) {
+    Ua[q] = UL[q] + a[0] * Rm[q][0];
+    Ub[q] = UR[q] - a[3] * Rm[q][3];
+  }
+  for (int k = 0; k < 4; k++) {
+    T l = fabs(lam[k]);
+    if (k == 0 || k == 3) {
+      bool oka, okb;
+      T la = k == 0 ? roe_acoustic(UL, e, -1, oka) : roe_acoustic(Ub, e, 1, oka);
+      T lb = k == 0 ? roe_acoustic(Ua, e, -1, okb) : roe_acoustic(UR, e, 1, okb);
+      if (oka && okb) {
+        T d1 = lam[k] - la, d2 = lb - lam[k];
+        T delta = d1 > d2 ? d1 : d2;
+        if (delta > 0.0 && l < delta) l = (lam[k] * lam[k] + delta * delta) / (2.0 * delta);
+      }
+    }
+    a[k] = l * a[k];
+  }
+  for (int q = 0; q < 4; q++) {
+    T d = ((Rm[q][0] * a[0] + Rm[q][1] * a[1]) + Rm[q][2] * a[2]) + Rm[q][3] * a[3];
+    G[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * d;
+  }
+}
+
+template <class T>
+MMD T weno5(T v1, T v2, T v3, T v4, T v5);
+
+// characteristic-wise WENO5 at a face from the six stencil states (face
+// normal first): returns the primitive states on both sides
+template <class T>
+MMD void char_weno(const PrimT<T> Ws[6], const Eos& e, double igm1, PrimT<T>& WL,
+                   PrimT<T>& WR) {
+  T U[6][4], w[6][4];
+  for (int q = 0; q < 6; q++) roe_cons(Ws[q], e, igm1, U[q]);
+  T u, v, Hr, c, Lm[4][4], Rm[4][4];
+  roe_average(Ws[2], Ws[3], e, igm1, u, v, Hr, c);
+  roe_eig(e.g, u, v, Hr, c, Lm, Rm);
+  for (int q = 0; q < 6; q++) roe_mv(Lm, U[q], w[q]);
+  T cl[4], cr[4], UL[4], UR[4];
+  for (int k = 0; k < 4; k++) {
+    cl[k] = weno5(w[0][k], w[1][k], w[2][k], w[3][k], w[4][k]);
+    cr[k] = weno5(w[5][k], w[4][k], w[3][k], w[2][k], w[1][k]);
+  }
+  roe_mv(Rm, cl, UL);
+  roe_mv(Rm, cr, UR);
+  T pL, pR, F[4];
+  roe_phys(UL, e, F, pL);
+  roe_phys(UR, e, F, pR);
+  WL.r = UL[0]; WL.u = UL[1] / UL[0]; WL.v = UL[2] / UL[0]; WL.p = pL;
+  WR.r = UR[0]; WR.u = UR[1] / UR[0]; WR.v = UR[2] / UR[0]; WR.p = pR;
+}
+
+// face flux of the Roe variant from the six stencil states (face-normal
+// order, cells i-2 .. i+3 of face i+1/2); all_ok: every stencil cell holds a
+// state.  A reconstructed state that is not physical (or a stencil cell
+// without a state) falls back to the first-order states of the two face
+// cells; the return value is false then.
+template <class T>
+MMD bool roe_face(const PrimT<T> Ws[6], bool all_ok, const Eos& e, double igm1, T G[4]) {
+  PrimT<T> L, R;
+  bool ok = all_ok;
+  if (ok) {
+    char_weno(Ws, e, igm1, L, R);
+    if (!(L.r > 0.0) || !(R.r > 0.0) || !(L.p + e.pinf > 0.0) || !(R.p + e.pinf > 0.0))
+      ok = false;
+  }
+  if (!ok) {
+    L = Ws[2];
+    R = Ws[3];
+  }
+  roe_flux(L, R, e, igm1, G);
+  return ok;
 }
 
 // ---------------------------------------------------------------------------
