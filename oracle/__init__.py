@@ -54,7 +54,7 @@ class Config(C.Structure):
                 ("k_ext", C.c_int32), ("band_ls", C.c_int32),
                 ("eos", C.c_int32 * MAXM), ("rho0", C.c_double * MAXM),
                 ("tait_B", C.c_double * MAXM), ("p0", C.c_double * MAXM),
-                ("flux", C.c_int32)]
+                ("flux", C.c_int32), ("scale_sep", C.c_int32)]
 
 
 def make_config(cfg):
@@ -72,6 +72,7 @@ def make_config(cfg):
         c.tait_B[m] = float(cfg.get("tait_B", [0.0] * cfg["n_mat"])[m])
         c.p0[m] = float(cfg.get("p0", [0.0] * cfg["n_mat"])[m])
     c.flux = int(cfg.get("flux", 0))
+    c.scale_sep = int(cfg.get("scale_sep", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])
@@ -258,7 +259,7 @@ class Oracle:
         return cx, cy
 
     def diag(self):
-        out = np.zeros(N_DIAG_HEAD + 2 * self.M * 4)
+        out = np.zeros(N_DIAG_HEAD + 3 * self.M * 4 + 3)
         self._L.or_diag(self._h, out)
         M = self.M
         head = out[:N_DIAG_HEAD]
@@ -267,7 +268,10 @@ class Oracle:
                     n_ifskip=int(head[5]), n_stranded=int(head[6]),
                     n_mixsrc=int(head[7]), n_updates=int(head[8]),
                     bnd=out[9:9 + 4 * M].reshape(M, 4),
-                    xsum=out[9 + 4 * M:9 + 8 * M].reshape(M, 4))
+                    xsum=out[9 + 4 * M:9 + 8 * M].reshape(M, 4),
+                    n_absorb=int(out[9 + 8 * M]), n_relabel=int(out[10 + 8 * M]),
+                    n_oddball=int(out[11 + 8 * M]),
+                    xfer=out[12 + 8 * M:12 + 12 * M].reshape(M, 4))
 
     def set_state(self, Q, phi, chi):
         """Replace (Q, phi, chi); the geometry is rebuilt from the level set

@@ -68,6 +68,9 @@ typedef struct {
   int32_t eos[OR_MAXM];
   double rho0[OR_MAXM], tait_B[OR_MAXM], p0[OR_MAXM];
   int32_t flux;
+  /* 1: the interface scale-separation model after every time step
+     (Sec. 2.3.3) */
+  int32_t scale_sep;
 } or_config;
 
 typedef struct {
@@ -107,8 +110,17 @@ typedef struct {
   real dt;         /* step size; its derivative is always zero (frozen) */
   long nstep;
   long n_posfix, n_fluxskip, n_ifskip, n_stranded, n_mixsrc, n_upd;
+  long n_absorb, n_relabel, n_oddball;
+  /* stranded mixing sources of a stage: cell, material and receiving
+     material, in the order found; cells relabelled and their new material */
+  int *abk, *abr, *rlk, *rlto;
+  long nab, nrl;
   real bnd[OR_MAXM][OR_NV], bnd_c[OR_MAXM][OR_NV];
   real xsum[OR_MAXM][OR_NV], xsum_c[OR_MAXM][OR_NV];
+  /* conserved quantities moved between materials of one cell (stranded
+     sources, scale separation): received minus given, per material */
+  real xfer[OR_MAXM][OR_NV], xfer_c[OR_MAXM][OR_NV];
+  double xw;       /* weight in the full step of a change to the stage state */
   int err_code;
   long err_cell;
 } St;
@@ -1294,10 +1306,26 @@ static void levelset_stage(St *s, double b, double c) {
  * eligible target the 8-neighbour (2-neighbour in 1D) of largest alpha >=
  * alpha_mix and chi = r takes the whole exchange (ties: lower linear index); without one
  * the cell is left as it is and counted. */
+/* The conserved quantities of material r in cell k join those of material
+ * to, book-kept in xfer with the weight xw that a change of the current
+ * stage's state carries into the end of the step (the product of the later
+ * stages' coefficients of the previous stage in the beta form: 1/6, 2/3, 1
+ * for the three stages of RK3; 1 after the step). */
+static void move_q(St *s, int k, int r, int to) {
+  for (int v = 0; v < 4; v++) {
+    real q = M4(s, s->Q, r, v, k);
+    M4(s, s->Q, to, v, k) = M4(s, s->Q, to, v, k) + q;
+    M4(s, s->Q, r, v, k) = 0.0;
+    neumaier(&s->xfer[to][v], &s->xfer_c[to][v], s->xw * q);
+    neumaier(&s->xfer[r][v], &s->xfer_c[r][v], -(s->xw * q));
+  }
+}
+
 static void mixing(St *s) {
   int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
   double amix = s->c.alpha_mix;
   size_t nc = s->NC;
+  s->nab = s->nrl = 0;
   for (int r = 0; r < s->M; r++) {
     int *T = s->mixT;
     real *Mx = s->mixM;
@@ -1355,7 +1383,34 @@ static void mixing(St *s) {
               if (at >= amix && s->chit[t] == r && at > bestA) { bestA = at; bt = t; }
             }
           if (bt < 0) {
-            s->n_stranded++;
+            /* Reading (stranded source): no neighbour of material r can
+               take the exchange.  If r is the cell's own material (a
+               fragment of r too small to be resolved, with no resolved part
+               of r next to it), the cell is given to the other material of
+               largest volume fraction in it (ties: lower index), the
+               indicator swap of the scale-separation model (Sec. 2.3.3).
+               After the exchanges, the conserved quantities of every
+               stranded source join those of the cell's material as it is
+               after these swaps (a source of that material itself stays).
+               Total mass, momentum and energy stay conserved; the masses
+               of the single materials do not. */
+            if (s->chit[k] == r) {
+              real ba = 0.0;
+              int to = -1;
+              for (int m = 0; m < s->M; m++)
+                if (m != r && M1(s, s->al, m, k) > ba) {
+                  ba = M1(s, s->al, m, k);
+                  to = m;
+                }
+              if (to >= 0) {
+                s->rlk[s->nrl] = k;
+                s->rlto[s->nrl] = to;
+                s->nrl++;
+              }
+            }
+            s->abk[s->nab] = k;
+            s->abr[s->nab] = r;
+            s->nab++;
             continue;
           }
           tk[0] = bt;
@@ -1423,6 +1478,136 @@ static void mixing(St *s) {
         }
       }
   }
+  /* stranded sources join the material of their cell after the swaps, in
+     the order found (material, then row-major cell) */
+  for (long a = 0; a < s->nab; a++) {
+    int k = s->abk[a], r = s->abr[a], to = s->chit[k];
+    for (long b = 0; b < s->nrl; b++)
+      if (s->rlk[b] == k) to = s->rlto[b];
+    if (to == r) {
+      s->n_stranded++;
+      continue;
+    }
+    move_q(s, k, r, to);
+    s->n_absorb++;
+  }
+  s->n_relabel += s->nrl;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interface scale separation (Sec. 2.3.3)                                  */
+/* ------------------------------------------------------------------------ */
+/* Does cell k hold part of the contour phi^r = off?  Reading: the contour
+ * crosses the cell when the local level set of r at its centre and its four
+ * corners (each the mean of the four cells around it) is <= off somewhere
+ * and > off somewhere else. */
+static int crosses(const St *s, const real *phi, const int *chi, int r, int k, double off) {
+  int NX = s->NX, two = s->c.dim == 2;
+  real c = lsv(phi, chi, r, k) - off;
+  real mn = c, mx = c;
+  for (int cj = 0; cj < 1 + two; cj++)
+    for (int ci = 0; ci < 2; ci++) {
+      int k0 = k + (ci ? 0 : -1) + (two ? (cj ? 0 : -NX) : 0);
+      real v;
+      if (two)
+        v = (lsv(phi, chi, r, k0) + lsv(phi, chi, r, k0 + 1) + lsv(phi, chi, r, k0 + NX) +
+             lsv(phi, chi, r, k0 + NX + 1)) * 0.25 - off;
+      else
+        v = (lsv(phi, chi, r, k0) + lsv(phi, chi, r, k0 + 1)) * 0.5 - off;
+      if (v < mn) mn = v;
+      if (v > mx) mx = v;
+    }
+  return mn <= 0.0 && mx > 0.0;
+}
+
+/* After a time step: with eps = 0.75 h, S_-^r (S_+^r) are the cells crossed
+ * by the contour phi^r = eps (= -eps), the boundary of material r shrunk
+ * (grown) by eps.  An oddball cell is a cut cell whose own material chi_1
+ * has no cell of S_-^chi_1 in its 3 x 3 block: the material is thinner than
+ * 2 eps there.  It is given to the other material chi_1* of largest volume
+ * fraction, and its distance becomes |d_min - eps|, d_min the distance from
+ * its centre to the eps-grown boundary of chi_1*, found from the cells of
+ * S_+^chi_1* within 3 cells (the point of the contour along the normal at
+ * their centres); without such a cell the distance is kept.
+ * Readings: (1) the new topology must be resolved: chi_1* itself needs a
+ * cell of S_-^chi_1* in the 3 x 3 block, else the cell is left as it is (in
+ * mixing layers where both materials are thinner than 2 eps the criterion
+ * otherwise flags the cells of both in turn and swaps them back and forth,
+ * step after step); (2) the conserved quantities of chi_1 in the cell join
+ * those of chi_1* (the paper does not say how they move; totals are
+ * conserved); (3) the distance is capped at the band width.
+ * Every decision reads the fields before any swap.  The geometry and the
+ * volume-fraction correction are then evaluated again. */
+static void scale_separation(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2, M = s->M;
+  double eps = 0.75 * s->h;
+  size_t nc = s->NC;
+  unsigned char *sm = s->xs, *sp = s->band2;
+  int *newchi = s->co;
+  real *newphi = s->cv;
+  memcpy(newchi, s->chi, nc * sizeof(int));
+  memcpy(newphi, s->phi, nc * sizeof(real));
+  memset(sm, 0, nc);
+  memset(sp, 0, nc);
+  for (int j = -two; j < ny + two; j++)
+    for (int i = -1; i <= nx; i++) {
+      int k = ID(s, i, j);
+      for (int r = 0; r < M; r++) {
+        if (crosses(s, s->phi, s->chi, r, k, eps)) sm[k] |= (unsigned char)(1u << r);
+        if (crosses(s, s->phi, s->chi, r, k, -eps)) sp[k] |= (unsigned char)(1u << r);
+      }
+    }
+  int any = 0;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j), c1 = s->chi[k];
+      if (!(M1(s, s->al, c1, k) < 1.0)) continue;
+      unsigned near = 0;
+      for (int dj = -two; dj <= two; dj++)
+        for (int di = -1; di <= 1; di++) near |= sm[ID(s, i + di, j + dj)];
+      if (near >> c1 & 1) continue;
+      int c2 = -1;
+      real ba = 0.0;
+      for (int r = 0; r < M; r++)
+        if (r != c1 && M1(s, s->al, r, k) > ba) {
+          ba = M1(s, s->al, r, k);
+          c2 = r;
+        }
+      if (c2 < 0 || !(near >> c2 & 1)) continue;
+      s->n_oddball++;
+      any = 1;
+      real dmin = -1.0;
+      for (int dj = -3 * two; dj <= 3 * two; dj++)
+        for (int di = -3; di <= 3; di++) {
+          int ii = i + di, jj = j + dj;
+          if (ii < -1 || ii > nx || (two && (jj < -1 || jj > ny))) continue;
+          int k0 = ID(s, ii, jj);
+          if (!(sp[k0] >> c2 & 1)) continue;
+          real gx = lsv(s->phi, s->chi, c2, k0 + 1) - lsv(s->phi, s->chi, c2, k0 - 1);
+          real gy = two ? lsv(s->phi, s->chi, c2, k0 + s->NX) - lsv(s->phi, s->chi, c2, k0 - s->NX)
+                        : 0.0;
+          real gn = sqrt(gx * gx + gy * gy);
+          if (!(gn > 0.0)) continue;
+          real f = lsv(s->phi, s->chi, c2, k0) + eps;
+          real ex = di * s->dx - f * (gx / gn), ey = dj * s->dy - f * (gy / gn);
+          real d = sqrt(ex * ex + ey * ey);
+          if (dmin < 0.0 || d < dmin) dmin = d;
+        }
+      newchi[k] = c2;
+      if (dmin >= 0.0) {
+        real a = fabs(dmin - eps);
+        newphi[k] = a < s->bls ? a : (real)s->bls;
+      }
+      move_q(s, k, c1, c2);
+    }
+  if (!any) return;
+  memcpy(s->chi, newchi, nc * sizeof(int));
+  memcpy(s->phi, newphi, nc * sizeof(real));
+  fill_ls(s, s->phi, s->chi);
+  geometry(s, s->phi, s->chi);
+  for (int r = 0; r < M; r++)
+    for (size_t k = 0; k < nc; k++) M1(s, s->mass, r, k) = M4(s, s->Q, r, 0, k);
+  vf_correction(s, s->chi, s->mass);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1438,7 +1623,8 @@ void or_destroy(St *s) {
   void *p[] = {s->phi, s->phin, s->phit, s->chi, s->chin, s->chit, s->Q,
                s->Qn, s->Qt, s->al, s->ax, s->ay, s->cx, s->cy, s->W, s->lw,
                s->Wv, s->lok, s->band, s->band2, s->list, s->vok, s->reg, s->lv, s->X, s->vx, s->vy, s->Fx, s->Fy,
-               s->mass, s->cv, s->co, s->xs, s->mixM, s->mixT};
+               s->mass, s->cv, s->co, s->xs, s->mixM, s->mixT, s->abk, s->abr,
+               s->rlk, s->rlto};
   for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); i++) free(p[i]);
   free(s);
 }
@@ -1494,6 +1680,8 @@ St *or_create(const or_config *c) {
   s->cv = (real *)zalloc(nc * R); s->co = (int *)zalloc(nc * 4);
   s->xs = (unsigned char *)zalloc(nc);
   s->mixM = (real *)zalloc(3 * 4 * nc * R); s->mixT = (int *)zalloc(3 * nc * 4);
+  s->abk = (int *)zalloc(M * nc * 4); s->abr = (int *)zalloc(M * nc * 4);
+  s->rlk = (int *)zalloc(nc * 4); s->rlto = (int *)zalloc(nc * 4);
   for (int v = 0; v < 4; v++) s->inflow[v] = c->inflow_W[v];
   if (!s->mixT || !s->mixM || !s->Q) {
     or_destroy(s);
@@ -1565,6 +1753,8 @@ static int init_impl(St *s, const double *phi, const int32_t *chi, const double 
   memset(s->bnd_c, 0, sizeof(s->bnd_c));
   memset(s->xsum, 0, sizeof(s->xsum));
   memset(s->xsum_c, 0, sizeof(s->xsum_c));
+  memset(s->xfer, 0, sizeof(s->xfer));
+  memset(s->xfer_c, 0, sizeof(s->xfer_c));
   return s->err_code;
 }
 
@@ -1644,12 +1834,27 @@ int or_step(St *s, int nsteps) {
         for (size_t k = 0; k < (size_t)s->NC; k++)
           M1(s, s->mass, r, k) = M4(s, s->Qt, r, 0, k);
       vf_correction(s, s->chit, s->mass);
+      s->xw = 1.0;
+      for (int later = st + 1; later < ns; later++) s->xw *= c[later];
       mixing(s);
+      if (s->nrl) {
+        /* relabelled cells: geometry and correction of the new indicator
+           field, the correction ordered by the masses after mixing */
+        for (long a = 0; a < s->nrl; a++) s->chit[s->rlk[a]] = s->rlto[a];
+        fill_ls(s, s->phit, s->chit);
+        geometry(s, s->phit, s->chit);
+        for (int r = 0; r < s->M; r++)
+          for (size_t k = 0; k < (size_t)s->NC; k++)
+            M1(s, s->mass, r, k) = M4(s, s->Q, r, 0, k);
+        vf_correction(s, s->chit, s->mass);
+      }
       real *tp = s->phi; s->phi = s->phit; s->phit = tp;
       int *tc = s->chi; s->chi = s->chit; s->chit = tc;
     }
     s->t += RV(s->dt);
     s->nstep++;
+    s->xw = 1.0;
+    if (s->c.scale_sep) scale_separation(s);
   }
   return OR_OK;
 }
@@ -1713,6 +1918,11 @@ int or_diag(const St *s, double *out) {
       out[9 + r * 4 + v] = RV(s->bnd[r][v] + s->bnd_c[r][v]);
       out[9 + s->M * 4 + r * 4 + v] = RV(s->xsum[r][v] + s->xsum_c[r][v]);
     }
+  for (int r = 0; r < s->M; r++)
+    for (int v = 0; v < 4; v++) out[12 + 8 * s->M + r * 4 + v] = RV(s->xfer[r][v] + s->xfer_c[r][v]);
+  out[9 + 8 * s->M] = (double)s->n_absorb;
+  out[10 + 8 * s->M] = (double)s->n_relabel;
+  out[11 + 8 * s->M] = (double)s->n_oddball;
   return OR_OK;
 }
 

@@ -16,7 +16,10 @@ recomputed with the oracle's formulas.  The readings pinned are:
   according to the averaged values"), and target t receives the fraction
   beta_t of that exchange; without an eligible x/y/diagonal target the
   8-neighbour of largest alpha (ties: lower linear index) takes all; a
-  vanishing source hands over all of its state, exactly;
+  vanishing source hands over all of its state, exactly; a source with no
+  eligible neighbour at all (stranded) joins the cell's own material, or, if
+  it is the cell's own material, the material of largest other alpha, to
+  which the cell is then relabelled;
 * extension: Jacobi sweeps from the upwind neighbours along increasing
   phi^r weighted by |g_x|, |g_y|, a value once set is kept, then sweeps of
   the mean of the valid neighbours; the band reaches 4 cells;
@@ -81,7 +84,7 @@ class MixCase:
         if Q is not None:
             self.Q[0, :, j, i] = Q
 
-    def run(self):
+    def run(self, full=False):
         self.al[1] = np.where(self.al[0] > 0.0, 0.0, 1.0)
         self.al[1][self.chi == 1] = 1.0 - self.al[0][self.chi == 1]
         self.Q[1] = 0.0
@@ -90,6 +93,9 @@ class MixCase:
         d0 = self.o.diag()
         out = self.o.mix(self.Q, self.al, self.phi, self.chi)
         d1 = self.o.diag()
+        self.absorbed = d1["n_absorb"] - d0["n_absorb"]
+        if full:
+            return out, d1["n_mixsrc"] - d0["n_mixsrc"], d1["n_stranded"] - d0["n_stranded"]
         # material 1 never mixes here
         assert np.array_equal(out[1], self.Q[1])
         return out[0], d1["n_mixsrc"] - d0["n_mixsrc"], d1["n_stranded"] - d0["n_stranded"]
@@ -209,17 +215,53 @@ def test_mixing_fallback_largest_neighbour_lowest_index():
     assert np.array_equal(out[:, 1, 1], Qc)
 
 
-def test_mixing_stranded_source_is_left_and_counted():
-    """No neighbour of material 0 at all: the source keeps its state and is
-    counted as stranded."""
+def test_mixing_stranded_source_joins_the_cells_material():
+    """No neighbour of material 0 at all, in a cell of material 1: the
+    source's conserved quantities are added to material 1's in the same cell
+    (exactly), material 0 is left empty there, nothing else changes, and the
+    source is counted as absorbed, not stranded."""
     c = MixCase()
     Qs = np.array([0.1, 0.05, 0.0, 0.3])
     c.cell(2, 2, 1, 0.5, 0.1, Qs)
     c.cell(3, 2, 1, 0.2, 0.0)
     c.cell(1, 2, 1, 0.4, 0.0)
-    out, nsrc, nstr = c.run()
-    assert (nsrc, nstr) == (1, 1)
-    assert np.array_equal(out, c.Q[0])
+    out, nsrc, nstr = c.run(full=True)
+    assert (nsrc, nstr, c.absorbed) == (1, 0, 1)
+    assert np.array_equal(out[0], np.zeros_like(out[0]))
+    # material 1 of the cell: alpha 0.9 of (1, 0, 0, 2.5) plus Q_s
+    assert np.array_equal(out[1, :, 2, 2], np.array([0.9 + 0.1, 0.05, 0.0, 2.25 + 0.3]))
+    keep = np.ones((c.ny, c.nx), bool)
+    keep[2, 2] = False
+    assert np.array_equal(out[1][:, keep], c.Q[1][:, keep])
+
+
+def test_mixing_stranded_own_material_goes_to_largest_other():
+    """Three materials; cell (2,2) belongs to material 0, which fills only
+    0.3 of it, with no other cell of material 0 around (a fragment): its
+    state joins material 2 (alpha 0.45), not material 1 (alpha 0.25), in the
+    cell, and the cell is counted as relabelled (the indicator itself changes
+    in the step, see test_stranded_fragment_is_relabelled_in_a_step)."""
+    nx = ny = 5
+    o = oracle.Oracle(cfg2(nx, ny, M=3))
+    phi = np.ones((ny, nx))
+    chi = np.ones((ny, nx), np.int32)
+    al = np.zeros((3, ny, nx))
+    al[1] = 1.0
+    al[:, 2, 2] = (0.3, 0.25, 0.45)
+    chi[2, 2] = 0
+    phi[2, 2] = 0.05
+    Q = np.zeros((3, 4, ny, nx))
+    for m in range(3):
+        Q[m, 0] = al[m] * (1.0 + m)
+        Q[m, 3] = al[m] * (2.0 + m)
+    d0 = o.diag()
+    out = o.mix(Q, al, phi, chi)
+    d1 = o.diag()
+    assert d1["n_relabel"] - d0["n_relabel"] == 1
+    assert d1["n_absorb"] - d0["n_absorb"] == 1
+    assert np.array_equal(out[0, :, 2, 2], np.zeros(4))
+    assert np.array_equal(out[2, :, 2, 2], Q[2, :, 2, 2] + Q[0, :, 2, 2])
+    assert np.array_equal(out[1], Q[1])
 
 
 def test_mixing_vanishing_source_hands_over_exactly():
