@@ -77,6 +77,13 @@ typedef struct {
   int32_t flux;                  /* MM_FLUX_HLLC (0): component-wise WENO5 + */
                                  /* HLLC; MM_FLUX_ROE (1): characteristic-  */
                                  /* wise WENO5 + Roe                        */
+  /* 1: the interface scale-separation model (Sec. 2.3.3) after every time
+   * step.  Oddball cells, cut cells whose material has no cell crossed by
+   * its contour shifted 0.75 h inwards within their 3 x 3 block, go to the
+   * other material of largest volume fraction when that one is resolved in
+   * the block; their distance is re-assigned from the outward-shifted
+   * contour of the new material and their conserved quantities join it. */
+  int32_t scale_sep;
 } mm_config;
 enum { MM_EOS_STIFFENED = 0, MM_EOS_TAIT = 1 };
 enum { MM_FLUX_HLLC = 0, MM_FLUX_ROE = 1 };
@@ -89,6 +96,7 @@ typedef struct {
   int64_t n_fluxskip;      /* faces with A > 0 whose cells had no state     */
   int64_t n_ifskip;        /* interfaces skipped for lack of a ghost state  */
   int64_t n_stranded;      /* mixing sources without an eligible target     */
+                           /* left in place (no other material to join)    */
   int64_t n_mixsrc;        /* mixing sources processed                      */
   int64_t n_updates;       /* active material-cell RK-substep updates       */
   int64_t err_cell;        /* j*nx+i of the lowest non-physical real cell   */
@@ -111,6 +119,14 @@ typedef struct {
   /* Step (counted from 1 since mm_init_state) in which the non-physical
    * state of err_cell was found, -1 if none. */
   int64_t err_step;
+  /* Mixing sources without an eligible target whose conserved quantities
+   * joined another material of their cell (Sec. 2.3.2 mixing; a fragment of
+   * the cell's own material first gives the cell to the material of largest
+   * other volume fraction: n_relabel), and oddball cells of the scale
+   * separation, since mm_init_state.  Where these act, totals are conserved
+   * but the masses of single materials are not, and sum_Q - bnd_in - exch
+   * differs from its initial value by the quantities moved. */
+  int64_t n_absorb, n_relabel, n_oddball;
 } mm_diag;
 
 typedef struct mm_ctx mm_ctx;

@@ -44,7 +44,7 @@ class MMConfig(C.Structure):
                 ("k_ext", C.c_int32), ("band_ls", C.c_int32),
                 ("eos", C.c_int32 * MAX_MAT), ("rho0", C.c_double * MAX_MAT),
                 ("tait_B", C.c_double * MAX_MAT), ("p0", C.c_double * MAX_MAT),
-                ("flux", C.c_int32)]
+                ("flux", C.c_int32), ("scale_sep", C.c_int32)]
 
 
 class MMDiag(C.Structure):
@@ -56,7 +56,8 @@ class MMDiag(C.Structure):
                 ("sum_Q", (C.c_double * 4) * 8), ("bnd_in", (C.c_double * 4) * 8),
                 ("exch", (C.c_double * 4) * 8),
                 ("n_band", C.c_int64), ("n_ghost", C.c_int64), ("n_tiles", C.c_int64),
-                ("err_step", C.c_int64)]
+                ("err_step", C.c_int64), ("n_absorb", C.c_int64),
+                ("n_relabel", C.c_int64), ("n_oddball", C.c_int64)]
 
 
 _DIAG_ARRAYS = ("sum_Q", "bnd_in", "exch")
@@ -154,6 +155,7 @@ def make_config(cfg):
         c.tait_B[m] = float(cfg.get("tait_B", [0.0] * M)[m])
         c.p0[m] = float(cfg.get("p0", [0.0] * M)[m])
     c.flux = int(cfg.get("flux", 0))
+    c.scale_sep = int(cfg.get("scale_sep", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])

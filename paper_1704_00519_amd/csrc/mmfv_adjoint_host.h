@@ -355,6 +355,10 @@ extern "C" mm_status mm_adjoint_step(mm_ctx* c, const double* lamQ_in, const dou
   if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
   if (c->tape_K <= 0 || c->tape_rev <= 0)
     return fail(c, MM_ESTATE, "no recorded step left to reverse");
+  if (c->tape_moved)
+    return fail(c, MM_ENOTIMPL,
+                "a recorded step moved conserved quantities between materials (stranded "
+                "mixing sources or scale separation); the adjoint does not cover it");
   mm_status st = adj_alloc(c);
   if (st != MM_OK) return st;
   const Params& P = c->P;

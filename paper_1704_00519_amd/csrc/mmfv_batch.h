@@ -72,6 +72,9 @@ static size_t layout_bufs(const Params& P, Bufs& B, char* base) {
   take(B.vx, nc); take(B.vy, nc); take(B.vit, nc);
   take(B.mixM, M * 3 * 4 * nc); take(B.mixT, M * 3 * nc);
   take(B.srcStamp, M * nc); take(B.tgtStamp, M * nc);
+  take(B.strStamp, M * nc); take(B.abMark, nc); take(B.rlStamp, nc);
+  take(B.rlTo, nc); take(B.ssTo, nc); take(B.abList, nc); take(B.ssList, nc);
+  take(B.ssPhi, nc);
   take(B.tiles, 1);
   take(B.blist, 1);
   B.glist = nullptr;  // the batched kernel sweeps cells, not a queue
@@ -455,6 +458,9 @@ extern "C" mm_status mm_batch_get_diagnostics(mm_batch* b, mm_diag* out) {
     d.n_fluxskip = (int64_t)c[C_FLUXSKIP];
     d.n_ifskip = (int64_t)c[C_IFSKIP];
     d.n_stranded = (int64_t)c[C_STRANDED];
+    d.n_absorb = (int64_t)c[C_ABSORB];
+    d.n_relabel = (int64_t)c[C_RELABEL];
+    d.n_oddball = (int64_t)c[C_ODDBALL];
     d.n_mixsrc = (int64_t)c[C_MIXSRC];
     d.n_updates = (int64_t)c[C_UPD];
     d.err_cell = c[C_ERR] == NO_ERR ? -1 : (int64_t)c[C_ERR];

@@ -40,6 +40,14 @@ struct Bufs {
   unsigned long long* ctr; // smax bits, error cell, counters
   const double* dts;       // step-size schedule (replayed while position < length)
   double* dtpart;          // per-workgroup maxima of the wave speeds (step size)
+  // stranded mixing sources of the stage (stamp per material and cell), the
+  // cells holding one (list and listing stamp), relabelled cells (stamp and
+  // new material); scale separation: oddball cells and their new material
+  // and distance
+  uint32_t *strStamp, *abMark, *rlStamp;
+  uint8_t *rlTo, *ssTo;
+  int32_t *abList, *ssList;
+  double* ssPhi;
 };
 
 enum { S_DT = 0, S_LX, S_LY, S_LV, S_DTFIX, S_T, S_SPOS, S_SN };
@@ -77,7 +85,13 @@ enum { C_SMAX = 0, C_ERR, C_POSFIX, C_FLUXSKIP, C_IFSKIP, C_STRANDED, C_MIXSRC,
        C_STEPNO, C_ERRSTEP,
        // cells of an initial state given in device memory with chi outside
        // [0, n_mat) or phi negative or not a number
-       C_BADIN, C_N };
+       C_BADIN,
+       // conserved quantities moved between the materials of a cell (stranded
+       // mixing sources), cells relabelled, oddball cells of the scale
+       // separation; list lengths of the current stage / step; stamps of the
+       // last stage with a relabelled cell and of the last step with an
+       // oddball cell (the geometry is evaluated again when they match)
+       C_ABSORB, C_RELABEL, C_ODDBALL, C_NAB, C_NSS, C_RLSTAMP, C_SSSTAMP, C_N };
 constexpr unsigned long long NO_ERR = ~0ull;
 // book-keeping regions of MAXM x 4 doubles each: accumulated net boundary
 // inflow and its compensation, accumulated exchange and its compensation,
@@ -440,8 +454,14 @@ MMD void b_classify(const Params& P, const Bufs& B, int i, int j) {
   B.rowc[k] = (uint8_t)(c ? 1 : 0);
   B.rowl[k] = (uint8_t)((c || B.phi[k] < P.bls) ? 1 : 0);
 }
+// gate >= 0: run only if counter gate holds the current stage's stamp (the
+// classification and geometry evaluated again after cells changed material)
+MMD bool gated_off(const Bufs& B, int gate) {
+  return gate >= 0 && B.ctr[gate] != B.ctr[C_STAMP];
+}
 template <int D>
-__global__ void k_classify(Params P, Bufs B) {
+__global__ void k_classify(Params P, Bufs B, int gate) {
+  if (gated_off(B, gate)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i == 0 && j == 0) B.ctr[C_NTILES] = 0;  // the tile list is rebuilt next
@@ -469,7 +489,8 @@ MMD void b_dist_row(const Params& P, const Bufs& B, int i, int j) {
   (D == 1 ? B.dls : B.tdl)[k] = (uint8_t)dl;
 }
 template <int D>
-__global__ void k_dist_row(Params P, Bufs B) {
+__global__ void k_dist_row(Params P, Bufs B, int gate) {
+  if (gated_off(B, gate)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= P.nx || j >= P.ny) return;
@@ -488,7 +509,8 @@ struct ClassDistSmem {
   unsigned long long mrow[2][CY + 2 * CF];  // the flags of a frame row as bits
 };
 static_assert(CX + 2 * CF <= 64, "a frame row fits one 64-bit mask");
-__global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B) {
+__global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B, int gate) {
+  if (gated_off(B, gate)) return;
   __shared__ ClassDistSmem S;
   constexpr int HX = CX + 2 * CF + 2, HY = CY + 2 * CF + 2;
   constexpr int FX = CX + 2 * CF, FY = CY + 2 * CF;
@@ -1798,7 +1820,29 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
           }
         }
       if (bt < 0) {
-        wave_count(&B.ctr[C_STRANDED], 1);
+        // stranded: marked for the absorb pass (after every material's
+        // exchanges); a fragment of the cell's own material also decides
+        // the cell's new material, the other of largest volume fraction
+        B.strStamp[(size_t)r * P.NC + k] = stamp;
+        if (chk == r) {
+          double ba = 0.0;
+          int to = -1;
+          for (int m = 0; m < P.M; m++) {
+            double am = alpha_u(P, B, m, k);
+            if (m != r && am > ba) {
+              ba = am;
+              to = m;
+            }
+          }
+          if (to >= 0) {
+            B.rlTo[k] = (uint8_t)to;
+            B.rlStamp[k] = stamp;
+          }
+        }
+        if (B.abList && atomicExch(&B.abMark[k], stamp) != stamp) {
+          unsigned long long at = atomicAdd(&B.ctr[C_NAB], 1ull);
+          B.abList[at] = k;
+        }
         continue;
       }
       tn[0] = bt;
@@ -1838,6 +1882,173 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   }
 }
 
+// Stranded mixing sources of cell k (after every material's exchanges): the
+// cell takes the new material decided by a stranded fragment of its own
+// material, then each stranded material's conserved quantities join the
+// cell's material (a stranded source of that material itself stays), in
+// material order.  Returns whether the cell was relabelled.
+template <int D>
+MMD bool b_absorb(const Params& P, const Bufs& B, int k, int didx, uint32_t stamp) {
+  double* Q = B.Q[didx];
+  uint8_t* occp = B.occ[didx];
+  bool rel = B.rlStamp[k] == stamp;
+  int to = rel ? (int)B.rlTo[k] : (int)B.chi[k];
+  unsigned occ = occp[k];
+  for (int r = 0; r < P.M; r++) {
+    if (B.strStamp[(size_t)r * P.NC + k] != stamp) continue;
+    if (r == to) {
+      atomicAdd(&B.ctr[C_STRANDED], 1ull);
+      continue;
+    }
+    bool nz = false;
+    for (int v = 0; v < 4; v++) {
+      if (D == 1 && v == 2) continue;
+      double q = loadQ<D>(P, Q, (const uint8_t*)occp, r, v, k);
+      double t = loadQ<D>(P, Q, (const uint8_t*)occp, to, v, k);
+      double n = t + q;
+      storeQ<D>(P, Q, to, v, k, n);
+      storeQ<D>(P, Q, r, v, k, 0.0);
+      if (n != 0.0) nz = true;
+    }
+    // occupancy read by loadQ above: update it only after both loads
+    occ &= ~(1u << r);
+    if (nz) occ |= 1u << to;
+    occp[k] = (uint8_t)occ;
+    atomicAdd(&B.ctr[C_ABSORB], 1ull);
+  }
+  if (rel) {
+    B.chi[k] = (uint8_t)to;
+    atomicAdd(&B.ctr[C_RELABEL], 1ull);
+  }
+  return rel;
+}
+
+// y sides of the level-set frame: columns i in [-H, nx+H), frame cell t
+MMD void b_bc_ls_y(const Params& P, int t, double* phi, uint8_t* chi) {
+  int i = t / (2 * H) - H, q = t % (2 * H);
+  int j, sj;
+  if (q < H) {
+    j = -1 - q;
+    sj = src_lo(j, P.bc[2]);
+  } else {
+    j = P.ny + (q - H);
+    sj = src_hi(j, P.ny, P.bc[3]);
+  }
+  int k = cid(P, i, j), ks = cid(P, i, sj);
+  phi[k] = phi[ks];
+  chi[k] = chi[ks];
+}
+
+// ---------------------------------------------------------------------------
+// Interface scale separation (Sec. 2.3.3), after every time step when
+// enabled: oddball cells (cut cells whose material has no cell crossed by its
+// eps-inner contour, eps = 0.75 h, in the 3 x 3 block) go to the other
+// material of largest volume fraction, provided that one is resolved there
+// (has such a cell in the block); their distance becomes |d_min - eps| with
+// d_min the distance to the eps-grown boundary of the new material, found
+// from the crossed cells within 3 cells; conserved quantities follow.
+// ---------------------------------------------------------------------------
+// does the contour phi^r = off cross cell (i, j)?  Centre and four corners
+// (means of the four cells around each corner) on both sides of off
+template <int D>
+MMD bool crosses(const Params& P, const Bufs& B, int r, int i, int j, double off) {
+  double c = lsv(B.phi, B.chi, r, cid(P, i, j)) - off;
+  double mn = c, mx = c;
+  for (int cj = 0; cj < (D == 2 ? 2 : 1); cj++)
+    for (int ci = 0; ci < 2; ci++) {
+      int x0 = i - 1 + ci, y0 = D == 2 ? j - 1 + cj : 0;
+      double v;
+      if (D == 2)
+        v = (lsv(B.phi, B.chi, r, cid(P, x0, y0)) + lsv(B.phi, B.chi, r, cid(P, x0 + 1, y0)) +
+             lsv(B.phi, B.chi, r, cid(P, x0, y0 + 1)) +
+             lsv(B.phi, B.chi, r, cid(P, x0 + 1, y0 + 1))) * 0.25 - off;
+      else
+        v = (lsv(B.phi, B.chi, r, cid(P, x0, 0)) + lsv(B.phi, B.chi, r, cid(P, x0 + 1, 0))) * 0.5 - off;
+      if (v < mn) mn = v;
+      if (v > mx) mx = v;
+    }
+  return mn <= 0.0 && mx > 0.0;
+}
+template <int D>
+MMD bool resolved_near(const Params& P, const Bufs& B, int r, int i, int j, double eps) {
+  for (int dj = -(D == 2); dj <= (D == 2); dj++)
+    for (int di = -1; di <= 1; di++)
+      if (crosses<D>(P, B, r, i + di, j + dj, eps)) return true;
+  return false;
+}
+// oddball test of cell (i, j); an oddball cell is listed with its new
+// material and distance (the fields themselves change only in k_ss_apply)
+template <int D>
+MMD void b_ss_detect(const Params& P, const Bufs& B, int i, int j) {
+  int k = cid(P, i, j);
+  int c1 = B.chi[k];
+  if (!(alpha_u(P, B, c1, k) < 1.0)) return;
+  double eps = 0.75 * P.h;
+  if (resolved_near<D>(P, B, c1, i, j, eps)) return;
+  int c2 = -1;
+  double ba = 0.0;
+  for (int r = 0; r < P.M; r++) {
+    double a = alpha_u(P, B, r, k);
+    if (r != c1 && a > ba) {
+      ba = a;
+      c2 = r;
+    }
+  }
+  if (c2 < 0 || !resolved_near<D>(P, B, c2, i, j, eps)) return;
+  double dmin = -1.0;
+  int R = D == 2 ? 3 : 0;
+  for (int dj = -R; dj <= R; dj++)
+    for (int di = -3; di <= 3; di++) {
+      int ii = i + di, jj = j + dj;
+      if (ii < -1 || ii > P.nx || (D == 2 && (jj < -1 || jj > P.ny))) continue;
+      if (!crosses<D>(P, B, c2, ii, jj, -eps)) continue;
+      int k0 = cid(P, ii, jj);
+      double gx = lsv(B.phi, B.chi, c2, cid(P, ii + 1, jj)) - lsv(B.phi, B.chi, c2, cid(P, ii - 1, jj));
+      double gy = D == 2 ? lsv(B.phi, B.chi, c2, cid(P, ii, jj + 1)) -
+                               lsv(B.phi, B.chi, c2, cid(P, ii, jj - 1))
+                         : 0.0;
+      double gn = sqrt(gx * gx + gy * gy);
+      if (!(gn > 0.0)) continue;
+      double f = lsv(B.phi, B.chi, c2, k0) + eps;
+      double ex = di * P.dx - f * (gx / gn), ey = dj * P.dy - f * (gy / gn);
+      double d = sqrt(ex * ex + ey * ey);
+      if (dmin < 0.0 || d < dmin) dmin = d;
+    }
+  double np = B.phi[k];
+  if (dmin >= 0.0) {
+    double a = fabs(dmin - eps);
+    np = a < P.bls ? a : P.bls;
+  }
+  B.ssTo[k] = (uint8_t)c2;
+  B.ssPhi[k] = np;
+  unsigned long long at = atomicAdd(&B.ctr[C_NSS], 1ull);
+  B.ssList[at] = k;
+  atomicAdd(&B.ctr[C_ODDBALL], 1ull);
+}
+// an oddball cell takes its new material and distance; the conserved
+// quantities of its old material join the new one
+template <int D>
+MMD void b_ss_apply(const Params& P, const Bufs& B, int k, int didx) {
+  double* Q = B.Q[didx];
+  uint8_t* occp = B.occ[didx];
+  int c1 = B.chi[k], c2 = B.ssTo[k];
+  unsigned occ = occp[k];
+  bool nz = false;
+  for (int v = 0; v < 4; v++) {
+    if (D == 1 && v == 2) continue;
+    double q = loadQ<D>(P, Q, (const uint8_t*)occp, c1, v, k);
+    double t = loadQ<D>(P, Q, (const uint8_t*)occp, c2, v, k);
+    double n = t + q;
+    storeQ<D>(P, Q, c2, v, k, n);
+    storeQ<D>(P, Q, c1, v, k, 0.0);
+    if (n != 0.0) nz = true;
+  }
+  occ &= ~(1u << c1);
+  if (nz) occ |= 1u << c2;
+  occp[k] = (uint8_t)occ;
+  B.chi[k] = (uint8_t)c2;
+  B.phi[k] = B.ssPhi[k];
+}
 template <int D>
 // materials r0 <= r < r1 of cell (i, j); with word_occ the occupancy bits
 // are set and cleared by atomics on the aligned 32-bit word that holds the
@@ -2320,7 +2531,8 @@ __global__ void __launch_bounds__(256) k_tiles(Params P, Bufs B, int didx, int n
 template <int D>
 __global__ void __launch_bounds__(256) k_tiles_geom(Params P, Bufs B, int didx, int nidx,
                                                     int nt, int nb, double* save_Q,
-                                                    uint8_t* save_occ) {
+                                                    uint8_t* save_occ, int gate) {
+  if (gated_off(B, gate)) return;
   int b = blockIdx.x;
   if (b < nb) {
     for (int t = b; t < nt; t += nb) tile_flag(P, B, didx, nidx, t, (int)threadIdx.x, (int)blockDim.x);
@@ -2648,6 +2860,52 @@ __global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx, CopyLi
   int r = blockIdx.y;
   for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st, r, r + 1, true); });
 }
+// The stage's stranded sources, listed by the mixing (one workgroup): when a
+// cell was relabelled the level-set frame is filled again and the stage's
+// stamp recorded, so that the classification and geometry launched next run
+// again (with the masses after mixing); the list is emptied for the next
+// stage.
+template <int D>
+__global__ void __launch_bounds__(256) k_absorb(Params P, Bufs B, int didx) {
+  int n = (int)B.ctr[C_NAB];
+  if (n == 0) return;
+  uint32_t st = (uint32_t)B.ctr[C_STAMP];
+  bool rel = false;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) rel |= b_absorb<D>(P, B, B.abList[e], didx, st);
+  if (__syncthreads_or(rel)) {
+    for (int t = threadIdx.x; t < P.ny * 2 * H; t += blockDim.x) b_bc_ls_x(P, t, B.phi, B.chi);
+    __syncthreads();
+    if (D == 2)
+      for (int t = threadIdx.x; t < (P.nx + 2 * H) * 2 * H; t += blockDim.x)
+        b_bc_ls_y(P, t, B.phi, B.chi);
+    if (threadIdx.x == 0) B.ctr[C_RLSTAMP] = st;
+  }
+  if (threadIdx.x == 0) B.ctr[C_NAB] = 0;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) t_ss_detect(Params P, Bufs B) {
+  for_tiles(P, B, [&](int i, int j) { b_ss_detect<D>(P, B, i, j); });
+}
+// the step's oddball cells (one workgroup), then the level-set frame and
+// the stamp that runs the classification and geometry launched next
+template <int D>
+__global__ void __launch_bounds__(256) k_ss_apply(Params P, Bufs B, int didx) {
+  int n = (int)B.ctr[C_NSS];
+  if (n == 0) return;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) b_ss_apply<D>(P, B, B.ssList[e], didx);
+  __syncthreads();
+  for (int t = threadIdx.x; t < P.ny * 2 * H; t += blockDim.x) b_bc_ls_x(P, t, B.phi, B.chi);
+  __syncthreads();
+  if (D == 2)
+    for (int t = threadIdx.x; t < (P.nx + 2 * H) * 2 * H; t += blockDim.x)
+      b_bc_ls_y(P, t, B.phi, B.chi);
+  if (threadIdx.x == 0) {
+    B.ctr[C_SSSTAMP] = B.ctr[C_STAMP];
+    B.ctr[C_NSS] = 0;
+  }
+}
+
 // All ghost-extension sweeps of one material on one active 16 x 16 tile in
 // one launch (2D).  A sweep reaches one cell further, so the tile and a frame
 // of EXR >= k_ext + 4 cells determine the tile's ghost states exactly: the
@@ -2983,8 +3241,39 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       PHASE(b_geom<1>(P, B, i_, 0, didx, (const double*)nullptr));
       PHASE(b_mix1<1>(P, B, i_, 0, didx, stamp, 0, P.M));
       PHASE(b_mix2<1>(P, B, i_, 0, didx, stamp, 0, P.M, false));
+      {
+        // stranded sources; a relabelled cell: frame, classification and
+        // geometry once more (masses after mixing)
+        int nab = (int)B.ctr[C_NAB];
+        bool rel = false;
+        for (int e = tid; e < nab; e += T) rel |= b_absorb<1>(P, B, B.abList[e], didx, stamp);
+        if (__syncthreads_or(rel)) {
+          for (int t = tid; t < 2 * H; t += T) b_bc_ls_x(P, t, B.phi, B.chi);
+          __syncthreads();
+          PHASE(b_classify<1>(P, B, i_, 0));
+          PHASE(b_dist_row<1>(P, B, i_, 0));
+          PHASE(b_geom<1>(P, B, i_, 0, didx, (const double*)nullptr));
+        }
+        if (tid == 0) B.ctr[C_NAB] = 0;
+        __syncthreads();
+      }
       stamp++;
       sidx = didx;
+    }
+    if (P.scale_sep) {
+      PHASE(b_ss_detect<1>(P, B, i_, 0));
+      int nss = (int)B.ctr[C_NSS];
+      for (int e = tid; e < nss; e += T) b_ss_apply<1>(P, B, B.ssList[e], 0);
+      __syncthreads();
+      if (nss > 0) {
+        for (int t = tid; t < 2 * H; t += T) b_bc_ls_x(P, t, B.phi, B.chi);
+        __syncthreads();
+        PHASE(b_classify<1>(P, B, i_, 0));
+        PHASE(b_dist_row<1>(P, B, i_, 0));
+        PHASE(b_geom<1>(P, B, i_, 0, 0, (const double*)nullptr));
+      }
+      if (tid == 0) B.ctr[C_NSS] = 0;
+      __syncthreads();
     }
     if (tid == 0) {
       B.scal[S_T] += B.scal[S_DT];

@@ -46,6 +46,9 @@ struct mm_ctx {
   // tape of recorded steps for the adjoint: a checkpoint every tape_K steps
   // and the step size of every step; tape_rev steps are still to reverse
   int tape_K = 0;
+  // a recorded step moved conserved quantities between materials (stranded
+  // mixing sources, scale separation): the tape cannot be reversed
+  bool tape_moved = false;
   int64_t tape_n = 0, tape_rev = 0;
   std::vector<char*> ckpt;
   double* tape_dt = nullptr;
@@ -173,6 +176,7 @@ static bool valid_config(const mm_config* c, std::string& why) {
       return why = "Tait material needs rho0 > 0, B > 0 and B >= p0", false;
   }
   if (c->flux != MM_FLUX_HLLC && c->flux != MM_FLUX_ROE) return why = "bad flux code", false;
+  if (c->scale_sep != 0 && c->scale_sep != 1) return why = "scale_sep must be 0 or 1", false;
   if (c->flux == MM_FLUX_ROE)
     for (int m = 0; m < c->n_mat; m++)
       if (c->eos[m] == MM_EOS_TAIT) return why = "the Roe flux takes stiffened gases only", false;
@@ -229,6 +233,7 @@ static Params make_params(const mm_config* cfg) {
     P.igm1[m] = 1.0 / (cfg->gamma[m] - 1.0);
   }
   P.flux = cfg->flux == MM_FLUX_ROE ? FLUX_ROE : FLUX_HLLC;
+  P.scale_sep = cfg->scale_sep;
   for (int q = 0; q < 4; q++) {
     P.bc[q] = cfg->bc[q];
     P.inflow_W[q] = cfg->inflow_W[q];
@@ -283,6 +288,8 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.vx, nc); A(B.vy, nc); A(B.vit, nc);
   A(B.mixM, M * 3 * 4 * nc); A(B.mixT, M * 3 * nc);
   A(B.srcStamp, M * nc); A(B.tgtStamp, M * nc);
+  A(B.strStamp, M * nc); A(B.abMark, nc); A(B.rlStamp, nc);
+  A(B.rlTo, nc); A(B.ssTo, nc); A(B.abList, nc); A(B.ssList, nc); A(B.ssPhi, nc);
   A(B.tiles, (size_t)((P.nx + 15) / 16 + 16) * ((P.ny + 15) / 16 + 1));
   A(B.blist, nc);
   A(B.glist, M * nc);
@@ -396,15 +403,16 @@ static void bc_ls(mm_ctx* c) {
            c->B.chi);
 }
 
+// gate >= 0: the launches run only when counter gate holds the stage's stamp
 template <int D>
-static void classify(mm_ctx* c) {
+static void classify(mm_ctx* c, int gate = -1) {
   const Params& P = c->P;
   if (D == 2) {
     LAUNCH(k_classify_dist2, dim3((P.nx + CX - 1) / CX, (P.ny + CY - 1) / CY), dim3(256), P,
-           c->B);
+           c->B, gate);
   } else {
-    LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B);
-    LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B);
+    LAUNCH(k_classify<D>, cell_grid(c), cell_block(c), P, c->B, gate);
+    LAUNCH(k_dist_row<D>, cell_grid(c), cell_block(c), P, c->B, gate);
   }
 }
 
@@ -519,9 +527,29 @@ static void stage_levelset(mm_ctx* c, int didx, int nidx, double w, bool advance
   // with save_Q, Q* and its occupancy are copied by extra workgroups
   int nb = nt;  // one workgroup per tile and part (measured faster than fewer, longer ones)
   LAUNCH(k_tiles_geom<D>, dim3(2 * nb + (save_Q ? 512 : 0)), tb, P, c->B, didx, nidx, nt, nb,
-         save_Q, save_occ);
+         save_Q, save_occ, -1);
   LAUNCH(t_mix1<D>, dim3(tg.x, P.M), tb, P, c->B, didx);
   LAUNCH(t_mix2<D>, dim3(tg.x, P.M, post.n ? 2 : 1), tb, P, c->B, didx, post);
+  // stranded sources; where a cell was relabelled, classification and
+  // geometry once more (these launches return at once otherwise)
+  LAUNCH(k_absorb<D>, dim3(1), tb, P, c->B, didx);
+  classify<D>(c, C_RLSTAMP);
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nb), tb, P, c->B, didx, nidx, nt, nb, (double*)nullptr,
+         (uint8_t*)nullptr, (int)C_RLSTAMP);
+}
+
+// scale separation after a step: oddball cells of the listed tiles, their
+// swap, then classification and geometry once more if there was one
+template <int D>
+static void scale_separation(mm_ctx* c) {
+  const Params& P = c->P;
+  dim3 tg = tile_grid(c), tb(256);
+  int nt = n_tiles(P);
+  LAUNCH(t_ss_detect<D>, tg, tb, P, c->B);
+  LAUNCH(k_ss_apply<D>, dim3(1), tb, P, c->B, 0);
+  classify<D>(c, C_SSSTAMP);
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nt), tb, P, c->B, 0, 0, nt, nt, (double*)nullptr,
+         (uint8_t*)nullptr, (int)C_SSSTAMP);
 }
 
 // pre / post: copies run by extra workgroups of the stage's first and last
@@ -563,6 +591,7 @@ static void one_step(mm_ctx* c) {
   for (int s = 0; s < ns; s++)
     stage<D>(c, s, stage_src(s), 0, stage_dst(s, ns), b[s], cc[s], w[s], nullptr, nullptr,
              s == ns - 1);
+  if (c->P.scale_sep) scale_separation<D>(c);
 }
 
 static mm_status stage_inputs(mm_ctx* c, size_t bytes, const void* src, int ptr_kind,
@@ -616,6 +645,15 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
   HIP_OK(c, hipMemsetAsync(c->B.scal, 0, 8 * sizeof(double), c->stream));
   HIP_OK(c, hipMemsetAsync(c->B.cons, 0, CONS_N * sizeof(double), c->stream));
   for (int b = 0; b < 3; b++) HIP_OK(c, hipMemsetAsync(c->B.occ[b], 0, P.NC, c->stream));
+  // stamps start again from 1: no mark of an earlier run may match
+  {
+    size_t nc = P.NC, M = P.M;
+    HIP_OK(c, hipMemsetAsync(c->B.srcStamp, 0, M * nc * 4, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->B.tgtStamp, 0, M * nc * 4, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->B.strStamp, 0, M * nc * 4, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->B.abMark, 0, nc * 4, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->B.rlStamp, 0, nc * 4, c->stream));
+  }
   dim3 g = cell_grid(c), bl = cell_block(c);
   LAUNCH(k_load_ls, g, bl, P, c->B, dphi, dchi);
   if (c->D == 2) {
@@ -826,6 +864,9 @@ extern "C" mm_status mm_get_diagnostics(mm_ctx* c, mm_diag* out) {
   out->n_fluxskip = (int64_t)ctr[C_FLUXSKIP];
   out->n_ifskip = (int64_t)ctr[C_IFSKIP];
   out->n_stranded = (int64_t)ctr[C_STRANDED];
+  out->n_absorb = (int64_t)ctr[C_ABSORB];
+  out->n_relabel = (int64_t)ctr[C_RELABEL];
+  out->n_oddball = (int64_t)ctr[C_ODDBALL];
   out->n_mixsrc = (int64_t)ctr[C_MIXSRC];
   out->n_updates = (int64_t)ctr[C_UPD];
   out->err_cell = ctr[C_ERR] == NO_ERR ? c->err_cell : (int64_t)ctr[C_ERR];
@@ -922,12 +963,26 @@ extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
 // Steps with the tape kept: a checkpoint of the state every K steps and the
 // step size of every step.  A new tape starts when none is open, when K
 // changes, or once reverse steps have been taken.
+// the counters of moves between materials (sum), after the queued work
+static mm_status moves_count(mm_ctx* c, unsigned long long* out) {
+  unsigned long long v[3];
+  static_assert(C_RELABEL == C_ABSORB + 1 && C_ODDBALL == C_ABSORB + 2, "adjacent counters");
+  HIP_OK(c, hipMemcpyAsync(v, c->B.ctr + C_ABSORB, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  *out = v[0] + v[1] + v[2];
+  return MM_OK;
+}
+
 static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_out) {
   if (c->tape_K != K || c->tape_rev != c->tape_n) {
     c->tape_K = K;
     c->tape_n = c->tape_rev = 0;
     c->seg_n0 = -1;
+    c->tape_moved = false;
   }
+  unsigned long long moves0 = 0, moves1 = 0;
+  mm_status mst = moves_count(c, &moves0);
+  if (mst != MM_OK) return mst;
   size_t need = (size_t)(c->tape_n + n_steps) * sizeof(double);
   if (need > c->tape_dt_cap) {
     double* nd = nullptr;
@@ -961,7 +1016,12 @@ static mm_status step_record(mm_ctx* c, int32_t n_steps, int32_t K, double* t_ou
     c->tape_rev = c->tape_n;
   }
   c->seg_n0 = -1;
-  return finish_steps(c, t_out);
+  mm_status st = finish_steps(c, t_out);
+  if (st != MM_OK) return st;
+  mst = moves_count(c, &moves1);
+  if (mst != MM_OK) return mst;
+  if (moves1 != moves0) c->tape_moved = true;
+  return MM_OK;
 }
 
 // Guard of plain steps: the state a call starts from (snapshot with counters,

@@ -2,9 +2,13 @@
 //
 // Every expression is written in a fixed evaluation order and the library is
 // compiled without floating-point contraction, so each operation is rounded
-// exactly once as written; FP64 division and square root are the correctly
-// rounded IEEE operations.  This makes results reproducible bit for bit
-// across launch shapes.
+// exactly once as written.  This makes results reproducible bit for bit
+// across launch shapes.  FP64 addition, multiplication and square root round
+// like the host's IEEE operations; FP64 division is faithful and almost
+// always correctly rounded, but not when the exact quotient lies within about
+// 1e-16 ulp of a rounding midpoint (such quotients arise between numbers near
+// 1), so a host computation of the same expressions can differ in the last
+// bit there.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,6 +35,7 @@ struct Params {
   int tait[MAXM];                 // 1: Tait material (pressure from density)
   double taitB[MAXM], rho0[MAXM];
   int flux;                       // FLUX_HLLC or FLUX_ROE
+  int scale_sep;                  // 1: interface scale separation after each step
 };
 enum { FLUX_HLLC = 0, FLUX_ROE = 1 };
 
