@@ -1334,7 +1334,14 @@ static void mixing(St *s) {
       for (int i = 0; i < nx; i++) {
         int k = ID(s, i, j);
         real as = M1(s, s->al, r, k);
-        if (!(as < amix) && s->chit[k] == r) continue;
+        /* Reading (empty part): a cell's own material with a volume
+           fraction but no conserved quantities at all (left so by a move
+           between materials, stranded sources or scale separation) is
+           filled from its neighbours like a new cell, whatever its alpha */
+        int empty = 1;
+        for (int v = 0; v < 4; v++)
+          if (M4(s, s->Qt, r, v, k) != 0.0) empty = 0;
+        if (!(as < amix) && s->chit[k] == r && !(empty && as > 0.0)) continue;
         if (!(as > 0.0)) {
           int nz = 0;
           for (int v = 0; v < 4; v++)

@@ -1769,13 +1769,13 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
       hn[n] = B.chi[kn[n]];
       pn[n] = B.phi[kn[n]];
     }
-    if (!(as < amix) && chk == r) continue;
-    if (!(as > 0.0)) {
-      bool nz = false;
-      for (int v = 0; v < 4; v++)
-        if (qk[v] != 0.0) nz = true;
-      if (!nz) continue;
-    }
+    // a part of the cell's own material with a volume fraction but nothing
+    // in it (left so by a move between materials) is filled like a new cell
+    bool nz = false;
+    for (int v = 0; v < 4; v++)
+      if (qk[v] != 0.0) nz = true;
+    if (!(as < amix) && chk == r && !(!nz && as > 0.0)) continue;
+    if (!(as > 0.0) && !nz) continue;
     wave_count(&B.ctr[C_MIXSRC], 1);
     auto lsn = [&](int n) { return hn[n] == r ? pn[n] : -pn[n]; };
     double gx = lsn(5) - lsn(3);

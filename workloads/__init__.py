@@ -96,7 +96,7 @@ def _dist_segment(px, py, ax, ay, bx, by):
     return np.sqrt((px - qx) ** 2 + (py - qy) ** 2)
 
 
-def triple_point(nx=896, ny=384, steps=2000, scale_sep=1):
+def triple_point(nx=896, ny=384, steps=2000, scale_sep=0):
     """Case III: 7 x 3 box, reflective walls, triple point at (1, 1.5)."""
     x, dx = _centres(nx, 0.0, 7.0)
     y, dy = _centres(ny, 0.0, 3.0)
@@ -232,7 +232,7 @@ def air_water_tube_1d(n=400, x_if=None, air=(50.0, 0.0, 1000.0), water_rho=1000.
 
 
 def shock_helium_water(nx=512, ny=128, steps=200, x_shock=0.5, bubble=(1.1, 0.5, 0.25),
-                       column=(2.0, 0.5, 0.2)):
+                       column=(2.0, 0.5, 0.2), scale_sep=1):
     """Case VI set-up (Table 2): a Mach 6 shock in air (post-shock state from
     the normal-shock relations; Table 2 prints (5.268, 5.752, 41.83)) hits a
     helium bubble (gamma 1.667, rho 0.138) that then meets a water column
