@@ -44,7 +44,7 @@ FP64_NOFMA_PEAK_TOPS = 39.3
 BYTES_PER_UPDATE_2D = 32.0 + 32.0 + 2.0 / 3.0 * 32.0
 # the main workload and its full length
 WORKLOAD = dict(name="shock_bubble", nx=2048, ny=512)
-FULL_STEPS = 2000
+FULL_STEPS = 3000
 # FP64 operations (add, subtract, multiply, divide, square root) of one bulk
 # 2D update, mean over the three SSP-RK3 stages: 2 faces x (8 WENO5 + 1 HLLC)
 # + the cell's primitive state + 4 RK combinations.  Counted from the

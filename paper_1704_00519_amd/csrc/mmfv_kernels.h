@@ -1167,7 +1167,9 @@ MMD void dt_reduce_block(const Params& P, const Bufs& B, int nblk) {
 
 // flux of material r across the face between cell (i, j) and its +1
 // neighbour in direction dir (0: x, 1: y); stencil of six cells
-template <int D>
+// FLUX: the face-flux variant fixed at compile time (FLUX_HLLC, FLUX_ROE) or
+// chosen from the parameters (-1, for the less frequent callers)
+template <int D, int FLUX = -1>
 MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
                    const uint8_t* occ, int r, int i, int j, int dir,
                    bool count, double F[4]) {
@@ -1188,7 +1190,7 @@ MMD void face_flux(const Params& P, const Bufs& B, const double* Q,
   Prim L, R;
   auto nrm = [&](const Prim& w) { return dir == 0 ? w.u : w.v; };
   auto tng = [&](const Prim& w) { return dir == 0 ? w.v : w.u; };
-  if (P.flux == FLUX_ROE) {
+  if (FLUX == FLUX_ROE || (FLUX < 0 && P.flux == FLUX_ROE)) {
     Prim Ws[6];
     for (int q = 0; q < 6; q++) {
       Ws[q].r = Wc[q].r;
@@ -2186,7 +2188,7 @@ __global__ void k_load_ls(Params P, Bufs B, const double* phi, const int32_t* ch
 // computes that face's aperture-weighted flux for every material; the lane
 // of the left face then combines them into the stage update.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int FLUX = -1>
 MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, int didx,
                           double bcoef, double ccoef, int bx, int nbx) {
   // threads are (cell, material, face): the aperture-scaled flux of one
@@ -2213,7 +2215,7 @@ MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, in
       bool count = f == 0 ? i == 0 : (f == 2 ? j == 0 : true);
       double A = apd(P, B, r, fi, fj, dir);
       double F[4] = {0.0, 0.0, 0.0, 0.0};
-      if (A > 0.0) face_flux<D>(P, B, Qs, os, r, fi, fj, dir, count, F);
+      if (A > 0.0) face_flux<D, FLUX>(P, B, Qs, os, r, fi, fj, dir, count, F);
       for (int v = 0; v < 4; v++) sF[tid][v] = A > 0.0 ? A * F[v] : 0.0;
     }
     __syncthreads();
@@ -2333,7 +2335,7 @@ MMD void cons_accumulate(const Bufs& B, int r, const double t[8], double w) {
 // flux term of one domain-boundary face of material r: side 0 is the low
 // face of row/column q (x-face i-1/2 of row q, or y-face j-1/2 of column q),
 // side 1 the high face; out = A F (0 where A = 0)
-template <int D>
+template <int D, int FLUX = -1>
 MMD void cons_face(const Params& P, const Bufs& B, const double* Qs, const uint8_t* os, int r,
                    int dir, int q, int side, double out[4]) {
   double F[4] = {0, 0, 0, 0};
@@ -2341,11 +2343,11 @@ MMD void cons_face(const Params& P, const Bufs& B, const double* Qs, const uint8
   if (dir == 0) {
     int i = side == 0 ? -1 : P.nx - 1;
     A = apx<D>(P, B, r, i, q);
-    if (A > 0.0) face_flux<D>(P, B, Qs, os, r, i, q, 0, false, F);
+    if (A > 0.0) face_flux<D, FLUX>(P, B, Qs, os, r, i, q, 0, false, F);
   } else {
     int j = side == 0 ? -1 : P.ny - 1;
     A = apy(P, B, r, q, j);
-    if (A > 0.0) face_flux<D>(P, B, Qs, os, r, q, j, 1, false, F);
+    if (A > 0.0) face_flux<D, FLUX>(P, B, Qs, os, r, q, j, 1, false, F);
   }
   for (int v = 0; v < 4; v++) out[v] = A > 0.0 ? A * F[v] : 0.0;
 }
@@ -2372,7 +2374,7 @@ MMD int cons_rows(const Params& P) { return P.dim == 2 ? P.ny + P.nx : 1; }
 // exchange.
 constexpr int CONS_ROWS = 128;
 
-template <int D>
+template <int D, int FLUX = -1>
 MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int bx, int r) {
   __shared__ double red[4 * 8];
   __shared__ double face[CONS_ROWS][2][4];
@@ -2388,7 +2390,7 @@ MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int 
     bool ok = q < cons_rows(P);
     double f[4] = {0, 0, 0, 0};
     int dir = q < P.ny ? 0 : 1;
-    if (ok) cons_face<D>(P, B, Qs, os, r, dir, dir == 0 ? (int)q : (int)(q - P.ny), side, f);
+    if (ok) cons_face<D, FLUX>(P, B, Qs, os, r, dir, dir == 0 ? (int)q : (int)(q - P.ny), side, f);
     for (int v = 0; v < 4; v++) face[row][side][v] = f[v];
     __syncthreads();
     if (ok && side == 0) {
@@ -2827,17 +2829,17 @@ __global__ void __launch_bounds__(256) k_ls_commit_bc(Params P, Bufs B, int ntb,
 // stage's source state, fluxes and exchange terms, the level-set stage only
 // the level sets, the velocity and the step size: none of it is written by
 // the band update, so their latency hides behind the band work.
-template <int D>
+template <int D, int FLUX>
 __global__ void __launch_bounds__(256) k_flux_list_cons(Params P, Bufs B, int sidx, int nidx,
                                                         int didx, double bcoef, double ccoef,
                                                         int nfb, int nbb, int ncons, int nls) {
   int b = blockIdx.x, nc = ncons * P.M;
   if (b < nc)
-    cons_part_block<D>(P, B, sidx, nbb, b % ncons, b / ncons);
+    cons_part_block<D, FLUX>(P, B, sidx, nbb, b % ncons, b / ncons);
   else if (b < nc + nls)
     for_tiles_n(P, B, b - nc, nls, [&](int i, int j) { b_ls<D>(P, B, i, j, bcoef, ccoef); });
   else
-    flux_list_blocks<D>(P, B, sidx, nidx, didx, bcoef, ccoef, b - nc - nls, nfb);
+    flux_list_blocks<D, FLUX>(P, B, sidx, nidx, didx, bcoef, ccoef, b - nc - nls, nfb);
 }
 template <int D>
 __global__ void __launch_bounds__(256) t_mix1(Params P, Bufs B, int didx) {
@@ -2860,6 +2862,22 @@ __global__ void __launch_bounds__(256) t_mix2(Params P, Bufs B, int didx, CopyLi
   int r = blockIdx.y;
   for_tiles(P, B, [&](int i, int j) { b_mix2<D>(P, B, i, j, didx, st, r, r + 1, true); });
 }
+// is cell k within H cells of the domain boundary (its level set and
+// indicator are copied into the frame)?
+MMD bool near_edge(const Params& P, int k) {
+  int i = k % P.NX - H, j = k / P.NX - P.HY;
+  return i < H || i >= P.nx - H || (P.dim == 2 && (j < H || j >= P.ny - H));
+}
+// both sides of the level-set frame again, by the whole workgroup
+template <int D>
+MMD void refill_ls_frame(const Params& P, const Bufs& B) {
+  for (int t = threadIdx.x; t < P.ny * 2 * H; t += blockDim.x) b_bc_ls_x(P, t, B.phi, B.chi);
+  __syncthreads();
+  if (D == 2)
+    for (int t = threadIdx.x; t < (P.nx + 2 * H) * 2 * H; t += blockDim.x)
+      b_bc_ls_y(P, t, B.phi, B.chi);
+}
+
 // The stage's stranded sources, listed by the mixing (one workgroup): when a
 // cell was relabelled the level-set frame is filled again and the stage's
 // stamp recorded, so that the classification and geometry launched next run
@@ -2870,14 +2888,16 @@ __global__ void __launch_bounds__(256) k_absorb(Params P, Bufs B, int didx) {
   int n = (int)B.ctr[C_NAB];
   if (n == 0) return;
   uint32_t st = (uint32_t)B.ctr[C_STAMP];
-  bool rel = false;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) rel |= b_absorb<D>(P, B, B.abList[e], didx, st);
+  bool rel = false, edge = false;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    int k = B.abList[e];
+    if (b_absorb<D>(P, B, k, didx, st)) {
+      rel = true;
+      edge |= near_edge(P, k);
+    }
+  }
   if (__syncthreads_or(rel)) {
-    for (int t = threadIdx.x; t < P.ny * 2 * H; t += blockDim.x) b_bc_ls_x(P, t, B.phi, B.chi);
-    __syncthreads();
-    if (D == 2)
-      for (int t = threadIdx.x; t < (P.nx + 2 * H) * 2 * H; t += blockDim.x)
-        b_bc_ls_y(P, t, B.phi, B.chi);
+    if (__syncthreads_or(edge)) refill_ls_frame<D>(P, B);
     if (threadIdx.x == 0) B.ctr[C_RLSTAMP] = st;
   }
   if (threadIdx.x == 0) B.ctr[C_NAB] = 0;
@@ -2893,13 +2913,12 @@ template <int D>
 __global__ void __launch_bounds__(256) k_ss_apply(Params P, Bufs B, int didx) {
   int n = (int)B.ctr[C_NSS];
   if (n == 0) return;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) b_ss_apply<D>(P, B, B.ssList[e], didx);
-  __syncthreads();
-  for (int t = threadIdx.x; t < P.ny * 2 * H; t += blockDim.x) b_bc_ls_x(P, t, B.phi, B.chi);
-  __syncthreads();
-  if (D == 2)
-    for (int t = threadIdx.x; t < (P.nx + 2 * H) * 2 * H; t += blockDim.x)
-      b_bc_ls_y(P, t, B.phi, B.chi);
+  bool edge = false;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    b_ss_apply<D>(P, B, B.ssList[e], didx);
+    edge |= near_edge(P, B.ssList[e]);
+  }
+  if (__syncthreads_or(edge)) refill_ls_frame<D>(P, B);
   if (threadIdx.x == 0) {
     B.ctr[C_SSSTAMP] = B.ctr[C_STAMP];
     B.ctr[C_NSS] = 0;

@@ -496,9 +496,14 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   if (c->ev_used >= 4096) prof_collect(c);
   // band update with the book-keeping partials and the level-set stage
   constexpr int FLUX_LIST_BLOCKS = 2048;
-  LAUNCH(k_flux_list_cons<D>, dim3(cons_blocks(P) * P.M + tg.x + FLUX_LIST_BLOCKS), dim3(256),
-         P, c->B, sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P), cons_blocks(P),
-         (int)tg.x);
+  if (P.flux == FLUX_ROE)
+    LAUNCH((k_flux_list_cons<D, FLUX_ROE>), dim3(cons_blocks(P) * P.M + tg.x + FLUX_LIST_BLOCKS),
+           dim3(256), P, c->B, sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P),
+           cons_blocks(P), (int)tg.x);
+  else
+    LAUNCH((k_flux_list_cons<D, FLUX_HLLC>), dim3(cons_blocks(P) * P.M + tg.x + FLUX_LIST_BLOCKS),
+           dim3(256), P, c->B, sidx, nidx, didx, b, cc, FLUX_LIST_BLOCKS, cons_bnd_blocks(P),
+           cons_blocks(P), (int)tg.x);
   if (D == 1)
     LAUNCH(k_cons_fin, dim3(P.M * 8), dim3(64), P, c->B, cons_blocks(P), w, advance ? 1 : 0);
 }
