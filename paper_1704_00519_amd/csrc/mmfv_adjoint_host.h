@@ -85,6 +85,12 @@ static void snap_load(mm_ctx* c, const char* src, int sidx, Copies* extra = null
   uint8_t* cls[4] = {c->B.cut, c->B.xs, c->B.dcut, c->B.dls};
   for (int q = 0; q < 4; q++) cp.add(cls[q], src + L.cls + q * nc, nc);
   cp.fill0(&c->B.ctr[C_NTILES], sizeof(unsigned long long));
+  // the quiet-block maps of the classification describe another state
+  if (D == 2) {
+    size_t ncb = (size_t)((P.nx + CX - 1) / CX) * ((P.ny + CY - 1) / CY);
+    cp.fill0(c->B.cquiet[0], ncb);
+    cp.fill0(c->B.cquiet[1], ncb);
+  }
   cp.run(c);
   if (tiles) build_tiles<D>(c, sidx, 0);  // only forward kernels read the tile list
 }

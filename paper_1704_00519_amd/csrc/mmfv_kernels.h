@@ -44,6 +44,9 @@ struct Bufs {
   // cells holding one (list and listing stamp), relabelled cells (stamp and
   // new material); scale separation: oddball cells and their new material
   // and distance
+  // 2D classification blocks that held no cut or band cell, one map per
+  // stage parity (1: quiet; 0: not, or not known)
+  uint8_t* cquiet[2];
   uint32_t *strStamp, *abMark, *rlStamp;
   uint8_t *rlTo, *ssTo;
   int32_t *abList, *ssList;
@@ -509,13 +512,39 @@ struct ClassDistSmem {
   unsigned long long mrow[2][CY + 2 * CF];  // the flags of a frame row as bits
 };
 static_assert(CX + 2 * CF <= 64, "a frame row fits one 64-bit mask");
+//
+// A block whose 3 x 3 neighbourhood of blocks held no cut or band cell at
+// the previous stage is skipped: the level set and the indicators move less
+// than a cell per stage, so such a block is still at least CY - 1 > RD cells
+// from any flagged cell, and its outputs (single-material local sets, no cut
+// cell, capped distances) are those it already holds.  The maps alternate
+// with the parity of the stage stamp (read the previous stage's, write the
+// current one); a restored state clears them, which makes every block run.
 __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B, int gate) {
   if (gated_off(B, gate)) return;
   __shared__ ClassDistSmem S;
   constexpr int HX = CX + 2 * CF + 2, HY = CY + 2 * CF + 2;
   constexpr int FX = CX + 2 * CF, FY = CY + 2 * CF;
+  static_assert(CY - 1 > RD && CX - 1 > RD, "a quiet block neighbourhood spans more than RD");
   int tid = threadIdx.x, i0 = blockIdx.x * CX, j0 = blockIdx.y * CY;
   if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) B.ctr[C_NTILES] = 0;
+  int par = (int)(B.ctr[C_STAMP] & 1);
+  const uint8_t* prevq = B.cquiet[par ^ 1];
+  uint8_t* curq = B.cquiet[par];
+  int me = blockIdx.y * gridDim.x + blockIdx.x;
+  {
+    bool quiet = true;
+    for (int dj = -1; dj <= 1; dj++)
+      for (int di = -1; di <= 1; di++) {
+        int bx = (int)blockIdx.x + di, by = (int)blockIdx.y + dj;
+        if (bx >= 0 && by >= 0 && bx < (int)gridDim.x && by < (int)gridDim.y)
+          quiet = quiet && prevq[by * gridDim.x + bx] != 0;
+      }
+    if (quiet) {
+      if (tid == 0) curq[me] = 1;
+      return;
+    }
+  }
   // indicators of the frame cells that border a domain cell (-1..nx, -1..ny)
   // and the level-set test of the frame's domain cells: every load of the
   // thread is issued before the first is used
@@ -544,6 +573,7 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B, int ga
   }
   __syncthreads();
   // flags of the domain cells of the frame (zero outside the domain)
+  bool own_flag = false;
 #pragma unroll
   for (int n = 0; n < N2; n++) {
     int q = tid + n * 256;
@@ -561,11 +591,13 @@ __global__ void __launch_bounds__(256) k_classify_dist2(Params P, Bufs B, int ga
       if (fx >= CF && fx < CF + CX && fy >= CF && fy < CF + CY) {
         B.xs[k] = (uint8_t)b;
         B.cut[k] = c;
+        if (f) own_flag = true;
       }
     }
     S.fl[fy][fx] = f;
   }
-  __syncthreads();
+  int flagged = __syncthreads_or(own_flag);  // also the barrier after the flags
+  if (tid == 0) curq[me] = flagged ? 0 : 1;
   // the frame's rows as bit masks (four 16-cell pieces per row)
   if (tid < 2 * FY) S.mrow[tid / FY][tid % FY] = 0;
   __syncthreads();

@@ -288,6 +288,10 @@ extern "C" mm_status mm_create(const mm_config* cfg, void* hip_stream, mm_ctx** 
   A(B.vx, nc); A(B.vy, nc); A(B.vit, nc);
   A(B.mixM, M * 3 * 4 * nc); A(B.mixT, M * 3 * nc);
   A(B.srcStamp, M * nc); A(B.tgtStamp, M * nc);
+  {
+    size_t ncb = (size_t)((P.nx + CX - 1) / CX) * ((P.ny + CY - 1) / CY);
+    A(B.cquiet[0], ncb); A(B.cquiet[1], ncb);
+  }
   A(B.strStamp, M * nc); A(B.abMark, nc); A(B.rlStamp, nc);
   A(B.rlTo, nc); A(B.ssTo, nc); A(B.abList, nc); A(B.ssList, nc); A(B.ssPhi, nc);
   A(B.tiles, (size_t)((P.nx + 15) / 16 + 16) * ((P.ny + 15) / 16 + 1));
@@ -658,6 +662,9 @@ extern "C" mm_status mm_init_state(mm_ctx* c, const double* phi, const int32_t* 
     HIP_OK(c, hipMemsetAsync(c->B.strStamp, 0, M * nc * 4, c->stream));
     HIP_OK(c, hipMemsetAsync(c->B.abMark, 0, nc * 4, c->stream));
     HIP_OK(c, hipMemsetAsync(c->B.rlStamp, 0, nc * 4, c->stream));
+    size_t ncb = (size_t)((P.nx + CX - 1) / CX) * ((P.ny + CY - 1) / CY);
+    HIP_OK(c, hipMemsetAsync(c->B.cquiet[0], 0, ncb, c->stream));
+    HIP_OK(c, hipMemsetAsync(c->B.cquiet[1], 0, ncb, c->stream));
   }
   dim3 g = cell_grid(c), bl = cell_block(c);
   LAUNCH(k_load_ls, g, bl, P, c->B, dphi, dchi);
