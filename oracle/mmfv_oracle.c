@@ -71,6 +71,13 @@ typedef struct {
   /* 1: the interface scale-separation model after every time step
      (Sec. 2.3.3) */
   int32_t scale_sep;
+  /* coord = 1: 1D cylindrical (radial) geometry, x the radius (Sec. 3 Case
+     II); fs_on = 1: material fs_mat is an ambient that is not solved, and
+     its interfaces are free surfaces under the pressure law of fs_p (Case
+     II's p(t): p_hi up to t0, then linear to p_lo at t1; reading: p_lo
+     afterwards) */
+  int32_t coord, fs_on, fs_mat;
+  double fs_p[5];  /* p_hi, p_lo, t0, t1, density of the ambient */
 } or_config;
 
 typedef struct {
@@ -121,11 +128,14 @@ typedef struct {
      sources, scale separation): received minus given, per material */
   real xfer[OR_MAXM][OR_NV], xfer_c[OR_MAXM][OR_NV];
   double xw;       /* weight in the full step of a change to the stage state */
+  double tstage;   /* time of the current stage's input state */
   int err_code;
   long err_cell;
 } St;
 
 #define ID(s, i, j) (((j) + (s)->HY) * (s)->NX + (i) + OR_H)
+/* the ambient material of a free surface (not solved) */
+#define PASSIVE(s, r) ((s)->c.fs_on && (r) == (s)->c.fs_mat)
 #define M1(s, a, m, k) ((a)[(size_t)(m) * (s)->NC + (k)])
 #define M4(s, a, m, v, k) ((a)[((size_t)(m) * OR_NV + (v)) * (s)->NC + (k)])
 
@@ -504,6 +514,15 @@ static void geometry(St *s, const real *phi, const int *chi) {
         int il = inside(s->cv[kl], s->co[kl], r), ir = inside(s->cv[k], s->co[k], r);
         al[k] = (seg_frac(s->cv[kl], il, c, ic) + seg_frac(c, ic, s->cv[k], ir)) * 0.5;
         cx[k] = ax[k] - ax[kl];
+        if (s->c.coord == 1) {
+          /* cylindrical: the interface area r_s per cell volume r_i dx, from
+             the faces' areas and the volume fraction (alpha dx = r_s - r_{i-1/2}
+             for a material on the inner side), so that a uniform pressure
+             balances the faces, the geometric source and the exchange */
+          double rl = s->c.x0 + i * s->dx, rr = s->c.x0 + (i + 1) * s->dx;
+          double ri = s->c.x0 + (i + 0.5) * s->dx;
+          cx[k] = ((ax[k] * rr - ax[kl] * rl) - al[k] * s->dx) / ri;
+        }
         cy[k] = 0.0;
       }
       continue;
@@ -610,14 +629,43 @@ static void record_err(St *s, int code, int i, int j) {
 /* Real cells of material r: chi == r and alpha^r > 0; W = prim(Q / alpha).
  * Reading (guards): rho <= 0, p + p_inf <= 0 or a non-finite value there is
  * a non-physical state and stops the run. */
+/* Pressure on a free surface at time t (Sec. 3 Case II). */
+static double fs_pressure(const St *s, double t) {
+  const double *f = s->c.fs_p;
+  if (t <= f[2]) return f[0];
+  if (t >= f[3]) return f[1];
+  return f[0] - (f[0] - f[1]) * (t - f[2]) / (f[3] - f[2]);
+}
+
+/* The ambient of a free surface is not solved: its state is the prescribed
+ * one (the ambient density, at rest, at the surface pressure of the stage's
+ * time) in every cell, and its conserved quantities alpha U of that state. */
+static void ambient_state(St *s) {
+  int r = s->c.fs_mat, nx = s->c.nx, ny = s->c.ny;
+  real W[4] = {s->c.fs_p[4], 0.0, 0.0, fs_pressure(s, s->tstage)};
+  real E = energy(s, r, W[0], W[1], W[2], W[3]);
+  for (size_t k = 0; k < (size_t)s->NC; k++) {
+    for (int v = 0; v < 4; v++) M4(s, s->W, r, v, k) = W[v];
+    M1(s, s->Wv, r, k) = 1;
+  }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      real a = M1(s, s->al, r, k);
+      real U[4] = {W[0], 0.0, 0.0, E};
+      for (int v = 0; v < 4; v++) M4(s, s->Q, r, v, k) = a > 0.0 ? a * U[v] : 0.0;
+    }
+}
+
 static void real_states(St *s) {
   int nx = s->c.nx, ny = s->c.ny;
   memset(s->Wv, 0, (size_t)s->M * s->NC);
+  if (s->c.fs_on) ambient_state(s);
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       int k = ID(s, i, j), r = s->chi[k];
       real a = M1(s, s->al, r, k);
-      if (!(a > 0.0)) continue;
+      if (!(a > 0.0) || PASSIVE(s, r)) continue;
       real U[4], W[4];
       for (int v = 0; v < 4; v++) U[v] = M4(s, s->Q, r, v, k) / a;
       prim(s, r, U, W);
@@ -729,6 +777,33 @@ static void extension(St *s) {
   (void)nc;
 }
 
+static real wave_jump(const St *s, int m, const real *W, real ps);
+
+/* Free surface (Sec. 3 Case II): the ambient's own waves are not solved, so
+ * the surface's Riemann problem against the prescribed pressure ps can be far
+ * faster than the solved side's sound speed.  Reading: in a cell holding the
+ * surface, the step is bounded by max(|u|, |v|) + |du| + c_s for every solved
+ * material present, du the velocity jump of its wave to ps and c_s that
+ * wave's front speed relative to the material (c for a rarefaction; the
+ * stiffened-gas shock speed c sqrt(1 + (g + 1)/(2 g) (ps - p)/(p + pinf))
+ * for a shock). */
+static real fs_speed(St *s, int k) {
+  real ps = fs_pressure(s, s->tstage), smax = 0.0;
+  for (int m = 0; m < s->M; m++) {
+    if (!(s->xs[k] >> m & 1) || PASSIVE(s, m) || !M1(s, s->Wv, m, k)) continue;
+    real W[4] = {M4(s, s->W, m, 0, k), M4(s, s->W, m, 1, k), M4(s, s->W, m, 2, k),
+                 M4(s, s->W, m, 3, k)};
+    double g = s->c.gamma[m];
+    real pb = W[3] + s->pinfe[m];
+    real c = sqrt(g * pb / W[0]);
+    if (ps > W[3]) c = c * sqrt(1.0 + (g + 1.0) / (2.0 * g) * ((ps - W[3]) / pb));
+    real u = fabs(W[1]), v = fabs(W[2]);
+    real w = (u > v ? u : v) + fabs(wave_jump(s, m, W, ps)) + c;
+    if (w > smax) smax = w;
+  }
+  return smax;
+}
+
 /* CFL time step (Sec. 2.3, Sec. 3: CFL number 0.6).  Reading: one step size
  * per time step from the time-n state, dt = CFL h / max over real cells of
  * max(|u| + c, |v| + c). */
@@ -738,13 +813,17 @@ static real cfl_dt(St *s) {
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       int k = ID(s, i, j), r = s->chi[k];
-      if (!M1(s, s->Wv, r, k)) continue;
+      if (!M1(s, s->Wv, r, k) || PASSIVE(s, r)) continue;
       real rho = M4(s, s->W, r, 0, k), u = M4(s, s->W, r, 1, k),
              v = M4(s, s->W, r, 2, k), p = M4(s, s->W, r, 3, k);
       real c = sqrt(s->c.gamma[r] * (p + s->pinfe[r]) / rho);
       real a = fabs(u) + c, b = fabs(v) + c;
       real w = a > b ? a : b;
       if (w > smax) smax = w;
+      if (s->c.fs_on && (s->xs[k] >> s->c.fs_mat & 1)) {
+        w = fs_speed(s, k);
+        if (w > smax) smax = w;
+      }
     }
   return s->c.cfl * s->h / smax;
 }
@@ -765,6 +844,21 @@ static real cfl_dt(St *s) {
  * X^a = (0, p* c^a_x, p* c^a_y, p* S_M |c^a|), X^b = -X^a, zero for every
  * other material.  Reading: p* is the mean of its two equal forms.  At
  * stage 0 the interface velocity S_M n is kept for the level set. */
+/* Velocity jump across the wave of a stiffened-gas state W (rho, u_n, u_t, p)
+ * of material m that brings its pressure to ps (Toro's pressure function,
+ * pressures shifted by p_inf): a shock for ps > p, a rarefaction otherwise. */
+static real wave_jump(const St *s, int m, const real *W, real ps) {
+  double g = s->c.gamma[m], pinf = s->pinfe[m];
+  real pb = W[3] + pinf, psb = ps + pinf;
+  if (ps > W[3]) {
+    real A = 2.0 / ((g + 1.0) * W[0]);
+    real B = (g - 1.0) / (g + 1.0) * pb;
+    return (ps - W[3]) * sqrt(A / (psb + B));
+  }
+  real c = sqrt(g * pb / W[0]);
+  return 2.0 * c / (g - 1.0) * (pow(psb / pb, (g - 1.0) / (2.0 * g)) - 1.0);
+}
+
 static void interface_exchange(St *s, int stage) {
   int nx = s->c.nx, ny = s->c.ny;
   memset(s->X, 0, (size_t)s->M * 4 * s->NC * sizeof(real));
@@ -804,18 +898,34 @@ static void interface_exchange(St *s, int stage) {
       WR[1] = M4(s, s->W, a, 1, k) * nxv + M4(s, s->W, a, 2, k) * nyv;
       WR[2] = 0.0;
       WR[3] = M4(s, s->W, a, 3, k);
-      real SL, SR;
-      wave_speeds(WL, s->c.gamma[bb], s->pinfe[bb], s->tait[bb], WR, s->c.gamma[a], s->pinfe[a],
-                  s->tait[a], &SL, &SR);
-      real SM = contact_speed(WL, WR, SL, SR);
-      real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
-      real ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
-                         (pR + WR[0] * (SR - uR) * (SM - uR)));
+      real SM, ps;
+      if (PASSIVE(s, a) || PASSIVE(s, bb)) {
+        /* free surface (Sec. 3 Case II): the ambient is not solved; the
+           surface pressure is prescribed, and the surface moves with the
+           velocity the solved side's wave reaches at that pressure (the
+           solved side is the right state when it is a, the left one
+           otherwise, along n) */
+        ps = fs_pressure(s, s->tstage);
+        SM = PASSIVE(s, bb) ? WR[1] + wave_jump(s, a, WR, ps) : WL[1] - wave_jump(s, bb, WL, ps);
+      } else {
+        real SL, SR;
+        wave_speeds(WL, s->c.gamma[bb], s->pinfe[bb], s->tait[bb], WR, s->c.gamma[a],
+                    s->pinfe[a], s->tait[a], &SL, &SR);
+        SM = contact_speed(WL, WR, SL, SR);
+        real pL = WL[3], pR = WR[3], uL = WL[1], uR = WR[1];
+        ps = 0.5 * ((pL + WL[0] * (SL - uL) * (SM - uL)) +
+                    (pR + WR[0] * (SR - uR) * (SM - uR)));
+      }
       M4(s, s->X, a, 0, k) = 0.0;
       M4(s, s->X, a, 1, k) = ps * cxa;
       M4(s, s->X, a, 2, k) = ps * cya;
       M4(s, s->X, a, 3, k) = ps * SM * nrm;
       for (int v = 0; v < 4; v++) M4(s, s->X, bb, v, k) = -M4(s, s->X, a, v, k);
+      /* nothing is exchanged with an ambient that is not solved */
+      if (PASSIVE(s, a))
+        for (int v = 0; v < 4; v++) M4(s, s->X, a, v, k) = 0.0;
+      if (PASSIVE(s, bb))
+        for (int v = 0; v < 4; v++) M4(s, s->X, bb, v, k) = 0.0;
       if (stage == 0) {
         s->vx[k] = SM * nxv;
         s->vy[k] = SM * nyv;
@@ -1033,6 +1143,11 @@ static int face_flux(St *s, int r, const int *kk /* 6 cells */, int normal,
 static void fluxes(St *s) {
   int nx = s->c.nx, ny = s->c.ny;
   for (int r = 0; r < s->M; r++) {
+    if (PASSIVE(s, r)) {
+      memset(&M4(s, s->Fx, r, 0, 0), 0, (size_t)4 * s->NC * sizeof(real));
+      if (s->c.dim == 2) memset(&M4(s, s->Fy, r, 0, 0), 0, (size_t)4 * s->NC * sizeof(real));
+      continue;
+    }
     for (int j = 0; j < ny; j++)
       for (int i = -1; i < nx; i++) {
         int k = ID(s, i, j);
@@ -1087,11 +1202,17 @@ static void rk_update(St *s, double b, double c, double w) {
   for (int r = 0; r < s->M; r++)
     for (int j = 0; j < ny; j++)
       for (int i = 0; i < nx; i++)
-        if (M1(s, s->al, r, ID(s, i, j)) > 0.0) s->n_upd++;
+        if (M1(s, s->al, r, ID(s, i, j)) > 0.0 && !PASSIVE(s, r)) s->n_upd++;
   real lx = s->dt / s->dx, ly = s->dt / s->dy;
   real lv = s->c.dim == 2 ? s->dt / (s->dx * s->dy) : s->dt / s->dx;
+  int cyl = s->c.coord == 1;
   for (int r = 0; r < s->M; r++)
     for (int v = 0; v < 4; v++) {
+      if (PASSIVE(s, r)) {  /* not solved: the stage leaves it as it is */
+        for (int j = 0; j < ny; j++)
+          for (int i = 0; i < nx; i++) M4(s, s->Qt, r, v, ID(s, i, j)) = M4(s, s->Q, r, v, ID(s, i, j));
+        continue;
+      }
       for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
           int k = ID(s, i, j), kl = ID(s, i - 1, j);
@@ -1099,6 +1220,16 @@ static void rk_update(St *s, double b, double c, double w) {
           real fl = Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0;
           real fr = Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, k) : 0.0;
           real rhs = lx * (fl - fr);
+          if (cyl) {
+            /* cylindrical: face areas r_{i-1/2}, r_{i+1/2} per cell volume
+               r_i dx, and the geometric source p alpha / r_i of the radial
+               momentum (the pressure of the material's state in the cell) */
+            double rl = s->c.x0 + i * s->dx, rr = s->c.x0 + (i + 1) * s->dx;
+            double ri = s->c.x0 + (i + 0.5) * s->dx;
+            rhs = lx * (fl * rl - fr * rr) / ri;
+            if (v == 1 && M1(s, s->Wv, r, k))
+              rhs = rhs + s->dt * (M1(s, s->al, r, k) * M4(s, s->W, r, 3, k) / ri);
+          }
           if (s->c.dim == 2) {
             int kb = ID(s, i, j - 1);
             real Ab = M1(s, s->ay, r, kb), At = M1(s, s->ay, r, k);
@@ -1115,8 +1246,10 @@ static void rk_update(St *s, double b, double c, double w) {
       for (int j = 0; j < ny; j++) {
         int kl = ID(s, -1, j), kr = ID(s, nx - 1, j);
         real Al = M1(s, s->ax, r, kl), Ar = M1(s, s->ax, r, kr);
-        in += lx * ((Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0) -
-                    (Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, kr) : 0.0));
+        /* cylindrical: r-weighted (the sums are of r_i Q_i) */
+        double rlo = cyl ? s->c.x0 : 1.0, rhi = cyl ? s->c.x0 + nx * s->dx : 1.0;
+        in += lx * ((Al > 0.0 ? Al * M4(s, s->Fx, r, v, kl) : 0.0) * rlo -
+                    (Ar > 0.0 ? Ar * M4(s, s->Fx, r, v, kr) : 0.0) * rhi);
       }
       if (s->c.dim == 2)
         for (int i = 0; i < nx; i++) {
@@ -1127,7 +1260,18 @@ static void rk_update(St *s, double b, double c, double w) {
         }
       real xsum = 0.0;
       for (int j = 0; j < ny; j++)
-        for (int i = 0; i < nx; i++) xsum += lv * M4(s, s->X, r, v, ID(s, i, j));
+        for (int i = 0; i < nx; i++) {
+          int k = ID(s, i, j);
+          if (!cyl) {
+            xsum += lv * M4(s, s->X, r, v, k);
+            continue;
+          }
+          /* cylindrical: r-weighted exchange plus the geometric source */
+          double ri = s->c.x0 + (i + 0.5) * s->dx;
+          xsum += lv * M4(s, s->X, r, v, k) * ri;
+          if (v == 1 && M1(s, s->Wv, r, k))
+            xsum += s->dt * (M1(s, s->al, r, k) * M4(s, s->W, r, 3, k));
+        }
       neumaier(&s->bnd[r][v], &s->bnd_c[r][v], w * in);
       neumaier(&s->xsum[r][v], &s->xsum_c[r][v], w * xsum);
     }
@@ -1312,12 +1456,15 @@ static void levelset_stage(St *s, double b, double c) {
  * stages' coefficients of the previous stage in the beta form: 1/6, 2/3, 1
  * for the three stages of RK3; 1 after the step). */
 static void move_q(St *s, int k, int r, int to) {
+  /* cylindrical: the book-keeping is of r_i Q_i, like the balances */
+  double ri = 1.0;
+  if (s->c.coord == 1) ri = s->c.x0 + ((k % s->NX) - OR_H + 0.5) * s->dx;
   for (int v = 0; v < 4; v++) {
     real q = M4(s, s->Q, r, v, k);
     M4(s, s->Q, to, v, k) = M4(s, s->Q, to, v, k) + q;
     M4(s, s->Q, r, v, k) = 0.0;
-    neumaier(&s->xfer[to][v], &s->xfer_c[to][v], s->xw * q);
-    neumaier(&s->xfer[r][v], &s->xfer_c[r][v], -(s->xw * q));
+    neumaier(&s->xfer[to][v], &s->xfer_c[to][v], s->xw * q * ri);
+    neumaier(&s->xfer[r][v], &s->xfer_c[r][v], -(s->xw * q * ri));
   }
 }
 
@@ -1326,7 +1473,9 @@ static void mixing(St *s) {
   double amix = s->c.alpha_mix;
   size_t nc = s->NC;
   s->nab = s->nrl = 0;
+  int cyl = s->c.coord == 1;
   for (int r = 0; r < s->M; r++) {
+    if (PASSIVE(s, r)) continue;  /* not solved */
     int *T = s->mixT;
     real *Mx = s->mixM;
     for (size_t q = 0; q < 3 * nc; q++) T[q] = -1;
@@ -1428,20 +1577,31 @@ static void mixing(St *s) {
           T[(size_t)q * nc + k] = tk[q];
           if (tk[q] >= 0) last = q;
         }
+        /* cylindrical: volumes and contents carry the cells' radii (the
+           exchange is of content, alpha r and Q r in place of alpha and Q) */
+        double rs = cyl ? s->c.x0 + (i + 0.5) * s->dx : 1.0;
         if (as > 0.0) {
           for (int q = 0; q < 3; q++) {
             if (tk[q] < 0) continue;
             real at = M1(s, s->al, r, tk[q]);
+            double rt = cyl ? s->c.x0 + (i + (tk[q] - k) + 0.5) * s->dx : 1.0;
             for (int v = 0; v < 4; v++) {
               real Qs = M4(s, s->Qt, r, v, k), Qtg = M4(s, s->Qt, r, v, tk[q]);
-              Mx[((size_t)q * 4 + v) * nc + k] = beta[q] * ((as * Qtg - at * Qs) / (as + at));
+              if (cyl) {
+                real aS = as * rs, aT = at * rt, qS = Qs * rs, qT = Qtg * rt;
+                Mx[((size_t)q * 4 + v) * nc + k] = beta[q] * ((aS * qT - aT * qS) / (aS + aT));
+              } else {
+                Mx[((size_t)q * 4 + v) * nc + k] = beta[q] * ((as * Qtg - at * Qs) / (as + at));
+              }
             }
           }
         } else {
           /* vanishing cell: with alpha_s = 0 the exchange is M_t = -beta_t Q_s;
              the last target takes the exact remainder so the source ends at 0 */
           for (int v = 0; v < 4; v++) {
-            real Qs = M4(s, s->Qt, r, v, k), acc = Qs;
+            real Qs = M4(s, s->Qt, r, v, k);
+            if (cyl) Qs = Qs * rs;
+            real acc = Qs;
             for (int q = 0; q < 3; q++) {
               if (tk[q] < 0) continue;
               real m = q == last ? -acc : -(beta[q] * Qs);
@@ -1458,10 +1618,12 @@ static void mixing(St *s) {
         int k = ID(s, i, j);
         for (int v = 0; v < 4; v++) {
           real q0 = M4(s, s->Qt, r, v, k);
+          double rc = cyl ? s->c.x0 + (i + 0.5) * s->dx : 1.0;
           int src = 0;
           for (int q = 0; q < 3; q++)
             if (T[(size_t)q * nc + k] >= 0) {
-              q0 = q0 + Mx[((size_t)q * 4 + v) * nc + k];
+              q0 = cyl ? q0 + Mx[((size_t)q * 4 + v) * nc + k] / rc
+                       : q0 + Mx[((size_t)q * 4 + v) * nc + k];
               src = 1;
             }
           if (!src) {
@@ -1479,7 +1641,7 @@ static void mixing(St *s) {
               }
               row[dj + 1] = (a[0] + a[2]) + a[1];
             }
-            q0 = q0 - ((row[0] + row[2]) + row[1]);
+            q0 = cyl ? q0 - ((row[0] + row[2]) + row[1]) / rc : q0 - ((row[0] + row[2]) + row[1]);
           }
           M4(s, s->Q, r, v, k) = q0;
         }
@@ -1640,6 +1802,16 @@ St *or_create(const or_config *c) {
   if (!c || (c->dim != 1 && c->dim != 2) || c->nx < 1 || c->ny < 1 ||
       (c->dim == 1 && c->ny != 1) || c->n_mat < 1 || c->n_mat > OR_MAXM)
     return NULL;
+  if ((c->coord != 0 && c->coord != 1) || (c->coord == 1 && (c->dim != 1 || c->x0 < 0.0)))
+    return NULL;
+  if (c->fs_on != 0 && c->fs_on != 1) return NULL;
+  if (c->fs_on) {
+    if (c->fs_mat < 0 || c->fs_mat >= c->n_mat || !(c->fs_p[4] > 0.0) ||
+        !(c->fs_p[3] > c->fs_p[2]) || c->flux != 0)
+      return NULL;
+    for (int m = 0; m < c->n_mat; m++)
+      if (c->eos[m] != 0) return NULL;
+  }
   for (int m = 0; m < c->n_mat; m++)
     if (c->eos[m] < 0 || c->eos[m] > 1 ||
         (c->eos[m] == 1 && !(c->rho0[m] > 0.0 && c->tait_B[m] > 0.0)))
@@ -1821,6 +1993,9 @@ int or_step(St *s, int nsteps) {
     memcpy(s->chin, s->chi, s->NC * sizeof(int));
     for (int st = 0; st < ns; st++) {
       s->err_code = OR_OK;
+      /* time of the stage's input state: t_n, then t_n + dt (and for RK3
+         t_n + dt/2) */
+      s->tstage = st == 0 ? s->t : s->t + (st == 1 ? 1.0 : 0.5) * (double)RV(s->dt);
       local_sets(s, s->chi, s->xs);
       real_states(s);
       if (s->err_code) return s->err_code;

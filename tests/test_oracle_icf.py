@@ -1,0 +1,195 @@
+"""Pins of the oracle's Case II machinery (Sec. 3, 1D cylindrical ICF
+implosion): radial geometry with the geometric source of the radial
+momentum and the matching interface area, content-weighted mixing, and a
+free surface toward an ambient that is not solved, under the prescribed
+pressure law p(t).
+
+* rest: three materials at uniform pressure in radial geometry stay at rest
+  and keep their densities, with all materials solved and with a free
+  surface at the same constant pressure;
+* conservation: the r-weighted masses of the core and the shell are
+  constant to rounding, and every r-weighted momentum and energy balance
+  closes with the boundary, exchange-plus-source and transfer terms;
+* an independent solution: a radial blast wave against the 2D Cartesian
+  oracle on a quarter plane with reflective axes (the same physics with no
+  radial terms);
+* the free surface against the exact solution of a planar slab at rest
+  struck by a constant surface pressure (a shock into the slab; the surface
+  moves with the post-shock velocity);
+* the paper's own statements about Case II: the shell thins while the
+  driving pressure is constant, until about t = 0.047, and the inner
+  interface reaches its smallest radius between t = 0.17 and t = 0.24.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from exact_riemann import Side, star_state
+
+
+def radial(n, L):
+    dx = L / n
+    return (np.arange(n) + 0.5) * dx, dx
+
+
+def rest_case(fs_on):
+    n = 120
+    r, dx = radial(n, 1.5)
+    cfg = wl.base_config(dim=1, nx=n, ny=1, x0=0.0, x1=1.5, gamma=[1.4, 1.667, 4.4],
+                         pinf=[0.0, 0.0, 6.0], bc=[wl.BC_REFLECTIVE] * 4, coord=1,
+                         fs_on=fs_on, fs_mat=2, fs_p=[1.0, 1.0, 0.0, 1.0, 0.1])
+    chi = np.where(r < 0.7, 0, np.where(r < 1.13, 1, 2)).astype(np.int32)
+    phi = np.minimum(np.minimum(np.abs(r - 0.7), np.abs(r - 1.13)), 8 * dx)
+    W = np.zeros((3, 3, 1, n))
+    W[:, 0] = np.array([0.2, 1.0, 3.0])[:, None, None]
+    W[:, 2] = 1.0
+    return dict(cfg=cfg, phi=phi[None], chi=chi[None], W=W)
+
+
+@pytest.mark.parametrize("fs_on", [0, 1])
+def test_radial_rest_at_uniform_pressure(fs_on):
+    w = rest_case(fs_on)
+    o = oracle.run(w, steps=60)
+    g = o.get()
+    Q, al = g["Q"], g["alpha"]
+    for m, rho in ((0, 0.2), (1, 1.0)):
+        on = al[m, 0] > 1e-3
+        assert np.abs(Q[m, 1, 0][on]).max() <= 1e-13
+        assert np.abs(Q[m, 0, 0][on] / al[m, 0][on] - rho).max() <= 1e-12 * rho
+
+
+def sums_r(o, n, L):
+    r, dx = radial(n, L)
+    Q = o.get()["Q"]
+    out = np.zeros((Q.shape[0], 4))
+    for m in range(Q.shape[0]):
+        for c, v in enumerate((0, 1, 3)):
+            out[m, v] = math.fsum(Q[m, c, 0] * r)
+    return out
+
+
+def test_radial_conservation_and_balances():
+    n = 320
+    w = wl.icf_1d(n=n)
+    o0 = oracle.Oracle(w["cfg"])
+    assert o0.init(w["phi"], w["chi"], w["W"]) == 0
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    assert o.step(300) == 0
+    s0, s1 = sums_r(o0, n, 1.5), sums_r(o, n, 1.5)
+    d = o.diag()
+    # the core's and the shell's masses: nothing crosses the axis or the
+    # free surface
+    assert np.all(np.abs(s1[:2, 0] - s0[:2, 0]) <= 1e-13 * s0[:2, 0])
+    # momentum and energy of the solved materials: boundary, exchange with
+    # the geometric source, transfers (the sums are of r_i Q_i)
+    bal = (s1 - s0)[:2] - (d["bnd"] + d["xsum"] + d["xfer"])[:2]
+    scale = np.abs(s1[:2]).max()
+    assert np.abs(bal).max() <= 1e-12 * scale, bal
+    # the shell gains energy from the work of the surface pressure
+    assert s1[1, 3] > s0[1, 3]
+
+
+def test_radial_blast_against_2d_cartesian():
+    """p = 1 for r < 0.3 (rho 1), p = 0.1 outside (rho 0.125), one ideal gas
+    at rest; at t = 0.2 the density along the x axis of the 2D run on [0,1]^2
+    (reflective at x = 0 and y = 0) against the 1D radial run on the same
+    spacing: within 2.5% in L1, and the shock in the same cell or the next."""
+    n, L, T = 120, 1.0, 0.2
+    r, dx = radial(n, L)
+    cfg1 = wl.base_config(dim=1, nx=n, ny=1, n_mat=1, x0=0.0, x1=L, gamma=[1.4], pinf=[0.0],
+                          bc=[wl.BC_REFLECTIVE, wl.BC_TRANSMISSIVE] * 2, coord=1)
+    W1 = np.stack([np.where(r < 0.3, 1.0, 0.125), 0 * r, np.where(r < 0.3, 1.0, 0.1)])[None, :, None, :]
+    o1 = oracle.Oracle(cfg1)
+    assert o1.init(np.full((1, n), 8 * dx), np.zeros((1, n), np.int32), W1) == 0
+    while o1.diag()["t"] < T:
+        assert o1.step(1) == 0
+    X, Y = np.meshgrid(r, r)
+    R = np.sqrt(X * X + Y * Y)
+    cfg2 = wl.base_config(dim=2, nx=n, ny=n, n_mat=1, x0=0.0, x1=L, y0=0.0, y1=L, gamma=[1.4],
+                          pinf=[0.0], bc=[wl.BC_REFLECTIVE, wl.BC_TRANSMISSIVE] * 2)
+    W2 = np.stack([np.where(R < 0.3, 1.0, 0.125), 0 * R, 0 * R, np.where(R < 0.3, 1.0, 0.1)])[None]
+    o2 = oracle.Oracle(cfg2)
+    assert o2.init(np.full((n, n), 8 * dx), np.zeros((n, n), np.int32), W2) == 0
+    while o2.diag()["t"] < o1.diag()["t"]:
+        assert o2.step(1) == 0
+    rho1 = o1.get()["Q"][0, 0, 0]
+    rho2 = o2.get()["Q"][0, 0, 0]
+    err = np.abs(rho1 - rho2).sum() / np.abs(rho2).sum()
+    print("t", o1.diag()["t"], o2.diag()["t"], "L1 rel", err)
+    assert abs(o1.diag()["t"] - o2.diag()["t"]) < 0.01
+    assert err < 0.025
+    s1 = np.argmax(np.abs(np.diff(rho1)))
+    s2 = np.argmax(np.abs(np.diff(rho2)))
+    assert abs(s1 - s2) <= 1
+
+
+def test_free_surface_planar_exact():
+    """A slab of gas at rest (rho 1, p 0.1, gamma 1.4) on [0, 0.6) with a free
+    surface at x = 0.6 under p = 13 (the ambient beyond is not solved): a
+    shock runs into the slab; the surface moves with the post-shock velocity
+    u* = -f(13) (Toro's pressure function of the slab state) and the density
+    behind the shock is the Rankine-Hugoniot one."""
+    n = 400
+    x, dx = radial(n, 1.0)
+    cfg = wl.base_config(dim=1, nx=n, ny=1, n_mat=2, x0=0.0, x1=1.0, gamma=[1.4, 1.4],
+                         pinf=[0.0, 0.0], bc=[wl.BC_REFLECTIVE, wl.BC_TRANSMISSIVE] * 2,
+                         fs_on=1, fs_mat=1, fs_p=[13.0, 13.0, 0.0, 1.0, 0.1])
+    xs0 = 0.6 + 0.3 * dx
+    chi = (x >= xs0).astype(np.int32)
+    phi = np.minimum(np.abs(x - xs0), 8 * dx)
+    W = np.zeros((2, 3, 1, n))
+    W[0, 0], W[0, 2] = 1.0, 0.1
+    W[1, 0], W[1, 2] = 0.1, 13.0
+    o = oracle.Oracle(cfg)
+    assert o.init(phi[None], chi[None], W) == 0
+    while o.diag()["t"] < 0.08:
+        assert o.step(1) == 0
+    t = o.diag()["t"]
+    g = o.get()
+    al = g["alpha"][0, 0]
+    xs = al.sum() * dx  # the slab ends where its volume ends
+    slab = Side(1.0, 0.0, 0.1, 1.4)
+    u_star = -slab.f(13.0)
+    assert abs(xs - (xs0 + u_star * t)) <= 0.5 * dx, (xs, xs0 + u_star * t)
+    g_ = 1.4
+    q = 13.0 / 0.1
+    rho_post = 1.0 * (q + (g_ - 1) / (g_ + 1)) / ((g_ - 1) / (g_ + 1) * q + 1)
+    # shock position: mass conservation, the slab mass between shock and surface
+    ws = (13.0 - 0.1) / (1.0 * -u_star)  # shock speed relative to the gas ahead
+    x_shock = xs0 - ws * t
+    mid = (x > x_shock + 6 * dx) & (x < xs - 6 * dx)
+    rho = g["Q"][0, 0, 0][mid] / al[mid]
+    assert mid.sum() > 5
+    # start-up errors of the moving surface stay in the post-shock plateau
+    # (within 2% here); its mean is the Rankine-Hugoniot density to 0.5%
+    assert abs(rho.mean() / rho_post - 1.0) < 0.005, (rho.mean(), rho_post)
+    assert np.abs(rho / rho_post - 1.0).max() < 0.025, (rho.min(), rho.max(), rho_post)
+
+
+def test_case_ii_paper_statements():
+    n = 320
+    w = wl.icf_1d(n=n)
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    dx = 1.5 / n
+    hist = []
+    while o.diag()["t"] < 0.3:
+        assert o.step(1) == 0
+        al = o.get()["alpha"]
+        rin = al[0, 0].sum() * dx
+        hist.append((o.diag()["t"], rin, rin + al[1, 0].sum() * dx))
+    h = np.array(hist)
+    thick = h[:, 2] - h[:, 1]
+    t_thin = h[np.argmin(thick), 0]
+    t_stag = h[np.argmin(h[:, 1]), 0]
+    print("thinnest shell at t =", t_thin, "stagnation at t =", t_stag)
+    # the outer interface moves inward from the start
+    assert h[10, 2] < 1.2 and np.all(np.diff(h[: len(h) // 2, 2]) <= 1e-12)
+    # the shell thins until about t = 0.047 (printed), then thickens
+    assert 0.04 <= t_thin <= 0.055
+    # stagnation (smallest inner radius) between t = 0.17 and 0.24 (printed)
+    assert 0.17 <= t_stag <= 0.24

@@ -318,6 +318,29 @@ def uniform_pressure_2d(nx=48, ny=40, shape="circle", p0=1.0, steps=100):
                 name="uniform_pressure_" + shape)
 
 
+# Case II's free-surface pressure law: 13 up to t = 0.04, then linear to 0.5
+# at t = 0.125, then 0.5; the ambient (not solved) has density 0.1
+ICF_PRESSURE = (13.0, 0.5, 0.04, 0.125, 0.1)
+
+
+def icf_1d(n=320, r_in=1.0, r_out=1.2, gammas=(1.667, 1.667, 1.667), steps=None, t_end=0.3):
+    """Case II: 1D cylindrical implosion on r in [0, 1.5] (Table 1): light
+    core (rho 0.05, p 0.1) for r < r_in, dense shell (rho 1, p 0.1) up to
+    r_out, ambient (rho 0.1, p 13) outside, all at rest; the ambient is not
+    solved and the shell's outer interface is a free surface under the
+    pressure law of ICF_PRESSURE.  Reflective axis."""
+    x, dx = _centres(n, 0.0, 1.5)
+    cfg = base_config(dim=1, nx=n, ny=1, x0=0.0, x1=1.5, gamma=list(gammas),
+                      pinf=[0.0, 0.0, 0.0], bc=[BC_REFLECTIVE, BC_TRANSMISSIVE] * 2,
+                      coord=1, fs_on=1, fs_mat=2, fs_p=list(ICF_PRESSURE))
+    chi = np.where(x < r_in, 0, np.where(x < r_out, 1, 2)).astype(np.int32)
+    phi = np.minimum(np.abs(x - r_in), np.abs(x - r_out))
+    phi = np.minimum(phi, cfg["band_ls"] * dx)
+    W = _fill_W(3, 1, (1, n), [(0.05, 0.0, 0.1), (1.0, 0.0, 0.1), (0.1, 0.0, 13.0)])
+    return dict(cfg=cfg, phi=phi[None], chi=chi[None], W=W, steps=steps, t_end=t_end,
+                name="icf_1d")
+
+
 def workload(name, **kw):
     """Named workloads with their full sizes and step counts."""
     if name == "shock_tube_1d":
