@@ -84,6 +84,24 @@ typedef struct {
    * the block; their distance is re-assigned from the outward-shifted
    * contour of the new material and their conserved quantities join it. */
   int32_t scale_sep;
+  /* 1D cylindrical geometry and free surfaces (Sec. 3, Case II: the
+   * implosion driven by a pressure on the shell's outer surface).
+   * coord = 1 (dim 1, x0 >= 0): x is the radius; faces have the area
+   * r_{i+-1/2}, cells the volume r_i dx, the radial momentum takes the
+   * geometric source alpha p / r_i, a cut cell's interface area follows
+   * from its faces and volume fraction, mixing exchanges r-weighted content,
+   * and the diagnostics' sum_Q, bnd_in and exch are totals of r_i Q_i.
+   * fs_on = 1 (dim 1, stiffened gases, HLLC): material fs_mat is an ambient
+   * that is not solved.  At every stage its state is density fs_p[4] at
+   * rest under p(t) (p(t) = fs_p[0] up to t = fs_p[2], linear to fs_p[1] at
+   * t = fs_p[3] > fs_p[2], fs_p[1] afterwards); its conserved quantities are
+   * alpha times that state; it has no fluxes and exchanges nothing; its
+   * interfaces are free surfaces whose pressure is p(t) and whose velocity
+   * is the solved side's wave jump to p(t); the step size also counts that
+   * wave.  All zero: planar geometry, every material solved.  The adjoint
+   * (record_tape) is not built for either. */
+  int32_t coord, fs_on, fs_mat;
+  double fs_p[5];
 } mm_config;
 enum { MM_EOS_STIFFENED = 0, MM_EOS_TAIT = 1 };
 enum { MM_FLUX_HLLC = 0, MM_FLUX_ROE = 1 };

@@ -44,7 +44,9 @@ class MMConfig(C.Structure):
                 ("k_ext", C.c_int32), ("band_ls", C.c_int32),
                 ("eos", C.c_int32 * MAX_MAT), ("rho0", C.c_double * MAX_MAT),
                 ("tait_B", C.c_double * MAX_MAT), ("p0", C.c_double * MAX_MAT),
-                ("flux", C.c_int32), ("scale_sep", C.c_int32)]
+                ("flux", C.c_int32), ("scale_sep", C.c_int32),
+                ("coord", C.c_int32), ("fs_on", C.c_int32), ("fs_mat", C.c_int32),
+                ("fs_p", C.c_double * 5)]
 
 
 class MMDiag(C.Structure):
@@ -156,6 +158,11 @@ def make_config(cfg):
         c.p0[m] = float(cfg.get("p0", [0.0] * M)[m])
     c.flux = int(cfg.get("flux", 0))
     c.scale_sep = int(cfg.get("scale_sep", 0))
+    c.coord = int(cfg.get("coord", 0))
+    c.fs_on = int(cfg.get("fs_on", 0))
+    c.fs_mat = int(cfg.get("fs_mat", 0))
+    for q, x in enumerate(cfg.get("fs_p", [0.0] * 5)):
+        c.fs_p[q] = float(x)
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])

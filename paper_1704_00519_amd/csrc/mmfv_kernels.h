@@ -290,6 +290,87 @@ MMD Prim Wget(const Params& P, const Bufs& B, const double* Qs,
 }
 
 // ---------------------------------------------------------------------------
+// Cylindrical geometry and free surfaces (Sec. 3, Case II)
+// ---------------------------------------------------------------------------
+// x0 + i dx: the radius of face i - 1/2 for an integer i, of the centre of
+// cell i for i + 0.5
+MMD double rad(const Params& P, double i) { return P.x0 + i * P.dx; }
+// the ambient of a free surface: not solved
+MMD bool passive(const Params& P, int r) { return P.fs_on && r == P.fs_mat; }
+// time of the input state of stage s: t_n, then t_n + dt (and t_n + dt/2
+// for the third stage of RK3)
+MMD double stage_time(const Bufs& B, int s) {
+  double t = B.scal[S_T];
+  return s == 0 ? t : t + (s == 1 ? 1.0 : 0.5) * B.scal[S_DT];
+}
+// surface pressure p(t): p_hi up to t0, linear to p_lo at t1, p_lo after
+MMD double fs_pressure(const Params& P, double t) {
+  const double* f = P.fs_p;
+  if (t <= f[2]) return f[0];
+  if (t >= f[3]) return f[1];
+  return f[0] - (f[0] - f[1]) * (t - f[2]) / (f[3] - f[2]);
+}
+// velocity jump across the wave that brings a stiffened-gas state of
+// material m (density rho, pressure p) to the pressure ps: Toro's pressure
+// function with pressures shifted by p_inf (shock for ps > p, else
+// rarefaction)
+MMD double wave_jump(const Params& P, int m, double rho, double p, double ps) {
+  double g = P.gamma[m], pinf = P.pinf[m];
+  double pb = p + pinf, psb = ps + pinf;
+  if (ps > p) {
+    double A = 2.0 / ((g + 1.0) * rho);
+    double Bs = (g - 1.0) / (g + 1.0) * pb;
+    return (ps - p) * sqrt(A / (psb + Bs));
+  }
+  double c = sqrt(g * pb / rho);
+  return 2.0 * c / (g - 1.0) * (::pow(psb / pb, (g - 1.0) / (2.0 * g)) - 1.0);
+}
+// wave speed bound of a free surface in a cell whose material m has the
+// state w: max(|u|, |v|) + |du| + the wave's front speed relative to the
+// material (c for a rarefaction, the stiffened-gas shock speed
+// c sqrt(1 + (g + 1)/(2 g) (ps - p)/(p + p_inf)) for a shock)
+MMD double fs_speed(const Params& P, int m, const Prim& w, double ps) {
+  double g = P.gamma[m];
+  double pb = w.p + P.pinf[m];
+  double c = sqrt(g * pb / w.r);
+  if (ps > w.p) c = c * sqrt(1.0 + (g + 1.0) / (2.0 * g) * ((ps - w.p) / pb));
+  double u = fabs(w.u), v = fabs(w.v);
+  return (u > v ? u : v) + fabs(wave_jump(P, m, w.r, w.p, ps)) + c;
+}
+// The ambient at stage s, cell k (any cell of the padded array): its state is
+// the prescribed one (density fs_p[4], at rest, under p of the stage's time)
+// and valid; in interior cells its conserved quantities in buffer sidx are
+// alpha U of that state, the occupancy following
+template <int D>
+MMD void b_ambient(const Params& P, const Bufs& B, int k, int sidx, int s) {
+  int r = P.fs_mat;
+  double p = fs_pressure(P, stage_time(B, s)), rho = P.fs_p[4];
+  size_t o = (size_t)r * 4 * P.NC + k;
+  B.W[o] = rho;
+  B.W[o + (size_t)P.NC] = 0.0;
+  B.W[o + (size_t)2 * P.NC] = 0.0;
+  B.W[o + (size_t)3 * P.NC] = p;
+  B.Wit[(size_t)r * P.NC + k] = 1;
+  int i = k % P.NX - H, j = k / P.NX - P.HY;
+  if (!interior(P, i, j)) return;
+  double a = alpha_at<D>(P, B, r, k);
+  double U[4] = {rho, 0.0, 0.0, total_energy(rho, 0.0, 0.0, p, P.gamma[r], P.pinf[r], P.igm1[r])};
+  bool nz = false;
+  for (int v = 0; v < 4; v++) {
+    double x = a > 0.0 ? a * U[v] : 0.0;
+    storeQ<D>(P, B.Q[sidx], r, v, k, x);
+    if (x != 0.0 && !(D == 1 && v == 2)) nz = true;
+  }
+  unsigned occ = B.occ[sidx][k];
+  B.occ[sidx][k] = (uint8_t)(nz ? occ | (1u << r) : occ & ~(1u << r));
+}
+template <int D>
+__global__ void __launch_bounds__(256) k_ambient(Params P, Bufs B, int sidx, int s) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < P.NC) b_ambient<D>(P, B, k, sidx, s);
+}
+
+// ---------------------------------------------------------------------------
 // Boundary frames
 // ---------------------------------------------------------------------------
 MMD int src_lo(int i, int type) { return type == 1 ? -1 - i : 0; }
@@ -710,6 +791,13 @@ MMD void b_geom(const Params& P, const Bufs& B, int i, int j, int midx, const do
       B.ax[(size_t)r * P.NC + k] = Ar;
       if (i == 0) B.ax[(size_t)r * P.NC + kl] = Al;
       B.cx[(size_t)r * P.NC + k] = Ar - Al;
+      if (P.coord == 1)
+        // cylindrical: interface area per cell volume r_i dx from the faces'
+        // areas and the volume fraction (alpha dx = r_s - r_{i-1/2} for a
+        // material on the inner side), so that a uniform pressure balances
+        // faces, geometric source and exchange
+        B.cx[(size_t)r * P.NC + k] =
+            ((Ar * rad(P, i + 1) - Al * rad(P, i)) - al[r] * P.dx) / rad(P, i + 0.5);
       B.cy[(size_t)r * P.NC + k] = 0.0;
       continue;
     }
@@ -851,6 +939,7 @@ MMD void b_real(const Params& P, const Bufs& B, int i, int j, int sidx) {
   if (errored(B) || B.dcut[k] > 7) return;
   for (int r = 0; r < P.M; r++) B.Wit[(size_t)r * P.NC + k] = 0;
   int r = B.chi[k];
+  if (passive(P, r)) return;  // set by the ambient pass
   double a = B.cut[k] ? B.al[(size_t)r * P.NC + k] : 1.0;
   if (!(a > 0.0)) return;
   const double* Q = B.Q[sidx];
@@ -876,13 +965,19 @@ template <int D>
 MMD double b_dt_cell(const Params& P, const Bufs& B, int i, int j, int sidx) {
   int k = cid(P, i, j), r = B.chi[k];
   double w = 0.0;
-  if (alpha_at<D>(P, B, r, k) > 0.0) {
+  if (alpha_at<D>(P, B, r, k) > 0.0 && !passive(P, r)) {
     bool valid;
     Prim s = Wget<D>(P, B, B.Q[sidx], B.occ[sidx], r, i, j, valid);
     double c = sqrt(P.gamma[r] * (s.p + P.pinf[r]) / s.r);
     double a = fabs(s.u) + c, b = fabs(s.v) + c;
     w = a > b ? a : b;
     if (!(w > 0.0)) w = 0.0;
+    // a free surface in the cell: its wave against the prescribed pressure
+    // (time t_n) bounds the step too
+    if (P.fs_on && ((B.xs[k] >> P.fs_mat) & 1) && ((B.xs[k] >> r) & 1)) {
+      double f = fs_speed(P, r, s, fs_pressure(P, B.scal[S_T]));
+      if (f > w) w = f;
+    }
   }
   return w;
 }
@@ -1001,8 +1096,9 @@ MMD void b_ext(const Params& P, const Bufs& B, int i, int j, int sidx, int sweep
 // Reduced interface interaction (Sec. 2.3.2) in cut cells
 // ---------------------------------------------------------------------------
 template <int D>
-MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int stage0) {
+MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int stage) {
   int k = cid(P, i, j);
+  bool stage0 = stage == 0;
   (void)k;
   if (errored(B) || !B.cut[k]) return;
   for (int r = 0; r < P.M; r++)
@@ -1040,20 +1136,31 @@ MMD void b_iface(const Params& P, const Bufs& B, int i, int j, int sidx, int sta
   R.u = Wa.u * nxv + Wa.v * nyv;
   R.v = 0.0;
   R.p = Wa.p;
-  double SL, SR;
-  wave_speeds(L, eos_of(P, bb), R, eos_of(P, a), SL, SR);
-  double SM = contact_speed(L, R, SL, SR);
-  double ps = 0.5 * ((L.p + L.r * (SL - L.u) * (SM - L.u)) +
-                     (R.p + R.r * (SR - R.u) * (SM - R.u)));
+  double SM, ps;
+  bool pa = passive(P, a), pb = passive(P, bb);
+  if (pa || pb) {
+    // free surface (Sec. 3 Case II): the pressure is prescribed, and the
+    // surface moves with the velocity the solved side's wave reaches at it
+    // (the solved side is R when it is a, L otherwise, along n)
+    ps = fs_pressure(P, stage_time(B, stage));
+    SM = pb ? R.u + wave_jump(P, a, R.r, R.p, ps) : L.u - wave_jump(P, bb, L.r, L.p, ps);
+  } else {
+    double SL, SR;
+    wave_speeds(L, eos_of(P, bb), R, eos_of(P, a), SL, SR);
+    SM = contact_speed(L, R, SL, SR);
+    ps = 0.5 * ((L.p + L.r * (SL - L.u) * (SM - L.u)) +
+                (R.p + R.r * (SR - R.u) * (SM - R.u)));
+  }
   double X1 = ps * cxa, X2 = ps * cya, X3 = ps * SM * nrm;
   size_t oa = (size_t)a * 4 * P.NC, ob = (size_t)bb * 4 * P.NC;
-  B.X[oa + (size_t)1 * P.NC + k] = X1;
-  B.X[oa + (size_t)2 * P.NC + k] = X2;
-  B.X[oa + (size_t)3 * P.NC + k] = X3;
-  B.X[ob + k] = -0.0;
-  B.X[ob + (size_t)1 * P.NC + k] = -X1;
-  B.X[ob + (size_t)2 * P.NC + k] = -X2;
-  B.X[ob + (size_t)3 * P.NC + k] = -X3;
+  // nothing is exchanged with an ambient that is not solved
+  B.X[oa + (size_t)1 * P.NC + k] = pa ? 0.0 : X1;
+  B.X[oa + (size_t)2 * P.NC + k] = pa ? 0.0 : X2;
+  B.X[oa + (size_t)3 * P.NC + k] = pa ? 0.0 : X3;
+  B.X[ob + k] = pb ? 0.0 : -0.0;
+  B.X[ob + (size_t)1 * P.NC + k] = pb ? 0.0 : -X1;
+  B.X[ob + (size_t)2 * P.NC + k] = pb ? 0.0 : -X2;
+  B.X[ob + (size_t)3 * P.NC + k] = pb ? 0.0 : -X3;
   if (stage0) {
     B.vx[k] = SM * nxv;
     B.vy[k] = SM * nyv;
@@ -1277,7 +1384,7 @@ MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int
   const uint8_t* on = B.occ[nidx];
   double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
   // non-cut cells are real cells of their material: check them here
-  if (!B.cut[k]) {
+  if (!B.cut[k] && !passive(P, B.chi[k])) {
     bool vd;
     int r = B.chi[k];
     Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
@@ -1287,9 +1394,19 @@ MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int
   unsigned occ = 0;
   unsigned long long nact = 0;
   for (int r = 0; r < P.M; r++)
-    if (alpha_at<D>(P, B, r, k) > 0.0) nact++;
+    if (alpha_at<D>(P, B, r, k) > 0.0 && !passive(P, r)) nact++;
   wave_count(&B.ctr[C_UPD], (unsigned)nact);
   for (int r = 0; r < P.M; r++) {
+    if (passive(P, r)) {
+      // an ambient that is not solved: the stage leaves it as it is
+      bool nz = false;
+      for (int v = 0; v < 4; v++) {
+        out[r][v] = loadQ<D>(P, Qs, os, r, v, k);
+        if (out[r][v] != 0.0 && !(D == 1 && v == 2)) nz = true;
+      }
+      if (nz) occ |= 1u << r;
+      continue;
+    }
     double Fl[4] = {0, 0, 0, 0}, Fr[4] = {0, 0, 0, 0}, Fb[4] = {0, 0, 0, 0},
            Ft[4] = {0, 0, 0, 0};
     double Al = apx<D>(P, B, r, i - 1, j), Ar = apx<D>(P, B, r, i, j);
@@ -1311,6 +1428,14 @@ MMD void b_flux_band(const Params& P, const Bufs& B, int i, int j, int sidx, int
       double fl = Al > 0.0 ? Al * Fl[v] : 0.0;
       double fr = Ar > 0.0 ? Ar * Fr[v] : 0.0;
       double rhs = lx * (fl - fr);
+      if (D == 1 && P.coord == 1) {
+        // cylindrical: face areas per cell volume, geometric source
+        double ri = rad(P, i + 0.5);
+        rhs = lx * (fl * rad(P, i) - fr * rad(P, i + 1)) / ri;
+        bool vd;
+        Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
+        if (v == 1 && vd) rhs = rhs + B.scal[S_DT] * (alpha_at<D>(P, B, r, k) * w.p / ri);
+      }
       if (D == 2) {
         double fb = Ab > 0.0 ? Ab * Fb[v] : 0.0;
         double ft = At > 0.0 ? At * Ft[v] : 0.0;
@@ -1579,9 +1704,11 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
   bool isb = inb && B.bulk[k];
   int nb = __syncthreads_count(isb);
   if (nb == 0 || errored(B)) return;  // uniform across the workgroup
+  // updates of solved materials (an ambient that is not solved is copied)
+  int nu = P.fs_on ? __syncthreads_count(isb && B.chi[k] != P.fs_mat) : nb;
   if (tid == 0) {
-    atomicAdd(&B.ctr[C_UPD], (unsigned long long)nb);
-    atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nb);
+    atomicAdd(&B.ctr[C_UPD], (unsigned long long)nu);
+    atomicAdd(&B.ctr[stage0 ? C_UPDB0 : C_UPDB1], (unsigned long long)nu);
   }
   const double* Qs = B.Q[sidx];
   for (int q = tid; q < T + 6; q += T) {
@@ -1619,6 +1746,7 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
     // face f: between tile cells f-1 and f
     if (!(S.bulk[f] || S.bulk[f + 1])) continue;
     int m = S.bulk[f + 1] ? S.chi[f + 3] : S.chi[f + 2];
+    if (passive(P, m)) continue;  // no fluxes of an ambient that is not solved
     double pinf = P.pinf[m];
     const double* R0 = S.W[0];
     const double* U0 = S.W[1];
@@ -1659,7 +1787,13 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
     S.F[2][f] = G[3];
   }
   __syncthreads();
-  if (isb) {
+  if (isb && passive(P, S.chi[tid + 3])) {
+    // an ambient that is not solved: the stage leaves it as it is
+    int m = S.chi[tid + 3];
+    size_t o = (size_t)m * 3 * P.NC + k;
+    for (int v = 0; v < 3; v++) B.Q[didx][o + (size_t)v * P.NC] = Qs[o + (size_t)v * P.NC];
+    B.occ[didx][k] = (uint8_t)(1u << m);
+  } else if (isb) {
     int m = S.chi[tid + 3];
     Prim w;
     w.r = S.W[0][tid + 3];
@@ -1673,6 +1807,13 @@ MMD void bulk1_tile(const Params& P, const Bufs& B, Bulk1Smem& S, int i0, int si
     double* Qd = B.Q[didx];
     for (int v = 0; v < 3; v++) {
       double rhs = lx * (S.F[v][tid] - S.F[v][tid + 1]);
+      if (P.coord == 1) {
+        // cylindrical: face areas r_{i-1/2}, r_{i+1/2} per volume r_i dx,
+        // and the geometric source alpha p / r_i of the radial momentum
+        double ri = rad(P, i + 0.5);
+        rhs = lx * (S.F[v][tid] * rad(P, i) - S.F[v][tid + 1] * rad(P, i + 1)) / ri;
+        if (v == 1) rhs = rhs + B.scal[S_DT] * (1.0 * w.p / ri);
+      }
       rhs = rhs + lv * 0.0;
       double qs = Qs[o + (size_t)v * P.NC];
       double x = stage0 ? (qs + rhs) : (bcoef * Qn[o + (size_t)v * P.NC] + ccoef * (qs + rhs));
@@ -1788,7 +1929,12 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
       inn[n] = row && interior(P, i + di, j + dj);
     }
   uint8_t chk = B.chi[k];
+  // cylindrical: volumes and contents carry the cells' radii (the exchange
+  // is of content: alpha r and Q r in place of alpha and Q)
+  bool cyl = D == 1 && P.coord == 1;
+  double rs = cyl ? rad(P, i + 0.5) : 1.0;
   for (int r = r0; r < r1; r++) {
+    if (passive(P, r)) continue;  // an ambient that is not solved
     // every load of this material that does not depend on a decision below,
     // issued together: the cell's volume fraction and state, the level set
     // of the four face neighbours, volume fraction and indicator of all eight
@@ -1898,14 +2044,23 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
     }
     B.srcStamp[(size_t)r * P.NC + k] = stamp;
     for (int v = 0; v < 4; v++) {
-      double Qs = qk[v], acc = Qs;
+      // a vanishing cell sends its content (Q r in cylindrical geometry)
+      double Qs = qk[v];
+      if (cyl && !(as > 0.0)) Qs = Qs * rs;
+      double acc = Qs;
       for (int q = 0; q < 3; q++) {
         if (tk[q] < 0) continue;
         double m;
         if (as > 0.0) {
           double at2 = an[tn[q]];
           double Qt = qt[q][v];
-          m = beta[q] * ((as * Qt - at2 * Qs) / (as + at2));
+          if (cyl) {
+            double rt = rad(P, (i + (tn[q] % 3 - 1)) + 0.5);
+            double aS = as * rs, aT = at2 * rt, qS = Qs * rs, qT = Qt * rt;
+            m = beta[q] * ((aS * qT - aT * qS) / (aS + aT));
+          } else {
+            m = beta[q] * ((as * Qt - at2 * Qs) / (as + at2));
+          }
         } else {
           m = q == last ? -acc : -(beta[q] * Qs);
           acc = acc + m;
@@ -2094,6 +2249,10 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
   uint8_t* occp = B.occ[didx];
   unsigned occ = occp[k];
   bool touched = false;
+  // cylindrical: exchanges are of content, the cell's state changes by
+  // them over its radius
+  bool cyl = D == 1 && P.coord == 1;
+  double rc = cyl ? rad(P, i + 0.5) : 1.0;
   for (int r = r0; r < r1; r++) {
     bool src = B.srcStamp[(size_t)r * P.NC + k] == stamp;
     bool tgt = B.tgtStamp[(size_t)r * P.NC + k] == stamp;
@@ -2127,7 +2286,7 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
       size_t ov = (size_t)v * P.NC;
       if (src) {
         for (int q = 0; q < 3; q++)
-          if (mrow[0][q]) q0 = q0 + mrow[0][q][ov];
+          if (mrow[0][q]) q0 = cyl ? q0 + mrow[0][q][ov] / rc : q0 + mrow[0][q][ov];
       } else {
         double row[3];
         for (int dj = 0; dj < 3; dj++) {
@@ -2136,7 +2295,7 @@ MMD void b_mix2(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
           double a2 = mrow[dj][2] ? mrow[dj][2][ov] : 0.0;
           row[dj] = (a0 + a2) + a1;
         }
-        q0 = q0 - ((row[0] + row[2]) + row[1]);
+        q0 = cyl ? q0 - ((row[0] + row[2]) + row[1]) / rc : q0 - ((row[0] + row[2]) + row[1]);
       }
       nq[v] = q0;
       if (q0 != 0.0 && !(D == 1 && v == 2)) nz = true;
@@ -2245,7 +2404,8 @@ MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, in
       // face f: 0 low x, 1 high x, 2 low y, 3 high y
       int dir = f >> 1, fi = f == 0 ? i - 1 : i, fj = f == 2 ? j - 1 : j;
       bool count = f == 0 ? i == 0 : (f == 2 ? j == 0 : true);
-      double A = apd(P, B, r, fi, fj, dir);
+      // no fluxes of an ambient that is not solved
+      double A = passive(P, r) ? 0.0 : apd(P, B, r, fi, fj, dir);
       double F[4] = {0.0, 0.0, 0.0, 0.0};
       if (A > 0.0) face_flux<D, FLUX>(P, B, Qs, os, r, fi, fj, dir, count, F);
       for (int v = 0; v < 4; v++) sF[tid][v] = A > 0.0 ? A * F[v] : 0.0;
@@ -2255,12 +2415,24 @@ MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, in
       const double* Qn = B.Q[nidx];
       const uint8_t* on = B.occ[nidx];
       double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+      bool pas = passive(P, r);
       // non-cut cells are real cells of their material: checked by that
       // material's thread
-      if (!B.cut[k] && r == B.chi[k]) {
+      if (!B.cut[k] && r == B.chi[k] && !pas) {
         bool vd;
         Prim w = Wget<D>(P, B, Qs, os, r, i, j, vd);
         if (nonphys(w, P.pinf[r])) flag_error(P, B, i, j);
+      }
+      // cylindrical: radii of the faces and the centre, and the state whose
+      // pressure gives the geometric source
+      double rl = 0.0, rr = 0.0, ri = 1.0, src = 0.0;
+      bool hsrc = false;
+      if (D == 1 && P.coord == 1 && !pas) {
+        rl = rad(P, i);
+        rr = rad(P, i + 1);
+        ri = rad(P, i + 0.5);
+        Prim w = Wget<D>(P, B, Qs, os, r, i, j, hsrc);
+        if (hsrc) src = B.scal[S_DT] * (alpha_at<D>(P, B, r, k) * w.p / ri);
       }
       double out[4];
       bool nz = false;
@@ -2269,12 +2441,22 @@ MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, in
           out[v] = 0.0;
           continue;
         }
+        double qs = loadQ<D>(P, Qs, os, r, v, k);
+        if (pas) {
+          // an ambient that is not solved: the stage leaves it as it is
+          out[v] = qs;
+          if (qs != 0.0) nz = true;
+          continue;
+        }
         double rhs = lx * (sF[tid][v] - sF[tid + 1][v]);
+        if (D == 1 && P.coord == 1) {
+          rhs = lx * (sF[tid][v] * rl - sF[tid + 1][v] * rr) / ri;
+          if (v == 1 && hsrc) rhs = rhs + src;
+        }
         if (D == 2) rhs = rhs + ly * (sF[tid + 2][v] - sF[tid + FPC - 1][v]);
         double X = B.cut[k] ? B.X[((size_t)r * 4 + v) * P.NC + k] : 0.0;
         rhs = rhs + lv * X;
         double qn = loadQ<D>(P, Qn, on, r, v, k);
-        double qs = loadQ<D>(P, Qs, os, r, v, k);
         double x = bcoef * qn + ccoef * (qs + rhs);
         out[v] = x;
         if (x != 0.0) nz = true;
@@ -2283,7 +2465,7 @@ MMD void flux_list_blocks(const Params& P, const Bufs& B, int sidx, int nidx, in
         atomicOr(&sOcc[c], 1u << r);
         for (int v = 0; v < 4; v++) storeQ<D>(P, B.Q[didx], r, v, k, out[v]);
       }
-      wave_count(&B.ctr[C_UPD], alpha_at<D>(P, B, r, k) > 0.0 ? 1u : 0u);
+      wave_count(&B.ctr[C_UPD], alpha_at<D>(P, B, r, k) > 0.0 && !pas ? 1u : 0u);
     }
     __syncthreads();
     if (tid < cpb && base + tid < nb) B.occ[didx][B.blist[base + tid]] = (uint8_t)sOcc[tid];
@@ -2415,6 +2597,12 @@ MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int 
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* part = B.cpart + ((size_t)bx * P.M + r) * 8;
   bool any = true;
+  if (passive(P, r)) {
+    // an ambient that is not solved has no fluxes and exchanges nothing
+    if (threadIdx.x == 0)
+      for (int v = 0; v < 8; v++) part[v] = 0.0;
+    return;
+  }
   if (bx < nbb) {
     // thread t: face (side t & 1) of row/column q
     int t = threadIdx.x, row = t >> 1, side = t & 1;
@@ -2427,7 +2615,11 @@ MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int 
     __syncthreads();
     if (ok && side == 0) {
       double l = dir == 0 ? B.scal[S_LX] : B.scal[S_LY];
-      for (int v = 0; v < 4; v++) acc[v] = l * (face[row][0][v] - face[row][1][v]);
+      // cylindrical: the faces' radii (totals of r_i Q_i)
+      double rlo = P.coord == 1 ? rad(P, 0) : 1.0, rhi = P.coord == 1 ? rad(P, P.nx) : 1.0;
+      for (int v = 0; v < 4; v++)
+        acc[v] = P.coord == 1 ? l * (face[row][0][v] * rlo - face[row][1][v] * rhi)
+                              : l * (face[row][0][v] - face[row][1][v]);
     }
   } else {
     // cell indices fit 32 bits (the cell count NC is an int); the cut flags
@@ -2445,11 +2637,35 @@ MMD void cons_part_block(const Params& P, const Bufs& B, int sidx, int nbb, int 
     }
     bool mine = false;
     double lv = B.scal[S_LV];
+    if (D == 1 && P.coord == 1) {
+      // cylindrical: r-weighted exchange of the cut cells and the geometric
+      // source alpha p dt of every cell where the material has a state
+      double dt = B.scal[S_DT];
+      for (int u = 0; u < NQ; u++) {
+        int q = q0 + (int)threadIdx.x + u * 256;
+        if (q >= n) continue;
+        double ri = rad(P, q + 0.5);
+        if (cq[u]) {
+          mine = true;
+          for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + kq[u]] * ri;
+        }
+        double a = alpha_at<D>(P, B, r, kq[u]);
+        if (a > 0.0) {
+          bool vd;
+          Prim w = Wget<D>(P, B, Qs, os, r, q, 0, vd);
+          if (vd) {
+            acc[5] += dt * (a * w.p);
+            mine = true;
+          }
+        }
+      }
+    } else {
 #pragma unroll
-    for (int u = 0; u < NQ; u++) {
-      if (!cq[u]) continue;
-      mine = true;
-      for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + kq[u]];
+      for (int u = 0; u < NQ; u++) {
+        if (!cq[u]) continue;
+        mine = true;
+        for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + kq[u]];
+      }
     }
     any = __syncthreads_or(mine);
   }
@@ -2496,7 +2712,11 @@ MMD void qsum_range(const Params& P, const Bufs& B, int sidx, int r, long q0, lo
   for (int v = 0; v < 8; v++) acc[v] = 0.0;
   for (long q = q0 + tid; q < q1; q += T) {
     int k = cid(P, (int)(q % P.nx), (int)(q / P.nx));
-    for (int v = 0; v < 4; v++) acc[v] += loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, v, k);
+    // cylindrical: totals of r_i Q_i
+    double ri = P.coord == 1 ? rad(P, (double)q + 0.5) : 1.0;
+    for (int v = 0; v < 4; v++)
+      acc[v] += P.coord == 1 ? loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, v, k) * ri
+                             : loadQ<D>(P, B.Q[sidx], B.occ[sidx], r, v, k);
   }
 }
 
@@ -2665,7 +2885,7 @@ __global__ void __launch_bounds__(256) t_near_col_flags(Params P, Bufs B, int si
 // exchange reads the states of its own cut cell only, the frame neither the
 // exchange terms nor the velocities it writes.
 template <int D>
-__global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx, int stage0,
+__global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx, int stage,
                                                      int ntb, int ndt) {
   // with ndt > 0 the last workgroup sets the step size from the ndt wave-speed
   // maxima of the bulk-flag workgroups (nothing else in this launch reads it)
@@ -2675,7 +2895,7 @@ __global__ void __launch_bounds__(256) t_iface_frame(Params P, Bufs B, int sidx,
   }
   if ((int)blockIdx.x < ntb) {
     for_tiles_n(P, B, (int)blockIdx.x, ntb,
-                [&](int i, int j) { b_iface<D>(P, B, i, j, sidx, stage0); });
+                [&](int i, int j) { b_iface<D>(P, B, i, j, sidx, stage); });
     return;
   }
   int t = ((int)blockIdx.x - ntb) * (int)blockDim.x + (int)threadIdx.x;
@@ -3235,6 +3455,10 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
     for (int s = 0; s < ns; s++) {
       int didx = s == ns - 1 ? 0 : s + 1;
       PHASE(b_real<1>(P, B, i_, 0, sidx));
+      if (P.fs_on) {
+        for (int k = tid; k < P.NC; k += T) b_ambient<1>(P, B, k, sidx, s);
+        __syncthreads();
+      }
       if (s == 0) {
         double w = 0.0;
         for (int i = tid; i < P.nx; i += T) w = fmax(w, b_dt_cell<1>(P, B, i, 0, sidx));
@@ -3253,7 +3477,7 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
       for (int t = tid; t < 2 * H * P.M; t += T) b_bc_W_x<1>(P, B, t, sidx);
       __syncthreads();
       if (s == 0) PHASE(b_vreset<1>(P, B, i_, 0));
-      PHASE(b_iface<1>(P, B, i_, 0, sidx, s == 0 ? 1 : 0));
+      PHASE(b_iface<1>(P, B, i_, 0, sidx, s));
       if (s == 0) {
         for (int sw = 0; sw < 4; sw++) PHASE(b_vext<1>(P, B, i_, 0, sw));
         PHASE(b_vfill<1>(P, B, i_, 0, sidx));
@@ -3269,16 +3493,31 @@ k_batch1d(const Params* Pa, const Bufs* Ba, int nsteps, int rk_order) {
         if (tid < 2 * P.M)
           cons_face<1>(P, B, B.Q[sidx], B.occ[sidx], tid >> 1, 0, 0, tid & 1, fb + tid * 4);
         __syncthreads();
-        double lv = B.scal[S_LV], lx = B.scal[S_LX];
+        double lv = B.scal[S_LV], lx = B.scal[S_LX], dt = B.scal[S_DT];
+        bool cyl = P.coord == 1;
         for (int r = 0; r < P.M; r++) {
+          // an ambient that is not solved: nothing to book
+          if (passive(P, r)) continue;
           double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
           for (int i = tid; i < P.nx; i += T) {
             int k = cid(P, i, 0);
+            double ri = cyl ? rad(P, i + 0.5) : 1.0;
             if (B.cut[k])
-              for (int v = 0; v < 4; v++) acc[4 + v] += lv * B.X[((size_t)r * 4 + v) * P.NC + k];
+              for (int v = 0; v < 4; v++)
+                acc[4 + v] += cyl ? lv * B.X[((size_t)r * 4 + v) * P.NC + k] * ri
+                                  : lv * B.X[((size_t)r * 4 + v) * P.NC + k];
+            // cylindrical: geometric source of the radial momentum
+            double a = cyl ? alpha_at<1>(P, B, r, k) : 0.0;
+            if (a > 0.0) {
+              bool vd;
+              Prim w = Wget<1>(P, B, B.Q[sidx], B.occ[sidx], r, i, 0, vd);
+              if (vd) acc[5] += dt * (a * w.p);
+            }
           }
           if (tid == 0)
-            for (int v = 0; v < 4; v++) acc[v] = lx * (fb[2 * r * 4 + v] - fb[(2 * r + 1) * 4 + v]);
+            for (int v = 0; v < 4; v++)
+              acc[v] = cyl ? lx * (fb[2 * r * 4 + v] * rad(P, 0) - fb[(2 * r + 1) * 4 + v] * rad(P, P.nx))
+                           : lx * (fb[2 * r * 4 + v] - fb[(2 * r + 1) * 4 + v]);
           block_sum8(acc, sm.red + 64);
           if (tid == 0) cons_accumulate(B, r, acc, wc[s]);
         }

@@ -180,6 +180,20 @@ static bool valid_config(const mm_config* c, std::string& why) {
   if (c->flux == MM_FLUX_ROE)
     for (int m = 0; m < c->n_mat; m++)
       if (c->eos[m] == MM_EOS_TAIT) return why = "the Roe flux takes stiffened gases only", false;
+  if (c->coord != 0 && c->coord != 1) return why = "coord must be 0 or 1", false;
+  if (c->coord == 1 && (c->dim != 1 || !(c->x0 >= 0.0)))
+    return why = "cylindrical geometry needs dim 1 and x0 >= 0", false;
+  if (c->fs_on != 0 && c->fs_on != 1) return why = "fs_on must be 0 or 1", false;
+  if (c->fs_on) {
+    if (c->dim != 1) return why = "free surfaces are built for dim 1", false;
+    if (c->fs_mat < 0 || c->fs_mat >= c->n_mat) return why = "bad fs_mat", false;
+    if (!(c->fs_p[4] > 0.0) || !(c->fs_p[3] > c->fs_p[2]) || !std::isfinite(c->fs_p[0]) ||
+        !std::isfinite(c->fs_p[1]) || !std::isfinite(c->fs_p[3]))
+      return why = "free surface needs a finite p(t), t1 > t0 and an ambient density > 0", false;
+    if (c->flux != MM_FLUX_HLLC) return why = "free surfaces take the HLLC flux only", false;
+    for (int m = 0; m < c->n_mat; m++)
+      if (c->eos[m] == MM_EOS_TAIT) return why = "free surfaces take stiffened gases only", false;
+  }
   for (int q = 0; q < 4; q++)
     if (c->bc[q] < 0 || c->bc[q] > 3) return why = "bad boundary code", false;
   if (c->inflow_mat < 0 || c->inflow_mat >= c->n_mat) return why = "bad inflow_mat", false;
@@ -234,6 +248,11 @@ static Params make_params(const mm_config* cfg) {
   }
   P.flux = cfg->flux == MM_FLUX_ROE ? FLUX_ROE : FLUX_HLLC;
   P.scale_sep = cfg->scale_sep;
+  P.coord = cfg->coord;
+  P.fs_on = cfg->fs_on;
+  P.fs_mat = cfg->fs_mat;
+  P.x0 = cfg->x0;
+  for (int q = 0; q < 5; q++) P.fs_p[q] = cfg->fs_p[q];
   for (int q = 0; q < 4; q++) {
     P.bc[q] = cfg->bc[q];
     P.inflow_W[q] = cfg->inflow_W[q];
@@ -458,6 +477,10 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   dim3 tg = tile_grid(c), tb(256);
   LAUNCH(t_real_near_row<D>, dim3(2 * tg.x + (pre.n ? 256 : 0)), tb, P, c->B, sidx, (int)tg.x,
          pre);
+  // the ambient of a free surface: its prescribed state and conserved
+  // quantities at the stage's time (before the ghost queue and the bulk
+  // flags, which read its validity and occupancy)
+  if (P.fs_on) LAUNCH(k_ambient<D>, lin_grid(P.NC), dim3(256), P, c->B, sidx, s);
   LAUNCH(t_near_col_flags<D>, dim3(tg.x + g.x * g.y), tb, P, c->B, sidx, nidx, s == 0 ? 1 : 0,
          (int)tg.x, (int)g.x, (int)g.y, (int)bl.x);
   static_assert(EXR >= 8 + 4, "the tile frame covers every sweep (k_ext <= 8)");
@@ -470,7 +493,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   long nframe = (D == 2 ? (long)P.ny + P.nx + 2 * H : (long)P.ny) * 2 * H * P.M;
   int ndt = s == 0 ? (int)(g.x * g.y) : 0;  // stage 0: one more workgroup sets the step size
   LAUNCH(t_iface_frame<D>, dim3(tg.x + lin_grid(nframe).x + (ndt ? 1 : 0)), tb, P, c->B, sidx,
-         s == 0 ? 1 : 0, (int)tg.x, ndt);
+         s, (int)tg.x, ndt);
   if (s == 0 && D == 2) {
     LAUNCH(k_vext_tiles, tg, tb, P, c->B, sidx);
   } else if (s == 0) {
@@ -782,6 +805,8 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
   if (record_tape < 0) return fail(c, MM_EINVAL, "record_tape < 0");
   if (record_tape > 0 && c->P.flux != FLUX_HLLC)
     return fail(c, MM_ENOTIMPL, "the adjoint is built for the HLLC face flux only");
+  if (record_tape > 0 && (c->P.coord != 0 || c->P.fs_on))
+    return fail(c, MM_ENOTIMPL, "the adjoint is built for planar geometry without free surfaces");
   if (record_tape > 0) return step_record(c, n_steps, record_tape, t_out);
   c->tape_K = 0;  // plain steps end any tape
   c->tape_n = c->tape_rev = 0;

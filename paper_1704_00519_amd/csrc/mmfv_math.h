@@ -36,6 +36,10 @@ struct Params {
   double taitB[MAXM], rho0[MAXM];
   int flux;                       // FLUX_HLLC or FLUX_ROE
   int scale_sep;                  // 1: interface scale separation after each step
+  int coord;                      // 1: 1D cylindrical, x the radius
+  int fs_on, fs_mat;              // material fs_mat: an ambient that is not solved
+  double x0;                      // low end of the domain in x
+  double fs_p[5];                 // p_hi, p_lo, t0, t1, density of the ambient
 };
 enum { FLUX_HLLC = 0, FLUX_ROE = 1 };
 
