@@ -18,6 +18,7 @@ events around its launches on the stream it runs on), with its FP64
 operation rate against the FP64 vector issue rate beside it, the whole
 step's HBM fraction, the same workload at 8192 x 2048 (working set far
 beyond the 256 MB last-level cache), the triple point at 896 x 384, the
+1D cylindrical implosion (one instance and its parameter study batched), the
 batched form, the adjoint, and the CPU oracle's rate on a bounded sample of
 the same workload.
 """
@@ -184,6 +185,49 @@ def triple_point_leg(pk, wl, stream, steps=300, warm=10):
     return dict(workload="triple_point_896x384", value=r["rate"], unit="updates/s",
                 steps=steps, warmup=warm, ms_per_step=r["ms"] / steps,
                 t_start=r["t_start"], t_end=r["t_end"])
+
+
+def icf_leg(pk, wl, stream, n=1280, steps=5350, sweep_n=320, sweep_steps=1199, warm=10):
+    """Case II (the 1D cylindrical implosion with a free surface): one
+    instance at n cells over the run to t = 0.3 (`steps` steps), and the
+    paper's parameter study as one batched launch over a 16 x 16 grid (shell
+    thickness 0.16 to 0.31, gamma_2 / gamma_1 from 1 to 10: 256 instances at
+    sweep_n cells, sweep_steps steps each; shells of 0.15 and thinner stop
+    with a non-physical state near stagnation at these resolutions for some
+    gamma ratios); the oracle's rate on the 320-cell instance beside them."""
+    import torch
+    import oracle
+    w = wl.icf_1d(n=n)
+    s, r = timed_run(pk, w, stream, steps, 0, warm)
+    s.close()
+    insts = [wl.icf_1d(n=sweep_n, r_out=1.0 + float(dr), gammas=(1.667, 1.667 * float(q), 1.667))
+             for dr in np.linspace(0.16, 0.31, 16) for q in np.linspace(1.0, 10.0, 16)]
+    b = pk.Batch(insts, stream=stream.cuda_stream)
+    b.init(insts)
+    b.step(1)
+    torch.cuda.synchronize()
+    u0 = sum(d["n_updates"] for d in b.diag())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(sweep_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = sum(d["n_updates"] for d in b.diag()) - u0
+    t_end = [round(d["t"], 4) for d in b.diag()]
+    wo = wl.icf_1d(n=320)
+    o = oracle.Oracle(wo["cfg"])
+    assert o.init(wo["phi"], wo["chi"], wo["W"]) == 0
+    t0 = time.perf_counter()
+    o.step(1199)
+    el = time.perf_counter() - t0
+    return dict(workload=f"icf_1d_{n}", value=r["rate"], unit="updates/s", steps=steps,
+                ms_per_step=r["ms"] / steps, t_end=r["t_end"],
+                sweep=dict(instances=len(insts), cells=sweep_n, steps=sweep_steps + 1,
+                           value=upd / (ms * 1e-3), unit="updates/s", ms=ms,
+                           t_end_min=min(t_end), t_end_max=max(t_end)),
+                cpu_oracle=dict(value=o.diag()["n_updates"] / el, unit="updates/s", cores=1,
+                                sample="icf_1d 320 cells, 1199 steps (to t = 0.3)"))
 
 
 def host_cpu():
@@ -370,6 +414,7 @@ def main():
         if not args.no_hbm_leg:
             out["hbm_resident"] = hbm_resident_leg(pk, wl, stream)
         out["triple_point"] = triple_point_leg(pk, wl, stream)
+        out["icf"] = icf_leg(pk, wl, stream)
         if not args.no_batch:
             out["batched"] = batched(pk, wl, stream, args.batch_steps)
         if not args.no_adjoint:
