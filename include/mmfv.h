@@ -255,6 +255,46 @@ typedef struct {
 mm_status mm_set_profiling(mm_ctx *ctx, int32_t enable);
 mm_status mm_get_profile(mm_ctx *ctx, mm_profile *out);
 
+/* ---- Multiresolution analysis (Sec. 2.4) ------------------------------
+ * The block structure the paper's adaptive grid would give the current 2D
+ * state.  Levels l = 0 (coarsest) .. L (the context's grid); level l has
+ * nx / 2^(L-l) x ny / 2^(L-l) cells in blocks of `block` x `block` cells, so
+ * nx and ny must be multiples of block * 2^L.  Fields: the mixture density
+ * and total energy (sums over the materials).  Projection: the mean of the
+ * four children; prediction: the tensor product of the 1D 5th-order
+ * operator u +- sum_m g_m (u[i+m] - u[i-m]), g = (-22/128, 3/128), edge
+ * cells repeated beyond the domain; a detail (value - prediction) of level
+ * l is significant when its magnitude exceeds 2^(2 (l - L)) eps times the
+ * field's largest magnitude.  Interface position identifier: a block of the
+ * context's grid with a cell whose level-set value is below `band` (the
+ * narrow band), and its ancestors.  A level-l block (l < L) is refined when
+ * it has the identifier or a block of its 3 x 3 neighbourhood has a
+ * significant detail among its children; grading refines the parents of
+ * the 3 x 3 neighbourhood of every refined block; blocks exist at level 0
+ * and below refined existing blocks.
+ * leaf_level: int32 per block of the context's grid ((ny/block) x
+ * (nx/block), row-major): the level of the leaf covering it.  flags (NULL
+ * to skip): uint8 per block, the detail flags of levels 0 .. L-1, then the
+ * identifiers of levels 0 .. L, each level row-major.  Both in host or
+ * device memory per ptr_kind (caller-owned); *res on the host.  MM_EINVAL
+ * for a 1D context, a grid that does not divide, block < 2, L outside
+ * [1, MM_MR_MAXL] or eps <= 0; MM_ESTATE before mm_init_state.  The state
+ * is not changed. */
+#define MM_MR_MAXL 10
+typedef struct {
+  int32_t block, levels;   /* block side in cells (16), L                   */
+  double eps;              /* threshold of the finest level's details       */
+  double band;             /* narrow band: level-set values below it        */
+} mm_mr_params;
+typedef struct {
+  int64_t exist[MM_MR_MAXL + 1];  /* blocks that exist, per level           */
+  int64_t leaf[MM_MR_MAXL + 1];   /* leaf blocks, per level                 */
+  double compression;             /* leaf cells / the context's cells       */
+  double scale[2];                /* largest |rho|, |rho E| (mixture)       */
+} mm_mr_result;
+mm_status mm_mr_analyse(mm_ctx *ctx, const mm_mr_params *p, int32_t *leaf_level,
+                        uint8_t *flags, mm_mr_result *res, int32_t ptr_kind);
+
 /* ---- Batched form ------------------------------------------------------
  * Many independent 1D problems of uneven size (same n_mat and rk_order)
  * advanced together: one persistent launch, one workgroup per instance,

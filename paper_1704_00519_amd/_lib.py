@@ -25,7 +25,7 @@ EXPORTS = ("mm_create", "mm_init_state", "mm_step", "mm_get_conserved",
            "mm_get_diagnostics", "mm_set_dt", "mm_set_dt_schedule", "mm_set_guard",
            "mm_adjoint_step", "mm_adjoint_inflow",
            "mm_tape_info", "mm_destroy",
-           "mm_last_error", "mm_set_profiling", "mm_get_profile",
+           "mm_last_error", "mm_set_profiling", "mm_get_profile", "mm_mr_analyse",
            "mm_batch_create", "mm_batch_init_state", "mm_batch_step",
            "mm_batch_get_conserved", "mm_batch_get_diagnostics",
            "mm_batch_set_threads", "mm_batch_get_threads", "mm_batch_destroy",
@@ -79,6 +79,19 @@ class MMProfile(C.Structure):
                 ("bulk_updates", C.c_int64), ("bulk_bytes", C.c_double)]
 
 
+MR_MAXL = 10
+
+
+class MMMrParams(C.Structure):
+    _fields_ = [("block", C.c_int32), ("levels", C.c_int32), ("eps", C.c_double),
+                ("band", C.c_double)]
+
+
+class MMMrResult(C.Structure):
+    _fields_ = [("exist", C.c_int64 * (MR_MAXL + 1)), ("leaf", C.c_int64 * (MR_MAXL + 1)),
+                ("compression", C.c_double), ("scale", C.c_double * 2)]
+
+
 class MMError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -112,6 +125,7 @@ def load():
         L.mm_destroy.argtypes = [vp]
         L.mm_set_profiling.argtypes = [vp, i32]
         L.mm_get_profile.argtypes = [vp, C.POINTER(MMProfile)]
+        L.mm_mr_analyse.argtypes = [vp, C.POINTER(MMMrParams), vp, vp, C.POINTER(MMMrResult), i32]
         L.mm_batch_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
         L.mm_batch_init_state.argtypes = [vp, vp, vp, vp, i32]
         L.mm_batch_step.argtypes = [vp, i32]
@@ -135,7 +149,7 @@ def load():
                      "mm_get_diagnostics", "mm_set_dt", "mm_set_dt_schedule",
                      "mm_set_guard", "mm_adjoint_step",
                      "mm_adjoint_inflow", "mm_tape_info",
-                     "mm_destroy", "mm_set_profiling", "mm_get_profile"):
+                     "mm_destroy", "mm_set_profiling", "mm_get_profile", "mm_mr_analyse"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -308,6 +322,40 @@ class Solver:
 
     def set_profiling(self, on=True):
         self._check(load().mm_set_profiling(self._h, 1 if on else 0))
+
+    def mr_analyse(self, block=16, levels=3, eps=1e-3, band=None, flags=True):
+        """Multiresolution analysis of the current state (2D): the leaf level
+        of every block of the grid, per level the detail flags (levels
+        0..L-1) and interface identifiers (0..L), the counts of existing and
+        leaf blocks, the compression and the fields' largest magnitudes.
+        band defaults to the level set's band width."""
+        if band is None:
+            band = self.cfg["band_ls"] * min((self.cfg["x1"] - self.cfg["x0"]) / self.nx,
+                                             (self.cfg["y1"] - self.cfg["y0"]) / self.ny)
+        nbx, nby = self.nx // block, self.ny // block
+        leaf = np.zeros((nby, nbx), np.int32)
+        shapes = [(nby >> (levels - l), nbx >> (levels - l)) for l in range(levels + 1)]
+        nfl = sum(a * b for a, b in shapes[:levels]) + sum(a * b for a, b in shapes)
+        fl = np.zeros(nfl, np.uint8)
+        p = MMMrParams(int(block), int(levels), float(eps), float(band))
+        r = MMMrResult()
+        self._check(load().mm_mr_analyse(self._h, C.byref(p), leaf.ctypes.data,
+                                         fl.ctypes.data if flags else None, C.byref(r),
+                                         MM_HOST))
+        out = dict(leaf=leaf, counts=[(int(r.exist[l]), int(r.leaf[l])) for l in range(levels + 1)],
+                   compression=r.compression, scale=[r.scale[0], r.scale[1]])
+        if flags:
+            det, ifc, o = [], [], 0
+            for l in range(levels):
+                n = shapes[l][0] * shapes[l][1]
+                det.append(fl[o:o + n].reshape(shapes[l]).astype(bool))
+                o += n
+            for l in range(levels + 1):
+                n = shapes[l][0] * shapes[l][1]
+                ifc.append(fl[o:o + n].reshape(shapes[l]).astype(bool))
+                o += n
+            out.update(detail=det, iface=ifc)
+        return out
 
     def profile(self):
         p = MMProfile()

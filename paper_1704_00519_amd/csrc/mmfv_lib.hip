@@ -12,6 +12,7 @@
 #include "mmfv.h"
 #include "mmfv_adjoint.h"
 #include "mmfv_kernels.h"
+#include "mmfv_mr.h"
 
 using namespace mmfv;
 
@@ -76,6 +77,9 @@ struct mm_ctx {
   double* guard_cons = nullptr;
   int64_t err_step = -1;   // failing step (1-based) of the last failure
   int64_t err_cell = -1;   // its lowest non-physical cell
+  // multiresolution analysis: pyramid of the two fields, flags, counts
+  char* mr_buf = nullptr;
+  size_t mr_cap = 0;
 };
 
 static void prof_mark(mm_ctx* c) {
@@ -139,7 +143,7 @@ static void free_all(mm_ctx* c) {
   for (char* p : c->ckpt) (void)hipFree(p);
   c->ckpt.clear();
   void* extra[] = {c->tape_dt, c->seg, c->final_snap, c->dts, c->guard_snap, c->guard_ctr,
-                   c->guard_scal, c->guard_cons};
+                   c->guard_scal, c->guard_cons, c->mr_buf};
   for (void* p : extra)
     if (p) (void)hipFree(p);
   c->tape_dt = nullptr;
@@ -147,6 +151,8 @@ static void free_all(mm_ctx* c) {
   c->final_snap = nullptr;
   c->dts = nullptr;
   c->guard_snap = nullptr;
+  c->mr_buf = nullptr;
+  c->mr_cap = 0;
   c->guard_ctr = nullptr;
   c->guard_scal = nullptr;
   c->guard_cons = nullptr;
@@ -990,6 +996,120 @@ extern "C" mm_status mm_get_profile(mm_ctx* c, mm_profile* out) {
   out->bulk_launches = c->prof_launches;
   out->bulk_updates = (int64_t)(u0 + u1);
   out->bulk_bytes = u0 * 2.0 * w + u1 * 3.0 * w;
+  return MM_OK;
+}
+
+// Multiresolution analysis (Sec. 2.4) of the current 2D state
+__global__ void __launch_bounds__(256) k_mr_flags_u8(const uint32_t* a, uint8_t* out, long n) {
+  long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = a[q] ? 1 : 0;
+}
+extern "C" mm_status mm_mr_analyse(mm_ctx* c, const mm_mr_params* p, int32_t* leaf_level,
+                                   uint8_t* flags, mm_mr_result* res, int32_t ptr_kind) {
+  if (!c || !p || !leaf_level || !res) return MM_EINVAL;
+  c->adj_clean = false;
+  if (!c->ready) return fail(c, MM_ESTATE, "mm_mr_analyse before mm_init_state");
+  if (ptr_kind != MM_HOST && ptr_kind != MM_DEVICE) return fail(c, MM_EINVAL, "bad ptr_kind");
+  const Params& P = c->P;
+  int bs = p->block, L = p->levels;
+  if (P.dim != 2) return fail(c, MM_EINVAL, "multiresolution analysis is built for 2D");
+  if (bs < 2 || L < 1 || L > MR_MAXL || !(p->eps > 0.0) || std::isnan(p->band))
+    return fail(c, MM_EINVAL, "block >= 2, 1 <= levels <= MM_MR_MAXL, eps > 0 required");
+  long unit = (long)bs << L;
+  if (P.nx % unit || P.ny % unit)
+    return fail(c, MM_EINVAL, "nx and ny must be multiples of block * 2^levels");
+  MrLevels V;
+  memset(&V, 0, sizeof(V));
+  V.L = L;
+  long nflag = 0;
+  size_t ncell[MR_MAXL + 1], cell_off[MR_MAXL + 1], ncells = 0;
+  for (int l = 0; l <= L; l++) {
+    V.nbx[l] = P.nx / (bs << (L - l));
+    V.nby[l] = P.ny / (bs << (L - l));
+    V.off[l] = nflag;
+    nflag += (long)V.nbx[l] * V.nby[l];
+    ncell[l] = ((size_t)P.nx >> (L - l)) * ((size_t)P.ny >> (L - l));
+    cell_off[l] = ncells;
+    ncells += ncell[l];
+  }
+  // layout: two pyramids of doubles, four flag arrays, the maxima, counts
+  size_t b_u = 2 * ncells * sizeof(double), b_f = 4 * (size_t)nflag * sizeof(uint32_t);
+  size_t need = b_u + b_f + 2 * sizeof(unsigned long long) +
+                2 * (MR_MAXL + 1) * sizeof(unsigned long long) + 256;
+  if (c->mr_cap < need) {
+    if (c->mr_buf) (void)hipFree(c->mr_buf);
+    c->mr_buf = nullptr;
+    c->mr_cap = 0;
+    if (hipMalloc(&c->mr_buf, need) != hipSuccess) return fail(c, MM_ENOMEM, "multiresolution buffers");
+    c->mr_cap = need;
+  }
+  double* u0 = (double*)c->mr_buf;
+  double* u1 = u0 + ncells;
+  uint32_t* detail = (uint32_t*)(u1 + ncells);
+  uint32_t* iface = detail + nflag;
+  uint32_t* refine = iface + nflag;
+  uint32_t* exist = refine + nflag;
+  // four arrays of nflag words: 16 nflag bytes, so the maxima stay aligned
+  unsigned long long* smax = (unsigned long long*)(exist + nflag);
+  unsigned long long* counts = smax + 2;
+  // clear flags and maxima (a fill kernel, not a memset node)
+  Copies z;
+  z.fill0(detail, 4 * (size_t)nflag * sizeof(uint32_t) + 2 * sizeof(unsigned long long));
+  z.run(c);
+  LAUNCH(k_mr_fields, dim3((P.nx + 15) / 16, (P.ny + 15) / 16), dim3(256), P, c->B,
+         u0 + cell_off[L], u1 + cell_off[L], iface + V.off[L], bs, p->band, smax);
+  for (int l = L - 1; l >= 0; l--)
+    LAUNCH(k_mr_project, lin_grid((long)ncell[l]), dim3(256), u0 + cell_off[l + 1],
+           u1 + cell_off[l + 1], u0 + cell_off[l], u1 + cell_off[l], (int)(P.nx >> (L - l)),
+           (int)(P.ny >> (L - l)));
+  for (int l = 0; l < L; l++) {
+    double e = std::ldexp(1.0, 2 * (l + 1 - L)) * p->eps;
+    LAUNCH(k_mr_detail, lin_grid((long)ncell[l + 1]), dim3(256), u0 + cell_off[l],
+           u1 + cell_off[l], u0 + cell_off[l + 1], u1 + cell_off[l + 1],
+           (int)(P.nx >> (L - l)), (int)(P.ny >> (L - l)), bs, e, smax, detail + V.off[l]);
+  }
+  int32_t* dleaf = leaf_level;
+  uint8_t* dflags = flags;
+  long nleaf = (long)V.nbx[L] * V.nby[L];
+  long nfl = (V.off[L] /* detail of levels < L */) + nflag /* identifiers */;
+  if (ptr_kind == MM_HOST) {
+    size_t need_in = nleaf * sizeof(int32_t) + (flags ? nfl : 0) + 64;
+    if (c->d_in_bytes < need_in) {
+      if (c->d_in) (void)hipFree(c->d_in);
+      c->d_in = nullptr;
+      c->d_in_bytes = 0;
+      if (hipMalloc(&c->d_in, need_in) != hipSuccess) return fail(c, MM_ENOMEM, "staging buffer");
+      c->d_in_bytes = need_in;
+    }
+    dleaf = (int32_t*)c->d_in;
+    dflags = flags ? (uint8_t*)(dleaf + nleaf) : nullptr;
+  }
+  LAUNCH(k_mr_tree, dim3(1), dim3(1024), V, detail, iface, refine, exist, dleaf, counts);
+  if (dflags) {
+    LAUNCH(k_mr_flags_u8, lin_grid(V.off[L]), dim3(256), detail, dflags, V.off[L]);
+    LAUNCH(k_mr_flags_u8, lin_grid(nflag), dim3(256), iface, dflags + V.off[L], nflag);
+  }
+  HIP_OK(c, hipGetLastError());
+  unsigned long long hc[2 * (MR_MAXL + 1) + 2];
+  HIP_OK(c, hipMemcpyAsync(hc, smax, (2 + 2 * (L + 1)) * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
+  if (ptr_kind == MM_HOST) {
+    HIP_OK(c, hipMemcpyAsync(leaf_level, dleaf, nleaf * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    if (flags)
+      HIP_OK(c, hipMemcpyAsync(flags, dflags, nfl, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  memset(res, 0, sizeof(*res));
+  double cells = 0.0;
+  for (int l = 0; l <= L; l++) {
+    res->exist[l] = (int64_t)hc[2 + 2 * l];
+    res->leaf[l] = (int64_t)hc[2 + 2 * l + 1];
+    cells += (double)res->leaf[l] * bs * bs;
+  }
+  res->compression = cells / ((double)P.nx * P.ny);
+  memcpy(&res->scale[0], &hc[0], sizeof(double));
+  memcpy(&res->scale[1], &hc[1], sizeof(double));
   return MM_OK;
 }
 
