@@ -230,6 +230,42 @@ def icf_leg(pk, wl, stream, n=1280, steps=5350, sweep_n=320, sweep_steps=1199, w
                                 sample="icf_1d 320 cells, 1199 steps (to t = 0.3)"))
 
 
+def mr_leg(s, stream, w, block=16, levels=5, eps=1e-3, reps=20):
+    """Multiresolution analysis (Sec. 2.4) of the state the solver holds:
+    the paper's block structure (16 x 16 blocks, five levels above the
+    4 x 1 coarsest blocks of the 2048 x 512 grid), timed over `reps` calls
+    (each synchronises and copies the leaf map out), against the HBM roof
+    from its algorithmic bytes: per cell of the grid 41 B for the fields
+    (rho and rho E of the cell's material, occupancy and level set read,
+    two fields written) and per level 16 B per fine and per coarse cell for
+    each of the projection and the detail passes.  Beside it, the oracle's
+    analysis (numpy) of the workload's initial state, on the host."""
+    import torch
+    nx, ny = s.nx, s.ny
+    r = s.mr_analyse(block=block, levels=levels, eps=eps, flags=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = s.mr_analyse(block=block, levels=levels, eps=eps, flags=False)
+    el = (time.perf_counter() - t0) / reps
+    n = [(nx >> (levels - l)) * (ny >> (levels - l)) for l in range(levels + 1)]
+    byt = 41.0 * nx * ny + sum(2 * 16.0 * (n[l + 1] + n[l]) for l in range(levels))
+    gbs = byt / el / 1e9
+    import oracle
+    from oracle import mr
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    g = o.get()
+    band = s.cfg["band_ls"] * min((s.cfg["x1"] - s.cfg["x0"]) / nx, (s.cfg["y1"] - s.cfg["y0"]) / ny)
+    t0 = time.perf_counter()
+    mr.analyse(g["Q"], g["phi"], band, B=block, L=levels, eps=eps)
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    return dict(block=block, levels=levels, eps=eps, ms=el * 1e3, bytes=byt,
+                achieved_gbs=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 4),
+                counts=r["counts"], compression=r["compression"],
+                cpu_oracle_ms=round(cpu_ms, 1))
+
+
 def host_cpu():
     """Host core count and model of the machine the oracle runs on."""
     model = ""
@@ -365,6 +401,8 @@ def main():
                     help="only the main workload (for profiler runs)")
     ap.add_argument("--grid", default=f"{WORKLOAD['nx']}x{WORKLOAD['ny']}",
                     help="grid of the shock-bubble workload (profiler runs at other sizes)")
+    ap.add_argument("--icf-only", action="store_true",
+                    help="run only the Case II leg (one JSON object)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -377,6 +415,12 @@ def main():
     import paper_1704_00519_amd as pk
     import workloads as wl
 
+    if args.icf_only:
+        torch.cuda.set_device(0)
+        stream = torch.cuda.Stream()
+        torch.cuda.set_stream(stream)
+        print(json.dumps(icf_leg(pk, wl, stream)))
+        return
     nx, ny = (int(v) for v in args.grid.split("x"))
     w = wl.shock_bubble(nx=nx, ny=ny)
     torch.cuda.set_device(0)
@@ -386,6 +430,7 @@ def main():
     s, r = timed_run(pk, w, stream, args.steps, args.warmup, start)
     value = r["rate"]
     prof = profile_bulk(s, max(1, min(args.steps, 20)))
+    mr = None if args.no_extra else mr_leg(s, stream, w)
     s.close()
     roofline = bulk_roofline(prof)
     roofline["traffic"] = measured_traffic(f"{nx}x{ny}")
@@ -410,6 +455,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8,
                                          "launches": 3}
+    if mr is not None:
+        out["mr"] = mr
     if not args.no_extra:
         if not args.no_hbm_leg:
             out["hbm_resident"] = hbm_resident_leg(pk, wl, stream)

@@ -1034,8 +1034,10 @@ extern "C" mm_status mm_mr_analyse(mm_ctx* c, const mm_mr_params* p, int32_t* le
   }
   // layout: two pyramids of doubles, four flag arrays, the maxima, counts
   size_t b_u = 2 * ncells * sizeof(double), b_f = 4 * (size_t)nflag * sizeof(uint32_t);
+  dim3 gf((P.nx + MR_TILE - 1) / MR_TILE, (P.ny + MR_TILE - 1) / MR_TILE);
+  long nwg = (long)gf.x * gf.y;
   size_t need = b_u + b_f + 2 * sizeof(unsigned long long) +
-                2 * (MR_MAXL + 1) * sizeof(unsigned long long) + 256;
+                2 * (MR_MAXL + 1) * sizeof(unsigned long long) + 2 * nwg * sizeof(double) + 256;
   if (c->mr_cap < need) {
     if (c->mr_buf) (void)hipFree(c->mr_buf);
     c->mr_buf = nullptr;
@@ -1052,19 +1054,23 @@ extern "C" mm_status mm_mr_analyse(mm_ctx* c, const mm_mr_params* p, int32_t* le
   // four arrays of nflag words: 16 nflag bytes, so the maxima stay aligned
   unsigned long long* smax = (unsigned long long*)(exist + nflag);
   unsigned long long* counts = smax + 2;
+  double* part = (double*)(counts + 2 * (MR_MAXL + 1));
   // clear flags and maxima (a fill kernel, not a memset node)
   Copies z;
   z.fill0(detail, 4 * (size_t)nflag * sizeof(uint32_t) + 2 * sizeof(unsigned long long));
   z.run(c);
-  LAUNCH(k_mr_fields, dim3((P.nx + 15) / 16, (P.ny + 15) / 16), dim3(256), P, c->B,
-         u0 + cell_off[L], u1 + cell_off[L], iface + V.off[L], bs, p->band, smax);
+  LAUNCH(k_mr_fields, gf, dim3(256), P, c->B, u0 + cell_off[L], u1 + cell_off[L],
+         iface + V.off[L], bs, p->band, part);
+  LAUNCH(k_mr_max, dim3(1), dim3(1024), part, nwg, smax);
   for (int l = L - 1; l >= 0; l--)
     LAUNCH(k_mr_project, lin_grid((long)ncell[l]), dim3(256), u0 + cell_off[l + 1],
            u1 + cell_off[l + 1], u0 + cell_off[l], u1 + cell_off[l], (int)(P.nx >> (L - l)),
            (int)(P.ny >> (L - l)));
   for (int l = 0; l < L; l++) {
     double e = std::ldexp(1.0, 2 * (l + 1 - L)) * p->eps;
-    LAUNCH(k_mr_detail, lin_grid((long)ncell[l + 1]), dim3(256), u0 + cell_off[l],
+    int nxf = (int)(P.nx >> (L - l - 1)), nyf = (int)(P.ny >> (L - l - 1));
+    LAUNCH(k_mr_detail, dim3((nxf + MR_TILE - 1) / MR_TILE, (nyf + MR_TILE - 1) / MR_TILE),
+           dim3(256), u0 + cell_off[l],
            u1 + cell_off[l], u0 + cell_off[l + 1], u1 + cell_off[l + 1],
            (int)(P.nx >> (L - l)), (int)(P.ny >> (L - l)), bs, e, smax, detail + V.off[l]);
   }

@@ -15,15 +15,38 @@ namespace mmfv {
 constexpr int MR_MAXL = 10;
 constexpr double MR_G1 = -22.0 / 128.0, MR_G2 = 3.0 / 128.0;
 
+// Flags of the blocks a 16 x 16 tile of cells (origin i0, j0) touches, in
+// LDS: at most 9 x 9 blocks (block side >= 2); one atomic per touched,
+// flagged block when the tile is done.
+constexpr int MR_TILE = 16, MR_LOC = 9;
+struct MrTileFlags {
+  int bx0, by0, nlx, nly;
+  MMD void init(int i0, int j0, int bs) {
+    bx0 = i0 / bs;
+    by0 = j0 / bs;
+    nlx = (i0 + MR_TILE - 1) / bs - bx0 + 1;
+    nly = (j0 + MR_TILE - 1) / bs - by0 + 1;
+  }
+  MMD int local(int i, int j, int bs) const { return (j / bs - by0) * nlx + (i / bs - bx0); }
+};
+
 // Level-L fields (the sums over the materials, in material order, of rho
 // and rho E), the interface identifier of the solver-grid blocks (a cell in
-// the narrow band: level-set value below band), and the largest magnitudes
-// of the two fields as the bit patterns of non-negative doubles (ordered
-// like their values).  16 x 16 cells per workgroup.
+// the narrow band: level-set value below band), and per workgroup the
+// largest magnitudes of the two fields (part[2 b], part[2 b + 1]).  One
+// 16 x 16 tile of cells per workgroup.
 __global__ void __launch_bounds__(256) k_mr_fields(Params P, Bufs B, double* u0, double* u1,
                                                    uint32_t* iface, int bs, double band,
-                                                   unsigned long long* smax) {
-  int i = blockIdx.x * 16 + (int)threadIdx.x % 16, j = blockIdx.y * 16 + (int)threadIdx.x / 16;
+                                                   double* part) {
+  __shared__ uint32_t sf[MR_LOC * MR_LOC];
+  __shared__ double r0[4], r1[4];
+  int tid = threadIdx.x;
+  int i0 = blockIdx.x * MR_TILE, j0 = blockIdx.y * MR_TILE;
+  int i = i0 + tid % MR_TILE, j = j0 + tid / MR_TILE;
+  MrTileFlags tf;
+  tf.init(i0, j0, bs);
+  if (tid < MR_LOC * MR_LOC) sf[tid] = 0;
+  __syncthreads();
   bool in = i < P.nx && j < P.ny;
   double a0 = 0.0, a1 = 0.0;
   if (in) {
@@ -39,15 +62,52 @@ __global__ void __launch_bounds__(256) k_mr_fields(Params P, Bufs B, double* u0,
     u1[q] = E;
     a0 = fabs(rho);
     a1 = fabs(E);
-    if (B.phi[k] < band) atomicOr(&iface[(size_t)(j / bs) * (P.nx / bs) + i / bs], 1u);
+    if (B.phi[k] < band) sf[tf.local(i, j, bs)] = 1;
   }
   for (int o = 32; o > 0; o >>= 1) {
     a0 = fmax(a0, __shfl_xor(a0, o));
     a1 = fmax(a1, __shfl_xor(a1, o));
   }
   if (__lane_id() == 0) {
-    atomicMax(&smax[0], (unsigned long long)__double_as_longlong(a0));
-    atomicMax(&smax[1], (unsigned long long)__double_as_longlong(a1));
+    r0[tid >> 6] = a0;
+    r1[tid >> 6] = a1;
+  }
+  __syncthreads();
+  if (tid < tf.nlx * tf.nly && sf[tid]) {
+    int bi = tf.bx0 + tid % tf.nlx, bj = tf.by0 + tid / tf.nlx;
+    if (bi < P.nx / bs && bj < P.ny / bs) atomicOr(&iface[(size_t)bj * (P.nx / bs) + bi], 1u);
+  }
+  if (tid == 0) {
+    size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = fmax(fmax(r0[0], r0[1]), fmax(r0[2], r0[3]));
+    part[2 * b + 1] = fmax(fmax(r1[0], r1[1]), fmax(r1[2], r1[3]));
+  }
+}
+
+// the largest magnitudes from the n workgroup pairs, as the bit patterns of
+// non-negative doubles; one workgroup of 1024 threads
+__global__ void __launch_bounds__(1024) k_mr_max(const double* part, long n,
+                                                 unsigned long long* smax) {
+  __shared__ double s0[1024], s1[1024];
+  int tid = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  for (long q = tid; q < n; q += 1024) {
+    a0 = fmax(a0, part[2 * q]);
+    a1 = fmax(a1, part[2 * q + 1]);
+  }
+  s0[tid] = a0;
+  s1[tid] = a1;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (tid < h) {
+      s0[tid] = fmax(s0[tid], s0[tid + h]);
+      s1[tid] = fmax(s1[tid], s1[tid + h]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    smax[0] = (unsigned long long)__double_as_longlong(s0[0]);
+    smax[1] = (unsigned long long)__double_as_longlong(s1[0]);
   }
 }
 
@@ -90,23 +150,36 @@ MMD double mr_predict(const double* u, int nxc, int nyc, int ic, int jc, int a, 
 // Details of level l+1 (fine, 2 nxc x 2 nyc) against the prediction from
 // level l (coarse): a level-l block (bs x bs coarse cells, 2 bs x 2 bs fine)
 // is flagged when a child cell's |detail| exceeds e times the field's
-// largest magnitude, in either field.
+// largest magnitude, in either field.  One 16 x 16 tile of fine cells per
+// workgroup; the flags of the blocks it touches go through LDS.
 __global__ void __launch_bounds__(256) k_mr_detail(const double* c0, const double* c1,
                                                    const double* f0, const double* f1, int nxc,
                                                    int nyc, int bs, double e,
                                                    const unsigned long long* smax,
                                                    uint32_t* flag) {
-  long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  int nxf = 2 * nxc;
-  if (q >= (long)nxf * 2 * nyc) return;
-  int fi = (int)(q % nxf), fj = (int)(q / nxf);
-  double thr0 = e * __longlong_as_double((long long)smax[0]);
-  double thr1 = e * __longlong_as_double((long long)smax[1]);
-  int ic = fi >> 1, jc = fj >> 1, a = fi & 1, b = fj & 1;
-  double d0 = f0[q] - mr_predict(c0, nxc, nyc, ic, jc, a, b);
-  double d1 = f1[q] - mr_predict(c1, nxc, nyc, ic, jc, a, b);
-  if (fabs(d0) > thr0 || fabs(d1) > thr1)
-    atomicOr(&flag[(size_t)(fj / (2 * bs)) * (nxc / bs) + fi / (2 * bs)], 1u);
+  __shared__ uint32_t sf[MR_LOC * MR_LOC];
+  int tid = threadIdx.x;
+  int nxf = 2 * nxc, nyf = 2 * nyc, fbs = 2 * bs;
+  int i0 = blockIdx.x * MR_TILE, j0 = blockIdx.y * MR_TILE;
+  int fi = i0 + tid % MR_TILE, fj = j0 + tid / MR_TILE;
+  MrTileFlags tf;
+  tf.init(i0, j0, fbs);
+  if (tid < MR_LOC * MR_LOC) sf[tid] = 0;
+  __syncthreads();
+  if (fi < nxf && fj < nyf) {
+    double thr0 = e * __longlong_as_double((long long)smax[0]);
+    double thr1 = e * __longlong_as_double((long long)smax[1]);
+    int ic = fi >> 1, jc = fj >> 1, a = fi & 1, b = fj & 1;
+    size_t q = (size_t)fj * nxf + fi;
+    double d0 = f0[q] - mr_predict(c0, nxc, nyc, ic, jc, a, b);
+    double d1 = f1[q] - mr_predict(c1, nxc, nyc, ic, jc, a, b);
+    if (fabs(d0) > thr0 || fabs(d1) > thr1) sf[tf.local(fi, fj, fbs)] = 1;
+  }
+  __syncthreads();
+  if (tid < tf.nlx * tf.nly && sf[tid]) {
+    int bi = tf.bx0 + tid % tf.nlx, bj = tf.by0 + tid / tf.nlx;
+    if (bi < nxc / bs && bj < nyc / bs) atomicOr(&flag[(size_t)bj * (nxc / bs) + bi], 1u);
+  }
 }
 
 // Block structure, one workgroup.  Per level l: nbx[l] x nby[l] blocks at
