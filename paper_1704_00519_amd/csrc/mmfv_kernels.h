@@ -3016,6 +3016,39 @@ __global__ void __launch_bounds__(256) k_vext_tiles(Params P, Bufs B, int sidx) 
   }
 }
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
+
+// 1D: every ghost-extension sweep of a stage in one workgroup, a barrier
+// between sweeps (each sweep reads the states the previous ones left, as
+// separate launches would; the queue of a 1D problem is short)
+__global__ void __launch_bounds__(1024) k_ext_all1(Params P, Bufs B, int sidx) {
+  int n = (int)B.ctr[C_NGHOST];
+  if (errored(B)) return;
+  for (int sw = 0; sw < P.kext + 4; sw++) {
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+      int e = B.glist[q];
+      int k = e >> 3, r = e & 7;
+      if (B.Wit[(size_t)r * P.NC + k] != 0) continue;
+      ext_one<1>(P, B, k % P.NX - H, 0, r, sidx, sw);
+    }
+    __syncthreads();
+  }
+}
+// 1D, stage 0: the four level-set velocity sweeps and the fill over the
+// listed tiles in one workgroup, a barrier after each pass
+__global__ void __launch_bounds__(1024) k_vel_all1(Params P, Bufs B, int sidx) {
+  int ncell = (int)B.ctr[C_NTILES] * 256;
+  for (int pass = 0; pass < 5; pass++) {
+    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+      int i = B.tiles[q / 256] * 256 + q % 256;
+      if (i >= P.nx) continue;
+      if (pass < 4)
+        b_vext<1>(P, B, i, 0, pass);
+      else
+        b_vfill<1>(P, B, i, 0, sidx);
+    }
+    __syncthreads();
+  }
+}
 TILE_KERNEL(t_ls_commit, b_ls_commit, )
 
 // Commit of the new level set and its frame in one launch (2D), with the

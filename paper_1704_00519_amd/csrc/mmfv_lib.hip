@@ -493,8 +493,8 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   if (D == 2) {
     LAUNCH(k_ext_tiles, dim3(tg.x, P.M), tb, P, c->B, sidx);
   } else {
-    for (int sw = 0; sw < P.kext + 4; sw++)
-      LAUNCH(k_ext_list<D>, dim3(256), dim3(256), P, c->B, sidx, sw);
+    // the sweeps of a 1D stage in one workgroup (its queue is short)
+    LAUNCH(k_ext_all1, dim3(1), dim3(1024), P, c->B, sidx);
   }
   long nframe = (D == 2 ? (long)P.ny + P.nx + 2 * H : (long)P.ny) * 2 * H * P.M;
   int ndt = s == 0 ? (int)(g.x * g.y) : 0;  // stage 0: one more workgroup sets the step size
@@ -503,8 +503,7 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
   if (s == 0 && D == 2) {
     LAUNCH(k_vext_tiles, tg, tb, P, c->B, sidx);
   } else if (s == 0) {
-    for (int sw = 0; sw < 4; sw++) LAUNCH(t_vext<D>, tg, tb, P, c->B, sw);
-    LAUNCH(t_vfill<D>, tg, tb, P, c->B, sidx);
+    LAUNCH(k_vel_all1, dim3(1), dim3(1024), P, c->B, sidx);
   }
   prof_mark(c);
   if (D == 2 && P.flux == FLUX_ROE)
