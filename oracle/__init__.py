@@ -56,7 +56,7 @@ class Config(C.Structure):
                 ("tait_B", C.c_double * MAXM), ("p0", C.c_double * MAXM),
                 ("flux", C.c_int32), ("scale_sep", C.c_int32),
                 ("coord", C.c_int32), ("fs_on", C.c_int32), ("fs_mat", C.c_int32),
-                ("fs_p", C.c_double * 5)]
+                ("fs_p", C.c_double * 5), ("reinit", C.c_int32)]
 
 
 def make_config(cfg):
@@ -80,6 +80,7 @@ def make_config(cfg):
     c.fs_mat = int(cfg.get("fs_mat", 0))
     for q, v in enumerate(cfg.get("fs_p", [0.0] * 5)):
         c.fs_p[q] = float(v)
+    c.reinit = int(cfg.get("reinit", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])
@@ -118,6 +119,7 @@ def lib(tangent=False):
         L.or_t_roe.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_char_weno.argtypes = [vp, C.c_int, dp, dp, dp]
         L.or_t_iface.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
+        L.or_t_reinit.argtypes = [vp]
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         L.or_t_mixing.argtypes = [vp, dp, dp, dp, ip, dp]
         L.or_t_extension.argtypes = [vp, dp, ip, dp, up, dp, up]
@@ -191,6 +193,11 @@ class Oracle:
         WL, WR = np.zeros(4), np.zeros(4)
         self._L.or_t_char_weno(self._h, int(m), np.ascontiguousarray(Wc, float).ravel(), WL, WR)
         return WL, WR
+
+    def reinit(self):
+        """Redistance the current level set (the step's final pass) and
+        evaluate the geometry again."""
+        self._L.or_t_reinit(self._h)
 
     def iface(self, mL, WL, mR, WR):
         out = np.zeros(4)

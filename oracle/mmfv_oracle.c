@@ -78,6 +78,9 @@ typedef struct {
      afterwards) */
   int32_t coord, fs_on, fs_mat;
   double fs_p[5];  /* p_hi, p_lo, t0, t1, density of the ambient */
+  /* 1: redistancing of the regional level set after every time step
+     (reading: the paper describes none) */
+  int32_t reinit;
 } or_config;
 
 typedef struct {
@@ -1779,6 +1782,96 @@ static void scale_separation(St *s) {
   vf_correction(s, s->chi, s->mass);
 }
 
+/* Redistancing of the regional level set after every time step.  Reading:
+ * the paper describes no reinitialisation (its reference for the
+ * multi-region level set is not at hand); without one the distance field
+ * degenerates in stretched layers (values near 0 over whole regions, every
+ * cell cut), which stops the triple point's run.  Band cells (phi below the
+ * band width) take new distances, the others keep the band width; the
+ * material indicator does not change.
+ * (1) A band cell with an interior 4-neighbour of another material: per
+ * axis, the distance to the crossing of the local level set between the
+ * two centres, h phi_c / (phi_c + phi_n) (h/2 where both are 0), the
+ * smaller of the two sides; with crossings on both axes the distance to the
+ * straight line through them, d_x d_y / sqrt(d_x^2 + d_y^2) (0 when one is
+ * 0), else the one crossing; capped at the band width.  Other cells: the
+ * band width.
+ * (2) band_ls + 1 Jacobi sweeps over the band cells: the smallest of the
+ * cell's value and, over its interior 8 neighbours of the same material,
+ * the neighbour's value plus the distance of the centres; capped at the
+ * band width.
+ * Then the frame, the geometry and the correction (masses of the state). */
+static void reinit(St *s) {
+  int nx = s->c.nx, ny = s->c.ny, two = s->c.dim == 2;
+  double bls = s->bls;
+  real *a = s->cv, *b = s->phit;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      real pc = s->phi[k], best = bls;
+      if (pc < bls) {
+        real dxm = -1.0, dym = -1.0;
+        for (int q = 0; q < 4; q++) {
+          int di = q == 0 ? -1 : (q == 1 ? 1 : 0), dj = q == 2 ? -1 : (q == 3 ? 1 : 0);
+          if (!two && dj != 0) continue;
+          int ii = i + di, jj = j + dj;
+          if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+          int kn = ID(s, ii, jj);
+          if (s->chi[kn] == s->chi[k]) continue;
+          real pn = s->phi[kn], sum = pc + pn;
+          double hh = q < 2 ? s->dx : s->dy;
+          real d = sum > 0.0 ? hh * (pc / sum) : 0.5 * hh;
+          if (q < 2) {
+            if (dxm < 0.0 || d < dxm) dxm = d;
+          } else if (dym < 0.0 || d < dym) {
+            dym = d;
+          }
+        }
+        if (dxm >= 0.0 && dym >= 0.0)
+          best = dxm > 0.0 && dym > 0.0 ? (dxm * dym) / sqrt(dxm * dxm + dym * dym) : 0.0;
+        else if (dxm >= 0.0)
+          best = dxm;
+        else if (dym >= 0.0)
+          best = dym;
+        if (best > bls) best = bls;
+      }
+      a[k] = best;
+    }
+  for (int sw = 0; sw <= s->c.band_ls; sw++) {
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) {
+        int k = ID(s, i, j);
+        real v = a[k];
+        if (s->phi[k] < bls)
+          for (int dj = -two; dj <= two; dj++)
+            for (int di = -1; di <= 1; di++) {
+              if (di == 0 && dj == 0) continue;
+              int ii = i + di, jj = j + dj;
+              if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+              int kn = ID(s, ii, jj);
+              if (s->chi[kn] != s->chi[k]) continue;
+              double ex = di * s->dx, ey = dj * s->dy;
+              real cand = a[kn] + sqrt(ex * ex + ey * ey);
+              if (cand < v) v = cand;
+            }
+        b[k] = v < bls ? v : bls;
+      }
+    real *t = a;
+    a = b;
+    b = t;
+  }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      int k = ID(s, i, j);
+      if (s->phi[k] < bls) s->phi[k] = a[k];
+    }
+  fill_ls(s, s->phi, s->chi);
+  geometry(s, s->phi, s->chi);
+  for (int r = 0; r < s->M; r++)
+    for (size_t k = 0; k < (size_t)s->NC; k++) M1(s, s->mass, r, k) = M4(s, s->Q, r, 0, k);
+  vf_correction(s, s->chi, s->mass);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Public C API used by the tests through ctypes                            */
 /* ------------------------------------------------------------------------ */
@@ -1805,6 +1898,7 @@ St *or_create(const or_config *c) {
   if ((c->coord != 0 && c->coord != 1) || (c->coord == 1 && (c->dim != 1 || c->x0 < 0.0)))
     return NULL;
   if (c->fs_on != 0 && c->fs_on != 1) return NULL;
+  if (c->reinit != 0 && c->reinit != 1) return NULL;
   if (c->fs_on) {
     if (c->fs_mat < 0 || c->fs_mat >= c->n_mat || !(c->fs_p[4] > 0.0) ||
         !(c->fs_p[3] > c->fs_p[2]) || c->flux != 0)
@@ -2037,6 +2131,7 @@ int or_step(St *s, int nsteps) {
     s->nstep++;
     s->xw = 1.0;
     if (s->c.scale_sep) scale_separation(s);
+    if (s->c.reinit) reinit(s);
   }
   return OR_OK;
 }
@@ -2141,6 +2236,9 @@ void or_t_roe(St *s, int m, const double *WL, const double *WR, double *F) {
 
 /* Characteristic-wise WENO5 states at a face from six stencil states
  * Wc[q] = (rho, u_n, u_t, p), q = 0..5 (cells i-2 .. i+3 of face i+1/2). */
+/* the redistancing alone, on the current state (its level set is replaced) */
+void or_t_reinit(St *s) { reinit(s); }
+
 void or_t_char_weno(St *s, int m, const double *Wc, double *WL, double *WR) {
   real W6[6][4], L[4], R[4];
   int perm[4] = {0, 1, 2, 3};
