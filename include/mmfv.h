@@ -102,6 +102,21 @@ typedef struct {
    * (record_tape) is not built for either. */
   int32_t coord, fs_on, fs_mat;
   double fs_p[5];
+  /* 1 (dim 2, band_ls <= 10): redistancing of the level set after every
+   * time step (after the scale separation).  Band cells (phi below the band
+   * width) take new distances, the others keep the band width, the
+   * material indicator stays: a cell with a 4-neighbour of another material
+   * takes, per axis, the distance to the crossing of the local level set
+   * between the two centres, h phi_c / (phi_c + phi_n) (h/2 where both are
+   * 0), the smaller side; with crossings on both axes the distance to the
+   * line through them, d_x d_y / sqrt(d_x^2 + d_y^2) (0 if one is 0), else
+   * the one crossing; band_ls + 1 Jacobi sweeps then take the smallest of a
+   * band cell's value and its same-material 8-neighbours' values plus the
+   * centre distance, capped at the band width; geometry and correction are
+   * evaluated again.  The paper describes no reinitialisation; without it
+   * the distance degenerates in stretched layers.  The adjoint (record_tape)
+   * is not built for it. */
+  int32_t reinit;
 } mm_config;
 enum { MM_EOS_STIFFENED = 0, MM_EOS_TAIT = 1 };
 enum { MM_FLUX_HLLC = 0, MM_FLUX_ROE = 1 };

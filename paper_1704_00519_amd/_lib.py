@@ -46,7 +46,7 @@ class MMConfig(C.Structure):
                 ("tait_B", C.c_double * MAX_MAT), ("p0", C.c_double * MAX_MAT),
                 ("flux", C.c_int32), ("scale_sep", C.c_int32),
                 ("coord", C.c_int32), ("fs_on", C.c_int32), ("fs_mat", C.c_int32),
-                ("fs_p", C.c_double * 5)]
+                ("fs_p", C.c_double * 5), ("reinit", C.c_int32)]
 
 
 class MMDiag(C.Structure):
@@ -177,6 +177,7 @@ def make_config(cfg):
     c.fs_mat = int(cfg.get("fs_mat", 0))
     for q, x in enumerate(cfg.get("fs_p", [0.0] * 5)):
         c.fs_p[q] = float(x)
+    c.reinit = int(cfg.get("reinit", 0))
     for q in range(4):
         c.bc[q] = int(cfg["bc"][q])
         c.inflow_W[q] = float(cfg["inflow_W"][q])

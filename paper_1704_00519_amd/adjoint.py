@@ -99,6 +99,7 @@ class NestedBubble:
         W, inflow = self.fields(torch.as_tensor(params, dtype=torch.float64))
         cfg = dict(self.w["cfg"])
         cfg["inflow_W"] = [float(v) for v in inflow]
+        cfg["reinit"] = 0  # the adjoint is built without the redistancing
         s = _lib.Solver(cfg, stream=stream)
         s.init(self.w["phi"], self.w["chi"], W.numpy())
         return s

@@ -3017,6 +3017,112 @@ __global__ void __launch_bounds__(256) k_vext_tiles(Params P, Bufs B, int sidx) 
 }
 TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 
+// ---------------------------------------------------------------------------
+// Redistancing of the regional level set after a time step (2D).  Per listed
+// 16 x 16 tile, in LDS over the tile and a frame of band_ls + 2 cells: the
+// interface distances of the band cells from the crossings with their
+// 4-neighbours of another material, then band_ls + 1 Jacobi sweeps of the
+// 8-neighbour path distance within the material (each sweep reaches one
+// cell further, so the tile's own cells are exact after the last one); the
+// tile's band cells go to ptmp, committed by k_reinit_commit (other tiles
+// read the old level set of their frames meanwhile).
+// ---------------------------------------------------------------------------
+constexpr int RI_T = 16, RI_FMAX = 12, RI_W = RI_T + 2 * RI_FMAX;
+struct ReinitSmem {
+  double a[RI_W * RI_W], b[RI_W * RI_W], phi[RI_W * RI_W];
+  uint8_t chi[RI_W * RI_W], in[RI_W * RI_W];
+};
+__global__ void __launch_bounds__(256) k_reinit_tiles(Params P, Bufs B) {
+  __shared__ ReinitSmem S;
+  int tid = threadIdx.x;
+  int ntile = (int)B.ctr[C_NTILES], ntx = tiles_x(P);
+  const int FR = P.nband + 2;  // frame: band_ls + 2 <= RI_FMAX
+  const int W = RI_T + 2 * FR, nsw = FR - 1;
+  double bls = P.bls;
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    int tile = B.tiles[t];
+    int i0 = (tile % ntx) * RI_T - FR, j0 = (tile / ntx) * RI_T - FR;
+    for (int q = tid; q < W * W; q += 256) {
+      int ci = i0 + q % W, cj = j0 + q / W;
+      bool in = ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny;
+      int k = in ? cid(P, ci, cj) : 0;
+      S.in[q] = in ? 1 : 0;
+      S.phi[q] = in ? B.phi[k] : bls;
+      S.chi[q] = in ? B.chi[k] : 0;
+    }
+    __syncthreads();
+    // interface distances (cells of the outer ring have no full neighbourhood
+    // and are never read for the tile's own cells)
+    for (int q = tid; q < W * W; q += 256) {
+      int lx = q % W, ly = q / W;
+      double best = bls;
+      double pc = S.phi[q];
+      if (S.in[q] && pc < bls && lx > 0 && ly > 0 && lx < W - 1 && ly < W - 1) {
+        double dxm = -1.0, dym = -1.0;
+        for (int n = 0; n < 4; n++) {
+          int o = n == 0 ? -1 : (n == 1 ? 1 : (n == 2 ? -W : W));
+          int qn = q + o;
+          if (!S.in[qn] || S.chi[qn] == S.chi[q]) continue;
+          double pn = S.phi[qn], sum = pc + pn;
+          double hh = n < 2 ? P.dx : P.dy;
+          double d = sum > 0.0 ? hh * (pc / sum) : 0.5 * hh;
+          if (n < 2) {
+            if (dxm < 0.0 || d < dxm) dxm = d;
+          } else if (dym < 0.0 || d < dym) {
+            dym = d;
+          }
+        }
+        if (dxm >= 0.0 && dym >= 0.0)
+          best = dxm > 0.0 && dym > 0.0 ? (dxm * dym) / sqrt(dxm * dxm + dym * dym) : 0.0;
+        else if (dxm >= 0.0)
+          best = dxm;
+        else if (dym >= 0.0)
+          best = dym;
+        if (best > bls) best = bls;
+      }
+      S.a[q] = best;
+    }
+    __syncthreads();
+    double* src = S.a;
+    double* dst = S.b;
+    for (int sw = 0; sw < nsw; sw++) {
+      for (int q = tid; q < W * W; q += 256) {
+        int lx = q % W, ly = q / W;
+        double v = src[q];
+        if (S.in[q] && S.phi[q] < bls && lx > 0 && ly > 0 && lx < W - 1 && ly < W - 1) {
+          for (int dj = -1; dj <= 1; dj++)
+            for (int di = -1; di <= 1; di++) {
+              if (di == 0 && dj == 0) continue;
+              int qn = q + dj * W + di;
+              if (!S.in[qn] || S.chi[qn] != S.chi[q]) continue;
+              double ex = di * P.dx, ey = dj * P.dy;
+              double cand = src[qn] + sqrt(ex * ex + ey * ey);
+              if (cand < v) v = cand;
+            }
+        }
+        dst[q] = v < bls ? v : bls;
+      }
+      __syncthreads();
+      double* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+    for (int q = tid; q < RI_T * RI_T; q += 256) {
+      int lx = FR + q % RI_T, ly = FR + q / RI_T, lq = ly * W + lx;
+      int ci = i0 + lx, cj = j0 + ly;
+      if (ci < P.nx && cj < P.ny) B.ptmp[cid(P, ci, cj)] = src[lq];
+    }
+    __syncthreads();  // the LDS window is reused by the next tile
+  }
+}
+// commit of the redistanced band cells of the listed tiles
+__global__ void __launch_bounds__(256) k_reinit_commit(Params P, Bufs B) {
+  for_tiles(P, B, [&](int i, int j) {
+    int k = cid(P, i, j);
+    if (B.phi[k] < P.bls) B.phi[k] = B.ptmp[k];
+  });
+}
+
 // 1D: every ghost-extension sweep of a stage in one workgroup, a barrier
 // between sweeps (each sweep reads the states the previous ones left, as
 // separate launches would; the queue of a 1D problem is short)

@@ -190,6 +190,9 @@ static bool valid_config(const mm_config* c, std::string& why) {
   if (c->coord == 1 && (c->dim != 1 || !(c->x0 >= 0.0)))
     return why = "cylindrical geometry needs dim 1 and x0 >= 0", false;
   if (c->fs_on != 0 && c->fs_on != 1) return why = "fs_on must be 0 or 1", false;
+  if (c->reinit != 0 && c->reinit != 1) return why = "reinit must be 0 or 1", false;
+  if (c->reinit && (c->dim != 2 || c->band_ls > 10))
+    return why = "the redistancing is built for dim 2 with band_ls <= 10", false;
   if (c->fs_on) {
     if (c->dim != 1) return why = "free surfaces are built for dim 1", false;
     if (c->fs_mat < 0 || c->fs_mat >= c->n_mat) return why = "bad fs_mat", false;
@@ -259,6 +262,8 @@ static Params make_params(const mm_config* cfg) {
   P.fs_mat = cfg->fs_mat;
   P.x0 = cfg->x0;
   for (int q = 0; q < 5; q++) P.fs_p[q] = cfg->fs_p[q];
+  P.reinit = cfg->reinit;
+  P.nband = cfg->band_ls;
   for (int q = 0; q < 4; q++) {
     P.bc[q] = cfg->bc[q];
     P.inflow_W[q] = cfg->inflow_W[q];
@@ -620,6 +625,21 @@ static int rk_coefs(const mm_config& cfg, double* b, double* cc, double* w) {
 static int stage_src(int s) { return s; }
 static int stage_dst(int s, int ns) { return s == ns - 1 ? 0 : s + 1; }
 
+// redistancing of the level set after a step (2D), then classification and
+// geometry of the new level set
+template <int D>
+static void reinit_levelset(mm_ctx* c) {
+  const Params& P = c->P;
+  dim3 tg = tile_grid(c), tb(256);
+  LAUNCH(k_reinit_tiles, tg, tb, P, c->B);
+  LAUNCH(k_reinit_commit, tg, tb, P, c->B);
+  bc_ls<D>(c);
+  classify<D>(c);
+  int nt = n_tiles(P);
+  LAUNCH(k_tiles_geom<D>, dim3(2 * nt), tb, P, c->B, 0, 0, nt, nt, (double*)nullptr,
+         (uint8_t*)nullptr, -1);
+}
+
 template <int D>
 static void one_step(mm_ctx* c) {
   double b[3], cc[3], w[3];
@@ -629,6 +649,7 @@ static void one_step(mm_ctx* c) {
     stage<D>(c, s, stage_src(s), 0, stage_dst(s, ns), b[s], cc[s], w[s], nullptr, nullptr,
              s == ns - 1);
   if (c->P.scale_sep) scale_separation<D>(c);
+  if (D == 2 && c->P.reinit) reinit_levelset<D>(c);
 }
 
 static mm_status stage_inputs(mm_ctx* c, size_t bytes, const void* src, int ptr_kind,
@@ -812,6 +833,8 @@ extern "C" mm_status mm_step(mm_ctx* c, int32_t n_steps, int32_t record_tape, do
     return fail(c, MM_ENOTIMPL, "the adjoint is built for the HLLC face flux only");
   if (record_tape > 0 && (c->P.coord != 0 || c->P.fs_on))
     return fail(c, MM_ENOTIMPL, "the adjoint is built for planar geometry without free surfaces");
+  if (record_tape > 0 && c->P.reinit)
+    return fail(c, MM_ENOTIMPL, "the adjoint is built without the level-set redistancing");
   if (record_tape > 0) return step_record(c, n_steps, record_tape, t_out);
   c->tape_K = 0;  // plain steps end any tape
   c->tape_n = c->tape_rev = 0;

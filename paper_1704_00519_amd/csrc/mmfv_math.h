@@ -40,6 +40,8 @@ struct Params {
   int fs_on, fs_mat;              // material fs_mat: an ambient that is not solved
   double x0;                      // low end of the domain in x
   double fs_p[5];                 // p_hi, p_lo, t0, t1, density of the ambient
+  int reinit;                     // 1: redistancing of the level set after each step
+  int nband;                      // band width of the level set in cells
 };
 enum { FLUX_HLLC = 0, FLUX_ROE = 1 };
 

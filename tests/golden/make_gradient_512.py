@@ -37,7 +37,7 @@ def centroid(alpha, x):
 
 def main():
     w = wl.shock_bubble(nx=NX, ny=NY, rho_outer=PARAMS[0], rho_inner=PARAMS[1],
-                        mach=PARAMS[2])
+                        mach=PARAMS[2], reinit=0)  # the adjoint is built without it
     cfg = w["cfg"]
     dx = (cfg["x1"] - cfg["x0"]) / NX
     x = np.broadcast_to(cfg["x0"] + (np.arange(NX) + 0.5) * dx, (NY, NX))

@@ -49,7 +49,7 @@ def single2d(nx=40, ny=24):
 
 
 def drifting_bubble(nx=96, ny=32):
-    w = wl.shock_bubble(nx=nx, ny=ny)
+    w = wl.shock_bubble(nx=nx, ny=ny, reinit=0)
     w["W"] = w["W"].copy()
     w["W"][:, 1] += 0.3
     w["W"][:, 2] += 0.1
@@ -62,8 +62,8 @@ CASES = {
     "tube_1step": (lambda: wl.shock_tube_1d(n=120), 20, 1),
     "tube_4steps": (lambda: wl.shock_tube_1d(n=120), 20, 4),
     "drifting_bubble": (drifting_bubble, 15, 1),
-    "bubble_at_rest_2steps": (lambda: wl.shock_bubble(nx=128, ny=32), 20, 2),
-    "bubble_hit_3steps": (lambda: wl.shock_bubble(nx=128, ny=32), 60, 3),
+    "bubble_at_rest_2steps": (lambda: wl.shock_bubble(nx=128, ny=32, reinit=0), 20, 2),
+    "bubble_hit_3steps": (lambda: wl.shock_bubble(nx=128, ny=32, reinit=0), 60, 3),
 }
 
 
@@ -183,7 +183,7 @@ def central_differences(prob, params, steps, K, dts, g):
 
 def test_centroid_gradient_against_tangent_and_differences(pk):
     from paper_1704_00519_amd import adjoint as ad
-    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32))
+    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32, reinit=0))
     params = np.array([0.138, 3.15, 1.22])
     steps, K = 70, 16  # past the first contact of the shock with the shell
     dts = ad.nominal_schedule(prob, params, steps)
@@ -211,7 +211,7 @@ def test_gradient_study_size_against_stored_tangent(pk):
                                 "gradient_nested_bubble_512.npz"))
     params = gold["params"]
     steps, K = int(gold["steps"]), 30
-    prob = ad.NestedBubble(wl.shock_bubble(nx=512, ny=128))
+    prob = ad.NestedBubble(wl.shock_bubble(nx=512, ny=128, reinit=0))
     _, s, _ = prob.run(params, steps, record=1)
     assert np.array_equal(s.tape()[2], gold["dts"])
     assert s.diag()["n_updates"] == int(gold["n_updates"])
@@ -240,7 +240,7 @@ def test_reverse_graph_matches_direct(pk):
     equals that of direct launches on the null stream up to the order of the
     atomic sums."""
     from paper_1704_00519_amd import adjoint as ad
-    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32))
+    prob = ad.NestedBubble(wl.shock_bubble(nx=128, ny=32, reinit=0))
     params = np.array([0.138, 3.15, 1.22])
     steps, K = 40, 16  # segments of 16, 16 and 8 steps
     grads = []
@@ -261,7 +261,7 @@ def test_forward_after_reverse_steps(pk):
     """Reverse calls leave the forward run as it was: steps taken after some
     reverse calls give, bit for bit, what the same steps give without them
     (the forward tile list is rebuilt on the next step)."""
-    w = wl.shock_bubble(nx=128, ny=32)
+    w = wl.shock_bubble(nx=128, ny=32, reinit=0)
     out = []
     for reverse in (False, True):
         s = pk.Solver(w["cfg"])

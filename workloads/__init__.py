@@ -96,14 +96,15 @@ def _dist_segment(px, py, ax, ay, bx, by):
     return np.sqrt((px - qx) ** 2 + (py - qy) ** 2)
 
 
-def triple_point(nx=896, ny=384, steps=2000, scale_sep=0):
-    """Case III: 7 x 3 box, reflective walls, triple point at (1, 1.5)."""
+def triple_point(nx=896, ny=384, steps=2000, scale_sep=0, reinit=1):
+    """Case III: 7 x 3 box, reflective walls, triple point at (1, 1.5);
+    the level set redistanced after every step (reinit)."""
     x, dx = _centres(nx, 0.0, 7.0)
     y, dy = _centres(ny, 0.0, 3.0)
     X, Y = np.meshgrid(x, y)
     cfg = base_config(dim=2, nx=nx, ny=ny, x0=0.0, x1=7.0, y0=0.0, y1=3.0,
                       gamma=[1.5, 1.4, 1.5], pinf=[0.0, 0.0, 0.0],
-                      bc=[BC_REFLECTIVE] * 4, scale_sep=scale_sep)
+                      bc=[BC_REFLECTIVE] * 4, scale_sep=scale_sep, reinit=reinit)
     # interfaces are axis-aligned: distances are exact differences
     d1 = np.where((Y >= 0.0) & (Y <= 3.0), np.abs(X - 1.0),
                   _dist_segment(X, Y, 1.0, 0.0, 1.0, 3.0))
@@ -119,10 +120,11 @@ def triple_point(nx=896, ny=384, steps=2000, scale_sep=0):
 
 def shock_bubble(nx=2048, ny=512, mach=1.22, rho_outer=0.138, rho_inner=3.15,
                  steps=3000, x_shock=0.5, centre=(1.2, 0.5), r_out=0.25,
-                 r_in=0.1, scale_sep=1):
+                 r_in=0.1, scale_sep=1, reinit=1):
     """Planar Mach ``mach`` shock in ambient gas hitting a nested bubble:
     outer shell (gamma 1.648, rho_outer) and inner core (gamma 1.249,
-    rho_inner), both at p = 1, on a 4 x 1 domain."""
+    rho_inner), both at p = 1, on a 4 x 1 domain; scale separation and the
+    redistancing of the level set after every step."""
     x, dx = _centres(nx, 0.0, 4.0)
     y, dy = _centres(ny, 0.0, 1.0)
     X, Y = np.meshgrid(x, y)
@@ -131,7 +133,8 @@ def shock_bubble(nx=2048, ny=512, mach=1.22, rho_outer=0.138, rho_inner=3.15,
     cfg = base_config(dim=2, nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
                       gamma=[g0, 1.648, 1.249], pinf=[0.0, 0.0, 0.0],
                       bc=[BC_INFLOW, BC_OUTFLOW, BC_REFLECTIVE, BC_REFLECTIVE],
-                      inflow_W=[rho1, u1, 0.0, p1], inflow_mat=0, scale_sep=scale_sep)
+                      inflow_W=[rho1, u1, 0.0, p1], inflow_mat=0, scale_sep=scale_sep,
+                      reinit=reinit)
     d = np.sqrt((X - centre[0]) ** 2 + (Y - centre[1]) ** 2)
     phi = np.minimum(np.abs(d - r_out), np.abs(d - r_in))
     phi = np.minimum(phi, cfg["band_ls"] * min(dx, dy))
@@ -232,7 +235,7 @@ def air_water_tube_1d(n=400, x_if=None, air=(50.0, 0.0, 1000.0), water_rho=1000.
 
 
 def shock_helium_water(nx=512, ny=128, steps=200, x_shock=0.5, bubble=(1.1, 0.5, 0.25),
-                       column=(2.0, 0.5, 0.2), scale_sep=1):
+                       column=(2.0, 0.5, 0.2), scale_sep=1, reinit=1):
     """Case VI set-up (Table 2): a Mach 6 shock in air (post-shock state from
     the normal-shock relations; Table 2 prints (5.268, 5.752, 41.83)) hits a
     helium bubble (gamma 1.667, rho 0.138) that then meets a water column
@@ -247,7 +250,8 @@ def shock_helium_water(nx=512, ny=128, steps=200, x_shock=0.5, bubble=(1.1, 0.5,
     cfg = base_config(dim=2, nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
                       gamma=[1.4, 1.667, 1.4], pinf=[0.0, 0.0, 0.0],
                       bc=[BC_INFLOW, BC_OUTFLOW, BC_REFLECTIVE, BC_REFLECTIVE],
-                      inflow_W=[rho1, u1, 0.0, p1], inflow_mat=0, scale_sep=scale_sep)
+                      inflow_W=[rho1, u1, 0.0, p1], inflow_mat=0, scale_sep=scale_sep,
+                      reinit=reinit)
     tait_config(cfg, [2])
     db = np.sqrt((X - bubble[0]) ** 2 + (Y - bubble[1]) ** 2) - bubble[2]
     dc = np.sqrt((X - column[0]) ** 2 + (Y - column[1]) ** 2) - column[2]
