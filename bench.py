@@ -76,14 +76,17 @@ def measured_traffic(grid="2048x512"):
 def bulk_kernel_sha256():
     """Hash of the bulk kernel's source: its section of mmfv_kernels.h (from
     the bulk-update comment to the 1D bulk tile) and the point-wise numerics
-    it calls (mmfv_math.h)."""
+    it calls (mmfv_math.h from its templates on; the parameter block before
+    them gains fields that the kernel does not read)."""
     import hashlib
     kern = open(os.path.join(ROOT, KERNEL_SOURCES[0]), "rb").read()
     a = kern.index(b"// Bulk update: cells with no cut cell")
     b = kern.index(b"// 1D bulk update of one tile")
+    math = open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb").read()
+    m0 = math.index(b"// The point-wise functions below are templates")
     d = hashlib.sha256()
     d.update(kern[a:b])
-    d.update(open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb").read())
+    d.update(math[m0:])
     return d.hexdigest()
 
 
