@@ -3030,7 +3030,9 @@ TILE_KERNEL(t_vfill, b_vfill, COMMA int sidx, COMMA sidx)
 constexpr int RI_T = 16, RI_FMAX = 12, RI_W = RI_T + 2 * RI_FMAX;
 struct ReinitSmem {
   double a[RI_W * RI_W], b[RI_W * RI_W], phi[RI_W * RI_W];
-  uint8_t chi[RI_W * RI_W], in[RI_W * RI_W];
+  uint8_t chi[RI_W * RI_W], in[RI_W * RI_W], nb[RI_W * RI_W];
+  uint16_t list[RI_W * RI_W];
+  int nlist;
 };
 __global__ void __launch_bounds__(256) k_reinit_tiles(Params P, Bufs B) {
   __shared__ ReinitSmem S;
@@ -3039,9 +3041,22 @@ __global__ void __launch_bounds__(256) k_reinit_tiles(Params P, Bufs B) {
   const int FR = P.nband + 2;  // frame: band_ls + 2 <= RI_FMAX
   const int W = RI_T + 2 * FR, nsw = FR - 1;
   double bls = P.bls;
+  // neighbour n of the 8 (dj, di) in row-major order without the centre:
+  // its offset in the window and its centre distance
+  int off[8];
+  double dist[8];
+  for (int n = 0, q = 0; q < 9; q++) {
+    if (q == 4) continue;
+    int di = q % 3 - 1, dj = q / 3 - 1;
+    double ex = di * P.dx, ey = dj * P.dy;
+    off[n] = dj * W + di;
+    dist[n] = sqrt(ex * ex + ey * ey);
+    n++;
+  }
   for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
     int tile = B.tiles[t];
     int i0 = (tile % ntx) * RI_T - FR, j0 = (tile / ntx) * RI_T - FR;
+    if (tid == 0) S.nlist = 0;
     for (int q = tid; q < W * W; q += 256) {
       int ci = i0 + q % W, cj = j0 + q / W;
       bool in = ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny;
@@ -3051,8 +3066,10 @@ __global__ void __launch_bounds__(256) k_reinit_tiles(Params P, Bufs B) {
       S.chi[q] = in ? B.chi[k] : 0;
     }
     __syncthreads();
-    // interface distances (cells of the outer ring have no full neighbourhood
-    // and are never read for the tile's own cells)
+    // interface distances; the band cells away from the window's outer ring
+    // are listed with the mask of their same-material interior neighbours
+    // (cells of the ring have no full neighbourhood and are never read for
+    // the tile's own cells)
     for (int q = tid; q < W * W; q += 256) {
       int lx = q % W, ly = q / W;
       double best = bls;
@@ -3079,26 +3096,33 @@ __global__ void __launch_bounds__(256) k_reinit_tiles(Params P, Bufs B) {
         else if (dym >= 0.0)
           best = dym;
         if (best > bls) best = bls;
+        unsigned m = 0;
+        for (int n = 0; n < 8; n++) {
+          int qn = q + off[n];
+          if (S.in[qn] && S.chi[qn] == S.chi[q]) m |= 1u << n;
+        }
+        S.nb[q] = (uint8_t)m;
+        int at = atomicAdd(&S.nlist, 1);
+        S.list[at] = (uint16_t)q;
       }
       S.a[q] = best;
+      S.b[q] = best;
     }
     __syncthreads();
+    // Jacobi sweeps over the listed band cells (every other cell keeps its
+    // value, the band width, in both buffers)
     double* src = S.a;
     double* dst = S.b;
+    int nl = S.nlist;
     for (int sw = 0; sw < nsw; sw++) {
-      for (int q = tid; q < W * W; q += 256) {
-        int lx = q % W, ly = q / W;
+      for (int e = tid; e < nl; e += 256) {
+        int q = S.list[e];
+        unsigned m = S.nb[q];
         double v = src[q];
-        if (S.in[q] && S.phi[q] < bls && lx > 0 && ly > 0 && lx < W - 1 && ly < W - 1) {
-          for (int dj = -1; dj <= 1; dj++)
-            for (int di = -1; di <= 1; di++) {
-              if (di == 0 && dj == 0) continue;
-              int qn = q + dj * W + di;
-              if (!S.in[qn] || S.chi[qn] != S.chi[q]) continue;
-              double ex = di * P.dx, ey = dj * P.dy;
-              double cand = src[qn] + sqrt(ex * ex + ey * ey);
-              if (cand < v) v = cand;
-            }
+        for (int n = 0; n < 8; n++) {
+          if (!((m >> n) & 1)) continue;
+          double cand = src[q + off[n]] + dist[n];
+          if (cand < v) v = cand;
         }
         dst[q] = v < bls ? v : bls;
       }
