@@ -40,6 +40,8 @@ def pk():
 @pytest.mark.parametrize("name", sorted(RUNS))
 def test_long_run_matches_stored_oracle_run(pk, name):
     path = os.path.join(HERE, "golden", f"long_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle run for {name}: tests/golden/make_long_runs.py writes it")
     ref = np.load(path)
     w = RUNS[name]()
     steps, status = int(ref["steps"]), int(ref["status"])
