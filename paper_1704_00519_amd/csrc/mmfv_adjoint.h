@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) k_a_mix(Params P, Bufs B, Adj A) {
         lgy += lw * 2.0 * gy * at[1];
         aadd(&A1(P, A.lal, r, tk[1]), lw * gy * gy);
       } else {
-        double sg = gx * gy > 0.0 ? 1.0 : -1.0;
+        double sg = gx * gy < 0.0 ? -1.0 : 1.0;  // d|x|/dx = +1 at 0, as fabs of the dual types
         lgx += lw * sg * gy * at[2];
         lgy += lw * sg * gx * at[2];
         aadd(&A1(P, A.lal, r, tk[2]), lw * fabs(gx * gy));
@@ -744,7 +744,7 @@ __global__ void __launch_bounds__(256) k_a_vext(Params P, Bufs B, Adj A, int swe
     aadd(&A.lvy[ky], loy * wy / ws);
     double lwx = (lox * (B.vx[kx] - ox) + loy * (B.vy[kx] - oy)) / ws;
     double lwy = (lox * (B.vx[ky] - ox) + loy * (B.vy[ky] - oy)) / ws;
-    double lgx = gx > 0.0 ? lwx : -lwx, lgy = gy > 0.0 ? lwy : -lwy;
+    double lgx = gx < 0.0 ? -lwx : lwx, lgy = gy < 0.0 ? -lwy : lwy;
     aadd(&A.lphi[kxp], lgx);
     aadd(&A.lphi[kxm], -lgx);
     aadd(&A.lphi[kyp], lgy);
@@ -1007,7 +1007,7 @@ __global__ void __launch_bounds__(256) k_a_ext(Params P, Bufs B, Adj A, int sidx
           lwx += lo[c] * (av[c] - out) / ws;
           lwy += lo[c] * (bv[c] - out) / ws;
         }
-        double lgx = gx > 0.0 ? lwx : -lwx, lgy = gy > 0.0 ? lwy : -lwy;
+        double lgx = gx < 0.0 ? -lwx : lwx, lgy = gy < 0.0 ? -lwy : lwy;
         aadd(&A.lphi[kxp], lgx * lsgn(B.chi, r, kxp));
         aadd(&A.lphi[kxm], -lgx * lsgn(B.chi, r, kxm));
         aadd(&A.lphi[kyp], lgy * lsgn(B.chi, r, kyp));
@@ -1190,7 +1190,7 @@ __global__ void __launch_bounds__(256) k_a_ext_tiles(Params P, Bufs B, Adj A, in
               if (own) {
                 int kc = cid(P, ci, cj);
                 int kxp = kc + 1, kxm = kc - 1, kyp = kc + P.NX, kym = kc - P.NX;
-                double lgx = gx > 0.0 ? lwx : -lwx, lgy = gy > 0.0 ? lwy : -lwy;
+                double lgx = gx < 0.0 ? -lwx : lwx, lgy = gy < 0.0 ? -lwy : lwy;
                 aadd(&A.lphi[kxp], lgx * lsgn(B.chi, r, kxp));
                 aadd(&A.lphi[kxm], -lgx * lsgn(B.chi, r, kxm));
                 aadd(&A.lphi[kyp], lgy * lsgn(B.chi, r, kyp));
