@@ -7,8 +7,6 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "mmfv_lib.hip")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("mmfv_math.h", "mmfv_kernels.h")] + \
-    [os.path.join(ROOT, "include", "mmfv.h")]
 LIB = os.path.join(HERE, "libmmfv.so")
 
 # FP64 throughout, every operation rounded once as written (no contraction,

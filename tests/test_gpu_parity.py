@@ -221,7 +221,7 @@ def batch_instances(n, nmin, nmax, steps):
     return wl.batched_tubes(n_inst=n, nmin=nmin, nmax=nmax, steps=steps)
 
 
-@pytest.mark.parametrize("threads", [0, 64, 1024])
+@pytest.mark.parametrize("threads", [0, 64, 128, 256, 512, 1024])
 def test_batched_instances_match_oracle(pk, threads):
     steps = 25
     insts = batch_instances(12, 40, 700, steps)
