@@ -1489,10 +1489,14 @@ static void mixing(St *s) {
         /* Reading (empty part): a cell's own material with a volume
            fraction but no conserved quantities at all (left so by a move
            between materials, stranded sources or scale separation) is
-           filled from its neighbours like a new cell, whatever its alpha */
+           filled from its neighbours like a new cell, whatever its alpha;
+           so is a part with 0 < alpha < 1 and no mass (a partial density of
+           zero or roundoff of either sign: an interface that crossed a face
+           that had no aperture yet for this material) */
         int empty = 1;
         for (int v = 0; v < 4; v++)
           if (M4(s, s->Qt, r, v, k) != 0.0) empty = 0;
+        if (!(M4(s, s->Qt, r, 0, k) > 0.0) && as < 1.0) empty = 1;
         if (!(as < amix) && s->chit[k] == r && !(empty && as > 0.0)) continue;
         if (!(as > 0.0)) {
           int nz = 0;

@@ -84,7 +84,15 @@ __global__ void __launch_bounds__(256) k_a_mix(Params P, Bufs B, Adj A) {
   if (!B.cut[k] && A.occstar[k] == (uint8_t)(1u << B.chi[k])) return;
   for (int r = blockIdx.z; r == (int)blockIdx.z; r++) {
     double as = alpha_at<D>(P, B, r, k);
-    if (!(as < amix) && B.chi[k] == r) continue;
+    // own-material parts with nothing in them, or with 0 < alpha < 1 and no
+    // mass, are sources like new cells
+    if (!(as < amix) && B.chi[k] == r) {
+      bool nz = false;
+      for (int v = 0; v < 4; v++)
+        if (loadQ<D>(P, A.Qstar, A.occstar, r, v, k) != 0.0) nz = true;
+      bool nomass = !nz || (!(loadQ<D>(P, A.Qstar, A.occstar, r, 0, k) > 0.0) && as < 1.0);
+      if (!(nomass && as > 0.0)) continue;
+    }
     if (!(as > 0.0)) {
       bool nz = false;
       for (int v = 0; v < 4; v++)

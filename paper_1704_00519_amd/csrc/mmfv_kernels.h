@@ -1950,11 +1950,15 @@ MMD void b_mix1(const Params& P, const Bufs& B, int i, int j, int didx, uint32_t
       pn[n] = B.phi[kn[n]];
     }
     // a part of the cell's own material with a volume fraction but nothing
-    // in it (left so by a move between materials) is filled like a new cell
+    // in it (left so by a move between materials) is filled like a new
+    // cell; so is a part with 0 < alpha < 1 and no mass (a partial density
+    // of zero or roundoff of either sign: an interface that crossed a face
+    // that had no aperture yet for this material)
     bool nz = false;
     for (int v = 0; v < 4; v++)
       if (qk[v] != 0.0) nz = true;
-    if (!(as < amix) && chk == r && !(!nz && as > 0.0)) continue;
+    bool nomass = !nz || (!(qk[0] > 0.0) && as < 1.0);
+    if (!(as < amix) && chk == r && !(nomass && as > 0.0)) continue;
     if (!(as > 0.0) && !nz) continue;
     wave_count(&B.ctr[C_MIXSRC], 1);
     auto lsn = [&](int n) { return hn[n] == r ? pn[n] : -pn[n]; };

@@ -136,12 +136,15 @@ def radii(alpha, dx):
     return rin, rin + alpha[1].sum() * dx
 
 
-@pytest.mark.parametrize("n", [160, 320, 640, 1280])
-def test_case_ii_resolutions_to_t03(pk, n):
+@pytest.mark.parametrize("n,dr,ratio", [(160, 0.2, 1.0), (320, 0.2, 1.0), (640, 0.2, 1.0),
+                                         (1280, 0.2, 1.0), (320, 0.1, 1.0), (640, 0.05, 2.8)])
+def test_case_ii_resolutions_to_t03(pk, n, dr, ratio):
     """The paper's resolutions, to t = 0.3 (past stagnation), in one run of
-    each side; the interface radii (volumes of core and shell) agree too."""
-    w = wl.icf_1d(n=n)
-    print("icf resolution", n, flush=True)
+    each side; the interface radii (volumes of core and shell) agree too.
+    The last two are thin shells of the parameter study that reach t = 0.3
+    only with new-cell filling of own-material parts without mass."""
+    w = wl.icf_1d(n=n, r_out=1.0 + dr, gammas=(1.667, 1.667 * ratio, 1.667))
+    print("icf resolution", n, dr, ratio, flush=True)
     o = oracle.Oracle(w["cfg"])
     assert o.init(w["phi"], w["chi"], w["W"]) == 0
     k = 0

@@ -169,6 +169,36 @@ def test_mixing_new_cell_takes_the_neighbours_density():
     assert close(out[:, 2, 3], 1.0 * Qt / 1.25)
 
 
+def test_mixing_own_partial_cell_without_mass_fills_like_a_new_cell():
+    """A part of the cell's own material with alpha_mix <= alpha < 1 whose
+    partial density is roundoff (here negative) is filled like a new cell:
+    the pair ends at the averaged density (Q_s + Q_t)/(alpha_s + alpha_t).
+    With positive mass, or with alpha = 1, the same cell is no source."""
+    Qt = np.array([2.0, 1.0, 0.5, 6.0])
+    junk = np.array([-1e-18, 3e-19, 0.0, 2e-17])
+
+    def case(alpha, Qs):
+        c = MixCase()
+        c.cell(2, 2, 0, 0.5, alpha, Qs)  # the cell's own material
+        c.cell(3, 2, 0, 0.5, 1.0, Qt)    # lsv +0.5: the target side
+        c.cell(1, 2, 1, 0.5, 0.0)        # lsv -0.5 -> g_x = 1
+        c.cell(2, 1, 1, 0.7, 0.0)
+        c.cell(2, 3, 1, 0.7, 0.0)        # g_y = 0
+        return c.run()
+
+    out, nsrc, _ = case(0.6, junk)
+    assert nsrc == 1
+    U = (junk + Qt) / 1.6
+    assert close(out[:, 2, 2], 0.6 * U)
+    assert close(out[:, 2, 3], 1.0 * U)
+    assert out[0, 2, 2] > 0.0
+    Qm = np.array([0.9, 0.1, 0.0, 2.0])
+    out, nsrc, _ = case(0.6, Qm)
+    assert nsrc == 0 and np.array_equal(out[:, 2, 2], Qm)
+    out, nsrc, _ = case(1.0, junk)
+    assert nsrc == 0 and np.array_equal(out[:, 2, 2], junk)
+
+
 def test_mixing_only_diagonal_target():
     """The x and y neighbours hold none of material 0 (ineligible, and not
     sources themselves); the diagonal neighbour is a full cell: it takes the

@@ -193,3 +193,16 @@ def test_case_ii_paper_statements():
     assert 0.04 <= t_thin <= 0.055
     # stagnation (smallest inner radius) between t = 0.17 and 0.24 (printed)
     assert 0.17 <= t_stag <= 0.24
+
+
+def test_thin_shell_reaches_t03():
+    """Shell r_2 - r_1 = 0.1 at 320 cells (gamma_2 = gamma_1): its free
+    surface runs ahead at about 13 after the drive pressure has dropped and
+    the interface enters cells whose face has no aperture yet for the shell;
+    the part of the shell there has alpha >= alpha_mix and a partial density
+    of roundoff, and is filled like a new cell.  The run reaches t = 0.3."""
+    w = wl.icf_1d(n=320, r_out=1.1)
+    o = oracle.Oracle(w["cfg"])
+    assert o.init(w["phi"], w["chi"], w["W"]) == 0
+    while o.diag()["t"] < 0.3:
+        assert o.step(10) == 0
