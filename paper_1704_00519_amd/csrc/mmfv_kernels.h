@@ -1543,11 +1543,12 @@ MMD bool bulk_face(const Params& P, const Bufs& B, const BulkTile<BX, BY>& sm, i
 // of a few tiles per compute unit (896 x 384: three); 28 x 32 cells with
 // 1024 threads (73.6 KB) for larger grids, where the smaller frame overhead
 // wins once every CU has several tiles to work through (measured crossover
-// between 3 and 9 tiles of 28 x 16 per CU).  The register budget is left to
-// the compiler: a tighter one spills to scratch, and the spill traffic
+// between 3 and 9 tiles of 28 x 16 per CU; 30 x 33 tiles, whose face sets
+// fill all 1024 threads, measured no faster).  The register budget is left
+// to the compiler: a tighter one spills to scratch, and the spill traffic
 // outweighs the extra waves.
 constexpr int BULK_BX = 28, BULK_BY = 16, BULK_NT = 512;
-constexpr int BULK_BYW = 32, BULK_NTW = 1024;
+constexpr int BULK_BXW = 28, BULK_BYW = 32, BULK_NTW = 1024;
 constexpr int BULK_WIDE_TILES_PER_CU = 6;
 
 template <int BX, int BY, int NT, int FLUX>
@@ -1606,7 +1607,7 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
     size_t o = (size_t)ch[n] * 4 * P.NC + kk[n];
     bool has = (oc[n] >> ch[n]) & 1;
     if (ind[n]) {
-      for (int v = 0; v < 4; v++) U[n][v] = has ? Qs[o + (size_t)v * P.NC] / 1.0 : 0.0;
+      for (int v = 0; v < 4; v++) U[n][v] = has ? Qs[o + (size_t)v * P.NC] : 0.0;
     } else if (inr[n]) {
       for (int v = 0; v < 4; v++) U[n][v] = B.W[o + (size_t)v * P.NC];
     } else {
@@ -1641,7 +1642,7 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
     if (q < (BX + 2) * (BY + 2)) sm.bulk[q / (BX + 2)][q % (BX + 2)] = bf[n];
   }
   __syncthreads();
-  double lx = B.scal[S_LX], ly = B.scal[S_LY], lv = B.scal[S_LV];
+  double lx = B.scal[S_LX], ly = B.scal[S_LY];
   // x-faces: face f is the left face of tile cell (f % (BX+1), f / (BX+1))
 #pragma unroll 1
   for (int f = tid; f < NFX; f += NT) {
@@ -1677,7 +1678,6 @@ k_flux_bulk2(Params P, Bufs B, int sidx, int nidx, int didx, double bcoef,
   double* Qd = B.Q[didx];
   for (int v = 0; v < 4; v++) {
     double rhs = acc[v] + ly * (sm.F[v][fb] - sm.F[v][ft]);
-    rhs = rhs + lv * 0.0;
     double qs = qs_own[v];
     double x = stage0 ? (qs + rhs) : (bcoef * qn_own[v] + ccoef * (qs + rhs));
     Qd[om + (size_t)v * P.NC] = x;

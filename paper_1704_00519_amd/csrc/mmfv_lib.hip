@@ -519,8 +519,8 @@ static void stage_fluid(mm_ctx* c, int s, int sidx, int nidx, int didx, double b
            dim3(BULK_NT), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
   else if (D == 2)
     if (c->bulk_wide)
-      LAUNCH((k_flux_bulk2<BULK_BX, BULK_BYW, BULK_NTW, FLUX_HLLC>),
-             dim3((P.nx + BULK_BX - 1) / BULK_BX, (P.ny + BULK_BYW - 1) / BULK_BYW),
+      LAUNCH((k_flux_bulk2<BULK_BXW, BULK_BYW, BULK_NTW, FLUX_HLLC>),
+             dim3((P.nx + BULK_BXW - 1) / BULK_BXW, (P.ny + BULK_BYW - 1) / BULK_BYW),
              dim3(BULK_NTW), P, c->B, sidx, nidx, didx, b, cc, s == 0 ? 1 : 0);
     else
       LAUNCH((k_flux_bulk2<BULK_BX, BULK_BY, BULK_NT, FLUX_HLLC>),
